@@ -1,0 +1,98 @@
+"""CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+A plain sequential bulk-synchronous Pregel (oracle.c) that executes the
+iPregel applications of Figs. 8-10 with naive vertex selection (Section 4.3.1)
+and one-slot combining mailboxes (Section 4.3.3).  Only the tests, the smoke
+check and the benchmark's CPU-baseline leg may import this package; the GPU
+library never does, and the two share no code.
+
+Every function here is pinned by CPU tests against closed forms, invariants
+and textbook routines (see tests/test_oracle_pins.py).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+APP_PAGERANK, APP_CC, APP_SSSP = 0, 1, 2
+APPS = {"pagerank": APP_PAGERANK, "pr": APP_PAGERANK, "cc": APP_CC, "sssp": APP_SSSP}
+OK, NOT_CONVERGED, EINVAL, EBADGRAPH, EOVERFLOW = 0, 1, -1, -2, -3
+INF = 0xFFFFFFFF
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c (gcc -O2, no FP contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-Wall",
+                               "-fPIC", "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.orc_run.argtypes = [ctypes.c_int, ctypes.c_uint32, P, P, P, ctypes.c_uint32, ctypes.c_uint32,
+                                P, P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
+        lib.orc_run.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class OracleResult:
+    values: np.ndarray        # float64 (PageRank) or uint32 (CC, SSSP)
+    trace: np.ndarray         # [supersteps, 3] uint64: active, senders, messages
+    supersteps: int
+    status: int
+    seconds: float            # wall time of the superstep loop call
+
+
+def run(app, n: int, csr_off: np.ndarray, csr_dst: np.ndarray, param: int, source: int = 0,
+        csr_w=None, trace_cap: int = 1 << 16) -> OracleResult:
+    """Run one application on a CSR graph held in host memory.
+
+    param: PageRank -> number of rank updates (the superstep at which
+    vertices stop broadcasting, 10 in Fig. 8); CC/SSSP -> cap on the number
+    of supersteps, 0 = unlimited.
+    """
+    app = APPS[app] if isinstance(app, str) else int(app)
+    off = np.ascontiguousarray(csr_off, dtype=np.uint64)
+    adj = np.ascontiguousarray(csr_dst, dtype=np.int32)
+    if adj.size == 0:
+        adj = np.zeros(1, dtype=np.int32)
+    w = None if csr_w is None else np.ascontiguousarray(csr_w, dtype=np.uint32)
+    if w is not None and w.size == 0:
+        w = np.zeros(1, dtype=np.uint32)
+    vals = np.zeros(max(n, 1), dtype=np.float64 if app == APP_PAGERANK else np.uint32)
+    trace = np.zeros((trace_cap, 3), dtype=np.uint64)
+    steps = ctypes.c_uint32(0)
+    t0 = time.perf_counter()
+    st = _L().orc_run(app, n, off.ctypes.data, adj.ctypes.data, None if w is None else w.ctypes.data,
+                      source, param, vals.ctypes.data, trace.ctypes.data, trace_cap, ctypes.byref(steps))
+    dt = time.perf_counter() - t0
+    k = min(int(steps.value), trace_cap)
+    return OracleResult(values=vals[:n], trace=trace[:k].copy(), supersteps=int(steps.value), status=int(st),
+                        seconds=dt)
+
+
+def run_graph(app, g, param: int, source: int = 0, weighted: bool = True, trace_cap: int = 1 << 16):
+    """Convenience wrapper for any object with n, csr_off, csr_dst, csr_w."""
+    w = getattr(g, "csr_w", None) if weighted else None
+    return run(app, g.n, g.csr_off, g.csr_dst, param, source=source, csr_w=w, trace_cap=trace_cap)

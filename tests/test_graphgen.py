@@ -1,0 +1,80 @@
+"""Input generators: determinism, structure and the recipe's invariants."""
+import numpy as np
+
+import graphgen
+from tests.graphs_small import edge_arrays
+
+
+def _edge_set(g):
+    s, d = edge_arrays(g)
+    return set(zip(s.tolist(), d.tolist()))
+
+
+def test_rmat_deterministic_and_clean():
+    a = graphgen.rmat(12, 16, seed=7)
+    b = graphgen.rmat(12, 16, seed=7)
+    c = graphgen.rmat(12, 16, seed=8)
+    assert np.array_equal(a.csr_off, b.csr_off) and np.array_equal(a.csr_dst, b.csr_dst)
+    assert not np.array_equal(a.csr_dst[:1000], c.csr_dst[:1000])
+    s, d = edge_arrays(a)
+    assert not (s == d).any()                        # no self-loops
+    key = s * a.n + d
+    assert np.all(np.diff(key) > 0)                  # sorted and duplicate-free
+    assert a.csr_off[0] == 0 and a.csr_off[-1] == a.csr_dst.size
+
+
+def test_rmat_skew_hub_at_zero():
+    # Unpermuted R-MAT with a = 0.57 concentrates edges on low ids.
+    g = graphgen.rmat(14, 16, seed=1)
+    od = np.diff(g.csr_off)
+    assert od[0] == od.max()
+    assert g.m > 0.8 * 16 * g.n
+
+
+def test_csc_is_transpose():
+    g = graphgen.rmat(11, 8, seed=3)
+    s, d = edge_arrays(g)
+    ts = np.repeat(np.arange(g.n), np.diff(g.csc_off).astype(np.int64))
+    assert set(zip(d.tolist(), s.tolist())) == set(zip(ts.tolist(), g.csc_src.tolist()))
+    for v in range(0, g.n, 97):
+        lst = g.csc_src[g.csc_off[v]:g.csc_off[v + 1]]
+        assert np.all(np.diff(lst) > 0)
+
+
+def test_symmetrised_is_symmetric():
+    g = graphgen.rmat(11, 16, seed=2, symmetric=True)
+    e = _edge_set(g)
+    assert all((v, u) in e for (u, v) in e)
+    assert g.csc_src is g.csr_dst
+
+
+def test_weights_symmetric_and_in_range():
+    g = graphgen.grid_with_shortcuts(32, 0.01, seed=3)
+    assert g.csr_w.min() >= 1 and g.csr_w.max() <= 255
+    s, d = edge_arrays(g)
+    w = {(u, v): x for u, v, x in zip(s.tolist(), d.tolist(), g.csr_w.tolist())}
+    assert all(w[(v, u)] == x for (u, v), x in w.items())
+    grid_edges = 2 * 32 * 31
+    assert g.meta["shortcuts"] == int(0.01 * grid_edges)
+    assert g.m == 2 * (grid_edges + g.meta["shortcuts"])
+
+
+def test_duplicates_and_loops_kept_on_request():
+    g = graphgen.from_edges(3, [0, 0, 1, 2], [1, 1, 1, 0], keep_self_loops=True, keep_duplicates=True)
+    assert g.csr_dst.tolist() == [1, 1, 1, 0]
+    g = graphgen.from_edges(3, [0, 0, 1, 2], [1, 1, 1, 0])
+    assert g.csr_dst.tolist() == [1, 0]
+
+
+def test_small_family_sizes():
+    fam = graphgen.small_graph_family(count=6, seed=41)
+    for g in fam:
+        assert 2 ** 10 <= g.n <= 2 ** 16
+        assert g.csr_off[-1] == g.csr_dst.size
+
+
+def test_pick_sources_distinct_and_eligible():
+    g = graphgen.rmat(12, 16, seed=4, symmetric=True)
+    src = graphgen.pick_sources(g, 64, seed=40)
+    assert len(set(src.tolist())) == 64
+    assert (np.diff(g.csr_off)[src] > 0).all()
