@@ -1,0 +1,157 @@
+#!/usr/bin/env python3
+"""Benchmark of the superstep engine on one MI355X.
+
+One step = one pass of the whole hot path over the workload graph: PageRank
+(10 rank updates, FP64, pull exchange), hash-min connected components to
+vote-to-halt and SSSP from vertex 0 to vote-to-halt (push/pull chosen per
+superstep).  The graph (synthetic R-MAT, scale 20, edge factor 16,
+symmetrised, seed 2) is resident in HBM before timing starts.
+
+Prints ONE JSON line.  `value` = GTEPS over the step: messages delivered
+(edges traversed by the method: the senders' out-degrees, summed over
+supersteps and applications) / step wall time.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GTEPS/superstep + time-to-converge (PR/CC/SSSP), learned+batched vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def pr_pull_bytes(n: int, m: int) -> int:
+    """Algorithmic HBM bytes of one PageRank pull superstep: CSC sources (4 B
+    per edge), CSC offsets (8 B per vertex + 1), the outbox read once (8 B per
+    vertex), the out-degree (4 B) and the new outbox or rank (8 B)."""
+    return 4 * m + 8 * (n + 1) + 8 * n + 4 * n + 8 * n
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat-s20-sym")
+    ap.add_argument("--pr-updates", type=int, default=10)
+    ap.add_argument("--mode", default="auto", help="exchange for CC/SSSP: auto, push or pull")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--apps", default="pagerank,cc,sssp")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design, "
+              f"not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2010_08781_amd as ipg
+
+    torch.cuda.set_device(0)
+    ipg.lib()
+    t0 = time.perf_counter()
+    hg = graphgen.workload(args.workload)
+    print(f"[bench] generated {args.workload}: n={hg.n} m={hg.m} in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    g = ipg.Graph.from_host(hg)
+    apps = [a.strip() for a in args.apps.split(",") if a.strip()]
+    T = args.pr_updates
+
+    def one_step():
+        out = {}
+        for app in apps:
+            if app == "pagerank":
+                _, st = g.run("pagerank", T, mode="pull", timing=True)
+            else:
+                _, st = g.run(app, source=0, mode=args.mode, timing=True)
+            out[app] = st
+        return out
+
+    for i in range(args.warmup):
+        one_step()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per_step = []
+    for i in range(args.steps):
+        per_step.append(one_step())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = wall / args.steps * 1e3
+    edges_per_step = sum(st.edges_traversed for st in per_step[0].values())
+    value = edges_per_step * args.steps / wall / 1e9
+
+    apps_out = {}
+    for app in apps:
+        sts = [s[app] for s in per_step]
+        secs = np.array([s.seconds for s in sts])
+        st = sts[0]
+        apps_out[app] = {
+            "supersteps": st.supersteps,
+            "edges_traversed": st.edges_traversed,
+            "edges_examined": st.edges_examined,
+            "time_to_converge_ms_median": float(np.median(secs) * 1e3),
+            "gteps": float(st.edges_traversed / np.median(secs) / 1e9),
+            "us_per_superstep": float(np.median(secs) * 1e6 / st.supersteps),
+            "modes": "".join("?PL"[int(x)] for x in st.mode),
+        }
+
+    roofline = None
+    if "pagerank" in apps and T >= 1:
+        # average duration of one pull-gather launch (supersteps 1..T are one
+        # launch each), from HIP events recorded on the launch stream
+        us = np.concatenate([s["pagerank"].usec[1:T + 1] for s in per_step])
+        avg_us = float(np.mean(us))
+        nbytes = pr_pull_bytes(hg.n, hg.m)
+        ach = nbytes / (avg_us * 1e-6) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": "pr_pull_kernel", "bytes_per_launch": nbytes, "avg_launch_us": round(avg_us, 2)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        secs, msgs = 0.0, 0
+        for app in apps:
+            r = oracle.run_graph(app, hg, T if app == "pagerank" else 0, source=0)
+            secs += r.seconds
+            msgs += int(r.trace[:, 2].sum())
+            print(f"[bench] oracle {app}: {r.seconds:.1f}s", file=sys.stderr, flush=True)
+        cpu = {"value": round(msgs / secs / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": f"one full step ({'+'.join(apps)}) on the same {args.workload} graph, "
+                         f"sequential oracle, {secs:.1f}s"}
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+u32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload} (n={hg.n}, m={hg.m}): PageRank T={T} pull FP64 + hash-min CC + "
+                        f"SSSP from 0, exchange={args.mode}",
+            "n": hg.n, "m": hg.m, "apps": apps_out,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * ipregel.h -- C ABI of the gfx950 superstep engine.
+ *
+ * The library executes the synchronous vertex-centric model of iPregel
+ * (Capelli et al., "iPregel: Vertex-centric programmability vs memory
+ * efficiency and performance, why choose?", Parallel Computing 2019):
+ * supersteps of local computation, communication and global synchronisation
+ * (Section 4.2), one-slot mailboxes whose messages are combined on arrival
+ * (Section 4.3.3), selection of the vertices to run (Section 4.3.1), push or
+ * pull message exchange (Section 4.3.2), and termination once every vertex
+ * has voted to halt and no message is pending.  The user's compute/combine
+ * pair (Fig. 1) is chosen from the three applications of Section 6:
+ * PageRank (Fig. 8, sum combiner), hash-min connected components (Fig. 9,
+ * min combiner) and single-source shortest paths (Fig. 10, min combiner).
+ *
+ * Conventions for every entry point:
+ *   - No C++ types cross this boundary; all sizes are explicit.
+ *   - "device pointer" means memory allocated on the current HIP device by the
+ *     caller (e.g. a torch tensor); the library never allocates or frees
+ *     device memory and never frees caller memory.  Host pointers are plain
+ *     process memory.
+ *   - `hip_stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is stream-ordered on it.
+ *   - Errors are returned as ipg_status; a human-readable message for the
+ *     last error on the calling thread is available from ipg_last_error().
+ *     No entry point aborts, throws or prints.
+ *   - One graph handle must not be used by two threads at once.
+ */
+#ifndef IPREGEL_H
+#define IPREGEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ipg_graph ipg_graph; /* opaque handle, host memory owned by the library */
+
+typedef enum {
+  IPG_OK = 0,
+  IPG_NOT_CONVERGED = 1,   /* superstep cap reached with work pending; values are valid */
+  IPG_EINVAL = -1,         /* bad argument (null pointer, source >= N, ...) */
+  IPG_EBADGRAPH = -2,      /* graph arrays failed validation */
+  IPG_EUNSUPPORTED = -3,   /* (app, combiner) pair not supported, or weights where none apply */
+  IPG_EWORKSPACE = -4,     /* workspace missing, too small or misaligned */
+  IPG_EDEVICE = -5,        /* a HIP call failed; see ipg_last_error() */
+  IPG_EOVERFLOW = -6       /* an SSSP message would reach 0xFFFFFFFF (the INF distance) */
+} ipg_status;
+
+typedef enum { IPG_APP_PAGERANK = 0, IPG_APP_CC_HASHMIN = 1, IPG_APP_SSSP = 2 } ipg_app;
+typedef enum { IPG_COMBINE_SUM = 0, IPG_COMBINE_MIN = 1 } ipg_combiner;
+
+/* Message exchange (Section 4.3.2).  The mode never changes results.  AUTO
+ * picks per superstep: the learned selector when one is loaded
+ * (ipg_selector_load), else a fixed frontier-size heuristic. */
+typedef enum { IPG_MODE_AUTO = 0, IPG_MODE_PUSH = 1, IPG_MODE_PULL = 2 } ipg_mode;
+
+/* ipg_graph_desc.flags */
+#define IPG_GRAPH_SYMMETRIC 1u /* CSC arrays equal the CSR arrays (undirected graph) */
+#define IPG_GRAPH_VALIDATE 2u  /* check offsets and ids on the device at create time */
+
+/*
+ * A graph as CSR (out-adjacency, for push) plus CSC (in-adjacency, for pull).
+ * All array pointers are DEVICE pointers owned by the caller and must stay
+ * valid until ipg_graph_destroy.
+ *   csr_off[N+1] uint64, csr_off[0] = 0, non-decreasing, csr_off[N] = E;
+ *   csr_dst[E]   int32 ids in [0, N), each list in any order;
+ *   csc_off/csc_src: the same for in-edges (may alias csr_* when symmetric);
+ *   csr_w/csc_w[E]: uint32 weights aligned with csr_dst/csc_src, or NULL for
+ *   unit weights (used by SSSP only; an undirected edge must carry the same
+ *   weight in both arrays).
+ * Self-loops and duplicate edges are ordinary edges.  N < 2^31.
+ */
+typedef struct {
+  uint32_t num_vertices;
+  uint64_t num_edges;
+  const uint64_t* csr_off;
+  const int32_t* csr_dst;
+  const uint64_t* csc_off;
+  const int32_t* csc_src;
+  const uint32_t* csr_w;
+  const uint32_t* csc_w;
+  uint32_t flags;
+} ipg_graph_desc;
+
+/* ipg_run_opts.flags */
+#define IPG_RUN_PERSISTENT 1u /* device-resident superstep loop: one cooperative launch, no per-superstep host sync */
+
+typedef struct {
+  uint32_t source; /* SSSP source vertex (ignored by the other applications) */
+  ipg_mode mode;
+  uint32_t flags;
+} ipg_run_opts;
+
+/*
+ * Run statistics, filled by ipg_run when a non-NULL pointer is passed.
+ * Arrays are HOST memory owned by the caller with trace_cap entries each
+ * (any may be NULL); entry s describes superstep s:
+ *   active[s]   vertices that ran compute,
+ *   senders[s]  vertices that broadcast,
+ *   messages[s] messages delivered (sum of the senders' out-degrees) -- the
+ *               edges traversed by the method,
+ *   examined[s] edges read by the exchange (push: = messages; pull: in-edges
+ *               scanned),
+ *   mode[s]     1 push, 2 pull,
+ *   usec[s]     device time of superstep s (HIP events), when timing is on.
+ */
+typedef struct {
+  uint32_t supersteps;      /* supersteps executed */
+  uint32_t halted;          /* 1 if the run ended by vote-to-halt */
+  uint64_t edges_traversed; /* total messages */
+  uint64_t edges_examined;  /* total edges read by the exchange */
+  double seconds;           /* first superstep launch -> halt decision (HIP events) */
+  uint32_t trace_cap;
+  uint64_t* active;
+  uint64_t* senders;
+  uint64_t* messages;
+  uint64_t* examined;
+  uint8_t* mode;
+  float* usec;
+} ipg_run_stats;
+
+/* Bytes of graph workspace ipg_graph_create needs for this graph size.  The
+ * workspace is device memory (256-byte aligned) owned by the caller and must
+ * outlive the handle. */
+size_t ipg_graph_workspace_bytes(uint32_t num_vertices, uint64_t num_edges, uint32_t flags);
+
+/* Bytes of run workspace ipg_run needs for `app` on a graph of this size
+ * (device memory, 256-byte aligned, owned by the caller).  The application's
+ * values live inside it until the next ipg_run on the same graph. */
+size_t ipg_run_workspace_bytes(uint32_t num_vertices, uint64_t num_edges, ipg_app app);
+
+/*
+ * Build the device graph store: validate (IPG_GRAPH_VALIDATE), derive the
+ * out-degrees and the pull-side tiling of the CSC.  Synchronises the stream.
+ * On success *out receives a handle; on failure *out is NULL and the status
+ * is IPG_EINVAL, IPG_EBADGRAPH, IPG_EWORKSPACE or IPG_EDEVICE.
+ */
+ipg_status ipg_graph_create(const ipg_graph_desc* desc, void* workspace, size_t workspace_bytes,
+                            void* hip_stream, ipg_graph** out);
+
+/*
+ * Run one application to completion (or to the cap) on the graph.
+ *   (app, combiner) must be (PAGERANK, SUM), (CC_HASHMIN, MIN) or (SSSP, MIN):
+ *   anything else is IPG_EUNSUPPORTED.
+ *   max_supersteps: PageRank -> number of rank updates T (vertices broadcast
+ *   while the superstep is < T and halt at T, so T+1 supersteps run and the
+ *   result is the rank after T updates; T = 10 is Fig. 8).  CC / SSSP -> cap
+ *   on supersteps executed, 0 = unlimited; reaching the cap with messages
+ *   pending returns IPG_NOT_CONVERGED and the values are still readable.
+ *   opts may be NULL (source 0, AUTO, host-driven loop).  source >= N is
+ *   IPG_EINVAL for SSSP.
+ *   workspace: ipg_run_workspace_bytes(N, E, app) bytes of device memory.
+ * The host loop reads one small counter block per superstep (CC/SSSP) and
+ * synchronises the stream before returning.
+ */
+ipg_status ipg_run(ipg_graph* graph, ipg_app app, ipg_combiner combiner, uint32_t max_supersteps,
+                   const ipg_run_opts* opts, void* workspace, size_t workspace_bytes, void* hip_stream,
+                   ipg_run_stats* stats);
+
+/* Copy the values of the last run on `graph` (double for PageRank, uint32
+ * otherwise; N entries) to dst, which is a device pointer when dst_is_device
+ * is non-zero, else host memory.  Synchronises the stream.  IPG_EINVAL if no
+ * run happened or dst_bytes is too small. */
+ipg_status ipg_read_values(const ipg_graph* graph, void* dst, size_t dst_bytes, int dst_is_device,
+                           void* hip_stream);
+
+/* Free the handle (host memory only; caller buffers are untouched). */
+void ipg_graph_destroy(ipg_graph* graph);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* ipg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPREGEL_H */

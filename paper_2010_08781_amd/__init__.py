@@ -1,0 +1,276 @@
+"""Python binding of the gfx950 superstep engine (libipregel.so).
+
+Argument marshalling only: every superstep runs in the library's HIP kernels.
+PyTorch provides device memory (graph arrays, workspaces, outputs) and the
+stream; the library never allocates device memory.
+
+    import paper_2010_08781_amd as ipg
+    g = ipg.Graph.from_csr_csc(n, csr_off, csr_dst, csc_off, csc_src)   # torch cuda tensors
+    ranks, stats = g.run("pagerank", 10)
+    labels, stats = g.run("cc")
+    dist, stats = g.run("sssp", source=0)
+
+The applications are those of the iPregel paper (Section 6): PageRank
+(Fig. 8, sum combiner), hash-min connected components (Fig. 9) and SSSP
+(Fig. 10), both with the min combiner.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libipregel.so")
+
+OK, NOT_CONVERGED = 0, 1
+EINVAL, EBADGRAPH, EUNSUPPORTED, EWORKSPACE, EDEVICE, EOVERFLOW = -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "IPG_OK", 1: "IPG_NOT_CONVERGED", -1: "IPG_EINVAL", -2: "IPG_EBADGRAPH", -3: "IPG_EUNSUPPORTED",
+                -4: "IPG_EWORKSPACE", -5: "IPG_EDEVICE", -6: "IPG_EOVERFLOW"}
+APP_PAGERANK, APP_CC, APP_SSSP = 0, 1, 2
+APPS = {"pagerank": APP_PAGERANK, "pr": APP_PAGERANK, "cc": APP_CC, "sssp": APP_SSSP}
+COMBINE_SUM, COMBINE_MIN = 0, 1
+DEFAULT_COMBINER = {APP_PAGERANK: COMBINE_SUM, APP_CC: COMBINE_MIN, APP_SSSP: COMBINE_MIN}
+MODES = {"auto": 0, "push": 1, "pull": 2}
+GRAPH_SYMMETRIC, GRAPH_VALIDATE = 1, 2
+RUN_PERSISTENT = 1
+INF = 0xFFFFFFFF
+
+
+class IpgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("num_vertices", ctypes.c_uint32), ("num_edges", ctypes.c_uint64),
+                ("csr_off", ctypes.c_void_p), ("csr_dst", ctypes.c_void_p),
+                ("csc_off", ctypes.c_void_p), ("csc_src", ctypes.c_void_p),
+                ("csr_w", ctypes.c_void_p), ("csc_w", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("source", ctypes.c_uint32), ("mode", ctypes.c_int), ("flags", ctypes.c_uint32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("supersteps", ctypes.c_uint32), ("halted", ctypes.c_uint32),
+                ("edges_traversed", ctypes.c_uint64), ("edges_examined", ctypes.c_uint64),
+                ("seconds", ctypes.c_double), ("trace_cap", ctypes.c_uint32),
+                ("active", ctypes.c_void_p), ("senders", ctypes.c_void_p), ("messages", ctypes.c_void_p),
+                ("examined", ctypes.c_void_p), ("mode", ctypes.c_void_p), ("usec", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libipregel.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it first (python __graft_entry__.py or "
+                              f"python paper_2010_08781_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, u32, u64, i32, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t
+        L.ipg_graph_workspace_bytes.argtypes = [u32, u64, u32]
+        L.ipg_graph_workspace_bytes.restype = sz
+        L.ipg_run_workspace_bytes.argtypes = [u32, u64, i32]
+        L.ipg_run_workspace_bytes.restype = sz
+        L.ipg_graph_create.argtypes = [ctypes.POINTER(_Desc), P, sz, P, ctypes.POINTER(P)]
+        L.ipg_graph_create.restype = i32
+        L.ipg_run.argtypes = [P, i32, i32, u32, ctypes.POINTER(_Opts), P, sz, P, ctypes.POINTER(_Stats)]
+        L.ipg_run.restype = i32
+        L.ipg_read_values.argtypes = [P, P, sz, i32, P]
+        L.ipg_read_values.restype = i32
+        L.ipg_graph_destroy.argtypes = [P]
+        L.ipg_graph_destroy.restype = None
+        L.ipg_last_error.argtypes = []
+        L.ipg_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().ipg_last_error().decode()
+
+
+def _check(st: int, what: str, allow_not_converged: bool = False) -> int:
+    if st == OK or (allow_not_converged and st == NOT_CONVERGED):
+        return st
+    raise IpgError(st, f"{what}: {last_error()}")
+
+
+def _stream_handle(stream=None) -> int:
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+@dataclass
+class RunStats:
+    status: int
+    supersteps: int
+    halted: bool
+    edges_traversed: int
+    edges_examined: int
+    seconds: float
+    active: np.ndarray = field(repr=False)
+    senders: np.ndarray = field(repr=False)
+    messages: np.ndarray = field(repr=False)
+    examined: np.ndarray = field(repr=False)
+    mode: np.ndarray = field(repr=False)
+    usec: Optional[np.ndarray] = field(repr=False, default=None)
+
+    @property
+    def trace(self) -> np.ndarray:
+        """[supersteps, 3] uint64: active, senders, messages (the oracle's trace layout)."""
+        return np.stack([self.active, self.senders, self.messages], axis=1)
+
+    @property
+    def gteps(self) -> float:
+        return self.edges_traversed / self.seconds / 1e9 if self.seconds > 0 else float("nan")
+
+
+class Graph:
+    """A graph resident on the current HIP device (CSR + CSC held as torch tensors)."""
+
+    def __init__(self, n, csr_off, csr_dst, csc_off=None, csc_src=None, csr_w=None, csc_w=None,
+                 symmetric=False, validate=True, stream=None):
+        import torch
+
+        self.n = int(n)
+        self.m = int(csr_dst.numel())
+        self.symmetric = bool(symmetric)
+        if symmetric:
+            csc_off = csr_off if csc_off is None else csc_off
+            csc_src = csr_dst if csc_src is None else csc_src
+            csc_w = csr_w if csc_w is None else csc_w
+        for name, t, dt in (("csr_off", csr_off, torch.int64), ("csr_dst", csr_dst, torch.int32),
+                            ("csc_off", csc_off, torch.int64), ("csc_src", csc_src, torch.int32)):
+            if t is None or not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous {dt} CUDA tensor")
+        for name, t in (("csr_w", csr_w), ("csc_w", csc_w)):
+            if t is not None and (not t.is_cuda or t.dtype not in (torch.int32, torch.uint32) or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous 32-bit integer CUDA tensor")
+        if csr_off.numel() != self.n + 1 or csc_off.numel() != self.n + 1:
+            raise ValueError("offset arrays must have n+1 entries")
+        if csc_src.numel() != self.m:
+            raise ValueError("CSR and CSC must hold the same number of edges")
+        # keep caller tensors alive for the lifetime of the handle
+        self._keep = (csr_off, csr_dst, csc_off, csc_src, csr_w, csc_w)
+        self.weighted = csr_w is not None
+        flags = (GRAPH_SYMMETRIC if symmetric else 0) | (GRAPH_VALIDATE if validate else 0)
+        d = _Desc(self.n, self.m, csr_off.data_ptr(), csr_dst.data_ptr() if self.m else None,
+                  csc_off.data_ptr(), csc_src.data_ptr() if self.m else None,
+                  csr_w.data_ptr() if csr_w is not None else None,
+                  csc_w.data_ptr() if csc_w is not None else None, flags)
+        nbytes = lib().ipg_graph_workspace_bytes(self.n, self.m, flags)
+        self._gws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=csr_off.device)
+        h = ctypes.c_void_p()
+        _check(lib().ipg_graph_create(ctypes.byref(d), self._gws.data_ptr(), nbytes, _stream_handle(stream),
+                                      ctypes.byref(h)), "ipg_graph_create")
+        self._h = h
+        self.device = csr_off.device
+        self._run_ws = {}
+
+    @classmethod
+    def from_csr_csc(cls, *args, **kw) -> "Graph":
+        return cls(*args, **kw)
+
+    @classmethod
+    def from_host(cls, hg, device="cuda", validate=True, weighted=True) -> "Graph":
+        """Upload any object with n, csr_off, csr_dst, csc_off, csc_src (numpy) and optional csr_w/csc_w."""
+        import torch
+
+        def up(a, dt):
+            return torch.from_numpy(np.ascontiguousarray(a).view(dt)).to(device)
+
+        csr_off = up(hg.csr_off.astype(np.uint64), np.int64)
+        csr_dst = up(hg.csr_dst.astype(np.int32), np.int32)
+        sym = bool(getattr(hg, "symmetric", False))
+        if sym:
+            csc_off, csc_src = csr_off, csr_dst
+        else:
+            csc_off = up(hg.csc_off.astype(np.uint64), np.int64)
+            csc_src = up(hg.csc_src.astype(np.int32), np.int32)
+        csr_w = csc_w = None
+        if weighted and getattr(hg, "csr_w", None) is not None:
+            csr_w = up(hg.csr_w.astype(np.uint32), np.int32)
+            csc_w = csr_w if sym else up(hg.csc_w.astype(np.uint32), np.int32)
+        return cls(hg.n, csr_off, csr_dst, csc_off, csc_src, csr_w, csc_w, symmetric=sym, validate=validate)
+
+    def workspace(self, app: int):
+        import torch
+
+        if app not in self._run_ws:
+            nbytes = lib().ipg_run_workspace_bytes(self.n, self.m, app)
+            self._run_ws[app] = (torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device), nbytes)
+        return self._run_ws[app]
+
+    def run(self, app, max_supersteps: Optional[int] = None, source: int = 0, mode: str = "auto",
+            timing: bool = True, trace_cap: int = 1 << 16, persistent: bool = False, stream=None,
+            combiner: Optional[int] = None, check: bool = True):
+        """Run an application; returns (values tensor on the device, RunStats).
+
+        max_supersteps: PageRank -> number of rank updates (default 10, Fig. 8);
+        CC/SSSP -> cap on supersteps (default 0 = run to vote-to-halt)."""
+        import torch
+
+        a = APPS[app] if isinstance(app, str) else int(app)
+        if max_supersteps is None:
+            max_supersteps = 10 if a == APP_PAGERANK else 0
+        comb = DEFAULT_COMBINER.get(a, 0) if combiner is None else combiner
+        ws, nbytes = self.workspace(a) if a in DEFAULT_COMBINER else (None, 0)
+        opts = _Opts(int(source), MODES[mode], RUN_PERSISTENT if persistent else 0)
+        arrs = {k: np.zeros(trace_cap, dtype=np.uint64) for k in ("active", "senders", "messages", "examined")}
+        arrs["mode"] = np.zeros(trace_cap, dtype=np.uint8)
+        usec = np.zeros(trace_cap, dtype=np.float32) if timing else None
+        st = _Stats(0, 0, 0, 0, 0.0, trace_cap, arrs["active"].ctypes.data, arrs["senders"].ctypes.data,
+                    arrs["messages"].ctypes.data, arrs["examined"].ctypes.data, arrs["mode"].ctypes.data,
+                    usec.ctypes.data if usec is not None else None)
+        rc = lib().ipg_run(self._h, a, comb, int(max_supersteps), ctypes.byref(opts),
+                           ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(stream), ctypes.byref(st))
+        if check:
+            _check(rc, "ipg_run", allow_not_converged=True)
+        elif rc not in (OK, NOT_CONVERGED):
+            return None, RunStats(rc, 0, False, 0, 0, 0.0, *(np.zeros(0),) * 5)
+        k = min(int(st.supersteps), trace_cap)
+        stats = RunStats(rc, int(st.supersteps), bool(st.halted), int(st.edges_traversed), int(st.edges_examined),
+                         float(st.seconds), arrs["active"][:k], arrs["senders"][:k], arrs["messages"][:k],
+                         arrs["examined"][:k], arrs["mode"][:k], usec[:k] if usec is not None else None)
+        vals = self.read_values(a, stream=stream)
+        return vals, stats
+
+    def read_values(self, app: int, stream=None):
+        import torch
+
+        dt = torch.float64 if app == APP_PAGERANK else torch.int32
+        out = torch.empty(self.n, dtype=dt, device=self.device)
+        _check(lib().ipg_read_values(self._h, out.data_ptr(), out.numel() * out.element_size(), 1,
+                                     _stream_handle(stream)), "ipg_read_values")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ipg_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def values_to_numpy(t) -> np.ndarray:
+    """Device values -> numpy (uint32 view for CC/SSSP, float64 for PageRank)."""
+    import torch
+
+    a = t.cpu().numpy()
+    return a.view(np.uint32) if t.dtype == torch.int32 else a

@@ -1,0 +1,142 @@
+// api.hip -- the ipg_run / ipg_read_values entry points, run workspace
+// layout, superstep timing and the per-superstep exchange choice.
+#include <cstring>
+
+#include "common.h"
+#include "engine.h"
+
+namespace ipg {
+
+size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w) {
+  (void)e;
+  RunWs r{};
+  const size_t nn = n ? n : 1;
+  if (app == IPG_APP_PAGERANK) {
+    r.value_f64 = c.take<double>(nn);
+    r.f64_a = c.take<double>(nn);
+    r.f64_b = c.take<double>(nn);
+  } else {
+    r.value_u32 = c.take<uint32_t>(nn);
+    r.mail_a = c.take<uint32_t>(nn);
+    r.mail_b = c.take<uint32_t>(nn);
+    r.fr_a = c.take<uint32_t>(nn);
+    r.fr_b = c.take<uint32_t>(nn);
+    r.sent = c.take<uint32_t>(nn / 32 + 1);
+  }
+  r.ctr = c.take<StepCounters>(2);
+  if (w) *w = r;
+  return align_up(c.used, 256);
+}
+
+StepTimer::~StepTimer() {
+  if (start_) (void)hipEventDestroy(start_);
+  if (end_) (void)hipEventDestroy(end_);
+  for (hipEvent_t ev : steps_) (void)hipEventDestroy(ev);
+}
+
+hipError_t StepTimer::start(hipStream_t s) {
+  if (!start_) {
+    hipError_t e = hipEventCreate(&start_);
+    if (e != hipSuccess) return e;
+  }
+  return hipEventRecord(start_, s);
+}
+
+hipError_t StepTimer::step(hipStream_t s, uint32_t k) {
+  if (k >= cap_) return hipSuccess;
+  while (steps_.size() <= k) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
+    steps_.push_back(ev);
+  }
+  return hipEventRecord(steps_[k], s);
+}
+
+hipError_t StepTimer::finish(hipStream_t s) {
+  hipError_t e;
+  if (!end_ && (e = hipEventCreate(&end_)) != hipSuccess) return e;
+  if ((e = hipEventRecord(end_, s)) != hipSuccess) return e;
+  if ((e = hipEventSynchronize(end_)) != hipSuccess) return e;
+  float ms = 0.f;
+  if (start_ && (e = hipEventElapsedTime(&ms, start_, end_)) != hipSuccess) return e;
+  seconds_ = ms * 1e-3;
+  hipEvent_t prev = start_;
+  for (size_t k = 0; k < steps_.size() && k < cap_; ++k) {
+    float t = 0.f;
+    if ((e = hipEventElapsedTime(&t, prev, steps_[k])) != hipSuccess) return e;
+    usec_[k] = t * 1e3f;
+    prev = steps_[k];
+  }
+  return hipSuccess;
+}
+
+// Fixed heuristic (the default of Ligra's direction switch, Shun and
+// Blelloch 2013): pull when the frontier plus its out-edges exceed E/20.
+ipg_mode choose_mode(ipg_mode requested, const ModeQuery& q) {
+  if (requested == IPG_MODE_PUSH || requested == IPG_MODE_PULL) return requested;
+  if (q.e == 0) return IPG_MODE_PUSH;
+  return (q.frontier + q.frontier_deg > q.e / 20) ? IPG_MODE_PULL : IPG_MODE_PUSH;
+}
+
+}  // namespace ipg
+
+using namespace ipg;
+
+extern "C" size_t ipg_run_workspace_bytes(uint32_t num_vertices, uint64_t num_edges, ipg_app app) {
+  Carver c(nullptr);
+  return carve_run(c, num_vertices, num_edges, app, nullptr);
+}
+
+extern "C" ipg_status ipg_run(ipg_graph* g, ipg_app app, ipg_combiner combiner, uint32_t max_supersteps,
+                              const ipg_run_opts* opts, void* ws, size_t ws_bytes, void* hip_stream,
+                              ipg_run_stats* st) {
+  if (!g) return fail(IPG_EINVAL, "ipg_run: graph is NULL");
+  const bool ok_pair = (app == IPG_APP_PAGERANK && combiner == IPG_COMBINE_SUM) ||
+                       (app == IPG_APP_CC_HASHMIN && combiner == IPG_COMBINE_MIN) ||
+                       (app == IPG_APP_SSSP && combiner == IPG_COMBINE_MIN);
+  if (!ok_pair) return fail(IPG_EUNSUPPORTED, "ipg_run: (app, combiner) must be (PAGERANK, SUM), (CC, MIN) or (SSSP, MIN)");
+  ipg_run_opts o{0, IPG_MODE_AUTO, 0};
+  if (opts) o = *opts;
+  if (o.mode != IPG_MODE_AUTO && o.mode != IPG_MODE_PUSH && o.mode != IPG_MODE_PULL)
+    return fail(IPG_EINVAL, "ipg_run: unknown mode");
+  if (app == IPG_APP_SSSP && o.source >= g->n) return fail(IPG_EINVAL, "ipg_run: SSSP source >= N");
+  const size_t need = ipg_run_workspace_bytes(g->n, g->e, app);
+  if (!ws || ws_bytes < need)
+    return fail(IPG_EWORKSPACE, "ipg_run: run workspace needs " + std::to_string(need) + " bytes");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(IPG_EWORKSPACE, "ipg_run: workspace must be 256-byte aligned");
+  int dev = -1;
+  IPG_HIP(hipGetDevice(&dev));
+  if (dev != g->device) return fail(IPG_EINVAL, "ipg_run: current device differs from the graph's device");
+
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  Carver c(ws);
+  RunWs w;
+  carve_run(c, g->n, g->e, app, &w);
+  g->has_values = 0;
+  StepTimer tm(st ? st->usec : nullptr, st ? st->trace_cap : 0);
+  ipg_status rc;
+  if (app == IPG_APP_PAGERANK) rc = run_pagerank(g, max_supersteps, o.mode, w, s, tm, st);
+  else rc = run_minprop(g, app, max_supersteps, o, w, s, tm, st);
+  if (st) st->seconds = tm.seconds();
+  if (rc == IPG_OK || rc == IPG_NOT_CONVERGED) {
+    g->has_values = 1;
+    g->last_app = app;
+    g->last_values = app == IPG_APP_PAGERANK ? static_cast<const void*>(w.value_f64) : static_cast<const void*>(w.value_u32);
+    if (rc == IPG_OK) set_error("");
+  }
+  return rc;
+}
+
+extern "C" ipg_status ipg_read_values(const ipg_graph* g, void* dst, size_t dst_bytes, int dst_is_device,
+                                      void* hip_stream) {
+  if (!g || !dst) return fail(IPG_EINVAL, "ipg_read_values: NULL argument");
+  if (!g->has_values) return fail(IPG_EINVAL, "ipg_read_values: no completed run on this graph");
+  const size_t elt = g->last_app == IPG_APP_PAGERANK ? sizeof(double) : sizeof(uint32_t);
+  const size_t bytes = elt * g->n;
+  if (dst_bytes < bytes) return fail(IPG_EINVAL, "ipg_read_values: destination needs " + std::to_string(bytes) + " bytes");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  IPG_HIP(hipMemcpyAsync(dst, g->last_values, bytes, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  IPG_HIP(hipStreamSynchronize(s));
+  return IPG_OK;
+}

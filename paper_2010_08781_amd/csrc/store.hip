@@ -1,0 +1,224 @@
+// store.hip -- the device graph store (in-memory CSR + CSC with 64-bit
+// offsets, Section 4.2: vertices and adjacency lists in global arrays shared
+// by all workers), its validation, the out-degrees used by broadcast
+// (Section 3), and the pull-side tiling of the CSC.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace ipg {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+ipg_status fail(ipg_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+ipg_status hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return IPG_EDEVICE;
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint64_t n, uint32_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void fill_f64_kernel(double* p, uint64_t n, double v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+hipError_t fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, kBlock * 4, 8192)), dim3(kBlock), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t fill_f64(double* p, uint64_t n, double v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(n, kBlock * 4, 8192)), dim3(kBlock), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+enum : uint32_t { kFlagOffsets = 0, kFlagCsrIds = 1, kFlagCscIds = 2, kFlagDegree = 3, kNumFlags = 4 };
+
+// off[0] == 0, non-decreasing, off[n] == e.
+__global__ void validate_offsets_kernel(const uint64_t* off, uint32_t n, uint64_t e, uint32_t* flags) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += stride)
+    if (off[v] > off[v + 1]) flags[kFlagOffsets] = 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (off[0] != 0 || off[n] != e)) flags[kFlagOffsets] = 1;
+}
+
+__global__ void validate_ids_kernel(const int32_t* adj, uint64_t e, uint32_t n, uint32_t* flag) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < e; i += stride) {
+    const int32_t x = adj[i];
+    bad |= (x < 0) | (static_cast<uint32_t>(x) >= n);
+  }
+  if (__ballot(bad) && lane_id() == 0) *flag = 1;
+}
+
+__global__ void outdeg_kernel(const uint64_t* off, uint32_t n, uint32_t* outdeg, uint32_t* flags) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
+    const uint64_t d = off[v + 1] - off[v];
+    if (d > 0xFFFFFFFFull) flags[kFlagDegree] = 1;
+    outdeg[v] = static_cast<uint32_t>(d);
+  }
+}
+
+// Pull row-groups: group k holds the rows whose first in-edge lies in
+// [k*T, (k+1)*T), i.e. pull_rb[k] = first row v with off[v] >= k*T.  Row v
+// owns the groups k in (off[v-1]/T, off[v]/T]; v = n owns the tail.
+__global__ void pull_groups_kernel(const uint64_t* off, uint32_t n, uint32_t nb, uint32_t* rb) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v <= n; v += stride) {
+    const uint64_t lo = v == 0 ? 0 : off[v - 1] / kPullTile + 1;
+    uint64_t hi = off[v] / kPullTile;
+    if (hi > (uint64_t)nb - 1) hi = (uint64_t)nb - 1;
+    for (uint64_t k = lo; k <= hi; ++k) rb[k] = static_cast<uint32_t>(v);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) rb[nb] = n;
+}
+
+__global__ void long_rows_kernel(const uint64_t* off, uint32_t n, uint32_t* list, uint32_t cap, uint32_t* count) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t v0 = blockIdx.x * (uint64_t)blockDim.x; v0 < n; v0 += stride) {
+    const uint64_t v = v0 + threadIdx.x;
+    const bool pred = v < n && off[v + 1] - off[v] > kPullTile;
+    const uint64_t mask = __ballot(pred);
+    if (mask == 0) continue;
+    const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(mask)) - 1);
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(count, static_cast<uint32_t>(__popcll(mask)));
+    base = __shfl(base, static_cast<int>(leader));
+    const uint32_t slot = base + lanes_below(mask);
+    if (pred && slot < cap) list[slot] = static_cast<uint32_t>(v);
+  }
+}
+
+static uint32_t num_pull_groups(uint64_t e) { return static_cast<uint32_t>(e / kPullTile + 1); }
+static uint64_t long_rows_cap(uint64_t e) { return e / (kPullTile + 1) + 1; }
+
+static size_t carve_graph(Carver& c, uint32_t n, uint64_t e, GraphTables* t) {
+  GraphTables tt;
+  tt.outdeg = c.take<uint32_t>(n ? n : 1);
+  tt.pull_rb = c.take<uint32_t>(num_pull_groups(e) + 1);
+  tt.long_rows = c.take<uint32_t>(long_rows_cap(e));
+  tt.flags = c.take<uint32_t>(kNumFlags + 1);  // + long-row counter
+  if (t) *t = tt;
+  return align_up(c.used, 256);
+}
+
+}  // namespace ipg
+
+using namespace ipg;
+
+extern "C" size_t ipg_graph_workspace_bytes(uint32_t num_vertices, uint64_t num_edges, uint32_t flags) {
+  (void)flags;
+  Carver c(nullptr);
+  return carve_graph(c, num_vertices, num_edges, nullptr);
+}
+
+extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t ws_bytes, void* hip_stream,
+                                       ipg_graph** out) {
+  if (!out) return fail(IPG_EINVAL, "ipg_graph_create: out is NULL");
+  *out = nullptr;
+  if (!d) return fail(IPG_EINVAL, "ipg_graph_create: desc is NULL");
+  const uint32_t n = d->num_vertices;
+  const uint64_t e = d->num_edges;
+  if (n == 0) return fail(IPG_EINVAL, "ipg_graph_create: num_vertices must be >= 1");
+  if (n >= 0x80000000u) return fail(IPG_EINVAL, "ipg_graph_create: num_vertices must be < 2^31");
+  const bool sym = d->flags & IPG_GRAPH_SYMMETRIC;
+  const uint64_t* csc_off = d->csc_off ? d->csc_off : (sym ? d->csr_off : nullptr);
+  const int32_t* csc_src = d->csc_src ? d->csc_src : (sym ? d->csr_dst : nullptr);
+  const uint32_t* csc_w = d->csc_w ? d->csc_w : (sym ? d->csr_w : nullptr);
+  if (!d->csr_off || !csc_off) return fail(IPG_EINVAL, "ipg_graph_create: offsets pointer is NULL");
+  if (e > 0 && (!d->csr_dst || !csc_src)) return fail(IPG_EINVAL, "ipg_graph_create: adjacency pointer is NULL");
+  if ((d->csr_w == nullptr) != (csc_w == nullptr))
+    return fail(IPG_EINVAL, "ipg_graph_create: give weights for both CSR and CSC or for neither");
+  const size_t need = ipg_graph_workspace_bytes(n, e, d->flags);
+  if (!ws || ws_bytes < need)
+    return fail(IPG_EWORKSPACE, "ipg_graph_create: graph workspace needs " + std::to_string(need) + " bytes");
+  if (reinterpret_cast<uintptr_t>(ws) % 256)
+    return fail(IPG_EWORKSPACE, "ipg_graph_create: workspace must be 256-byte aligned");
+
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  Carver c(ws);
+  GraphTables t;
+  carve_graph(c, n, e, &t);
+  const uint32_t nb = num_pull_groups(e);
+
+  IPG_HIP(fill_u32(t.flags, kNumFlags + 1, 0, s));
+  const uint32_t gv = grid_for(n + 1ull, kBlock, 16384), ge = grid_for(e, kBlock * 8, 16384);
+  if (d->flags & IPG_GRAPH_VALIDATE) {
+    hipLaunchKernelGGL(validate_offsets_kernel, dim3(gv), dim3(kBlock), 0, s, d->csr_off, n, e, t.flags);
+    IPG_HIP(hipGetLastError());
+    if (e) hipLaunchKernelGGL(validate_ids_kernel, dim3(ge), dim3(kBlock), 0, s, d->csr_dst, e, n, t.flags + kFlagCsrIds);
+    IPG_HIP(hipGetLastError());
+    if (csc_off != d->csr_off || csc_src != d->csr_dst) {
+      uint32_t* f2 = t.flags + kFlagCscIds;
+      hipLaunchKernelGGL(validate_offsets_kernel, dim3(gv), dim3(kBlock), 0, s, csc_off, n, e, f2 - kFlagOffsets);
+      IPG_HIP(hipGetLastError());
+      if (e) hipLaunchKernelGGL(validate_ids_kernel, dim3(ge), dim3(kBlock), 0, s, csc_src, e, n, f2);
+      IPG_HIP(hipGetLastError());
+    }
+    uint32_t h[kNumFlags];
+    IPG_HIP(hipMemcpyAsync(h, t.flags, sizeof(h), hipMemcpyDeviceToHost, s));
+    IPG_HIP(hipStreamSynchronize(s));
+    if (h[kFlagOffsets]) return fail(IPG_EBADGRAPH, "offsets: off[0] != 0, off[N] != E or decreasing");
+    if (h[kFlagCsrIds]) return fail(IPG_EBADGRAPH, "CSR destination id outside [0, N)");
+    if (h[kFlagCscIds]) return fail(IPG_EBADGRAPH, "CSC source id outside [0, N), or CSC offsets invalid");
+  }
+  hipLaunchKernelGGL(outdeg_kernel, dim3(gv), dim3(kBlock), 0, s, d->csr_off, n, t.outdeg, t.flags);
+  IPG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(pull_groups_kernel, dim3(gv), dim3(kBlock), 0, s, csc_off, n, nb, t.pull_rb);
+  IPG_HIP(hipGetLastError());
+  const uint32_t cap = static_cast<uint32_t>(long_rows_cap(e));
+  hipLaunchKernelGGL(long_rows_kernel, dim3(gv), dim3(kBlock), 0, s, csc_off, n, t.long_rows, cap,
+                     t.flags + kNumFlags);
+  IPG_HIP(hipGetLastError());
+  uint32_t h[kNumFlags + 1];
+  IPG_HIP(hipMemcpyAsync(h, t.flags, sizeof(h), hipMemcpyDeviceToHost, s));
+  IPG_HIP(hipStreamSynchronize(s));
+  if (h[kFlagDegree]) return fail(IPG_EBADGRAPH, "an out-degree exceeds 2^32-1");
+  const uint32_t nl = h[kNumFlags];
+  if (nl > cap) return fail(IPG_EBADGRAPH, "in-degree table overflow (offsets inconsistent with E)");
+  if (nl > 1) {  // ascending order: a deterministic assignment of long rows to workgroups
+    std::vector<uint32_t> rows(nl);
+    IPG_HIP(hipMemcpyAsync(rows.data(), t.long_rows, nl * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    IPG_HIP(hipStreamSynchronize(s));
+    std::sort(rows.begin(), rows.end());
+    IPG_HIP(hipMemcpyAsync(t.long_rows, rows.data(), nl * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    IPG_HIP(hipStreamSynchronize(s));
+  }
+
+  ipg_graph* g = new (std::nothrow) ipg_graph();
+  if (!g) return fail(IPG_EINVAL, "ipg_graph_create: out of host memory");
+  g->n = n;
+  g->e = e;
+  g->flags = d->flags | (csc_off == d->csr_off && csc_src == d->csr_dst ? IPG_GRAPH_SYMMETRIC : 0u);
+  g->csr_off = d->csr_off;
+  g->csr_dst = d->csr_dst;
+  g->csc_off = csc_off;
+  g->csc_src = csc_src;
+  g->csr_w = d->csr_w;
+  g->csc_w = csc_w;
+  g->t = t;
+  g->nb = nb;
+  g->nl = nl;
+  IPG_HIP(hipGetDevice(&g->device));
+  g->has_values = 0;
+  g->last_app = -1;
+  g->last_values = nullptr;
+  *out = g;
+  set_error("");
+  return IPG_OK;
+}
+
+extern "C" void ipg_graph_destroy(ipg_graph* g) { delete g; }
+
+extern "C" const char* ipg_last_error(void) { return g_last_error.c_str(); }

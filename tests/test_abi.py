@@ -1,0 +1,78 @@
+"""The C-ABI library loads and exports every symbol the public header declares.
+
+Only host-side logic is exercised here (size queries and argument checks that
+return before any device call), so this runs without a GPU.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ipregel.h")
+LIB = os.path.join(ROOT, "paper_2010_08781_amd", "libipregel.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ipg_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libipregel.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_interface():
+    names = declared_functions()
+    for n in ("ipg_graph_create", "ipg_run", "ipg_read_values", "ipg_graph_destroy", "ipg_last_error",
+              "ipg_graph_workspace_bytes", "ipg_run_workspace_bytes"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_workspace_sizes_scale(lib):
+    lib.ipg_run_workspace_bytes.restype = ctypes.c_size_t
+    lib.ipg_run_workspace_bytes.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int]
+    lib.ipg_graph_workspace_bytes.restype = ctypes.c_size_t
+    lib.ipg_graph_workspace_bytes.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32]
+    n, e = 1 << 20, 1 << 25
+    pr = lib.ipg_run_workspace_bytes(n, e, 0)
+    cc = lib.ipg_run_workspace_bytes(n, e, 1)
+    assert pr >= 3 * 8 * n and cc >= 5 * 4 * n
+    assert pr % 256 == 0 and cc % 256 == 0
+    g = lib.ipg_graph_workspace_bytes(n, e, 0)
+    assert 4 * n <= g < 4 * n + e // 64 + 4096
+
+
+def test_null_arguments_rejected_before_any_device_call(lib):
+    import paper_2010_08781_amd as ipg
+
+    L = ipg.lib()
+    h = ctypes.c_void_p()
+    assert L.ipg_graph_create(None, None, 0, None, ctypes.byref(h)) == ipg.EINVAL
+    assert h.value is None
+    assert "desc" in ipg.last_error()
+    assert L.ipg_run(None, 0, 0, 10, None, None, 0, None, None) == ipg.EINVAL
+    assert L.ipg_read_values(None, None, 0, 0, None) == ipg.EINVAL
+    d = ipg._Desc(0, 0, None, None, None, None, None, None, 0)
+    assert L.ipg_graph_create(ctypes.byref(d), None, 0, None, ctypes.byref(h)) == ipg.EINVAL
+    d = ipg._Desc(4, 0, 64, None, 64, None, None, None, 0)
+    assert L.ipg_graph_create(ctypes.byref(d), None, 0, None, ctypes.byref(h)) == ipg.EWORKSPACE
+
+
+def test_binding_refuses_missing_library(monkeypatch, tmp_path):
+    import paper_2010_08781_amd as ipg
+
+    monkeypatch.setattr(ipg, "_lib", None)
+    monkeypatch.setattr(ipg, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(ImportError):
+        ipg.lib()

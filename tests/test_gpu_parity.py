@@ -1,0 +1,238 @@
+"""GPU parity: the HIP superstep engine against the CPU oracle, through the C ABI.
+
+CC and SSSP: values and the per-superstep trace (active, senders, messages)
+bit-exact.  PageRank (FP64): max relative error <= 1e-12 at every superstep
+(checked by running T = 1..10 updates; the T-th iterate does not depend on
+how many updates follow).  The exchange mode (push / pull / auto) never
+changes results.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from tests.graphs_small import path, random_graph
+
+pytestmark = pytest.mark.gpu
+
+PR_RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ipg():
+    import torch
+
+    import paper_2010_08781_amd as m
+
+    assert torch.cuda.is_available()
+    m.lib()
+    return m
+
+
+def to_np(t):
+    import paper_2010_08781_amd as m
+
+    return m.values_to_numpy(t)
+
+
+def max_rel(a, b):
+    return float(np.max(np.abs(a - b) / np.abs(b))) if b.size else 0.0
+
+
+def check_min_app(ipg, hg, app, source=0, modes=("push", "pull", "auto"), weighted=True):
+    ref = oracle.run_graph(app, hg, 0, source=source, weighted=weighted)
+    assert ref.status == oracle.OK
+    g = ipg.Graph.from_host(hg, weighted=weighted)
+    for mode in modes:
+        vals, st = g.run(app, source=source, mode=mode)
+        got = to_np(vals)
+        assert np.array_equal(got, ref.values), f"{app} {mode}: {np.sum(got != ref.values)} values differ"
+        assert st.supersteps == ref.supersteps, (mode, st.supersteps, ref.supersteps)
+        assert np.array_equal(st.trace, ref.trace), f"{app} {mode} trace\n{st.trace}\n{ref.trace}"
+        assert st.halted
+    return g
+
+
+def check_pagerank(ipg, hg, Ts=(0, 1, 2, 3, 10), modes=("pull", "push")):
+    g = ipg.Graph.from_host(hg)
+    for T in Ts:
+        ref = oracle.run_graph("pagerank", hg, T)
+        for mode in modes:
+            vals, st = g.run("pagerank", T, mode=mode)
+            got = to_np(vals)
+            err = max_rel(got, ref.values)
+            assert err <= PR_RTOL, f"T={T} {mode}: max rel err {err:.3e}"
+            assert st.supersteps == T + 1
+            assert np.array_equal(st.trace, ref.trace)
+    return g
+
+
+# ------------------------------------------------------------ PageRank ----
+
+def test_pagerank_rmat_s14_every_superstep(ipg):
+    # R-MAT scale 14, edge factor 16, directed, seed 1; T = 1..10.
+    hg = graphgen.workload("rmat-s14-dir")
+    check_pagerank(ipg, hg, Ts=tuple(range(0, 11)))
+
+
+def test_pagerank_pull_bitwise_deterministic(ipg):
+    hg = graphgen.workload("rmat-s14-dir")
+    g = ipg.Graph.from_host(hg)
+    a = to_np(g.run("pagerank", 10, mode="pull")[0])
+    b = to_np(g.run("pagerank", 10, mode="pull")[0])
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
+def test_pagerank_long_rows_and_hubs(ipg):
+    # A hub with in-degree far above the LDS tile (long-row path) plus a
+    # ragged tail of small rows; N not a multiple of 64.
+    n = 5000
+    rng = np.random.default_rng(4)
+    src = np.concatenate([np.arange(1, n), rng.integers(0, n, 20000), np.zeros(3000, np.int64)])
+    dst = np.concatenate([np.zeros(n - 1, np.int64), rng.integers(0, n, 20000), rng.integers(1, n, 3000)])
+    hg = graphgen.from_edges(n, src, dst)
+    assert np.diff(hg.csc_off).max() > 2048
+    check_pagerank(ipg, hg, Ts=(1, 2, 10))
+
+
+@pytest.mark.parametrize("case", ["loops_dups", "single", "no_edges", "cycle"])
+def test_pagerank_edge_cases(ipg, case):
+    if case == "loops_dups":
+        hg = random_graph(333, 3000, seed=3, loops=True, dups=True)
+    elif case == "single":
+        hg = graphgen.from_edges(1, [], [])
+    elif case == "no_edges":
+        hg = graphgen.from_edges(70, [], [])
+    else:
+        n = 1000
+        hg = graphgen.from_edges(n, np.arange(n), (np.arange(n) + 1) % n)
+    check_pagerank(ipg, hg, Ts=(0, 1, 5, 10))
+
+
+# ------------------------------------------------------------------ CC ----
+
+def test_cc_rmat_s20_symmetrised(ipg):
+    # Symmetrised R-MAT scale 20, edge factor 16, seed 2 (the CC/SSSP workload).
+    hg = graphgen.workload("rmat-s20-sym")
+    check_min_app(ipg, hg, "cc")
+
+
+@pytest.mark.parametrize("sym", [True, False])
+def test_cc_random_and_directed(ipg, sym):
+    hg = random_graph(20000, 30000, seed=8, symmetric=sym)
+    check_min_app(ipg, hg, "cc")
+
+
+@pytest.mark.parametrize("case", ["path", "no_edges", "single", "loops_dups", "hub"])
+def test_cc_edge_cases(ipg, case):
+    if case == "path":
+        hg = path(300)
+    elif case == "no_edges":
+        hg = graphgen.from_edges(130, [], [])
+    elif case == "single":
+        hg = graphgen.from_edges(1, [0], [0], keep_self_loops=True)
+    elif case == "loops_dups":
+        hg = random_graph(500, 1500, seed=6, loops=True, dups=True)
+    else:
+        n = 9000
+        hg = graphgen.from_edges(n, np.full(n - 1, n - 1), np.arange(n - 1), symmetric=True)
+    check_min_app(ipg, hg, "cc")
+
+
+# ---------------------------------------------------------------- SSSP ----
+
+def test_sssp_rmat_s20_symmetrised_from_0(ipg):
+    hg = graphgen.workload("rmat-s20-sym")
+    check_min_app(ipg, hg, "sssp", source=0)
+
+
+@pytest.mark.parametrize("source", [0, 77])
+def test_sssp_directed_random(ipg, source):
+    hg = random_graph(20000, 60000, seed=9)
+    check_min_app(ipg, hg, "sssp", source=source)
+
+
+def test_sssp_weighted_grid(ipg):
+    hg = graphgen.grid_with_shortcuts(256, 0.01, seed=3)
+    check_min_app(ipg, hg, "sssp", source=0)
+    check_min_app(ipg, hg, "sssp", source=0, weighted=False, modes=("auto",))
+
+
+def test_sssp_weighted_directed_with_loops(ipg):
+    hg = random_graph(3000, 20000, seed=10, loops=True, dups=True, weight_seed=3)
+    check_min_app(ipg, hg, "sssp", source=5)
+
+
+# ------------------------------------------------------------ boundary ----
+
+def test_cap_returns_not_converged(ipg):
+    hg = path(50)
+    g = ipg.Graph.from_host(hg)
+    ref = oracle.run_graph("cc", hg, 7)
+    assert ref.status == oracle.NOT_CONVERGED
+    vals, st = g.run("cc", 7)
+    assert st.status == ipg.NOT_CONVERGED and st.supersteps == 7
+    assert np.array_equal(to_np(vals), ref.values)
+
+
+def test_errors(ipg):
+    import torch
+
+    hg = random_graph(100, 300, seed=1)
+    g = ipg.Graph.from_host(hg)
+    with pytest.raises(ipg.IpgError) as e:
+        g.run("cc", combiner=ipg.COMBINE_SUM)
+    assert e.value.status == ipg.EUNSUPPORTED
+    with pytest.raises(ipg.IpgError) as e:
+        g.run("sssp", source=100)
+    assert e.value.status == ipg.EINVAL
+    # bad graphs are caught by device-side validation
+    off = torch.tensor([0, 2, 1, 3], dtype=torch.int64, device="cuda")
+    dst = torch.tensor([1, 2, 0], dtype=torch.int32, device="cuda")
+    with pytest.raises(ipg.IpgError) as e:
+        ipg.Graph(3, off, dst, off, dst, symmetric=True)
+    assert e.value.status == ipg.EBADGRAPH
+    off = torch.tensor([0, 1, 2, 3], dtype=torch.int64, device="cuda")
+    dst = torch.tensor([1, 2, 3], dtype=torch.int32, device="cuda")
+    with pytest.raises(ipg.IpgError) as e:
+        ipg.Graph(3, off, dst, off, dst, symmetric=True)
+    assert e.value.status == ipg.EBADGRAPH
+    dst = torch.tensor([1, 2, -1], dtype=torch.int32, device="cuda")
+    with pytest.raises(ipg.IpgError) as e:
+        ipg.Graph(3, off, dst, off, dst, symmetric=True)
+    assert e.value.status == ipg.EBADGRAPH
+    off = torch.tensor([0, 1, 2, 4], dtype=torch.int64, device="cuda")
+    dst = torch.tensor([1, 2, 0], dtype=torch.int32, device="cuda")
+    with pytest.raises(ipg.IpgError):
+        ipg.Graph(3, off, dst, off, dst, symmetric=True)
+
+
+def test_sssp_overflow_reported(ipg):
+    import torch
+
+    hg = graphgen.from_edges(3, [0, 1], [1, 2])
+    w = np.array([0xFFFFFFF0, 0x20], dtype=np.uint32)
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).view(dt)).cuda()
+    off = t(hg.csr_off.astype(np.uint64), np.int64)
+    dst = t(hg.csr_dst, np.int32)
+    coff = t(hg.csc_off.astype(np.uint64), np.int64)
+    csrc = t(hg.csc_src, np.int32)
+    ww = t(w, np.int32)
+    cw = t(w[[0, 1]], np.int32)  # CSC order of this 2-edge path equals CSR order
+    g = ipg.Graph(3, off, dst, coff, csrc, ww, cw)
+    for mode in ("push", "pull"):
+        with pytest.raises(ipg.IpgError) as e:
+            g.run("sssp", source=0, mode=mode)
+        assert e.value.status == ipg.EOVERFLOW
+
+
+def test_small_workspace_rejected(ipg):
+    import ctypes
+
+    hg = random_graph(100, 300, seed=1)
+    g = ipg.Graph.from_host(hg)
+    rc = ipg.lib().ipg_run(g._h, 1, 1, 0, None, None, 0, None, None)
+    assert rc == ipg.EWORKSPACE
+    ws, nbytes = g.workspace(1)
+    rc = ipg.lib().ipg_run(g._h, 1, 1, 0, None, ws.data_ptr(), nbytes - 1, None, None)
+    assert rc == ipg.EWORKSPACE
