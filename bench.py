@@ -105,15 +105,17 @@ def main():
 
     roofline = None
     if "pagerank" in apps and T >= 1:
-        # average duration of one pull-gather launch (supersteps 1..T are one
-        # launch each), from HIP events recorded on the launch stream
+        # average duration of one pull superstep (the long-row chunk launch
+        # plus the row-group gather launch), from HIP events recorded on the
+        # launch stream around each superstep
         us = np.concatenate([s["pagerank"].usec[1:T + 1] for s in per_step])
         avg_us = float(np.mean(us))
         nbytes = pr_pull_bytes(hg.n, hg.m)
         ach = nbytes / (avg_us * 1e-6) / 1e9
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                    "kernel": "pr_pull_kernel", "bytes_per_launch": nbytes, "avg_launch_us": round(avg_us, 2)}
+                    "kernel": "pr_chunk_kernel+pr_pull_kernel (one PageRank pull superstep)",
+                    "bytes_per_launch": nbytes, "avg_launch_us": round(avg_us, 2)}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -53,8 +53,9 @@ typedef enum { IPG_APP_PAGERANK = 0, IPG_APP_CC_HASHMIN = 1, IPG_APP_SSSP = 2 } 
 typedef enum { IPG_COMBINE_SUM = 0, IPG_COMBINE_MIN = 1 } ipg_combiner;
 
 /* Message exchange (Section 4.3.2).  The mode never changes results.  AUTO
- * picks per superstep: the learned selector when one is loaded
- * (ipg_selector_load), else a fixed frontier-size heuristic. */
+ * picks per superstep: the learned selector when ipg_run_opts.selector is
+ * set, else a fixed frontier-size heuristic.  PageRank runs every vertex in
+ * every superstep, so its AUTO is pull. */
 typedef enum { IPG_MODE_AUTO = 0, IPG_MODE_PUSH = 1, IPG_MODE_PULL = 2 } ipg_mode;
 
 /* ipg_graph_desc.flags */
@@ -89,9 +90,11 @@ typedef struct {
 #define IPG_RUN_PERSISTENT 1u /* device-resident superstep loop: one cooperative launch, no per-superstep host sync */
 
 typedef struct {
-  uint32_t source; /* SSSP source vertex (ignored by the other applications) */
+  uint32_t source;          /* SSSP source vertex (ignored by the other applications) */
   ipg_mode mode;
   uint32_t flags;
+  const double* selector;   /* DEVICE pointer to IPG_SELECTOR_PARAMS trained selector parameters
+                               (see ipg_selector_train), used by IPG_MODE_AUTO; NULL = fixed heuristic */
 } ipg_run_opts;
 
 /*
@@ -166,6 +169,30 @@ ipg_status ipg_run(ipg_graph* graph, ipg_app app, ipg_combiner combiner, uint32_
  * run happened or dst_bytes is too small. */
 ipg_status ipg_read_values(const ipg_graph* graph, void* dst, size_t dst_bytes, int dst_is_device,
                            void* hip_stream);
+
+/*
+ * Learned exchange selector (an extension of Section 4.3.2, where the push /
+ * pull choice is a compile-time flag set by the user's experiments).
+ * A 4-16-16-2 tanh MLP in FP64 predicts log2 of the time of a push and of a
+ * pull superstep from log2(1+|F|)/32, log2(1+sum of out-degrees of F)/32,
+ * min(superstep,128)/64 and log2(1+E)/32; AUTO runs the smaller prediction.
+ * Parameters are packed W1[16][4], b1[16], W2[16][16], b2[16], W3[2][16], b3[2].
+ * All arrays are DEVICE memory owned by the caller; x is [n][4], y and t [n][2].
+ */
+#define IPG_SELECTOR_PARAMS 386
+#define IPG_SELECTOR_INPUTS 4
+#define IPG_SELECTOR_OUTPUTS 2
+
+/* Workspace bytes for ipg_selector_grad / ipg_selector_train on n samples. */
+size_t ipg_selector_workspace_bytes(uint32_t n_samples);
+/* y = network(x) for n samples.  Stream-ordered, no synchronisation. */
+ipg_status ipg_selector_forward(const double* params, const double* x, uint32_t n, double* y, void* hip_stream);
+/* grad = d/dparams of (1/2n) * sum (y - t)^2 over the n samples.  Stream-ordered. */
+ipg_status ipg_selector_grad(const double* params, const double* x, const double* t, uint32_t n, double* grad,
+                             void* workspace, size_t workspace_bytes, void* hip_stream);
+/* `epochs` full-batch gradient-descent steps params -= lr * grad, in place, on the device. */
+ipg_status ipg_selector_train(double* params, const double* x, const double* t, uint32_t n, uint32_t epochs,
+                              double lr, void* workspace, size_t workspace_bytes, void* hip_stream);
 
 /* Free the handle (host memory only; caller buffers are untouched). */
 void ipg_graph_destroy(ipg_graph* graph);

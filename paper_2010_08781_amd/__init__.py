@@ -54,7 +54,8 @@ class _Desc(ctypes.Structure):
 
 
 class _Opts(ctypes.Structure):
-    _fields_ = [("source", ctypes.c_uint32), ("mode", ctypes.c_int), ("flags", ctypes.c_uint32)]
+    _fields_ = [("source", ctypes.c_uint32), ("mode", ctypes.c_int), ("flags", ctypes.c_uint32),
+                ("selector", ctypes.c_void_p)]
 
 
 class _Stats(ctypes.Structure):
@@ -91,6 +92,14 @@ def lib():
         L.ipg_graph_destroy.restype = None
         L.ipg_last_error.argtypes = []
         L.ipg_last_error.restype = ctypes.c_char_p
+        L.ipg_selector_workspace_bytes.argtypes = [u32]
+        L.ipg_selector_workspace_bytes.restype = sz
+        L.ipg_selector_forward.argtypes = [P, P, u32, P, P]
+        L.ipg_selector_forward.restype = i32
+        L.ipg_selector_grad.argtypes = [P, P, P, u32, P, P, sz, P]
+        L.ipg_selector_grad.restype = i32
+        L.ipg_selector_train.argtypes = [P, P, P, u32, u32, ctypes.c_double, P, sz, P]
+        L.ipg_selector_train.restype = i32
         _lib = L
     return _lib
 
@@ -215,7 +224,7 @@ class Graph:
 
     def run(self, app, max_supersteps: Optional[int] = None, source: int = 0, mode: str = "auto",
             timing: bool = True, trace_cap: int = 1 << 16, persistent: bool = False, stream=None,
-            combiner: Optional[int] = None, check: bool = True):
+            combiner: Optional[int] = None, check: bool = True, selector=None):
         """Run an application; returns (values tensor on the device, RunStats).
 
         max_supersteps: PageRank -> number of rank updates (default 10, Fig. 8);
@@ -227,7 +236,10 @@ class Graph:
             max_supersteps = 10 if a == APP_PAGERANK else 0
         comb = DEFAULT_COMBINER.get(a, 0) if combiner is None else combiner
         ws, nbytes = self.workspace(a) if a in DEFAULT_COMBINER else (None, 0)
-        opts = _Opts(int(source), MODES[mode], RUN_PERSISTENT if persistent else 0)
+        if selector is not None:
+            _check_selector(selector)
+        opts = _Opts(int(source), MODES[mode], RUN_PERSISTENT if persistent else 0,
+                     selector.data_ptr() if selector is not None else None)
         arrs = {k: np.zeros(trace_cap, dtype=np.uint64) for k in ("active", "senders", "messages", "examined")}
         arrs["mode"] = np.zeros(trace_cap, dtype=np.uint8)
         usec = np.zeros(trace_cap, dtype=np.float32) if timing else None
@@ -266,6 +278,81 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------ selector ----
+
+SELECTOR_PARAMS, SELECTOR_INPUTS, SELECTOR_OUTPUTS = 386, 4, 2
+
+
+def _check_selector(p):
+    import torch
+
+    if not p.is_cuda or p.dtype != torch.float64 or p.numel() != SELECTOR_PARAMS or not p.is_contiguous():
+        raise ValueError(f"selector parameters must be a contiguous float64 CUDA tensor of {SELECTOR_PARAMS}")
+
+
+def _check_batch(x, t=None):
+    import torch
+
+    if not x.is_cuda or x.dtype != torch.float64 or x.dim() != 2 or x.shape[1] != SELECTOR_INPUTS:
+        raise ValueError("selector inputs must be a float64 CUDA tensor [n, 4]")
+    if t is not None and (not t.is_cuda or t.dtype != torch.float64 or tuple(t.shape) != (x.shape[0], SELECTOR_OUTPUTS)):
+        raise ValueError("selector targets must be a float64 CUDA tensor [n, 2]")
+
+
+def selector_forward(params, x, stream=None):
+    """Predicted log2-times [n, 2] (push, pull) for inputs x [n, 4]."""
+    import torch
+
+    _check_selector(params)
+    _check_batch(x)
+    x = x.contiguous()
+    y = torch.empty((x.shape[0], SELECTOR_OUTPUTS), dtype=torch.float64, device=x.device)
+    _check(lib().ipg_selector_forward(params.data_ptr(), x.data_ptr(), x.shape[0], y.data_ptr(),
+                                      _stream_handle(stream)), "ipg_selector_forward")
+    return y
+
+
+def _selector_ws(n, device):
+    import torch
+
+    nbytes = lib().ipg_selector_workspace_bytes(n)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
+
+
+def selector_grad(params, x, t, stream=None):
+    """Gradient of (1/2n) sum (y - t)^2 with respect to the parameters."""
+    import torch
+
+    _check_selector(params)
+    _check_batch(x, t)
+    x, t = x.contiguous(), t.contiguous()
+    g = torch.empty(SELECTOR_PARAMS, dtype=torch.float64, device=x.device)
+    ws, nbytes = _selector_ws(x.shape[0], x.device)
+    _check(lib().ipg_selector_grad(params.data_ptr(), x.data_ptr(), t.data_ptr(), x.shape[0], g.data_ptr(),
+                                   ws.data_ptr(), nbytes, _stream_handle(stream)), "ipg_selector_grad")
+    return g
+
+
+def selector_train(params, x, t, epochs: int, lr: float, stream=None):
+    """In-place full-batch gradient descent on the device."""
+    _check_selector(params)
+    _check_batch(x, t)
+    x, t = x.contiguous(), t.contiguous()
+    ws, nbytes = _selector_ws(x.shape[0], x.device)
+    _check(lib().ipg_selector_train(params.data_ptr(), x.data_ptr(), t.data_ptr(), x.shape[0], int(epochs), float(lr),
+                                    ws.data_ptr(), nbytes, _stream_handle(stream)), "ipg_selector_train")
+    return params
+
+
+def selector_features(frontier, frontier_deg, superstep, num_edges) -> np.ndarray:
+    """The network's inputs for superstep states (same definition as the library's)."""
+    f = np.asarray(frontier, dtype=np.float64)
+    d = np.asarray(frontier_deg, dtype=np.float64)
+    s = np.minimum(np.asarray(superstep, dtype=np.float64), 128.0)
+    e = np.broadcast_to(np.asarray(num_edges, dtype=np.float64), f.shape)
+    return np.stack([np.log2(1 + f) / 32, np.log2(1 + d) / 32, s / 64, np.log2(1 + e) / 32], axis=-1)
 
 
 def values_to_numpy(t) -> np.ndarray:

@@ -8,22 +8,24 @@
 namespace ipg {
 
 size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w) {
-  (void)e;
   RunWs r{};
   const size_t nn = n ? n : 1;
   if (app == IPG_APP_PAGERANK) {
     r.value_f64 = c.take<double>(nn);
     r.f64_a = c.take<double>(nn);
     r.f64_b = c.take<double>(nn);
+    r.partial = c.take<double>(chunks_cap(e));
   } else {
     r.value_u32 = c.take<uint32_t>(nn);
     r.mail_a = c.take<uint32_t>(nn);
     r.mail_b = c.take<uint32_t>(nn);
     r.fr_a = c.take<uint32_t>(nn);
     r.fr_b = c.take<uint32_t>(nn);
-    r.sent = c.take<uint32_t>(nn / 32 + 1);
+    r.outbox = c.take<uint32_t>(nn);
+    r.list_ctr = c.take<uint32_t>(2);
+    r.decision = c.take<Decision>(1);
   }
-  r.ctr = c.take<StepCounters>(2);
+  r.ctr = c.take<CtrSlot>(2 * kCtrSlots);
   if (w) *w = r;
   return align_up(c.used, 256);
 }
@@ -73,8 +75,7 @@ hipError_t StepTimer::finish(hipStream_t s) {
 
 // Fixed heuristic (the default of Ligra's direction switch, Shun and
 // Blelloch 2013): pull when the frontier plus its out-edges exceed E/20.
-ipg_mode choose_mode(ipg_mode requested, const ModeQuery& q) {
-  if (requested == IPG_MODE_PUSH || requested == IPG_MODE_PULL) return requested;
+ipg_mode heuristic_mode(const ModeQuery& q) {
   if (q.e == 0) return IPG_MODE_PUSH;
   return (q.frontier + q.frontier_deg > q.e / 20) ? IPG_MODE_PULL : IPG_MODE_PUSH;
 }
@@ -96,7 +97,7 @@ extern "C" ipg_status ipg_run(ipg_graph* g, ipg_app app, ipg_combiner combiner, 
                        (app == IPG_APP_CC_HASHMIN && combiner == IPG_COMBINE_MIN) ||
                        (app == IPG_APP_SSSP && combiner == IPG_COMBINE_MIN);
   if (!ok_pair) return fail(IPG_EUNSUPPORTED, "ipg_run: (app, combiner) must be (PAGERANK, SUM), (CC, MIN) or (SSSP, MIN)");
-  ipg_run_opts o{0, IPG_MODE_AUTO, 0};
+  ipg_run_opts o{0, IPG_MODE_AUTO, 0, nullptr};
   if (opts) o = *opts;
   if (o.mode != IPG_MODE_AUTO && o.mode != IPG_MODE_PUSH && o.mode != IPG_MODE_PULL)
     return fail(IPG_EINVAL, "ipg_run: unknown mode");

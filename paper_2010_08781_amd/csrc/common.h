@@ -22,6 +22,12 @@ constexpr uint32_t kInf = 0xFFFFFFFFu;  // INF distance and identity of the min 
 // through LDS.  Rows with more than kPullTile in-edges get a workgroup each.
 constexpr uint32_t kPullTile = 1024;
 
+inline uint32_t num_pull_groups(uint64_t e) { return static_cast<uint32_t>(e / kPullTile + 1); }
+// Rows with more than kPullTile in-edges: fewer than E / (kPullTile + 1) + 1.
+inline uint64_t long_rows_cap(uint64_t e) { return e / (kPullTile + 1) + 1; }
+// Chunks of the long rows: sum of ceil(deg / kPullTile) <= E/kPullTile + (long rows).
+inline uint64_t chunks_cap(uint64_t e) { return e / kPullTile + long_rows_cap(e) + 1; }
+
 // ---------------------------------------------------------------- status --
 void set_error(const std::string& msg);
 ipg_status fail(ipg_status st, const std::string& msg);
@@ -54,8 +60,50 @@ struct GraphTables {
   uint32_t* outdeg;     // [n] out-degree (u32)
   uint32_t* pull_rb;    // [nb+1] first CSC row of each pull row-group
   uint32_t* long_rows;  // [nl] rows with in-degree > kPullTile, ascending
+  uint32_t* lr_first;   // [nl+1] first chunk of each long row (chunks of kPullTile in-edges)
+  uint32_t* ch_row;     // [nc] index into long_rows of each chunk
   uint32_t* flags;      // [4] validation flags
 };
+
+// Pull-side view of the CSC handed to the gather kernels.  A launch has nc
+// chunk workgroups (long rows, kPullTile in-edges each) followed by nb
+// row-group workgroups.
+struct PullTiling {
+  const uint64_t* off;
+  const int32_t* src;
+  const uint32_t* rb;
+  const uint32_t* long_rows;
+  const uint32_t* lr_first;
+  const uint32_t* ch_row;
+  uint32_t nl, nc, nb;
+};
+
+struct ChunkRef {
+  uint32_t l;         // long-row index
+  uint32_t j, nch;    // chunk index within the row, chunks of the row
+  uint32_t v;         // the row (vertex)
+  uint64_t beg, end;  // in-edge range of this chunk
+};
+
+__device__ __forceinline__ ChunkRef chunk_ref(const PullTiling& t, uint32_t c) {
+  ChunkRef r;
+  r.l = t.ch_row[c];
+  const uint32_t f = t.lr_first[r.l];
+  r.j = c - f;
+  r.nch = t.lr_first[r.l + 1] - f;
+  r.v = t.long_rows[r.l];
+  const uint64_t rb = t.off[r.v], re = t.off[r.v + 1];
+  r.beg = rb + static_cast<uint64_t>(r.j) * kPullTile;
+  r.end = r.beg + kPullTile < re ? r.beg + kPullTile : re;
+  return r;
+}
+
+// Rows [r0, r1) of row-group k, without a long last row (it is chunked).
+__device__ __forceinline__ void group_rows(const PullTiling& t, uint32_t k, uint32_t& r0, uint32_t& r1) {
+  r0 = t.rb[k];
+  r1 = t.rb[k + 1];
+  if (r1 > r0 && t.off[r1] - t.off[r1 - 1] > kPullTile) --r1;
+}
 
 }  // namespace ipg
 
@@ -72,6 +120,7 @@ struct ipg_graph {
   ipg::GraphTables t;
   uint32_t nb;  // number of pull row-groups
   uint32_t nl;  // number of long rows
+  uint32_t nc;  // number of long-row chunks
   int device;
   // last run
   int has_values;
@@ -118,33 +167,78 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
   return v;
 }
 
-// Block-wide sum of per-thread counters, then one atomicAdd per block.  Must
-// be reached by every thread of the block.
-__device__ __forceinline__ void block_add_u64(uint64_t x, unsigned long long* dst) {
-  __shared__ uint64_t part[kWavesPerBlock];
-  x = wave_sum_u64(x);
-  const int w = threadIdx.x / kWave;
-  if (lane_id() == 0) part[w] = x;
+// Per-superstep counters.  Same-address device-scope atomics serialize
+// device-wide (about 11 ns each on MI355X), so every workgroup adds into one
+// of kCtrSlots slots (its own 128-byte line, chosen by blockIdx % kCtrSlots)
+// and the host sums the slots.
+constexpr int kCtrSlots = 64;
+struct alignas(128) CtrSlot {
+  uint32_t next_count;          // vertices with a message for the next superstep
+  uint32_t overflow;            // an SSSP message would reach INF
+  unsigned long long senders;   // vertices that broadcast
+  unsigned long long messages;  // sum of the senders' out-degrees
+  unsigned long long next_deg;  // sum of out-degrees of the next frontier
+  unsigned long long pad[12];
+};
+static_assert(sizeof(CtrSlot) == 128, "one slot per 128-byte line");
+
+// Host-side sum of the slots of one superstep.
+struct StepCounters {
+  uint64_t next_count, senders, messages, next_deg;
+  uint32_t overflow;
+};
+
+__device__ __forceinline__ CtrSlot* my_slot(CtrSlot* base) { return base + (blockIdx.x % kCtrSlots); }
+
+// Zero the kCtrSlots slots at `c` (called by workgroup 0 only).
+__device__ __forceinline__ void clear_slots(CtrSlot* c) {
+  if (c && blockIdx.x == 0) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(c);
+    for (uint32_t i = threadIdx.x; i < kCtrSlots * sizeof(CtrSlot) / 4; i += blockDim.x) w[i] = 0;
+  }
+}
+
+// Workgroup-wide sum of per-thread counters, then at most one atomic per
+// non-zero field into the workgroup's slot.  Every thread must call it.
+__device__ __forceinline__ void flush_counters(CtrSlot* base, uint64_t senders, uint64_t messages, uint64_t next_count,
+                                               uint64_t next_deg, uint32_t overflow) {
+  __shared__ unsigned long long part[4][kWavesPerBlock];
+  __shared__ uint32_t ovf;
+  if (threadIdx.x == 0) ovf = 0;
+  senders = wave_sum_u64(senders);
+  messages = wave_sum_u64(messages);
+  next_count = wave_sum_u64(next_count);
+  next_deg = wave_sum_u64(next_deg);
+  const bool any_ovf = __ballot(overflow != 0) != 0;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t s = 0;
-    for (int i = 0; i < kWavesPerBlock; ++i) s += part[i];
-    if (s) atomicAdd(dst, static_cast<unsigned long long>(s));
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    part[0][w] = senders;
+    part[1][w] = messages;
+    part[2][w] = next_count;
+    part[3][w] = next_deg;
+    if (any_ovf) ovf = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    unsigned long long t = 0;
+    for (int i = 0; i < kWavesPerBlock; ++i) t += part[threadIdx.x][i];
+    CtrSlot* c = my_slot(base);
+    if (t) {
+      if (threadIdx.x == 0) atomicAdd(&c->senders, t);
+      if (threadIdx.x == 1) atomicAdd(&c->messages, t);
+      if (threadIdx.x == 2) atomicAdd(&c->next_count, static_cast<uint32_t>(t));
+      if (threadIdx.x == 3) atomicAdd(&c->next_deg, t);
+    }
+    if (threadIdx.x == 0 && ovf) atomicOr(&c->overflow, 1u);
   }
   __syncthreads();
 }
 
-// Per-superstep counters written by the kernels and read back by the host.
-struct StepCounters {
-  uint32_t next_count;           // vertices appended to the next frontier
-  uint32_t overflow;             // an SSSP message would reach INF
-  unsigned long long senders;    // vertices that broadcast
-  unsigned long long messages;   // sum of senders' out-degrees
-  unsigned long long examined;   // edges read by the exchange
-  unsigned long long next_deg;   // sum of out-degrees of the next frontier
-  unsigned long long pad[3];
-};
-static_assert(sizeof(StepCounters) == 64, "one cache line");
+// Fixed grid for the grid-stride exchange kernels: enough resident
+// workgroups to cover the chip (256 CUs) several times over, few enough that
+// per-workgroup counter flushes stay cheap.
+constexpr uint32_t kExchangeGrid = 4096;
 
 __global__ void fill_u32_kernel(uint32_t* p, uint64_t n, uint32_t v);
 __global__ void fill_f64_kernel(double* p, uint64_t n, double v);

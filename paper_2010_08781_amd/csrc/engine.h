@@ -7,21 +7,49 @@
 
 namespace ipg {
 
+inline PullTiling pull_tiling(const ipg_graph* g) {
+  PullTiling t;
+  t.off = g->csc_off;
+  t.src = g->csc_src;
+  t.rb = g->t.pull_rb;
+  t.long_rows = g->t.long_rows;
+  t.lr_first = g->t.lr_first;
+  t.ch_row = g->t.ch_row;
+  t.nl = g->nl;
+  t.nc = g->nc;
+  t.nb = g->nb;
+  return t;
+}
+
+// End-of-superstep summary written by the decide kernel: the counter slots
+// summed, and the selector's choice for the next superstep.
+struct Decision {
+  unsigned long long next_count, senders, messages, next_deg;
+  uint32_t overflow;
+  int32_t mode;   // IPG_MODE_PUSH / IPG_MODE_PULL from the selector, 0 if none ran
+  double margin;  // predicted log2 time of push minus pull
+  unsigned long long pad[2];
+};
+static_assert(sizeof(Decision) == 64, "one 64-byte record");
+
 // Run workspace, carved from the caller's device buffer.
 struct RunWs {
   // PageRank
   double* value_f64;  // [n] ranks after the last update
   double* f64_a;      // [n] outbox (pull) or mailbox (push), ping
   double* f64_b;      // [n] pong
+  double* partial;    // [chunks] partial sums of long-row chunks (pull)
   // CC / SSSP
   uint32_t* value_u32;  // [n] labels or distances
   uint32_t* mail_a;     // [n] one-slot min mailboxes, ping (INF = empty)
   uint32_t* mail_b;     // [n] pong
   uint32_t* fr_a;       // [n] frontier list, ping
   uint32_t* fr_b;       // [n] pong
-  uint32_t* sent;       // [n/32+1] senders of the current superstep (pull form)
+  uint32_t* outbox;     // [n] one-slot outbox of the pull form: the broadcast value, INF if none
+  uint32_t* list_ctr;   // [2] next-frontier list length (push form), slot s & 1
+  struct Decision* decision;  // end-of-superstep summary read by the host
   // both
-  StepCounters* ctr;    // [2] per-superstep counters (slot s & 1)
+  CtrSlot* ctr;         // [2][kCtrSlots] per-superstep counters (set s & 1)
 };
 
 size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w);
@@ -55,7 +83,8 @@ struct ModeQuery {
   uint32_t superstep;
   ipg_app app;
 };
-ipg_mode choose_mode(ipg_mode requested, const ModeQuery& q);
+// Fixed heuristic used when no selector is given.
+ipg_mode heuristic_mode(const ModeQuery& q);
 
 ipg_status run_pagerank(ipg_graph* g, uint32_t T, ipg_mode mode, const RunWs& w, hipStream_t s, StepTimer& tm,
                         ipg_run_stats* st);

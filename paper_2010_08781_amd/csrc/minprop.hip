@@ -3,111 +3,135 @@
 //
 // Both applications vote to halt after every compute ("systematic halt",
 // Section 4.3.1), so the vertices active in superstep s+1 are exactly the
-// recipients of a message in superstep s.  The next frontier is therefore
-// built while messages are delivered: a recipient is appended when its
-// mailbox was empty (the atomic min returns the identity INF), which also
-// removes duplicates -- the selection bypass of Section 4.3.1, with the
-// per-thread lists replaced by wavefront-ballot compaction.
+// recipients of a message in superstep s: the vertices whose one-slot
+// mailbox is not empty (INF).  The mailbox array therefore *is* the next
+// frontier; no separate selection pass is needed (the selection bypass of
+// Section 4.3.1).  When the exchange is a push, the recipients whose mailbox
+// was empty (the atomic min returned INF -- exactly one sender per recipient
+// sees that, so there are no duplicates) are also appended to a compact list,
+// so that a small next frontier can be visited without sweeping all N
+// mailboxes.
 //
-// Superstep s >= 1 for a frontier vertex v: consume its one-slot mailbox
-// (reset it to INF); if the message is below value(v), lower value(v) and
-// broadcast -- value(v) for CC, value(v) + 1 (or + w(v, x) per out-edge when
-// weighted) for SSSP.  Superstep 0: CC sets value = id and every vertex
-// broadcasts; SSSP sets value = 0 at the source (which broadcasts) and INF
-// elsewhere.
+// Superstep s >= 1 for an active vertex v: consume its mailbox (reset it to
+// INF); if the message is below value(v), lower value(v) and broadcast --
+// value(v) for CC, value(v) + 1 (or + w(v, x) per out-edge when weighted)
+// for SSSP.  Superstep 0: CC sets value = id and every vertex broadcasts;
+// SSSP sets value = 0 at the source (which broadcasts) and INF elsewhere.
 //
 // Mailboxes are double-buffered (consume from `mail_in`, deliver into
 // `mail_out`) so that a superstep never sees a message sent in the same
 // superstep (Section 4.2).
+#include <algorithm>
+#include <vector>
+
 #include "common.h"
 #include "engine.h"
 #include "scatter.h"
+#include "selector.h"
 
 namespace ipg {
 
-enum : int { kPhaseSendAll = 0, kPhaseSendSource = 1, kPhaseStep = 2 };
-
-__device__ __forceinline__ void clear_counters(StepCounters* c) {
-  if (c && blockIdx.x == 0 && threadIdx.x < sizeof(StepCounters) / 4) reinterpret_cast<uint32_t*>(c)[threadIdx.x] = 0;
-}
+// Which vertices run compute in a launch.
+enum : int {
+  kSendAll = 0,     // superstep 0 of CC: every vertex broadcasts its id
+  kSendSource = 1,  // superstep 0 of SSSP: the source broadcasts
+  kStepList = 2,    // s >= 1, active vertices given as a list
+  kStepDense = 3    // s >= 1, active vertices = non-empty mailboxes (sweep all N)
+};
 
 // value = id (CC) or 0 at the source / INF elsewhere (SSSP).  With `pull_s0`
-// the superstep-0 senders are also recorded in the sent bitmap (which must be
-// zero) and counted.
+// superstep 0 is exchanged by pull: the senders' broadcast values are written
+// to the outbox (INF for the others) and the senders are counted.
 __global__ __launch_bounds__(kBlock) void minprop_init_kernel(uint32_t n, int app, uint32_t source, uint32_t* value,
-                                                              const uint32_t* outdeg, int pull_s0, uint32_t* sent,
-                                                              StepCounters* ctr) {
+                                                              const uint32_t* outdeg, int pull_s0, uint32_t* outbox,
+                                                              CtrSlot* ctr) {
   uint64_t senders = 0, messages = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
     const bool sends = (app == IPG_APP_CC_HASHMIN) || v == source;
-    value[v] = app == IPG_APP_CC_HASHMIN ? static_cast<uint32_t>(v) : (v == source ? 0u : kInf);
-    if (pull_s0 && sends) {
-      atomicOr(sent + (v >> 5), 1u << (v & 31));
-      senders += 1;
-      messages += outdeg[v];
+    const uint32_t x = app == IPG_APP_CC_HASHMIN ? static_cast<uint32_t>(v) : (v == source ? 0u : kInf);
+    value[v] = x;
+    if (pull_s0) {
+      outbox[v] = sends ? x : kInf;
+      if (sends) {
+        senders += 1;
+        messages += outdeg[v];
+      }
     }
   }
-  if (pull_s0) {
-    block_add_u64(senders, &ctr->senders);
-    block_add_u64(messages, &ctr->messages);
+  if (pull_s0) flush_counters(ctr, senders, messages, 0, 0, 0);
+}
+
+struct Active {
+  int phase;
+  uint32_t count;           // list length, or N for the dense and send-all phases
+  const uint32_t* list;
+  uint32_t source;
+};
+
+// Vertex of slot i of a launch.
+__device__ __forceinline__ uint32_t active_vertex(const Active& act, uint64_t i) {
+  const uint32_t id = static_cast<uint32_t>(i);
+  const uint32_t from_list = act.phase == kStepList ? act.list[i] : id;
+  return act.phase == kSendSource ? act.source : from_list;
+}
+
+// Compute of vertex v in a launch: returns whether v broadcasts, and the
+// value it broadcasts.
+__device__ __forceinline__ bool compute_min(int phase, uint32_t v, uint32_t* value, uint32_t* mail_in, uint32_t& msg) {
+  if (phase == kSendAll || phase == kSendSource) {
+    msg = value[v];
+    return true;
   }
+  const uint32_t m = mail_in[v];
+  if (m == kInf) return false;  // dense sweep: no message, not active
+  mail_in[v] = kInf;
+  if (m < value[v]) {
+    value[v] = m;
+    msg = m;
+    return true;
+  }
+  return false;
 }
 
 struct MinPushArgs {
-  int phase;
-  uint32_t source;
-  uint32_t count;             // frontier entries (or N for kPhaseSendAll)
-  const uint32_t* frontier_in;
-  const uint64_t* off;        // CSR
+  Active act;
+  const uint64_t* off;  // CSR
   const int32_t* dst;
-  const uint32_t* w;          // CSR weights or null
+  const uint32_t* w;    // CSR weights or null
   const uint32_t* outdeg;
   uint32_t* value;
   uint32_t* mail_in;
   uint32_t* mail_out;
-  uint32_t* frontier_out;
-  StepCounters* ctr;
-  StepCounters* ctr_clear;
+  uint32_t* list_out;   // next frontier (recipients whose mailbox was empty)
+  uint32_t* list_ctr;
+  CtrSlot* ctr;
+  CtrSlot* ctr_clear;
 };
 
-// Fused compute + push scatter of one superstep (one thread per frontier
-// entry, out-edges expanded by twc_scatter).
+// Fused compute + push scatter of one superstep: one thread per active
+// vertex, out-edges expanded by twc_scatter.  Recipients whose mailbox was
+// empty are appended to the next-frontier list by wave-ballot compaction
+// (one global atomic per wave and ballot).
 template <int APP, bool W>
 __global__ __launch_bounds__(kBlock) void minprop_push_kernel(MinPushArgs a) {
-  clear_counters(a.ctr_clear);
+  clear_slots(a.ctr_clear);
   const uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x;
   bool has = false;
   uint64_t beg = 0, end = 0;
   uint32_t msg = 0;
-  if (i < a.count) {
-    uint32_t v;
-    if (a.phase == kPhaseSendAll) {
-      v = static_cast<uint32_t>(i);
-      has = true;
-      msg = a.value[v];
-    } else if (a.phase == kPhaseSendSource) {
-      v = a.source;
-      has = true;
-      msg = a.value[v];
-    } else {
-      v = a.frontier_in[i];
-      const uint32_t m = a.mail_in[v];
-      a.mail_in[v] = kInf;
-      if (m < a.value[v]) {
-        a.value[v] = m;
-        has = true;
-        msg = m;
-      }
-    }
+  uint64_t senders = 0, messages = 0, next_count = 0, next_deg = 0;
+  uint32_t overflow = 0;
+  if (i < a.act.count) {
+    const uint32_t v = active_vertex(a.act, i);
+    has = compute_min(a.act.phase, v, a.value, a.mail_in, msg);
     if (has) {
       beg = a.off[v];
       end = a.off[v + 1];
+      senders = 1;
+      messages = end - beg;
     }
   }
-  const uint64_t senders = has ? 1 : 0, messages = end - beg;
-  uint64_t next_deg = 0;
-  uint32_t overflow = 0;
   uint32_t* mail = a.mail_out;
   twc_scatter(has, beg, end, msg, [&](uint64_t e, uint32_t p) {
     const uint32_t x = static_cast<uint32_t>(a.dst[e]);
@@ -116,76 +140,62 @@ __global__ __launch_bounds__(kBlock) void minprop_push_kernel(MinPushArgs a) {
     bool fresh = false;
     if (m >= kInf) overflow = 1;
     else fresh = atomicMin(mail + x, static_cast<uint32_t>(m)) == kInf;
-    wave_append(fresh, x, a.frontier_out, &a.ctr->next_count);
-    if (fresh) next_deg += a.outdeg[x];
+    wave_append(fresh, x, a.list_out, a.list_ctr);
+    if (fresh) {
+      next_count += 1;
+      next_deg += a.outdeg[x];
+    }
   });
-  block_add_u64(senders, &a.ctr->senders);
-  block_add_u64(messages, &a.ctr->messages);
-  block_add_u64(messages, &a.ctr->examined);
-  block_add_u64(next_deg, &a.ctr->next_deg);
-  if (__ballot(overflow) && lane_id() == 0) atomicOr(&a.ctr->overflow, 1u);
+  flush_counters(a.ctr, senders, messages, next_count, next_deg, overflow);
 }
 
 struct MinApplyArgs {
-  uint32_t count;
-  const uint32_t* frontier_in;
+  Active act;
   const uint32_t* outdeg;
   uint32_t* value;
   uint32_t* mail_in;
-  uint32_t* sent;             // bitmap, zero on entry
-  StepCounters* ctr;
-  StepCounters* ctr_clear;
+  uint32_t* outbox;  // all INF on entry
+  CtrSlot* ctr;
 };
 
-// Compute phase of a pull superstep: consume mailboxes of the frontier,
-// record the senders in the bitmap (their value is the one-slot outbox).
+// Compute phase of a pull superstep: consume the mailboxes of the active
+// vertices; a vertex whose value drops broadcasts it through its one-slot
+// outbox (Section 4.3.2: one broadcast value per vertex, read by the
+// out-neighbours).
 __global__ __launch_bounds__(kBlock) void minprop_apply_kernel(MinApplyArgs a) {
-  clear_counters(a.ctr_clear);
   uint64_t senders = 0, messages = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < a.count; i += stride) {
-    const uint32_t v = a.frontier_in[i];
-    const uint32_t m = a.mail_in[v];
-    a.mail_in[v] = kInf;
-    if (m < a.value[v]) {
-      a.value[v] = m;
-      atomicOr(a.sent + (v >> 5), 1u << (v & 31));
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < a.act.count; i += stride) {
+    const uint32_t v = active_vertex(a.act, i);
+    uint32_t msg;
+    if (compute_min(a.act.phase, v, a.value, a.mail_in, msg)) {
+      a.outbox[v] = msg;
       senders += 1;
       messages += a.outdeg[v];
     }
   }
-  block_add_u64(senders, &a.ctr->senders);
-  block_add_u64(messages, &a.ctr->messages);
+  flush_counters(a.ctr, senders, messages, 0, 0, 0);
 }
 
 struct MinPullArgs {
-  const uint64_t* off;   // CSC
-  const int32_t* src;
-  const uint32_t* w;     // CSC weights or null
+  PullTiling t;
+  const uint32_t* w;       // CSC weights or null
   const uint32_t* outdeg;
-  const uint32_t* rb;
-  const uint32_t* long_rows;
-  uint32_t nl;
-  const uint32_t* sent;
-  const uint32_t* value;
+  const uint32_t* outbox;  // broadcast values of this superstep, INF = no broadcast
   uint32_t* mail_out;
-  uint32_t* frontier_out;
-  StepCounters* ctr;
-  StepCounters* ctr_clear;
+  CtrSlot* ctr;
+  CtrSlot* ctr_clear;
 };
 
-// Message a sender u offers over in-edge e (INF when u did not broadcast).
+// The message an in-edge carries: the source's broadcast value o (CC), plus
+// 1 or the edge weight w (SSSP); INF when the source did not broadcast.
 template <int APP, bool W>
-__device__ __forceinline__ uint32_t pull_msg(const MinPullArgs& a, uint64_t e, uint32_t& overflow) {
-  const uint32_t u = static_cast<uint32_t>(a.src[e]);
-  if (!((a.sent[u >> 5] >> (u & 31)) & 1u)) return kInf;
-  uint64_t m = a.value[u];
-  if (APP == IPG_APP_SSSP) m += W ? a.w[e] : 1u;
-  if (m >= kInf) {
-    overflow = 1;
-    return kInf;
-  }
-  return static_cast<uint32_t>(m);
+__device__ __forceinline__ uint32_t edge_msg(uint32_t o, uint32_t w, uint32_t& overflow) {
+  if (APP == IPG_APP_CC_HASHMIN) return o;
+  const uint64_t m = static_cast<uint64_t>(o) + (W ? w : 1u);
+  const bool live = o != kInf;
+  overflow |= (live && m >= kInf) ? 1u : 0u;
+  return (live && m < kInf) ? static_cast<uint32_t>(m) : kInf;
 }
 
 __device__ __forceinline__ uint32_t wave_min(uint32_t x) {
@@ -194,101 +204,174 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t x) {
   return x;
 }
 
-// Exchange of a pull superstep over the CSC, same tiling as the PageRank
-// pull: long rows first (a workgroup each), then LDS-staged row-groups.
+// Exchange of a pull superstep over the CSC (grid-stride over work items):
+// long-row chunks first -- each folds the minimum of its kPullTile in-edges
+// into the row's mailbox with an atomic min, and the chunk that finds the
+// mailbox empty counts the row as newly active -- then the row-groups,
+// whose in-edge messages are staged in LDS and min-reduced per row.
 template <int APP, bool W>
 __global__ __launch_bounds__(kBlock) void minprop_pull_kernel(MinPullArgs a) {
   __shared__ uint32_t tile[2 * kPullTile];
   __shared__ uint32_t red[kWavesPerBlock];
-  clear_counters(a.ctr_clear);
-  const uint32_t b = blockIdx.x, tid = threadIdx.x;
-  uint64_t examined = 0, next_deg = 0;
+  clear_slots(a.ctr_clear);
+  const uint32_t tid = threadIdx.x;
+  const int32_t* src = a.t.src;
+  const uint64_t* off = a.t.off;
+  uint64_t next_count = 0, next_deg = 0;
   uint32_t overflow = 0;
-  if (b < a.nl) {
-    const uint32_t v = a.long_rows[b];
-    const uint64_t beg = a.off[v], end = a.off[v + 1];
-    uint32_t m = kInf;
-    for (uint64_t e = beg + tid; e < end; e += kBlock) m = min(m, pull_msg<APP, W>(a, e, overflow));
-    m = wave_min(m);
-    if (lane_id() == 0) red[tid / kWave] = m;
-    __syncthreads();
-    if (tid == 0) {
-      m = min(min(red[0], red[1]), min(red[2], red[3]));
-      examined = end - beg;
-      if (m < kInf) {
-        a.mail_out[v] = m;
-        a.frontier_out[atomicAdd(&a.ctr->next_count, 1u)] = v;
-        next_deg = a.outdeg[v];
+  const uint32_t items = a.t.nc + a.t.nb;
+  for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
+    if (item < a.t.nc) {
+      const ChunkRef r = chunk_ref(a.t, item);
+      constexpr int kPer = kPullTile / kBlock;
+      uint64_t e[kPer];
+      int32_t u[kPer];
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        e[k] = r.beg + tid + k * kBlock;
+        e[k] = e[k] < r.end ? e[k] : r.end - 1;
+        u[k] = __builtin_nontemporal_load(src + e[k]);
       }
-    }
-  } else {
-    const uint32_t k = b - a.nl;
-    const uint32_t r0 = a.rb[k];
-    uint32_t r1 = a.rb[k + 1];
-    if (r1 > r0 && a.off[r1] - a.off[r1 - 1] > kPullTile) --r1;
-    if (r0 < r1) {  // block-uniform
-      const uint64_t e0 = a.off[r0];
-      uint32_t span = static_cast<uint32_t>(a.off[r1] - e0);
-      if (span > 2 * kPullTile) span = 2 * kPullTile;
-      for (uint32_t i = tid; i < span; i += kBlock) tile[i] = pull_msg<APP, W>(a, e0 + i, overflow);
-      if (tid == 0) examined = span;
+      uint32_t o[kPer], w[kPer];
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        o[k] = a.outbox[u[k]];
+        w[k] = W ? a.w[e[k]] : 1u;
+      }
+      uint32_t m = kInf;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k)
+        if (r.beg + tid + k * kBlock < r.end) m = min(m, edge_msg<APP, W>(o[k], w[k], overflow));
+      m = wave_min(m);
+      if (lane_id() == 0) red[tid / kWave] = m;
       __syncthreads();
-      const uint32_t nrows = r1 - r0;
-      uint32_t G = kWave;
-      while (G > 1 && G * nrows > kBlock) G >>= 1;
-      const uint32_t groups = kBlock / G, gi = tid / G, li = tid % G;
-      for (uint32_t base = 0; base < nrows; base += groups) {
-        const uint32_t row = base + gi;
-        uint32_t m = kInf;
-        if (row < nrows) {
-          const uint32_t v = r0 + row;
-          uint32_t lo = static_cast<uint32_t>(a.off[v] - e0), hi = static_cast<uint32_t>(a.off[v + 1] - e0);
-          if (hi > span) hi = span;
-          for (uint32_t j = lo + li; j < hi; j += G) m = min(m, tile[j]);
+      if (tid == 0) {
+        m = min(min(red[0], red[1]), min(red[2], red[3]));
+        if (m < kInf && atomicMin(a.mail_out + r.v, m) == kInf) {
+          next_count += 1;
+          next_deg += a.outdeg[r.v];
         }
-        for (uint32_t o = G >> 1; o >= 1; o >>= 1) m = min(m, static_cast<uint32_t>(__shfl_xor(m, static_cast<int>(o))));
-        const bool got = li == 0 && row < nrows && m < kInf;
-        if (got) {
-          a.mail_out[r0 + row] = m;
-          next_deg += a.outdeg[r0 + row];
-        }
-        wave_append(got, r0 + row, a.frontier_out, &a.ctr->next_count);
+      }
+      __syncthreads();
+      continue;
+    }
+    uint32_t r0, r1;
+    group_rows(a.t, item - a.t.nc, r0, r1);
+    if (r0 >= r1) continue;  // block-uniform
+    const uint64_t e0 = off[r0];
+    uint32_t span = static_cast<uint32_t>(off[r1] - e0);
+    if (span > 2 * kPullTile) span = 2 * kPullTile;
+    for (uint32_t base = 0; base < span; base += 4 * kBlock) {  // block-uniform
+      uint32_t ic[4];
+      int32_t u[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t i = base + tid + k * kBlock;
+        ic[k] = i < span ? i : span - 1;
+        u[k] = __builtin_nontemporal_load(src + e0 + ic[k]);
+      }
+      uint32_t o[4], w[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        o[k] = a.outbox[u[k]];
+        w[k] = W ? a.w[e0 + ic[k]] : 1u;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t i = base + tid + k * kBlock;
+        if (i < span) tile[i] = edge_msg<APP, W>(o[k], w[k], overflow);
       }
     }
+    __syncthreads();
+    const uint32_t nrows = r1 - r0;
+    uint32_t G = kWave;
+    while (G > 1 && G * nrows > kBlock) G >>= 1;
+    const uint32_t groups = kBlock / G, gi = tid / G, li = tid % G;
+    for (uint32_t rb = 0; rb < nrows; rb += groups) {
+      const uint32_t row = rb + gi;
+      uint32_t m = kInf;
+      if (row < nrows) {
+        const uint32_t v = r0 + row;
+        uint32_t lo = static_cast<uint32_t>(off[v] - e0), hi = static_cast<uint32_t>(off[v + 1] - e0);
+        if (hi > span) hi = span;
+        for (uint32_t j = lo + li; j < hi; j += G) m = min(m, tile[j]);
+      }
+      for (uint32_t o = G >> 1; o >= 1; o >>= 1) m = min(m, static_cast<uint32_t>(__shfl_xor(m, static_cast<int>(o))));
+      if (li == 0 && row < nrows && m < kInf) {
+        a.mail_out[r0 + row] = m;
+        next_count += 1;
+        next_deg += a.outdeg[r0 + row];
+      }
+    }
+    __syncthreads();  // the tile is reused by the next item
   }
-  block_add_u64(examined, &a.ctr->examined);
-  block_add_u64(next_deg, &a.ctr->next_deg);
-  if (__ballot(overflow) && lane_id() == 0) atomicOr(&a.ctr->overflow, 1u);
+  flush_counters(a.ctr, 0, 0, next_count, next_deg, overflow);
+}
+
+// End of a superstep: sum the counter slots (one wavefront, lane t reads
+// slot t) and, when a selector is given and work is pending, choose the
+// exchange of the next superstep with the network.
+__global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_t next_superstep, uint64_t e,
+                                                       const double* sel, Decision* out) {
+  static_assert(kCtrSlots == kWave, "one slot per lane");
+  const CtrSlot& x = c[threadIdx.x];
+  const uint64_t nc = wave_sum_u64(x.next_count);
+  const uint64_t se = wave_sum_u64(x.senders);
+  const uint64_t me = wave_sum_u64(x.messages);
+  const uint64_t nd = wave_sum_u64(x.next_deg);
+  const bool ovf = __ballot(x.overflow != 0) != 0;
+  if (threadIdx.x == 0) {
+    Decision d;
+    d.next_count = nc;
+    d.senders = se;
+    d.messages = me;
+    d.next_deg = nd;
+    d.overflow = ovf ? 1u : 0u;
+    d.mode = 0;
+    d.margin = 0.0;
+    d.pad[0] = d.pad[1] = 0;
+    if (sel && nc) {
+      int m = 0;
+      d.margin = sel_predict_mode(sel, nc, nd, next_superstep, e, &m);
+      d.mode = m;
+    }
+    *out = d;
+  }
 }
 
 // ------------------------------------------------------------------ host --
 
 template <int APP, bool W>
-static hipError_t launch_push(const MinPushArgs& a, uint32_t items, hipStream_t s) {
-  hipLaunchKernelGGL((minprop_push_kernel<APP, W>), dim3(grid_for(items, kBlock, 0xFFFFFFFFu)), dim3(kBlock), 0, s, a);
+static hipError_t launch_push(const MinPushArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((minprop_push_kernel<APP, W>), dim3(grid_for(a.act.count, kBlock, 0xFFFFFFFFu)), dim3(kBlock), 0, s,
+                     a);
   return hipGetLastError();
 }
 template <int APP, bool W>
-static hipError_t launch_pull(const MinPullArgs& a, uint32_t blocks, hipStream_t s) {
-  hipLaunchKernelGGL((minprop_pull_kernel<APP, W>), dim3(blocks), dim3(kBlock), 0, s, a);
+static hipError_t launch_pull(const MinPullArgs& a, hipStream_t s) {
+  const uint32_t grid = std::max(1u, std::min(a.t.nc + a.t.nb, kExchangeGrid));
+  hipLaunchKernelGGL((minprop_pull_kernel<APP, W>), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-static hipError_t push_dispatch(ipg_app app, bool weighted, const MinPushArgs& a, uint32_t items, hipStream_t s) {
-  if (app == IPG_APP_CC_HASHMIN) return launch_push<IPG_APP_CC_HASHMIN, false>(a, items, s);
-  return weighted ? launch_push<IPG_APP_SSSP, true>(a, items, s) : launch_push<IPG_APP_SSSP, false>(a, items, s);
+static hipError_t push_dispatch(ipg_app app, bool weighted, const MinPushArgs& a, hipStream_t s) {
+  if (app == IPG_APP_CC_HASHMIN) return launch_push<IPG_APP_CC_HASHMIN, false>(a, s);
+  return weighted ? launch_push<IPG_APP_SSSP, true>(a, s) : launch_push<IPG_APP_SSSP, false>(a, s);
 }
-static hipError_t pull_dispatch(ipg_app app, bool weighted, const MinPullArgs& a, uint32_t blocks, hipStream_t s) {
-  if (app == IPG_APP_CC_HASHMIN) return launch_pull<IPG_APP_CC_HASHMIN, false>(a, blocks, s);
-  return weighted ? launch_pull<IPG_APP_SSSP, true>(a, blocks, s) : launch_pull<IPG_APP_SSSP, false>(a, blocks, s);
+static hipError_t pull_dispatch(ipg_app app, bool weighted, const MinPullArgs& a, hipStream_t s) {
+  if (app == IPG_APP_CC_HASHMIN) return launch_pull<IPG_APP_CC_HASHMIN, false>(a, s);
+  return weighted ? launch_pull<IPG_APP_SSSP, true>(a, s) : launch_pull<IPG_APP_SSSP, false>(a, s);
 }
+
+// Frontier lists up to this size are visited through the list; larger ones
+// by sweeping the mailboxes.
+static uint64_t list_limit(uint32_t n) { return std::max<uint64_t>(4096, n / 16); }
 
 ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_opts& o, const RunWs& w,
                        hipStream_t s, StepTimer& tm, ipg_run_stats* st) {
   const uint32_t n = g->n;
   const uint64_t e = g->e;
   const bool weighted = app == IPG_APP_SSSP && g->csr_w != nullptr;
-  const uint32_t words = n / 32 + 1;
   const uint32_t gv = grid_for(n, kBlock, 16384);
 
   // Out-degree of the SSSP source, for the superstep-0 exchange choice.
@@ -301,31 +384,52 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
   }
   IPG_HIP(fill_u32(w.mail_a, n, kInf, s));
   IPG_HIP(fill_u32(w.mail_b, n, kInf, s));
-  IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.ctr), 2 * sizeof(StepCounters) / 4, 0, s));
+  IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.ctr), 2 * kCtrSlots * sizeof(CtrSlot) / 4, 0, s));
+  IPG_HIP(fill_u32(w.list_ctr, 2, 0, s));
 
   uint32_t *fin = w.fr_a, *fout = w.fr_b, *min_ = w.mail_a, *mout = w.mail_b;
   uint64_t count = app == IPG_APP_CC_HASHMIN ? n : 1;
   uint64_t degsum = app == IPG_APP_CC_HASHMIN ? e : src_deg;
+  bool list_ok = false;  // fin holds the whole active set
   uint32_t step = 0;
   ipg_status status = IPG_OK;
   uint64_t tot_msgs = 0, tot_exam = 0;
+  int next_sel_mode = 0;  // the selector's choice for the coming superstep
+  if (o.mode == IPG_MODE_AUTO && o.selector) {
+    double hp[kSelParams];
+    IPG_HIP(hipMemcpyAsync(hp, o.selector, sizeof(hp), hipMemcpyDeviceToHost, s));
+    IPG_HIP(hipStreamSynchronize(s));
+    sel_predict_mode(hp, count, degsum, 0, e, &next_sel_mode);
+  }
   IPG_HIP(tm.start(s));
   for (;;) {
     ModeQuery q{n, e, count, degsum, step, app};
-    const ipg_mode mode = choose_mode(o.mode, q);
-    StepCounters* c = w.ctr + (step & 1);
-    StepCounters* cc = w.ctr + ((step + 1) & 1);
+    ipg_mode mode = o.mode;
+    if (mode == IPG_MODE_AUTO) mode = next_sel_mode ? static_cast<ipg_mode>(next_sel_mode) : heuristic_mode(q);
+    CtrSlot* c = w.ctr + (step & 1) * kCtrSlots;
+    CtrSlot* cc = w.ctr + ((step + 1) & 1) * kCtrSlots;
+    uint32_t* lc = w.list_ctr + (step & 1);
+    Active act;
+    act.source = o.source;
+    act.list = fin;
+    if (step == 0) {
+      act.phase = app == IPG_APP_CC_HASHMIN ? kSendAll : kSendSource;
+      act.count = app == IPG_APP_CC_HASHMIN ? n : 1;
+    } else if (list_ok) {
+      act.phase = kStepList;
+      act.count = static_cast<uint32_t>(count);
+    } else {
+      act.phase = kStepDense;
+      act.count = n;
+    }
     if (mode == IPG_MODE_PUSH) {
       if (step == 0) {
         hipLaunchKernelGGL(minprop_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, static_cast<int>(app), o.source,
-                           w.value_u32, g->t.outdeg, 0, w.sent, c);
+                           w.value_u32, g->t.outdeg, 0, w.outbox, c);
         IPG_HIP(hipGetLastError());
       }
       MinPushArgs a;
-      a.phase = step > 0 ? kPhaseStep : (app == IPG_APP_CC_HASHMIN ? kPhaseSendAll : kPhaseSendSource);
-      a.source = o.source;
-      a.count = static_cast<uint32_t>(count);
-      a.frontier_in = fin;
+      a.act = act;
       a.off = g->csr_off;
       a.dst = g->csr_dst;
       a.w = weighted ? g->csr_w : nullptr;
@@ -333,58 +437,58 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
       a.value = w.value_u32;
       a.mail_in = min_;
       a.mail_out = mout;
-      a.frontier_out = fout;
+      a.list_out = fout;
+      a.list_ctr = lc;
       a.ctr = c;
       a.ctr_clear = cc;
-      IPG_HIP(push_dispatch(app, weighted, a, a.count, s));
+      IPG_HIP(push_dispatch(app, weighted, a, s));
     } else {
-      IPG_HIP(fill_u32(w.sent, words, 0u, s));
       if (step == 0) {
         hipLaunchKernelGGL(minprop_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, static_cast<int>(app), o.source,
-                           w.value_u32, g->t.outdeg, 1, w.sent, c);
+                           w.value_u32, g->t.outdeg, 1, w.outbox, c);
         IPG_HIP(hipGetLastError());
       } else {
+        IPG_HIP(fill_u32(w.outbox, n, kInf, s));
         MinApplyArgs ap;
-        ap.count = static_cast<uint32_t>(count);
-        ap.frontier_in = fin;
+        ap.act = act;
         ap.outdeg = g->t.outdeg;
         ap.value = w.value_u32;
         ap.mail_in = min_;
-        ap.sent = w.sent;
+        ap.outbox = w.outbox;
         ap.ctr = c;
-        ap.ctr_clear = nullptr;
-        hipLaunchKernelGGL(minprop_apply_kernel, dim3(grid_for(count, kBlock, 16384)), dim3(kBlock), 0, s, ap);
+        hipLaunchKernelGGL(minprop_apply_kernel, dim3(grid_for(act.count, kBlock, 8192)), dim3(kBlock), 0, s, ap);
         IPG_HIP(hipGetLastError());
       }
       MinPullArgs pa;
-      pa.off = g->csc_off;
-      pa.src = g->csc_src;
+      pa.t = pull_tiling(g);
       pa.w = weighted ? g->csc_w : nullptr;
       pa.outdeg = g->t.outdeg;
-      pa.rb = g->t.pull_rb;
-      pa.long_rows = g->t.long_rows;
-      pa.nl = g->nl;
-      pa.sent = w.sent;
-      pa.value = w.value_u32;
+      pa.outbox = w.outbox;
       pa.mail_out = mout;
-      pa.frontier_out = fout;
       pa.ctr = c;
       pa.ctr_clear = cc;
-      IPG_HIP(pull_dispatch(app, weighted, pa, g->nl + g->nb, s));
+      IPG_HIP(pull_dispatch(app, weighted, pa, s));
     }
     IPG_HIP(tm.step(s, step));
-    StepCounters h;
-    IPG_HIP(hipMemcpyAsync(&h, c, sizeof(h), hipMemcpyDeviceToHost, s));
+    const double* sel = o.mode == IPG_MODE_AUTO ? o.selector : nullptr;
+    hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kWave), 0, s, c, step + 1, e, sel, w.decision);
+    IPG_HIP(hipGetLastError());
+    uint32_t lcount = 0;
+    Decision h;
+    IPG_HIP(hipMemcpyAsync(&h, w.decision, sizeof(h), hipMemcpyDeviceToHost, s));
+    IPG_HIP(hipMemcpyAsync(&lcount, lc, sizeof(lcount), hipMemcpyDeviceToHost, s));
+    IPG_HIP(fill_u32(lc, 1, 0, s));  // reused two supersteps later
     IPG_HIP(hipStreamSynchronize(s));
+    const uint64_t examined = mode == IPG_MODE_PUSH ? h.messages : e;
     if (st && step < st->trace_cap) {
       if (st->active) st->active[step] = step == 0 ? n : count;
       if (st->senders) st->senders[step] = h.senders;
       if (st->messages) st->messages[step] = h.messages;
-      if (st->examined) st->examined[step] = h.examined;
+      if (st->examined) st->examined[step] = examined;
       if (st->mode) st->mode[step] = static_cast<uint8_t>(mode);
     }
     tot_msgs += h.messages;
-    tot_exam += h.examined;
+    tot_exam += examined;
     ++step;
     if (h.overflow) {
       status = fail(IPG_EOVERFLOW, "SSSP distance would reach 0xFFFFFFFF (INF)");
@@ -395,8 +499,14 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
       status = IPG_NOT_CONVERGED;
       break;
     }
+    if (mode == IPG_MODE_PUSH && lcount != h.next_count) {
+      status = fail(IPG_EDEVICE, "frontier list length disagrees with the mailbox count");
+      break;
+    }
     count = h.next_count;
     degsum = h.next_deg;
+    next_sel_mode = h.mode;
+    list_ok = mode == IPG_MODE_PUSH && count <= list_limit(n);
     std::swap(fin, fout);
     std::swap(min_, mout);
   }

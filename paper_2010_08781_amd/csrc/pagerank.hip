@@ -15,6 +15,8 @@
 // one-slot mailboxes with FP64 atomic adds (the lock-free combiner the paper
 // lists as future work, Section 4.3.2 and Section 9); summation order varies
 // from run to run within rounding.
+#include <algorithm>
+
 #include "common.h"
 #include "engine.h"
 #include "scatter.h"
@@ -22,15 +24,12 @@
 namespace ipg {
 
 struct PrPullArgs {
-  const uint64_t* off;    // CSC offsets
-  const int32_t* src;     // CSC sources
+  PullTiling t;
   const uint32_t* outdeg;
-  const uint32_t* rb;     // pull row-groups
-  const uint32_t* long_rows;
-  uint32_t nl;
   const double* contrib_in;
   double* contrib_out;
   double* value;
+  double* partial;        // per long-row chunk
   double ratio;           // 0.15 / N
   int last;               // superstep == T: store the rank, no broadcast
 };
@@ -45,61 +44,109 @@ __device__ __forceinline__ void pr_finish(const PrPullArgs& a, uint32_t v, doubl
   }
 }
 
-// One launch per superstep.  Workgroups [0, nl) each reduce one long row
-// (in-degree > kPullTile); workgroups [nl, nl + nb) each take one row-group:
-// its in-edges (< 2*kPullTile) are gathered into LDS with coalesced reads of
-// the CSC, then each row is reduced from LDS by G lanes (G chosen from the
-// group's row count so that the 256 lanes stay busy).
+// Sum over the workgroup in a fixed order; every thread gets the result.
+__device__ __forceinline__ double block_sum(double s, double* red) {
+  s = wave_sum(s);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = s;
+  __syncthreads();
+  const double t = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return t;
+}
+
+// First launch of a pull superstep: the partial sum of every chunk of
+// kPullTile in-edges of a long row (grid-stride over chunks).  Loads are
+// unconditional (index clamped into the chunk) so that all of a thread's
+// gathers are in flight together; out-of-range lanes are masked.
+__global__ __launch_bounds__(kBlock) void pr_chunk_kernel(PrPullArgs a) {
+  __shared__ double red[kWavesPerBlock];
+  const uint32_t tid = threadIdx.x;
+  const int32_t* src = a.t.src;
+  for (uint32_t c = blockIdx.x; c < a.t.nc; c += gridDim.x) {
+    const ChunkRef r = chunk_ref(a.t, c);
+    constexpr int kPer = kPullTile / kBlock;
+    int32_t u[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      uint64_t e = r.beg + tid + k * kBlock;
+      e = e < r.end ? e : r.end - 1;
+      u[k] = __builtin_nontemporal_load(src + e);
+    }
+    double x[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) x[k] = a.contrib_in[u[k]];
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (r.beg + tid + k * kBlock < r.end) s += x[k];
+    s = block_sum(s, red);
+    if (tid == 0) a.partial[c] = s;
+  }
+}
+
+// Second launch of a pull superstep (grid-stride over nl + nb work items):
+//  * item l < nl: finish long row l -- add its chunk partials in chunk order
+//    (a fixed order, so results are bitwise reproducible);
+//  * item nl + k: row-group k.  Its in-edges (fewer than 2*kPullTile) are
+//    streamed from the CSC with coalesced loads, their sources' outboxes
+//    gathered into LDS, then each row is reduced from LDS by G lanes (G from
+//    the group's row count so that the 256 lanes stay busy).
 __global__ __launch_bounds__(kBlock) void pr_pull_kernel(PrPullArgs a) {
   __shared__ double tile[2 * kPullTile];
   __shared__ double red[kWavesPerBlock];
-  const uint32_t b = blockIdx.x;
   const uint32_t tid = threadIdx.x;
-  if (b < a.nl) {
-    const uint32_t v = a.long_rows[b];
-    const uint64_t beg = a.off[v], end = a.off[v + 1];
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    uint64_t e = beg + tid;
-    for (; e + 3 * kBlock < end; e += 4 * kBlock) {
-      const int32_t u0 = a.src[e], u1 = a.src[e + kBlock], u2 = a.src[e + 2 * kBlock], u3 = a.src[e + 3 * kBlock];
-      s0 += a.contrib_in[u0];
-      s1 += a.contrib_in[u1];
-      s2 += a.contrib_in[u2];
-      s3 += a.contrib_in[u3];
+  const int32_t* src = a.t.src;
+  const uint64_t* off = a.t.off;
+  const uint32_t items = a.t.nl + a.t.nb;
+  for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
+    if (item < a.t.nl) {
+      const uint32_t f = a.t.lr_first[item], nch = a.t.lr_first[item + 1] - f;
+      double x = 0.0;
+      for (uint32_t i = tid; i < nch; i += kBlock) x += a.partial[f + i];
+      x = block_sum(x, red);
+      if (tid == 0) pr_finish(a, a.t.long_rows[item], x);
+      continue;
     }
-    for (; e < end; e += kBlock) s0 += a.contrib_in[a.src[e]];
-    double s = (s0 + s1) + (s2 + s3);
-    s = wave_sum(s);
-    if (lane_id() == 0) red[tid / kWave] = s;
+    uint32_t r0, r1;
+    group_rows(a.t, item - a.t.nl, r0, r1);
+    if (r0 >= r1) continue;  // block-uniform
+    const uint64_t e0 = off[r0];
+    uint32_t span = static_cast<uint32_t>(off[r1] - e0);
+    if (span > 2 * kPullTile) span = 2 * kPullTile;  // only reachable with inconsistent offsets
+    for (uint32_t base = 0; base < span; base += 4 * kBlock) {  // block-uniform, at most 2 passes
+      int32_t u[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t i = base + tid + k * kBlock;
+        u[k] = __builtin_nontemporal_load(src + e0 + (i < span ? i : span - 1));
+      }
+      double x[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[k] = a.contrib_in[u[k]];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t i = base + tid + k * kBlock;
+        if (i < span) tile[i] = x[k];
+      }
+    }
     __syncthreads();
-    if (tid == 0) pr_finish(a, v, (red[0] + red[1]) + (red[2] + red[3]));
-    return;
-  }
-  const uint32_t k = b - a.nl;
-  const uint32_t r0 = a.rb[k];
-  uint32_t r1 = a.rb[k + 1];
-  if (r1 > r0 && a.off[r1] - a.off[r1 - 1] > kPullTile) --r1;  // the group's long last row has its own workgroup
-  if (r0 >= r1) return;
-  const uint64_t e0 = a.off[r0];
-  uint32_t span = static_cast<uint32_t>(a.off[r1] - e0);
-  if (span > 2 * kPullTile) span = 2 * kPullTile;  // only reachable with inconsistent offsets
-  for (uint32_t i = tid; i < span; i += kBlock) tile[i] = a.contrib_in[a.src[e0 + i]];
-  __syncthreads();
-  const uint32_t nrows = r1 - r0;
-  uint32_t G = kWave;
-  while (G > 1 && G * nrows > kBlock) G >>= 1;
-  const uint32_t groups = kBlock / G, gi = tid / G, li = tid % G;
-  for (uint32_t base = 0; base < nrows; base += groups) {
-    const uint32_t row = base + gi;
-    double s = 0.0;
-    if (row < nrows) {
-      const uint32_t v = r0 + row;
-      uint32_t lo = static_cast<uint32_t>(a.off[v] - e0), hi = static_cast<uint32_t>(a.off[v + 1] - e0);
-      if (hi > span) hi = span;
-      for (uint32_t j = lo + li; j < hi; j += G) s += tile[j];
+    const uint32_t nrows = r1 - r0;
+    uint32_t G = kWave;
+    while (G > 1 && G * nrows > kBlock) G >>= 1;
+    const uint32_t groups = kBlock / G, gi = tid / G, li = tid % G;
+    for (uint32_t rb = 0; rb < nrows; rb += groups) {
+      const uint32_t row = rb + gi;
+      double s = 0.0;
+      if (row < nrows) {
+        const uint32_t v = r0 + row;
+        uint32_t lo = static_cast<uint32_t>(off[v] - e0), hi = static_cast<uint32_t>(off[v + 1] - e0);
+        if (hi > span) hi = span;
+        for (uint32_t j = lo + li; j < hi; j += G) s += tile[j];
+      }
+      for (uint32_t o = G >> 1; o >= 1; o >>= 1) s += __shfl_xor(s, static_cast<int>(o));
+      if (li == 0 && row < nrows) pr_finish(a, r0 + row, s);
     }
-    for (uint32_t o = G >> 1; o >= 1; o >>= 1) s += __shfl_xor(s, static_cast<int>(o));
-    if (li == 0 && row < nrows) pr_finish(a, r0 + row, s);
+    __syncthreads();  // the tile is reused by the next item
   }
 }
 
@@ -175,19 +222,20 @@ ipg_status run_pagerank(ipg_graph* g, uint32_t T, ipg_mode mode, const RunWs& w,
     IPG_HIP(hipGetLastError());
     IPG_HIP(tm.step(s, 0));
     PrPullArgs a;
-    a.off = g->csc_off;
-    a.src = g->csc_src;
+    a.t = pull_tiling(g);
     a.outdeg = g->t.outdeg;
-    a.rb = g->t.pull_rb;
-    a.long_rows = g->t.long_rows;
-    a.nl = g->nl;
     a.value = w.value_f64;
+    a.partial = w.partial;
     a.ratio = ratio;
     for (uint32_t step = 1; step <= T; ++step) {
       a.contrib_in = (step & 1) ? w.f64_a : w.f64_b;
       a.contrib_out = (step & 1) ? w.f64_b : w.f64_a;
       a.last = step == T;
-      hipLaunchKernelGGL(pr_pull_kernel, dim3(g->nl + g->nb), dim3(kBlock), 0, s, a);
+      if (g->nc) {
+        hipLaunchKernelGGL(pr_chunk_kernel, dim3(std::min(g->nc, kExchangeGrid)), dim3(kBlock), 0, s, a);
+        IPG_HIP(hipGetLastError());
+      }
+      hipLaunchKernelGGL(pr_pull_kernel, dim3(std::min(g->nl + g->nb, kExchangeGrid)), dim3(kBlock), 0, s, a);
       IPG_HIP(hipGetLastError());
       IPG_HIP(tm.step(s, step));
     }

@@ -1,0 +1,54 @@
+// selector.h -- the exchange selector's network, shared by the training
+// kernels and the superstep engine (inference on the device).
+#pragma once
+
+#include "common.h"
+
+namespace ipg {
+
+constexpr int kSelD = 4, kSelH = 16, kSelK = 2;
+constexpr int kSelParams = kSelH * kSelD + kSelH + kSelH * kSelH + kSelH + kSelK * kSelH + kSelK;
+
+// Inputs of the network for one superstep.
+__host__ __device__ inline void sel_features(uint64_t frontier, uint64_t frontier_deg, uint32_t superstep, uint64_t e,
+                                             double* x) {
+  x[0] = log2(1.0 + static_cast<double>(frontier)) / 32.0;
+  x[1] = log2(1.0 + static_cast<double>(frontier_deg)) / 32.0;
+  x[2] = static_cast<double>(superstep < 128u ? superstep : 128u) / 64.0;
+  x[3] = log2(1.0 + static_cast<double>(e)) / 32.0;
+}
+
+__host__ __device__ inline void sel_forward1(const double* p, const double* x, double* h1, double* h2, double* y) {
+  const double* W1 = p;
+  const double* b1 = W1 + kSelH * kSelD;
+  const double* W2 = b1 + kSelH;
+  const double* b2 = W2 + kSelH * kSelH;
+  const double* W3 = b2 + kSelH;
+  const double* b3 = W3 + kSelK * kSelH;
+  for (int j = 0; j < kSelH; ++j) {
+    double z = b1[j];
+    for (int d = 0; d < kSelD; ++d) z += W1[j * kSelD + d] * x[d];
+    h1[j] = tanh(z);
+  }
+  for (int j = 0; j < kSelH; ++j) {
+    double z = b2[j];
+    for (int l = 0; l < kSelH; ++l) z += W2[j * kSelH + l] * h1[l];
+    h2[j] = tanh(z);
+  }
+  for (int k = 0; k < kSelK; ++k) {
+    double z = b3[k];
+    for (int j = 0; j < kSelH; ++j) z += W3[k * kSelH + j] * h2[j];
+    y[k] = z;
+  }
+}
+
+__host__ __device__ inline double sel_predict_mode(const double* p, uint64_t frontier, uint64_t frontier_deg, uint32_t superstep,
+                                   uint64_t e, int* mode) {
+  double x[kSelD], h1[kSelH], h2[kSelH], y[kSelK];
+  sel_features(frontier, frontier_deg, superstep, e, x);
+  sel_forward1(p, x, h1, h2, y);
+  *mode = y[1] < y[0] ? IPG_MODE_PULL : IPG_MODE_PUSH;
+  return y[0] - y[1];
+}
+
+}  // namespace ipg

@@ -100,14 +100,19 @@ __global__ void long_rows_kernel(const uint64_t* off, uint32_t n, uint32_t* list
   }
 }
 
-static uint32_t num_pull_groups(uint64_t e) { return static_cast<uint32_t>(e / kPullTile + 1); }
-static uint64_t long_rows_cap(uint64_t e) { return e / (kPullTile + 1) + 1; }
+__global__ void row_degrees_kernel(const uint64_t* off, const uint32_t* rows, uint32_t nr, uint64_t* deg) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nr; i += (uint64_t)gridDim.x * blockDim.x)
+    deg[i] = off[rows[i] + 1] - off[rows[i]];
+}
+
 
 static size_t carve_graph(Carver& c, uint32_t n, uint64_t e, GraphTables* t) {
   GraphTables tt;
   tt.outdeg = c.take<uint32_t>(n ? n : 1);
   tt.pull_rb = c.take<uint32_t>(num_pull_groups(e) + 1);
   tt.long_rows = c.take<uint32_t>(long_rows_cap(e));
+  tt.lr_first = c.take<uint32_t>(long_rows_cap(e) + 1);
+  tt.ch_row = c.take<uint32_t>(chunks_cap(e));
   tt.flags = c.take<uint32_t>(kNumFlags + 1);  // + long-row counter
   if (t) *t = tt;
   return align_up(c.used, 256);
@@ -187,12 +192,36 @@ extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t
   if (h[kFlagDegree]) return fail(IPG_EBADGRAPH, "an out-degree exceeds 2^32-1");
   const uint32_t nl = h[kNumFlags];
   if (nl > cap) return fail(IPG_EBADGRAPH, "in-degree table overflow (offsets inconsistent with E)");
-  if (nl > 1) {  // ascending order: a deterministic assignment of long rows to workgroups
+  uint32_t nc = 0;
+  if (nl > 0) {
+    // Long rows in ascending order (a deterministic assignment to
+    // workgroups), cut into chunks of kPullTile in-edges.
     std::vector<uint32_t> rows(nl);
     IPG_HIP(hipMemcpyAsync(rows.data(), t.long_rows, nl * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     IPG_HIP(hipStreamSynchronize(s));
     std::sort(rows.begin(), rows.end());
     IPG_HIP(hipMemcpyAsync(t.long_rows, rows.data(), nl * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    // degrees via the chunk table's space (large enough: nl <= chunks_cap / 2)
+    uint64_t* degs = reinterpret_cast<uint64_t*>(t.ch_row);
+    hipLaunchKernelGGL(row_degrees_kernel, dim3(grid_for(nl, kBlock, 1024)), dim3(kBlock), 0, s, csc_off, t.long_rows, nl,
+                       degs);
+    IPG_HIP(hipGetLastError());
+    std::vector<uint64_t> deg(nl);
+    IPG_HIP(hipMemcpyAsync(deg.data(), degs, nl * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    IPG_HIP(hipStreamSynchronize(s));
+    std::vector<uint32_t> first(nl + 1), chrow;
+    uint64_t acc = 0;
+    for (uint32_t l = 0; l < nl; ++l) {
+      first[l] = static_cast<uint32_t>(acc);
+      const uint64_t k = (deg[l] + kPullTile - 1) / kPullTile;
+      acc += k;
+      if (acc > chunks_cap(e)) return fail(IPG_EBADGRAPH, "long-row chunk table overflow (offsets inconsistent with E)");
+      for (uint64_t j = 0; j < k; ++j) chrow.push_back(l);
+    }
+    first[nl] = static_cast<uint32_t>(acc);
+    nc = static_cast<uint32_t>(acc);
+    IPG_HIP(hipMemcpyAsync(t.lr_first, first.data(), (nl + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    IPG_HIP(hipMemcpyAsync(t.ch_row, chrow.data(), nc * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     IPG_HIP(hipStreamSynchronize(s));
   }
 
@@ -210,6 +239,7 @@ extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t
   g->t = t;
   g->nb = nb;
   g->nl = nl;
+  g->nc = nc;
   IPG_HIP(hipGetDevice(&g->device));
   g->has_values = 0;
   g->last_app = -1;

@@ -163,6 +163,21 @@ def test_sssp_weighted_directed_with_loops(ipg):
     check_min_app(ipg, hg, "sssp", source=5)
 
 
+def test_push_frontier_list_dense_transitions(ipg):
+    # SSSP from a hub on a symmetrised R-MAT: the push frontier goes from a
+    # short list (the source) to a dense sweep of the mailboxes and back to
+    # a list; every transition must keep values and traces exact.
+    hg = graphgen.rmat(16, 16, seed=6, symmetric=True)
+    ref = oracle.run_graph("sssp", hg, 0, source=0)
+    g = ipg.Graph.from_host(hg)
+    vals, st = g.run("sssp", source=0, mode="push")
+    assert np.array_equal(to_np(vals), ref.values)
+    assert np.array_equal(st.trace, ref.trace)
+    limit = max(4096, hg.n // 16)
+    sizes = ref.trace[1:, 0]
+    assert (sizes > limit).any() and (sizes[sizes > 0] <= limit).any()
+
+
 # ------------------------------------------------------------ boundary ----
 
 def test_cap_returns_not_converged(ipg):
