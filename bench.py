@@ -41,6 +41,8 @@ def main():
     ap.add_argument("--mode", default="auto", help="exchange for CC/SSSP: auto, push or pull")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apps", default="pagerank,cc,sssp")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (to scale HBM byte counters), then exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -55,6 +57,16 @@ def main():
     import paper_2010_08781_amd as ipg
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        x = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n, "copies": 3}), flush=True)
+        return
     ipg.lib()
     t0 = time.perf_counter()
     hg = graphgen.workload(args.workload)
@@ -114,7 +126,7 @@ def main():
         ach = nbytes / (avg_us * 1e-6) / 1e9
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                    "kernel": "pr_chunk_kernel+pr_pull_kernel (one PageRank pull superstep)",
+                    "kernel": "pr_items_kernel+pr_longrow_kernel (one PageRank pull superstep)",
                     "bytes_per_launch": nbytes, "avg_launch_us": round(avg_us, 2)}
 
     cpu = None

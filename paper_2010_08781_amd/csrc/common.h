@@ -18,15 +18,24 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr uint32_t kInf = 0xFFFFFFFFu;  // INF distance and identity of the min mailbox
 
 // Pull tiling of the CSC: rows are grouped by the edge chunk of width
-// kPullTile that contains their first in-edge; a group's edges are staged
-// through LDS.  Rows with more than kPullTile in-edges get a workgroup each.
-constexpr uint32_t kPullTile = 1024;
+// kPullTile that contains their first in-edge, so a group's in-edges (rows
+// of at most kPullTile in-edges) span fewer than kWaveTile = 2*kPullTile
+// edges and fit one wavefront's LDS tile.  Rows with more in-edges ("long
+// rows") are cut into chunks of kWaveTile in-edges.
+constexpr uint32_t kPullTile = 256;
+constexpr uint32_t kWaveTile = 2 * kPullTile;
+
+// A pull work item holds at most kItemRows rows (runs of vertices without
+// in-edges would otherwise pile into one item).
+constexpr uint32_t kItemRows = 64;
 
 inline uint32_t num_pull_groups(uint64_t e) { return static_cast<uint32_t>(e / kPullTile + 1); }
 // Rows with more than kPullTile in-edges: fewer than E / (kPullTile + 1) + 1.
 inline uint64_t long_rows_cap(uint64_t e) { return e / (kPullTile + 1) + 1; }
-// Chunks of the long rows: sum of ceil(deg / kPullTile) <= E/kPullTile + (long rows).
-inline uint64_t chunks_cap(uint64_t e) { return e / kPullTile + long_rows_cap(e) + 1; }
+// Chunks of the long rows: sum of ceil(deg / kWaveTile) <= E/kWaveTile + (long rows).
+inline uint64_t chunks_cap(uint64_t e) { return e / kWaveTile + long_rows_cap(e) + 1; }
+// Pull items: row pieces (at most groups + N / kItemRows) and long-row chunks.
+inline uint64_t items_cap(uint32_t n, uint64_t e) { return num_pull_groups(e) + n / kItemRows + 1 + chunks_cap(e); }
 
 // ---------------------------------------------------------------- status --
 void set_error(const std::string& msg);
@@ -56,12 +65,26 @@ struct Carver {
 };
 
 // ---------------------------------------------------------- graph handle --
+// One unit of pull work for one wavefront: either rows [r0, r1) whose
+// in-edges are [e0, e0 + ne) (fewer than kWaveTile edges, at most kItemRows
+// rows), or chunk `slot` of a long row r0 (ne <= kWaveTile edges from e0).
+struct PullItem {
+  uint64_t e0;
+  uint32_t ne;
+  uint32_t r0;
+  uint32_t r1;
+  uint32_t slot;  // kNoSlot for a row item
+};
+static_assert(sizeof(PullItem) == 24, "packed item");
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+
 struct GraphTables {
   uint32_t* outdeg;     // [n] out-degree (u32)
   uint32_t* pull_rb;    // [nb+1] first CSC row of each pull row-group
   uint32_t* long_rows;  // [nl] rows with in-degree > kPullTile, ascending
-  uint32_t* lr_first;   // [nl+1] first chunk of each long row (chunks of kPullTile in-edges)
+  uint32_t* lr_first;   // [nl+1] first chunk of each long row (chunks of kWaveTile in-edges)
   uint32_t* ch_row;     // [nc] index into long_rows of each chunk
+  PullItem* items;      // [ni] pull work items: the nc chunks first, then the row pieces
   uint32_t* flags;      // [4] validation flags
 };
 
@@ -75,35 +98,9 @@ struct PullTiling {
   const uint32_t* long_rows;
   const uint32_t* lr_first;
   const uint32_t* ch_row;
-  uint32_t nl, nc, nb;
+  const PullItem* items;
+  uint32_t nl, nc, nb, ni;
 };
-
-struct ChunkRef {
-  uint32_t l;         // long-row index
-  uint32_t j, nch;    // chunk index within the row, chunks of the row
-  uint32_t v;         // the row (vertex)
-  uint64_t beg, end;  // in-edge range of this chunk
-};
-
-__device__ __forceinline__ ChunkRef chunk_ref(const PullTiling& t, uint32_t c) {
-  ChunkRef r;
-  r.l = t.ch_row[c];
-  const uint32_t f = t.lr_first[r.l];
-  r.j = c - f;
-  r.nch = t.lr_first[r.l + 1] - f;
-  r.v = t.long_rows[r.l];
-  const uint64_t rb = t.off[r.v], re = t.off[r.v + 1];
-  r.beg = rb + static_cast<uint64_t>(r.j) * kPullTile;
-  r.end = r.beg + kPullTile < re ? r.beg + kPullTile : re;
-  return r;
-}
-
-// Rows [r0, r1) of row-group k, without a long last row (it is chunked).
-__device__ __forceinline__ void group_rows(const PullTiling& t, uint32_t k, uint32_t& r0, uint32_t& r1) {
-  r0 = t.rb[k];
-  r1 = t.rb[k + 1];
-  if (r1 > r0 && t.off[r1] - t.off[r1 - 1] > kPullTile) --r1;
-}
 
 }  // namespace ipg
 
@@ -121,6 +118,7 @@ struct ipg_graph {
   uint32_t nb;  // number of pull row-groups
   uint32_t nl;  // number of long rows
   uint32_t nc;  // number of long-row chunks
+  uint32_t ni;  // number of pull items
   int device;
   // last run
   int has_values;
@@ -239,6 +237,18 @@ __device__ __forceinline__ void flush_counters(CtrSlot* base, uint64_t senders, 
 // workgroups to cover the chip (256 CUs) several times over, few enough that
 // per-workgroup counter flushes stay cheap.
 constexpr uint32_t kExchangeGrid = 4096;
+// Grid of the pull item kernels: 8 resident workgroups (32 wavefronts, each
+// working on its own items) on each of 256 CUs.
+constexpr uint32_t kPullGrid = 2048;
+
+// Wavefront-local LDS ordering: make this lane's LDS writes visible to the
+// other lanes of its wavefront (LDS operations of one wavefront execute in
+// order; this also stops the compiler from moving LDS accesses across it).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __global__ void fill_u32_kernel(uint32_t* p, uint64_t n, uint32_t v);
 __global__ void fill_f64_kernel(double* p, uint64_t n, double v);

@@ -15,9 +15,11 @@ inline PullTiling pull_tiling(const ipg_graph* g) {
   t.long_rows = g->t.long_rows;
   t.lr_first = g->t.lr_first;
   t.ch_row = g->t.ch_row;
+  t.items = g->t.items;
   t.nl = g->nl;
   t.nc = g->nc;
   t.nb = g->nb;
+  t.ni = g->ni;
   return t;
 }
 

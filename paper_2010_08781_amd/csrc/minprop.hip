@@ -204,106 +204,89 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t x) {
   return x;
 }
 
-// Exchange of a pull superstep over the CSC (grid-stride over work items):
-// long-row chunks first -- each folds the minimum of its kPullTile in-edges
-// into the row's mailbox with an atomic min, and the chunk that finds the
-// mailbox empty counts the row as newly active -- then the row-groups,
-// whose in-edge messages are staged in LDS and min-reduced per row.
+// Exchange of a pull superstep over the CSC: every wavefront works through
+// its own pull items, as in the PageRank item kernel.  A long-row chunk
+// folds the minimum of its in-edges into the row's mailbox with an atomic
+// min, and the chunk that finds the mailbox empty counts the row as newly
+// active; a row item min-reduces each row from its LDS tile.
 template <int APP, bool W>
 __global__ __launch_bounds__(kBlock) void minprop_pull_kernel(MinPullArgs a) {
-  __shared__ uint32_t tile[2 * kPullTile];
-  __shared__ uint32_t red[kWavesPerBlock];
+  constexpr int kPer = kWaveTile / kWave;
+  constexpr int kRowPer = (kItemRows + kWave) / kWave;
+  __shared__ uint32_t s_tile[kWavesPerBlock][kWaveTile];
+  __shared__ uint32_t s_off[kWavesPerBlock][kItemRows + 1];
   clear_slots(a.ctr_clear);
-  const uint32_t tid = threadIdx.x;
+  const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
+  uint32_t* tile = s_tile[wv];
+  uint32_t* soff = s_off[wv];
   const int32_t* src = a.t.src;
   const uint64_t* off = a.t.off;
   uint64_t next_count = 0, next_deg = 0;
   uint32_t overflow = 0;
-  const uint32_t items = a.t.nc + a.t.nb;
-  for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
-    if (item < a.t.nc) {
-      const ChunkRef r = chunk_ref(a.t, item);
-      constexpr int kPer = kPullTile / kBlock;
-      uint64_t e[kPer];
-      int32_t u[kPer];
+  const uint32_t nw = gridDim.x * kWavesPerBlock;
+  for (uint32_t item = blockIdx.x * kWavesPerBlock + wv; item < a.t.ni; item += nw) {
+    const PullItem it = a.t.items[item];
+    const bool chunk = it.slot != kNoSlot;
+    const uint32_t ne = it.ne < kWaveTile ? it.ne : kWaveTile;
+    const uint32_t nrows = chunk ? 0 : it.r1 - it.r0;
+    uint32_t ic[kPer];
+    int32_t u[kPer];
 #pragma unroll
-      for (int k = 0; k < kPer; ++k) {
-        e[k] = r.beg + tid + k * kBlock;
-        e[k] = e[k] < r.end ? e[k] : r.end - 1;
-        u[k] = __builtin_nontemporal_load(src + e[k]);
-      }
-      uint32_t o[kPer], w[kPer];
+    for (int k = 0; k < kPer; ++k) {
+      const uint32_t i = lane + k * kWave;
+      ic[k] = i < ne ? i : (ne ? ne - 1 : 0);
+      u[k] = ne ? __builtin_nontemporal_load(src + it.e0 + ic[k]) : 0;
+    }
+    if (!chunk) {
 #pragma unroll
-      for (int k = 0; k < kPer; ++k) {
-        o[k] = a.outbox[u[k]];
-        w[k] = W ? a.w[e[k]] : 1u;
+      for (int k = 0; k < kRowPer; ++k) {
+        const uint32_t r = lane + k * kWave;
+        if (r <= nrows) soff[r] = static_cast<uint32_t>(off[it.r0 + r] - it.e0);
       }
+    }
+    uint32_t o[kPer], w[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      o[k] = ne ? a.outbox[u[k]] : kInf;
+      w[k] = (W && ne) ? a.w[it.e0 + ic[k]] : 1u;
+    }
+    if (chunk) {
       uint32_t m = kInf;
 #pragma unroll
       for (int k = 0; k < kPer; ++k)
-        if (r.beg + tid + k * kBlock < r.end) m = min(m, edge_msg<APP, W>(o[k], w[k], overflow));
+        if (lane + k * kWave < ne) m = min(m, edge_msg<APP, W>(o[k], w[k], overflow));
       m = wave_min(m);
-      if (lane_id() == 0) red[tid / kWave] = m;
-      __syncthreads();
-      if (tid == 0) {
-        m = min(min(red[0], red[1]), min(red[2], red[3]));
-        if (m < kInf && atomicMin(a.mail_out + r.v, m) == kInf) {
-          next_count += 1;
-          next_deg += a.outdeg[r.v];
-        }
+      if (lane == 0 && m < kInf && atomicMin(a.mail_out + it.r0, m) == kInf) {
+        next_count += 1;
+        next_deg += a.outdeg[it.r0];
       }
-      __syncthreads();
       continue;
     }
-    uint32_t r0, r1;
-    group_rows(a.t, item - a.t.nc, r0, r1);
-    if (r0 >= r1) continue;  // block-uniform
-    const uint64_t e0 = off[r0];
-    uint32_t span = static_cast<uint32_t>(off[r1] - e0);
-    if (span > 2 * kPullTile) span = 2 * kPullTile;
-    for (uint32_t base = 0; base < span; base += 4 * kBlock) {  // block-uniform
-      uint32_t ic[4];
-      int32_t u[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint32_t i = base + tid + k * kBlock;
-        ic[k] = i < span ? i : span - 1;
-        u[k] = __builtin_nontemporal_load(src + e0 + ic[k]);
-      }
-      uint32_t o[4], w[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        o[k] = a.outbox[u[k]];
-        w[k] = W ? a.w[e0 + ic[k]] : 1u;
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint32_t i = base + tid + k * kBlock;
-        if (i < span) tile[i] = edge_msg<APP, W>(o[k], w[k], overflow);
-      }
+    for (int k = 0; k < kPer; ++k) {
+      const uint32_t i = lane + k * kWave;
+      if (i < ne) tile[i] = edge_msg<APP, W>(o[k], w[k], overflow);
     }
-    __syncthreads();
-    const uint32_t nrows = r1 - r0;
+    wave_lds_sync();
     uint32_t G = kWave;
-    while (G > 1 && G * nrows > kBlock) G >>= 1;
-    const uint32_t groups = kBlock / G, gi = tid / G, li = tid % G;
+    while (G > 1 && G * nrows > kWave) G >>= 1;
+    const uint32_t groups = kWave / G, gi = lane / G, li = lane % G;
     for (uint32_t rb = 0; rb < nrows; rb += groups) {
       const uint32_t row = rb + gi;
       uint32_t m = kInf;
       if (row < nrows) {
-        const uint32_t v = r0 + row;
-        uint32_t lo = static_cast<uint32_t>(off[v] - e0), hi = static_cast<uint32_t>(off[v + 1] - e0);
-        if (hi > span) hi = span;
+        uint32_t lo = soff[row], hi = soff[row + 1];
+        if (hi > ne) hi = ne;
         for (uint32_t j = lo + li; j < hi; j += G) m = min(m, tile[j]);
       }
-      for (uint32_t o = G >> 1; o >= 1; o >>= 1) m = min(m, static_cast<uint32_t>(__shfl_xor(m, static_cast<int>(o))));
+      for (uint32_t x = G >> 1; x >= 1; x >>= 1) m = min(m, static_cast<uint32_t>(__shfl_xor(m, static_cast<int>(x))));
       if (li == 0 && row < nrows && m < kInf) {
-        a.mail_out[r0 + row] = m;
+        a.mail_out[it.r0 + row] = m;
         next_count += 1;
-        next_deg += a.outdeg[r0 + row];
+        next_deg += a.outdeg[it.r0 + row];
       }
     }
-    __syncthreads();  // the tile is reused by the next item
+    wave_lds_sync();  // the tile is rewritten by the next item
   }
   flush_counters(a.ctr, 0, 0, next_count, next_deg, overflow);
 }
@@ -349,7 +332,7 @@ static hipError_t launch_push(const MinPushArgs& a, hipStream_t s) {
 }
 template <int APP, bool W>
 static hipError_t launch_pull(const MinPullArgs& a, hipStream_t s) {
-  const uint32_t grid = std::max(1u, std::min(a.t.nc + a.t.nb, kExchangeGrid));
+  const uint32_t grid = std::max(1u, std::min(a.t.ni, kPullGrid));
   hipLaunchKernelGGL((minprop_pull_kernel<APP, W>), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }

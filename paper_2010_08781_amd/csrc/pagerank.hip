@@ -54,100 +54,105 @@ __device__ __forceinline__ double block_sum(double s, double* red) {
   return t;
 }
 
-// First launch of a pull superstep: the partial sum of every chunk of
-// kPullTile in-edges of a long row (grid-stride over chunks).  Loads are
-// unconditional (index clamped into the chunk) so that all of a thread's
-// gathers are in flight together; out-of-range lanes are masked.
-__global__ __launch_bounds__(kBlock) void pr_chunk_kernel(PrPullArgs a) {
-  __shared__ double red[kWavesPerBlock];
-  const uint32_t tid = threadIdx.x;
+// Pull superstep, first launch.  Every wavefront works through its own pull
+// items (grid-stride over wavefronts), with its own LDS tile and no
+// workgroup barrier, so 32 items per CU are in flight.  An item needs one
+// metadata load; then all of its independent loads are issued together --
+// the CSC sources (non-temporal; indices clamped into the item so no lane
+// branches), the row offsets and out-degrees -- and the outbox gathers
+// follow in one more round trip.
+//  * row item: the gathered outboxes are staged in LDS and each row is
+//    summed by G lanes (G from the item's row count), then finished here;
+//  * long-row chunk: a fixed-order wavefront sum stored as the chunk's
+//    partial (added up by the second launch).
+__global__ __launch_bounds__(kBlock) void pr_items_kernel(PrPullArgs a) {
+  constexpr int kPer = kWaveTile / kWave;
+  constexpr int kRowPer = (kItemRows + kWave) / kWave;
+  __shared__ double s_tile[kWavesPerBlock][kWaveTile];
+  __shared__ uint32_t s_off[kWavesPerBlock][kItemRows + 1];
+  __shared__ uint32_t s_deg[kWavesPerBlock][kItemRows];
+  const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
+  double* tile = s_tile[wv];
+  uint32_t* soff = s_off[wv];
+  uint32_t* sdeg = s_deg[wv];
   const int32_t* src = a.t.src;
-  for (uint32_t c = blockIdx.x; c < a.t.nc; c += gridDim.x) {
-    const ChunkRef r = chunk_ref(a.t, c);
-    constexpr int kPer = kPullTile / kBlock;
+  const uint64_t* off = a.t.off;
+  const uint32_t nw = gridDim.x * kWavesPerBlock;
+  for (uint32_t item = blockIdx.x * kWavesPerBlock + wv; item < a.t.ni; item += nw) {
+    const PullItem it = a.t.items[item];
+    const bool chunk = it.slot != kNoSlot;
+    const uint32_t ne = it.ne < kWaveTile ? it.ne : kWaveTile;  // ne > kWaveTile only with bad offsets
+    const uint32_t nrows = chunk ? 0 : it.r1 - it.r0;
     int32_t u[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      uint64_t e = r.beg + tid + k * kBlock;
-      e = e < r.end ? e : r.end - 1;
-      u[k] = __builtin_nontemporal_load(src + e);
+      const uint32_t i = lane + k * kWave;
+      u[k] = ne ? __builtin_nontemporal_load(src + it.e0 + (i < ne ? i : ne - 1)) : 0;
+    }
+    if (!chunk) {
+#pragma unroll
+      for (int k = 0; k < kRowPer; ++k) {
+        const uint32_t r = lane + k * kWave;
+        if (r <= nrows) soff[r] = static_cast<uint32_t>(off[it.r0 + r] - it.e0);
+        if (r < nrows) sdeg[r] = a.outdeg[it.r0 + r];
+      }
     }
     double x[kPer];
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) x[k] = a.contrib_in[u[k]];
-    double s = 0.0;
+    for (int k = 0; k < kPer; ++k) x[k] = ne ? a.contrib_in[u[k]] : 0.0;
+    if (chunk) {
+      double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < kPer; ++k)
-      if (r.beg + tid + k * kBlock < r.end) s += x[k];
-    s = block_sum(s, red);
-    if (tid == 0) a.partial[c] = s;
-  }
-}
-
-// Second launch of a pull superstep (grid-stride over nl + nb work items):
-//  * item l < nl: finish long row l -- add its chunk partials in chunk order
-//    (a fixed order, so results are bitwise reproducible);
-//  * item nl + k: row-group k.  Its in-edges (fewer than 2*kPullTile) are
-//    streamed from the CSC with coalesced loads, their sources' outboxes
-//    gathered into LDS, then each row is reduced from LDS by G lanes (G from
-//    the group's row count so that the 256 lanes stay busy).
-__global__ __launch_bounds__(kBlock) void pr_pull_kernel(PrPullArgs a) {
-  __shared__ double tile[2 * kPullTile];
-  __shared__ double red[kWavesPerBlock];
-  const uint32_t tid = threadIdx.x;
-  const int32_t* src = a.t.src;
-  const uint64_t* off = a.t.off;
-  const uint32_t items = a.t.nl + a.t.nb;
-  for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
-    if (item < a.t.nl) {
-      const uint32_t f = a.t.lr_first[item], nch = a.t.lr_first[item + 1] - f;
-      double x = 0.0;
-      for (uint32_t i = tid; i < nch; i += kBlock) x += a.partial[f + i];
-      x = block_sum(x, red);
-      if (tid == 0) pr_finish(a, a.t.long_rows[item], x);
+      for (int k = 0; k < kPer; ++k)
+        if (lane + k * kWave < ne) s += x[k];
+      s = wave_sum(s);
+      if (lane == 0) a.partial[it.slot] = s;
       continue;
     }
-    uint32_t r0, r1;
-    group_rows(a.t, item - a.t.nl, r0, r1);
-    if (r0 >= r1) continue;  // block-uniform
-    const uint64_t e0 = off[r0];
-    uint32_t span = static_cast<uint32_t>(off[r1] - e0);
-    if (span > 2 * kPullTile) span = 2 * kPullTile;  // only reachable with inconsistent offsets
-    for (uint32_t base = 0; base < span; base += 4 * kBlock) {  // block-uniform, at most 2 passes
-      int32_t u[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint32_t i = base + tid + k * kBlock;
-        u[k] = __builtin_nontemporal_load(src + e0 + (i < span ? i : span - 1));
-      }
-      double x[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) x[k] = a.contrib_in[u[k]];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint32_t i = base + tid + k * kBlock;
-        if (i < span) tile[i] = x[k];
-      }
+    for (int k = 0; k < kPer; ++k) {
+      const uint32_t i = lane + k * kWave;
+      if (i < ne) tile[i] = x[k];
     }
-    __syncthreads();
-    const uint32_t nrows = r1 - r0;
+    wave_lds_sync();
     uint32_t G = kWave;
-    while (G > 1 && G * nrows > kBlock) G >>= 1;
-    const uint32_t groups = kBlock / G, gi = tid / G, li = tid % G;
+    while (G > 1 && G * nrows > kWave) G >>= 1;
+    const uint32_t groups = kWave / G, gi = lane / G, li = lane % G;
     for (uint32_t rb = 0; rb < nrows; rb += groups) {
       const uint32_t row = rb + gi;
       double s = 0.0;
       if (row < nrows) {
-        const uint32_t v = r0 + row;
-        uint32_t lo = static_cast<uint32_t>(off[v] - e0), hi = static_cast<uint32_t>(off[v + 1] - e0);
-        if (hi > span) hi = span;
+        uint32_t lo = soff[row], hi = soff[row + 1];
+        if (hi > ne) hi = ne;
         for (uint32_t j = lo + li; j < hi; j += G) s += tile[j];
       }
       for (uint32_t o = G >> 1; o >= 1; o >>= 1) s += __shfl_xor(s, static_cast<int>(o));
-      if (li == 0 && row < nrows) pr_finish(a, r0 + row, s);
+      if (li == 0 && row < nrows) {
+        const double rank = a.ratio + 0.85 * s;
+        const uint32_t v = it.r0 + row;
+        if (a.last) {
+          a.value[v] = rank;
+        } else {
+          const uint32_t d = sdeg[row];
+          a.contrib_out[v] = d ? rank / static_cast<double>(d) : 0.0;
+        }
+      }
     }
-    __syncthreads();  // the tile is reused by the next item
+    wave_lds_sync();  // the tile is rewritten by the next item
   }
+}
+
+// Pull superstep, second launch: each long row adds its chunk partials in
+// chunk order (one wavefront per row; a fixed order, so results are
+// bitwise reproducible).
+__global__ __launch_bounds__(kBlock) void pr_longrow_kernel(PrPullArgs a) {
+  const uint32_t l = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (l >= a.t.nl) return;  // wave-uniform
+  const uint32_t f = a.t.lr_first[l], nch = a.t.lr_first[l + 1] - f;
+  double s = 0.0;
+  for (uint32_t i = lane_id(); i < nch; i += kWave) s += a.partial[f + i];
+  s = wave_sum(s);
+  if (lane_id() == 0) pr_finish(a, a.t.long_rows[l], s);
 }
 
 // Superstep 0 of the pull form: rank 1/N, outbox 1/N/outdeg.
@@ -231,12 +236,15 @@ ipg_status run_pagerank(ipg_graph* g, uint32_t T, ipg_mode mode, const RunWs& w,
       a.contrib_in = (step & 1) ? w.f64_a : w.f64_b;
       a.contrib_out = (step & 1) ? w.f64_b : w.f64_a;
       a.last = step == T;
-      if (g->nc) {
-        hipLaunchKernelGGL(pr_chunk_kernel, dim3(std::min(g->nc, kExchangeGrid)), dim3(kBlock), 0, s, a);
+      if (g->ni) {
+        hipLaunchKernelGGL(pr_items_kernel, dim3(std::min(g->ni, kPullGrid)), dim3(kBlock), 0, s, a);
         IPG_HIP(hipGetLastError());
       }
-      hipLaunchKernelGGL(pr_pull_kernel, dim3(std::min(g->nl + g->nb, kExchangeGrid)), dim3(kBlock), 0, s, a);
-      IPG_HIP(hipGetLastError());
+      if (g->nl) {
+        hipLaunchKernelGGL(pr_longrow_kernel, dim3((g->nl + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0, s,
+                           a);
+        IPG_HIP(hipGetLastError());
+      }
       IPG_HIP(tm.step(s, step));
     }
   } else {

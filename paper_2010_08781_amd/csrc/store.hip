@@ -100,6 +100,23 @@ __global__ void long_rows_kernel(const uint64_t* off, uint32_t n, uint32_t* list
   }
 }
 
+// Edge ranges of the pull items (row pieces: [off[r0], off[r1]); chunks:
+// kWaveTile in-edges of row r0 starting at chunk index e0 * kWaveTile).
+__global__ void item_edges_kernel(const uint64_t* off, PullItem* items, uint32_t ni) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < ni; i += (uint64_t)gridDim.x * blockDim.x) {
+    PullItem it = items[i];
+    if (it.slot == kNoSlot) {
+      it.e0 = off[it.r0];
+      it.ne = static_cast<uint32_t>(off[it.r1] - it.e0);
+    } else {
+      const uint64_t beg = off[it.r0] + it.e0 * kWaveTile, end = off[it.r0 + 1];
+      it.e0 = beg;
+      it.ne = static_cast<uint32_t>(end - beg < kWaveTile ? end - beg : kWaveTile);
+    }
+    items[i] = it;
+  }
+}
+
 __global__ void row_degrees_kernel(const uint64_t* off, const uint32_t* rows, uint32_t nr, uint64_t* deg) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nr; i += (uint64_t)gridDim.x * blockDim.x)
     deg[i] = off[rows[i] + 1] - off[rows[i]];
@@ -113,6 +130,7 @@ static size_t carve_graph(Carver& c, uint32_t n, uint64_t e, GraphTables* t) {
   tt.long_rows = c.take<uint32_t>(long_rows_cap(e));
   tt.lr_first = c.take<uint32_t>(long_rows_cap(e) + 1);
   tt.ch_row = c.take<uint32_t>(chunks_cap(e));
+  tt.items = c.take<PullItem>(items_cap(n, e));
   tt.flags = c.take<uint32_t>(kNumFlags + 1);  // + long-row counter
   if (t) *t = tt;
   return align_up(c.used, 256);
@@ -195,14 +213,14 @@ extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t
   uint32_t nc = 0;
   if (nl > 0) {
     // Long rows in ascending order (a deterministic assignment to
-    // workgroups), cut into chunks of kPullTile in-edges.
+    // workgroups), cut into chunks of kWaveTile in-edges.
     std::vector<uint32_t> rows(nl);
     IPG_HIP(hipMemcpyAsync(rows.data(), t.long_rows, nl * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     IPG_HIP(hipStreamSynchronize(s));
     std::sort(rows.begin(), rows.end());
     IPG_HIP(hipMemcpyAsync(t.long_rows, rows.data(), nl * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    // degrees via the chunk table's space (large enough: nl <= chunks_cap / 2)
-    uint64_t* degs = reinterpret_cast<uint64_t*>(t.ch_row);
+    // degrees via the item table's space (24 bytes per item, more items than long rows)
+    uint64_t* degs = reinterpret_cast<uint64_t*>(t.items);
     hipLaunchKernelGGL(row_degrees_kernel, dim3(grid_for(nl, kBlock, 1024)), dim3(kBlock), 0, s, csc_off, t.long_rows, nl,
                        degs);
     IPG_HIP(hipGetLastError());
@@ -213,7 +231,7 @@ extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t
     uint64_t acc = 0;
     for (uint32_t l = 0; l < nl; ++l) {
       first[l] = static_cast<uint32_t>(acc);
-      const uint64_t k = (deg[l] + kPullTile - 1) / kPullTile;
+      const uint64_t k = (deg[l] + kWaveTile - 1) / kWaveTile;
       acc += k;
       if (acc > chunks_cap(e)) return fail(IPG_EBADGRAPH, "long-row chunk table overflow (offsets inconsistent with E)");
       for (uint64_t j = 0; j < k; ++j) chrow.push_back(l);
@@ -223,6 +241,39 @@ extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t
     IPG_HIP(hipMemcpyAsync(t.lr_first, first.data(), (nl + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     IPG_HIP(hipMemcpyAsync(t.ch_row, chrow.data(), nc * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     IPG_HIP(hipStreamSynchronize(s));
+  }
+
+  // Pull work items: the long-row chunks, then each row-group cut into
+  // pieces of at most kItemRows rows (a group's long last row is chunked).
+  uint32_t ni = 0;
+  {
+    std::vector<uint32_t> rb(nb + 1), lrows(nl), lfirst(nl + 1);
+    IPG_HIP(hipMemcpyAsync(rb.data(), t.pull_rb, (nb + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    if (nl) {
+      IPG_HIP(hipMemcpyAsync(lrows.data(), t.long_rows, nl * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      IPG_HIP(hipMemcpyAsync(lfirst.data(), t.lr_first, (nl + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    }
+    IPG_HIP(hipStreamSynchronize(s));
+    std::vector<PullItem> items;
+    items.reserve(static_cast<size_t>(nb) + nc + n / kItemRows + 1);
+    for (uint32_t l = 0; l < nl; ++l)
+      for (uint32_t j = lfirst[l]; j < lfirst[l + 1]; ++j)
+        items.push_back(PullItem{j - lfirst[l], 0, lrows[l], lrows[l] + 1, j});
+    for (uint32_t k = 0; k < nb; ++k) {
+      const uint32_t r0 = rb[k];
+      uint32_t r1 = rb[k + 1];
+      if (r1 > r0 && std::binary_search(lrows.begin(), lrows.end(), r1 - 1)) --r1;
+      for (uint32_t a = r0; a < r1; a += kItemRows)
+        items.push_back(PullItem{0, 0, a, std::min(r1, a + kItemRows), kNoSlot});
+    }
+    if (items.size() > items_cap(n, e)) return fail(IPG_EBADGRAPH, "pull item table overflow");
+    ni = static_cast<uint32_t>(items.size());
+    if (ni) {
+      IPG_HIP(hipMemcpyAsync(t.items, items.data(), ni * sizeof(PullItem), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(item_edges_kernel, dim3(grid_for(ni, kBlock, 4096)), dim3(kBlock), 0, s, csc_off, t.items, ni);
+      IPG_HIP(hipGetLastError());
+      IPG_HIP(hipStreamSynchronize(s));
+    }
   }
 
   ipg_graph* g = new (std::nothrow) ipg_graph();
@@ -240,6 +291,7 @@ extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t
   g->nb = nb;
   g->nl = nl;
   g->nc = nc;
+  g->ni = ni;
   IPG_HIP(hipGetDevice(&g->device));
   g->has_values = 0;
   g->last_app = -1;
