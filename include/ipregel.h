@@ -108,7 +108,9 @@ typedef struct {
  *   examined[s] edges read by the exchange (push: = messages; pull: in-edges
  *               scanned),
  *   mode[s]     1 push, 2 pull,
- *   usec[s]     device time of superstep s (HIP events), when timing is on.
+ *   usec[s]     device time of superstep s (HIP events), when timing is on,
+ *   frontier_deg[s]  sum of the out-degrees of the vertices active in s
+ *               (the selector's second input).
  */
 typedef struct {
   uint32_t supersteps;      /* supersteps executed */
@@ -123,6 +125,7 @@ typedef struct {
   uint64_t* examined;
   uint8_t* mode;
   float* usec;
+  uint64_t* frontier_deg;
 } ipg_run_stats;
 
 /* Bytes of graph workspace ipg_graph_create needs for this graph size.  The

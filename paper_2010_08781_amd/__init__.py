@@ -63,7 +63,8 @@ class _Stats(ctypes.Structure):
                 ("edges_traversed", ctypes.c_uint64), ("edges_examined", ctypes.c_uint64),
                 ("seconds", ctypes.c_double), ("trace_cap", ctypes.c_uint32),
                 ("active", ctypes.c_void_p), ("senders", ctypes.c_void_p), ("messages", ctypes.c_void_p),
-                ("examined", ctypes.c_void_p), ("mode", ctypes.c_void_p), ("usec", ctypes.c_void_p)]
+                ("examined", ctypes.c_void_p), ("mode", ctypes.c_void_p), ("usec", ctypes.c_void_p),
+                ("frontier_deg", ctypes.c_void_p)]
 
 
 _lib = None
@@ -135,6 +136,7 @@ class RunStats:
     examined: np.ndarray = field(repr=False)
     mode: np.ndarray = field(repr=False)
     usec: Optional[np.ndarray] = field(repr=False, default=None)
+    frontier_deg: Optional[np.ndarray] = field(repr=False, default=None)
 
     @property
     def trace(self) -> np.ndarray:
@@ -240,12 +242,13 @@ class Graph:
             _check_selector(selector)
         opts = _Opts(int(source), MODES[mode], RUN_PERSISTENT if persistent else 0,
                      selector.data_ptr() if selector is not None else None)
-        arrs = {k: np.zeros(trace_cap, dtype=np.uint64) for k in ("active", "senders", "messages", "examined")}
+        arrs = {k: np.zeros(trace_cap, dtype=np.uint64)
+                for k in ("active", "senders", "messages", "examined", "frontier_deg")}
         arrs["mode"] = np.zeros(trace_cap, dtype=np.uint8)
         usec = np.zeros(trace_cap, dtype=np.float32) if timing else None
         st = _Stats(0, 0, 0, 0, 0.0, trace_cap, arrs["active"].ctypes.data, arrs["senders"].ctypes.data,
                     arrs["messages"].ctypes.data, arrs["examined"].ctypes.data, arrs["mode"].ctypes.data,
-                    usec.ctypes.data if usec is not None else None)
+                    usec.ctypes.data if usec is not None else None, arrs["frontier_deg"].ctypes.data)
         rc = lib().ipg_run(self._h, a, comb, int(max_supersteps), ctypes.byref(opts),
                            ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(stream), ctypes.byref(st))
         if check:
@@ -255,7 +258,8 @@ class Graph:
         k = min(int(st.supersteps), trace_cap)
         stats = RunStats(rc, int(st.supersteps), bool(st.halted), int(st.edges_traversed), int(st.edges_examined),
                          float(st.seconds), arrs["active"][:k], arrs["senders"][:k], arrs["messages"][:k],
-                         arrs["examined"][:k], arrs["mode"][:k], usec[:k] if usec is not None else None)
+                         arrs["examined"][:k], arrs["mode"][:k], usec[:k] if usec is not None else None,
+                         arrs["frontier_deg"][:k])
         vals = self.read_values(a, stream=stream)
         return vals, stats
 

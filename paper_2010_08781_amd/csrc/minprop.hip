@@ -469,6 +469,7 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
       if (st->messages) st->messages[step] = h.messages;
       if (st->examined) st->examined[step] = examined;
       if (st->mode) st->mode[step] = static_cast<uint8_t>(mode);
+      if (st->frontier_deg) st->frontier_deg[step] = degsum;
     }
     tot_msgs += h.messages;
     tot_exam += examined;

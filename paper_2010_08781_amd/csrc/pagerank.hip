@@ -284,6 +284,7 @@ ipg_status run_pagerank(ipg_graph* g, uint32_t T, ipg_mode mode, const RunWs& w,
       if (st->messages) st->messages[k] = k < T ? g->e : 0;
       if (st->examined) st->examined[k] = k < T ? g->e : 0;
       if (st->mode) st->mode[k] = push ? IPG_MODE_PUSH : IPG_MODE_PULL;
+      if (st->frontier_deg) st->frontier_deg[k] = g->e;
     }
   }
   return IPG_OK;

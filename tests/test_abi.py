@@ -50,9 +50,10 @@ def test_workspace_sizes_scale(lib):
     assert pr >= 3 * 8 * n and cc >= 5 * 4 * n
     assert pr % 256 == 0 and cc % 256 == 0
     g = lib.ipg_graph_workspace_bytes(n, e, 0)
-    # out-degrees plus the pull tiling tables and work items (tens of bytes per
-    # 1024 in-edges and per 448 vertices)
-    assert 4 * n <= g < 4 * n + e // 16 + n // 8 + 4096
+    # out-degrees plus the pull tiling tables and work items: a 24-byte item
+    # per 256-edge row group, per 64 rows and per long-row chunk, so well
+    # under half a byte per edge
+    assert 4 * n <= g < 4 * n + (3 * e) // 8 + n // 2 + 4096
 
 
 def test_null_arguments_rejected_before_any_device_call(lib):
