@@ -39,6 +39,8 @@ def main():
     ap.add_argument("--workload", default="rmat-s20-sym")
     ap.add_argument("--pr-updates", type=int, default=10)
     ap.add_argument("--mode", default="auto", help="exchange for CC/SSSP: auto, push or pull")
+    ap.add_argument("--selector", default="learned", choices=["learned", "heuristic"],
+                    help="what AUTO uses to pick the exchange: the trained network or the fixed rule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apps", default="pagerank,cc,sssp")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -75,14 +77,21 @@ def main():
     g = ipg.Graph.from_host(hg)
     apps = [a.strip() for a in args.apps.split(",") if a.strip()]
     T = args.pr_updates
+    sel = None
+    if args.selector == "learned" and args.mode == "auto":
+        from paper_2010_08781_amd import selector_fit
 
-    def one_step():
+        sel = selector_fit.load()
+        if sel is None:
+            sys.exit("bench.py: --selector learned but no trained selector parameters are installed")
+
+    def one_step(selector=sel):
         out = {}
         for app in apps:
             if app == "pagerank":
                 _, st = g.run("pagerank", T, mode="pull", timing=True)
             else:
-                _, st = g.run(app, source=0, mode=args.mode, timing=True)
+                _, st = g.run(app, source=0, mode=args.mode, timing=True, selector=selector)
             out[app] = st
         return out
 
@@ -114,6 +123,20 @@ def main():
             "us_per_superstep": float(np.median(secs) * 1e6 / st.supersteps),
             "modes": "".join("?PL"[int(x)] for x in st.mode),
         }
+
+    # The same CC/SSSP runs with the fixed heuristic picking the exchange (the
+    # plain method), outside the timed region, for the learned-vs-plain ratio.
+    learned_vs_plain = None
+    if sel is not None:
+        learned_vs_plain = {}
+        for app in apps:
+            if app == "pagerank":
+                continue
+            plain = np.median([g.run(app, source=0, mode="auto", timing=True)[1].seconds
+                               for _ in range(max(3, args.steps))])
+            mine = apps_out[app]["time_to_converge_ms_median"] / 1e3
+            learned_vs_plain[app] = {"learned_ms": round(mine * 1e3, 4), "plain_ms": round(float(plain) * 1e3, 4),
+                                     "speedup": round(float(plain) / mine, 4)}
 
     roofline = None
     if "pagerank" in apps and T >= 1:
@@ -158,9 +181,11 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload} (n={hg.n}, m={hg.m}): PageRank T={T} pull FP64 + hash-min CC + "
-                        f"SSSP from 0, exchange={args.mode}",
+                        f"SSSP from 0, exchange={args.mode}"
+                        f"{' (trained selector)' if sel is not None else ''}",
             "n": hg.n, "m": hg.m, "apps": apps_out,
         },
+        "learned_vs_plain": learned_vs_plain,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -174,6 +174,32 @@ ipg_status ipg_read_values(const ipg_graph* graph, void* dst, size_t dst_bytes, 
                            void* hip_stream);
 
 /*
+ * Batched SSSP with unit weights: up to IPG_BATCH_MAX_SOURCES single-source
+ * runs of Fig. 10 on one graph, executed as one superstep loop.  With unit
+ * weights all messages of a superstep carry the same value, so the min
+ * mailbox of each (source, vertex) pair is one bit and the queries advance
+ * together with bit-parallel masks.  Results equal the separate runs:
+ *   dist: DEVICE memory, [num_sources][N] uint32 (query-major: row i holds
+ *         the values of the run from sources[i]); INF = unreached.
+ *   sources: DEVICE pointer to num_sources vertex ids (repeats allowed),
+ *         copied to the host and checked (< N) before any kernel runs.
+ *   stats (optional): supersteps = the largest superstep count of the
+ *         queries; active/senders/messages[s] = the sums over queries of the
+ *         single-source traces (a finished query adds 0); examined[s] = edges
+ *         read by the shared exchange; mode[s] its direction.
+ *   max_supersteps: cap on supersteps, 0 = none (IPG_NOT_CONVERGED when
+ *         reached with messages pending).  opts->mode forces push or pull;
+ *         opts->source and opts->selector are ignored.
+ * A graph with weights is IPG_EUNSUPPORTED.  Synchronises the stream once
+ * per superstep.
+ */
+#define IPG_BATCH_MAX_SOURCES 256
+size_t ipg_multi_sssp_workspace_bytes(uint32_t num_vertices, uint64_t num_edges);
+ipg_status ipg_run_multi_sssp(ipg_graph* graph, const uint32_t* sources, uint32_t num_sources,
+                              uint32_t max_supersteps, const ipg_run_opts* opts, uint32_t* dist, size_t dist_bytes,
+                              void* workspace, size_t workspace_bytes, void* hip_stream, ipg_run_stats* stats);
+
+/*
  * Learned exchange selector (an extension of Section 4.3.2, where the push /
  * pull choice is a compile-time flag set by the user's experiments).
  * A 4-16-16-2 tanh MLP in FP64 predicts log2 of the time of a push and of a

@@ -38,6 +38,7 @@ MODES = {"auto": 0, "push": 1, "pull": 2}
 GRAPH_SYMMETRIC, GRAPH_VALIDATE = 1, 2
 RUN_PERSISTENT = 1
 INF = 0xFFFFFFFF
+BATCH_MAX_SOURCES = 256
 
 
 class IpgError(RuntimeError):
@@ -93,6 +94,10 @@ def lib():
         L.ipg_graph_destroy.restype = None
         L.ipg_last_error.argtypes = []
         L.ipg_last_error.restype = ctypes.c_char_p
+        L.ipg_multi_sssp_workspace_bytes.argtypes = [u32, u64]
+        L.ipg_multi_sssp_workspace_bytes.restype = sz
+        L.ipg_run_multi_sssp.argtypes = [P, P, u32, u32, ctypes.POINTER(_Opts), P, sz, P, sz, P, ctypes.POINTER(_Stats)]
+        L.ipg_run_multi_sssp.restype = i32
         L.ipg_selector_workspace_bytes.argtypes = [u32]
         L.ipg_selector_workspace_bytes.restype = sz
         L.ipg_selector_forward.argtypes = [P, P, u32, P, P]
@@ -146,6 +151,29 @@ class RunStats:
     @property
     def gteps(self) -> float:
         return self.edges_traversed / self.seconds / 1e9 if self.seconds > 0 else float("nan")
+
+
+class _Trace:
+    """Host arrays for ipg_run_stats and their conversion to RunStats."""
+
+    def __init__(self, cap: int, timing: bool):
+        self.cap = cap
+        self.a = {k: np.zeros(cap, dtype=np.uint64) for k in ("active", "senders", "messages", "examined", "frontier_deg")}
+        self.a["mode"] = np.zeros(cap, dtype=np.uint8)
+        self.usec = np.zeros(cap, dtype=np.float32) if timing else None
+        a = self.a
+        self.st = _Stats(0, 0, 0, 0, 0.0, cap, a["active"].ctypes.data, a["senders"].ctypes.data,
+                         a["messages"].ctypes.data, a["examined"].ctypes.data, a["mode"].ctypes.data,
+                         self.usec.ctypes.data if self.usec is not None else None, a["frontier_deg"].ctypes.data)
+
+    def stats(self, rc: int) -> "RunStats":
+        st, a = self.st, self.a
+        if rc not in (OK, NOT_CONVERGED):
+            return RunStats(rc, 0, False, 0, 0, 0.0, *(np.zeros(0),) * 5)
+        k = min(int(st.supersteps), self.cap)
+        return RunStats(rc, int(st.supersteps), bool(st.halted), int(st.edges_traversed), int(st.edges_examined),
+                        float(st.seconds), a["active"][:k], a["senders"][:k], a["messages"][:k], a["examined"][:k],
+                        a["mode"][:k], self.usec[:k] if self.usec is not None else None, a["frontier_deg"][:k])
 
 
 class Graph:
@@ -242,26 +270,43 @@ class Graph:
             _check_selector(selector)
         opts = _Opts(int(source), MODES[mode], RUN_PERSISTENT if persistent else 0,
                      selector.data_ptr() if selector is not None else None)
-        arrs = {k: np.zeros(trace_cap, dtype=np.uint64)
-                for k in ("active", "senders", "messages", "examined", "frontier_deg")}
-        arrs["mode"] = np.zeros(trace_cap, dtype=np.uint8)
-        usec = np.zeros(trace_cap, dtype=np.float32) if timing else None
-        st = _Stats(0, 0, 0, 0, 0.0, trace_cap, arrs["active"].ctypes.data, arrs["senders"].ctypes.data,
-                    arrs["messages"].ctypes.data, arrs["examined"].ctypes.data, arrs["mode"].ctypes.data,
-                    usec.ctypes.data if usec is not None else None, arrs["frontier_deg"].ctypes.data)
+        tr = _Trace(trace_cap, timing)
         rc = lib().ipg_run(self._h, a, comb, int(max_supersteps), ctypes.byref(opts),
-                           ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(stream), ctypes.byref(st))
+                           ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(stream),
+                           ctypes.byref(tr.st))
         if check:
             _check(rc, "ipg_run", allow_not_converged=True)
         elif rc not in (OK, NOT_CONVERGED):
-            return None, RunStats(rc, 0, False, 0, 0, 0.0, *(np.zeros(0),) * 5)
-        k = min(int(st.supersteps), trace_cap)
-        stats = RunStats(rc, int(st.supersteps), bool(st.halted), int(st.edges_traversed), int(st.edges_examined),
-                         float(st.seconds), arrs["active"][:k], arrs["senders"][:k], arrs["messages"][:k],
-                         arrs["examined"][:k], arrs["mode"][:k], usec[:k] if usec is not None else None,
-                         arrs["frontier_deg"][:k])
+            return None, tr.stats(rc)
         vals = self.read_values(a, stream=stream)
-        return vals, stats
+        return vals, tr.stats(rc)
+
+    def run_multi_sssp(self, sources, max_supersteps: int = 0, mode: str = "auto", timing: bool = True,
+                       trace_cap: int = 1 << 16, stream=None, out=None, check: bool = True):
+        """Batched unit-weight SSSP from up to 256 sources in one superstep loop.
+
+        Returns (dist [Q, N] int32 tensor holding uint32 distances, RunStats whose
+        trace is the sum of the single-source traces)."""
+        import torch
+
+        src = torch.as_tensor(np.asarray(sources, dtype=np.int64).astype(np.int32), device=self.device) \
+            if not torch.is_tensor(sources) else sources.to(device=self.device, dtype=torch.int32).contiguous()
+        q = int(src.numel())
+        if out is None:
+            out = torch.empty((q, self.n), dtype=torch.int32, device=self.device)
+        key = "multi_sssp"
+        if key not in self._run_ws:
+            nb = lib().ipg_multi_sssp_workspace_bytes(self.n, self.m)
+            self._run_ws[key] = (torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device), nb)
+        ws, nbytes = self._run_ws[key]
+        opts = _Opts(0, MODES[mode], 0, None)
+        tr = _Trace(trace_cap, timing)
+        rc = lib().ipg_run_multi_sssp(self._h, src.data_ptr(), q, int(max_supersteps), ctypes.byref(opts),
+                                      out.data_ptr(), out.numel() * 4, ws.data_ptr(), nbytes, _stream_handle(stream),
+                                      ctypes.byref(tr.st))
+        if check:
+            _check(rc, "ipg_run_multi_sssp", allow_not_converged=True)
+        return out, tr.stats(rc)
 
     def read_values(self, app: int, stream=None):
         import torch

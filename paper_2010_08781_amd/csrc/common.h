@@ -176,7 +176,8 @@ struct alignas(128) CtrSlot {
   unsigned long long senders;   // vertices that broadcast
   unsigned long long messages;  // sum of the senders' out-degrees
   unsigned long long next_deg;  // sum of out-degrees of the next frontier
-  unsigned long long pad[12];
+  unsigned long long active;    // (batched SSSP) query-vertex pairs that received a message
+  unsigned long long pad[11];
 };
 static_assert(sizeof(CtrSlot) == 128, "one slot per 128-byte line");
 
@@ -199,14 +200,15 @@ __device__ __forceinline__ void clear_slots(CtrSlot* c) {
 // Workgroup-wide sum of per-thread counters, then at most one atomic per
 // non-zero field into the workgroup's slot.  Every thread must call it.
 __device__ __forceinline__ void flush_counters(CtrSlot* base, uint64_t senders, uint64_t messages, uint64_t next_count,
-                                               uint64_t next_deg, uint32_t overflow) {
-  __shared__ unsigned long long part[4][kWavesPerBlock];
+                                               uint64_t next_deg, uint32_t overflow, uint64_t active = 0) {
+  __shared__ unsigned long long part[5][kWavesPerBlock];
   __shared__ uint32_t ovf;
   if (threadIdx.x == 0) ovf = 0;
   senders = wave_sum_u64(senders);
   messages = wave_sum_u64(messages);
   next_count = wave_sum_u64(next_count);
   next_deg = wave_sum_u64(next_deg);
+  active = wave_sum_u64(active);
   const bool any_ovf = __ballot(overflow != 0) != 0;
   __syncthreads();
   const int w = threadIdx.x / kWave;
@@ -215,10 +217,11 @@ __device__ __forceinline__ void flush_counters(CtrSlot* base, uint64_t senders, 
     part[1][w] = messages;
     part[2][w] = next_count;
     part[3][w] = next_deg;
+    part[4][w] = active;
     if (any_ovf) ovf = 1;
   }
   __syncthreads();
-  if (threadIdx.x < 4) {
+  if (threadIdx.x < 5) {
     unsigned long long t = 0;
     for (int i = 0; i < kWavesPerBlock; ++i) t += part[threadIdx.x][i];
     CtrSlot* c = my_slot(base);
@@ -227,6 +230,7 @@ __device__ __forceinline__ void flush_counters(CtrSlot* base, uint64_t senders, 
       if (threadIdx.x == 1) atomicAdd(&c->messages, t);
       if (threadIdx.x == 2) atomicAdd(&c->next_count, static_cast<uint32_t>(t));
       if (threadIdx.x == 3) atomicAdd(&c->next_deg, t);
+      if (threadIdx.x == 4) atomicAdd(&c->active, t);
     }
     if (threadIdx.x == 0 && ovf) atomicOr(&c->overflow, 1u);
   }

@@ -30,9 +30,15 @@ struct Decision {
   uint32_t overflow;
   int32_t mode;   // IPG_MODE_PUSH / IPG_MODE_PULL from the selector, 0 if none ran
   double margin;  // predicted log2 time of push minus pull
-  unsigned long long pad[2];
+  unsigned long long active;  // summed `active` counters (batched SSSP)
+  unsigned long long pad;
 };
 static_assert(sizeof(Decision) == 64, "one 64-byte record");
+
+// Sum the counter slots `c` of a superstep into *out (one wavefront) and,
+// with a selector, choose the exchange of the next superstep.
+hipError_t launch_decide(const CtrSlot* c, uint32_t next_superstep, uint64_t e, const double* sel, Decision* out,
+                         hipStream_t s);
 
 // Run workspace, carved from the caller's device buffer.
 struct RunWs {

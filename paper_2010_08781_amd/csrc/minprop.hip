@@ -302,6 +302,7 @@ __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_
   const uint64_t se = wave_sum_u64(x.senders);
   const uint64_t me = wave_sum_u64(x.messages);
   const uint64_t nd = wave_sum_u64(x.next_deg);
+  const uint64_t ac = wave_sum_u64(x.active);
   const bool ovf = __ballot(x.overflow != 0) != 0;
   if (threadIdx.x == 0) {
     Decision d;
@@ -312,7 +313,8 @@ __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_
     d.overflow = ovf ? 1u : 0u;
     d.mode = 0;
     d.margin = 0.0;
-    d.pad[0] = d.pad[1] = 0;
+    d.active = ac;
+    d.pad = 0;
     if (sel && nc) {
       int m = 0;
       d.margin = sel_predict_mode(sel, nc, nd, next_superstep, e, &m);
@@ -323,6 +325,12 @@ __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_
 }
 
 // ------------------------------------------------------------------ host --
+
+hipError_t launch_decide(const CtrSlot* c, uint32_t next_superstep, uint64_t e, const double* sel, Decision* out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kWave), 0, s, c, next_superstep, e, sel, out);
+  return hipGetLastError();
+}
 
 template <int APP, bool W>
 static hipError_t launch_push(const MinPushArgs& a, hipStream_t s) {
@@ -454,8 +462,7 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
     }
     IPG_HIP(tm.step(s, step));
     const double* sel = o.mode == IPG_MODE_AUTO ? o.selector : nullptr;
-    hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kWave), 0, s, c, step + 1, e, sel, w.decision);
-    IPG_HIP(hipGetLastError());
+    IPG_HIP(launch_decide(c, step + 1, e, sel, w.decision, s));
     uint32_t lcount = 0;
     Decision h;
     IPG_HIP(hipMemcpyAsync(&h, w.decision, sizeof(h), hipMemcpyDeviceToHost, s));

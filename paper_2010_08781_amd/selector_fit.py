@@ -12,7 +12,7 @@ backward and SGD kernels (ipg_selector_train), and compared with the fixed
 heuristic on held-out graphs by its regret: the time lost against choosing
 the faster exchange in every superstep.
 
-    python -m paper_2010_08781_amd.selector_train --out paper_2010_08781_amd/selector_params.json
+    python -m paper_2010_08781_amd.selector_fit --out paper_2010_08781_amd/selector_params.json
 """
 from __future__ import annotations
 

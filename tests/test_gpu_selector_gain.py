@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 def test_trained_selector_regret_vs_heuristic():
     import paper_2010_08781_amd as ipg
-    from paper_2010_08781_amd import selector_train as st
+    from paper_2010_08781_amd import selector_fit as st
 
     params = st.load()
     assert params is not None, "selector_params.json missing"
