@@ -26,11 +26,19 @@
 //    the store's pull items (row pieces and long-row chunks), with the
 //    gathered 32-byte masks staged in a wavefront-owned LDS tile;
 //  * push: every vertex of the union frontier ORs its mask into its
-//    out-neighbours' receive rows with 64-bit atomics; the first sender to
-//    reach a vertex appends it to a touched list (wave-ballot compaction) and
-//    a settle pass runs compute over that list.
-// Masks are [N][4] uint64 rows (query q is bit q % 64 of word q / 64);
-// distances are written as [Q][N] uint32 (query-major, INF = unreached).
+//    out-neighbours' receive rows with 64-bit atomics and sets their bits in
+//    a touched bitmap; a settle pass runs compute on the touched vertices.
+// The union frontier of each superstep is kept as a bitmap of the non-empty
+// rows of F_s (set by wave-reduced atomic ORs spread over N/32 words: a
+// list with one shared counter costs one same-address atomic per
+// wavefront, and those serialize device-wide).
+// Masks are [N][4] uint64 rows (query q is bit q % 64 of word q / 64).  The
+// masks F_s of the last kMsHist supersteps are kept (a ring of level
+// buffers); distances are not written per superstep but expanded from that
+// history into [Q][N] uint32 (query-major, INF = unreached) by one
+// coalesced pass when the ring is full and at the end of the run.  A sparse
+// pull superstep reads a bitmap of the non-empty rows of F_{s-1} first and
+// gathers only those rows.
 #include <algorithm>
 #include <vector>
 
@@ -45,6 +53,10 @@ constexpr uint32_t kMsMaxQueries = 64 * kMsWords;
 static_assert(kMsMaxQueries == IPG_BATCH_MAX_SOURCES, "mask width");
 // Edges whose masks are staged in LDS at once by a row item (per wavefront).
 constexpr uint32_t kMsPass = 256;
+// Supersteps of level masks kept before they are expanded into distances.
+constexpr uint32_t kMsHist = 16;
+constexpr int kMsHistBits = 4;
+static_assert((1u << kMsHistBits) == kMsHist, "level index bits");
 
 typedef unsigned long long u64;
 
@@ -55,9 +67,7 @@ struct MsRun {
   const u64* f_in;   // F_{level-1}
   u64* f_out;        // F_level
   u64* vis;
-  uint32_t* dist;    // [Q][n]
-  uint32_t* list_out;
-  uint32_t* list_cnt;
+  uint32_t* nz_out;  // bitmap of the non-empty rows of f_out
   CtrSlot* ctr;
   CtrSlot* ctr_clear;
 };
@@ -65,19 +75,40 @@ struct MsRun {
 struct MsPullArgs {
   MsRun r;
   PullTiling t;
-  u64* partial;  // [chunks][4]
+  u64* partial;        // [chunks][4]
+  const uint32_t* nz;  // bitmap of the non-empty rows of f_in, or null (gather every row)
 };
+
+// Bit v of a bitmap.
+__device__ __forceinline__ bool bit_of(const uint32_t* bm, uint32_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
+
+// Set bit v of bitmap `bm` for every lane with `pred`, one atomic OR per
+// distinct 32-bit word of the wavefront (all lanes must call).
+__device__ __forceinline__ void wave_set_bits(bool pred, uint32_t v, uint32_t* bm) {
+  uint64_t pending = __ballot(pred);
+  while (pending) {
+    const int leader = __ffsll(static_cast<unsigned long long>(pending)) - 1;
+    const uint32_t word = static_cast<uint32_t>(__shfl(static_cast<int>(v), leader)) >> 5;
+    const bool mine = pred && (v >> 5) == word;
+    uint32_t bits = mine ? (1u << (v & 31)) : 0u;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) bits |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(bits), o));
+    if (static_cast<int>(lane_id()) == leader) atomicOr(bm + word, bits);
+    pending &= ~__ballot(mine);
+  }
+}
+
+__device__ __forceinline__ bool row_live(const uint32_t* nz, int32_t u) {
+  return nz == nullptr || ((nz[static_cast<uint32_t>(u) >> 5] >> (u & 31)) & 1u);
+}
 
 struct MsPushArgs {
   MsRun r;
-  const uint64_t* off;  // CSR
+  const uint64_t* off;     // CSR
   const int32_t* dst;
-  const uint32_t* list_in;  // union frontier of the previous superstep
-  uint32_t list_in_count;
-  u64* recv;          // [n][4], zero outside a push superstep
-  uint32_t* tflag;    // [n], zero outside a push superstep
-  uint32_t* touched;  // [n]
-  uint32_t* touched_cnt;
+  const uint32_t* nz_in;   // union frontier of the previous superstep (bitmap)
+  u64* recv;               // [n][4], zero outside a push superstep
+  uint32_t* touched;       // bitmap, zero outside a push superstep
 };
 
 __device__ __forceinline__ void load_mask(const u64* base, uint32_t v, u64 m[kMsWords]) {
@@ -132,75 +163,55 @@ __device__ __forceinline__ bool ms_compute(const MsRun& a, uint32_t v, const u64
   return sends;
 }
 
-// dist[q][v] = level for every bit q of F (one thread, scattered stores).
-__device__ __forceinline__ void ms_write_dist(const MsRun& a, uint32_t v, const u64 F[kMsWords]) {
-#pragma unroll
-  for (int k = 0; k < kMsWords; ++k) {
-    u64 m = F[k];
-    while (m) {
-      const uint32_t b = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(m)) - 1);
-      m &= m - 1;
-      a.dist[(size_t)(64 * k + b) * a.n + v] = a.level;
-    }
-  }
-}
-
-// Superstep 0: one thread per query sets its source's bit in vis and F_0,
-// writes distance 0, and appends each distinct source to the union frontier.
-__global__ __launch_bounds__(kBlock) void ms_init_kernel(const uint32_t* sources, uint32_t q, MsRun a,
-                                                         uint32_t* tflag) {
+// Superstep 0: one thread per query sets its source's bit in vis and F_0 and
+// marks the source in the union frontier (a repeated source counts once).
+__global__ __launch_bounds__(kBlock) void ms_init_kernel(const uint32_t* sources, uint32_t q, MsRun a) {
   const uint32_t i = threadIdx.x;
   uint64_t senders = 0, messages = 0, next_count = 0, next_deg = 0;
-  bool fresh = false;
-  uint32_t v = 0;
   if (i < q) {
-    v = sources[i];
+    const uint32_t v = sources[i];
     const u64 bit = 1ull << (i & 63);
     atomicOr(a.vis + (size_t)v * kMsWords + (i >> 6), bit);
     atomicOr(a.f_out + (size_t)v * kMsWords + (i >> 6), bit);
-    a.dist[(size_t)i * a.n + v] = 0;
     const uint32_t d = a.outdeg[v];
     senders = 1;
     messages = d;
-    fresh = atomicOr(tflag + v, 1u) == 0u;
-    if (fresh) {
+    const uint32_t vb = 1u << (v & 31);
+    if ((atomicOr(a.nz_out + (v >> 5), vb) & vb) == 0u) {
       next_count = 1;
       next_deg = d;
     }
   }
-  wave_append(fresh, v, a.list_out, a.list_cnt);
   flush_counters(a.ctr, senders, messages, next_count, next_deg, 0);
 }
 
-// Zero tflag for the listed vertices.
-__global__ void ms_unflag_kernel(const uint32_t* list, const uint32_t* cnt, uint32_t* tflag) {
-  const uint32_t c = *cnt;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < c; i += gridDim.x * blockDim.x) tflag[list[i]] = 0;
-}
-
-// Zero the mask rows of the listed vertices (the non-zero rows of a level
-// buffer about to be reused by a push superstep).
-__global__ void ms_clear_rows_kernel(const uint32_t* list, const uint32_t* cnt, u64* f) {
-  const uint32_t c = *cnt;
+// Zero the mask rows whose bits are set in `bm` (the non-empty rows of a
+// level buffer about to be reused by a push superstep); one thread per
+// bitmap word.
+__global__ void ms_clear_rows_kernel(const uint32_t* bm, uint32_t words, u64* f) {
   const u64 z[kMsWords] = {0, 0, 0, 0};
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < c; i += gridDim.x * blockDim.x)
-    store_mask(f, list[i], z);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x) {
+    uint32_t m = bm[i];
+    while (m) {
+      const uint32_t b = static_cast<uint32_t>(__ffs(m) - 1);
+      m &= m - 1;
+      store_mask(f, 32 * i + b, z);
+    }
+  }
 }
 
 // Pull exchange of superstep level-1 and compute of superstep `level`, over
 // the pull items (one wavefront per item, grid-stride over wavefronts).
 //  * row item: in passes of kMsPass edges, every lane gathers the masks of
 //    its edges' sources into the wavefront's LDS tile; a group of G lanes
-//    per row ORs the row's entries (G from the item's row count); the
-//    group's first lane computes the row; distances are then written per
-//    query bit, with lanes over the item's rows (coalesced along v);
+//    per row ORs the row's entries (G from the item's row count) and the
+//    group's first lane computes the row;
 //  * long-row chunk: the OR of its edges' masks is stored as the chunk's
 //    partial (combined by ms_longrow_kernel).
 __global__ __launch_bounds__(kBlock) void ms_pull_kernel(MsPullArgs a) {
   constexpr int kPer = kMsPass / kWave;
   constexpr int kChunkPer = kWaveTile / kWave;
   constexpr int kRowPer = (kItemRows + kWave) / kWave;
-  static_assert(kItemRows * kMsWords <= kMsPass * kMsWords, "new masks reuse the tile");
   __shared__ u64 s_tile[kWavesPerBlock][kMsPass][kMsWords];
   __shared__ uint32_t s_off[kWavesPerBlock][kItemRows + 1];
   clear_slots(a.r.ctr_clear);
@@ -225,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void ms_pull_kernel(MsPullArgs a) {
       }
 #pragma unroll
       for (int k = 0; k < kChunkPer; ++k) {
-        if (u[k] >= 0) {
+        if (u[k] >= 0 && row_live(a.nz, u[k])) {
           u64 m[kMsWords];
           load_mask(a.r.f_in, static_cast<uint32_t>(u[k]), m);
 #pragma unroll
@@ -266,8 +277,8 @@ __global__ __launch_bounds__(kBlock) void ms_pull_kernel(MsPullArgs a) {
 #pragma unroll
       for (int k = 0; k < kPer; ++k) {
         if (u[k] >= 0) {
-          u64 m[kMsWords];
-          load_mask(a.r.f_in, static_cast<uint32_t>(u[k]), m);
+          u64 m[kMsWords] = {0, 0, 0, 0};
+          if (row_live(a.nz, u[k])) load_mask(a.r.f_in, static_cast<uint32_t>(u[k]), m);
 #pragma unroll
           for (int w = 0; w < kMsWords; ++w) tile[lane + k * kWave][w] = m[w];
         }
@@ -290,30 +301,9 @@ __global__ __launch_bounds__(kBlock) void ms_pull_kernel(MsPullArgs a) {
     if (owner) {
       u64 F[kMsWords];
       sends = ms_compute(a.r, v, acc, F, c);
-#pragma unroll
-      for (int w = 0; w < kMsWords; ++w) tile[gi][w] = F[w];
     }
-    wave_append(sends, v, a.r.list_out, a.r.list_cnt);
-    wave_lds_sync();
-    // distances: lane r holds the new bits of row r; one coalesced store
-    // per query bit present in the item
-    u64 mine[kMsWords] = {0, 0, 0, 0};
-    if (lane < nrows) {
-#pragma unroll
-      for (int w = 0; w < kMsWords; ++w) mine[w] = tile[lane][w];
-    }
-#pragma unroll
-    for (int w = 0; w < kMsWords; ++w) {
-      u64 any = mine[w];
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) any |= shfl_xor_u64(any, o);
-      while (any) {
-        const uint32_t bit = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(any)) - 1);
-        any &= any - 1;
-        if ((mine[w] >> bit) & 1ull) a.r.dist[(size_t)(64 * w + bit) * n + it.r0 + lane] = a.r.level;
-      }
-    }
-    wave_lds_sync();  // the tile and offsets are rewritten by the next item
+    wave_set_bits(sends, v, a.r.nz_out);
+    wave_lds_sync();  // the offsets are rewritten by the next item
   }
   flush_counters(a.r.ctr, c.senders, c.messages, c.next_count, c.next_deg, 0, c.active);
 }
@@ -341,28 +331,22 @@ __global__ __launch_bounds__(kBlock) void ms_longrow_kernel(MsPullArgs a) {
     u64 F[kMsWords] = {0, 0, 0, 0};
     bool sends = false;
     if (lane == 0) sends = ms_compute(a.r, v, acc, F, c);
-    wave_append(sends, v, a.r.list_out, a.r.list_cnt);
-#pragma unroll
-    for (int w = 0; w < kMsWords; ++w) {
-      const u64 fw = static_cast<u64>(__shfl(static_cast<unsigned long long>(F[w]), 0));
-      if ((fw >> lane) & 1ull) a.r.dist[(size_t)(64 * w + lane) * a.r.n + v] = a.r.level;
-    }
+    if (sends) atomicOr(a.r.nz_out + (v >> 5), 1u << (v & 31));
   }
   flush_counters(a.r.ctr, c.senders, c.messages, c.next_count, c.next_deg, 0, c.active);
 }
 
-// Push exchange of superstep level-1: one thread per union-frontier vertex,
-// out-edges expanded by twc_scatter; each edge ORs the sender's mask into the
-// recipient's receive row.  The first sender to flag a recipient appends it
-// to the touched list.
+// Push exchange of superstep level-1: one thread per vertex, the vertices of
+// the union frontier send, with out-edges expanded by twc_scatter; each edge
+// ORs the sender's mask into the recipient's receive row and marks the
+// recipient touched.
 __global__ __launch_bounds__(kBlock) void ms_push_kernel(MsPushArgs a) {
   clear_slots(a.r.ctr_clear);
   const uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x;
   bool has = false;
   uint64_t beg = 0, end = 0;
-  uint32_t u = 0;
-  if (i < a.list_in_count) {
-    u = a.list_in[i];
+  const uint32_t u = static_cast<uint32_t>(i);
+  if (i < a.r.n && bit_of(a.nz_in, u)) {
     beg = a.off[u];
     end = a.off[u + 1];
     has = end > beg;
@@ -374,59 +358,112 @@ __global__ __launch_bounds__(kBlock) void ms_push_kernel(MsPushArgs a) {
 #pragma unroll
     for (int w = 0; w < kMsWords; ++w)
       if (m[w]) atomicOr(a.recv + (size_t)x * kMsWords + w, m[w]);
-    const bool fresh = atomicOr(a.tflag + x, 1u) == 0u;
-    wave_append(fresh, x, a.touched, a.touched_cnt);
+    const uint32_t xb = 1u << (x & 31);
+    if (!(a.touched[x >> 5] & xb)) atomicOr(a.touched + (x >> 5), xb);
   });
 }
 
-// Compute of a push superstep over the touched list: consume (and zero) the
-// receive rows.
+// Compute of a push superstep: every wavefront takes 64 consecutive vertices
+// (two bitmap words it owns), consumes and zeroes the receive rows of the
+// touched ones, and writes both words of the union-frontier bitmap and of
+// the (cleared) touched bitmap with plain stores.
 __global__ __launch_bounds__(kBlock) void ms_settle_kernel(MsPushArgs a) {
   MsCount c;
-  const uint32_t cnt = *a.touched_cnt;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
-    const uint32_t v = a.touched[i];
-    u64 R[kMsWords], F[kMsWords];
-    load_mask(a.recv, v, R);
-    const u64 z[kMsWords] = {0, 0, 0, 0};
-    store_mask(a.recv, v, z);
-    a.tflag[v] = 0;
-    const bool sends = ms_compute(a.r, v, R, F, c);
-    wave_append(sends, v, a.r.list_out, a.r.list_cnt);
-    if (sends) ms_write_dist(a.r, v, F);
+  const uint32_t lane = lane_id();
+  const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / kWave;
+  const uint64_t nwaves = (uint64_t)gridDim.x * blockDim.x / kWave;
+  for (uint64_t base = wave * kWave; base < a.r.n; base += nwaves * kWave) {  // wave-uniform
+    const uint32_t v = static_cast<uint32_t>(base) + lane;
+    const uint32_t word = static_cast<uint32_t>(base >> 5) + (lane >> 5);
+    const bool touched = v < a.r.n && ((a.touched[word] >> (v & 31)) & 1u);
+    bool sends = false;
+    if (touched) {
+      u64 R[kMsWords], F[kMsWords];
+      load_mask(a.recv, v, R);
+      const u64 z[kMsWords] = {0, 0, 0, 0};
+      store_mask(a.recv, v, z);
+      sends = ms_compute(a.r, v, R, F, c);
+    }
+    const uint64_t sm = __ballot(sends);
+    if (lane == 0) {
+      const uint32_t w0 = static_cast<uint32_t>(base >> 5);
+      a.r.nz_out[w0] = static_cast<uint32_t>(sm);
+      a.r.nz_out[w0 + 1] = static_cast<uint32_t>(sm >> 32);
+      a.touched[w0] = 0;
+      a.touched[w0 + 1] = 0;
+    }
   }
   flush_counters(a.r.ctr, c.senders, c.messages, c.next_count, c.next_deg, 0, c.active);
+}
+
+// Distances from the level masks of supersteps lvl0 .. lvl0+nlev-1 (ring
+// slot (lvl0 + j) % kMsHist): dist[q][v] = the superstep whose mask holds
+// bit q at v.  One thread per vertex; the level index of each bit is read
+// from bit planes built over the window, and the stores for one query are
+// coalesced along v.  The first window also writes INF where no bit is set;
+// later windows write only the distances they hold.
+__global__ __launch_bounds__(kBlock) void ms_expand_kernel(const u64* hist, uint32_t n, uint32_t q, uint32_t lvl0,
+                                                           uint32_t nlev, int first, uint32_t* dist) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
+    u64 found[kMsWords] = {0, 0, 0, 0};
+    u64 plane[kMsHistBits][kMsWords] = {};
+    for (uint32_t j = 0; j < nlev; ++j) {
+      const uint32_t slot = (lvl0 + j) % kMsHist;
+      u64 m[kMsWords];
+      load_mask(hist + (size_t)slot * n * kMsWords, static_cast<uint32_t>(v), m);
+#pragma unroll
+      for (int w = 0; w < kMsWords; ++w) {
+        found[w] |= m[w];
+#pragma unroll
+        for (int b = 0; b < kMsHistBits; ++b)
+          if ((j >> b) & 1u) plane[b][w] |= m[w];
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < kMsWords; ++w) {
+      const uint32_t qe = q > 64u * w ? (q - 64u * w < 64u ? q - 64u * w : 64u) : 0u;
+      for (uint32_t bit = 0; bit < qe; ++bit) {
+        uint32_t* out = dist + (size_t)(64u * w + bit) * n + v;
+        if ((found[w] >> bit) & 1ull) {
+          uint32_t lvl = 0;
+#pragma unroll
+          for (int b = 0; b < kMsHistBits; ++b) lvl |= static_cast<uint32_t>((plane[b][w] >> bit) & 1ull) << b;
+          *out = lvl0 + lvl;
+        } else if (first) {
+          *out = kInf;
+        }
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------------------ host --
 
 struct MsWs {
   u64* vis;
-  u64* f[2];
+  u64* hist;        // [kMsHist][n][4] level masks, slot = superstep % kMsHist
   u64* recv;
   u64* partial;
-  uint32_t* tflag;
-  uint32_t* list[2];
-  uint32_t* touched;
-  uint32_t* cnt;  // [4]: list[0] length, list[1] length, touched length, spare
-  CtrSlot* ctr;   // [2][kCtrSlots]
+  uint32_t* nzb;      // [kMsHist][words] union-frontier bitmap of each level slot
+  uint32_t* touched;  // [words] push: recipients of the superstep
+  CtrSlot* ctr;       // [2][kCtrSlots]
   Decision* decision;
 };
+
+// Bitmap words per vertex set: whole 64-vertex wavefront tiles (the settle
+// pass writes two words per wavefront).
+static size_t ms_words(uint32_t n) { return ((size_t)n + 63) / 64 * 2 + 2; }
 
 static size_t carve_ms(Carver& c, uint32_t n, uint64_t e, MsWs* out) {
   MsWs w{};
   const size_t nn = n ? n : 1;
   w.vis = c.take<u64>(nn * kMsWords);
-  w.f[0] = c.take<u64>(nn * kMsWords);
-  w.f[1] = c.take<u64>(nn * kMsWords);
+  w.hist = c.take<u64>(kMsHist * nn * kMsWords);
   w.recv = c.take<u64>(nn * kMsWords);
   w.partial = c.take<u64>(chunks_cap(e) * kMsWords);
-  w.tflag = c.take<uint32_t>(nn);
-  w.list[0] = c.take<uint32_t>(nn);
-  w.list[1] = c.take<uint32_t>(nn);
-  w.touched = c.take<uint32_t>(nn);
-  w.cnt = c.take<uint32_t>(4);
+  w.nzb = c.take<uint32_t>(kMsHist * ms_words(n));
+  w.touched = c.take<uint32_t>(ms_words(n));
   w.ctr = c.take<CtrSlot>(2 * kCtrSlots);
   w.decision = c.take<Decision>(1);
   if (out) *out = w;
@@ -445,78 +482,90 @@ static ipg_status run_msbfs(ipg_graph* g, const uint32_t* sources, uint32_t q, u
                             uint32_t* dist, const MsWs& w, hipStream_t s, StepTimer& tm, ipg_run_stats* st) {
   const uint32_t n = g->n;
   const uint64_t e = g->e;
-  IPG_HIP(fill_u32(dist, (uint64_t)q * n, kInf, s));
-  IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.vis), (uint64_t)n * 2 * kMsWords, 0, s));
-  IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.f[0]), (uint64_t)n * 2 * kMsWords, 0, s));
-  IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.f[1]), (uint64_t)n * 2 * kMsWords, 0, s));
-  IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.recv), (uint64_t)n * 2 * kMsWords, 0, s));
-  IPG_HIP(fill_u32(w.tflag, n, 0, s));
-  IPG_HIP(fill_u32(w.cnt, 4, 0, s));
+  const size_t rowset = (size_t)n * kMsWords;  // u64 per level buffer
+  const size_t words = ms_words(n);
+  auto slot_buf = [&](uint32_t level) { return w.hist + (size_t)(level % kMsHist) * rowset; };
+  auto slot_bits = [&](uint32_t level) { return w.nzb + (size_t)(level % kMsHist) * words; };
+  IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.vis), rowset * 2, 0, s));
+  IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.hist), rowset * 2, 0, s));  // slot 0
+  IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.recv), rowset * 2, 0, s));
+  IPG_HIP(fill_u32(w.nzb, words, 0, s));  // slot 0
+  IPG_HIP(fill_u32(w.touched, words, 0, s));
   IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.ctr), 2 * kCtrSlots * sizeof(CtrSlot) / 4, 0, s));
+
+  // Expansion of the levels [lvl0, lvl0 + nlev) of the ring into dist.
+  bool first_window = true;
+  auto expand = [&](uint32_t lvl0, uint32_t nlev) -> hipError_t {
+    hipLaunchKernelGGL(ms_expand_kernel, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, w.hist, n, q, lvl0, nlev,
+                       first_window ? 1 : 0, dist);
+    first_window = false;
+    return hipGetLastError();
+  };
 
   MsRun r{};
   r.n = n;
   r.outdeg = g->t.outdeg;
   r.vis = w.vis;
-  r.dist = dist;
   const PullTiling t = pull_tiling(g);
   uint64_t tot_msgs = 0, tot_exam = 0;
   uint64_t frontier = 0, frontier_deg = 0;
-  uint64_t list_len[2] = {0, 0};  // union-frontier list lengths held in list[0] / list[1]
+  bool used[kMsHist] = {};  // slot written since the run started (slot 0 is zeroed above)
+  uint32_t base = 0;        // first level not yet expanded into dist
   uint32_t step = 0;
   ipg_status status = IPG_OK;
   IPG_HIP(tm.start(s));
   for (;;) {
-    const int cur = step & 1, prev = cur ^ 1;
-    CtrSlot* c = w.ctr + cur * kCtrSlots;
-    CtrSlot* cc = w.ctr + prev * kCtrSlots;
+    const uint32_t slot = step % kMsHist;
+    if (step - base == kMsHist) {  // the ring is full: expand it before reusing slot `slot`
+      IPG_HIP(expand(base, kMsHist));
+      base += kMsHist;
+    }
+    CtrSlot* c = w.ctr + (step & 1) * kCtrSlots;
+    CtrSlot* cc = w.ctr + ((step + 1) & 1) * kCtrSlots;
     r.level = step;
-    r.f_out = w.f[cur];
-    r.f_in = w.f[prev];
-    r.list_out = w.list[cur];
-    r.list_cnt = w.cnt + cur;
+    r.f_out = slot_buf(step);
+    r.f_in = step ? slot_buf(step - 1) : nullptr;
+    r.nz_out = slot_bits(step);
     r.ctr = c;
     r.ctr_clear = cc;
     ipg_mode mode = IPG_MODE_PUSH;
     uint64_t examined = 0;
     if (step == 0) {
-      hipLaunchKernelGGL(ms_init_kernel, dim3(1), dim3(kBlock), 0, s, sources, q, r, w.tflag);
-      IPG_HIP(hipGetLastError());
-      hipLaunchKernelGGL(ms_unflag_kernel, dim3(1), dim3(kBlock), 0, s, w.list[cur], w.cnt + cur, w.tflag);
+      hipLaunchKernelGGL(ms_init_kernel, dim3(1), dim3(kBlock), 0, s, sources, q, r);
       IPG_HIP(hipGetLastError());
     } else {
       mode = ms_mode(o.mode, e, frontier, frontier_deg, 20);
       if (mode == IPG_MODE_PUSH) {
-        const uint32_t gc = grid_for(std::min<uint64_t>(frontier_deg + 1, n), kBlock, kExchangeGrid);
-        if (list_len[cur]) {
-          hipLaunchKernelGGL(ms_clear_rows_kernel, dim3(grid_for(list_len[cur], kBlock, kExchangeGrid)), dim3(kBlock),
-                             0, s, w.list[cur], w.cnt + cur, w.f[cur]);
+        // F_out must be zero outside the rows this superstep writes: zero the
+        // rows left by the slot's previous level (its bitmap, still intact)
+        if (!used[slot]) {
+          IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(r.f_out), rowset * 2, 0, s));
+        } else {
+          hipLaunchKernelGGL(ms_clear_rows_kernel, dim3(grid_for(words, kBlock, kExchangeGrid)), dim3(kBlock), 0, s,
+                             r.nz_out, static_cast<uint32_t>(words), r.f_out);
           IPG_HIP(hipGetLastError());
         }
-        IPG_HIP(fill_u32(w.cnt + cur, 1, 0, s));
-        IPG_HIP(fill_u32(w.cnt + 2, 1, 0, s));
         MsPushArgs a;
         a.r = r;
         a.off = g->csr_off;
         a.dst = g->csr_dst;
-        a.list_in = w.list[prev];
-        a.list_in_count = static_cast<uint32_t>(frontier);
+        a.nz_in = slot_bits(step - 1);
         a.recv = w.recv;
-        a.tflag = w.tflag;
         a.touched = w.touched;
-        a.touched_cnt = w.cnt + 2;
-        hipLaunchKernelGGL(ms_push_kernel, dim3(grid_for(frontier, kBlock, 0xFFFFFFFFu)), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(ms_push_kernel, dim3(grid_for(n, kBlock, 0xFFFFFFFFu)), dim3(kBlock), 0, s, a);
         IPG_HIP(hipGetLastError());
         a.r.ctr_clear = nullptr;
-        hipLaunchKernelGGL(ms_settle_kernel, dim3(gc), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(ms_settle_kernel, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, a);
         IPG_HIP(hipGetLastError());
         examined = frontier_deg;
       } else {
-        IPG_HIP(fill_u32(w.cnt + cur, 1, 0, s));
+        IPG_HIP(fill_u32(r.nz_out, words, 0, s));
         MsPullArgs a;
         a.r = r;
         a.t = t;
         a.partial = w.partial;
+        // sparse superstep: gather only the non-empty rows of F_{s-1}
+        a.nz = frontier < n / 8 ? slot_bits(step - 1) : nullptr;
         if (g->ni) {
           hipLaunchKernelGGL(ms_pull_kernel, dim3(std::min(g->ni, kPullGrid)), dim3(kBlock), 0, s, a);
           IPG_HIP(hipGetLastError());
@@ -530,6 +579,7 @@ static ipg_status run_msbfs(ipg_graph* g, const uint32_t* sources, uint32_t q, u
         examined = e;
       }
     }
+    used[slot] = true;
     IPG_HIP(tm.step(s, step));
     IPG_HIP(launch_decide(c, step + 1, e, nullptr, w.decision, s));
     Decision h;
@@ -546,7 +596,6 @@ static ipg_status run_msbfs(ipg_graph* g, const uint32_t* sources, uint32_t q, u
     }
     tot_msgs += h.messages;
     tot_exam += examined;
-    list_len[cur] = h.next_count;
     ++step;
     if (h.messages == 0) break;  // no message pending for any query: all halted
     if (cap && step >= cap) {
@@ -556,6 +605,7 @@ static ipg_status run_msbfs(ipg_graph* g, const uint32_t* sources, uint32_t q, u
     frontier = h.next_count;
     frontier_deg = h.next_deg;
   }
+  IPG_HIP(expand(base, step - base));
   IPG_HIP(tm.finish(s));
   if (st) {
     st->supersteps = step;
