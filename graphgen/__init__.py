@@ -268,6 +268,35 @@ def small_graph_family(count: int = 64, lo_log2: float = 10.0, hi_log2: float = 
     return graphs
 
 
+def disjoint_union(graphs: list, name: str = "union") -> HostGraph:
+    """Block-diagonal union: graph i's vertices are renumbered to start at
+    the sum of the earlier graphs' vertex counts.  meta["parts"] holds the
+    P+1 vertex offsets (uint32)."""
+    offs = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        offs[i + 1] = offs[i] + g.n
+    eoffs = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        eoffs[i + 1] = eoffs[i] + g.m
+
+    def cat(attr_off, attr_adj):
+        off = np.zeros(offs[-1] + 1, dtype=np.uint64)
+        adj = np.empty(eoffs[-1], dtype=np.int32)
+        for i, g in enumerate(graphs):
+            o = getattr(g, attr_off).astype(np.int64)
+            off[offs[i] + 1: offs[i + 1] + 1] = (o[1:] + eoffs[i]).astype(np.uint64)
+            adj[eoffs[i]: eoffs[i + 1]] = getattr(g, attr_adj).astype(np.int64) + offs[i]
+        return off, adj
+
+    csr_off, csr_dst = cat("csr_off", "csr_dst")
+    sym = all(g.symmetric for g in graphs)
+    csc_off, csc_src = (csr_off, csr_dst) if sym else cat("csc_off", "csc_src")
+    u = HostGraph(n=int(offs[-1]), csr_off=csr_off, csr_dst=csr_dst, csc_off=csc_off, csc_src=csc_src,
+                  symmetric=sym, name=name)
+    u.meta["parts"] = offs.astype(np.uint32)
+    return u
+
+
 def pick_sources(g: HostGraph, count: int, seed: int) -> np.ndarray:
     """`count` distinct vertices uniform among those with out-degree >= 1."""
     elig = (np.diff(g.csr_off) > 0).astype(np.uint8)

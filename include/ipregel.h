@@ -88,6 +88,10 @@ typedef struct {
 
 /* ipg_run_opts.flags */
 #define IPG_RUN_PERSISTENT 1u /* device-resident superstep loop: one cooperative launch, no per-superstep host sync */
+#define IPG_RUN_GRAPH 2u      /* PageRank: replay the whole superstep sequence as one hipGraph launch.  The
+                                 graph is captured on the first call and kept in the handle while T, the
+                                 exchange, the workspace and part_offsets stay the same; per-superstep
+                                 times (usec) are not recorded in this mode. */
 
 typedef struct {
   uint32_t source;          /* SSSP source vertex (ignored by the other applications) */
@@ -95,6 +99,14 @@ typedef struct {
   uint32_t flags;
   const double* selector;   /* DEVICE pointer to IPG_SELECTOR_PARAMS trained selector parameters
                                (see ipg_selector_train), used by IPG_MODE_AUTO; NULL = fixed heuristic */
+  /* PageRank over a disjoint union of graphs: DEVICE pointer to num_parts+1
+   * ascending vertex offsets (part_offsets[0] = 0, part_offsets[num_parts] = N).
+   * Vertex v of part p uses that part's vertex count N_p for its initial value
+   * 1/N_p and its ratio 0.15/N_p (Fig. 8), so when no edge crosses two parts
+   * each part's ranks equal a separate run on that part.  Copied to the host
+   * and checked on every call; NULL / 0 = one part of N vertices. */
+  const uint32_t* part_offsets;
+  uint32_t num_parts;
 } ipg_run_opts;
 
 /*

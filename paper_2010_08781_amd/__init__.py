@@ -36,7 +36,7 @@ COMBINE_SUM, COMBINE_MIN = 0, 1
 DEFAULT_COMBINER = {APP_PAGERANK: COMBINE_SUM, APP_CC: COMBINE_MIN, APP_SSSP: COMBINE_MIN}
 MODES = {"auto": 0, "push": 1, "pull": 2}
 GRAPH_SYMMETRIC, GRAPH_VALIDATE = 1, 2
-RUN_PERSISTENT = 1
+RUN_PERSISTENT, RUN_GRAPH = 1, 2
 INF = 0xFFFFFFFF
 BATCH_MAX_SOURCES = 256
 
@@ -56,7 +56,7 @@ class _Desc(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("source", ctypes.c_uint32), ("mode", ctypes.c_int), ("flags", ctypes.c_uint32),
-                ("selector", ctypes.c_void_p)]
+                ("selector", ctypes.c_void_p), ("part_offsets", ctypes.c_void_p), ("num_parts", ctypes.c_uint32)]
 
 
 class _Stats(ctypes.Structure):
@@ -254,11 +254,13 @@ class Graph:
 
     def run(self, app, max_supersteps: Optional[int] = None, source: int = 0, mode: str = "auto",
             timing: bool = True, trace_cap: int = 1 << 16, persistent: bool = False, stream=None,
-            combiner: Optional[int] = None, check: bool = True, selector=None):
+            combiner: Optional[int] = None, check: bool = True, selector=None, parts=None, graph: bool = False):
         """Run an application; returns (values tensor on the device, RunStats).
 
         max_supersteps: PageRank -> number of rank updates (default 10, Fig. 8);
-        CC/SSSP -> cap on supersteps (default 0 = run to vote-to-halt)."""
+        CC/SSSP -> cap on supersteps (default 0 = run to vote-to-halt).
+        parts: PageRank over a disjoint union -- int32 CUDA tensor of part
+        vertex offsets (P+1 entries); graph: replay PageRank as one hipGraph."""
         import torch
 
         a = APPS[app] if isinstance(app, str) else int(app)
@@ -268,8 +270,14 @@ class Graph:
         ws, nbytes = self.workspace(a) if a in DEFAULT_COMBINER else (None, 0)
         if selector is not None:
             _check_selector(selector)
-        opts = _Opts(int(source), MODES[mode], RUN_PERSISTENT if persistent else 0,
-                     selector.data_ptr() if selector is not None else None)
+        if parts is not None:
+            import torch
+
+            if not parts.is_cuda or parts.dtype != torch.int32 or not parts.is_contiguous() or parts.numel() < 2:
+                raise ValueError("parts must be a contiguous int32 CUDA tensor of P+1 offsets")
+        flags = (RUN_PERSISTENT if persistent else 0) | (RUN_GRAPH if graph else 0)
+        opts = _Opts(int(source), MODES[mode], flags, selector.data_ptr() if selector is not None else None,
+                     parts.data_ptr() if parts is not None else None, parts.numel() - 1 if parts is not None else 0)
         tr = _Trace(trace_cap, timing)
         rc = lib().ipg_run(self._h, a, comb, int(max_supersteps), ctypes.byref(opts),
                            ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(stream),
@@ -299,7 +307,7 @@ class Graph:
             nb = lib().ipg_multi_sssp_workspace_bytes(self.n, self.m)
             self._run_ws[key] = (torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device), nb)
         ws, nbytes = self._run_ws[key]
-        opts = _Opts(0, MODES[mode], 0, None)
+        opts = _Opts(0, MODES[mode], 0, None, None, 0)
         tr = _Trace(trace_cap, timing)
         rc = lib().ipg_run_multi_sssp(self._h, src.data_ptr(), q, int(max_supersteps), ctypes.byref(opts),
                                       out.data_ptr(), out.numel() * 4, ws.data_ptr(), nbytes, _stream_handle(stream),

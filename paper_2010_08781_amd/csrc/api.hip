@@ -15,6 +15,7 @@ size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w) {
     r.f64_a = c.take<double>(nn);
     r.f64_b = c.take<double>(nn);
     r.partial = c.take<double>(chunks_cap(e));
+    r.part_n = c.take<uint32_t>(nn);
   } else {
     r.value_u32 = c.take<uint32_t>(nn);
     r.mail_a = c.take<uint32_t>(nn);
@@ -97,11 +98,16 @@ extern "C" ipg_status ipg_run(ipg_graph* g, ipg_app app, ipg_combiner combiner, 
                        (app == IPG_APP_CC_HASHMIN && combiner == IPG_COMBINE_MIN) ||
                        (app == IPG_APP_SSSP && combiner == IPG_COMBINE_MIN);
   if (!ok_pair) return fail(IPG_EUNSUPPORTED, "ipg_run: (app, combiner) must be (PAGERANK, SUM), (CC, MIN) or (SSSP, MIN)");
-  ipg_run_opts o{0, IPG_MODE_AUTO, 0, nullptr};
+  ipg_run_opts o{0, IPG_MODE_AUTO, 0, nullptr, nullptr, 0};
   if (opts) o = *opts;
   if (o.mode != IPG_MODE_AUTO && o.mode != IPG_MODE_PUSH && o.mode != IPG_MODE_PULL)
     return fail(IPG_EINVAL, "ipg_run: unknown mode");
   if (app == IPG_APP_SSSP && o.source >= g->n) return fail(IPG_EINVAL, "ipg_run: SSSP source >= N");
+  if ((o.flags & IPG_RUN_GRAPH) && app != IPG_APP_PAGERANK)
+    return fail(IPG_EUNSUPPORTED, "ipg_run: IPG_RUN_GRAPH applies to PageRank only");
+  if (o.num_parts && app != IPG_APP_PAGERANK)
+    return fail(IPG_EUNSUPPORTED, "ipg_run: part_offsets apply to PageRank only");
+  if (o.num_parts && !o.part_offsets) return fail(IPG_EINVAL, "ipg_run: num_parts without part_offsets");
   const size_t need = ipg_run_workspace_bytes(g->n, g->e, app);
   if (!ws || ws_bytes < need)
     return fail(IPG_EWORKSPACE, "ipg_run: run workspace needs " + std::to_string(need) + " bytes");
@@ -117,7 +123,7 @@ extern "C" ipg_status ipg_run(ipg_graph* g, ipg_app app, ipg_combiner combiner, 
   g->has_values = 0;
   StepTimer tm(st ? st->usec : nullptr, st ? st->trace_cap : 0);
   ipg_status rc;
-  if (app == IPG_APP_PAGERANK) rc = run_pagerank(g, max_supersteps, o.mode, w, s, tm, st);
+  if (app == IPG_APP_PAGERANK) rc = run_pagerank(g, max_supersteps, o, w, ws, s, tm, st);
   else rc = run_minprop(g, app, max_supersteps, o, w, s, tm, st);
   if (st) st->seconds = tm.seconds();
   if (rc == IPG_OK || rc == IPG_NOT_CONVERGED) {

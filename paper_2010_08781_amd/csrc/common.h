@@ -124,6 +124,18 @@ struct ipg_graph {
   int has_values;
   int last_app;
   const void* last_values;
+  // PageRank superstep sequence captured as a hipGraph (IPG_RUN_GRAPH) and
+  // the run it was captured for
+  hipStream_t cap_stream;
+  hipGraph_t pr_graph;
+  hipGraphExec_t pr_exec;
+  struct {
+    uint32_t T;
+    int push;
+    const void* ws;
+    const uint32_t* parts;
+    uint32_t num_parts;
+  } pr_key;
 };
 
 namespace ipg {

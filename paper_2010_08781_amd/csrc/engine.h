@@ -47,6 +47,7 @@ struct RunWs {
   double* f64_a;      // [n] outbox (pull) or mailbox (push), ping
   double* f64_b;      // [n] pong
   double* partial;    // [chunks] partial sums of long-row chunks (pull)
+  uint32_t* part_n;   // [n] vertex count of each vertex's part (disjoint unions)
   // CC / SSSP
   uint32_t* value_u32;  // [n] labels or distances
   uint32_t* mail_a;     // [n] one-slot min mailboxes, ping (INF = empty)
@@ -94,8 +95,8 @@ struct ModeQuery {
 // Fixed heuristic used when no selector is given.
 ipg_mode heuristic_mode(const ModeQuery& q);
 
-ipg_status run_pagerank(ipg_graph* g, uint32_t T, ipg_mode mode, const RunWs& w, hipStream_t s, StepTimer& tm,
-                        ipg_run_stats* st);
+ipg_status run_pagerank(ipg_graph* g, uint32_t T, const ipg_run_opts& o, const RunWs& w, const void* ws,
+                        hipStream_t s, StepTimer& tm, ipg_run_stats* st);
 ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_opts& o, const RunWs& w,
                        hipStream_t s, StepTimer& tm, ipg_run_stats* st);
 

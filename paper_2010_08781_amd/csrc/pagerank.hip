@@ -16,6 +16,7 @@
 // lists as future work, Section 4.3.2 and Section 9); summation order varies
 // from run to run within rounding.
 #include <algorithm>
+#include <vector>
 
 #include "common.h"
 #include "engine.h"
@@ -31,11 +32,17 @@ struct PrPullArgs {
   double* value;
   double* partial;        // per long-row chunk
   double ratio;           // 0.15 / N
+  const uint32_t* part_n; // vertex count of each vertex's part, or null (one part)
   int last;               // superstep == T: store the rank, no broadcast
 };
 
+// 0.15 / N for the part that holds v.
+__device__ __forceinline__ double pr_ratio(double ratio, const uint32_t* part_n, uint32_t v) {
+  return part_n ? 0.15 / static_cast<double>(part_n[v]) : ratio;
+}
+
 __device__ __forceinline__ void pr_finish(const PrPullArgs& a, uint32_t v, double sum) {
-  const double rank = a.ratio + 0.85 * sum;
+  const double rank = pr_ratio(a.ratio, a.part_n, v) + 0.85 * sum;
   if (a.last) {
     a.value[v] = rank;
   } else {
@@ -128,8 +135,8 @@ __global__ __launch_bounds__(kBlock) void pr_items_kernel(PrPullArgs a) {
       }
       for (uint32_t o = G >> 1; o >= 1; o >>= 1) s += __shfl_xor(s, static_cast<int>(o));
       if (li == 0 && row < nrows) {
-        const double rank = a.ratio + 0.85 * s;
         const uint32_t v = it.r0 + row;
+        const double rank = pr_ratio(a.ratio, a.part_n, v) + 0.85 * s;
         if (a.last) {
           a.value[v] = rank;
         } else {
@@ -155,17 +162,37 @@ __global__ __launch_bounds__(kBlock) void pr_longrow_kernel(PrPullArgs a) {
   if (lane_id() == 0) pr_finish(a, a.t.long_rows[l], s);
 }
 
+// 1 / N for the part that holds v.
+__device__ __forceinline__ double pr_init(double init, const uint32_t* part_n, uint32_t v) {
+  return part_n ? 1.0 / static_cast<double>(part_n[v]) : init;
+}
+
 // Superstep 0 of the pull form: rank 1/N, outbox 1/N/outdeg.
-__global__ void pr_pull_init_kernel(uint32_t n, const uint32_t* outdeg, double init, double* contrib, double* value,
-                                    int last) {
+__global__ void pr_pull_init_kernel(uint32_t n, const uint32_t* outdeg, double init, const uint32_t* part_n,
+                                    double* contrib, double* value, int last) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
+    const double x = pr_init(init, part_n, static_cast<uint32_t>(v));
     if (last) {
-      value[v] = init;
+      value[v] = x;
     } else {
       const uint32_t d = outdeg[v];
-      contrib[v] = d ? init / static_cast<double>(d) : 0.0;
+      contrib[v] = d ? x / static_cast<double>(d) : 0.0;
     }
+  }
+}
+
+// Vertex count of the part of every vertex: part p holds [off[p], off[p+1]).
+__global__ void pr_part_n_kernel(const uint32_t* off, uint32_t parts, uint32_t n, uint32_t* part_n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
+    uint32_t lo = 0, hi = parts - 1;  // last part p with off[p] <= v
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= v) lo = mid;
+      else hi = mid - 1;
+    }
+    part_n[v] = off[lo + 1] - off[lo];
   }
 }
 
@@ -177,6 +204,7 @@ struct PrPushArgs {
   double* mail_out;      // atomically accumulated
   double* value;
   double ratio, init;
+  const uint32_t* part_n;
   int first, last;
 };
 
@@ -191,11 +219,11 @@ __global__ __launch_bounds__(kBlock) void pr_push_kernel(PrPushArgs a) {
   if (v < a.n) {
     double rank;
     if (a.first) {
-      rank = a.init;
+      rank = pr_init(a.init, a.part_n, static_cast<uint32_t>(v));
     } else {
       const double m = a.mail_in[v];
       a.mail_in[v] = 0.0;
-      rank = a.ratio + 0.85 * m;
+      rank = pr_ratio(a.ratio, a.part_n, static_cast<uint32_t>(v)) + 0.85 * m;
     }
     if (a.last) {
       a.value[v] = rank;
@@ -213,44 +241,53 @@ __global__ __launch_bounds__(kBlock) void pr_push_kernel(PrPushArgs a) {
 
 // ------------------------------------------------------------------ host --
 
-ipg_status run_pagerank(ipg_graph* g, uint32_t T, ipg_mode mode, const RunWs& w, hipStream_t s, StepTimer& tm,
-                        ipg_run_stats* st) {
+// Every launch of one PageRank run, in order, on stream s (also used to
+// capture the run as a graph, with tm == nullptr).
+static hipError_t enqueue_pagerank(ipg_graph* g, uint32_t T, bool push, const RunWs& w, const uint32_t* part_off,
+                                   uint32_t parts, hipStream_t s, StepTimer* tm) {
+  hipError_t err;
   const uint32_t n = g->n;
   const double ratio = 0.15 / static_cast<double>(n);
   const double init = 1.0 / static_cast<double>(n);
-  const bool push = (mode == IPG_MODE_PUSH);
   const uint32_t gv = grid_for(n, kBlock, 16384);
+  const uint32_t* part_n = nullptr;
+  if (part_off) {
+    hipLaunchKernelGGL(pr_part_n_kernel, dim3(gv), dim3(kBlock), 0, s, part_off, parts, n, w.part_n);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    part_n = w.part_n;
+  }
   if (!push) {
-    IPG_HIP(tm.start(s));
-    hipLaunchKernelGGL(pr_pull_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, g->t.outdeg, init, w.f64_a,
+    if (tm && (err = tm->start(s)) != hipSuccess) return err;
+    hipLaunchKernelGGL(pr_pull_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, g->t.outdeg, init, part_n, w.f64_a,
                        w.value_f64, T == 0);
-    IPG_HIP(hipGetLastError());
-    IPG_HIP(tm.step(s, 0));
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if (tm && (err = tm->step(s, 0)) != hipSuccess) return err;
     PrPullArgs a;
     a.t = pull_tiling(g);
     a.outdeg = g->t.outdeg;
     a.value = w.value_f64;
     a.partial = w.partial;
     a.ratio = ratio;
+    a.part_n = part_n;
     for (uint32_t step = 1; step <= T; ++step) {
       a.contrib_in = (step & 1) ? w.f64_a : w.f64_b;
       a.contrib_out = (step & 1) ? w.f64_b : w.f64_a;
       a.last = step == T;
       if (g->ni) {
         hipLaunchKernelGGL(pr_items_kernel, dim3(std::min(g->ni, kPullGrid)), dim3(kBlock), 0, s, a);
-        IPG_HIP(hipGetLastError());
+        if ((err = hipGetLastError()) != hipSuccess) return err;
       }
       if (g->nl) {
         hipLaunchKernelGGL(pr_longrow_kernel, dim3((g->nl + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0, s,
                            a);
-        IPG_HIP(hipGetLastError());
+        if ((err = hipGetLastError()) != hipSuccess) return err;
       }
-      IPG_HIP(tm.step(s, step));
+      if (tm && (err = tm->step(s, step)) != hipSuccess) return err;
     }
   } else {
-    IPG_HIP(fill_f64(w.f64_a, n, 0.0, s));
-    IPG_HIP(fill_f64(w.f64_b, n, 0.0, s));
-    IPG_HIP(tm.start(s));
+    if ((err = fill_f64(w.f64_a, n, 0.0, s)) != hipSuccess) return err;
+    if ((err = fill_f64(w.f64_b, n, 0.0, s)) != hipSuccess) return err;
+    if (tm && (err = tm->start(s)) != hipSuccess) return err;
     PrPushArgs a;
     a.n = n;
     a.off = g->csr_off;
@@ -258,6 +295,7 @@ ipg_status run_pagerank(ipg_graph* g, uint32_t T, ipg_mode mode, const RunWs& w,
     a.value = w.value_f64;
     a.ratio = ratio;
     a.init = init;
+    a.part_n = part_n;
     const uint32_t grid = grid_for(n, kBlock, 0xFFFFFFFFu);
     for (uint32_t step = 0; step <= T; ++step) {
       a.mail_in = (step & 1) ? w.f64_b : w.f64_a;
@@ -265,9 +303,75 @@ ipg_status run_pagerank(ipg_graph* g, uint32_t T, ipg_mode mode, const RunWs& w,
       a.first = step == 0;
       a.last = step == T;
       hipLaunchKernelGGL(pr_push_kernel, dim3(grid), dim3(kBlock), 0, s, a);
-      IPG_HIP(hipGetLastError());
-      IPG_HIP(tm.step(s, step));
+      if ((err = hipGetLastError()) != hipSuccess) return err;
+      if (tm && (err = tm->step(s, step)) != hipSuccess) return err;
     }
+  }
+  return hipSuccess;
+}
+
+// The captured graph of the run described by the arguments, capturing it
+// (again) when the handle holds none or one for another run.
+static ipg_status pagerank_graph(ipg_graph* g, uint32_t T, bool push, const RunWs& w, const void* ws,
+                                 const uint32_t* part_off, uint32_t parts, hipGraphExec_t* out) {
+  auto& k = g->pr_key;
+  if (g->pr_exec && k.T == T && k.push == (push ? 1 : 0) && k.ws == ws && k.parts == part_off && k.num_parts == parts) {
+    *out = g->pr_exec;
+    return IPG_OK;
+  }
+  if (g->pr_exec) {
+    IPG_HIP(hipGraphExecDestroy(g->pr_exec));
+    g->pr_exec = nullptr;
+  }
+  if (g->pr_graph) {
+    IPG_HIP(hipGraphDestroy(g->pr_graph));
+    g->pr_graph = nullptr;
+  }
+  if (!g->cap_stream) IPG_HIP(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+  IPG_HIP(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+  const hipError_t qe = enqueue_pagerank(g, T, push, w, part_off, parts, g->cap_stream, nullptr);
+  hipGraph_t graph = nullptr;
+  const hipError_t ce = hipStreamEndCapture(g->cap_stream, &graph);
+  if (qe != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_fail(qe, "capture of the PageRank supersteps");
+  }
+  IPG_HIP(ce);
+  g->pr_graph = graph;
+  IPG_HIP(hipGraphInstantiate(&g->pr_exec, graph, nullptr, nullptr, 0));
+  k.T = T;
+  k.push = push ? 1 : 0;
+  k.ws = ws;
+  k.parts = part_off;
+  k.num_parts = parts;
+  *out = g->pr_exec;
+  return IPG_OK;
+}
+
+ipg_status run_pagerank(ipg_graph* g, uint32_t T, const ipg_run_opts& o, const RunWs& w, const void* ws,
+                        hipStream_t s, StepTimer& tm, ipg_run_stats* st) {
+  const uint32_t n = g->n;
+  const bool push = (o.mode == IPG_MODE_PUSH);
+  const uint32_t* part_off = nullptr;
+  uint32_t parts = 0;
+  if (o.part_offsets && o.num_parts) {
+    std::vector<uint32_t> h(o.num_parts + 1);
+    IPG_HIP(hipMemcpyAsync(h.data(), o.part_offsets, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    IPG_HIP(hipStreamSynchronize(s));
+    if (h[0] != 0 || h[o.num_parts] != n) return fail(IPG_EINVAL, "ipg_run: part_offsets must run from 0 to N");
+    for (uint32_t p = 0; p < o.num_parts; ++p)
+      if (h[p + 1] <= h[p]) return fail(IPG_EINVAL, "ipg_run: part_offsets must be strictly increasing");
+    part_off = o.part_offsets;
+    parts = o.num_parts;
+  }
+  if (o.flags & IPG_RUN_GRAPH) {
+    hipGraphExec_t exec = nullptr;
+    const ipg_status rc = pagerank_graph(g, T, push, w, ws, part_off, parts, &exec);
+    if (rc != IPG_OK) return rc;
+    IPG_HIP(tm.start(s));
+    IPG_HIP(hipGraphLaunch(exec, s));
+  } else {
+    IPG_HIP(enqueue_pagerank(g, T, push, w, part_off, parts, s, &tm));
   }
   IPG_HIP(tm.finish(s));
   // The PageRank trace is fixed by Fig. 8: every vertex runs in every
@@ -285,6 +389,7 @@ ipg_status run_pagerank(ipg_graph* g, uint32_t T, ipg_mode mode, const RunWs& w,
       if (st->examined) st->examined[k] = k < T ? g->e : 0;
       if (st->mode) st->mode[k] = push ? IPG_MODE_PUSH : IPG_MODE_PULL;
       if (st->frontier_deg) st->frontier_deg[k] = g->e;
+      if ((o.flags & IPG_RUN_GRAPH) && st->usec) st->usec[k] = 0.f;
     }
   }
   return IPG_OK;

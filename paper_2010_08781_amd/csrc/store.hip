@@ -301,6 +301,12 @@ extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t
   return IPG_OK;
 }
 
-extern "C" void ipg_graph_destroy(ipg_graph* g) { delete g; }
+extern "C" void ipg_graph_destroy(ipg_graph* g) {
+  if (!g) return;
+  if (g->pr_exec) (void)hipGraphExecDestroy(g->pr_exec);
+  if (g->pr_graph) (void)hipGraphDestroy(g->pr_graph);
+  if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+  delete g;
+}
 
 extern "C" const char* ipg_last_error(void) { return g_last_error.c_str(); }

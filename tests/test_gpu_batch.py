@@ -160,3 +160,92 @@ def test_batch_full_size_sampled(ipg):
         assert int(row.max()) < st.supersteps
         per_level += torch.bincount(row, minlength=st.supersteps + 1)
     assert np.array_equal(per_level.cpu().numpy()[: st.supersteps].astype(np.uint64), tr[:, 1])
+
+
+# --------------------------------------------------- PageRank over parts --
+#
+# A disjoint union of graphs with per-part N: each part's ranks equal a
+# separate oracle run on that part (within the PageRank tolerance), in both
+# exchanges, eagerly and replayed as a hipGraph.
+
+PR_RTOL = 1e-12
+
+
+def _parts_tensor(u):
+    import torch
+
+    return torch.from_numpy(u.meta["parts"].astype(np.int32)).cuda()
+
+
+def _check_parts(u, graphs, ranks, T):
+    r = ranks.cpu().numpy()
+    offs = u.meta["parts"].astype(np.int64)
+    for i, hg in enumerate(graphs):
+        ref = oracle.run_graph("pagerank", hg, T)
+        got = r[offs[i]: offs[i + 1]]
+        err = float(np.max(np.abs(got - ref.values) / np.abs(ref.values)))
+        assert err <= PR_RTOL, f"part {i} (n={hg.n}): max rel err {err:.3e}"
+
+
+def test_pagerank_parts_match_separate_runs(ipg):
+    graphs = [graphgen.rmat_small(n, 8, seed=200 + n) for n in (1000, 1500, 3000, 64, 5000, 777)]
+    graphs.append(random_graph(50, 200, seed=9, loops=True, dups=True))
+    u = graphgen.disjoint_union(graphs)
+    g = ipg.Graph.from_host(u)
+    parts = _parts_tensor(u)
+    for mode in ("pull", "push"):
+        for T in (0, 1, 20):
+            ranks, st = g.run("pagerank", T, mode=mode, parts=parts)
+            _check_parts(u, graphs, ranks, T)
+            assert st.supersteps == T + 1
+
+
+def test_pagerank_graph_replay_equals_eager(ipg):
+    import torch
+
+    graphs = [graphgen.rmat_small(n, 8, seed=300 + n) for n in (2000, 4000, 1024)]
+    u = graphgen.disjoint_union(graphs)
+    g = ipg.Graph.from_host(u)
+    parts = _parts_tensor(u)
+    eager = {T: g.run("pagerank", T, mode="pull", parts=parts)[0].clone() for T in (5, 20)}
+    for rep in range(4):
+        for T in (20, 20, 5):  # same key replays; a new T re-captures
+            r, st = g.run("pagerank", T, mode="pull", parts=parts, graph=True)
+            assert torch.equal(r, eager[T]), f"replay {rep} T={T}"
+            assert st.seconds > 0
+        # eager work and synchronisation between replays
+        g.run("cc")
+        torch.cuda.synchronize()
+    r, _ = g.run("pagerank", 20, mode="push", parts=parts, graph=True)
+    _check_parts(u, graphs, r, 20)
+    # a whole graph (no parts) replayed
+    r, _ = g.run("pagerank", 7, mode="pull", graph=True)
+    assert torch.equal(r, g.run("pagerank", 7, mode="pull")[0])
+
+
+def test_pagerank_parts_errors(ipg):
+    import torch
+
+    u = graphgen.disjoint_union([random_graph(30, 90, seed=1), random_graph(20, 60, seed=2)])
+    g = ipg.Graph.from_host(u)
+    for bad in ([0, 30, 49], [0, 30, 30, 50], [1, 30, 50]):
+        with pytest.raises(ipg.IpgError) as e:
+            g.run("pagerank", 3, parts=torch.tensor(bad, dtype=torch.int32, device="cuda"))
+        assert e.value.status == ipg.EINVAL
+    with pytest.raises(ipg.IpgError) as e:
+        g.run("cc", parts=_parts_tensor(u))
+    assert e.value.status == ipg.EUNSUPPORTED
+    with pytest.raises(ipg.IpgError) as e:
+        g.run("sssp", graph=True)
+    assert e.value.status == ipg.EUNSUPPORTED
+
+
+def test_pagerank_small_graph_family_full_size(ipg):
+    # The batched workload at full size: 64 directed R-MAT graphs, n
+    # log-uniform in [2^10, 2^16], edge factor 8, 20 updates, one graph launch.
+    graphs = graphgen.small_graph_family(64, seed=41)
+    u = graphgen.disjoint_union(graphs, name="family64")
+    g = ipg.Graph.from_host(u)
+    print(f"[batch] family64 n={u.n} m={u.m}", flush=True)
+    r, st = g.run("pagerank", 20, mode="pull", parts=_parts_tensor(u), graph=True)
+    _check_parts(u, graphs, r, 20)

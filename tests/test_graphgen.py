@@ -78,3 +78,24 @@ def test_pick_sources_distinct_and_eligible():
     src = graphgen.pick_sources(g, 64, seed=40)
     assert len(set(src.tolist())) == 64
     assert (np.diff(g.csr_off)[src] > 0).all()
+
+
+def test_disjoint_union_renumbers_and_records_parts():
+    from tests.graphs_small import edge_arrays, random_graph
+
+    gs = [random_graph(10, 30, seed=1), random_graph(7, 12, seed=2), random_graph(5, 0, seed=3)]
+    u = graphgen.disjoint_union(gs)
+    assert u.n == 22 and u.m == sum(g.m for g in gs)
+    assert u.meta["parts"].tolist() == [0, 10, 17, 22]
+    us, ud = edge_arrays(u)
+    base = 0
+    want_s, want_d = [], []
+    for g in gs:
+        s, d = edge_arrays(g)
+        want_s += list(s + base)
+        want_d += list(d + base)
+        base += g.n
+    assert us.tolist() == want_s and ud.tolist() == want_d
+    # CSC of the union is the union of the CSCs
+    cs = np.repeat(np.arange(u.n), np.diff(u.csc_off).astype(np.int64))
+    assert sorted(zip(u.csc_src.tolist(), cs.tolist())) == sorted(zip(us.tolist(), ud.tolist()))
