@@ -31,6 +31,68 @@ def pr_pull_bytes(n: int, m: int) -> int:
     return 4 * m + 8 * (n + 1) + 8 * n + 4 * n + 8 * n
 
 
+def batched_vs_plain(ipg, graphgen, np, torch, reps: int = 3) -> dict:
+    """End-to-end time of the batched workload against the plain form on the
+    same GPU: 256 unit-weight SSSP queries (sources seeded among vertices with
+    out-edges) on R-MAT scale 22 symmetrised, plus 64 directed R-MAT graphs
+    (2^10..2^16 vertices, edge factor 8) with 20 PageRank updates each.
+    Batched = one multi-source run + one graph launch over the union with
+    per-part N; plain = 256 single-source runs + 64 separate PageRank runs
+    (exchange chosen by the fixed heuristic).  Inputs resident before timing."""
+    hg = graphgen.workload("rmat-s22-sym")
+    src = graphgen.pick_sources(hg, 256, seed=40)
+    g = ipg.Graph.from_host(hg)
+    fam = graphgen.small_graph_family(64, seed=41)
+    u = graphgen.disjoint_union(fam, name="family64")
+    gu = ipg.Graph.from_host(u)
+    parts = torch.from_numpy(u.meta["parts"].astype(np.int32)).cuda()
+    gs = [ipg.Graph.from_host(h) for h in fam]
+    del hg
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+
+    d = torch.empty((256, g.n), dtype=torch.int32, device="cuda")
+    out = {}
+    st_b = {}
+
+    def b_sssp():
+        st_b["s"] = g.run_multi_sssp(src, out=d, timing=False)[1]
+
+    def p_sssp():
+        for s in src:
+            g.run("sssp", source=int(s), timing=False)
+
+    def b_pr():
+        gu.run("pagerank", 20, mode="pull", parts=parts, graph=True, timing=False)
+
+    def p_pr():
+        for h in gs:
+            h.run("pagerank", 20, mode="pull", timing=False)
+
+    t = {"b_sssp": timed(b_sssp), "p_sssp": timed(p_sssp), "b_pr": timed(b_pr), "p_pr": timed(p_pr)}
+    out["sssp256_rmat_s22"] = {"batched_ms": round(t["b_sssp"] * 1e3, 3), "plain_ms": round(t["p_sssp"] * 1e3, 3),
+                               "speedup": round(t["p_sssp"] / t["b_sssp"], 2),
+                               "supersteps": st_b["s"].supersteps,
+                               "edges_traversed": st_b["s"].edges_traversed}
+    out["pagerank64_family"] = {"batched_ms": round(t["b_pr"] * 1e3, 3), "plain_ms": round(t["p_pr"] * 1e3, 3),
+                                "speedup": round(t["p_pr"] / t["b_pr"], 2), "n": u.n, "m": u.m}
+    tb, tp = t["b_sssp"] + t["b_pr"], t["p_sssp"] + t["p_pr"]
+    out["end_to_end"] = {"batched_ms": round(tb * 1e3, 3), "plain_ms": round(tp * 1e3, 3),
+                         "speedup": round(tp / tb, 2)}
+    for h in gs + [g, gu]:
+        h.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -43,6 +105,8 @@ def main():
                     help="what AUTO uses to pick the exchange: the trained network or the fixed rule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apps", default="pagerank,cc,sssp")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-vs-plain comparison (256-source SSSP on R-MAT s22 + 64 small PageRank graphs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (to scale HBM byte counters), then exit")
     args = ap.parse_args()
@@ -138,6 +202,11 @@ def main():
             learned_vs_plain[app] = {"learned_ms": round(mine * 1e3, 4), "plain_ms": round(float(plain) * 1e3, 4),
                                      "speedup": round(float(plain) / mine, 4)}
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_vs_plain(ipg, graphgen, np, torch)
+        print(f"[bench] batched vs plain: {json.dumps(batched['end_to_end'])}", file=sys.stderr, flush=True)
+
     roofline = None
     if "pagerank" in apps and T >= 1:
         # average duration of one pull superstep (the long-row chunk launch
@@ -186,6 +255,7 @@ def main():
             "n": hg.n, "m": hg.m, "apps": apps_out,
         },
         "learned_vs_plain": learned_vs_plain,
+        "batched_vs_plain": batched,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -25,6 +25,8 @@ size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w) {
     r.outbox = c.take<uint32_t>(nn);
     r.list_ctr = c.take<uint32_t>(2);
     r.decision = c.take<Decision>(1);
+    r.ctl = c.take<DevCtl>(1);
+    r.rec = c.take<DevRec>(kDevRec);
   }
   r.ctr = c.take<CtrSlot>(2 * kCtrSlots);
   if (w) *w = r;
@@ -74,11 +76,8 @@ hipError_t StepTimer::finish(hipStream_t s) {
   return hipSuccess;
 }
 
-// Fixed heuristic (the default of Ligra's direction switch, Shun and
-// Blelloch 2013): pull when the frontier plus its out-edges exceed E/20.
 ipg_mode heuristic_mode(const ModeQuery& q) {
-  if (q.e == 0) return IPG_MODE_PUSH;
-  return (q.frontier + q.frontier_deg > q.e / 20) ? IPG_MODE_PULL : IPG_MODE_PUSH;
+  return static_cast<ipg_mode>(heuristic_pick(q.e, q.frontier, q.frontier_deg));
 }
 
 }  // namespace ipg

@@ -35,6 +35,32 @@ struct Decision {
 };
 static_assert(sizeof(Decision) == 64, "one 64-byte record");
 
+// Control block of the device-driven superstep loop (IPG_RUN_PERSISTENT):
+// the state the host loop keeps between supersteps, kept in device memory
+// and advanced by the decide kernel at the end of every superstep.  The
+// exchange kernels of a superstep read it and return at once when the run
+// has halted or the superstep uses the other exchange.
+struct DevCtl {
+  uint32_t step;      // superstep about to run
+  uint32_t halted;    // 1 once the run has ended
+  int32_t status;     // IPG_OK, IPG_NOT_CONVERGED, IPG_EOVERFLOW or IPG_EDEVICE once halted
+  int32_t mode;       // exchange of the superstep about to run
+  uint32_t list_ok;   // its active set is the frontier list (else: the non-empty mailboxes)
+  uint32_t cap;       // superstep cap, 0 = none
+  unsigned long long count;   // active vertices of the superstep about to run
+  unsigned long long degsum;  // their out-degree sum
+  unsigned long long t_last;  // device wall clock at the end of the previous superstep
+  unsigned long long pad[2];
+};
+static_assert(sizeof(DevCtl) == 64, "one 64-byte block");
+
+// One superstep's trace record, written by the decide kernel.
+struct DevRec {
+  unsigned long long active, senders, messages, examined, frontier_deg, ticks;
+  uint32_t mode, pad;
+};
+constexpr uint32_t kDevRec = 256;  // ring of records; a chunk of supersteps never exceeds it
+
 // Sum the counter slots `c` of a superstep into *out (one wavefront) and,
 // with a selector, choose the exchange of the next superstep.
 hipError_t launch_decide(const CtrSlot* c, uint32_t next_superstep, uint64_t e, const double* sel, Decision* out,
@@ -57,6 +83,8 @@ struct RunWs {
   uint32_t* outbox;     // [n] one-slot outbox of the pull form: the broadcast value, INF if none
   uint32_t* list_ctr;   // [2] next-frontier list length (push form), slot s & 1
   struct Decision* decision;  // end-of-superstep summary read by the host
+  DevCtl* ctl;          // device-driven loop state
+  DevRec* rec;          // [kDevRec] device-driven loop trace ring
   // both
   CtrSlot* ctr;         // [2][kCtrSlots] per-superstep counters (set s & 1)
 };
@@ -92,7 +120,13 @@ struct ModeQuery {
   uint32_t superstep;
   ipg_app app;
 };
-// Fixed heuristic used when no selector is given.
+// Fixed heuristic used when no selector is given (the default of Ligra's
+// direction switch, Shun and Blelloch 2013): pull when the frontier plus its
+// out-edges exceed E/20.
+__host__ __device__ inline int heuristic_pick(uint64_t e, uint64_t frontier, uint64_t frontier_deg) {
+  if (e == 0) return IPG_MODE_PUSH;
+  return (frontier + frontier_deg > e / 20) ? IPG_MODE_PULL : IPG_MODE_PUSH;
+}
 ipg_mode heuristic_mode(const ModeQuery& q);
 
 ipg_status run_pagerank(ipg_graph* g, uint32_t T, const ipg_run_opts& o, const RunWs& w, const void* ws,

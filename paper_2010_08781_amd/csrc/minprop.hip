@@ -107,45 +107,68 @@ struct MinPushArgs {
   uint32_t* list_ctr;
   CtrSlot* ctr;
   CtrSlot* ctr_clear;
+  const DevCtl* ctl;    // device-driven loop: active set and exchange from here (else null)
+  uint32_t n;
 };
 
+// Active set of a device-driven superstep s >= 1: the list left by a push
+// superstep, or the non-empty mailboxes.
+__device__ __forceinline__ Active device_active(const DevCtl& c, const uint32_t* list, uint32_t n) {
+  Active act;
+  act.phase = c.list_ok ? kStepList : kStepDense;
+  act.count = c.list_ok ? static_cast<uint32_t>(c.count) : n;
+  act.list = list;
+  act.source = 0;
+  return act;
+}
+
 // Fused compute + push scatter of one superstep: one thread per active
-// vertex, out-edges expanded by twc_scatter.  Recipients whose mailbox was
-// empty are appended to the next-frontier list by wave-ballot compaction
-// (one global atomic per wave and ballot).
+// vertex (grid-stride in workgroup-uniform rounds), out-edges expanded by
+// twc_scatter.  Recipients whose mailbox was empty are appended to the
+// next-frontier list by wave-ballot compaction (one global atomic per wave
+// and ballot).
 template <int APP, bool W>
 __global__ __launch_bounds__(kBlock) void minprop_push_kernel(MinPushArgs a) {
+  Active act = a.act;
+  if (a.ctl) {
+    const DevCtl c = *a.ctl;
+    if (c.halted || c.mode != IPG_MODE_PUSH) return;  // uniform over the grid
+    act = device_active(c, a.act.list, a.n);
+  }
   clear_slots(a.ctr_clear);
-  const uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x;
-  bool has = false;
-  uint64_t beg = 0, end = 0;
-  uint32_t msg = 0;
   uint64_t senders = 0, messages = 0, next_count = 0, next_deg = 0;
   uint32_t overflow = 0;
-  if (i < a.act.count) {
-    const uint32_t v = active_vertex(a.act, i);
-    has = compute_min(a.act.phase, v, a.value, a.mail_in, msg);
-    if (has) {
-      beg = a.off[v];
-      end = a.off[v + 1];
-      senders = 1;
-      messages = end - beg;
-    }
-  }
   uint32_t* mail = a.mail_out;
-  twc_scatter(has, beg, end, msg, [&](uint64_t e, uint32_t p) {
-    const uint32_t x = static_cast<uint32_t>(a.dst[e]);
-    uint64_t m = p;
-    if (APP == IPG_APP_SSSP) m += W ? a.w[e] : 1u;
-    bool fresh = false;
-    if (m >= kInf) overflow = 1;
-    else fresh = atomicMin(mail + x, static_cast<uint32_t>(m)) == kInf;
-    wave_append(fresh, x, a.list_out, a.list_ctr);
-    if (fresh) {
-      next_count += 1;
-      next_deg += a.outdeg[x];
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t base = blockIdx.x * (uint64_t)kBlock; base < act.count; base += stride) {
+    const uint64_t i = base + threadIdx.x;
+    bool has = false;
+    uint64_t beg = 0, end = 0;
+    uint32_t msg = 0;
+    if (i < act.count) {
+      const uint32_t v = active_vertex(act, i);
+      has = compute_min(act.phase, v, a.value, a.mail_in, msg);
+      if (has) {
+        beg = a.off[v];
+        end = a.off[v + 1];
+        senders += 1;
+        messages += end - beg;
+      }
     }
-  });
+    twc_scatter(has, beg, end, msg, [&](uint64_t e, uint32_t p) {
+      const uint32_t x = static_cast<uint32_t>(a.dst[e]);
+      uint64_t m = p;
+      if (APP == IPG_APP_SSSP) m += W ? a.w[e] : 1u;
+      bool fresh = false;
+      if (m >= kInf) overflow = 1;
+      else fresh = atomicMin(mail + x, static_cast<uint32_t>(m)) == kInf;
+      wave_append(fresh, x, a.list_out, a.list_ctr);
+      if (fresh) {
+        next_count += 1;
+        next_deg += a.outdeg[x];
+      }
+    });
+  }
   flush_counters(a.ctr, senders, messages, next_count, next_deg, overflow);
 }
 
@@ -154,8 +177,10 @@ struct MinApplyArgs {
   const uint32_t* outdeg;
   uint32_t* value;
   uint32_t* mail_in;
-  uint32_t* outbox;  // all INF on entry
+  uint32_t* outbox;  // all INF on entry (host-driven loop)
   CtrSlot* ctr;
+  const DevCtl* ctl;  // device-driven loop: sweep all N and write every outbox slot (else null)
+  uint32_t n;
 };
 
 // Compute phase of a pull superstep: consume the mailboxes of the active
@@ -163,16 +188,25 @@ struct MinApplyArgs {
 // outbox (Section 4.3.2: one broadcast value per vertex, read by the
 // out-neighbours).
 __global__ __launch_bounds__(kBlock) void minprop_apply_kernel(MinApplyArgs a) {
+  Active act = a.act;
+  if (a.ctl) {
+    const DevCtl c = *a.ctl;
+    if (c.halted || c.mode != IPG_MODE_PULL) return;
+    act.phase = kStepDense;
+    act.count = a.n;
+  }
   uint64_t senders = 0, messages = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < a.act.count; i += stride) {
-    const uint32_t v = active_vertex(a.act, i);
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < act.count; i += stride) {
+    const uint32_t v = active_vertex(act, i);
     uint32_t msg;
-    if (compute_min(a.act.phase, v, a.value, a.mail_in, msg)) {
-      a.outbox[v] = msg;
+    const bool sends = compute_min(act.phase, v, a.value, a.mail_in, msg);
+    if (sends) {
       senders += 1;
       messages += a.outdeg[v];
     }
+    if (sends) a.outbox[v] = msg;
+    else if (a.ctl) a.outbox[v] = kInf;
   }
   flush_counters(a.ctr, senders, messages, 0, 0, 0);
 }
@@ -185,6 +219,7 @@ struct MinPullArgs {
   uint32_t* mail_out;
   CtrSlot* ctr;
   CtrSlot* ctr_clear;
+  const DevCtl* ctl;       // device-driven loop: run only when it chose pull (else null)
 };
 
 // The message an in-edge carries: the source's broadcast value o (CC), plus
@@ -215,6 +250,7 @@ __global__ __launch_bounds__(kBlock) void minprop_pull_kernel(MinPullArgs a) {
   constexpr int kRowPer = (kItemRows + kWave) / kWave;
   __shared__ uint32_t s_tile[kWavesPerBlock][kWaveTile];
   __shared__ uint32_t s_off[kWavesPerBlock][kItemRows + 1];
+  if (a.ctl && (a.ctl->halted || a.ctl->mode != IPG_MODE_PULL)) return;  // uniform over the grid
   clear_slots(a.ctr_clear);
   const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
   uint32_t* tile = s_tile[wv];
@@ -324,6 +360,81 @@ __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_
   }
 }
 
+// Start of a device-driven run: the state before superstep 0.
+__global__ void dd_start_kernel(DevCtl* ctl, int mode, uint64_t count, uint64_t degsum, uint32_t cap) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    DevCtl c{};
+    c.mode = mode;
+    c.cap = cap;
+    c.count = count;
+    c.degsum = degsum;
+    c.t_last = static_cast<unsigned long long>(wall_clock64());
+    *ctl = c;
+  }
+}
+
+// End of a device-driven superstep: sum the counter slots, record the
+// superstep, and decide on the device what the host loop decides -- halt
+// (no message pending, an overflow, the cap) and, otherwise, the active set
+// and the exchange of the next superstep (forced, the selector, or the fixed
+// heuristic).  Does nothing once the run has halted.
+__global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint32_t* lc, uint64_t e, uint32_t n,
+                                                          const double* sel, int forced, uint64_t list_limit,
+                                                          DevCtl* ctl, DevRec* rec) {
+  static_assert(kCtrSlots == kWave, "one slot per lane");
+  const unsigned long long now = static_cast<unsigned long long>(wall_clock64());
+  const DevCtl k = *ctl;
+  if (k.halted) return;
+  const CtrSlot& x = c[threadIdx.x];
+  const uint64_t nc = wave_sum_u64(x.next_count);
+  const uint64_t se = wave_sum_u64(x.senders);
+  const uint64_t me = wave_sum_u64(x.messages);
+  const uint64_t nd = wave_sum_u64(x.next_deg);
+  const bool ovf = __ballot(x.overflow != 0) != 0;
+  if (threadIdx.x != 0) return;
+  const uint32_t s = k.step;
+  DevRec r;
+  r.active = s == 0 ? n : k.count;
+  r.senders = se;
+  r.messages = me;
+  r.examined = k.mode == IPG_MODE_PUSH ? me : e;
+  r.frontier_deg = k.degsum;
+  r.ticks = now - k.t_last;
+  r.mode = static_cast<uint32_t>(k.mode);
+  r.pad = 0;
+  rec[s % kDevRec] = r;
+  const uint32_t lcount = *lc;
+  *lc = 0;  // the counter is reused two supersteps later
+  DevCtl nk = k;
+  nk.step = s + 1;
+  nk.t_last = now;
+  nk.count = nc;
+  nk.degsum = nd;
+  nk.list_ok = (k.mode == IPG_MODE_PUSH && nc <= list_limit) ? 1u : 0u;
+  if (ovf) {
+    nk.halted = 1;
+    nk.status = IPG_EOVERFLOW;
+  } else if (nc == 0) {
+    nk.halted = 1;
+    nk.status = IPG_OK;
+  } else if (k.cap && s + 1 >= k.cap) {
+    nk.halted = 1;
+    nk.status = IPG_NOT_CONVERGED;
+  } else if (k.mode == IPG_MODE_PUSH && lcount != nc) {
+    nk.halted = 1;
+    nk.status = IPG_EDEVICE;
+  } else if (forced) {
+    nk.mode = forced;
+  } else if (sel) {
+    int m = IPG_MODE_PUSH;
+    sel_predict_mode(sel, nc, nd, s + 1, e, &m);
+    nk.mode = m;
+  } else {
+    nk.mode = heuristic_pick(e, nc, nd);
+  }
+  *ctl = nk;
+}
+
 // ------------------------------------------------------------------ host --
 
 hipError_t launch_decide(const CtrSlot* c, uint32_t next_superstep, uint64_t e, const double* sel, Decision* out,
@@ -333,9 +444,8 @@ hipError_t launch_decide(const CtrSlot* c, uint32_t next_superstep, uint64_t e, 
 }
 
 template <int APP, bool W>
-static hipError_t launch_push(const MinPushArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((minprop_push_kernel<APP, W>), dim3(grid_for(a.act.count, kBlock, 0xFFFFFFFFu)), dim3(kBlock), 0, s,
-                     a);
+static hipError_t launch_push(const MinPushArgs& a, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL((minprop_push_kernel<APP, W>), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 template <int APP, bool W>
@@ -345,9 +455,9 @@ static hipError_t launch_pull(const MinPullArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-static hipError_t push_dispatch(ipg_app app, bool weighted, const MinPushArgs& a, hipStream_t s) {
-  if (app == IPG_APP_CC_HASHMIN) return launch_push<IPG_APP_CC_HASHMIN, false>(a, s);
-  return weighted ? launch_push<IPG_APP_SSSP, true>(a, s) : launch_push<IPG_APP_SSSP, false>(a, s);
+static hipError_t push_dispatch(ipg_app app, bool weighted, const MinPushArgs& a, uint32_t grid, hipStream_t s) {
+  if (app == IPG_APP_CC_HASHMIN) return launch_push<IPG_APP_CC_HASHMIN, false>(a, grid, s);
+  return weighted ? launch_push<IPG_APP_SSSP, true>(a, grid, s) : launch_push<IPG_APP_SSSP, false>(a, grid, s);
 }
 static hipError_t pull_dispatch(ipg_app app, bool weighted, const MinPullArgs& a, hipStream_t s) {
   if (app == IPG_APP_CC_HASHMIN) return launch_pull<IPG_APP_CC_HASHMIN, false>(a, s);
@@ -358,14 +468,104 @@ static hipError_t pull_dispatch(ipg_app app, bool weighted, const MinPullArgs& a
 // by sweeping the mailboxes.
 static uint64_t list_limit(uint32_t n) { return std::max<uint64_t>(4096, n / 16); }
 
-ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_opts& o, const RunWs& w,
-                       hipStream_t s, StepTimer& tm, ipg_run_stats* st) {
+// Ping-pong buffers of superstep `step`.
+struct StepBufs {
+  CtrSlot* c;    // this superstep's counters
+  CtrSlot* cc;   // the next superstep's counters (cleared by this superstep's exchange)
+  uint32_t* lc;  // this superstep's list length
+  uint32_t *fin, *fout, *mail_in, *mail_out;
+};
+static StepBufs bufs_for(const RunWs& w, uint32_t step) {
+  const bool odd = step & 1;
+  StepBufs b;
+  b.c = w.ctr + (odd ? kCtrSlots : 0);
+  b.cc = w.ctr + (odd ? 0 : kCtrSlots);
+  b.lc = w.list_ctr + (odd ? 1 : 0);
+  b.fin = odd ? w.fr_b : w.fr_a;
+  b.fout = odd ? w.fr_a : w.fr_b;
+  b.mail_in = odd ? w.mail_b : w.mail_a;
+  b.mail_out = odd ? w.mail_a : w.mail_b;
+  return b;
+}
+
+// The launches of one superstep.  With ctl == null the exchange is `mode`
+// and the active set `act` (host-driven loop, and superstep 0); with a
+// control block (device-driven superstep s >= 1) both exchanges are
+// launched on fixed grids and the control block picks one.
+static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint32_t step, ipg_mode mode,
+                               const Active& act, const RunWs& w, const DevCtl* ctl, hipStream_t s) {
   const uint32_t n = g->n;
-  const uint64_t e = g->e;
   const bool weighted = app == IPG_APP_SSSP && g->csr_w != nullptr;
   const uint32_t gv = grid_for(n, kBlock, 16384);
+  const StepBufs b = bufs_for(w, step);
+  const bool device = ctl != nullptr;
+  if (step == 0) {
+    hipLaunchKernelGGL(minprop_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, static_cast<int>(app), source,
+                       w.value_u32, g->t.outdeg, mode == IPG_MODE_PULL ? 1 : 0, w.outbox, b.c);
+    IPG_HIP(hipGetLastError());
+  }
+  if (device || mode == IPG_MODE_PUSH) {
+    MinPushArgs a;
+    a.act = act;
+    a.act.list = b.fin;
+    a.off = g->csr_off;
+    a.dst = g->csr_dst;
+    a.w = weighted ? g->csr_w : nullptr;
+    a.outdeg = g->t.outdeg;
+    a.value = w.value_u32;
+    a.mail_in = b.mail_in;
+    a.mail_out = b.mail_out;
+    a.list_out = b.fout;
+    a.list_ctr = b.lc;
+    a.ctr = b.c;
+    a.ctr_clear = b.cc;
+    a.ctl = ctl;
+    a.n = n;
+    const uint32_t grid = device ? kExchangeGrid : grid_for(act.count, kBlock, 0xFFFFFFFFu);
+    IPG_HIP(push_dispatch(app, weighted, a, grid, s));
+  }
+  if (device || mode == IPG_MODE_PULL) {
+    if (step > 0) {
+      if (!device) IPG_HIP(fill_u32(w.outbox, n, kInf, s));
+      MinApplyArgs ap;
+      ap.act = act;
+      ap.act.list = b.fin;
+      ap.outdeg = g->t.outdeg;
+      ap.value = w.value_u32;
+      ap.mail_in = b.mail_in;
+      ap.outbox = w.outbox;
+      ap.ctr = b.c;
+      ap.ctl = ctl;
+      ap.n = n;
+      const uint32_t grid = device ? gv : grid_for(act.count, kBlock, 8192);
+      hipLaunchKernelGGL(minprop_apply_kernel, dim3(grid), dim3(kBlock), 0, s, ap);
+      IPG_HIP(hipGetLastError());
+    }
+    MinPullArgs pa;
+    pa.t = pull_tiling(g);
+    pa.w = weighted ? g->csc_w : nullptr;
+    pa.outdeg = g->t.outdeg;
+    pa.outbox = w.outbox;
+    pa.mail_out = b.mail_out;
+    pa.ctr = b.c;
+    pa.ctr_clear = b.cc;
+    pa.ctl = ctl;
+    IPG_HIP(pull_dispatch(app, weighted, pa, s));
+  }
+  return IPG_OK;
+}
 
-  // Out-degree of the SSSP source, for the superstep-0 exchange choice.
+// State before superstep 0 shared by both loops: mailboxes empty, counters
+// zero, and the superstep-0 active set (every vertex for CC, the source for
+// SSSP) with its out-degree sum.
+struct MinStart {
+  uint64_t count, degsum;
+  int sel_mode;  // the selector's choice for superstep 0, 0 if none
+};
+static ipg_status start_minprop(ipg_graph* g, ipg_app app, const ipg_run_opts& o, const RunWs& w, hipStream_t s,
+                                MinStart* out) {
+  const uint32_t n = g->n;
+  const uint64_t e = g->e;
   uint64_t src_deg = 0;
   if (app == IPG_APP_SSSP) {
     uint64_t h[2];
@@ -377,97 +577,145 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
   IPG_HIP(fill_u32(w.mail_b, n, kInf, s));
   IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.ctr), 2 * kCtrSlots * sizeof(CtrSlot) / 4, 0, s));
   IPG_HIP(fill_u32(w.list_ctr, 2, 0, s));
-
-  uint32_t *fin = w.fr_a, *fout = w.fr_b, *min_ = w.mail_a, *mout = w.mail_b;
-  uint64_t count = app == IPG_APP_CC_HASHMIN ? n : 1;
-  uint64_t degsum = app == IPG_APP_CC_HASHMIN ? e : src_deg;
-  bool list_ok = false;  // fin holds the whole active set
-  uint32_t step = 0;
-  ipg_status status = IPG_OK;
-  uint64_t tot_msgs = 0, tot_exam = 0;
-  int next_sel_mode = 0;  // the selector's choice for the coming superstep
+  out->count = app == IPG_APP_CC_HASHMIN ? n : 1;
+  out->degsum = app == IPG_APP_CC_HASHMIN ? e : src_deg;
+  out->sel_mode = 0;
   if (o.mode == IPG_MODE_AUTO && o.selector) {
     double hp[kSelParams];
     IPG_HIP(hipMemcpyAsync(hp, o.selector, sizeof(hp), hipMemcpyDeviceToHost, s));
     IPG_HIP(hipStreamSynchronize(s));
-    sel_predict_mode(hp, count, degsum, 0, e, &next_sel_mode);
+    sel_predict_mode(hp, out->count, out->degsum, 0, e, &out->sel_mode);
   }
+  return IPG_OK;
+}
+
+static Active step0_active(ipg_app app, uint32_t n, uint32_t source) {
+  Active act;
+  act.source = source;
+  act.list = nullptr;
+  act.phase = app == IPG_APP_CC_HASHMIN ? kSendAll : kSendSource;
+  act.count = app == IPG_APP_CC_HASHMIN ? n : 1;
+  return act;
+}
+
+// Device-driven loop (IPG_RUN_PERSISTENT): the host enqueues supersteps in
+// chunks of growing length without reading anything back; the control
+// block decides halt, active set and exchange on the device, the kernels
+// of the supersteps after the halt return at once, and the host reads the
+// control block and the chunk's trace records once per chunk.
+static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_opts& o, const RunWs& w,
+                                     hipStream_t s, StepTimer& tm, ipg_run_stats* st) {
+  const uint32_t n = g->n;
+  const uint64_t e = g->e;
+  MinStart m0;
+  ipg_status rc = start_minprop(g, app, o, w, s, &m0);
+  if (rc != IPG_OK) return rc;
+  int khz = 0;
+  IPG_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g->device));
+  const double us_per_tick = khz > 0 ? 1e3 / khz : 0.0;
+  const double* sel = o.mode == IPG_MODE_AUTO ? o.selector : nullptr;
+  const int forced = o.mode == IPG_MODE_AUTO ? 0 : static_cast<int>(o.mode);
+  ipg_mode mode0 = o.mode;
+  if (mode0 == IPG_MODE_AUTO)
+    mode0 = m0.sel_mode ? static_cast<ipg_mode>(m0.sel_mode)
+                        : static_cast<ipg_mode>(heuristic_pick(e, m0.count, m0.degsum));
+  IPG_HIP(tm.start(s));
+  hipLaunchKernelGGL(dd_start_kernel, dim3(1), dim3(1), 0, s, w.ctl, static_cast<int>(mode0), m0.count, m0.degsum,
+                     cap);
+  IPG_HIP(hipGetLastError());
+  rc = enqueue_step(g, app, o.source, 0, mode0, step0_active(app, n, o.source), w, nullptr, s);
+  if (rc != IPG_OK) return rc;
+  uint32_t enqueued = 0;  // supersteps whose launches are in the stream, minus one
+  uint32_t recorded = 0;  // supersteps whose records were read
+  uint32_t chunk = 1;
+  DevCtl h{};
+  uint64_t tot_msgs = 0, tot_exam = 0;
+  std::vector<DevRec> recs(kDevRec);
+  for (;;) {
+    for (uint32_t k = 0; k < chunk; ++k) {
+      const uint32_t step = enqueued + k;
+      if (step > 0) {
+        Active unused{};
+        rc = enqueue_step(g, app, o.source, step, IPG_MODE_AUTO, unused, w, w.ctl, s);
+        if (rc != IPG_OK) return rc;
+      }
+      const StepBufs b = bufs_for(w, step);
+      hipLaunchKernelGGL(dd_decide_kernel, dim3(1), dim3(kWave), 0, s, b.c, b.lc, e, n, sel, forced, list_limit(n),
+                         w.ctl, w.rec);
+      IPG_HIP(hipGetLastError());
+    }
+    enqueued += chunk;
+    IPG_HIP(hipMemcpyAsync(&h, w.ctl, sizeof(h), hipMemcpyDeviceToHost, s));
+    IPG_HIP(hipMemcpyAsync(recs.data(), w.rec, kDevRec * sizeof(DevRec), hipMemcpyDeviceToHost, s));
+    IPG_HIP(hipStreamSynchronize(s));
+    for (; recorded < h.step; ++recorded) {
+      const DevRec& r = recs[recorded % kDevRec];
+      if (st && recorded < st->trace_cap) {
+        if (st->active) st->active[recorded] = r.active;
+        if (st->senders) st->senders[recorded] = r.senders;
+        if (st->messages) st->messages[recorded] = r.messages;
+        if (st->examined) st->examined[recorded] = r.examined;
+        if (st->mode) st->mode[recorded] = static_cast<uint8_t>(r.mode);
+        if (st->frontier_deg) st->frontier_deg[recorded] = r.frontier_deg;
+        // device time of the superstep, between the wall-clock stamps of two decide kernels
+        if (st->usec) st->usec[recorded] = static_cast<float>(r.ticks * us_per_tick);
+      }
+      tot_msgs += r.messages;
+      tot_exam += r.examined;
+    }
+    if (h.halted) break;
+    chunk = std::min<uint32_t>(chunk * 2, 64);
+  }
+  IPG_HIP(tm.finish(s));
+  if (st) {
+    st->supersteps = h.step;
+    st->halted = h.status == IPG_OK;
+    st->edges_traversed = tot_msgs;
+    st->edges_examined = tot_exam;
+  }
+  if (h.status == IPG_EOVERFLOW) return fail(IPG_EOVERFLOW, "SSSP distance would reach 0xFFFFFFFF (INF)");
+  if (h.status == IPG_EDEVICE) return fail(IPG_EDEVICE, "frontier list length disagrees with the mailbox count");
+  return static_cast<ipg_status>(h.status);
+}
+
+ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_opts& o, const RunWs& w,
+                       hipStream_t s, StepTimer& tm, ipg_run_stats* st) {
+  if (o.flags & IPG_RUN_PERSISTENT) return run_minprop_device(g, app, cap, o, w, s, tm, st);
+  const uint32_t n = g->n;
+  const uint64_t e = g->e;
+  MinStart m0;
+  ipg_status status = start_minprop(g, app, o, w, s, &m0);
+  if (status != IPG_OK) return status;
+  uint64_t count = m0.count, degsum = m0.degsum;
+  int next_sel_mode = m0.sel_mode;  // the selector's choice for the coming superstep
+  bool list_ok = false;             // the superstep's active set is the list left by a push
+  uint32_t step = 0;
+  uint64_t tot_msgs = 0, tot_exam = 0;
   IPG_HIP(tm.start(s));
   for (;;) {
     ModeQuery q{n, e, count, degsum, step, app};
     ipg_mode mode = o.mode;
     if (mode == IPG_MODE_AUTO) mode = next_sel_mode ? static_cast<ipg_mode>(next_sel_mode) : heuristic_mode(q);
-    CtrSlot* c = w.ctr + (step & 1) * kCtrSlots;
-    CtrSlot* cc = w.ctr + ((step + 1) & 1) * kCtrSlots;
-    uint32_t* lc = w.list_ctr + (step & 1);
+    const StepBufs b = bufs_for(w, step);
     Active act;
-    act.source = o.source;
-    act.list = fin;
     if (step == 0) {
-      act.phase = app == IPG_APP_CC_HASHMIN ? kSendAll : kSendSource;
-      act.count = app == IPG_APP_CC_HASHMIN ? n : 1;
-    } else if (list_ok) {
-      act.phase = kStepList;
-      act.count = static_cast<uint32_t>(count);
+      act = step0_active(app, n, o.source);
     } else {
-      act.phase = kStepDense;
-      act.count = n;
+      act.source = o.source;
+      act.list = b.fin;
+      act.phase = list_ok ? kStepList : kStepDense;
+      act.count = list_ok ? static_cast<uint32_t>(count) : n;
     }
-    if (mode == IPG_MODE_PUSH) {
-      if (step == 0) {
-        hipLaunchKernelGGL(minprop_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, static_cast<int>(app), o.source,
-                           w.value_u32, g->t.outdeg, 0, w.outbox, c);
-        IPG_HIP(hipGetLastError());
-      }
-      MinPushArgs a;
-      a.act = act;
-      a.off = g->csr_off;
-      a.dst = g->csr_dst;
-      a.w = weighted ? g->csr_w : nullptr;
-      a.outdeg = g->t.outdeg;
-      a.value = w.value_u32;
-      a.mail_in = min_;
-      a.mail_out = mout;
-      a.list_out = fout;
-      a.list_ctr = lc;
-      a.ctr = c;
-      a.ctr_clear = cc;
-      IPG_HIP(push_dispatch(app, weighted, a, s));
-    } else {
-      if (step == 0) {
-        hipLaunchKernelGGL(minprop_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, static_cast<int>(app), o.source,
-                           w.value_u32, g->t.outdeg, 1, w.outbox, c);
-        IPG_HIP(hipGetLastError());
-      } else {
-        IPG_HIP(fill_u32(w.outbox, n, kInf, s));
-        MinApplyArgs ap;
-        ap.act = act;
-        ap.outdeg = g->t.outdeg;
-        ap.value = w.value_u32;
-        ap.mail_in = min_;
-        ap.outbox = w.outbox;
-        ap.ctr = c;
-        hipLaunchKernelGGL(minprop_apply_kernel, dim3(grid_for(act.count, kBlock, 8192)), dim3(kBlock), 0, s, ap);
-        IPG_HIP(hipGetLastError());
-      }
-      MinPullArgs pa;
-      pa.t = pull_tiling(g);
-      pa.w = weighted ? g->csc_w : nullptr;
-      pa.outdeg = g->t.outdeg;
-      pa.outbox = w.outbox;
-      pa.mail_out = mout;
-      pa.ctr = c;
-      pa.ctr_clear = cc;
-      IPG_HIP(pull_dispatch(app, weighted, pa, s));
-    }
+    status = enqueue_step(g, app, o.source, step, mode, act, w, nullptr, s);
+    if (status != IPG_OK) return status;
     IPG_HIP(tm.step(s, step));
     const double* sel = o.mode == IPG_MODE_AUTO ? o.selector : nullptr;
-    IPG_HIP(launch_decide(c, step + 1, e, sel, w.decision, s));
+    IPG_HIP(launch_decide(b.c, step + 1, e, sel, w.decision, s));
     uint32_t lcount = 0;
     Decision h;
     IPG_HIP(hipMemcpyAsync(&h, w.decision, sizeof(h), hipMemcpyDeviceToHost, s));
-    IPG_HIP(hipMemcpyAsync(&lcount, lc, sizeof(lcount), hipMemcpyDeviceToHost, s));
-    IPG_HIP(fill_u32(lc, 1, 0, s));  // reused two supersteps later
+    IPG_HIP(hipMemcpyAsync(&lcount, b.lc, sizeof(lcount), hipMemcpyDeviceToHost, s));
+    IPG_HIP(fill_u32(b.lc, 1, 0, s));  // reused two supersteps later
     IPG_HIP(hipStreamSynchronize(s));
     const uint64_t examined = mode == IPG_MODE_PUSH ? h.messages : e;
     if (st && step < st->trace_cap) {
@@ -498,8 +746,6 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
     degsum = h.next_deg;
     next_sel_mode = h.mode;
     list_ok = mode == IPG_MODE_PUSH && count <= list_limit(n);
-    std::swap(fin, fout);
-    std::swap(min_, mout);
   }
   IPG_HIP(tm.finish(s));
   if (st) {
