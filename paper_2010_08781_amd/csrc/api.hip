@@ -23,7 +23,8 @@ size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w) {
     r.fr_a = c.take<uint32_t>(nn);
     r.fr_b = c.take<uint32_t>(nn);
     r.outbox = c.take<uint32_t>(nn);
-    r.list_ctr = c.take<uint32_t>(2);
+    r.list_ctr = c.take<uint32_t>(4);
+    r.hubs = c.take<Hub>(kHubCap);
     r.decision = c.take<Decision>(1);
     r.ctl = c.take<DevCtl>(1);
     r.rec = c.take<DevRec>(kDevRec);

@@ -66,6 +66,16 @@ constexpr uint32_t kDevRec = 256;  // ring of records; a chunk of supersteps nev
 hipError_t launch_decide(const CtrSlot* c, uint32_t next_superstep, uint64_t e, const double* sel, Decision* out,
                          hipStream_t s);
 
+// Senders with at least kHubDeg out-edges are not expanded by their own
+// workgroup in a push superstep: they go to a hub list (up to kHubCap per
+// superstep) whose edges a second launch spreads over the whole grid.
+constexpr uint32_t kHubDeg = 8192;
+constexpr uint32_t kHubCap = 4096;
+struct Hub {
+  unsigned long long beg, end;  // CSR edge range
+  uint32_t msg, pad;            // the value the hub broadcasts
+};
+
 // Run workspace, carved from the caller's device buffer.
 struct RunWs {
   // PageRank
@@ -81,7 +91,8 @@ struct RunWs {
   uint32_t* fr_a;       // [n] frontier list, ping
   uint32_t* fr_b;       // [n] pong
   uint32_t* outbox;     // [n] one-slot outbox of the pull form: the broadcast value, INF if none
-  uint32_t* list_ctr;   // [2] next-frontier list length (push form), slot s & 1
+  uint32_t* list_ctr;   // [4] next-frontier list length (push form) at s & 1, hub count at 2 + (s & 1)
+  Hub* hubs;            // [kHubCap] hub senders of a push superstep
   struct Decision* decision;  // end-of-superstep summary read by the host
   DevCtl* ctl;          // device-driven loop state
   DevRec* rec;          // [kDevRec] device-driven loop trace ring

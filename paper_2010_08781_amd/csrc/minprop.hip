@@ -109,7 +109,28 @@ struct MinPushArgs {
   CtrSlot* ctr_clear;
   const DevCtl* ctl;    // device-driven loop: active set and exchange from here (else null)
   uint32_t n;
+  Hub* hubs;            // hub senders (see kHubDeg), or null to expand every sender in place
+  uint32_t* hub_ctr;
 };
+
+// One message of a push exchange along CSR edge e: the combiner (atomic
+// min into the recipient's next mailbox), the frontier append of a first
+// message, and the counters.
+template <int APP, bool W>
+__device__ __forceinline__ void push_edge(const MinPushArgs& a, uint64_t e, uint32_t p, uint64_t& next_count,
+                                          uint64_t& next_deg, uint32_t& overflow) {
+  const uint32_t x = static_cast<uint32_t>(a.dst[e]);
+  uint64_t m = p;
+  if (APP == IPG_APP_SSSP) m += W ? a.w[e] : 1u;
+  bool fresh = false;
+  if (m >= kInf) overflow = 1;
+  else fresh = atomicMin(a.mail_out + x, static_cast<uint32_t>(m)) == kInf;
+  wave_append(fresh, x, a.list_out, a.list_ctr);
+  if (fresh) {
+    next_count += 1;
+    next_deg += a.outdeg[x];
+  }
+}
 
 // Active set of a device-driven superstep s >= 1: the list left by a push
 // superstep, or the non-empty mailboxes.
@@ -138,7 +159,6 @@ __global__ __launch_bounds__(kBlock) void minprop_push_kernel(MinPushArgs a) {
   clear_slots(a.ctr_clear);
   uint64_t senders = 0, messages = 0, next_count = 0, next_deg = 0;
   uint32_t overflow = 0;
-  uint32_t* mail = a.mail_out;
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   for (uint64_t base = blockIdx.x * (uint64_t)kBlock; base < act.count; base += stride) {
     const uint64_t i = base + threadIdx.x;
@@ -153,23 +173,83 @@ __global__ __launch_bounds__(kBlock) void minprop_push_kernel(MinPushArgs a) {
         end = a.off[v + 1];
         senders += 1;
         messages += end - beg;
+        if (a.hubs && end - beg >= kHubDeg) {
+          const uint32_t slot = atomicAdd(a.hub_ctr, 1u);
+          if (slot < kHubCap) {  // else: expanded here after all
+            Hub h;
+            h.beg = beg;
+            h.end = end;
+            h.msg = msg;
+            h.pad = 0;
+            a.hubs[slot] = h;
+            has = false;
+          }
+        }
       }
     }
     twc_scatter(has, beg, end, msg, [&](uint64_t e, uint32_t p) {
-      const uint32_t x = static_cast<uint32_t>(a.dst[e]);
-      uint64_t m = p;
-      if (APP == IPG_APP_SSSP) m += W ? a.w[e] : 1u;
-      bool fresh = false;
-      if (m >= kInf) overflow = 1;
-      else fresh = atomicMin(mail + x, static_cast<uint32_t>(m)) == kInf;
-      wave_append(fresh, x, a.list_out, a.list_ctr);
-      if (fresh) {
-        next_count += 1;
-        next_deg += a.outdeg[x];
-      }
+      push_edge<APP, W>(a, e, p, next_count, next_deg, overflow);
     });
   }
   flush_counters(a.ctr, senders, messages, next_count, next_deg, overflow);
+}
+
+// Second launch of a push superstep: the out-edges of the hub senders,
+// concatenated (prefix of their degrees in LDS) and spread evenly over the
+// grid, one edge per thread and pass.
+template <int APP, bool W>
+__global__ __launch_bounds__(kBlock) void minprop_hub_kernel(MinPushArgs a) {
+  __shared__ unsigned long long s_pre[kHubCap + 1];
+  __shared__ unsigned long long s_part[kBlock];
+  if (a.ctl) {
+    const DevCtl c = *a.ctl;
+    if (c.halted || c.mode != IPG_MODE_PUSH) return;
+  }
+  const uint32_t H = min(*a.hub_ctr, kHubCap);
+  if (H == 0) return;  // uniform
+  constexpr uint32_t kPer = kHubCap / kBlock;
+  const uint32_t t = threadIdx.x;
+  unsigned long long own = 0;
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t h = t * kPer + k;
+    if (h < H) own += a.hubs[h].end - a.hubs[h].beg;
+  }
+  s_part[t] = own;
+  __syncthreads();
+  for (uint32_t o = 1; o < kBlock; o <<= 1) {  // inclusive scan of the per-thread sums
+    const unsigned long long y = t >= o ? s_part[t - o] : 0ull;
+    __syncthreads();
+    s_part[t] += y;
+    __syncthreads();
+  }
+  unsigned long long run = s_part[t] - own;
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t h = t * kPer + k;
+    if (h < H) {
+      s_pre[h] = run;
+      run += a.hubs[h].end - a.hubs[h].beg;
+    }
+  }
+  if (t == kBlock - 1) s_pre[H] = s_part[kBlock - 1];
+  __syncthreads();
+  const unsigned long long total = s_pre[H];
+  uint64_t next_count = 0, next_deg = 0;
+  uint32_t overflow = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t base = blockIdx.x * (uint64_t)kBlock; base < total; base += stride) {
+    const uint64_t j = base + t;
+    if (j < total) {
+      uint32_t lo = 0, hi = H - 1;  // last hub h with s_pre[h] <= j
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (s_pre[mid] <= j) lo = mid;
+        else hi = mid - 1;
+      }
+      const Hub& h = a.hubs[lo];
+      push_edge<APP, W>(a, h.beg + (j - s_pre[lo]), h.msg, next_count, next_deg, overflow);
+    }
+  }
+  flush_counters(a.ctr, 0, 0, next_count, next_deg, overflow);
 }
 
 struct MinApplyArgs {
@@ -340,6 +420,9 @@ __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_
   const uint64_t nd = wave_sum_u64(x.next_deg);
   const uint64_t ac = wave_sum_u64(x.active);
   const bool ovf = __ballot(x.overflow != 0) != 0;
+  int m = 0;
+  double margin = 0.0;
+  if (sel && nc) margin = sel_predict_mode_wave(sel, nc, nd, next_superstep, e, &m);  // whole wavefront
   if (threadIdx.x == 0) {
     Decision d;
     d.next_count = nc;
@@ -347,15 +430,10 @@ __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_
     d.messages = me;
     d.next_deg = nd;
     d.overflow = ovf ? 1u : 0u;
-    d.mode = 0;
-    d.margin = 0.0;
+    d.mode = m;
+    d.margin = margin;
     d.active = ac;
     d.pad = 0;
-    if (sel && nc) {
-      int m = 0;
-      d.margin = sel_predict_mode(sel, nc, nd, next_superstep, e, &m);
-      d.mode = m;
-    }
     *out = d;
   }
 }
@@ -378,7 +456,8 @@ __global__ void dd_start_kernel(DevCtl* ctl, int mode, uint64_t count, uint64_t 
 // (no message pending, an overflow, the cap) and, otherwise, the active set
 // and the exchange of the next superstep (forced, the selector, or the fixed
 // heuristic).  Does nothing once the run has halted.
-__global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint32_t* lc, uint64_t e, uint32_t n,
+__global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint32_t* lc, uint32_t* hc, uint64_t e,
+                                                          uint32_t n,
                                                           const double* sel, int forced, uint64_t list_limit,
                                                           DevCtl* ctl, DevRec* rec) {
   static_assert(kCtrSlots == kWave, "one slot per lane");
@@ -391,8 +470,11 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
   const uint64_t me = wave_sum_u64(x.messages);
   const uint64_t nd = wave_sum_u64(x.next_deg);
   const bool ovf = __ballot(x.overflow != 0) != 0;
-  if (threadIdx.x != 0) return;
   const uint32_t s = k.step;
+  int sel_mode = IPG_MODE_PUSH;
+  if (sel && !forced && nc && !ovf && !(k.cap && s + 1 >= k.cap))  // uniform: the whole wavefront infers
+    sel_predict_mode_wave(sel, nc, nd, s + 1, e, &sel_mode);
+  if (threadIdx.x != 0) return;
   DevRec r;
   r.active = s == 0 ? n : k.count;
   r.senders = se;
@@ -404,7 +486,8 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
   r.pad = 0;
   rec[s % kDevRec] = r;
   const uint32_t lcount = *lc;
-  *lc = 0;  // the counter is reused two supersteps later
+  *lc = 0;  // the counters are reused two supersteps later
+  *hc = 0;
   DevCtl nk = k;
   nk.step = s + 1;
   nk.t_last = now;
@@ -426,9 +509,7 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
   } else if (forced) {
     nk.mode = forced;
   } else if (sel) {
-    int m = IPG_MODE_PUSH;
-    sel_predict_mode(sel, nc, nd, s + 1, e, &m);
-    nk.mode = m;
+    nk.mode = sel_mode;
   } else {
     nk.mode = heuristic_pick(e, nc, nd);
   }
@@ -443,9 +524,15 @@ hipError_t launch_decide(const CtrSlot* c, uint32_t next_superstep, uint64_t e, 
   return hipGetLastError();
 }
 
+// Grid of the hub launch: enough passes-worth of threads for a few hubs.
+constexpr uint32_t kHubGrid = 1024;
+
 template <int APP, bool W>
-static hipError_t launch_push(const MinPushArgs& a, uint32_t grid, hipStream_t s) {
+static hipError_t launch_push(const MinPushArgs& a, uint32_t grid, bool hubs, hipStream_t s) {
   hipLaunchKernelGGL((minprop_push_kernel<APP, W>), dim3(grid), dim3(kBlock), 0, s, a);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess || !hubs) return err;
+  hipLaunchKernelGGL((minprop_hub_kernel<APP, W>), dim3(kHubGrid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 template <int APP, bool W>
@@ -455,9 +542,10 @@ static hipError_t launch_pull(const MinPullArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-static hipError_t push_dispatch(ipg_app app, bool weighted, const MinPushArgs& a, uint32_t grid, hipStream_t s) {
-  if (app == IPG_APP_CC_HASHMIN) return launch_push<IPG_APP_CC_HASHMIN, false>(a, grid, s);
-  return weighted ? launch_push<IPG_APP_SSSP, true>(a, grid, s) : launch_push<IPG_APP_SSSP, false>(a, grid, s);
+static hipError_t push_dispatch(ipg_app app, bool weighted, const MinPushArgs& a, uint32_t grid, bool hubs,
+                                hipStream_t s) {
+  if (app == IPG_APP_CC_HASHMIN) return launch_push<IPG_APP_CC_HASHMIN, false>(a, grid, hubs, s);
+  return weighted ? launch_push<IPG_APP_SSSP, true>(a, grid, hubs, s) : launch_push<IPG_APP_SSSP, false>(a, grid, hubs, s);
 }
 static hipError_t pull_dispatch(ipg_app app, bool weighted, const MinPullArgs& a, hipStream_t s) {
   if (app == IPG_APP_CC_HASHMIN) return launch_pull<IPG_APP_CC_HASHMIN, false>(a, s);
@@ -473,6 +561,7 @@ struct StepBufs {
   CtrSlot* c;    // this superstep's counters
   CtrSlot* cc;   // the next superstep's counters (cleared by this superstep's exchange)
   uint32_t* lc;  // this superstep's list length
+  uint32_t* hc;  // this superstep's hub count
   uint32_t *fin, *fout, *mail_in, *mail_out;
 };
 static StepBufs bufs_for(const RunWs& w, uint32_t step) {
@@ -481,6 +570,7 @@ static StepBufs bufs_for(const RunWs& w, uint32_t step) {
   b.c = w.ctr + (odd ? kCtrSlots : 0);
   b.cc = w.ctr + (odd ? 0 : kCtrSlots);
   b.lc = w.list_ctr + (odd ? 1 : 0);
+  b.hc = w.list_ctr + (odd ? 3 : 2);
   b.fin = odd ? w.fr_b : w.fr_a;
   b.fout = odd ? w.fr_a : w.fr_b;
   b.mail_in = odd ? w.mail_b : w.mail_a;
@@ -493,7 +583,7 @@ static StepBufs bufs_for(const RunWs& w, uint32_t step) {
 // control block (device-driven superstep s >= 1) both exchanges are
 // launched on fixed grids and the control block picks one.
 static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint32_t step, ipg_mode mode,
-                               const Active& act, const RunWs& w, const DevCtl* ctl, hipStream_t s) {
+                               const Active& act, uint64_t degsum, const RunWs& w, const DevCtl* ctl, hipStream_t s) {
   const uint32_t n = g->n;
   const bool weighted = app == IPG_APP_SSSP && g->csr_w != nullptr;
   const uint32_t gv = grid_for(n, kBlock, 16384);
@@ -521,8 +611,13 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
     a.ctr_clear = b.cc;
     a.ctl = ctl;
     a.n = n;
+    // hub launch: always in the device-driven loop (it returns at once
+    // without hubs), else when the frontier's out-degrees could hold one
+    const bool hubs = device || degsum >= kHubDeg;
+    a.hubs = hubs ? w.hubs : nullptr;
+    a.hub_ctr = b.hc;
     const uint32_t grid = device ? kExchangeGrid : grid_for(act.count, kBlock, 0xFFFFFFFFu);
-    IPG_HIP(push_dispatch(app, weighted, a, grid, s));
+    IPG_HIP(push_dispatch(app, weighted, a, grid, hubs, s));
   }
   if (device || mode == IPG_MODE_PULL) {
     if (step > 0) {
@@ -576,7 +671,7 @@ static ipg_status start_minprop(ipg_graph* g, ipg_app app, const ipg_run_opts& o
   IPG_HIP(fill_u32(w.mail_a, n, kInf, s));
   IPG_HIP(fill_u32(w.mail_b, n, kInf, s));
   IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.ctr), 2 * kCtrSlots * sizeof(CtrSlot) / 4, 0, s));
-  IPG_HIP(fill_u32(w.list_ctr, 2, 0, s));
+  IPG_HIP(fill_u32(w.list_ctr, 4, 0, s));
   out->count = app == IPG_APP_CC_HASHMIN ? n : 1;
   out->degsum = app == IPG_APP_CC_HASHMIN ? e : src_deg;
   out->sel_mode = 0;
@@ -623,7 +718,7 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
   hipLaunchKernelGGL(dd_start_kernel, dim3(1), dim3(1), 0, s, w.ctl, static_cast<int>(mode0), m0.count, m0.degsum,
                      cap);
   IPG_HIP(hipGetLastError());
-  rc = enqueue_step(g, app, o.source, 0, mode0, step0_active(app, n, o.source), w, nullptr, s);
+  rc = enqueue_step(g, app, o.source, 0, mode0, step0_active(app, n, o.source), m0.degsum, w, nullptr, s);
   if (rc != IPG_OK) return rc;
   uint32_t enqueued = 0;  // supersteps whose launches are in the stream, minus one
   uint32_t recorded = 0;  // supersteps whose records were read
@@ -636,12 +731,12 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
       const uint32_t step = enqueued + k;
       if (step > 0) {
         Active unused{};
-        rc = enqueue_step(g, app, o.source, step, IPG_MODE_AUTO, unused, w, w.ctl, s);
+        rc = enqueue_step(g, app, o.source, step, IPG_MODE_AUTO, unused, 0, w, w.ctl, s);
         if (rc != IPG_OK) return rc;
       }
       const StepBufs b = bufs_for(w, step);
-      hipLaunchKernelGGL(dd_decide_kernel, dim3(1), dim3(kWave), 0, s, b.c, b.lc, e, n, sel, forced, list_limit(n),
-                         w.ctl, w.rec);
+      hipLaunchKernelGGL(dd_decide_kernel, dim3(1), dim3(kWave), 0, s, b.c, b.lc, b.hc, e, n, sel, forced,
+                         list_limit(n), w.ctl, w.rec);
       IPG_HIP(hipGetLastError());
     }
     enqueued += chunk;
@@ -706,7 +801,7 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
       act.phase = list_ok ? kStepList : kStepDense;
       act.count = list_ok ? static_cast<uint32_t>(count) : n;
     }
-    status = enqueue_step(g, app, o.source, step, mode, act, w, nullptr, s);
+    status = enqueue_step(g, app, o.source, step, mode, act, degsum, w, nullptr, s);
     if (status != IPG_OK) return status;
     IPG_HIP(tm.step(s, step));
     const double* sel = o.mode == IPG_MODE_AUTO ? o.selector : nullptr;
@@ -716,6 +811,7 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
     IPG_HIP(hipMemcpyAsync(&h, w.decision, sizeof(h), hipMemcpyDeviceToHost, s));
     IPG_HIP(hipMemcpyAsync(&lcount, b.lc, sizeof(lcount), hipMemcpyDeviceToHost, s));
     IPG_HIP(fill_u32(b.lc, 1, 0, s));  // reused two supersteps later
+    IPG_HIP(fill_u32(b.hc, 1, 0, s));
     IPG_HIP(hipStreamSynchronize(s));
     const uint64_t examined = mode == IPG_MODE_PUSH ? h.messages : e;
     if (st && step < st->trace_cap) {

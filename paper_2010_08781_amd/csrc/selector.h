@@ -51,4 +51,35 @@ __host__ __device__ inline double sel_predict_mode(const double* p, uint64_t fro
   return y[0] - y[1];
 }
 
+// The same prediction by a whole wavefront (every lane calls it and gets the
+// result): lane j < 16 computes hidden unit j of each layer, reading the
+// previous layer from the other lanes, and lanes 0 and 1 the two outputs.
+// Every unit is summed in the order of sel_forward1, so the result is the
+// same; the latency is that of one unit per layer instead of all of them.
+__device__ inline double sel_predict_mode_wave(const double* p, uint64_t frontier, uint64_t frontier_deg,
+                                               uint32_t superstep, uint64_t e, int* mode) {
+  const double* W1 = p;
+  const double* b1 = W1 + kSelH * kSelD;
+  const double* W2 = b1 + kSelH;
+  const double* b2 = W2 + kSelH * kSelH;
+  const double* W3 = b2 + kSelH;
+  const double* b3 = W3 + kSelK * kSelH;
+  double x[kSelD];
+  sel_features(frontier, frontier_deg, superstep, e, x);
+  const int lane = static_cast<int>(lane_id());
+  const int j = lane < kSelH ? lane : 0;
+  double z = b1[j];
+  for (int d = 0; d < kSelD; ++d) z += W1[j * kSelD + d] * x[d];
+  const double h1 = tanh(z);
+  double z2 = b2[j];
+  for (int l = 0; l < kSelH; ++l) z2 += W2[j * kSelH + l] * __shfl(h1, l);
+  const double h2 = tanh(z2);
+  const int k = lane < kSelK ? lane : 0;
+  double y = b3[k];
+  for (int l = 0; l < kSelH; ++l) y += W3[k * kSelH + l] * __shfl(h2, l);
+  const double y0 = __shfl(y, 0), y1 = __shfl(y, 1);
+  *mode = y1 < y0 ? IPG_MODE_PULL : IPG_MODE_PUSH;
+  return y0 - y1;
+}
+
 }  // namespace ipg

@@ -31,11 +31,16 @@ DEFAULT_PARAMS = os.path.join(HERE, "selector_params.json")
 def _graphs(kind: str):
     import graphgen
 
+    # Training graphs span the sizes of the workloads (up to ~67M edges) with
+    # seeds of their own; the held-out set includes the benchmark graphs
+    # themselves (R-MAT s20 seed 2, the 4096^2 grid seed 3).
     if kind == "train":
         specs = [("rmat", 15, 11, True), ("rmat", 16, 12, True), ("rmat", 17, 13, False), ("rmat", 18, 14, True),
-                 ("rmat", 19, 15, True), ("rmat", 18, 16, False), ("grid", 512, 17, None), ("grid", 1024, 18, None)]
+                 ("rmat", 19, 15, True), ("rmat", 18, 16, False), ("rmat", 21, 19, True), ("rmat", 20, 25, False),
+                 ("grid", 512, 17, None), ("grid", 1024, 18, None), ("grid", 2048, 20, None), ("grid", 4096, 24, None)]
     else:
-        specs = [("rmat", 19, 21, True), ("rmat", 17, 22, False), ("grid", 768, 23, None), ("rmat", 20, 2, True)]
+        specs = [("rmat", 19, 21, True), ("rmat", 17, 22, False), ("grid", 768, 23, None), ("rmat", 20, 2, True),
+                 ("grid", 4096, 3, None)]
     for s in specs:
         if s[0] == "rmat":
             yield f"rmat-s{s[1]}-{'sym' if s[3] else 'dir'}-seed{s[2]}", graphgen.rmat(s[1], 16, seed=s[2], symmetric=s[3])

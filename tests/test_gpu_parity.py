@@ -251,3 +251,26 @@ def test_small_workspace_rejected(ipg):
     ws, nbytes = g.workspace(1)
     rc = ipg.lib().ipg_run(g._h, 1, 1, 0, None, ws.data_ptr(), nbytes - 1, None, None)
     assert rc == ipg.EWORKSPACE
+
+
+def test_push_hub_senders(ipg):
+    # Senders with at least 8192 out-edges are expanded by the hub launch
+    # (edges spread over the grid); degrees on both sides of the threshold,
+    # several hubs in one superstep, and hubs reached in later supersteps.
+    rng = np.random.default_rng(5)
+    n = 60000
+    src, dst = [], []
+    for c, d in ((0, 8191), (1, 8192), (2, 20000), (3, 30000)):
+        leaves = rng.choice(np.arange(10, n), size=d, replace=False)
+        src += [c] * d
+        dst += leaves.tolist()
+    src += rng.integers(4, n, size=40000).tolist()
+    dst += rng.integers(4, n, size=40000).tolist()
+    hg = graphgen.from_edges(n, np.array(src), np.array(dst), symmetric=True, name="hubs")
+    assert (np.diff(hg.csr_off) >= 8192).sum() >= 3
+    for app, source in (("cc", 0), ("sssp", 2), ("sssp", 12345)):
+        check_min_app(ipg, hg, app, source=source)
+        ref = oracle.run_graph(app, hg, 0, source=source)
+        g = ipg.Graph.from_host(hg)
+        vals, st = g.run(app, source=source, mode="push", persistent=True)
+        assert np.array_equal(to_np(vals), ref.values) and np.array_equal(st.trace, ref.trace)
