@@ -34,7 +34,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-Wall",
-                               "-fPIC", "-shared", "-o", tmp, _SRC])
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -51,6 +51,8 @@ def _L():
         lib.orc_run.argtypes = [ctypes.c_int, ctypes.c_uint32, P, P, P, ctypes.c_uint32, ctypes.c_uint32,
                                 P, P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
         lib.orc_run.restype = ctypes.c_int
+        lib.orc_pagerank_deltas.argtypes = [ctypes.c_uint32, P, P, ctypes.c_uint32, P, P]
+        lib.orc_pagerank_deltas.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -90,6 +92,30 @@ def run(app, n: int, csr_off: np.ndarray, csr_dst: np.ndarray, param: int, sourc
     k = min(int(steps.value), trace_cap)
     return OracleResult(values=vals[:n], trace=trace[:k].copy(), supersteps=int(steps.value), status=int(st),
                         seconds=dt)
+
+
+def pagerank_deltas(n: int, csr_off, csr_dst, updates: int) -> np.ndarray:
+    """L1 change of every update of Fig. 8's PageRank: out[s] = sum_v
+    |r_s(v) - r_{s-1}(v)| for s = 1..updates (out[0] = 0)."""
+    off = np.ascontiguousarray(csr_off, dtype=np.uint64)
+    adj = np.ascontiguousarray(csr_dst, dtype=np.int32)
+    if adj.size == 0:
+        adj = np.zeros(1, dtype=np.int32)
+    vals = np.zeros(max(n, 1), dtype=np.float64)
+    d = np.zeros(updates + 1, dtype=np.float64)
+    st = _L().orc_pagerank_deltas(n, off.ctypes.data, adj.ctypes.data, updates, vals.ctypes.data, d.ctypes.data)
+    assert st == OK, st
+    return d
+
+
+def pagerank_converge(g, tol: float, max_updates: int):
+    """PageRank to convergence: stop after the first update s >= 1 whose L1
+    change is below tol (or after max_updates).  Returns (result of the
+    fixed run with T = that update, T, deltas)."""
+    d = pagerank_deltas(g.n, g.csr_off, g.csr_dst, max_updates)
+    below = np.flatnonzero(d[1:] < tol)
+    T = int(below[0]) + 1 if below.size else max_updates
+    return run_graph("pagerank", g, T), T, d
 
 
 def run_graph(app, g, param: int, source: int = 0, weighted: bool = True, trace_cap: int = 1 << 16):

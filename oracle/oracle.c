@@ -45,6 +45,7 @@
  *
  * Build: gcc -O2 -ffp-contract=off (no fast-math; IEEE round-to-nearest).
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -90,7 +91,7 @@ static void orc_send_sum(orc_fbox* next, uint32_t w, double m) {
 
 static int orc_pagerank(uint32_t n, const uint64_t* off, const int32_t* adj, uint32_t threshold,
                         uint32_t max_supersteps, double* value, uint64_t* trace, uint32_t trace_cap,
-                        uint32_t* supersteps_out) {
+                        uint32_t* supersteps_out, double* deltas) {
   const double initial_value = 1.0 / (double)n;
   const double ratio = 0.15 / (double)n;
   uint8_t* halted = calloc(n ? n : 1, 1);
@@ -100,6 +101,7 @@ static int orc_pagerank(uint32_t n, const uint64_t* off, const int32_t* adj, uin
   uint32_t s = 0;
   for (;; ++s) {
     uint64_t active = 0, senders = 0, messages = 0;
+    double l1 = 0.0; /* L1 change of this update, summed in ascending vertex order */
     for (uint32_t v = 0; v < n; ++v) {
       if (!(s == 0 || !halted[v] || in.has[v])) continue;
       halted[v] = 0;
@@ -110,7 +112,9 @@ static int orc_pagerank(uint32_t n, const uint64_t* off, const int32_t* adj, uin
       } else {
         double sum = 0.0;
         if (in.has[v]) sum += in.box[v]; /* at most one combined message */
+        const double old = value[v];
         value[v] = ratio + 0.85 * sum;
+        if (deltas) l1 += fabs(value[v] - old);
       }
       if (s < threshold) {
         /* broadcast(value / out_neighbour_count) */
@@ -132,6 +136,7 @@ static int orc_pagerank(uint32_t n, const uint64_t* off, const int32_t* adj, uin
       trace[3 * (uint64_t)s + 1] = senders;
       trace[3 * (uint64_t)s + 2] = messages;
     }
+    if (deltas) deltas[s] = l1;
     /* global synchronisation: next becomes the inbox, next is emptied */
     orc_fbox t = in;
     in = next;
@@ -286,7 +291,7 @@ int orc_run(int app, uint32_t n, const uint64_t* off, const int32_t* adj, const 
   if (!orc_check_graph(n, off, adj)) return ORC_EBADGRAPH;
   if (app == ORC_APP_PAGERANK) {
     if (n == 0) return ORC_EINVAL;
-    return orc_pagerank(n, off, adj, param, 0, (double*)values, trace, trace_cap, supersteps);
+    return orc_pagerank(n, off, adj, param, 0, (double*)values, trace, trace_cap, supersteps, NULL);
   }
   if (app == ORC_APP_CC) return orc_minprop(app, n, off, adj, NULL, 0, param, (uint32_t*)values, trace, trace_cap, supersteps);
   if (app == ORC_APP_SSSP) {
@@ -294,4 +299,21 @@ int orc_run(int app, uint32_t n, const uint64_t* off, const int32_t* adj, const 
     return orc_minprop(app, n, off, adj, w, source, param, (uint32_t*)values, trace, trace_cap, supersteps);
   }
   return ORC_EINVAL;
+}
+
+/*
+ * PageRank run to convergence (an extension the paper points to in Section
+ * 6.1: real PageRank stops once the ranks settle rather than after a fixed
+ * number of iterations).  Runs Fig. 8 for `threshold` updates and stores in
+ * deltas[s] (s = 1..threshold) the L1 change of update s, the sum over all
+ * vertices, in ascending id order, of |rank after s - rank after s-1|;
+ * deltas[0] = 0.  The caller picks the first update whose change is below
+ * its tolerance.
+ */
+int orc_pagerank_deltas(uint32_t n, const uint64_t* off, const int32_t* adj, uint32_t threshold, double* values,
+                        double* deltas) {
+  uint32_t steps = 0;
+  if (!off || (!adj && n && off[n]) || !values || !deltas || n == 0) return ORC_EINVAL;
+  if (!orc_check_graph(n, off, adj)) return ORC_EBADGRAPH;
+  return orc_pagerank(n, off, adj, threshold, 0, values, NULL, 0, &steps, deltas);
 }

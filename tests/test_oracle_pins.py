@@ -324,3 +324,55 @@ def test_bad_graph_rejected():
     assert oracle.run("cc", 2, off, np.array([1, 0], np.int32), 0).status == oracle.EBADGRAPH
     off = np.array([0, 1, 2], dtype=np.uint64)
     assert oracle.run("cc", 2, off, np.array([1, 2], np.int32), 0).status == oracle.EBADGRAPH
+
+
+# ----------------------------------------------- PageRank to convergence --
+
+def test_pr_deltas_exact_rationals():
+    # The L1 change of every update, from the exact rational iterates
+    # (3/20, 17/20), against the oracle's doubles.
+    g = random_graph(30, 120, seed=44, loops=True, dups=True)
+    n = g.n
+    s, d = edge_arrays(g)
+    deg = np.bincount(s, minlength=n)
+    r = [Fraction(1, n)] * n
+    exact = [Fraction(0)]
+    for _ in range(12):
+        acc = [Fraction(0)] * n
+        for u, v in zip(s.tolist(), d.tolist()):
+            acc[v] += r[u] / int(deg[u])
+        nr = [Fraction(3, 20) / n + Fraction(17, 20) * a for a in acc]
+        exact.append(sum(abs(a - b) for a, b in zip(nr, r)))
+        r = nr
+    got = oracle.pagerank_deltas(n, g.csr_off, g.csr_dst, 12)
+    ex = np.array([float(x) for x in exact])
+    assert got[0] == 0.0
+    assert np.all(np.abs(got[1:] - ex[1:]) <= 1e-13 * ex[1:] + 1e-18)
+
+
+def test_pr_deltas_contract_by_damping():
+    # r' = 0.15/N + 0.85 M r with column sums of M at most 1 (dangling mass is
+    # dropped), so ||r_{s+1} - r_s||_1 <= 0.85 ||r_s - r_{s-1}||_1.
+    for seed in (1, 2, 3):
+        g = random_graph(500, 3000, seed=seed)
+        d = oracle.pagerank_deltas(g.n, g.csr_off, g.csr_dst, 30)
+        assert np.all(d[2:] <= 0.85 * d[1:-1] * (1 + 1e-9) + 1e-18)
+        assert d[1] > 0
+
+
+def test_pr_deltas_cycle_is_stationary():
+    g = directed_cycle(64)
+    d = oracle.pagerank_deltas(g.n, g.csr_off, g.csr_dst, 5)
+    assert np.all(d <= 64 * 2.0 ** -52 / 64)
+
+
+def test_pr_converge_equals_fixed_run():
+    g = random_graph(400, 2400, seed=7)
+    res, T, d = oracle.pagerank_converge(g, 1e-6, 200)
+    assert 1 <= T < 200 and d[T] < 1e-6 and np.all(d[1:T] >= 1e-6)
+    fixed = oracle.run_graph("pagerank", g, T)
+    assert np.array_equal(res.values, fixed.values)
+    assert res.supersteps == T + 1
+    # never below the tolerance: runs the cap
+    _, T2, _ = oracle.pagerank_converge(g, 0.0, 15)
+    assert T2 == 15
