@@ -107,6 +107,13 @@ typedef struct {
    * and checked on every call; NULL / 0 = one part of N vertices. */
   const uint32_t* part_offsets;
   uint32_t num_parts;
+  /* PageRank to convergence when > 0: after every update s the L1 change
+   * sum_v |r_s(v) - r_{s-1}(v)| is reduced (ipg_run_stats.residual), and the
+   * run stops after the first update whose change is below `tolerance`
+   * (IPG_OK; the values are those of a run with T = that update), or after
+   * max_supersteps updates (IPG_NOT_CONVERGED, values valid).  max_supersteps
+   * must then be >= 1; not combinable with IPG_RUN_GRAPH.  0 = fixed T. */
+  double tolerance;
 } ipg_run_opts;
 
 /*
@@ -122,7 +129,8 @@ typedef struct {
  *   mode[s]     1 push, 2 pull,
  *   usec[s]     device time of superstep s (HIP events), when timing is on,
  *   frontier_deg[s]  sum of the out-degrees of the vertices active in s
- *               (the selector's second input).
+ *               (the selector's second input),
+ *   residual[s] PageRank run with a tolerance: the L1 change of update s.
  */
 typedef struct {
   uint32_t supersteps;      /* supersteps executed */
@@ -138,6 +146,7 @@ typedef struct {
   uint8_t* mode;
   float* usec;
   uint64_t* frontier_deg;
+  double* residual;         /* PageRank with a tolerance: L1 change of update s (entry 0 is 0) */
 } ipg_run_stats;
 
 /* Bytes of graph workspace ipg_graph_create needs for this graph size.  The

@@ -56,7 +56,8 @@ class _Desc(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("source", ctypes.c_uint32), ("mode", ctypes.c_int), ("flags", ctypes.c_uint32),
-                ("selector", ctypes.c_void_p), ("part_offsets", ctypes.c_void_p), ("num_parts", ctypes.c_uint32)]
+                ("selector", ctypes.c_void_p), ("part_offsets", ctypes.c_void_p), ("num_parts", ctypes.c_uint32),
+                ("tolerance", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -65,7 +66,7 @@ class _Stats(ctypes.Structure):
                 ("seconds", ctypes.c_double), ("trace_cap", ctypes.c_uint32),
                 ("active", ctypes.c_void_p), ("senders", ctypes.c_void_p), ("messages", ctypes.c_void_p),
                 ("examined", ctypes.c_void_p), ("mode", ctypes.c_void_p), ("usec", ctypes.c_void_p),
-                ("frontier_deg", ctypes.c_void_p)]
+                ("frontier_deg", ctypes.c_void_p), ("residual", ctypes.c_void_p)]
 
 
 _lib = None
@@ -142,6 +143,7 @@ class RunStats:
     mode: np.ndarray = field(repr=False)
     usec: Optional[np.ndarray] = field(repr=False, default=None)
     frontier_deg: Optional[np.ndarray] = field(repr=False, default=None)
+    residual: Optional[np.ndarray] = field(repr=False, default=None)
 
     @property
     def trace(self) -> np.ndarray:
@@ -161,10 +163,12 @@ class _Trace:
         self.a = {k: np.zeros(cap, dtype=np.uint64) for k in ("active", "senders", "messages", "examined", "frontier_deg")}
         self.a["mode"] = np.zeros(cap, dtype=np.uint8)
         self.usec = np.zeros(cap, dtype=np.float32) if timing else None
+        self.residual = np.zeros(cap, dtype=np.float64)
         a = self.a
         self.st = _Stats(0, 0, 0, 0, 0.0, cap, a["active"].ctypes.data, a["senders"].ctypes.data,
                          a["messages"].ctypes.data, a["examined"].ctypes.data, a["mode"].ctypes.data,
-                         self.usec.ctypes.data if self.usec is not None else None, a["frontier_deg"].ctypes.data)
+                         self.usec.ctypes.data if self.usec is not None else None, a["frontier_deg"].ctypes.data,
+                         self.residual.ctypes.data)
 
     def stats(self, rc: int) -> "RunStats":
         st, a = self.st, self.a
@@ -173,7 +177,8 @@ class _Trace:
         k = min(int(st.supersteps), self.cap)
         return RunStats(rc, int(st.supersteps), bool(st.halted), int(st.edges_traversed), int(st.edges_examined),
                         float(st.seconds), a["active"][:k], a["senders"][:k], a["messages"][:k], a["examined"][:k],
-                        a["mode"][:k], self.usec[:k] if self.usec is not None else None, a["frontier_deg"][:k])
+                        a["mode"][:k], self.usec[:k] if self.usec is not None else None, a["frontier_deg"][:k],
+                        self.residual[:k])
 
 
 class Graph:
@@ -254,13 +259,16 @@ class Graph:
 
     def run(self, app, max_supersteps: Optional[int] = None, source: int = 0, mode: str = "auto",
             timing: bool = True, trace_cap: int = 1 << 16, persistent: bool = False, stream=None,
-            combiner: Optional[int] = None, check: bool = True, selector=None, parts=None, graph: bool = False):
+            combiner: Optional[int] = None, check: bool = True, selector=None, parts=None, graph: bool = False,
+            tol: float = 0.0):
         """Run an application; returns (values tensor on the device, RunStats).
 
         max_supersteps: PageRank -> number of rank updates (default 10, Fig. 8);
         CC/SSSP -> cap on supersteps (default 0 = run to vote-to-halt).
         parts: PageRank over a disjoint union -- int32 CUDA tensor of part
-        vertex offsets (P+1 entries); graph: replay PageRank as one hipGraph."""
+        vertex offsets (P+1 entries); graph: replay PageRank as one hipGraph;
+        tol: PageRank to convergence (stop after the first update whose L1
+        change is below tol; max_supersteps caps the updates)."""
         import torch
 
         a = APPS[app] if isinstance(app, str) else int(app)
@@ -277,7 +285,8 @@ class Graph:
                 raise ValueError("parts must be a contiguous int32 CUDA tensor of P+1 offsets")
         flags = (RUN_PERSISTENT if persistent else 0) | (RUN_GRAPH if graph else 0)
         opts = _Opts(int(source), MODES[mode], flags, selector.data_ptr() if selector is not None else None,
-                     parts.data_ptr() if parts is not None else None, parts.numel() - 1 if parts is not None else 0)
+                     parts.data_ptr() if parts is not None else None, parts.numel() - 1 if parts is not None else 0,
+                     float(tol))
         tr = _Trace(trace_cap, timing)
         rc = lib().ipg_run(self._h, a, comb, int(max_supersteps), ctypes.byref(opts),
                            ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(stream),
@@ -307,7 +316,7 @@ class Graph:
             nb = lib().ipg_multi_sssp_workspace_bytes(self.n, self.m)
             self._run_ws[key] = (torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device), nb)
         ws, nbytes = self._run_ws[key]
-        opts = _Opts(0, MODES[mode], 0, None, None, 0)
+        opts = _Opts(0, MODES[mode], 0, None, None, 0, 0.0)
         tr = _Trace(trace_cap, timing)
         rc = lib().ipg_run_multi_sssp(self._h, src.data_ptr(), q, int(max_supersteps), ctypes.byref(opts),
                                       out.data_ptr(), out.numel() * 4, ws.data_ptr(), nbytes, _stream_handle(stream),

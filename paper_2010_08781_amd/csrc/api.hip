@@ -16,6 +16,7 @@ size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w) {
     r.f64_b = c.take<double>(nn);
     r.partial = c.take<double>(chunks_cap(e));
     r.part_n = c.take<uint32_t>(nn);
+    r.l1 = c.take<double>(kCtrSlots * 16);  // one 128-byte line per slot
   } else {
     r.value_u32 = c.take<uint32_t>(nn);
     r.mail_a = c.take<uint32_t>(nn);
@@ -98,7 +99,7 @@ extern "C" ipg_status ipg_run(ipg_graph* g, ipg_app app, ipg_combiner combiner, 
                        (app == IPG_APP_CC_HASHMIN && combiner == IPG_COMBINE_MIN) ||
                        (app == IPG_APP_SSSP && combiner == IPG_COMBINE_MIN);
   if (!ok_pair) return fail(IPG_EUNSUPPORTED, "ipg_run: (app, combiner) must be (PAGERANK, SUM), (CC, MIN) or (SSSP, MIN)");
-  ipg_run_opts o{0, IPG_MODE_AUTO, 0, nullptr, nullptr, 0};
+  ipg_run_opts o{0, IPG_MODE_AUTO, 0, nullptr, nullptr, 0, 0.0};
   if (opts) o = *opts;
   if (o.mode != IPG_MODE_AUTO && o.mode != IPG_MODE_PUSH && o.mode != IPG_MODE_PULL)
     return fail(IPG_EINVAL, "ipg_run: unknown mode");
@@ -108,6 +109,12 @@ extern "C" ipg_status ipg_run(ipg_graph* g, ipg_app app, ipg_combiner combiner, 
   if (o.num_parts && app != IPG_APP_PAGERANK)
     return fail(IPG_EUNSUPPORTED, "ipg_run: part_offsets apply to PageRank only");
   if (o.num_parts && !o.part_offsets) return fail(IPG_EINVAL, "ipg_run: num_parts without part_offsets");
+  if (o.tolerance != 0.0) {
+    if (app != IPG_APP_PAGERANK) return fail(IPG_EUNSUPPORTED, "ipg_run: a tolerance applies to PageRank only");
+    if (!(o.tolerance > 0.0)) return fail(IPG_EINVAL, "ipg_run: tolerance must be > 0");
+    if (max_supersteps == 0) return fail(IPG_EINVAL, "ipg_run: a tolerance needs max_supersteps >= 1 (cap on updates)");
+    if (o.flags & IPG_RUN_GRAPH) return fail(IPG_EUNSUPPORTED, "ipg_run: a tolerance cannot be combined with IPG_RUN_GRAPH");
+  }
   const size_t need = ipg_run_workspace_bytes(g->n, g->e, app);
   if (!ws || ws_bytes < need)
     return fail(IPG_EWORKSPACE, "ipg_run: run workspace needs " + std::to_string(need) + " bytes");

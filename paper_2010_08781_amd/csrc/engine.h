@@ -84,6 +84,7 @@ struct RunWs {
   double* f64_b;      // [n] pong
   double* partial;    // [chunks] partial sums of long-row chunks (pull)
   uint32_t* part_n;   // [n] vertex count of each vertex's part (disjoint unions)
+  double* l1;         // [kCtrSlots] L1 change of an update, spread over slots (convergence runs)
   // CC / SSSP
   uint32_t* value_u32;  // [n] labels or distances
   uint32_t* mail_a;     // [n] one-slot min mailboxes, ping (INF = empty)

@@ -33,22 +33,46 @@ struct PrPullArgs {
   double* partial;        // per long-row chunk
   double ratio;           // 0.15 / N
   const uint32_t* part_n; // vertex count of each vertex's part, or null (one part)
+  double* l1;             // convergence run: rank stored every update, its L1 change added here (else null)
   int last;               // superstep == T: store the rank, no broadcast
 };
+
+// The rank of v after this update: the outbox for the next update, the
+// stored rank when this is the last update, and both (plus the change of
+// the rank) in a convergence run.
+__device__ __forceinline__ void pr_store(const PrPullArgs& a, uint32_t v, double rank, uint32_t d, double& l1) {
+  if (a.l1) {
+    l1 += fabs(rank - a.value[v]);
+    a.value[v] = rank;
+  } else if (a.last) {
+    a.value[v] = rank;
+    return;
+  }
+  a.contrib_out[v] = d ? rank / static_cast<double>(d) : 0.0;
+}
+
+// Workgroup sum of the threads' L1 changes added to one of kCtrSlots
+// 128-byte slots (every thread must call).
+__device__ __forceinline__ void flush_l1(double* slots, double x) {
+  __shared__ double part[kWavesPerBlock];
+  x = wave_sum(x);
+  if (lane_id() == 0) part[threadIdx.x / kWave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < kWavesPerBlock; ++i) t += part[i];
+    if (t != 0.0) unsafeAtomicAdd(slots + (blockIdx.x % kCtrSlots) * 16, t);
+  }
+}
 
 // 0.15 / N for the part that holds v.
 __device__ __forceinline__ double pr_ratio(double ratio, const uint32_t* part_n, uint32_t v) {
   return part_n ? 0.15 / static_cast<double>(part_n[v]) : ratio;
 }
 
-__device__ __forceinline__ void pr_finish(const PrPullArgs& a, uint32_t v, double sum) {
+__device__ __forceinline__ void pr_finish(const PrPullArgs& a, uint32_t v, double sum, double& l1) {
   const double rank = pr_ratio(a.ratio, a.part_n, v) + 0.85 * sum;
-  if (a.last) {
-    a.value[v] = rank;
-  } else {
-    const uint32_t d = a.outdeg[v];
-    a.contrib_out[v] = d ? rank / static_cast<double>(d) : 0.0;
-  }
+  pr_store(a, v, rank, a.outdeg[v], l1);
 }
 
 // Sum over the workgroup in a fixed order; every thread gets the result.
@@ -85,6 +109,7 @@ __global__ __launch_bounds__(kBlock) void pr_items_kernel(PrPullArgs a) {
   const int32_t* src = a.t.src;
   const uint64_t* off = a.t.off;
   const uint32_t nw = gridDim.x * kWavesPerBlock;
+  double l1 = 0.0;
   for (uint32_t item = blockIdx.x * kWavesPerBlock + wv; item < a.t.ni; item += nw) {
     const PullItem it = a.t.items[item];
     const bool chunk = it.slot != kNoSlot;
@@ -137,16 +162,12 @@ __global__ __launch_bounds__(kBlock) void pr_items_kernel(PrPullArgs a) {
       if (li == 0 && row < nrows) {
         const uint32_t v = it.r0 + row;
         const double rank = pr_ratio(a.ratio, a.part_n, v) + 0.85 * s;
-        if (a.last) {
-          a.value[v] = rank;
-        } else {
-          const uint32_t d = sdeg[row];
-          a.contrib_out[v] = d ? rank / static_cast<double>(d) : 0.0;
-        }
+        pr_store(a, v, rank, sdeg[row], l1);
       }
     }
     wave_lds_sync();  // the tile is rewritten by the next item
   }
+  if (a.l1) flush_l1(a.l1, l1);
 }
 
 // Pull superstep, second launch: each long row adds its chunk partials in
@@ -154,12 +175,15 @@ __global__ __launch_bounds__(kBlock) void pr_items_kernel(PrPullArgs a) {
 // bitwise reproducible).
 __global__ __launch_bounds__(kBlock) void pr_longrow_kernel(PrPullArgs a) {
   const uint32_t l = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-  if (l >= a.t.nl) return;  // wave-uniform
-  const uint32_t f = a.t.lr_first[l], nch = a.t.lr_first[l + 1] - f;
-  double s = 0.0;
-  for (uint32_t i = lane_id(); i < nch; i += kWave) s += a.partial[f + i];
-  s = wave_sum(s);
-  if (lane_id() == 0) pr_finish(a, a.t.long_rows[l], s);
+  double l1 = 0.0;
+  if (l < a.t.nl) {  // wave-uniform
+    const uint32_t f = a.t.lr_first[l], nch = a.t.lr_first[l + 1] - f;
+    double s = 0.0;
+    for (uint32_t i = lane_id(); i < nch; i += kWave) s += a.partial[f + i];
+    s = wave_sum(s);
+    if (lane_id() == 0) pr_finish(a, a.t.long_rows[l], s, l1);
+  }
+  if (a.l1) flush_l1(a.l1, l1);
 }
 
 // 1 / N for the part that holds v.
@@ -167,15 +191,15 @@ __device__ __forceinline__ double pr_init(double init, const uint32_t* part_n, u
   return part_n ? 1.0 / static_cast<double>(part_n[v]) : init;
 }
 
-// Superstep 0 of the pull form: rank 1/N, outbox 1/N/outdeg.
+// Superstep 0 of the pull form: rank 1/N, outbox 1/N/outdeg (and the rank
+// itself when a convergence run tracks its changes).
 __global__ void pr_pull_init_kernel(uint32_t n, const uint32_t* outdeg, double init, const uint32_t* part_n,
-                                    double* contrib, double* value, int last) {
+                                    double* contrib, double* value, int last, int track) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
     const double x = pr_init(init, part_n, static_cast<uint32_t>(v));
-    if (last) {
-      value[v] = x;
-    } else {
+    if (last || track) value[v] = x;
+    if (!last) {
       const uint32_t d = outdeg[v];
       contrib[v] = d ? x / static_cast<double>(d) : 0.0;
     }
@@ -205,6 +229,7 @@ struct PrPushArgs {
   double* value;
   double ratio, init;
   const uint32_t* part_n;
+  double* l1;            // convergence run: rank stored every superstep, its L1 change added here
   int first, last;
 };
 
@@ -213,6 +238,7 @@ struct PrPushArgs {
 // out-neighbour's next mailbox.
 __global__ __launch_bounds__(kBlock) void pr_push_kernel(PrPushArgs a) {
   const uint64_t v = blockIdx.x * (uint64_t)kBlock + threadIdx.x;
+  double l1 = 0.0;
   bool has = false;
   uint64_t beg = 0, end = 0;
   double c = 0.0;
@@ -224,10 +250,10 @@ __global__ __launch_bounds__(kBlock) void pr_push_kernel(PrPushArgs a) {
       const double m = a.mail_in[v];
       a.mail_in[v] = 0.0;
       rank = pr_ratio(a.ratio, a.part_n, static_cast<uint32_t>(v)) + 0.85 * m;
+      if (a.l1) l1 += fabs(rank - a.value[v]);
     }
-    if (a.last) {
-      a.value[v] = rank;
-    } else {
+    if (a.last || a.l1) a.value[v] = rank;
+    if (!a.last) {
       beg = a.off[v];
       end = a.off[v + 1];
       has = end > beg;
@@ -237,6 +263,7 @@ __global__ __launch_bounds__(kBlock) void pr_push_kernel(PrPushArgs a) {
   double* mail = a.mail_out;
   const int32_t* dst = a.dst;
   twc_scatter(has, beg, end, c, [&](uint64_t e, double p) { unsafeAtomicAdd(mail + dst[e], p); });
+  if (a.l1) flush_l1(a.l1, l1);
 }
 
 // ------------------------------------------------------------------ host --
@@ -259,7 +286,7 @@ static hipError_t enqueue_pagerank(ipg_graph* g, uint32_t T, bool push, const Ru
   if (!push) {
     if (tm && (err = tm->start(s)) != hipSuccess) return err;
     hipLaunchKernelGGL(pr_pull_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, g->t.outdeg, init, part_n, w.f64_a,
-                       w.value_f64, T == 0);
+                       w.value_f64, T == 0, 0);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if (tm && (err = tm->step(s, 0)) != hipSuccess) return err;
     PrPullArgs a;
@@ -269,6 +296,7 @@ static hipError_t enqueue_pagerank(ipg_graph* g, uint32_t T, bool push, const Ru
     a.partial = w.partial;
     a.ratio = ratio;
     a.part_n = part_n;
+    a.l1 = nullptr;
     for (uint32_t step = 1; step <= T; ++step) {
       a.contrib_in = (step & 1) ? w.f64_a : w.f64_b;
       a.contrib_out = (step & 1) ? w.f64_b : w.f64_a;
@@ -296,6 +324,7 @@ static hipError_t enqueue_pagerank(ipg_graph* g, uint32_t T, bool push, const Ru
     a.ratio = ratio;
     a.init = init;
     a.part_n = part_n;
+    a.l1 = nullptr;
     const uint32_t grid = grid_for(n, kBlock, 0xFFFFFFFFu);
     for (uint32_t step = 0; step <= T; ++step) {
       a.mail_in = (step & 1) ? w.f64_b : w.f64_a;
@@ -348,6 +377,115 @@ static ipg_status pagerank_graph(ipg_graph* g, uint32_t T, bool push, const RunW
   return IPG_OK;
 }
 
+// PageRank to convergence: the same supersteps with every update's L1
+// change reduced on the device and read back; the run stops after the
+// first update whose change is below `tol`, or after Tmax updates.
+// Returns the number of updates run in *T_out.
+static ipg_status run_pagerank_converge(ipg_graph* g, uint32_t Tmax, bool push, double tol, const RunWs& w,
+                                        const uint32_t* part_off, uint32_t parts, hipStream_t s, StepTimer& tm,
+                                        ipg_run_stats* st, uint32_t* T_out, bool* converged) {
+  const uint32_t n = g->n;
+  const double ratio = 0.15 / static_cast<double>(n);
+  const double init = 1.0 / static_cast<double>(n);
+  const uint32_t gv = grid_for(n, kBlock, 16384);
+  const uint32_t* part_n = nullptr;
+  if (part_off) {
+    hipLaunchKernelGGL(pr_part_n_kernel, dim3(gv), dim3(kBlock), 0, s, part_off, parts, n, w.part_n);
+    IPG_HIP(hipGetLastError());
+    part_n = w.part_n;
+  }
+  constexpr uint32_t kSlotDoubles = kCtrSlots * 16;
+  double h[kSlotDoubles];
+  // L1 change of the update just enqueued (read back, slots summed in order)
+  auto change = [&](uint32_t step, double* out) -> ipg_status {
+    IPG_HIP(hipMemcpyAsync(h, w.l1, sizeof(h), hipMemcpyDeviceToHost, s));
+    IPG_HIP(hipStreamSynchronize(s));
+    double d = 0.0;
+    for (int b = 0; b < kCtrSlots; ++b) d += h[b * 16];
+    if (st && st->residual && step < st->trace_cap) st->residual[step] = d;
+    *out = d;
+    return IPG_OK;
+  };
+  *converged = false;
+  uint32_t T = Tmax;
+  if (st && st->residual && st->trace_cap) st->residual[0] = 0.0;
+  if (!push) {
+    IPG_HIP(tm.start(s));
+    hipLaunchKernelGGL(pr_pull_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, g->t.outdeg, init, part_n, w.f64_a,
+                       w.value_f64, 0, 1);
+    IPG_HIP(hipGetLastError());
+    IPG_HIP(tm.step(s, 0));
+    PrPullArgs a;
+    a.t = pull_tiling(g);
+    a.outdeg = g->t.outdeg;
+    a.value = w.value_f64;
+    a.partial = w.partial;
+    a.ratio = ratio;
+    a.part_n = part_n;
+    a.l1 = w.l1;
+    a.last = 0;
+    for (uint32_t step = 1; step <= Tmax; ++step) {
+      IPG_HIP(fill_f64(w.l1, kSlotDoubles, 0.0, s));
+      a.contrib_in = (step & 1) ? w.f64_a : w.f64_b;
+      a.contrib_out = (step & 1) ? w.f64_b : w.f64_a;
+      if (g->ni) {
+        hipLaunchKernelGGL(pr_items_kernel, dim3(std::min(g->ni, kPullGrid)), dim3(kBlock), 0, s, a);
+        IPG_HIP(hipGetLastError());
+      }
+      if (g->nl) {
+        hipLaunchKernelGGL(pr_longrow_kernel, dim3((g->nl + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0, s,
+                           a);
+        IPG_HIP(hipGetLastError());
+      }
+      IPG_HIP(tm.step(s, step));
+      double d = 0.0;
+      const ipg_status rc = change(step, &d);
+      if (rc != IPG_OK) return rc;
+      if (d < tol) {
+        T = step;
+        *converged = true;
+        break;
+      }
+    }
+  } else {
+    IPG_HIP(fill_f64(w.f64_a, n, 0.0, s));
+    IPG_HIP(fill_f64(w.f64_b, n, 0.0, s));
+    IPG_HIP(tm.start(s));
+    PrPushArgs a;
+    a.n = n;
+    a.off = g->csr_off;
+    a.dst = g->csr_dst;
+    a.value = w.value_f64;
+    a.ratio = ratio;
+    a.init = init;
+    a.part_n = part_n;
+    a.l1 = w.l1;
+    const uint32_t grid = grid_for(n, kBlock, 0xFFFFFFFFu);
+    for (uint32_t step = 0; step <= Tmax; ++step) {
+      IPG_HIP(fill_f64(w.l1, kSlotDoubles, 0.0, s));
+      a.mail_in = (step & 1) ? w.f64_b : w.f64_a;
+      a.mail_out = (step & 1) ? w.f64_a : w.f64_b;
+      a.first = step == 0;
+      a.last = step == Tmax;
+      hipLaunchKernelGGL(pr_push_kernel, dim3(grid), dim3(kBlock), 0, s, a);
+      IPG_HIP(hipGetLastError());
+      IPG_HIP(tm.step(s, step));
+      if (step == 0) continue;
+      double d = 0.0;
+      const ipg_status rc = change(step, &d);
+      if (rc != IPG_OK) return rc;
+      if (d < tol) {
+        T = step;
+        *converged = true;
+        break;
+      }
+    }
+  }
+  IPG_HIP(tm.finish(s));
+  *T_out = T;
+  return IPG_OK;
+}
+
 ipg_status run_pagerank(ipg_graph* g, uint32_t T, const ipg_run_opts& o, const RunWs& w, const void* ws,
                         hipStream_t s, StepTimer& tm, ipg_run_stats* st) {
   const uint32_t n = g->n;
@@ -364,22 +502,30 @@ ipg_status run_pagerank(ipg_graph* g, uint32_t T, const ipg_run_opts& o, const R
     part_off = o.part_offsets;
     parts = o.num_parts;
   }
-  if (o.flags & IPG_RUN_GRAPH) {
+  bool converged = true;
+  if (o.tolerance > 0.0) {
+    uint32_t Tdone = T;
+    const ipg_status rc = run_pagerank_converge(g, T, push, o.tolerance, w, part_off, parts, s, tm, st, &Tdone,
+                                                &converged);
+    if (rc != IPG_OK) return rc;
+    T = Tdone;
+  } else if (o.flags & IPG_RUN_GRAPH) {
     hipGraphExec_t exec = nullptr;
     const ipg_status rc = pagerank_graph(g, T, push, w, ws, part_off, parts, &exec);
     if (rc != IPG_OK) return rc;
     IPG_HIP(tm.start(s));
     IPG_HIP(hipGraphLaunch(exec, s));
+    IPG_HIP(tm.finish(s));
   } else {
     IPG_HIP(enqueue_pagerank(g, T, push, w, part_off, parts, s, &tm));
+    IPG_HIP(tm.finish(s));
   }
-  IPG_HIP(tm.finish(s));
   // The PageRank trace is fixed by Fig. 8: every vertex runs in every
   // superstep and broadcasts while s < T.
   if (st) {
     const uint32_t steps = T + 1;
     st->supersteps = steps;
-    st->halted = 1;
+    st->halted = converged ? 1 : 0;
     st->edges_traversed = static_cast<uint64_t>(T) * g->e;
     st->edges_examined = static_cast<uint64_t>(T) * g->e;
     for (uint32_t k = 0; k < steps && k < st->trace_cap; ++k) {
@@ -392,7 +538,7 @@ ipg_status run_pagerank(ipg_graph* g, uint32_t T, const ipg_run_opts& o, const R
       if ((o.flags & IPG_RUN_GRAPH) && st->usec) st->usec[k] = 0.f;
     }
   }
-  return IPG_OK;
+  return converged ? IPG_OK : IPG_NOT_CONVERGED;
 }
 
 }  // namespace ipg
