@@ -254,6 +254,9 @@ def main():
                         f"{' (trained selector)' if sel is not None else ''}",
             "n": hg.n, "m": hg.m, "apps": apps_out,
         },
+        "footprint": {k: v for k, v in ipg.footprint(hg.n, hg.m, symmetric=bool(hg.symmetric),
+                                                      weighted=hg.csr_w is not None).items()
+                      if k in ("total", "bytes_per_edge", "graph_workspace")},
         "learned_vs_plain": learned_vs_plain,
         "batched_vs_plain": batched,
         "roofline": roofline,

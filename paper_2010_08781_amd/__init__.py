@@ -427,3 +427,28 @@ def values_to_numpy(t) -> np.ndarray:
 
     a = t.cpu().numpy()
     return a.view(np.uint32) if t.dtype == torch.int32 else a
+
+
+# ----------------------------------------------------------- footprint ----
+
+def footprint(n: int, m: int, symmetric: bool = False, weighted: bool = False) -> dict:
+    """Device memory of a graph and of each application's run, in bytes
+    (the library's own size queries plus the caller-owned graph arrays):
+    the device-side counterpart of the paper's memory-usage comparison
+    (Table 3).  A symmetric graph stores one adjacency (CSC aliases CSR)."""
+    L = lib()
+    flags = GRAPH_SYMMETRIC if symmetric else 0
+    adj = 8 * (n + 1) + 4 * m
+    arrays = {"csr": adj, "csc": 0 if symmetric else adj,
+              "weights": (4 * m if symmetric else 8 * m) if weighted else 0}
+    graph_ws = int(L.ipg_graph_workspace_bytes(n, m, flags))
+    base = sum(arrays.values()) + graph_ws
+    runs = {name: int(L.ipg_run_workspace_bytes(n, m, app)) for name, app in
+            (("pagerank", APP_PAGERANK), ("cc", APP_CC), ("sssp", APP_SSSP))}
+    runs["multi_sssp"] = int(L.ipg_multi_sssp_workspace_bytes(n, m))
+    out = {"n": n, "m": m, "symmetric": symmetric, "weighted": weighted, "graph_arrays": arrays,
+           "graph_workspace": graph_ws, "run_workspace": runs,
+           "total": {k: base + v for k, v in runs.items()}}
+    out["bytes_per_edge"] = {k: round(v / max(m, 1), 3) for k, v in out["total"].items()}
+    out["bytes_per_vertex_run"] = {k: round(v / max(n, 1), 3) for k, v in runs.items()}
+    return out

@@ -79,3 +79,20 @@ def test_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(ipg, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(ImportError):
         ipg.lib()
+
+
+def test_footprint_report_adds_up(lib):
+    import paper_2010_08781_amd as ipg
+
+    n, m = 1 << 20, 31 << 20
+    f = ipg.footprint(n, m, symmetric=True)
+    assert f["graph_arrays"]["csc"] == 0 and f["graph_arrays"]["csr"] == 8 * (n + 1) + 4 * m
+    d = ipg.footprint(n, m, symmetric=False, weighted=True)
+    assert d["graph_arrays"]["csc"] == d["graph_arrays"]["csr"] and d["graph_arrays"]["weights"] == 8 * m
+    for k, v in f["total"].items():
+        assert v == sum(f["graph_arrays"].values()) + f["graph_workspace"] + f["run_workspace"][k]
+    # the run state is a few words per vertex; the graph is ids plus offsets
+    assert f["bytes_per_vertex_run"]["pagerank"] < 48 and f["bytes_per_vertex_run"]["cc"] < 40
+    # batched SSSP: 256-bit visited and receive rows plus a 16-superstep ring of level masks
+    assert f["bytes_per_vertex_run"]["multi_sssp"] < (16 + 2) * 32 + 64
+    assert 4.0 <= f["bytes_per_edge"]["cc"] < 6.5
