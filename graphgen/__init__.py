@@ -318,6 +318,8 @@ def workload(name: str) -> HostGraph:
         return rmat(22, 16, seed=4, symmetric=True)
     if name == "rmat-s26-dir":
         return rmat(26, 16, seed=5, symmetric=False)
+    if name == "rmat-s26-sym":
+        return rmat(26, 16, seed=5, symmetric=True)
     raise KeyError(name)
 
 

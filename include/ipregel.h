@@ -61,6 +61,11 @@ typedef enum { IPG_MODE_AUTO = 0, IPG_MODE_PUSH = 1, IPG_MODE_PULL = 2 } ipg_mod
 /* ipg_graph_desc.flags */
 #define IPG_GRAPH_SYMMETRIC 1u /* CSC arrays equal the CSR arrays (undirected graph) */
 #define IPG_GRAPH_VALIDATE 2u  /* check offsets and ids on the device at create time */
+#define IPG_GRAPH_RENAME 4u    /* keep a second copy of the CSC source ids renamed hot-first (by descending
+                                  out-degree) for PageRank's pull exchange, whose outbox is then stored in
+                                  that order: the most-read outbox entries share cache lines.  Results are
+                                  unchanged (same values summed in the same order); costs 4E + 4N bytes of
+                                  graph workspace. */
 
 /*
  * A graph as CSR (out-adjacency, for push) plus CSC (in-adjacency, for pull).
@@ -93,6 +98,21 @@ typedef struct {
                                  exchange, the workspace and part_offsets stay the same; per-superstep
                                  times (usec) are not recorded in this mode. */
 
+/*
+ * Launch parameters of the exchange kernels; 0 keeps the library's default.
+ * They change speed only: results stay exact (CC, SSSP) and within the
+ * PageRank summation-order freedom.  Chosen per graph by an autotuner.
+ */
+typedef struct {
+  uint32_t pr_hot;     /* PageRank pull on a store built with IPG_GRAPH_RENAME: outbox entries of the
+                          most-read sources cached in LDS per workgroup (default 8192; capped to the
+                          LDS a workgroup can hold beside the kernel's tiles, 11200 on gfx950;
+                          UINT32_MAX = no cache) */
+  uint32_t pull_grid;  /* workgroups of the pull item kernels (default 2048) */
+  uint32_t push_div;   /* fixed exchange rule: pull when frontier + its out-edges > E / push_div (default 20) */
+  uint32_t list_div;   /* push frontiers up to max(4096, N / list_div) are visited as a list (default 16) */
+} ipg_tuning;
+
 typedef struct {
   uint32_t source;          /* SSSP source vertex (ignored by the other applications) */
   ipg_mode mode;
@@ -114,6 +134,7 @@ typedef struct {
    * max_supersteps updates (IPG_NOT_CONVERGED, values valid).  max_supersteps
    * must then be >= 1; not combinable with IPG_RUN_GRAPH.  0 = fixed T. */
   double tolerance;
+  const ipg_tuning* tuning; /* HOST pointer, or NULL for the defaults */
 } ipg_run_opts;
 
 /*

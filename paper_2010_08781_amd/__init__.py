@@ -35,7 +35,7 @@ APPS = {"pagerank": APP_PAGERANK, "pr": APP_PAGERANK, "cc": APP_CC, "sssp": APP_
 COMBINE_SUM, COMBINE_MIN = 0, 1
 DEFAULT_COMBINER = {APP_PAGERANK: COMBINE_SUM, APP_CC: COMBINE_MIN, APP_SSSP: COMBINE_MIN}
 MODES = {"auto": 0, "push": 1, "pull": 2}
-GRAPH_SYMMETRIC, GRAPH_VALIDATE = 1, 2
+GRAPH_SYMMETRIC, GRAPH_VALIDATE, GRAPH_RENAME = 1, 2, 4
 RUN_PERSISTENT, RUN_GRAPH = 1, 2
 INF = 0xFFFFFFFF
 BATCH_MAX_SOURCES = 256
@@ -54,10 +54,28 @@ class _Desc(ctypes.Structure):
                 ("csr_w", ctypes.c_void_p), ("csc_w", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("pr_hot", ctypes.c_uint32), ("pull_grid", ctypes.c_uint32), ("push_div", ctypes.c_uint32),
+                ("list_div", ctypes.c_uint32)]
+
+
+TUNING_FIELDS = ("pr_hot", "pull_grid", "push_div", "list_div")
+HOT_OFF = 0xFFFFFFFF
+
+
+def _tuning(t):
+    if t is None:
+        return None
+    unknown = set(t) - set(TUNING_FIELDS)
+    if unknown:
+        raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+    return _Tuning(*(int(t.get(k, 0)) for k in TUNING_FIELDS))
+
+
 class _Opts(ctypes.Structure):
     _fields_ = [("source", ctypes.c_uint32), ("mode", ctypes.c_int), ("flags", ctypes.c_uint32),
                 ("selector", ctypes.c_void_p), ("part_offsets", ctypes.c_void_p), ("num_parts", ctypes.c_uint32),
-                ("tolerance", ctypes.c_double)]
+                ("tolerance", ctypes.c_double), ("tuning", ctypes.c_void_p)]
 
 
 class _Stats(ctypes.Structure):
@@ -185,7 +203,7 @@ class Graph:
     """A graph resident on the current HIP device (CSR + CSC held as torch tensors)."""
 
     def __init__(self, n, csr_off, csr_dst, csc_off=None, csc_src=None, csr_w=None, csc_w=None,
-                 symmetric=False, validate=True, stream=None):
+                 symmetric=False, validate=True, stream=None, rename=True):
         import torch
 
         self.n = int(n)
@@ -209,7 +227,9 @@ class Graph:
         # keep caller tensors alive for the lifetime of the handle
         self._keep = (csr_off, csr_dst, csc_off, csc_src, csr_w, csc_w)
         self.weighted = csr_w is not None
-        flags = (GRAPH_SYMMETRIC if symmetric else 0) | (GRAPH_VALIDATE if validate else 0)
+        self.renamed = bool(rename)
+        flags = (GRAPH_SYMMETRIC if symmetric else 0) | (GRAPH_VALIDATE if validate else 0) | \
+            (GRAPH_RENAME if rename else 0)
         d = _Desc(self.n, self.m, csr_off.data_ptr(), csr_dst.data_ptr() if self.m else None,
                   csc_off.data_ptr(), csc_src.data_ptr() if self.m else None,
                   csr_w.data_ptr() if csr_w is not None else None,
@@ -228,7 +248,7 @@ class Graph:
         return cls(*args, **kw)
 
     @classmethod
-    def from_host(cls, hg, device="cuda", validate=True, weighted=True) -> "Graph":
+    def from_host(cls, hg, device="cuda", validate=True, weighted=True, rename=True) -> "Graph":
         """Upload any object with n, csr_off, csr_dst, csc_off, csc_src (numpy) and optional csr_w/csc_w."""
         import torch
 
@@ -247,7 +267,8 @@ class Graph:
         if weighted and getattr(hg, "csr_w", None) is not None:
             csr_w = up(hg.csr_w.astype(np.uint32), np.int32)
             csc_w = csr_w if sym else up(hg.csc_w.astype(np.uint32), np.int32)
-        return cls(hg.n, csr_off, csr_dst, csc_off, csc_src, csr_w, csc_w, symmetric=sym, validate=validate)
+        return cls(hg.n, csr_off, csr_dst, csc_off, csc_src, csr_w, csc_w, symmetric=sym, validate=validate,
+                   rename=rename)
 
     def workspace(self, app: int):
         import torch
@@ -260,7 +281,7 @@ class Graph:
     def run(self, app, max_supersteps: Optional[int] = None, source: int = 0, mode: str = "auto",
             timing: bool = True, trace_cap: int = 1 << 16, persistent: bool = False, stream=None,
             combiner: Optional[int] = None, check: bool = True, selector=None, parts=None, graph: bool = False,
-            tol: float = 0.0):
+            tol: float = 0.0, tuning: Optional[dict] = None):
         """Run an application; returns (values tensor on the device, RunStats).
 
         max_supersteps: PageRank -> number of rank updates (default 10, Fig. 8);
@@ -268,7 +289,8 @@ class Graph:
         parts: PageRank over a disjoint union -- int32 CUDA tensor of part
         vertex offsets (P+1 entries); graph: replay PageRank as one hipGraph;
         tol: PageRank to convergence (stop after the first update whose L1
-        change is below tol; max_supersteps caps the updates)."""
+        change is below tol; max_supersteps caps the updates); tuning: launch
+        parameters (see TUNING_FIELDS and the autotune module)."""
         import torch
 
         a = APPS[app] if isinstance(app, str) else int(app)
@@ -284,9 +306,10 @@ class Graph:
             if not parts.is_cuda or parts.dtype != torch.int32 or not parts.is_contiguous() or parts.numel() < 2:
                 raise ValueError("parts must be a contiguous int32 CUDA tensor of P+1 offsets")
         flags = (RUN_PERSISTENT if persistent else 0) | (RUN_GRAPH if graph else 0)
+        tun = _tuning(tuning)
         opts = _Opts(int(source), MODES[mode], flags, selector.data_ptr() if selector is not None else None,
                      parts.data_ptr() if parts is not None else None, parts.numel() - 1 if parts is not None else 0,
-                     float(tol))
+                     float(tol), ctypes.addressof(tun) if tun is not None else None)
         tr = _Trace(trace_cap, timing)
         rc = lib().ipg_run(self._h, a, comb, int(max_supersteps), ctypes.byref(opts),
                            ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(stream),
@@ -299,7 +322,8 @@ class Graph:
         return vals, tr.stats(rc)
 
     def run_multi_sssp(self, sources, max_supersteps: int = 0, mode: str = "auto", timing: bool = True,
-                       trace_cap: int = 1 << 16, stream=None, out=None, check: bool = True):
+                       trace_cap: int = 1 << 16, stream=None, out=None, check: bool = True,
+                       tuning: Optional[dict] = None):
         """Batched unit-weight SSSP from up to 256 sources in one superstep loop.
 
         Returns (dist [Q, N] int32 tensor holding uint32 distances, RunStats whose
@@ -316,7 +340,8 @@ class Graph:
             nb = lib().ipg_multi_sssp_workspace_bytes(self.n, self.m)
             self._run_ws[key] = (torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device), nb)
         ws, nbytes = self._run_ws[key]
-        opts = _Opts(0, MODES[mode], 0, None, None, 0, 0.0)
+        tun = _tuning(tuning)
+        opts = _Opts(0, MODES[mode], 0, None, None, 0, 0.0, ctypes.addressof(tun) if tun is not None else None)
         tr = _Trace(trace_cap, timing)
         rc = lib().ipg_run_multi_sssp(self._h, src.data_ptr(), q, int(max_supersteps), ctypes.byref(opts),
                                       out.data_ptr(), out.numel() * 4, ws.data_ptr(), nbytes, _stream_handle(stream),
@@ -431,13 +456,13 @@ def values_to_numpy(t) -> np.ndarray:
 
 # ----------------------------------------------------------- footprint ----
 
-def footprint(n: int, m: int, symmetric: bool = False, weighted: bool = False) -> dict:
+def footprint(n: int, m: int, symmetric: bool = False, weighted: bool = False, rename: bool = True) -> dict:
     """Device memory of a graph and of each application's run, in bytes
     (the library's own size queries plus the caller-owned graph arrays):
     the device-side counterpart of the paper's memory-usage comparison
     (Table 3).  A symmetric graph stores one adjacency (CSC aliases CSR)."""
     L = lib()
-    flags = GRAPH_SYMMETRIC if symmetric else 0
+    flags = (GRAPH_SYMMETRIC if symmetric else 0) | (GRAPH_RENAME if rename else 0)
     adj = 8 * (n + 1) + 4 * m
     arrays = {"csr": adj, "csc": 0 if symmetric else adj,
               "weights": (4 * m if symmetric else 8 * m) if weighted else 0}
@@ -446,7 +471,7 @@ def footprint(n: int, m: int, symmetric: bool = False, weighted: bool = False) -
     runs = {name: int(L.ipg_run_workspace_bytes(n, m, app)) for name, app in
             (("pagerank", APP_PAGERANK), ("cc", APP_CC), ("sssp", APP_SSSP))}
     runs["multi_sssp"] = int(L.ipg_multi_sssp_workspace_bytes(n, m))
-    out = {"n": n, "m": m, "symmetric": symmetric, "weighted": weighted, "graph_arrays": arrays,
+    out = {"n": n, "m": m, "symmetric": symmetric, "weighted": weighted, "rename": rename, "graph_arrays": arrays,
            "graph_workspace": graph_ws, "run_workspace": runs,
            "total": {k: base + v for k, v in runs.items()}}
     out["bytes_per_edge"] = {k: round(v / max(m, 1), 3) for k, v in out["total"].items()}

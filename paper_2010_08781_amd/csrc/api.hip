@@ -17,6 +17,7 @@ size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w) {
     r.partial = c.take<double>(chunks_cap(e));
     r.part_n = c.take<uint32_t>(nn);
     r.l1 = c.take<double>(kCtrSlots * 16);  // one 128-byte line per slot
+    r.value_hot = c.take<double>(nn);
   } else {
     r.value_u32 = c.take<uint32_t>(nn);
     r.mail_a = c.take<uint32_t>(nn);
@@ -78,8 +79,8 @@ hipError_t StepTimer::finish(hipStream_t s) {
   return hipSuccess;
 }
 
-ipg_mode heuristic_mode(const ModeQuery& q) {
-  return static_cast<ipg_mode>(heuristic_pick(q.e, q.frontier, q.frontier_deg));
+ipg_mode heuristic_mode(const ModeQuery& q, uint32_t div) {
+  return static_cast<ipg_mode>(heuristic_pick(q.e, q.frontier, q.frontier_deg, div));
 }
 
 }  // namespace ipg
@@ -99,7 +100,7 @@ extern "C" ipg_status ipg_run(ipg_graph* g, ipg_app app, ipg_combiner combiner, 
                        (app == IPG_APP_CC_HASHMIN && combiner == IPG_COMBINE_MIN) ||
                        (app == IPG_APP_SSSP && combiner == IPG_COMBINE_MIN);
   if (!ok_pair) return fail(IPG_EUNSUPPORTED, "ipg_run: (app, combiner) must be (PAGERANK, SUM), (CC, MIN) or (SSSP, MIN)");
-  ipg_run_opts o{0, IPG_MODE_AUTO, 0, nullptr, nullptr, 0, 0.0};
+  ipg_run_opts o{0, IPG_MODE_AUTO, 0, nullptr, nullptr, 0, 0.0, nullptr};
   if (opts) o = *opts;
   if (o.mode != IPG_MODE_AUTO && o.mode != IPG_MODE_PUSH && o.mode != IPG_MODE_PULL)
     return fail(IPG_EINVAL, "ipg_run: unknown mode");

@@ -78,14 +78,28 @@ struct PullItem {
 static_assert(sizeof(PullItem) == 24, "packed item");
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 
-struct GraphTables {
-  uint32_t* outdeg;     // [n] out-degree (u32)
+// Pull tiling of one CSC: device tables and their lengths.
+struct TilingTables {
   uint32_t* pull_rb;    // [nb+1] first CSC row of each pull row-group
   uint32_t* long_rows;  // [nl] rows with in-degree > kPullTile, ascending
   uint32_t* lr_first;   // [nl+1] first chunk of each long row (chunks of kWaveTile in-edges)
   uint32_t* ch_row;     // [nc] index into long_rows of each chunk
   PullItem* items;      // [ni] pull work items: the nc chunks first, then the row pieces
-  uint32_t* flags;      // [4] validation flags
+  uint32_t nb, nl, nc, ni;
+};
+
+struct GraphTables {
+  uint32_t* outdeg;     // [n] out-degree (u32)
+  uint32_t* flags;      // [4] validation flags (+ a counter)
+  TilingTables pull;    // tiling of the caller's CSC
+  // Hot-first store (IPG_GRAPH_RENAME), else null: every vertex renamed by
+  // descending out-degree, and the CSC rebuilt under the new names (rows in
+  // the new order, each row's sources in their original order).
+  uint32_t* perm;       // [n] new name of every vertex
+  uint32_t* outdeg_hot; // [n] out-degree by new name
+  uint64_t* off_hot;    // [n+1] CSC offsets by new name
+  int32_t* src_hot;     // [e] CSC sources, new names
+  TilingTables pull_hot;
 };
 
 // Pull-side view of the CSC handed to the gather kernels.  A launch has nc
@@ -115,10 +129,6 @@ struct ipg_graph {
   const uint32_t* csr_w;
   const uint32_t* csc_w;
   ipg::GraphTables t;
-  uint32_t nb;  // number of pull row-groups
-  uint32_t nl;  // number of long rows
-  uint32_t nc;  // number of long-row chunks
-  uint32_t ni;  // number of pull items
   int device;
   // last run
   int has_values;
@@ -135,6 +145,7 @@ struct ipg_graph {
     const void* ws;
     const uint32_t* parts;
     uint32_t num_parts;
+    uint32_t hot, grid;
   } pr_key;
 };
 

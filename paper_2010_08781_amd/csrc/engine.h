@@ -7,21 +7,24 @@
 
 namespace ipg {
 
-inline PullTiling pull_tiling(const ipg_graph* g) {
+inline PullTiling make_tiling(const uint64_t* off, const int32_t* src, const TilingTables& tt) {
   PullTiling t;
-  t.off = g->csc_off;
-  t.src = g->csc_src;
-  t.rb = g->t.pull_rb;
-  t.long_rows = g->t.long_rows;
-  t.lr_first = g->t.lr_first;
-  t.ch_row = g->t.ch_row;
-  t.items = g->t.items;
-  t.nl = g->nl;
-  t.nc = g->nc;
-  t.nb = g->nb;
-  t.ni = g->ni;
+  t.off = off;
+  t.src = src;
+  t.rb = tt.pull_rb;
+  t.long_rows = tt.long_rows;
+  t.lr_first = tt.lr_first;
+  t.ch_row = tt.ch_row;
+  t.items = tt.items;
+  t.nl = tt.nl;
+  t.nc = tt.nc;
+  t.nb = tt.nb;
+  t.ni = tt.ni;
   return t;
 }
+
+// The caller's CSC and its tiling.
+inline PullTiling pull_tiling(const ipg_graph* g) { return make_tiling(g->csc_off, g->csc_src, g->t.pull); }
 
 // End-of-superstep summary written by the decide kernel: the counter slots
 // summed, and the selector's choice for the next superstep.
@@ -85,6 +88,7 @@ struct RunWs {
   double* partial;    // [chunks] partial sums of long-row chunks (pull)
   uint32_t* part_n;   // [n] vertex count of each vertex's part (disjoint unions)
   double* l1;         // [kCtrSlots] L1 change of an update, spread over slots (convergence runs)
+  double* value_hot;  // [n] ranks under the hot-first names (renamed store), mapped back at the end
   // CC / SSSP
   uint32_t* value_u32;  // [n] labels or distances
   uint32_t* mail_a;     // [n] one-slot min mailboxes, ping (INF = empty)
@@ -135,11 +139,31 @@ struct ModeQuery {
 // Fixed heuristic used when no selector is given (the default of Ligra's
 // direction switch, Shun and Blelloch 2013): pull when the frontier plus its
 // out-edges exceed E/20.
-__host__ __device__ inline int heuristic_pick(uint64_t e, uint64_t frontier, uint64_t frontier_deg) {
+__host__ __device__ inline int heuristic_pick(uint64_t e, uint64_t frontier, uint64_t frontier_deg,
+                                              uint32_t div = 20) {
   if (e == 0) return IPG_MODE_PUSH;
-  return (frontier + frontier_deg > e / 20) ? IPG_MODE_PULL : IPG_MODE_PUSH;
+  return (frontier + frontier_deg > e / (div ? div : 20)) ? IPG_MODE_PULL : IPG_MODE_PUSH;
 }
-ipg_mode heuristic_mode(const ModeQuery& q);
+
+// Launch parameters of a run, defaults filled in (see ipg_tuning).
+struct Tune {
+  uint32_t pr_hot;     // 0 = no LDS outbox cache
+  uint32_t pull_grid;
+  uint32_t push_div;
+  uint32_t list_div;
+};
+constexpr uint32_t kHotDefault = 8192;  // 64 KB of LDS; the launch also caps it to the LDS left by the tiles
+inline Tune resolve_tuning(const ipg_tuning* t) {
+  Tune r{kHotDefault, kPullGrid, 20, 16};
+  if (t) {
+    if (t->pr_hot) r.pr_hot = t->pr_hot == 0xFFFFFFFFu ? 0 : t->pr_hot;
+    if (t->pull_grid) r.pull_grid = t->pull_grid;
+    if (t->push_div) r.push_div = t->push_div;
+    if (t->list_div) r.list_div = t->list_div;
+  }
+  return r;
+}
+ipg_mode heuristic_mode(const ModeQuery& q, uint32_t div = 20);
 
 ipg_status run_pagerank(ipg_graph* g, uint32_t T, const ipg_run_opts& o, const RunWs& w, const void* ws,
                         hipStream_t s, StepTimer& tm, ipg_run_stats* st);

@@ -457,9 +457,9 @@ __global__ void dd_start_kernel(DevCtl* ctl, int mode, uint64_t count, uint64_t 
 // and the exchange of the next superstep (forced, the selector, or the fixed
 // heuristic).  Does nothing once the run has halted.
 __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint32_t* lc, uint32_t* hc, uint64_t e,
-                                                          uint32_t n,
-                                                          const double* sel, int forced, uint64_t list_limit,
-                                                          DevCtl* ctl, DevRec* rec) {
+                                                          uint32_t n, const double* sel, int forced,
+                                                          uint64_t list_limit, uint32_t push_div, DevCtl* ctl,
+                                                          DevRec* rec) {
   static_assert(kCtrSlots == kWave, "one slot per lane");
   const unsigned long long now = static_cast<unsigned long long>(wall_clock64());
   const DevCtl k = *ctl;
@@ -511,7 +511,7 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
   } else if (sel) {
     nk.mode = sel_mode;
   } else {
-    nk.mode = heuristic_pick(e, nc, nd);
+    nk.mode = heuristic_pick(e, nc, nd, push_div);
   }
   *ctl = nk;
 }
@@ -536,8 +536,8 @@ static hipError_t launch_push(const MinPushArgs& a, uint32_t grid, bool hubs, hi
   return hipGetLastError();
 }
 template <int APP, bool W>
-static hipError_t launch_pull(const MinPullArgs& a, hipStream_t s) {
-  const uint32_t grid = std::max(1u, std::min(a.t.ni, kPullGrid));
+static hipError_t launch_pull(const MinPullArgs& a, uint32_t max_grid, hipStream_t s) {
+  const uint32_t grid = std::max(1u, std::min(a.t.ni, max_grid));
   hipLaunchKernelGGL((minprop_pull_kernel<APP, W>), dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
@@ -547,14 +547,14 @@ static hipError_t push_dispatch(ipg_app app, bool weighted, const MinPushArgs& a
   if (app == IPG_APP_CC_HASHMIN) return launch_push<IPG_APP_CC_HASHMIN, false>(a, grid, hubs, s);
   return weighted ? launch_push<IPG_APP_SSSP, true>(a, grid, hubs, s) : launch_push<IPG_APP_SSSP, false>(a, grid, hubs, s);
 }
-static hipError_t pull_dispatch(ipg_app app, bool weighted, const MinPullArgs& a, hipStream_t s) {
-  if (app == IPG_APP_CC_HASHMIN) return launch_pull<IPG_APP_CC_HASHMIN, false>(a, s);
-  return weighted ? launch_pull<IPG_APP_SSSP, true>(a, s) : launch_pull<IPG_APP_SSSP, false>(a, s);
+static hipError_t pull_dispatch(ipg_app app, bool weighted, const MinPullArgs& a, uint32_t grid, hipStream_t s) {
+  if (app == IPG_APP_CC_HASHMIN) return launch_pull<IPG_APP_CC_HASHMIN, false>(a, grid, s);
+  return weighted ? launch_pull<IPG_APP_SSSP, true>(a, grid, s) : launch_pull<IPG_APP_SSSP, false>(a, grid, s);
 }
 
 // Frontier lists up to this size are visited through the list; larger ones
 // by sweeping the mailboxes.
-static uint64_t list_limit(uint32_t n) { return std::max<uint64_t>(4096, n / 16); }
+static uint64_t list_limit(uint32_t n, uint32_t div) { return std::max<uint64_t>(4096, n / (div ? div : 16)); }
 
 // Ping-pong buffers of superstep `step`.
 struct StepBufs {
@@ -583,7 +583,8 @@ static StepBufs bufs_for(const RunWs& w, uint32_t step) {
 // control block (device-driven superstep s >= 1) both exchanges are
 // launched on fixed grids and the control block picks one.
 static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint32_t step, ipg_mode mode,
-                               const Active& act, uint64_t degsum, const RunWs& w, const DevCtl* ctl, hipStream_t s) {
+                               const Active& act, uint64_t degsum, const RunWs& w, const DevCtl* ctl, const Tune& tn,
+                               hipStream_t s) {
   const uint32_t n = g->n;
   const bool weighted = app == IPG_APP_SSSP && g->csr_w != nullptr;
   const uint32_t gv = grid_for(n, kBlock, 16384);
@@ -645,7 +646,7 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
     pa.ctr = b.c;
     pa.ctr_clear = b.cc;
     pa.ctl = ctl;
-    IPG_HIP(pull_dispatch(app, weighted, pa, s));
+    IPG_HIP(pull_dispatch(app, weighted, pa, tn.pull_grid, s));
   }
   return IPG_OK;
 }
@@ -702,6 +703,7 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
                                      hipStream_t s, StepTimer& tm, ipg_run_stats* st) {
   const uint32_t n = g->n;
   const uint64_t e = g->e;
+  const Tune tn = resolve_tuning(o.tuning);
   MinStart m0;
   ipg_status rc = start_minprop(g, app, o, w, s, &m0);
   if (rc != IPG_OK) return rc;
@@ -713,12 +715,12 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
   ipg_mode mode0 = o.mode;
   if (mode0 == IPG_MODE_AUTO)
     mode0 = m0.sel_mode ? static_cast<ipg_mode>(m0.sel_mode)
-                        : static_cast<ipg_mode>(heuristic_pick(e, m0.count, m0.degsum));
+                        : static_cast<ipg_mode>(heuristic_pick(e, m0.count, m0.degsum, tn.push_div));
   IPG_HIP(tm.start(s));
   hipLaunchKernelGGL(dd_start_kernel, dim3(1), dim3(1), 0, s, w.ctl, static_cast<int>(mode0), m0.count, m0.degsum,
                      cap);
   IPG_HIP(hipGetLastError());
-  rc = enqueue_step(g, app, o.source, 0, mode0, step0_active(app, n, o.source), m0.degsum, w, nullptr, s);
+  rc = enqueue_step(g, app, o.source, 0, mode0, step0_active(app, n, o.source), m0.degsum, w, nullptr, tn, s);
   if (rc != IPG_OK) return rc;
   uint32_t enqueued = 0;  // supersteps whose launches are in the stream, minus one
   uint32_t recorded = 0;  // supersteps whose records were read
@@ -731,12 +733,12 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
       const uint32_t step = enqueued + k;
       if (step > 0) {
         Active unused{};
-        rc = enqueue_step(g, app, o.source, step, IPG_MODE_AUTO, unused, 0, w, w.ctl, s);
+        rc = enqueue_step(g, app, o.source, step, IPG_MODE_AUTO, unused, 0, w, w.ctl, tn, s);
         if (rc != IPG_OK) return rc;
       }
       const StepBufs b = bufs_for(w, step);
       hipLaunchKernelGGL(dd_decide_kernel, dim3(1), dim3(kWave), 0, s, b.c, b.lc, b.hc, e, n, sel, forced,
-                         list_limit(n), w.ctl, w.rec);
+                         list_limit(n, tn.list_div), tn.push_div, w.ctl, w.rec);
       IPG_HIP(hipGetLastError());
     }
     enqueued += chunk;
@@ -778,6 +780,7 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
   if (o.flags & IPG_RUN_PERSISTENT) return run_minprop_device(g, app, cap, o, w, s, tm, st);
   const uint32_t n = g->n;
   const uint64_t e = g->e;
+  const Tune tn = resolve_tuning(o.tuning);
   MinStart m0;
   ipg_status status = start_minprop(g, app, o, w, s, &m0);
   if (status != IPG_OK) return status;
@@ -790,7 +793,7 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
   for (;;) {
     ModeQuery q{n, e, count, degsum, step, app};
     ipg_mode mode = o.mode;
-    if (mode == IPG_MODE_AUTO) mode = next_sel_mode ? static_cast<ipg_mode>(next_sel_mode) : heuristic_mode(q);
+    if (mode == IPG_MODE_AUTO) mode = next_sel_mode ? static_cast<ipg_mode>(next_sel_mode) : heuristic_mode(q, tn.push_div);
     const StepBufs b = bufs_for(w, step);
     Active act;
     if (step == 0) {
@@ -801,7 +804,7 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
       act.phase = list_ok ? kStepList : kStepDense;
       act.count = list_ok ? static_cast<uint32_t>(count) : n;
     }
-    status = enqueue_step(g, app, o.source, step, mode, act, degsum, w, nullptr, s);
+    status = enqueue_step(g, app, o.source, step, mode, act, degsum, w, nullptr, tn, s);
     if (status != IPG_OK) return status;
     IPG_HIP(tm.step(s, step));
     const double* sel = o.mode == IPG_MODE_AUTO ? o.selector : nullptr;
@@ -841,7 +844,7 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
     count = h.next_count;
     degsum = h.next_deg;
     next_sel_mode = h.mode;
-    list_ok = mode == IPG_MODE_PUSH && count <= list_limit(n);
+    list_ok = mode == IPG_MODE_PUSH && count <= list_limit(n, tn.list_div);
   }
   IPG_HIP(tm.finish(s));
   if (st) {

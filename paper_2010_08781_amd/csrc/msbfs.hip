@@ -482,6 +482,7 @@ static ipg_status run_msbfs(ipg_graph* g, const uint32_t* sources, uint32_t q, u
                             uint32_t* dist, const MsWs& w, hipStream_t s, StepTimer& tm, ipg_run_stats* st) {
   const uint32_t n = g->n;
   const uint64_t e = g->e;
+  const Tune tn = resolve_tuning(o.tuning);
   const size_t rowset = (size_t)n * kMsWords;  // u64 per level buffer
   const size_t words = ms_words(n);
   auto slot_buf = [&](uint32_t level) { return w.hist + (size_t)(level % kMsHist) * rowset; };
@@ -534,7 +535,7 @@ static ipg_status run_msbfs(ipg_graph* g, const uint32_t* sources, uint32_t q, u
       hipLaunchKernelGGL(ms_init_kernel, dim3(1), dim3(kBlock), 0, s, sources, q, r);
       IPG_HIP(hipGetLastError());
     } else {
-      mode = ms_mode(o.mode, e, frontier, frontier_deg, 20);
+      mode = ms_mode(o.mode, e, frontier, frontier_deg, tn.push_div);
       if (mode == IPG_MODE_PUSH) {
         // F_out must be zero outside the rows this superstep writes: zero the
         // rows left by the slot's previous level (its bitmap, still intact)
@@ -566,13 +567,13 @@ static ipg_status run_msbfs(ipg_graph* g, const uint32_t* sources, uint32_t q, u
         a.partial = w.partial;
         // sparse superstep: gather only the non-empty rows of F_{s-1}
         a.nz = frontier < n / 8 ? slot_bits(step - 1) : nullptr;
-        if (g->ni) {
-          hipLaunchKernelGGL(ms_pull_kernel, dim3(std::min(g->ni, kPullGrid)), dim3(kBlock), 0, s, a);
+        if (t.ni) {
+          hipLaunchKernelGGL(ms_pull_kernel, dim3(std::min(t.ni, tn.pull_grid)), dim3(kBlock), 0, s, a);
           IPG_HIP(hipGetLastError());
         }
         a.r.ctr_clear = nullptr;
-        if (g->nl) {
-          hipLaunchKernelGGL(ms_longrow_kernel, dim3((g->nl + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0,
+        if (t.nl) {
+          hipLaunchKernelGGL(ms_longrow_kernel, dim3((t.nl + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0,
                              s, a);
           IPG_HIP(hipGetLastError());
         }
@@ -633,7 +634,7 @@ extern "C" ipg_status ipg_run_multi_sssp(ipg_graph* g, const uint32_t* sources, 
   if (num_sources == 0 || num_sources > kMsMaxQueries)
     return fail(IPG_EINVAL, "ipg_run_multi_sssp: num_sources must be in [1, 256]");
   if (g->csr_w) return fail(IPG_EUNSUPPORTED, "ipg_run_multi_sssp: the graph has edge weights (unit weights only)");
-  ipg_run_opts o{0, IPG_MODE_AUTO, 0, nullptr, nullptr, 0, 0.0};
+  ipg_run_opts o{0, IPG_MODE_AUTO, 0, nullptr, nullptr, 0, 0.0, nullptr};
   if (opts) o = *opts;
   if (o.mode != IPG_MODE_AUTO && o.mode != IPG_MODE_PUSH && o.mode != IPG_MODE_PULL)
     return fail(IPG_EINVAL, "ipg_run_multi_sssp: unknown mode");

@@ -54,13 +54,13 @@ __device__ __forceinline__ void pr_store(const PrPullArgs& a, uint32_t v, double
 // Workgroup sum of the threads' L1 changes added to one of kCtrSlots
 // 128-byte slots (every thread must call).
 __device__ __forceinline__ void flush_l1(double* slots, double x) {
-  __shared__ double part[kWavesPerBlock];
+  __shared__ double part[1024 / kWave];
   x = wave_sum(x);
   if (lane_id() == 0) part[threadIdx.x / kWave] = x;
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = 0.0;
-    for (int i = 0; i < kWavesPerBlock; ++i) t += part[i];
+    for (uint32_t i = 0; i < blockDim.x / kWave; ++i) t += part[i];
     if (t != 0.0) unsafeAtomicAdd(slots + (blockIdx.x % kCtrSlots) * 16, t);
   }
 }
@@ -75,16 +75,6 @@ __device__ __forceinline__ void pr_finish(const PrPullArgs& a, uint32_t v, doubl
   pr_store(a, v, rank, a.outdeg[v], l1);
 }
 
-// Sum over the workgroup in a fixed order; every thread gets the result.
-__device__ __forceinline__ double block_sum(double s, double* red) {
-  s = wave_sum(s);
-  if (lane_id() == 0) red[threadIdx.x / kWave] = s;
-  __syncthreads();
-  const double t = (red[0] + red[1]) + (red[2] + red[3]);
-  __syncthreads();
-  return t;
-}
-
 // Pull superstep, first launch.  Every wavefront works through its own pull
 // items (grid-stride over wavefronts), with its own LDS tile and no
 // workgroup barrier, so 32 items per CU are in flight.  An item needs one
@@ -96,21 +86,31 @@ __device__ __forceinline__ double block_sum(double s, double* red) {
 //    summed by G lanes (G from the item's row count), then finished here;
 //  * long-row chunk: a fixed-order wavefront sum stored as the chunk's
 //    partial (added up by the second launch).
-__global__ __launch_bounds__(kBlock) void pr_items_kernel(PrPullArgs a) {
+// With a hot cache (hot > 0, hot-first store) the workgroup first copies the
+// outbox entries of the `hot` most-read sources -- names 0 .. hot-1 -- into
+// LDS, and gathers from those sources read LDS instead of the memory
+// hierarchy (the L1 miss rate of the random gathers is the bound).
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) void pr_items_kernel(PrPullArgs a, uint32_t hot) {
   constexpr int kPer = kWaveTile / kWave;
   constexpr int kRowPer = (kItemRows + kWave) / kWave;
-  __shared__ double s_tile[kWavesPerBlock][kWaveTile];
-  __shared__ uint32_t s_off[kWavesPerBlock][kItemRows + 1];
-  __shared__ uint32_t s_deg[kWavesPerBlock][kItemRows];
+  __shared__ double s_tile[WAVES][kWaveTile];
+  __shared__ uint32_t s_off[WAVES][kItemRows + 1];
+  __shared__ uint32_t s_deg[WAVES][kItemRows];
+  extern __shared__ double s_hot[];
   const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
   double* tile = s_tile[wv];
   uint32_t* soff = s_off[wv];
   uint32_t* sdeg = s_deg[wv];
   const int32_t* src = a.t.src;
   const uint64_t* off = a.t.off;
-  const uint32_t nw = gridDim.x * kWavesPerBlock;
+  if (hot) {
+    for (uint32_t i = threadIdx.x; i < hot; i += WAVES * kWave) s_hot[i] = a.contrib_in[i];
+    __syncthreads();
+  }
+  const uint32_t nw = gridDim.x * WAVES;
   double l1 = 0.0;
-  for (uint32_t item = blockIdx.x * kWavesPerBlock + wv; item < a.t.ni; item += nw) {
+  for (uint32_t item = blockIdx.x * WAVES + wv; item < a.t.ni; item += nw) {
     const PullItem it = a.t.items[item];
     const bool chunk = it.slot != kNoSlot;
     const uint32_t ne = it.ne < kWaveTile ? it.ne : kWaveTile;  // ne > kWaveTile only with bad offsets
@@ -131,7 +131,10 @@ __global__ __launch_bounds__(kBlock) void pr_items_kernel(PrPullArgs a) {
     }
     double x[kPer];
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) x[k] = ne ? a.contrib_in[u[k]] : 0.0;
+    for (int k = 0; k < kPer; ++k) {
+      const uint32_t uk = static_cast<uint32_t>(u[k]);
+      x[k] = !ne ? 0.0 : (uk < hot ? s_hot[uk] : a.contrib_in[uk]);
+    }
     if (chunk) {
       double s = 0.0;
 #pragma unroll
@@ -206,8 +209,10 @@ __global__ void pr_pull_init_kernel(uint32_t n, const uint32_t* outdeg, double i
   }
 }
 
-// Vertex count of the part of every vertex: part p holds [off[p], off[p+1]).
-__global__ void pr_part_n_kernel(const uint32_t* off, uint32_t parts, uint32_t n, uint32_t* part_n) {
+// Vertex count of the part of every vertex: part p holds [off[p], off[p+1]);
+// stored under the vertex's hot-first name when `perm` is given.
+__global__ void pr_part_n_kernel(const uint32_t* off, uint32_t parts, uint32_t n, const uint32_t* perm,
+                                 uint32_t* part_n) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
     uint32_t lo = 0, hi = parts - 1;  // last part p with off[p] <= v
@@ -216,8 +221,14 @@ __global__ void pr_part_n_kernel(const uint32_t* off, uint32_t parts, uint32_t n
       if (off[mid] <= v) lo = mid;
       else hi = mid - 1;
     }
-    part_n[v] = off[lo + 1] - off[lo];
+    part_n[perm ? perm[v] : v] = off[lo + 1] - off[lo];
   }
+}
+
+// Ranks back to the caller's vertex ids: value[v] = value_hot[perm[v]].
+__global__ void pr_unrename_kernel(const double* value_hot, const uint32_t* perm, uint32_t n, double* value) {
+  for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
+    value[v] = value_hot[perm[v]];
 }
 
 struct PrPushArgs {
@@ -268,31 +279,100 @@ __global__ __launch_bounds__(kBlock) void pr_push_kernel(PrPushArgs a) {
 
 // ------------------------------------------------------------------ host --
 
+// First launch of a pull superstep: the hot-cache form (16-wavefront
+// workgroups, one per CU with the cache in LDS) on a hot-first store, else
+// the plain form.
+// Largest LDS outbox cache of the 16-wavefront form: the device's LDS per
+// workgroup minus the kernel's static tiles (a larger request is rejected
+// by the runtime when the kernel is dispatched).  Queried once.
+static hipError_t max_hot_entries(uint32_t* out) {
+  static uint32_t cached = 0;
+  if (!cached) {
+    hipFuncAttributes attr;
+    hipError_t err = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&pr_items_kernel<16>));
+    if (err != hipSuccess) return err;
+    int dev = 0, lds = 0;
+    if ((err = hipGetDevice(&dev)) != hipSuccess) return err;
+    if ((err = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return err;
+    const size_t room = static_cast<size_t>(lds) > attr.sharedSizeBytes ? lds - attr.sharedSizeBytes : 0;
+    cached = static_cast<uint32_t>(room / sizeof(double)) & ~63u;
+    if (!cached) cached = 1;  // no room: caching is off (see below)
+  }
+  *out = cached;
+  return hipSuccess;
+}
+
+static hipError_t launch_pr_items(const PrPullArgs& a, bool renamed, const Tune& tn, uint32_t n, hipStream_t s) {
+  if (!a.t.ni) return hipSuccess;
+  uint32_t room = 0;
+  hipError_t err = max_hot_entries(&room);
+  if (err != hipSuccess) return err;
+  uint32_t hot = renamed ? std::min(std::min(tn.pr_hot, n), room) : 0;
+  if (hot < 64) hot = 0;
+  if (hot) {
+    constexpr int kW = 16;
+    const uint32_t grid = std::min(a.t.ni, tn.pull_grid / 8 ? tn.pull_grid / 8 : 1u);
+    hipLaunchKernelGGL(pr_items_kernel<kW>, dim3(grid), dim3(kW * kWave), hot * sizeof(double), s, a, hot);
+  } else {
+    hipLaunchKernelGGL(pr_items_kernel<kWavesPerBlock>, dim3(std::min(a.t.ni, tn.pull_grid)), dim3(kBlock), 0, s, a,
+                       0u);
+  }
+  return hipGetLastError();
+}
+
+// What PageRank's pull form runs on: the hot-first store when the graph
+// has one (every per-vertex array of the pull supersteps is then indexed by
+// the new names, and the ranks are mapped back after the last update), else
+// the caller's CSC.
+struct PrPullStore {
+  PullTiling t;
+  const uint32_t* outdeg;
+  const uint32_t* perm;  // null: no renaming
+  double* value;         // ranks as the supersteps store them
+};
+static PrPullStore pr_store_of(const ipg_graph* g, const RunWs& w) {
+  PrPullStore p;
+  if (g->t.perm) {
+    p.t = make_tiling(g->t.off_hot, g->t.src_hot, g->t.pull_hot);
+    p.outdeg = g->t.outdeg_hot;
+    p.perm = g->t.perm;
+    p.value = w.value_hot;
+  } else {
+    p.t = pull_tiling(g);
+    p.outdeg = g->t.outdeg;
+    p.perm = nullptr;
+    p.value = w.value_f64;
+  }
+  return p;
+}
+
 // Every launch of one PageRank run, in order, on stream s (also used to
 // capture the run as a graph, with tm == nullptr).
 static hipError_t enqueue_pagerank(ipg_graph* g, uint32_t T, bool push, const RunWs& w, const uint32_t* part_off,
-                                   uint32_t parts, hipStream_t s, StepTimer* tm) {
+                                   uint32_t parts, const Tune& tn, hipStream_t s, StepTimer* tm) {
   hipError_t err;
   const uint32_t n = g->n;
   const double ratio = 0.15 / static_cast<double>(n);
   const double init = 1.0 / static_cast<double>(n);
   const uint32_t gv = grid_for(n, kBlock, 16384);
+  const PrPullStore ps = pr_store_of(g, w);
   const uint32_t* part_n = nullptr;
   if (part_off) {
-    hipLaunchKernelGGL(pr_part_n_kernel, dim3(gv), dim3(kBlock), 0, s, part_off, parts, n, w.part_n);
+    hipLaunchKernelGGL(pr_part_n_kernel, dim3(gv), dim3(kBlock), 0, s, part_off, parts, n, push ? nullptr : ps.perm,
+                       w.part_n);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     part_n = w.part_n;
   }
   if (!push) {
     if (tm && (err = tm->start(s)) != hipSuccess) return err;
-    hipLaunchKernelGGL(pr_pull_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, g->t.outdeg, init, part_n, w.f64_a,
-                       w.value_f64, T == 0, 0);
+    hipLaunchKernelGGL(pr_pull_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, ps.outdeg, init, part_n, w.f64_a, ps.value,
+                       T == 0, 0);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if (tm && (err = tm->step(s, 0)) != hipSuccess) return err;
     PrPullArgs a;
-    a.t = pull_tiling(g);
-    a.outdeg = g->t.outdeg;
-    a.value = w.value_f64;
+    a.t = ps.t;
+    a.outdeg = ps.outdeg;
+    a.value = ps.value;
     a.partial = w.partial;
     a.ratio = ratio;
     a.part_n = part_n;
@@ -301,16 +381,17 @@ static hipError_t enqueue_pagerank(ipg_graph* g, uint32_t T, bool push, const Ru
       a.contrib_in = (step & 1) ? w.f64_a : w.f64_b;
       a.contrib_out = (step & 1) ? w.f64_b : w.f64_a;
       a.last = step == T;
-      if (g->ni) {
-        hipLaunchKernelGGL(pr_items_kernel, dim3(std::min(g->ni, kPullGrid)), dim3(kBlock), 0, s, a);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
-      }
-      if (g->nl) {
-        hipLaunchKernelGGL(pr_longrow_kernel, dim3((g->nl + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0, s,
-                           a);
+      if ((err = launch_pr_items(a, ps.perm != nullptr, tn, n, s)) != hipSuccess) return err;
+      if (ps.t.nl) {
+        hipLaunchKernelGGL(pr_longrow_kernel, dim3((ps.t.nl + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0,
+                           s, a);
         if ((err = hipGetLastError()) != hipSuccess) return err;
       }
       if (tm && (err = tm->step(s, step)) != hipSuccess) return err;
+    }
+    if (ps.perm) {
+      hipLaunchKernelGGL(pr_unrename_kernel, dim3(gv), dim3(kBlock), 0, s, ps.value, ps.perm, n, w.value_f64);
+      if ((err = hipGetLastError()) != hipSuccess) return err;
     }
   } else {
     if ((err = fill_f64(w.f64_a, n, 0.0, s)) != hipSuccess) return err;
@@ -342,9 +423,10 @@ static hipError_t enqueue_pagerank(ipg_graph* g, uint32_t T, bool push, const Ru
 // The captured graph of the run described by the arguments, capturing it
 // (again) when the handle holds none or one for another run.
 static ipg_status pagerank_graph(ipg_graph* g, uint32_t T, bool push, const RunWs& w, const void* ws,
-                                 const uint32_t* part_off, uint32_t parts, hipGraphExec_t* out) {
+                                 const uint32_t* part_off, uint32_t parts, const Tune& tn, hipGraphExec_t* out) {
   auto& k = g->pr_key;
-  if (g->pr_exec && k.T == T && k.push == (push ? 1 : 0) && k.ws == ws && k.parts == part_off && k.num_parts == parts) {
+  if (g->pr_exec && k.T == T && k.push == (push ? 1 : 0) && k.ws == ws && k.parts == part_off && k.num_parts == parts &&
+      k.hot == tn.pr_hot && k.grid == tn.pull_grid) {
     *out = g->pr_exec;
     return IPG_OK;
   }
@@ -358,7 +440,7 @@ static ipg_status pagerank_graph(ipg_graph* g, uint32_t T, bool push, const RunW
   }
   if (!g->cap_stream) IPG_HIP(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
   IPG_HIP(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
-  const hipError_t qe = enqueue_pagerank(g, T, push, w, part_off, parts, g->cap_stream, nullptr);
+  const hipError_t qe = enqueue_pagerank(g, T, push, w, part_off, parts, tn, g->cap_stream, nullptr);
   hipGraph_t graph = nullptr;
   const hipError_t ce = hipStreamEndCapture(g->cap_stream, &graph);
   if (qe != hipSuccess) {
@@ -373,6 +455,8 @@ static ipg_status pagerank_graph(ipg_graph* g, uint32_t T, bool push, const RunW
   k.ws = ws;
   k.parts = part_off;
   k.num_parts = parts;
+  k.hot = tn.pr_hot;
+  k.grid = tn.pull_grid;
   *out = g->pr_exec;
   return IPG_OK;
 }
@@ -382,15 +466,18 @@ static ipg_status pagerank_graph(ipg_graph* g, uint32_t T, bool push, const RunW
 // first update whose change is below `tol`, or after Tmax updates.
 // Returns the number of updates run in *T_out.
 static ipg_status run_pagerank_converge(ipg_graph* g, uint32_t Tmax, bool push, double tol, const RunWs& w,
-                                        const uint32_t* part_off, uint32_t parts, hipStream_t s, StepTimer& tm,
+                                        const uint32_t* part_off, uint32_t parts, const Tune& tn, hipStream_t s,
+                                        StepTimer& tm,
                                         ipg_run_stats* st, uint32_t* T_out, bool* converged) {
   const uint32_t n = g->n;
   const double ratio = 0.15 / static_cast<double>(n);
   const double init = 1.0 / static_cast<double>(n);
   const uint32_t gv = grid_for(n, kBlock, 16384);
+  const PrPullStore ps = pr_store_of(g, w);
   const uint32_t* part_n = nullptr;
   if (part_off) {
-    hipLaunchKernelGGL(pr_part_n_kernel, dim3(gv), dim3(kBlock), 0, s, part_off, parts, n, w.part_n);
+    hipLaunchKernelGGL(pr_part_n_kernel, dim3(gv), dim3(kBlock), 0, s, part_off, parts, n, push ? nullptr : ps.perm,
+                       w.part_n);
     IPG_HIP(hipGetLastError());
     part_n = w.part_n;
   }
@@ -411,14 +498,14 @@ static ipg_status run_pagerank_converge(ipg_graph* g, uint32_t Tmax, bool push, 
   if (st && st->residual && st->trace_cap) st->residual[0] = 0.0;
   if (!push) {
     IPG_HIP(tm.start(s));
-    hipLaunchKernelGGL(pr_pull_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, g->t.outdeg, init, part_n, w.f64_a,
-                       w.value_f64, 0, 1);
+    hipLaunchKernelGGL(pr_pull_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, ps.outdeg, init, part_n, w.f64_a, ps.value,
+                       0, 1);
     IPG_HIP(hipGetLastError());
     IPG_HIP(tm.step(s, 0));
     PrPullArgs a;
-    a.t = pull_tiling(g);
-    a.outdeg = g->t.outdeg;
-    a.value = w.value_f64;
+    a.t = ps.t;
+    a.outdeg = ps.outdeg;
+    a.value = ps.value;
     a.partial = w.partial;
     a.ratio = ratio;
     a.part_n = part_n;
@@ -428,13 +515,10 @@ static ipg_status run_pagerank_converge(ipg_graph* g, uint32_t Tmax, bool push, 
       IPG_HIP(fill_f64(w.l1, kSlotDoubles, 0.0, s));
       a.contrib_in = (step & 1) ? w.f64_a : w.f64_b;
       a.contrib_out = (step & 1) ? w.f64_b : w.f64_a;
-      if (g->ni) {
-        hipLaunchKernelGGL(pr_items_kernel, dim3(std::min(g->ni, kPullGrid)), dim3(kBlock), 0, s, a);
-        IPG_HIP(hipGetLastError());
-      }
-      if (g->nl) {
-        hipLaunchKernelGGL(pr_longrow_kernel, dim3((g->nl + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0, s,
-                           a);
+      IPG_HIP(launch_pr_items(a, ps.perm != nullptr, tn, n, s));
+      if (ps.t.nl) {
+        hipLaunchKernelGGL(pr_longrow_kernel, dim3((ps.t.nl + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0,
+                           s, a);
         IPG_HIP(hipGetLastError());
       }
       IPG_HIP(tm.step(s, step));
@@ -446,6 +530,10 @@ static ipg_status run_pagerank_converge(ipg_graph* g, uint32_t Tmax, bool push, 
         *converged = true;
         break;
       }
+    }
+    if (ps.perm) {
+      hipLaunchKernelGGL(pr_unrename_kernel, dim3(gv), dim3(kBlock), 0, s, ps.value, ps.perm, n, w.value_f64);
+      IPG_HIP(hipGetLastError());
     }
   } else {
     IPG_HIP(fill_f64(w.f64_a, n, 0.0, s));
@@ -490,6 +578,9 @@ ipg_status run_pagerank(ipg_graph* g, uint32_t T, const ipg_run_opts& o, const R
                         hipStream_t s, StepTimer& tm, ipg_run_stats* st) {
   const uint32_t n = g->n;
   const bool push = (o.mode == IPG_MODE_PUSH);
+  const Tune tn = resolve_tuning(o.tuning);
+  uint32_t room = 0;
+  IPG_HIP(max_hot_entries(&room));  // queried here, never during a stream capture
   const uint32_t* part_off = nullptr;
   uint32_t parts = 0;
   if (o.part_offsets && o.num_parts) {
@@ -505,19 +596,19 @@ ipg_status run_pagerank(ipg_graph* g, uint32_t T, const ipg_run_opts& o, const R
   bool converged = true;
   if (o.tolerance > 0.0) {
     uint32_t Tdone = T;
-    const ipg_status rc = run_pagerank_converge(g, T, push, o.tolerance, w, part_off, parts, s, tm, st, &Tdone,
+    const ipg_status rc = run_pagerank_converge(g, T, push, o.tolerance, w, part_off, parts, tn, s, tm, st, &Tdone,
                                                 &converged);
     if (rc != IPG_OK) return rc;
     T = Tdone;
   } else if (o.flags & IPG_RUN_GRAPH) {
     hipGraphExec_t exec = nullptr;
-    const ipg_status rc = pagerank_graph(g, T, push, w, ws, part_off, parts, &exec);
+    const ipg_status rc = pagerank_graph(g, T, push, w, ws, part_off, parts, tn, &exec);
     if (rc != IPG_OK) return rc;
     IPG_HIP(tm.start(s));
     IPG_HIP(hipGraphLaunch(exec, s));
     IPG_HIP(tm.finish(s));
   } else {
-    IPG_HIP(enqueue_pagerank(g, T, push, w, part_off, parts, s, &tm));
+    IPG_HIP(enqueue_pagerank(g, T, push, w, part_off, parts, tn, s, &tm));
     IPG_HIP(tm.finish(s));
   }
   // The PageRank trace is fixed by Fig. 8: every vertex runs in every

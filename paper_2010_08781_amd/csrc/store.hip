@@ -123,17 +123,157 @@ __global__ void row_degrees_kernel(const uint64_t* off, const uint32_t* rows, ui
 }
 
 
-static size_t carve_graph(Carver& c, uint32_t n, uint64_t e, GraphTables* t) {
-  GraphTables tt;
+// Hot-first CSC: row v of the caller's CSC becomes row perm[v], its
+// sources renamed, in their original order (one wavefront per row).
+__global__ void rename_rows_kernel(const uint64_t* off, const int32_t* src, uint32_t n, const uint32_t* perm,
+                                   const uint64_t* off_hot, int32_t* src_hot) {
+  const uint64_t nw = (uint64_t)gridDim.x * blockDim.x / kWave;
+  for (uint64_t v = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / kWave; v < n; v += nw) {
+    const uint64_t b = off[v], d = off[v + 1] - b, h = off_hot[perm[v]];
+    for (uint64_t j = lane_id(); j < d; j += kWave) src_hot[h + j] = static_cast<int32_t>(perm[src[b + j]]);
+  }
+}
+
+// out[perm[v]] = in[v].
+__global__ void scatter_u32_kernel(const uint32_t* in, const uint32_t* perm, uint32_t n, uint32_t* out) {
+  for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
+    out[perm[v]] = in[v];
+}
+
+static void carve_tiling(Carver& c, uint32_t n, uint64_t e, TilingTables* t) {
+  t->pull_rb = c.take<uint32_t>(num_pull_groups(e) + 1);
+  t->long_rows = c.take<uint32_t>(long_rows_cap(e));
+  t->lr_first = c.take<uint32_t>(long_rows_cap(e) + 1);
+  t->ch_row = c.take<uint32_t>(chunks_cap(e));
+  t->items = c.take<PullItem>(items_cap(n, e));
+  t->nb = t->nl = t->nc = t->ni = 0;
+}
+
+static size_t carve_graph(Carver& c, uint32_t n, uint64_t e, uint32_t flags, GraphTables* t) {
+  GraphTables tt{};
   tt.outdeg = c.take<uint32_t>(n ? n : 1);
-  tt.pull_rb = c.take<uint32_t>(num_pull_groups(e) + 1);
-  tt.long_rows = c.take<uint32_t>(long_rows_cap(e));
-  tt.lr_first = c.take<uint32_t>(long_rows_cap(e) + 1);
-  tt.ch_row = c.take<uint32_t>(chunks_cap(e));
-  tt.items = c.take<PullItem>(items_cap(n, e));
   tt.flags = c.take<uint32_t>(kNumFlags + 1);  // + long-row counter
+  carve_tiling(c, n, e, &tt.pull);
+  if (flags & IPG_GRAPH_RENAME) {
+    tt.perm = c.take<uint32_t>(n ? n : 1);
+    tt.outdeg_hot = c.take<uint32_t>(n ? n : 1);
+    tt.off_hot = c.take<uint64_t>((size_t)n + 1);
+    tt.src_hot = c.take<int32_t>(e ? e : 1);
+    carve_tiling(c, n, e, &tt.pull_hot);
+  }
   if (t) *t = tt;
   return align_up(c.used, 256);
+}
+
+// Pull tiling of a CSC (validated offsets): row-groups, long rows cut into
+// chunks, and the work items.  `counter` is one device word of scratch.
+static ipg_status build_tiling(const uint64_t* csc_off, uint32_t n, uint64_t e, TilingTables* t, uint32_t* counter,
+                               hipStream_t s) {
+  const uint32_t nb = num_pull_groups(e);
+  const uint32_t gv = grid_for(n + 1ull, kBlock, 16384);
+  IPG_HIP(fill_u32(counter, 1, 0, s));
+  hipLaunchKernelGGL(pull_groups_kernel, dim3(gv), dim3(kBlock), 0, s, csc_off, n, nb, t->pull_rb);
+  IPG_HIP(hipGetLastError());
+  const uint32_t cap = static_cast<uint32_t>(long_rows_cap(e));
+  hipLaunchKernelGGL(long_rows_kernel, dim3(gv), dim3(kBlock), 0, s, csc_off, n, t->long_rows, cap, counter);
+  IPG_HIP(hipGetLastError());
+  uint32_t nl = 0;
+  IPG_HIP(hipMemcpyAsync(&nl, counter, sizeof(nl), hipMemcpyDeviceToHost, s));
+  IPG_HIP(hipStreamSynchronize(s));
+  if (nl > cap) return fail(IPG_EBADGRAPH, "in-degree table overflow (offsets inconsistent with E)");
+  uint32_t nc = 0;
+  std::vector<uint32_t> lrows(nl), lfirst(nl + 1, 0);
+  if (nl > 0) {
+    // Long rows in ascending order (a deterministic assignment to
+    // workgroups), cut into chunks of kWaveTile in-edges.
+    IPG_HIP(hipMemcpyAsync(lrows.data(), t->long_rows, nl * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    IPG_HIP(hipStreamSynchronize(s));
+    std::sort(lrows.begin(), lrows.end());
+    IPG_HIP(hipMemcpyAsync(t->long_rows, lrows.data(), nl * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    // degrees via the item table's space (24 bytes per item, more items than long rows)
+    uint64_t* degs = reinterpret_cast<uint64_t*>(t->items);
+    hipLaunchKernelGGL(row_degrees_kernel, dim3(grid_for(nl, kBlock, 1024)), dim3(kBlock), 0, s, csc_off, t->long_rows,
+                       nl, degs);
+    IPG_HIP(hipGetLastError());
+    std::vector<uint64_t> deg(nl);
+    IPG_HIP(hipMemcpyAsync(deg.data(), degs, nl * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    IPG_HIP(hipStreamSynchronize(s));
+    std::vector<uint32_t> chrow;
+    uint64_t acc = 0;
+    for (uint32_t l = 0; l < nl; ++l) {
+      lfirst[l] = static_cast<uint32_t>(acc);
+      const uint64_t k = (deg[l] + kWaveTile - 1) / kWaveTile;
+      acc += k;
+      if (acc > chunks_cap(e)) return fail(IPG_EBADGRAPH, "long-row chunk table overflow (offsets inconsistent with E)");
+      for (uint64_t j = 0; j < k; ++j) chrow.push_back(l);
+    }
+    lfirst[nl] = static_cast<uint32_t>(acc);
+    nc = static_cast<uint32_t>(acc);
+    IPG_HIP(hipMemcpyAsync(t->lr_first, lfirst.data(), (nl + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    IPG_HIP(hipMemcpyAsync(t->ch_row, chrow.data(), nc * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    IPG_HIP(hipStreamSynchronize(s));
+  }
+  // Pull work items: the long-row chunks, then each row-group cut into
+  // pieces of at most kItemRows rows (a group's long last row is chunked).
+  std::vector<uint32_t> rb(nb + 1);
+  IPG_HIP(hipMemcpyAsync(rb.data(), t->pull_rb, (nb + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  IPG_HIP(hipStreamSynchronize(s));
+  std::vector<PullItem> items;
+  items.reserve(static_cast<size_t>(nb) + nc + n / kItemRows + 1);
+  for (uint32_t l = 0; l < nl; ++l)
+    for (uint32_t j = lfirst[l]; j < lfirst[l + 1]; ++j)
+      items.push_back(PullItem{j - lfirst[l], 0, lrows[l], lrows[l] + 1, j});
+  for (uint32_t k = 0; k < nb; ++k) {
+    const uint32_t r0 = rb[k];
+    uint32_t r1 = rb[k + 1];
+    if (r1 > r0 && std::binary_search(lrows.begin(), lrows.end(), r1 - 1)) --r1;
+    for (uint32_t a = r0; a < r1; a += kItemRows) items.push_back(PullItem{0, 0, a, std::min(r1, a + kItemRows), kNoSlot});
+  }
+  if (items.size() > items_cap(n, e)) return fail(IPG_EBADGRAPH, "pull item table overflow");
+  const uint32_t ni = static_cast<uint32_t>(items.size());
+  if (ni) {
+    IPG_HIP(hipMemcpyAsync(t->items, items.data(), ni * sizeof(PullItem), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(item_edges_kernel, dim3(grid_for(ni, kBlock, 4096)), dim3(kBlock), 0, s, csc_off, t->items, ni);
+    IPG_HIP(hipGetLastError());
+    IPG_HIP(hipStreamSynchronize(s));
+  }
+  t->nb = nb;
+  t->nl = nl;
+  t->nc = nc;
+  t->ni = ni;
+  return IPG_OK;
+}
+
+// The hot-first store: names by descending out-degree (degrees above 65534
+// tie; ties in id order -- a counting sort on the host), the CSC rebuilt
+// under those names and its tiling.
+static ipg_status build_hot_store(const uint64_t* csc_off, const int32_t* csc_src, uint32_t n, uint64_t e,
+                                  GraphTables* t, hipStream_t s) {
+  std::vector<uint32_t> deg(n), perm(n);
+  IPG_HIP(hipMemcpyAsync(deg.data(), t->outdeg, n * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  std::vector<uint64_t> off((size_t)n + 1), off_hot((size_t)n + 1, 0);
+  IPG_HIP(hipMemcpyAsync(off.data(), csc_off, off.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  IPG_HIP(hipStreamSynchronize(s));
+  constexpr uint32_t kKeys = 1u << 16;
+  std::vector<uint64_t> start(kKeys + 1, 0);
+  auto key = [&](uint32_t v) { return kKeys - 1 - std::min<uint32_t>(deg[v], kKeys - 1); };
+  for (uint32_t v = 0; v < n; ++v) ++start[key(v) + 1];
+  for (uint32_t k = 0; k < kKeys; ++k) start[k + 1] += start[k];
+  for (uint32_t v = 0; v < n; ++v) perm[v] = static_cast<uint32_t>(start[key(v)]++);
+  for (uint32_t v = 0; v < n; ++v) off_hot[(size_t)perm[v] + 1] = off[v + 1] - off[v];
+  for (uint32_t r = 0; r < n; ++r) off_hot[(size_t)r + 1] += off_hot[r];
+  IPG_HIP(hipMemcpyAsync(t->perm, perm.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  IPG_HIP(hipMemcpyAsync(t->off_hot, off_hot.data(), off_hot.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  const uint32_t gv = grid_for(n, kBlock, 16384);
+  hipLaunchKernelGGL(scatter_u32_kernel, dim3(gv), dim3(kBlock), 0, s, t->outdeg, t->perm, n, t->outdeg_hot);
+  IPG_HIP(hipGetLastError());
+  if (e) {
+    hipLaunchKernelGGL(rename_rows_kernel, dim3(grid_for(n, kWavesPerBlock, 16384)), dim3(kBlock), 0, s, csc_off,
+                       csc_src, n, t->perm, t->off_hot, t->src_hot);
+    IPG_HIP(hipGetLastError());
+  }
+  IPG_HIP(hipStreamSynchronize(s));
+  return build_tiling(t->off_hot, n, e, &t->pull_hot, t->flags + kNumFlags, s);
 }
 
 }  // namespace ipg
@@ -141,9 +281,8 @@ static size_t carve_graph(Carver& c, uint32_t n, uint64_t e, GraphTables* t) {
 using namespace ipg;
 
 extern "C" size_t ipg_graph_workspace_bytes(uint32_t num_vertices, uint64_t num_edges, uint32_t flags) {
-  (void)flags;
   Carver c(nullptr);
-  return carve_graph(c, num_vertices, num_edges, nullptr);
+  return carve_graph(c, num_vertices, num_edges, flags, nullptr);
 }
 
 extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t ws_bytes, void* hip_stream,
@@ -172,8 +311,7 @@ extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   Carver c(ws);
   GraphTables t;
-  carve_graph(c, n, e, &t);
-  const uint32_t nb = num_pull_groups(e);
+  carve_graph(c, n, e, d->flags, &t);
 
   IPG_HIP(fill_u32(t.flags, kNumFlags + 1, 0, s));
   const uint32_t gv = grid_for(n + 1ull, kBlock, 16384), ge = grid_for(e, kBlock * 8, 16384);
@@ -198,82 +336,15 @@ extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t
   }
   hipLaunchKernelGGL(outdeg_kernel, dim3(gv), dim3(kBlock), 0, s, d->csr_off, n, t.outdeg, t.flags);
   IPG_HIP(hipGetLastError());
-  hipLaunchKernelGGL(pull_groups_kernel, dim3(gv), dim3(kBlock), 0, s, csc_off, n, nb, t.pull_rb);
-  IPG_HIP(hipGetLastError());
-  const uint32_t cap = static_cast<uint32_t>(long_rows_cap(e));
-  hipLaunchKernelGGL(long_rows_kernel, dim3(gv), dim3(kBlock), 0, s, csc_off, n, t.long_rows, cap,
-                     t.flags + kNumFlags);
-  IPG_HIP(hipGetLastError());
-  uint32_t h[kNumFlags + 1];
+  uint32_t h[kNumFlags];
   IPG_HIP(hipMemcpyAsync(h, t.flags, sizeof(h), hipMemcpyDeviceToHost, s));
   IPG_HIP(hipStreamSynchronize(s));
   if (h[kFlagDegree]) return fail(IPG_EBADGRAPH, "an out-degree exceeds 2^32-1");
-  const uint32_t nl = h[kNumFlags];
-  if (nl > cap) return fail(IPG_EBADGRAPH, "in-degree table overflow (offsets inconsistent with E)");
-  uint32_t nc = 0;
-  if (nl > 0) {
-    // Long rows in ascending order (a deterministic assignment to
-    // workgroups), cut into chunks of kWaveTile in-edges.
-    std::vector<uint32_t> rows(nl);
-    IPG_HIP(hipMemcpyAsync(rows.data(), t.long_rows, nl * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    IPG_HIP(hipStreamSynchronize(s));
-    std::sort(rows.begin(), rows.end());
-    IPG_HIP(hipMemcpyAsync(t.long_rows, rows.data(), nl * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    // degrees via the item table's space (24 bytes per item, more items than long rows)
-    uint64_t* degs = reinterpret_cast<uint64_t*>(t.items);
-    hipLaunchKernelGGL(row_degrees_kernel, dim3(grid_for(nl, kBlock, 1024)), dim3(kBlock), 0, s, csc_off, t.long_rows, nl,
-                       degs);
-    IPG_HIP(hipGetLastError());
-    std::vector<uint64_t> deg(nl);
-    IPG_HIP(hipMemcpyAsync(deg.data(), degs, nl * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    IPG_HIP(hipStreamSynchronize(s));
-    std::vector<uint32_t> first(nl + 1), chrow;
-    uint64_t acc = 0;
-    for (uint32_t l = 0; l < nl; ++l) {
-      first[l] = static_cast<uint32_t>(acc);
-      const uint64_t k = (deg[l] + kWaveTile - 1) / kWaveTile;
-      acc += k;
-      if (acc > chunks_cap(e)) return fail(IPG_EBADGRAPH, "long-row chunk table overflow (offsets inconsistent with E)");
-      for (uint64_t j = 0; j < k; ++j) chrow.push_back(l);
-    }
-    first[nl] = static_cast<uint32_t>(acc);
-    nc = static_cast<uint32_t>(acc);
-    IPG_HIP(hipMemcpyAsync(t.lr_first, first.data(), (nl + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    IPG_HIP(hipMemcpyAsync(t.ch_row, chrow.data(), nc * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    IPG_HIP(hipStreamSynchronize(s));
-  }
-
-  // Pull work items: the long-row chunks, then each row-group cut into
-  // pieces of at most kItemRows rows (a group's long last row is chunked).
-  uint32_t ni = 0;
-  {
-    std::vector<uint32_t> rb(nb + 1), lrows(nl), lfirst(nl + 1);
-    IPG_HIP(hipMemcpyAsync(rb.data(), t.pull_rb, (nb + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    if (nl) {
-      IPG_HIP(hipMemcpyAsync(lrows.data(), t.long_rows, nl * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-      IPG_HIP(hipMemcpyAsync(lfirst.data(), t.lr_first, (nl + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    }
-    IPG_HIP(hipStreamSynchronize(s));
-    std::vector<PullItem> items;
-    items.reserve(static_cast<size_t>(nb) + nc + n / kItemRows + 1);
-    for (uint32_t l = 0; l < nl; ++l)
-      for (uint32_t j = lfirst[l]; j < lfirst[l + 1]; ++j)
-        items.push_back(PullItem{j - lfirst[l], 0, lrows[l], lrows[l] + 1, j});
-    for (uint32_t k = 0; k < nb; ++k) {
-      const uint32_t r0 = rb[k];
-      uint32_t r1 = rb[k + 1];
-      if (r1 > r0 && std::binary_search(lrows.begin(), lrows.end(), r1 - 1)) --r1;
-      for (uint32_t a = r0; a < r1; a += kItemRows)
-        items.push_back(PullItem{0, 0, a, std::min(r1, a + kItemRows), kNoSlot});
-    }
-    if (items.size() > items_cap(n, e)) return fail(IPG_EBADGRAPH, "pull item table overflow");
-    ni = static_cast<uint32_t>(items.size());
-    if (ni) {
-      IPG_HIP(hipMemcpyAsync(t.items, items.data(), ni * sizeof(PullItem), hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(item_edges_kernel, dim3(grid_for(ni, kBlock, 4096)), dim3(kBlock), 0, s, csc_off, t.items, ni);
-      IPG_HIP(hipGetLastError());
-      IPG_HIP(hipStreamSynchronize(s));
-    }
+  ipg_status rc = build_tiling(csc_off, n, e, &t.pull, t.flags + kNumFlags, s);
+  if (rc != IPG_OK) return rc;
+  if (d->flags & IPG_GRAPH_RENAME) {
+    rc = build_hot_store(csc_off, csc_src, n, e, &t, s);
+    if (rc != IPG_OK) return rc;
   }
 
   ipg_graph* g = new (std::nothrow) ipg_graph();
@@ -288,10 +359,6 @@ extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t
   g->csr_w = d->csr_w;
   g->csc_w = csc_w;
   g->t = t;
-  g->nb = nb;
-  g->nl = nl;
-  g->nc = nc;
-  g->ni = ni;
   IPG_HIP(hipGetDevice(&g->device));
   g->has_values = 0;
   g->last_app = -1;

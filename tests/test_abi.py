@@ -85,7 +85,7 @@ def test_footprint_report_adds_up(lib):
     import paper_2010_08781_amd as ipg
 
     n, m = 1 << 20, 31 << 20
-    f = ipg.footprint(n, m, symmetric=True)
+    f = ipg.footprint(n, m, symmetric=True, rename=False)
     assert f["graph_arrays"]["csc"] == 0 and f["graph_arrays"]["csr"] == 8 * (n + 1) + 4 * m
     d = ipg.footprint(n, m, symmetric=False, weighted=True)
     assert d["graph_arrays"]["csc"] == d["graph_arrays"]["csr"] and d["graph_arrays"]["weights"] == 8 * m
@@ -96,3 +96,6 @@ def test_footprint_report_adds_up(lib):
     # batched SSSP: 256-bit visited and receive rows plus a 16-superstep ring of level masks
     assert f["bytes_per_vertex_run"]["multi_sssp"] < (16 + 2) * 32 + 64
     assert 4.0 <= f["bytes_per_edge"]["cc"] < 6.5
+    # the hot-first copy of the sources adds 4 bytes per edge and 4 per vertex
+    r = ipg.footprint(n, m, symmetric=True, rename=True)
+    assert r["graph_workspace"] - f["graph_workspace"] >= 4 * m + 4 * n

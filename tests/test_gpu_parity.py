@@ -274,3 +274,77 @@ def test_push_hub_senders(ipg):
         g = ipg.Graph.from_host(hg)
         vals, st = g.run(app, source=source, mode="push", persistent=True)
         assert np.array_equal(to_np(vals), ref.values) and np.array_equal(st.trace, ref.trace)
+
+
+@pytest.mark.parametrize("sym", [False, True])
+def test_pagerank_hot_first_store(ipg, sym):
+    # The renamed store (vertices renamed by descending out-degree, the CSC
+    # rebuilt under the new names) sums the same values per row; only the
+    # grouping of rows into work items changes, so ranks agree with the
+    # oracle and with the plain store within the PageRank tolerance, and
+    # the renamed runs are deterministic.
+    import torch
+
+    hg = graphgen.rmat(15, 16, seed=8, symmetric=sym)
+    a = ipg.Graph.from_host(hg, rename=True)
+    b = ipg.Graph.from_host(hg, rename=False)
+    for T in (0, 1, 10):
+        ref = oracle.run_graph("pagerank", hg, T)
+        ra, _ = a.run("pagerank", T, mode="pull")
+        rb, _ = b.run("pagerank", T, mode="pull")
+        assert max_rel(to_np(ra), ref.values) <= PR_RTOL and max_rel(to_np(rb), ref.values) <= PR_RTOL
+        assert torch.equal(ra, a.run("pagerank", T, mode="pull")[0])
+    d = oracle.pagerank_deltas(hg.n, hg.csr_off, hg.csr_dst, 200)
+    tol = 1e-9
+    while np.any(np.abs(d[1:] - tol) <= max(1e-6 * tol, 1e-12)):
+        tol *= 1.37
+    ref, T, _ = oracle.pagerank_converge(hg, tol, 200)
+    ca, sa = a.run("pagerank", 200, mode="pull", tol=tol)
+    assert sa.supersteps == T + 1 and max_rel(to_np(ca), ref.values) <= PR_RTOL
+    # parts: each part's N, under the new names
+    parts = torch.tensor([0, 1000, hg.n], dtype=torch.int32, device="cuda")
+    pa, _ = a.run("pagerank", 5, parts=parts)
+    pb, _ = b.run("pagerank", 5, parts=parts)
+    assert max_rel(to_np(pa), to_np(pb)) <= PR_RTOL
+    # graph replay of the renamed run
+    assert torch.equal(a.run("pagerank", 10, mode="pull", graph=True)[0], a.run("pagerank", 10, mode="pull")[0])
+    # CC and SSSP read the caller's CSC either way
+    for app in ("cc", "sssp"):
+        assert torch.equal(a.run(app)[0], b.run(app)[0])
+
+
+def test_launch_parameters_never_change_results(ipg):
+    # every point of the autotuner's search space: PageRank within the
+    # tolerance of the oracle, CC / SSSP / batched SSSP exact
+    from paper_2010_08781_amd import autotune
+
+    hg = graphgen.rmat(15, 16, seed=9, symmetric=True)
+    g = ipg.Graph.from_host(hg)
+    ref = oracle.run_graph("pagerank", hg, 10)
+    for hot in autotune.SPACES["pagerank"]["pr_hot"]:
+        for grid in (64, 1024, 4096):
+            r, _ = g.run("pagerank", 10, mode="pull", tuning={"pr_hot": hot, "pull_grid": grid})
+            assert max_rel(to_np(r), ref.values) <= PR_RTOL, (hot, grid)
+    for app in ("cc", "sssp"):
+        ref = oracle.run_graph(app, hg, 0, source=0)
+        for t in ({"push_div": 10, "list_div": 8, "pull_grid": 64}, {"push_div": 40, "list_div": 32},
+                  {"push_div": 1}, {"push_div": 100000}):
+            for persistent in (False, True):
+                v, st = g.run(app, tuning=t, persistent=persistent)
+                assert np.array_equal(to_np(v), ref.values) and np.array_equal(st.trace, ref.trace), (app, t)
+    src = graphgen.pick_sources(hg, 40, seed=1)
+    want = g.run_multi_sssp(src)[0]
+    for t in ({"push_div": 5, "pull_grid": 64}, {"push_div": 40, "pull_grid": 4096}):
+        assert np.array_equal(g.run_multi_sssp(src, tuning=t)[0].cpu().numpy(), want.cpu().numpy())
+
+
+def test_autotune_on_device(ipg, tmp_path):
+    from paper_2010_08781_amd import autotune
+
+    hg = graphgen.rmat(14, 16, seed=1)
+    g = ipg.Graph.from_host(hg)
+    best = autotune.tune(g, hg, "pagerank", cache_path=str(tmp_path / "t.json"), reps=1)
+    r, _ = g.run("pagerank", 10, tuning=best)
+    assert max_rel(to_np(r), oracle.run_graph("pagerank", hg, 10).values) <= PR_RTOL
+    best = autotune.tune(g, hg, "sssp", cache_path=str(tmp_path / "t.json"), reps=1)
+    assert set(best) == {"push_div", "list_div", "pull_grid"}
