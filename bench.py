@@ -31,7 +31,41 @@ def pr_pull_bytes(n: int, m: int) -> int:
     return 4 * m + 8 * (n + 1) + 8 * n + 4 * n + 8 * n
 
 
-def batched_vs_plain(ipg, graphgen, np, torch, reps: int = 3) -> dict:
+# HBM traffic of the PageRank pull kernel from the committed rocprofv3 PMC
+# summary: valid only while the kernel sources are the ones it was taken on.
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pr_pull_traffic_{workload}.md")
+KERNEL_SOURCES = ("paper_2010_08781_amd/csrc/pagerank.hip", "paper_2010_08781_amd/csrc/common.h",
+                  "paper_2010_08781_amd/csrc/engine.h", "paper_2010_08781_amd/csrc/store.hip")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha1()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:12]
+
+
+def measured_traffic(workload: str, tuning) -> "int | None":
+    """Bytes per superstep (FETCH_SIZE + WRITE_SIZE, each scaled by the copy
+    calibration) recorded for this workload and launch parameters, or None."""
+    import re
+
+    path = TRAFFIC_SUMMARY.format(workload=workload)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"traffic_bytes_per_superstep:\s*(\d+)\s+sources:\s*([0-9a-f]+)\s+tuning:\s*(\{.*\})", text)
+    if not m or m.group(2) != kernel_source_hash():
+        return None
+    if json.loads(m.group(3)) != (tuning or {}):
+        return None
+    return int(m.group(1))
+
+
+def batched_vs_plain(ipg, graphgen, np, torch, reps: int = 3, tune_cache=None) -> dict:
     """End-to-end time of the batched workload against the plain form on the
     same GPU: 256 unit-weight SSSP queries (sources seeded among vertices with
     out-edges) on R-MAT scale 22 symmetrised, plus 64 directed R-MAT graphs
@@ -47,7 +81,6 @@ def batched_vs_plain(ipg, graphgen, np, torch, reps: int = 3) -> dict:
     gu = ipg.Graph.from_host(u)
     parts = torch.from_numpy(u.meta["parts"].astype(np.int32)).cuda()
     gs = [ipg.Graph.from_host(h) for h in fam]
-    del hg
 
     def timed(fn):
         fn()
@@ -64,8 +97,12 @@ def batched_vs_plain(ipg, graphgen, np, torch, reps: int = 3) -> dict:
     out = {}
     st_b = {}
 
+    from paper_2010_08781_amd import autotune
+
+    tms = autotune.tune(g, hg, "multi_sssp", cache_path=tune_cache, reps=1, sources=src, out=d) if tune_cache else None
+
     def b_sssp():
-        st_b["s"] = g.run_multi_sssp(src, out=d, timing=False)[1]
+        st_b["s"] = g.run_multi_sssp(src, out=d, timing=False, tuning=tms)[1]
 
     def p_sssp():
         for s in src:
@@ -88,6 +125,7 @@ def batched_vs_plain(ipg, graphgen, np, torch, reps: int = 3) -> dict:
     tb, tp = t["b_sssp"] + t["b_pr"], t["p_sssp"] + t["p_pr"]
     out["end_to_end"] = {"batched_ms": round(tb * 1e3, 3), "plain_ms": round(tp * 1e3, 3),
                          "speedup": round(tp / tb, 2)}
+    out["sssp256_rmat_s22"]["tuning"] = tms
     for h in gs + [g, gu]:
         h.close()
     return out
@@ -105,6 +143,9 @@ def main():
                     help="what AUTO uses to pick the exchange: the trained network or the fixed rule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apps", default="pagerank,cc,sssp")
+    ap.add_argument("--no-tune", action="store_true", help="run with the library's default launch parameters")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tuning_cache.json"),
+                    help="autotuner cache file")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain comparison (256-source SSSP on R-MAT s22 + 64 small PageRank graphs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -149,13 +190,23 @@ def main():
         if sel is None:
             sys.exit("bench.py: --selector learned but no trained selector parameters are installed")
 
+    # launch parameters from the autotuner (untimed; cached per graph signature)
+    tun = {app: None for app in apps}
+    if not args.no_tune:
+        from paper_2010_08781_amd import autotune
+
+        t0 = time.perf_counter()
+        for app in apps:
+            tun[app] = autotune.tune(g, hg, app, cache_path=args.tune_cache, reps=2, updates=T)
+        print(f"[bench] autotuned {tun} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+
     def one_step(selector=sel):
         out = {}
         for app in apps:
             if app == "pagerank":
-                _, st = g.run("pagerank", T, mode="pull", timing=True)
+                _, st = g.run("pagerank", T, mode="pull", timing=True, tuning=tun[app])
             else:
-                _, st = g.run(app, source=0, mode=args.mode, timing=True, selector=selector)
+                _, st = g.run(app, source=0, mode=args.mode, timing=True, selector=selector, tuning=tun[app])
             out[app] = st
         return out
 
@@ -196,7 +247,7 @@ def main():
         for app in apps:
             if app == "pagerank":
                 continue
-            plain = np.median([g.run(app, source=0, mode="auto", timing=True)[1].seconds
+            plain = np.median([g.run(app, source=0, mode="auto", timing=True, tuning=tun[app])[1].seconds
                                for _ in range(max(3, args.steps))])
             mine = apps_out[app]["time_to_converge_ms_median"] / 1e3
             learned_vs_plain[app] = {"learned_ms": round(mine * 1e3, 4), "plain_ms": round(float(plain) * 1e3, 4),
@@ -204,7 +255,7 @@ def main():
 
     batched = None
     if not args.no_batched:
-        batched = batched_vs_plain(ipg, graphgen, np, torch)
+        batched = batched_vs_plain(ipg, graphgen, np, torch, tune_cache=None if args.no_tune else args.tune_cache)
         print(f"[bench] batched vs plain: {json.dumps(batched['end_to_end'])}", file=sys.stderr, flush=True)
 
     roofline = None
@@ -216,10 +267,12 @@ def main():
         avg_us = float(np.mean(us))
         nbytes = pr_pull_bytes(hg.n, hg.m)
         ach = nbytes / (avg_us * 1e-6) / 1e9
+        traffic = measured_traffic(args.workload, tun.get("pagerank"))
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                    "kernel": "pr_items_kernel+pr_longrow_kernel (one PageRank pull superstep)",
-                    "bytes_per_launch": nbytes, "avg_launch_us": round(avg_us, 2)}
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "kernel": "pr_items_kernel + pr_longrow_kernel (one PageRank pull superstep)",
+                    "bytes_per_launch": nbytes, "avg_launch_us": round(avg_us, 2),
+                    "tuning": tun.get("pagerank"), "kernel_sources": kernel_source_hash()}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -254,6 +307,7 @@ def main():
                         f"{' (trained selector)' if sel is not None else ''}",
             "n": hg.n, "m": hg.m, "apps": apps_out,
         },
+        "tuning": tun,
         "footprint": {k: v for k, v in ipg.footprint(hg.n, hg.m, symmetric=bool(hg.symmetric),
                                                       weighted=hg.csr_w is not None).items()
                       if k in ("total", "bytes_per_edge", "graph_workspace")},
