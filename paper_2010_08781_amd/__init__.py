@@ -94,6 +94,11 @@ def lib():
     """Load libipregel.so; raises if it has not been built (there is no fallback)."""
     global _lib
     if _lib is None:
+        # PyTorch ships its own HIP runtime under the same soname; importing
+        # it first makes the library bind to that runtime instead of loading
+        # a second one into the process (two runtimes do not share the GPU).
+        import torch  # noqa: F401
+
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it first (python __graft_entry__.py or "
                               f"python paper_2010_08781_amd/build.py)")

@@ -1,7 +1,9 @@
 """Training data, GPU training and evaluation of the learned exchange selector.
 
 Labels come from timing the plain method.  Every CC/SSSP run is repeated
-with the exchange forced to push and forced to pull.  The state at the start
+with the exchange forced to push and forced to pull, under the launch
+parameters the autotuner picks for that graph (the configuration the
+selector is deployed with).  The state at the start
 of a superstep does not depend on the exchange (values and traces are
 identical in both runs), so superstep s of the two runs starts from the same
 state and their per-superstep device times (HIP events) give the two targets
@@ -58,16 +60,20 @@ def collect(kind: str = "train", reps: int = 3, verbose: bool = True):
     """Returns (X [n,4], T [n,2] log2-usec for push/pull, meta list)."""
     import paper_2010_08781_amd as ipg
 
+    from paper_2010_08781_amd import autotune
+
     X, T, meta = [], [], []
     for name, hg in _graphs(kind):
         g = ipg.Graph.from_host(hg)
+        tun = autotune.tune(g, hg, "cc", cache_path=None, reps=1)
+        tun.pop("push_div", None)  # the fixed rule's divisor: irrelevant to forced exchanges
         runs = [("cc", 0)] + [("sssp", s) for s in _sources(hg, 2, 99)]
         for app, src in runs:
             times = {}
             for mode in ("push", "pull"):
                 us = []
                 for _ in range(reps):
-                    _, st = g.run(app, source=src, mode=mode, timing=True)
+                    _, st = g.run(app, source=src, mode=mode, timing=True, tuning=tun)
                     us.append(st.usec.astype(np.float64))
                 times[mode] = np.median(np.stack(us), axis=0)
             feats = ipg.selector_features(st.active, st.frontier_deg, np.arange(st.supersteps), hg.m)
@@ -75,7 +81,7 @@ def collect(kind: str = "train", reps: int = 3, verbose: bool = True):
             T.append(np.log2(np.maximum(np.stack([times["push"], times["pull"]], axis=1), 1.0)))
             meta += [(name, app, src, s, int(st.active[s]), int(st.frontier_deg[s]), hg.m) for s in range(st.supersteps)]
             if verbose:
-                print(f"[selector] {kind} {name} {app} src={src}: {st.supersteps} supersteps, "
+                print(f"[selector] {kind} {name} {app} src={src} {tun}: {st.supersteps} supersteps, "
                       f"push {times['push'].sum():.0f} us, pull {times['pull'].sum():.0f} us", file=sys.stderr, flush=True)
         g.close()
     return np.concatenate(X), np.concatenate(T), meta
