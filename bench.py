@@ -4,7 +4,8 @@
 One step = one pass of the whole hot path over the workload graph: PageRank
 (10 rank updates, FP64, pull exchange), hash-min connected components to
 vote-to-halt and SSSP from vertex 0 to vote-to-halt (push/pull chosen per
-superstep).  The graph (synthetic R-MAT, scale 20, edge factor 16,
+superstep by the trained selector, device-driven superstep loop), with
+launch parameters from the autotuner.  The graph (synthetic R-MAT, scale 20, edge factor 16,
 symmetrised, seed 2) is resident in HBM before timing starts.
 
 Prints ONE JSON line.  `value` = GTEPS over the step: messages delivered
@@ -197,7 +198,7 @@ def main():
 
         t0 = time.perf_counter()
         for app in apps:
-            tun[app] = autotune.tune(g, hg, app, cache_path=args.tune_cache, reps=2, updates=T)
+            tun[app] = autotune.tune(g, hg, app, cache_path=args.tune_cache, reps=2, updates=T, persistent=True)
         print(f"[bench] autotuned {tun} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
 
     def one_step(selector=sel):
@@ -206,7 +207,8 @@ def main():
             if app == "pagerank":
                 _, st = g.run("pagerank", T, mode="pull", timing=True, tuning=tun[app])
             else:
-                _, st = g.run(app, source=0, mode=args.mode, timing=True, selector=selector, tuning=tun[app])
+                _, st = g.run(app, source=0, mode=args.mode, timing=True, selector=selector, tuning=tun[app],
+                              persistent=True)
             out[app] = st
         return out
 
@@ -254,8 +256,8 @@ def main():
             t_plain["push_div"] = 20
 
             def med(t):
-                return float(np.median([g.run(app, source=0, mode="auto", timing=True, tuning=t)[1].seconds
-                                        for _ in range(max(3, args.steps))]))
+                return float(np.median([g.run(app, source=0, mode="auto", timing=True, tuning=t,
+                                              persistent=True)[1].seconds for _ in range(max(3, args.steps))]))
 
             plain, rule = med(t_plain), med(tun[app])
             mine = apps_out[app]["time_to_converge_ms_median"] / 1e3

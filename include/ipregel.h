@@ -111,6 +111,9 @@ typedef struct {
   uint32_t pull_grid;  /* workgroups of the pull item kernels (default 2048) */
   uint32_t push_div;   /* fixed exchange rule: pull when frontier + its out-edges > E / push_div (default 20) */
   uint32_t list_div;   /* push frontiers up to max(4096, N / list_div) are visited as a list (default 16) */
+  uint32_t gate_div;   /* CC/SSSP pull: when fewer than N / gate_div vertices broadcast, the gather reads
+                          a bitmap of the senders first and skips the others' outboxes (default 8;
+                          UINT32_MAX = never) */
 } ipg_tuning;
 
 typedef struct {

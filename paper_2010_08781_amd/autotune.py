@@ -28,8 +28,8 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ipregel_tuning.
 # Candidate values per application (0 = the library's default).
 SPACES = {
     "pagerank": {"pr_hot": [0xFFFFFFFF, 2048, 4096, 8192, 11200], "pull_grid": [1024, 2048, 4096]},
-    "cc": {"push_div": [10, 20, 40], "list_div": [8, 16, 32], "pull_grid": [1024, 2048, 4096]},
-    "sssp": {"push_div": [10, 20, 40], "list_div": [8, 16, 32], "pull_grid": [1024, 2048, 4096]},
+    "cc": {"push_div": [10, 20, 40], "list_div": [8, 16, 32], "pull_grid": [2048, 4096], "gate_div": [4, 16]},
+    "sssp": {"push_div": [10, 20, 40], "list_div": [8, 16, 32], "pull_grid": [2048, 4096], "gate_div": [4, 16]},
     "multi_sssp": {"push_div": [5, 10, 20, 40], "pull_grid": [1024, 2048, 4096]},
 }
 

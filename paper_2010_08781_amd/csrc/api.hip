@@ -25,6 +25,8 @@ size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w) {
     r.fr_a = c.take<uint32_t>(nn);
     r.fr_b = c.take<uint32_t>(nn);
     r.outbox = c.take<uint32_t>(nn);
+    r.sent = c.take<uint32_t>(nn / 64 * 2 + 2);
+    r.gate = c.take<uint32_t>(1);
     r.list_ctr = c.take<uint32_t>(4);
     r.hubs = c.take<Hub>(kHubCap);
     r.decision = c.take<Decision>(1);

@@ -96,6 +96,8 @@ struct RunWs {
   uint32_t* fr_a;       // [n] frontier list, ping
   uint32_t* fr_b;       // [n] pong
   uint32_t* outbox;     // [n] one-slot outbox of the pull form: the broadcast value, INF if none
+  uint32_t* sent;       // [n/64*2 + 2] bitmap of the vertices that broadcast in a pull superstep
+  uint32_t* gate;       // [1] 1 when that superstep's senders are few enough to gate the gathers
   uint32_t* list_ctr;   // [4] next-frontier list length (push form) at s & 1, hub count at 2 + (s & 1)
   Hub* hubs;            // [kHubCap] hub senders of a push superstep
   struct Decision* decision;  // end-of-superstep summary read by the host
@@ -151,11 +153,13 @@ struct Tune {
   uint32_t pull_grid;
   uint32_t push_div;
   uint32_t list_div;
+  uint32_t gate_div;  // pull gathers only senders' outboxes when senders < N / gate_div (0 = never)
 };
 constexpr uint32_t kHotDefault = 8192;  // 64 KB of LDS; the launch also caps it to the LDS left by the tiles
 inline Tune resolve_tuning(const ipg_tuning* t) {
-  Tune r{kHotDefault, kPullGrid, 20, 16};
+  Tune r{kHotDefault, kPullGrid, 20, 16, 8};
   if (t) {
+    if (t->gate_div) r.gate_div = t->gate_div == 0xFFFFFFFFu ? 0 : t->gate_div;
     if (t->pr_hot) r.pr_hot = t->pr_hot == 0xFFFFFFFFu ? 0 : t->pr_hot;
     if (t->pull_grid) r.pull_grid = t->pull_grid;
     if (t->push_div) r.push_div = t->push_div;

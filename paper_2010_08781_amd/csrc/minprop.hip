@@ -261,6 +261,7 @@ struct MinApplyArgs {
   CtrSlot* ctr;
   const DevCtl* ctl;  // device-driven loop: sweep all N and write every outbox slot (else null)
   uint32_t n;
+  uint32_t* sent;     // bitmap of the senders (zero on entry), or null
 };
 
 // Compute phase of a pull superstep: consume the mailboxes of the active
@@ -276,19 +277,38 @@ __global__ __launch_bounds__(kBlock) void minprop_apply_kernel(MinApplyArgs a) {
     act.count = a.n;
   }
   uint64_t senders = 0, messages = 0;
+  // wavefront-uniform rounds (the sender bitmap is set a wavefront at a time)
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < act.count; i += stride) {
-    const uint32_t v = active_vertex(act, i);
-    uint32_t msg;
-    const bool sends = compute_min(act.phase, v, a.value, a.mail_in, msg);
-    if (sends) {
-      senders += 1;
-      messages += a.outdeg[v];
+  const uint64_t first = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~static_cast<uint32_t>(kWave - 1));
+  for (uint64_t base = first; base < act.count; base += stride) {
+    const uint64_t i = base + lane_id();
+    bool sends = false;
+    uint32_t v = 0;
+    if (i < act.count) {
+      v = active_vertex(act, i);
+      uint32_t msg;
+      sends = compute_min(act.phase, v, a.value, a.mail_in, msg);
+      if (sends) {
+        senders += 1;
+        messages += a.outdeg[v];
+        a.outbox[v] = msg;
+      } else if (a.ctl) {
+        a.outbox[v] = kInf;
+      }
     }
-    if (sends) a.outbox[v] = msg;
-    else if (a.ctl) a.outbox[v] = kInf;
+    if (a.sent) wave_set_bits(sends, v, a.sent);
   }
   flush_counters(a.ctr, senders, messages, 0, 0, 0);
+}
+
+// Between the compute and the exchange of a pull superstep: whether so few
+// vertices broadcast that the gather should consult the sender bitmap first
+// (senders < N / div).  One wavefront sums the counter slots.
+__global__ __launch_bounds__(kWave) void gate_kernel(const CtrSlot* c, uint32_t n, uint32_t div, const DevCtl* ctl,
+                                                     uint32_t* gate) {
+  if (ctl && (ctl->halted || ctl->mode != IPG_MODE_PULL)) return;
+  const uint64_t se = wave_sum_u64(c[threadIdx.x].senders);
+  if (threadIdx.x == 0) *gate = (div && se < n / div) ? 1u : 0u;
 }
 
 struct MinPullArgs {
@@ -300,6 +320,8 @@ struct MinPullArgs {
   CtrSlot* ctr;
   CtrSlot* ctr_clear;
   const DevCtl* ctl;       // device-driven loop: run only when it chose pull (else null)
+  const uint32_t* sent;    // bitmap of the senders, read when *gate is set
+  const uint32_t* gate;    // or null: gather every outbox
 };
 
 // The message an in-edge carries: the source's broadcast value o (CC), plus
@@ -331,6 +353,7 @@ __global__ __launch_bounds__(kBlock) void minprop_pull_kernel(MinPullArgs a) {
   __shared__ uint32_t s_tile[kWavesPerBlock][kWaveTile];
   __shared__ uint32_t s_off[kWavesPerBlock][kItemRows + 1];
   if (a.ctl && (a.ctl->halted || a.ctl->mode != IPG_MODE_PULL)) return;  // uniform over the grid
+  const uint32_t* sent = (a.gate && *a.gate) ? a.sent : nullptr;          // uniform as well
   clear_slots(a.ctr_clear);
   const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
   uint32_t* tile = s_tile[wv];
@@ -363,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void minprop_pull_kernel(MinPullArgs a) {
     uint32_t o[kPer], w[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      o[k] = ne ? a.outbox[u[k]] : kInf;
+      o[k] = (ne && row_live(sent, u[k])) ? a.outbox[u[k]] : kInf;
       w[k] = (W && ne) ? a.w[it.e0 + ic[k]] : 1u;
     }
     if (chunk) {
@@ -621,8 +644,10 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
     IPG_HIP(push_dispatch(app, weighted, a, grid, hubs, s));
   }
   if (device || mode == IPG_MODE_PULL) {
+    const bool gating = step > 0 && tn.gate_div != 0;
     if (step > 0) {
       if (!device) IPG_HIP(fill_u32(w.outbox, n, kInf, s));
+      if (gating) IPG_HIP(fill_u32(w.sent, (uint64_t)n / 64 * 2 + 2, 0, s));
       MinApplyArgs ap;
       ap.act = act;
       ap.act.list = b.fin;
@@ -633,9 +658,14 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
       ap.ctr = b.c;
       ap.ctl = ctl;
       ap.n = n;
+      ap.sent = gating ? w.sent : nullptr;
       const uint32_t grid = device ? gv : grid_for(act.count, kBlock, 8192);
       hipLaunchKernelGGL(minprop_apply_kernel, dim3(grid), dim3(kBlock), 0, s, ap);
       IPG_HIP(hipGetLastError());
+      if (gating) {
+        hipLaunchKernelGGL(gate_kernel, dim3(1), dim3(kWave), 0, s, b.c, n, tn.gate_div, ctl, w.gate);
+        IPG_HIP(hipGetLastError());
+      }
     }
     MinPullArgs pa;
     pa.t = pull_tiling(g);
@@ -646,6 +676,8 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
     pa.ctr = b.c;
     pa.ctr_clear = b.cc;
     pa.ctl = ctl;
+    pa.sent = w.sent;
+    pa.gate = gating ? w.gate : nullptr;
     IPG_HIP(pull_dispatch(app, weighted, pa, tn.pull_grid, s));
   }
   return IPG_OK;

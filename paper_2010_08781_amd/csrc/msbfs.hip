@@ -79,29 +79,6 @@ struct MsPullArgs {
   const uint32_t* nz;  // bitmap of the non-empty rows of f_in, or null (gather every row)
 };
 
-// Bit v of a bitmap.
-__device__ __forceinline__ bool bit_of(const uint32_t* bm, uint32_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
-
-// Set bit v of bitmap `bm` for every lane with `pred`, one atomic OR per
-// distinct 32-bit word of the wavefront (all lanes must call).
-__device__ __forceinline__ void wave_set_bits(bool pred, uint32_t v, uint32_t* bm) {
-  uint64_t pending = __ballot(pred);
-  while (pending) {
-    const int leader = __ffsll(static_cast<unsigned long long>(pending)) - 1;
-    const uint32_t word = static_cast<uint32_t>(__shfl(static_cast<int>(v), leader)) >> 5;
-    const bool mine = pred && (v >> 5) == word;
-    uint32_t bits = mine ? (1u << (v & 31)) : 0u;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) bits |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(bits), o));
-    if (static_cast<int>(lane_id()) == leader) atomicOr(bm + word, bits);
-    pending &= ~__ballot(mine);
-  }
-}
-
-__device__ __forceinline__ bool row_live(const uint32_t* nz, int32_t u) {
-  return nz == nullptr || ((nz[static_cast<uint32_t>(u) >> 5] >> (u & 31)) & 1u);
-}
-
 struct MsPushArgs {
   MsRun r;
   const uint64_t* off;     // CSR

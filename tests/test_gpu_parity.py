@@ -328,7 +328,8 @@ def test_launch_parameters_never_change_results(ipg):
     for app in ("cc", "sssp"):
         ref = oracle.run_graph(app, hg, 0, source=0)
         for t in ({"push_div": 10, "list_div": 8, "pull_grid": 64}, {"push_div": 40, "list_div": 32},
-                  {"push_div": 1}, {"push_div": 100000}):
+                  {"push_div": 1}, {"push_div": 100000, "gate_div": 1}, {"push_div": 100000, "gate_div": 0xFFFFFFFF},
+                  {"gate_div": 2, "pull_grid": 100}):
             for persistent in (False, True):
                 v, st = g.run(app, tuning=t, persistent=persistent)
                 assert np.array_equal(to_np(v), ref.values) and np.array_equal(st.trace, ref.trace), (app, t)
@@ -347,4 +348,4 @@ def test_autotune_on_device(ipg, tmp_path):
     r, _ = g.run("pagerank", 10, tuning=best)
     assert max_rel(to_np(r), oracle.run_graph("pagerank", hg, 10).values) <= PR_RTOL
     best = autotune.tune(g, hg, "sssp", cache_path=str(tmp_path / "t.json"), reps=1)
-    assert set(best) == {"push_div", "list_div", "pull_grid"}
+    assert set(best) == {"push_div", "list_div", "pull_grid", "gate_div"}
