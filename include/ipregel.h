@@ -93,6 +93,11 @@ typedef struct {
 
 /* ipg_run_opts.flags */
 #define IPG_RUN_PERSISTENT 1u /* device-resident superstep loop: one cooperative launch, no per-superstep host sync */
+#define IPG_RUN_ENQUEUE 4u    /* enqueue the run's work on the stream and return at once, with no host
+                                 synchronisation and no readback, so that the caller can capture it into a
+                                 graph: PageRank (fixed T; part_offsets are not checked; no timing) and
+                                 batched SSSP (device-driven supersteps up to max_supersteps <= 1024; the
+                                 outcome from ipg_multi_sssp_result).  Stats are not filled. */
 #define IPG_RUN_GRAPH 2u      /* PageRank: replay the whole superstep sequence as one hipGraph launch.  The
                                  graph is captured on the first call and kept in the handle while T, the
                                  exchange, the workspace and part_offsets stay the same; per-superstep
@@ -235,14 +240,23 @@ ipg_status ipg_read_values(const ipg_graph* graph, void* dst, size_t dst_bytes, 
  *   max_supersteps: cap on supersteps, 0 = none (IPG_NOT_CONVERGED when
  *         reached with messages pending).  opts->mode forces push or pull;
  *         opts->source and opts->selector are ignored.
- * A graph with weights is IPG_EUNSUPPORTED.  Synchronises the stream once
- * per superstep.
+ *   opts->flags: IPG_RUN_PERSISTENT runs the superstep loop on the device
+ *         (control block in the workspace; one readback per 16 supersteps);
+ *         IPG_RUN_ENQUEUE only enqueues it (see the flag).
+ * A graph with weights is IPG_EUNSUPPORTED.  The host-driven loop
+ * synchronises the stream once per superstep.
  */
 #define IPG_BATCH_MAX_SOURCES 256
 size_t ipg_multi_sssp_workspace_bytes(uint32_t num_vertices, uint64_t num_edges);
 ipg_status ipg_run_multi_sssp(ipg_graph* graph, const uint32_t* sources, uint32_t num_sources,
                               uint32_t max_supersteps, const ipg_run_opts* opts, uint32_t* dist, size_t dist_bytes,
                               void* workspace, size_t workspace_bytes, void* hip_stream, ipg_run_stats* stats);
+/* Outcome of the last device-driven batched run in `workspace` (after an
+ * IPG_RUN_ENQUEUE run has executed): fills stats (times from the device's
+ * wall clock) and returns its status -- IPG_EINVAL if a source was >= N
+ * (that query was skipped) or no such run has ended.  Synchronises. */
+ipg_status ipg_multi_sssp_result(const ipg_graph* graph, const void* workspace, size_t workspace_bytes,
+                                 void* hip_stream, ipg_run_stats* stats);
 
 /*
  * Learned exchange selector (an extension of Section 4.3.2, where the push /

@@ -36,7 +36,7 @@ COMBINE_SUM, COMBINE_MIN = 0, 1
 DEFAULT_COMBINER = {APP_PAGERANK: COMBINE_SUM, APP_CC: COMBINE_MIN, APP_SSSP: COMBINE_MIN}
 MODES = {"auto": 0, "push": 1, "pull": 2}
 GRAPH_SYMMETRIC, GRAPH_VALIDATE, GRAPH_RENAME = 1, 2, 4
-RUN_PERSISTENT, RUN_GRAPH = 1, 2
+RUN_PERSISTENT, RUN_GRAPH, RUN_ENQUEUE = 1, 2, 4
 INF = 0xFFFFFFFF
 BATCH_MAX_SOURCES = 256
 
@@ -122,6 +122,8 @@ def lib():
         L.ipg_multi_sssp_workspace_bytes.restype = sz
         L.ipg_run_multi_sssp.argtypes = [P, P, u32, u32, ctypes.POINTER(_Opts), P, sz, P, sz, P, ctypes.POINTER(_Stats)]
         L.ipg_run_multi_sssp.restype = i32
+        L.ipg_multi_sssp_result.argtypes = [P, P, sz, P, ctypes.POINTER(_Stats)]
+        L.ipg_multi_sssp_result.restype = i32
         L.ipg_selector_workspace_bytes.argtypes = [u32]
         L.ipg_selector_workspace_bytes.restype = sz
         L.ipg_selector_forward.argtypes = [P, P, u32, P, P]
@@ -286,7 +288,7 @@ class Graph:
     def run(self, app, max_supersteps: Optional[int] = None, source: int = 0, mode: str = "auto",
             timing: bool = True, trace_cap: int = 1 << 16, persistent: bool = False, stream=None,
             combiner: Optional[int] = None, check: bool = True, selector=None, parts=None, graph: bool = False,
-            tol: float = 0.0, tuning: Optional[dict] = None):
+            tol: float = 0.0, tuning: Optional[dict] = None, enqueue: bool = False):
         """Run an application; returns (values tensor on the device, RunStats).
 
         max_supersteps: PageRank -> number of rank updates (default 10, Fig. 8);
@@ -295,7 +297,9 @@ class Graph:
         vertex offsets (P+1 entries); graph: replay PageRank as one hipGraph;
         tol: PageRank to convergence (stop after the first update whose L1
         change is below tol; max_supersteps caps the updates); tuning: launch
-        parameters (see TUNING_FIELDS and the autotune module)."""
+        parameters (see TUNING_FIELDS and the autotune module); enqueue:
+        PageRank work only enqueued on the stream (capturable; returns
+        (None, None), read the ranks with read_values afterwards)."""
         import torch
 
         a = APPS[app] if isinstance(app, str) else int(app)
@@ -310,7 +314,7 @@ class Graph:
 
             if not parts.is_cuda or parts.dtype != torch.int32 or not parts.is_contiguous() or parts.numel() < 2:
                 raise ValueError("parts must be a contiguous int32 CUDA tensor of P+1 offsets")
-        flags = (RUN_PERSISTENT if persistent else 0) | (RUN_GRAPH if graph else 0)
+        flags = (RUN_PERSISTENT if persistent else 0) | (RUN_GRAPH if graph else 0) | (RUN_ENQUEUE if enqueue else 0)
         tun = _tuning(tuning)
         opts = _Opts(int(source), MODES[mode], flags, selector.data_ptr() if selector is not None else None,
                      parts.data_ptr() if parts is not None else None, parts.numel() - 1 if parts is not None else 0,
@@ -318,7 +322,10 @@ class Graph:
         tr = _Trace(trace_cap, timing)
         rc = lib().ipg_run(self._h, a, comb, int(max_supersteps), ctypes.byref(opts),
                            ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(stream),
-                           ctypes.byref(tr.st))
+                           None if enqueue else ctypes.byref(tr.st))
+        if enqueue:
+            _check(rc, "ipg_run")
+            return None, None
         if check:
             _check(rc, "ipg_run", allow_not_converged=True)
         elif rc not in (OK, NOT_CONVERGED):
@@ -328,11 +335,13 @@ class Graph:
 
     def run_multi_sssp(self, sources, max_supersteps: int = 0, mode: str = "auto", timing: bool = True,
                        trace_cap: int = 1 << 16, stream=None, out=None, check: bool = True,
-                       tuning: Optional[dict] = None):
+                       tuning: Optional[dict] = None, persistent: bool = False, enqueue: bool = False):
         """Batched unit-weight SSSP from up to 256 sources in one superstep loop.
 
         Returns (dist [Q, N] int32 tensor holding uint32 distances, RunStats whose
-        trace is the sum of the single-source traces)."""
+        trace is the sum of the single-source traces).  persistent: the loop
+        runs on the device; enqueue: the device-driven run is only enqueued
+        (capturable; stats None -- see multi_sssp_result)."""
         import torch
 
         src = torch.as_tensor(np.asarray(sources, dtype=np.int64).astype(np.int32), device=self.device) \
@@ -346,14 +355,28 @@ class Graph:
             self._run_ws[key] = (torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device), nb)
         ws, nbytes = self._run_ws[key]
         tun = _tuning(tuning)
-        opts = _Opts(0, MODES[mode], 0, None, None, 0, 0.0, ctypes.addressof(tun) if tun is not None else None)
+        flags = (RUN_PERSISTENT if persistent else 0) | (RUN_ENQUEUE if enqueue else 0)
+        opts = _Opts(0, MODES[mode], flags, None, None, 0, 0.0, ctypes.addressof(tun) if tun is not None else None)
         tr = _Trace(trace_cap, timing)
+        self._ms_src = src  # the device ids must outlive an enqueued run
         rc = lib().ipg_run_multi_sssp(self._h, src.data_ptr(), q, int(max_supersteps), ctypes.byref(opts),
                                       out.data_ptr(), out.numel() * 4, ws.data_ptr(), nbytes, _stream_handle(stream),
-                                      ctypes.byref(tr.st))
+                                      None if enqueue else ctypes.byref(tr.st))
+        if enqueue:
+            _check(rc, "ipg_run_multi_sssp")
+            return out, None
         if check:
             _check(rc, "ipg_run_multi_sssp", allow_not_converged=True)
         return out, tr.stats(rc)
+
+    def multi_sssp_result(self, trace_cap: int = 1024, stream=None, check: bool = True):
+        """RunStats of the last device-driven batched run (after an enqueued run executed)."""
+        ws, nbytes = self._run_ws["multi_sssp"]
+        tr = _Trace(trace_cap, True)
+        rc = lib().ipg_multi_sssp_result(self._h, ws.data_ptr(), nbytes, _stream_handle(stream), ctypes.byref(tr.st))
+        if check:
+            _check(rc, "ipg_multi_sssp_result", allow_not_converged=True)
+        return tr.stats(rc)
 
     def read_values(self, app: int, stream=None):
         import torch

@@ -112,6 +112,8 @@ extern "C" ipg_status ipg_run(ipg_graph* g, ipg_app app, ipg_combiner combiner, 
   if (o.num_parts && app != IPG_APP_PAGERANK)
     return fail(IPG_EUNSUPPORTED, "ipg_run: part_offsets apply to PageRank only");
   if (o.num_parts && !o.part_offsets) return fail(IPG_EINVAL, "ipg_run: num_parts without part_offsets");
+  if ((o.flags & IPG_RUN_ENQUEUE) && (app != IPG_APP_PAGERANK || o.tolerance != 0.0 || (o.flags & IPG_RUN_GRAPH)))
+    return fail(IPG_EUNSUPPORTED, "ipg_run: IPG_RUN_ENQUEUE applies to fixed-length PageRank without IPG_RUN_GRAPH");
   if (o.tolerance != 0.0) {
     if (app != IPG_APP_PAGERANK) return fail(IPG_EUNSUPPORTED, "ipg_run: a tolerance applies to PageRank only");
     if (!(o.tolerance > 0.0)) return fail(IPG_EINVAL, "ipg_run: tolerance must be > 0");
@@ -131,11 +133,12 @@ extern "C" ipg_status ipg_run(ipg_graph* g, ipg_app app, ipg_combiner combiner, 
   RunWs w;
   carve_run(c, g->n, g->e, app, &w);
   g->has_values = 0;
-  StepTimer tm(st ? st->usec : nullptr, st ? st->trace_cap : 0);
+  const bool enqueue = o.flags & IPG_RUN_ENQUEUE;
+  StepTimer tm(st && !enqueue ? st->usec : nullptr, st && !enqueue ? st->trace_cap : 0);
   ipg_status rc;
   if (app == IPG_APP_PAGERANK) rc = run_pagerank(g, max_supersteps, o, w, ws, s, tm, st);
   else rc = run_minprop(g, app, max_supersteps, o, w, s, tm, st);
-  if (st) st->seconds = tm.seconds();
+  if (st && !enqueue) st->seconds = tm.seconds();
   if (rc == IPG_OK || rc == IPG_NOT_CONVERGED) {
     g->has_values = 1;
     g->last_app = app;

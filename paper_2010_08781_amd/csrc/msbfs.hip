@@ -60,6 +60,28 @@ static_assert((1u << kMsHistBits) == kMsHist, "level index bits");
 
 typedef unsigned long long u64;
 
+// Control block of the device-driven form (the host loop's state, in device
+// memory): advanced by ms_dd_decide_kernel at the end of every superstep and
+// read by every kernel of the next one.
+struct MsCtl {
+  uint32_t step;       // superstep about to run
+  uint32_t halted;
+  int32_t status;      // IPG_OK or IPG_NOT_CONVERGED once halted
+  int32_t mode;        // exchange of the superstep about to run
+  int32_t forced;      // 0 = the fixed rule, else the forced exchange
+  uint32_t cap;        // superstep cap, 0 = none
+  uint32_t expanded;   // levels [0, expanded) are written to dist
+  uint32_t sparse;     // the coming pull gathers only the non-empty rows
+  uint32_t push_div;
+  uint32_t bad_source; // a source id >= N was given (it is skipped)
+  unsigned long long frontier, frontier_deg;  // union frontier after the last superstep
+  unsigned long long t_last;                  // wall clock at the end of the last superstep
+  unsigned long long tot_msgs, tot_exam;
+  unsigned long long pad;
+};
+static_assert(sizeof(MsCtl) == 88, "control block layout");
+constexpr uint32_t kMsRec = 1024;  // trace records kept on the device (enqueue-only runs)
+
 struct MsRun {
   uint32_t n;
   uint32_t level;  // superstep being computed
@@ -77,6 +99,7 @@ struct MsPullArgs {
   PullTiling t;
   u64* partial;        // [chunks][4]
   const uint32_t* nz;  // bitmap of the non-empty rows of f_in, or null (gather every row)
+  const MsCtl* ctl;    // device-driven form: run only when it chose pull; nz used when it says sparse
 };
 
 struct MsPushArgs {
@@ -86,7 +109,12 @@ struct MsPushArgs {
   const uint32_t* nz_in;   // union frontier of the previous superstep (bitmap)
   u64* recv;               // [n][4], zero outside a push superstep
   uint32_t* touched;       // bitmap, zero outside a push superstep
+  const MsCtl* ctl;        // device-driven form: run only when it chose push
 };
+
+__device__ __forceinline__ bool ms_skip(const MsCtl* ctl, int mode) {
+  return ctl && (ctl->halted || ctl->mode != mode);
+}
 
 __device__ __forceinline__ void load_mask(const u64* base, uint32_t v, u64 m[kMsWords]) {
   const ulonglong2* p = reinterpret_cast<const ulonglong2*>(base + (size_t)v * kMsWords);
@@ -142,11 +170,13 @@ __device__ __forceinline__ bool ms_compute(const MsRun& a, uint32_t v, const u64
 
 // Superstep 0: one thread per query sets its source's bit in vis and F_0 and
 // marks the source in the union frontier (a repeated source counts once).
-__global__ __launch_bounds__(kBlock) void ms_init_kernel(const uint32_t* sources, uint32_t q, MsRun a) {
+__global__ __launch_bounds__(kBlock) void ms_init_kernel(const uint32_t* sources, uint32_t q, MsRun a,
+                                                         uint32_t* bad) {
   const uint32_t i = threadIdx.x;
   uint64_t senders = 0, messages = 0, next_count = 0, next_deg = 0;
-  if (i < q) {
-    const uint32_t v = sources[i];
+  const uint32_t v = i < q ? sources[i] : 0;
+  if (i < q && v >= a.n) atomicOr(bad, 1u);  // checked on the host unless the run is enqueue-only
+  if (i < q && v < a.n) {
     const u64 bit = 1ull << (i & 63);
     atomicOr(a.vis + (size_t)v * kMsWords + (i >> 6), bit);
     atomicOr(a.f_out + (size_t)v * kMsWords + (i >> 6), bit);
@@ -191,6 +221,8 @@ __global__ __launch_bounds__(kBlock) void ms_pull_kernel(MsPullArgs a) {
   constexpr int kRowPer = (kItemRows + kWave) / kWave;
   __shared__ u64 s_tile[kWavesPerBlock][kMsPass][kMsWords];
   __shared__ uint32_t s_off[kWavesPerBlock][kItemRows + 1];
+  if (ms_skip(a.ctl, IPG_MODE_PULL)) return;  // uniform over the grid
+  const uint32_t* nz = a.ctl ? (a.ctl->sparse ? a.nz : nullptr) : a.nz;
   clear_slots(a.r.ctr_clear);
   const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
   u64(*tile)[kMsWords] = s_tile[wv];
@@ -213,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void ms_pull_kernel(MsPullArgs a) {
       }
 #pragma unroll
       for (int k = 0; k < kChunkPer; ++k) {
-        if (u[k] >= 0 && row_live(a.nz, u[k])) {
+        if (u[k] >= 0 && row_live(nz, u[k])) {
           u64 m[kMsWords];
           load_mask(a.r.f_in, static_cast<uint32_t>(u[k]), m);
 #pragma unroll
@@ -255,7 +287,7 @@ __global__ __launch_bounds__(kBlock) void ms_pull_kernel(MsPullArgs a) {
       for (int k = 0; k < kPer; ++k) {
         if (u[k] >= 0) {
           u64 m[kMsWords] = {0, 0, 0, 0};
-          if (row_live(a.nz, u[k])) load_mask(a.r.f_in, static_cast<uint32_t>(u[k]), m);
+          if (row_live(nz, u[k])) load_mask(a.r.f_in, static_cast<uint32_t>(u[k]), m);
 #pragma unroll
           for (int w = 0; w < kMsWords; ++w) tile[lane + k * kWave][w] = m[w];
         }
@@ -288,6 +320,7 @@ __global__ __launch_bounds__(kBlock) void ms_pull_kernel(MsPullArgs a) {
 // Second launch of a pull superstep: one wavefront per long row ORs the
 // partials of its chunks and computes the row.
 __global__ __launch_bounds__(kBlock) void ms_longrow_kernel(MsPullArgs a) {
+  if (ms_skip(a.ctl, IPG_MODE_PULL)) return;
   const uint32_t l = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   const uint32_t lane = lane_id();
   MsCount c;
@@ -318,6 +351,7 @@ __global__ __launch_bounds__(kBlock) void ms_longrow_kernel(MsPullArgs a) {
 // ORs the sender's mask into the recipient's receive row and marks the
 // recipient touched.
 __global__ __launch_bounds__(kBlock) void ms_push_kernel(MsPushArgs a) {
+  if (ms_skip(a.ctl, IPG_MODE_PUSH)) return;
   clear_slots(a.r.ctr_clear);
   const uint64_t i = blockIdx.x * (uint64_t)kBlock + threadIdx.x;
   bool has = false;
@@ -345,6 +379,7 @@ __global__ __launch_bounds__(kBlock) void ms_push_kernel(MsPushArgs a) {
 // touched ones, and writes both words of the union-frontier bitmap and of
 // the (cleared) touched bitmap with plain stores.
 __global__ __launch_bounds__(kBlock) void ms_settle_kernel(MsPushArgs a) {
+  if (ms_skip(a.ctl, IPG_MODE_PUSH)) return;
   MsCount c;
   const uint32_t lane = lane_id();
   const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / kWave;
@@ -379,8 +414,8 @@ __global__ __launch_bounds__(kBlock) void ms_settle_kernel(MsPushArgs a) {
 // from bit planes built over the window, and the stores for one query are
 // coalesced along v.  The first window also writes INF where no bit is set;
 // later windows write only the distances they hold.
-__global__ __launch_bounds__(kBlock) void ms_expand_kernel(const u64* hist, uint32_t n, uint32_t q, uint32_t lvl0,
-                                                           uint32_t nlev, int first, uint32_t* dist) {
+__device__ __forceinline__ void ms_expand_body(const u64* hist, uint32_t n, uint32_t q, uint32_t lvl0, uint32_t nlev,
+                                               bool first, uint32_t* dist) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
     u64 found[kMsWords] = {0, 0, 0, 0};
@@ -415,6 +450,126 @@ __global__ __launch_bounds__(kBlock) void ms_expand_kernel(const u64* hist, uint
   }
 }
 
+__global__ __launch_bounds__(kBlock) void ms_expand_kernel(const u64* hist, uint32_t n, uint32_t q, uint32_t lvl0,
+                                                           uint32_t nlev, int first, uint32_t* dist) {
+  ms_expand_body(hist, n, q, lvl0, nlev, first != 0, dist);
+}
+
+// Superstep-level exchange choice on the union frontier: the library's
+// fixed rule, pull when the frontier and its out-edges exceed E / div.
+__host__ __device__ inline ipg_mode ms_mode(ipg_mode forced, uint64_t e, uint64_t frontier, uint64_t frontier_deg,
+                                            uint32_t div) {
+  if (forced == IPG_MODE_PUSH || forced == IPG_MODE_PULL) return forced;
+  if (e == 0) return IPG_MODE_PUSH;
+  return frontier + frontier_deg > e / (div ? div : 20) ? IPG_MODE_PULL : IPG_MODE_PUSH;
+}
+
+// ------------------------------------------------------- device-driven --
+
+__global__ void ms_dd_start_kernel(MsCtl* ctl, int forced, uint32_t cap, uint32_t push_div) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    MsCtl c{};
+    c.mode = IPG_MODE_PUSH;  // superstep 0 is the sources' broadcast
+    c.forced = forced;
+    c.cap = cap;
+    c.push_div = push_div;
+    c.t_last = static_cast<unsigned long long>(wall_clock64());
+    *ctl = c;
+  }
+}
+
+// First launch of a device-driven superstep: prepare its level buffer.  A
+// push writes only the rows it reaches, so the rows left by the slot's
+// previous level are zeroed (the whole slot if it was never used); a pull
+// writes every row but builds its union-frontier bitmap with ORs, so the
+// slot's bitmap is zeroed.
+__global__ void ms_dd_prep_kernel(const MsCtl* ctl, u64* f_out, uint32_t* nz_out, uint32_t n, uint32_t words) {
+  const MsCtl c = *ctl;
+  if (c.halted) return;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t tid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (c.mode == IPG_MODE_PUSH) {
+    if (c.step < kMsHist) {
+      for (uint64_t i = tid; i < (uint64_t)n * kMsWords; i += stride) f_out[i] = 0;
+    } else {
+      const u64 z[kMsWords] = {0, 0, 0, 0};
+      for (uint64_t i = tid; i < words; i += stride) {
+        uint32_t m = nz_out[i];
+        while (m) {
+          const uint32_t b = static_cast<uint32_t>(__ffs(m) - 1);
+          m &= m - 1;
+          store_mask(f_out, static_cast<uint32_t>(32 * i + b), z);
+        }
+      }
+    }
+  } else {
+    for (uint64_t i = tid; i < words; i += stride) nz_out[i] = 0;
+  }
+}
+
+// End of a device-driven superstep: sum the counters, record the
+// superstep, and take the host loop's decisions (halt when no query has a
+// message pending or at the cap; the next exchange by the fixed rule on the
+// union frontier, or forced; a sparse pull when that frontier is small).
+__global__ __launch_bounds__(kWave) void ms_dd_decide_kernel(const CtrSlot* c, uint32_t n, uint64_t e, uint32_t q,
+                                                             MsCtl* ctl, DevRec* rec) {
+  static_assert(kCtrSlots == kWave, "one slot per lane");
+  const unsigned long long now = static_cast<unsigned long long>(wall_clock64());
+  const MsCtl k = *ctl;
+  if (k.halted) return;
+  const CtrSlot& x = c[threadIdx.x];
+  const uint64_t nc = wave_sum_u64(x.next_count);
+  const uint64_t se = wave_sum_u64(x.senders);
+  const uint64_t me = wave_sum_u64(x.messages);
+  const uint64_t nd = wave_sum_u64(x.next_deg);
+  const uint64_t ac = wave_sum_u64(x.active);
+  if (threadIdx.x != 0) return;
+  const uint32_t s = k.step;
+  const uint64_t examined = s == 0 ? 0 : (k.mode == IPG_MODE_PUSH ? k.frontier_deg : e);
+  DevRec r;
+  r.active = s == 0 ? (unsigned long long)q * n : ac;
+  r.senders = se;
+  r.messages = me;
+  r.examined = examined;
+  r.frontier_deg = k.frontier_deg;
+  r.ticks = now - k.t_last;
+  r.mode = static_cast<uint32_t>(k.mode);
+  r.pad = 0;
+  rec[s % kMsRec] = r;
+  MsCtl nk = k;
+  nk.step = s + 1;
+  nk.t_last = now;
+  nk.tot_msgs += me;
+  nk.tot_exam += examined;
+  if (me == 0) {
+    nk.halted = 1;
+    nk.status = IPG_OK;
+  } else if (k.cap && s + 1 >= k.cap) {
+    nk.halted = 1;
+    nk.status = IPG_NOT_CONVERGED;
+  } else {
+    nk.frontier = nc;
+    nk.frontier_deg = nd;
+    nk.mode = k.forced ? k.forced : ms_mode(IPG_MODE_AUTO, e, nc, nd, k.push_div);
+    nk.sparse = nc < n / 8 ? 1u : 0u;
+  }
+  *ctl = nk;
+}
+
+// After every chunk of 16 device-driven supersteps (16c .. 16c+15): expand
+// the levels not yet in dist -- at most the 16 of the ring, which the next
+// chunk overwrites; the first expansion also writes INF.
+__global__ __launch_bounds__(kBlock) void ms_dd_expand_kernel(const MsCtl* ctl, const u64* hist, uint32_t n,
+                                                              uint32_t q, uint32_t* dist) {
+  const uint32_t lvl0 = ctl->expanded, nlev = ctl->step - lvl0;
+  if (nlev == 0) return;
+  ms_expand_body(hist, n, q, lvl0, nlev, lvl0 == 0, dist);
+}
+
+__global__ void ms_dd_mark_kernel(MsCtl* ctl) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->expanded = ctl->step;
+}
+
 // ------------------------------------------------------------------ host --
 
 struct MsWs {
@@ -426,6 +581,8 @@ struct MsWs {
   uint32_t* touched;  // [words] push: recipients of the superstep
   CtrSlot* ctr;       // [2][kCtrSlots]
   Decision* decision;
+  MsCtl* ctl;         // device-driven form
+  DevRec* rec;        // [kMsRec] its trace records
 };
 
 // Bitmap words per vertex set: whole 64-vertex wavefront tiles (the settle
@@ -441,18 +598,12 @@ static size_t carve_ms(Carver& c, uint32_t n, uint64_t e, MsWs* out) {
   w.partial = c.take<u64>(chunks_cap(e) * kMsWords);
   w.nzb = c.take<uint32_t>(kMsHist * ms_words(n));
   w.touched = c.take<uint32_t>(ms_words(n));
+  w.ctl = c.take<MsCtl>(1);
+  w.rec = c.take<DevRec>(kMsRec);
   w.ctr = c.take<CtrSlot>(2 * kCtrSlots);
   w.decision = c.take<Decision>(1);
   if (out) *out = w;
   return align_up(c.used, 256);
-}
-
-// Superstep-level exchange choice on the union frontier: the library's
-// fixed rule, pull when the frontier and its out-edges exceed E / div.
-static ipg_mode ms_mode(ipg_mode forced, uint64_t e, uint64_t frontier, uint64_t frontier_deg, uint32_t div) {
-  if (forced == IPG_MODE_PUSH || forced == IPG_MODE_PULL) return forced;
-  if (e == 0) return IPG_MODE_PUSH;
-  return frontier + frontier_deg > e / (div ? div : 20) ? IPG_MODE_PULL : IPG_MODE_PUSH;
 }
 
 static ipg_status run_msbfs(ipg_graph* g, const uint32_t* sources, uint32_t q, uint32_t cap, const ipg_run_opts& o,
@@ -509,7 +660,7 @@ static ipg_status run_msbfs(ipg_graph* g, const uint32_t* sources, uint32_t q, u
     ipg_mode mode = IPG_MODE_PUSH;
     uint64_t examined = 0;
     if (step == 0) {
-      hipLaunchKernelGGL(ms_init_kernel, dim3(1), dim3(kBlock), 0, s, sources, q, r);
+      hipLaunchKernelGGL(ms_init_kernel, dim3(1), dim3(kBlock), 0, s, sources, q, r, &w.ctl->bad_source);
       IPG_HIP(hipGetLastError());
     } else {
       mode = ms_mode(o.mode, e, frontier, frontier_deg, tn.push_div);
@@ -530,6 +681,7 @@ static ipg_status run_msbfs(ipg_graph* g, const uint32_t* sources, uint32_t q, u
         a.nz_in = slot_bits(step - 1);
         a.recv = w.recv;
         a.touched = w.touched;
+        a.ctl = nullptr;
         hipLaunchKernelGGL(ms_push_kernel, dim3(grid_for(n, kBlock, 0xFFFFFFFFu)), dim3(kBlock), 0, s, a);
         IPG_HIP(hipGetLastError());
         a.r.ctr_clear = nullptr;
@@ -544,6 +696,7 @@ static ipg_status run_msbfs(ipg_graph* g, const uint32_t* sources, uint32_t q, u
         a.partial = w.partial;
         // sparse superstep: gather only the non-empty rows of F_{s-1}
         a.nz = frontier < n / 8 ? slot_bits(step - 1) : nullptr;
+        a.ctl = nullptr;
         if (t.ni) {
           hipLaunchKernelGGL(ms_pull_kernel, dim3(std::min(t.ni, tn.pull_grid)), dim3(kBlock), 0, s, a);
           IPG_HIP(hipGetLastError());
@@ -594,6 +747,137 @@ static ipg_status run_msbfs(ipg_graph* g, const uint32_t* sources, uint32_t q, u
   return status;
 }
 
+// Device-driven form (IPG_RUN_PERSISTENT, IPG_RUN_ENQUEUE): superstep 0,
+// then chunks of 16 supersteps whose kernels read the control block, each
+// chunk followed by the expansion of its levels.  With `enqueue_only` the
+// chunks needed to reach the cap are enqueued without any host
+// synchronisation (the run can be captured into a graph);
+// ipg_multi_sssp_result reads the outcome afterwards.  Otherwise the control
+// block and the chunk's records are read back after every chunk.
+static ipg_status run_msbfs_device(ipg_graph* g, const uint32_t* sources, uint32_t q, uint32_t cap,
+                                   const ipg_run_opts& o, uint32_t* dist, const MsWs& w, hipStream_t s,
+                                   bool enqueue_only) {
+  const uint32_t n = g->n;
+  const uint64_t e = g->e;
+  const Tune tn = resolve_tuning(o.tuning);
+  const size_t rowset = (size_t)n * kMsWords;
+  const size_t words = ms_words(n);
+  const int forced = o.mode == IPG_MODE_AUTO ? 0 : static_cast<int>(o.mode);
+  IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.vis), rowset * 2, 0, s));
+  IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.hist), rowset * 2, 0, s));  // slot 0
+  IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.recv), rowset * 2, 0, s));
+  IPG_HIP(fill_u32(w.nzb, words, 0, s));  // slot 0
+  IPG_HIP(fill_u32(w.touched, words, 0, s));
+  IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.ctr), 2 * kCtrSlots * sizeof(CtrSlot) / 4, 0, s));
+  hipLaunchKernelGGL(ms_dd_start_kernel, dim3(1), dim3(1), 0, s, w.ctl, forced, cap, tn.push_div);
+  IPG_HIP(hipGetLastError());
+  MsRun r{};
+  r.n = n;
+  r.outdeg = g->t.outdeg;
+  r.vis = w.vis;
+  r.level = 0;
+  r.f_out = w.hist;
+  r.f_in = nullptr;
+  r.nz_out = w.nzb;
+  r.ctr = w.ctr;
+  r.ctr_clear = w.ctr + kCtrSlots;
+  hipLaunchKernelGGL(ms_init_kernel, dim3(1), dim3(kBlock), 0, s, sources, q, r, &w.ctl->bad_source);
+  IPG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(ms_dd_decide_kernel, dim3(1), dim3(kWave), 0, s, w.ctr, n, e, q, w.ctl, w.rec);
+  IPG_HIP(hipGetLastError());
+  const PullTiling t = pull_tiling(g);
+  // Chunk c holds supersteps 16c .. 16c+15 (superstep 0, the sources'
+  // broadcast, is enqueued above): superstep 16c+p uses ring slot p, and the
+  // chunk's levels are expanded before the next chunk reuses the ring.
+  const uint32_t chunks = enqueue_only ? (cap + kMsHist - 1) / kMsHist : 0xFFFFFFFFu;
+  MsCtl h{};
+  for (uint32_t chunk = 0; chunk < chunks; ++chunk) {
+    for (uint32_t p = chunk == 0 ? 1 : 0; p < kMsHist; ++p) {
+      const uint32_t slot = p, prev = (p + kMsHist - 1) % kMsHist;
+      u64* f_out = w.hist + (size_t)slot * rowset;
+      uint32_t* nz_out = w.nzb + (size_t)slot * words;
+      hipLaunchKernelGGL(ms_dd_prep_kernel, dim3(grid_for(words, kBlock, 2048)), dim3(kBlock), 0, s, w.ctl, f_out,
+                         nz_out, n, static_cast<uint32_t>(words));
+      IPG_HIP(hipGetLastError());
+      MsRun rr = r;
+      rr.f_in = w.hist + (size_t)prev * rowset;
+      rr.f_out = f_out;
+      rr.nz_out = nz_out;
+      rr.ctr = w.ctr + (p & 1) * kCtrSlots;
+      rr.ctr_clear = w.ctr + ((p + 1) & 1) * kCtrSlots;
+      MsPushArgs a;
+      a.r = rr;
+      a.off = g->csr_off;
+      a.dst = g->csr_dst;
+      a.nz_in = w.nzb + (size_t)prev * words;
+      a.recv = w.recv;
+      a.touched = w.touched;
+      a.ctl = w.ctl;
+      hipLaunchKernelGGL(ms_push_kernel, dim3(grid_for(n, kBlock, 0xFFFFFFFFu)), dim3(kBlock), 0, s, a);
+      IPG_HIP(hipGetLastError());
+      a.r.ctr_clear = nullptr;
+      hipLaunchKernelGGL(ms_settle_kernel, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, a);
+      IPG_HIP(hipGetLastError());
+      MsPullArgs pa;
+      pa.r = rr;
+      pa.t = t;
+      pa.partial = w.partial;
+      pa.nz = w.nzb + (size_t)prev * words;
+      pa.ctl = w.ctl;
+      if (t.ni) {
+        hipLaunchKernelGGL(ms_pull_kernel, dim3(std::min(t.ni, tn.pull_grid)), dim3(kBlock), 0, s, pa);
+        IPG_HIP(hipGetLastError());
+      }
+      pa.r.ctr_clear = nullptr;
+      if (t.nl) {
+        hipLaunchKernelGGL(ms_longrow_kernel, dim3((t.nl + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0, s,
+                           pa);
+        IPG_HIP(hipGetLastError());
+      }
+      hipLaunchKernelGGL(ms_dd_decide_kernel, dim3(1), dim3(kWave), 0, s, rr.ctr, n, e, q, w.ctl, w.rec);
+      IPG_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(ms_dd_expand_kernel, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, w.ctl, w.hist, n, q,
+                       dist);
+    IPG_HIP(hipGetLastError());
+    hipLaunchKernelGGL(ms_dd_mark_kernel, dim3(1), dim3(1), 0, s, w.ctl);
+    IPG_HIP(hipGetLastError());
+    if (enqueue_only) continue;
+    IPG_HIP(hipMemcpyAsync(&h, w.ctl, sizeof(h), hipMemcpyDeviceToHost, s));
+    IPG_HIP(hipStreamSynchronize(s));
+    if (h.halted) break;
+  }
+  if (enqueue_only) return IPG_OK;
+  return static_cast<ipg_status>(h.status);
+}
+
+// Statistics of a device-driven run from its control block and records.
+static ipg_status ms_fill_stats(const MsCtl& h, const DevRec* recs, uint32_t first, int dev, ipg_run_stats* st) {
+  if (!st) return IPG_OK;
+  int khz = 0;
+  IPG_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  const double us_per_tick = khz > 0 ? 1e3 / khz : 0.0;
+  double secs = 0.0;
+  for (uint32_t k = first; k < h.step; ++k) {
+    const DevRec& x = recs[k % kMsRec];
+    secs += x.ticks * us_per_tick * 1e-6;
+    if (k >= st->trace_cap) continue;
+    if (st->active) st->active[k] = x.active;
+    if (st->senders) st->senders[k] = x.senders;
+    if (st->messages) st->messages[k] = x.messages;
+    if (st->examined) st->examined[k] = x.examined;
+    if (st->mode) st->mode[k] = static_cast<uint8_t>(x.mode);
+    if (st->frontier_deg) st->frontier_deg[k] = x.frontier_deg;
+    if (st->usec) st->usec[k] = static_cast<float>(x.ticks * us_per_tick);
+  }
+  st->supersteps = h.step;
+  st->halted = h.halted && h.status == IPG_OK;
+  st->edges_traversed = h.tot_msgs;
+  st->edges_examined = h.tot_exam;
+  st->seconds = secs;
+  return IPG_OK;
+}
+
 }  // namespace ipg
 
 using namespace ipg;
@@ -615,6 +899,10 @@ extern "C" ipg_status ipg_run_multi_sssp(ipg_graph* g, const uint32_t* sources, 
   if (opts) o = *opts;
   if (o.mode != IPG_MODE_AUTO && o.mode != IPG_MODE_PUSH && o.mode != IPG_MODE_PULL)
     return fail(IPG_EINVAL, "ipg_run_multi_sssp: unknown mode");
+  const bool enqueue = o.flags & IPG_RUN_ENQUEUE;
+  const bool device = enqueue || (o.flags & IPG_RUN_PERSISTENT);
+  if (enqueue && (max_supersteps == 0 || max_supersteps > kMsRec))
+    return fail(IPG_EINVAL, "ipg_run_multi_sssp: an enqueue-only run needs 1 <= max_supersteps <= 1024");
   const size_t need_dist = (size_t)num_sources * g->n * sizeof(uint32_t);
   if (dist_bytes < need_dist)
     return fail(IPG_EINVAL, "ipg_run_multi_sssp: dist needs " + std::to_string(need_dist) + " bytes");
@@ -627,18 +915,72 @@ extern "C" ipg_status ipg_run_multi_sssp(ipg_graph* g, const uint32_t* sources, 
   IPG_HIP(hipGetDevice(&dev));
   if (dev != g->device) return fail(IPG_EINVAL, "ipg_run_multi_sssp: current device differs from the graph's device");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  // The sources are checked on the host before any kernel indexes with them.
-  std::vector<uint32_t> hsrc(num_sources);
-  IPG_HIP(hipMemcpyAsync(hsrc.data(), sources, num_sources * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  IPG_HIP(hipStreamSynchronize(s));
-  for (uint32_t i = 0; i < num_sources; ++i)
-    if (hsrc[i] >= g->n) return fail(IPG_EINVAL, "ipg_run_multi_sssp: source " + std::to_string(i) + " >= N");
+  if (!enqueue) {
+    // The sources are checked on the host before any kernel indexes with
+    // them (an enqueue-only run checks them on the device: the result call
+    // reports an out-of-range source).
+    std::vector<uint32_t> hsrc(num_sources);
+    IPG_HIP(hipMemcpyAsync(hsrc.data(), sources, num_sources * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    IPG_HIP(hipStreamSynchronize(s));
+    for (uint32_t i = 0; i < num_sources; ++i)
+      if (hsrc[i] >= g->n) return fail(IPG_EINVAL, "ipg_run_multi_sssp: source " + std::to_string(i) + " >= N");
+  }
   Carver c(ws);
   MsWs w;
   carve_ms(c, g->n, g->e, &w);
-  StepTimer tm(st ? st->usec : nullptr, st ? st->trace_cap : 0);
-  const ipg_status rc = run_msbfs(g, sources, num_sources, max_supersteps, o, dist, w, s, tm, st);
-  if (st) st->seconds = tm.seconds();
+  ipg_status rc;
+  if (device) {
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (!enqueue && st) {
+      IPG_HIP(hipEventCreate(&t0));
+      IPG_HIP(hipEventCreate(&t1));
+      IPG_HIP(hipEventRecord(t0, s));
+    }
+    rc = run_msbfs_device(g, sources, num_sources, max_supersteps, o, dist, w, s, enqueue);
+    if (!enqueue && st && (rc == IPG_OK || rc == IPG_NOT_CONVERGED)) {
+      // per-superstep times from the device's wall-clock stamps; the run's
+      // time from events around it
+      MsCtl h{};
+      std::vector<DevRec> recs(kMsRec);
+      IPG_HIP(hipEventRecord(t1, s));
+      IPG_HIP(hipMemcpyAsync(&h, w.ctl, sizeof(h), hipMemcpyDeviceToHost, s));
+      IPG_HIP(hipMemcpyAsync(recs.data(), w.rec, kMsRec * sizeof(DevRec), hipMemcpyDeviceToHost, s));
+      IPG_HIP(hipStreamSynchronize(s));
+      const uint32_t first = h.step > kMsRec ? h.step - kMsRec : 0;
+      const ipg_status r2 = ms_fill_stats(h, recs.data(), first, dev, st);
+      if (r2 != IPG_OK) return r2;
+      float ms = 0.f;
+      IPG_HIP(hipEventElapsedTime(&ms, t0, t1));
+      st->seconds = ms * 1e-3;
+    }
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+  } else {
+    StepTimer tm(st ? st->usec : nullptr, st ? st->trace_cap : 0);
+    rc = run_msbfs(g, sources, num_sources, max_supersteps, o, dist, w, s, tm, st);
+    if (st) st->seconds = tm.seconds();
+  }
   if (rc == IPG_OK) set_error("");
   return rc;
+}
+
+extern "C" ipg_status ipg_multi_sssp_result(const ipg_graph* g, const void* ws, size_t ws_bytes, void* hip_stream,
+                                            ipg_run_stats* st) {
+  if (!g || !ws) return fail(IPG_EINVAL, "ipg_multi_sssp_result: NULL argument");
+  if (ws_bytes < ipg_multi_sssp_workspace_bytes(g->n, g->e))
+    return fail(IPG_EWORKSPACE, "ipg_multi_sssp_result: workspace too small");
+  Carver c(const_cast<void*>(ws));
+  MsWs w;
+  carve_ms(c, g->n, g->e, &w);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  MsCtl h{};
+  std::vector<DevRec> recs(kMsRec);
+  IPG_HIP(hipMemcpyAsync(&h, w.ctl, sizeof(h), hipMemcpyDeviceToHost, s));
+  IPG_HIP(hipMemcpyAsync(recs.data(), w.rec, kMsRec * sizeof(DevRec), hipMemcpyDeviceToHost, s));
+  IPG_HIP(hipStreamSynchronize(s));
+  if (h.bad_source) return fail(IPG_EINVAL, "ipg_multi_sssp_result: a source was >= N (skipped)");
+  const ipg_status r2 = ms_fill_stats(h, recs.data(), 0, g->device, st);
+  if (r2 != IPG_OK) return r2;
+  if (!h.halted) return fail(IPG_EINVAL, "ipg_multi_sssp_result: no device-driven run has ended in this workspace");
+  return static_cast<ipg_status>(h.status);
 }

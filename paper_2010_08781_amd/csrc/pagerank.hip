@@ -583,6 +583,10 @@ ipg_status run_pagerank(ipg_graph* g, uint32_t T, const ipg_run_opts& o, const R
   IPG_HIP(max_hot_entries(&room));  // queried here, never during a stream capture
   const uint32_t* part_off = nullptr;
   uint32_t parts = 0;
+  if (o.flags & IPG_RUN_ENQUEUE) {  // no host synchronisation: the offsets are the caller's to get right
+    IPG_HIP(enqueue_pagerank(g, T, push, w, o.num_parts ? o.part_offsets : nullptr, o.num_parts, tn, s, nullptr));
+    return IPG_OK;
+  }
   if (o.part_offsets && o.num_parts) {
     std::vector<uint32_t> h(o.num_parts + 1);
     IPG_HIP(hipMemcpyAsync(h.data(), o.part_offsets, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));

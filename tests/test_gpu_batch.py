@@ -249,3 +249,90 @@ def test_pagerank_small_graph_family_full_size(ipg):
     print(f"[batch] family64 n={u.n} m={u.m}", flush=True)
     r, st = g.run("pagerank", 20, mode="pull", parts=_parts_tensor(u), graph=True)
     _check_parts(u, graphs, r, 20)
+
+
+# ------------------------------------------ device-driven and one launch --
+
+@pytest.mark.parametrize("case", ["rmat", "path", "dir"])
+def test_batch_device_driven_matches_oracle(ipg, case):
+    # the superstep loop on the device (control block, chunks of 16
+    # supersteps with the level ring expanded after each chunk)
+    if case == "rmat":
+        hg = graphgen.rmat(12, 16, seed=7, symmetric=True)
+        src = graphgen.pick_sources(hg, 130, seed=3)
+    elif case == "path":
+        hg = path(400)  # about 400 supersteps: many chunks and ring wraps
+        src = np.array([0, 399, 200, 1], dtype=np.uint32)
+    else:
+        hg = graphgen.rmat(14, 16, seed=1, symmetric=False)
+        src = graphgen.pick_sources(hg, 96, seed=5)
+    vals, tr, S = oracle_batch(hg, src)
+    g = ipg.Graph.from_host(hg)
+    for mode in ("auto", "push", "pull"):
+        d, st = g.run_multi_sssp(src, mode=mode, persistent=True)
+        assert np.array_equal(d.cpu().numpy().view(np.uint32), vals), mode
+        assert st.supersteps == S and st.halted and np.array_equal(st.trace, tr), mode
+        assert st.seconds > 0 and (st.usec > 0).all()
+
+
+def test_batch_enqueue_then_result(ipg):
+    import torch
+
+    hg = graphgen.rmat(12, 16, seed=9, symmetric=True)
+    src = graphgen.pick_sources(hg, 64, seed=2)
+    vals, tr, S = oracle_batch(hg, src)
+    g = ipg.Graph.from_host(hg)
+    d, st = g.run_multi_sssp(src, max_supersteps=64, enqueue=True)
+    assert st is None
+    st = g.multi_sssp_result()
+    assert st.status == ipg.OK and st.supersteps == S and np.array_equal(st.trace, tr)
+    assert np.array_equal(d.cpu().numpy().view(np.uint32), vals)
+    # capped before the end: the distances set so far, the rest INF
+    d, _ = g.run_multi_sssp(src, max_supersteps=3, enqueue=True)
+    st = g.multi_sssp_result()
+    assert st.status == ipg.NOT_CONVERGED and st.supersteps == 3 and not st.halted
+    got = d.cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, np.where(vals <= 2, vals, ipg.INF))
+    with pytest.raises(ipg.IpgError) as e:
+        g.run_multi_sssp(src, max_supersteps=0, enqueue=True)
+    assert e.value.status == ipg.EINVAL
+    # an out-of-range source is skipped on the device and reported afterwards
+    bad = torch.tensor([0, hg.n + 5, 3], dtype=torch.int32, device="cuda")
+    g.run_multi_sssp(bad, max_supersteps=64, enqueue=True)
+    with pytest.raises(ipg.IpgError) as e:
+        g.multi_sssp_result()
+    assert e.value.status == ipg.EINVAL
+
+
+def test_batch_plan_is_one_graph_launch(ipg):
+    # batched SSSP + PageRank over a union of graphs captured as one graph;
+    # every replay, with eager work and synchronisation in between, equals
+    # the eager runs and the oracle
+    import torch
+
+    from paper_2010_08781_amd.batch import BatchPlan
+
+    hs = graphgen.rmat(13, 16, seed=11, symmetric=True)
+    src = graphgen.pick_sources(hs, 200, seed=4)
+    vals, tr, S = oracle_batch(hs, src)
+    fam = [graphgen.rmat_small(n, 8, seed=600 + n) for n in (1024, 3000, 1500, 5000)]
+    u = graphgen.disjoint_union(fam)
+    gs, gp = ipg.Graph.from_host(hs), ipg.Graph.from_host(u)
+    parts = torch.from_numpy(u.meta["parts"].astype(np.int32)).cuda()
+    eager_ranks = gp.run("pagerank", 20, mode="pull", parts=parts)[0].clone()
+    plan = BatchPlan(gs, src, gp, parts, updates=20, max_supersteps=48).capture()
+    offs = u.meta["parts"].astype(np.int64)
+    refs = [oracle.run_graph("pagerank", h, 20).values for h in fam]
+    for rep in range(3):
+        plan.dist.fill_(0)
+        plan.replay()
+        d, st = plan.sssp()
+        assert np.array_equal(d.cpu().numpy().view(np.uint32), vals), rep
+        assert st.supersteps == S and np.array_equal(st.trace, tr), rep
+        r = plan.ranks()
+        assert torch.equal(r, eager_ranks), rep
+        rn = r.cpu().numpy()
+        for i, ref in enumerate(refs):
+            assert np.max(np.abs(rn[offs[i]: offs[i + 1]] - ref) / ref) <= 1e-12
+        gs.run("cc")  # eager work between replays
+        torch.cuda.synchronize()
