@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apps", default="pagerank,cc,sssp")
     ap.add_argument("--no-tune", action="store_true", help="run with the library's default launch parameters")
+    ap.add_argument("--no-blocked", action="store_true",
+                    help="build the graph without blocked in-edges (PageRank then pulls with the row-item kernels)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tuning_cache.json"),
                     help="autotuner cache file")
     ap.add_argument("--no-batched", action="store_true",
@@ -188,7 +190,7 @@ def main():
     hg = graphgen.workload(args.workload)
     print(f"[bench] generated {args.workload}: n={hg.n} m={hg.m} in {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)
-    g = ipg.Graph.from_host(hg)
+    g = ipg.Graph.from_host(hg, blocked=not args.no_blocked)
     apps = [a.strip() for a in args.apps.split(",") if a.strip()]
     T = args.pr_updates
     sel = None
@@ -288,9 +290,12 @@ def main():
         nbytes = pr_pull_bytes(hg.n, hg.m)
         ach = nbytes / (avg_us * 1e-6) / 1e9
         traffic = measured_traffic(args.workload, tun.get("pagerank"))
+        blocked = g.blocked and (tun.get("pagerank") or {}).get("pr_blocked", 0) != 0xFFFFFFFF
+        kernel = ("pr_blocked_kernel + pr_blocked_finish_kernel" if blocked else
+                  "pr_items_kernel + pr_longrow_kernel") + " (one PageRank pull superstep)"
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": "pr_items_kernel + pr_longrow_kernel (one PageRank pull superstep)",
+                    "kernel": kernel,
                     "bytes_per_launch": nbytes, "avg_launch_us": round(avg_us, 2),
                     "tuning": tun.get("pagerank"), "kernel_sources": kernel_source_hash()}
 

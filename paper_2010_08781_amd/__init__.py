@@ -35,7 +35,7 @@ APPS = {"pagerank": APP_PAGERANK, "pr": APP_PAGERANK, "cc": APP_CC, "sssp": APP_
 COMBINE_SUM, COMBINE_MIN = 0, 1
 DEFAULT_COMBINER = {APP_PAGERANK: COMBINE_SUM, APP_CC: COMBINE_MIN, APP_SSSP: COMBINE_MIN}
 MODES = {"auto": 0, "push": 1, "pull": 2}
-GRAPH_SYMMETRIC, GRAPH_VALIDATE, GRAPH_RENAME = 1, 2, 4
+GRAPH_SYMMETRIC, GRAPH_VALIDATE, GRAPH_RENAME, GRAPH_BLOCKED = 1, 2, 4, 8
 RUN_PERSISTENT, RUN_GRAPH, RUN_ENQUEUE = 1, 2, 4
 INF = 0xFFFFFFFF
 BATCH_MAX_SOURCES = 256
@@ -56,10 +56,10 @@ class _Desc(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("pr_hot", ctypes.c_uint32), ("pull_grid", ctypes.c_uint32), ("push_div", ctypes.c_uint32),
-                ("list_div", ctypes.c_uint32), ("gate_div", ctypes.c_uint32)]
+                ("list_div", ctypes.c_uint32), ("gate_div", ctypes.c_uint32), ("pr_blocked", ctypes.c_uint32)]
 
 
-TUNING_FIELDS = ("pr_hot", "pull_grid", "push_div", "list_div", "gate_div")
+TUNING_FIELDS = ("pr_hot", "pull_grid", "push_div", "list_div", "gate_div", "pr_blocked")
 HOT_OFF = 0xFFFFFFFF
 
 
@@ -210,7 +210,7 @@ class Graph:
     """A graph resident on the current HIP device (CSR + CSC held as torch tensors)."""
 
     def __init__(self, n, csr_off, csr_dst, csc_off=None, csc_src=None, csr_w=None, csc_w=None,
-                 symmetric=False, validate=True, stream=None, rename=True):
+                 symmetric=False, validate=True, stream=None, rename=True, blocked=False):
         import torch
 
         self.n = int(n)
@@ -235,8 +235,9 @@ class Graph:
         self._keep = (csr_off, csr_dst, csc_off, csc_src, csr_w, csc_w)
         self.weighted = csr_w is not None
         self.renamed = bool(rename)
+        self.blocked = bool(blocked)
         flags = (GRAPH_SYMMETRIC if symmetric else 0) | (GRAPH_VALIDATE if validate else 0) | \
-            (GRAPH_RENAME if rename else 0)
+            (GRAPH_RENAME if rename else 0) | (GRAPH_BLOCKED if blocked else 0)
         d = _Desc(self.n, self.m, csr_off.data_ptr(), csr_dst.data_ptr() if self.m else None,
                   csc_off.data_ptr(), csc_src.data_ptr() if self.m else None,
                   csr_w.data_ptr() if csr_w is not None else None,
@@ -255,7 +256,7 @@ class Graph:
         return cls(*args, **kw)
 
     @classmethod
-    def from_host(cls, hg, device="cuda", validate=True, weighted=True, rename=True) -> "Graph":
+    def from_host(cls, hg, device="cuda", validate=True, weighted=True, rename=True, blocked=False) -> "Graph":
         """Upload any object with n, csr_off, csr_dst, csc_off, csc_src (numpy) and optional csr_w/csc_w."""
         import torch
 
@@ -275,7 +276,7 @@ class Graph:
             csr_w = up(hg.csr_w.astype(np.uint32), np.int32)
             csc_w = csr_w if sym else up(hg.csc_w.astype(np.uint32), np.int32)
         return cls(hg.n, csr_off, csr_dst, csc_off, csc_src, csr_w, csc_w, symmetric=sym, validate=validate,
-                   rename=rename)
+                   rename=rename, blocked=blocked)
 
     def workspace(self, app: int):
         import torch
@@ -484,13 +485,15 @@ def values_to_numpy(t) -> np.ndarray:
 
 # ----------------------------------------------------------- footprint ----
 
-def footprint(n: int, m: int, symmetric: bool = False, weighted: bool = False, rename: bool = True) -> dict:
+def footprint(n: int, m: int, symmetric: bool = False, weighted: bool = False, rename: bool = True,
+              blocked: bool = False) -> dict:
     """Device memory of a graph and of each application's run, in bytes
     (the library's own size queries plus the caller-owned graph arrays):
     the device-side counterpart of the paper's memory-usage comparison
     (Table 3).  A symmetric graph stores one adjacency (CSC aliases CSR)."""
     L = lib()
-    flags = (GRAPH_SYMMETRIC if symmetric else 0) | (GRAPH_RENAME if rename else 0)
+    flags = (GRAPH_SYMMETRIC if symmetric else 0) | (GRAPH_RENAME if rename else 0) | \
+        (GRAPH_BLOCKED if blocked else 0)
     adj = 8 * (n + 1) + 4 * m
     arrays = {"csr": adj, "csc": 0 if symmetric else adj,
               "weights": (4 * m if symmetric else 8 * m) if weighted else 0}
@@ -499,7 +502,8 @@ def footprint(n: int, m: int, symmetric: bool = False, weighted: bool = False, r
     runs = {name: int(L.ipg_run_workspace_bytes(n, m, app)) for name, app in
             (("pagerank", APP_PAGERANK), ("cc", APP_CC), ("sssp", APP_SSSP))}
     runs["multi_sssp"] = int(L.ipg_multi_sssp_workspace_bytes(n, m))
-    out = {"n": n, "m": m, "symmetric": symmetric, "weighted": weighted, "rename": rename, "graph_arrays": arrays,
+    out = {"n": n, "m": m, "symmetric": symmetric, "weighted": weighted, "rename": rename, "blocked": blocked,
+           "graph_arrays": arrays,
            "graph_workspace": graph_ws, "run_workspace": runs,
            "total": {k: base + v for k, v in runs.items()}}
     out["bytes_per_edge"] = {k: round(v / max(m, 1), 3) for k, v in out["total"].items()}

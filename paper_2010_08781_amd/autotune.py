@@ -2,7 +2,8 @@
 
 For a graph and an application it times the runs of a small grid of
 candidate parameter sets (ipg_tuning: the PageRank LDS outbox cache size,
-the pull grid, the push/pull rule's divisor and the frontier-list limit) and
+the pull grid, the push/pull rule's divisor and the frontier-list limit; on a
+graph with blocked in-edges also the row-item form of PageRank's pull) and
 keeps the fastest.  The choice is cached in a JSON file under a key made of
 the graph's signature -- vertex and edge counts, symmetry, weights, naming
 and a coarse profile of its out-degrees -- so a graph of the same shape is
@@ -43,6 +44,8 @@ def signature(hg, graph) -> str:
     desc = {"n": int(hg.n), "m": int(len(hg.csr_dst)), "sym": bool(getattr(hg, "symmetric", False)),
             "w": getattr(hg, "csr_w", None) is not None, "renamed": bool(getattr(graph, "renamed", False)),
             "deg": hist}
+    if getattr(graph, "blocked", False):
+        desc["blocked"] = True
     return hashlib.sha1(json.dumps(desc, sort_keys=True).encode()).hexdigest()[:16]
 
 
@@ -59,6 +62,19 @@ def _save(path, cache):
     with open(tmp, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
     os.replace(tmp, path)
+
+
+def candidates(graph, app: str) -> list:
+    """The parameter sets tried for `app` on this graph: the product of the
+    application's space; for PageRank on a graph with blocked in-edges, the
+    blocked pull (which has no launch parameters) and then the row-item
+    pull over the space."""
+    space = SPACES[app]
+    names = sorted(space)
+    out = [dict(zip(names, combo)) for combo in itertools.product(*(space[k] for k in names))]
+    if app == "pagerank" and getattr(graph, "blocked", False):
+        out = [{"pr_blocked": 0}] + [dict(t, pr_blocked=0xFFFFFFFF) for t in out]
+    return out
 
 
 def _runner(graph, app, kw):
@@ -83,12 +99,9 @@ def tune(graph, hg, app: str, cache_path: Optional[str] = DEFAULT_CACHE, reps: i
     if not retune and key in cache:
         return dict(cache[key]["tuning"])
     run = _runner(graph, app, kw)
-    space = SPACES[app]
-    names = sorted(space)
     results = []
     run(None)  # warm-up (first-touch of the workspaces)
-    for combo in itertools.product(*(space[k] for k in names)):
-        t = dict(zip(names, combo))
+    for t in candidates(graph, app):
         run(t)
         secs = [run(t).seconds for _ in range(reps)]
         results.append((float(np.median(secs)), t))

@@ -88,6 +88,70 @@ struct TilingTables {
   uint32_t nb, nl, nc, ni;
 };
 
+// Destination-blocked, source-sorted copy of the in-edges for PageRank's
+// blocked pull (IPG_GRAPH_BLOCKED).  The destinations are cut into blocks of
+// kBlkRows rows -- one workgroup's LDS of FP64 partial sums -- and each
+// block's in-edges are stored sorted by source (ties by destination), one
+// 32-bit word per edge: the source's offset within its window of
+// 2^kBlkWinBits sources in the high half, the destination's row within the
+// block in the low half.  The edges are cut into chunks of at most kBlkChunk
+// edges that never straddle a window (so a wavefront's window base is
+// uniform), and each block's chunks into slices, about one per CU.  A block
+// with one slice is finished by that slice's workgroup; the slices of a
+// larger block store partial sums that a second launch adds in slice order.
+constexpr uint32_t kBlkRows = 20224;
+constexpr uint32_t kBlkWinBits = 16;
+constexpr uint32_t kBlkChunk = 256;
+constexpr uint32_t kBlkSlices = 256;
+constexpr uint64_t kBlkMinSliceEdges = 65536;
+// Slice balancing: a 128-byte outbox line a chunk touches costs about as
+// much as this many edges (fitted to measured slice times on MI355X).
+constexpr uint64_t kBlkLineCost = 6;
+static_assert(kBlkRows <= (1u << 16), "row within a block fits 16 bits");
+
+struct BlkChunk {
+  uint64_t e0;     // first edge
+  uint32_t wbase;  // first source of the chunk's window
+  uint32_t n;      // edges (1 .. kBlkChunk)
+};
+struct BlkSlice {
+  uint32_t block;  // destination block
+  uint32_t c0, c1; // chunks [c0, c1)
+  uint32_t slot;   // partial-sum slot, kNoSlot when the slice is the block's only one
+};
+struct BlkFin {
+  uint32_t block;  // a block with more than one slice
+  uint32_t slot0;  // its slices' partial slots [slot0, slot0 + k)
+  uint32_t k;
+  uint32_t pad;
+};
+
+inline uint64_t blk_blocks(uint32_t n) { return (static_cast<uint64_t>(n) + kBlkRows - 1) / kBlkRows; }
+inline uint64_t blk_windows(uint32_t n) { return (static_cast<uint64_t>(n) + (1u << kBlkWinBits) - 1) >> kBlkWinBits; }
+// Target number of slices: about one per CU, none under kBlkMinSliceEdges edges.
+inline uint32_t blk_target_slices(uint64_t e) {
+  const uint64_t s = (e + kBlkMinSliceEdges - 1) / kBlkMinSliceEdges;
+  return static_cast<uint32_t>(s < 1 ? 1 : (s > kBlkSlices ? kBlkSlices : s));
+}
+// Chunks: at most one partial chunk per non-empty (block, window) segment.
+inline uint64_t blk_chunks_cap(uint32_t n, uint64_t e) {
+  const uint64_t segs = blk_blocks(n) * blk_windows(n);
+  return e / kBlkChunk + (segs < e ? segs : e) + 1;
+}
+// With fewer blocks than S, the S slices are shared out over the blocks in
+// proportion to their edges (at least one each); with more, every block is
+// one slice.  So the blocks with several slices hold at most S of them.
+inline uint64_t blk_slots_cap(uint64_t e) { return blk_target_slices(e); }
+
+struct BlockedTables {
+  uint32_t* edges;    // [e] packed edges (see above)
+  BlkChunk* chunks;
+  BlkSlice* slices;
+  BlkFin* fin;
+  double* partial;    // [slots][kBlkRows] partial sums of multi-slice blocks
+  uint32_t nchunks, nslices, nfin, nslots;
+};
+
 struct GraphTables {
   uint32_t* outdeg;     // [n] out-degree (u32)
   uint32_t* flags;      // [4] validation flags (+ a counter)
@@ -100,6 +164,9 @@ struct GraphTables {
   uint64_t* off_hot;    // [n+1] CSC offsets by new name
   int32_t* src_hot;     // [e] CSC sources, new names
   TilingTables pull_hot;
+  // IPG_GRAPH_BLOCKED: the blocked in-edges of the CSC PageRank's pull uses
+  // (the hot-first one when present), else edges == null.
+  BlockedTables blk;
 };
 
 // Pull-side view of the CSC handed to the gather kernels.  A launch has nc
@@ -145,7 +212,7 @@ struct ipg_graph {
     const void* ws;
     const uint32_t* parts;
     uint32_t num_parts;
-    uint32_t hot, grid;
+    uint32_t hot, grid, blocked;
   } pr_key;
 };
 

@@ -229,7 +229,6 @@ __global__ __launch_bounds__(kBlock) void ms_pull_kernel(MsPullArgs a) {
   uint32_t* soff = s_off[wv];
   const int32_t* src = a.t.src;
   const uint64_t* off = a.t.off;
-  const uint32_t n = a.r.n;
   MsCount c;
   const uint32_t nw = gridDim.x * kWavesPerBlock;
   for (uint32_t item = blockIdx.x * kWavesPerBlock + wv; item < a.t.ni; item += nw) {

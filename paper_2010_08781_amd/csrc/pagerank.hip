@@ -75,13 +75,59 @@ __device__ __forceinline__ void pr_finish(const PrPullArgs& a, uint32_t v, doubl
   pr_store(a, v, rank, a.outdeg[v], l1);
 }
 
+// One pull item held in registers ahead of its gathers: its metadata, its
+// CSC sources and, for a row item, the in-edge offsets and out-degrees of
+// its rows.
+struct ItemRegs {
+  PullItem it;
+  uint32_t ne;       // edges of the item (<= kWaveTile)
+  uint32_t nrows;    // rows of a row item, 0 for a long-row chunk
+  int32_t u[kWaveTile / kWave];
+  uint32_t off_lane; // low word of the CSC offset of row min(lane, nrows)
+  uint32_t off_end;  // low word of the CSC offset of row nrows (the item's end)
+  uint32_t deg;      // out-degree of row `lane` (lane < nrows)
+};
+static_assert(kItemRows == kWave, "one row per lane");
+
+__device__ __forceinline__ PullItem no_item() {
+  PullItem it;
+  it.e0 = 0;
+  it.ne = 0;
+  it.r0 = it.r1 = 0;
+  it.slot = kNoSlot;
+  return it;
+}
+
+// Every load is unconditional, from an index clamped into the item (an item
+// without edges reads a dummy word of the item table), so that no lane
+// branches around a load: a load under a branch is followed by a wait for
+// every load before it, the gathers of the previous item included.  Every
+// item has r0 < N (row items hold at least one row, a chunk names its long
+// row), so the clamped row indices are in range.
+__device__ __forceinline__ void load_item(const PrPullArgs& a, const PullItem& it, ItemRegs& R) {
+  constexpr int kPer = kWaveTile / kWave;
+  const uint32_t lane = lane_id();
+  R.it = it;
+  R.ne = it.ne < kWaveTile ? it.ne : kWaveTile;  // ne > kWaveTile only with bad offsets
+  R.nrows = it.slot != kNoSlot ? 0 : it.r1 - it.r0;
+  const int32_t* base = R.ne ? a.t.src + it.e0 : reinterpret_cast<const int32_t*>(a.t.items);
+  const uint32_t last = R.ne ? R.ne - 1 : 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const uint32_t i = lane + k * kWave;
+    R.u[k] = __builtin_nontemporal_load(base + (i < last ? i : last));
+  }
+  R.off_lane = static_cast<uint32_t>(a.t.off[it.r0 + (lane < R.nrows ? lane : R.nrows)]);
+  R.off_end = static_cast<uint32_t>(a.t.off[it.r0 + R.nrows]);
+  R.deg = a.outdeg[it.r0 + (lane < R.nrows ? lane : 0)];
+}
+
 // Pull superstep, first launch.  Every wavefront works through its own pull
 // items (grid-stride over wavefronts), with its own LDS tile and no
-// workgroup barrier, so 32 items per CU are in flight.  An item needs one
-// metadata load; then all of its independent loads are issued together --
-// the CSC sources (non-temporal; indices clamped into the item so no lane
-// branches), the row offsets and out-degrees -- and the outbox gathers
-// follow in one more round trip.
+// workgroup barrier.  The item loop is software-pipelined so that one
+// memory round trip per item is exposed instead of three: while the
+// outboxes of item i are gathered, the CSC sources, row offsets and
+// out-degrees of item i+1 and the metadata of item i+2 are in flight.
 //  * row item: the gathered outboxes are staged in LDS and each row is
 //    summed by G lanes (G from the item's row count), then finished here;
 //  * long-row chunk: a fixed-order wavefront sum stored as the chunk's
@@ -93,7 +139,8 @@ __device__ __forceinline__ void pr_finish(const PrPullArgs& a, uint32_t v, doubl
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void pr_items_kernel(PrPullArgs a, uint32_t hot) {
   constexpr int kPer = kWaveTile / kWave;
-  constexpr int kRowPer = (kItemRows + kWave) / kWave;
+  constexpr uint32_t kThreads = WAVES * kWave;
+  constexpr int kHotBatch = 12;  // outbox loads in flight per thread while the cache fills
   __shared__ double s_tile[WAVES][kWaveTile];
   __shared__ uint32_t s_off[WAVES][kItemRows + 1];
   __shared__ uint32_t s_deg[WAVES][kItemRows];
@@ -102,73 +149,95 @@ __global__ __launch_bounds__(WAVES * kWave) void pr_items_kernel(PrPullArgs a, u
   double* tile = s_tile[wv];
   uint32_t* soff = s_off[wv];
   uint32_t* sdeg = s_deg[wv];
-  const int32_t* src = a.t.src;
-  const uint64_t* off = a.t.off;
+  const uint64_t ni = a.t.ni, nw = static_cast<uint64_t>(gridDim.x) * WAVES;
+  uint64_t item = static_cast<uint64_t>(blockIdx.x) * WAVES + wv;
+  PullItem m_next = item + nw < ni ? a.t.items[item + nw] : no_item();
+  ItemRegs cur;
+  load_item(a, item < ni ? a.t.items[item] : no_item(), cur);
   if (hot) {
-    for (uint32_t i = threadIdx.x; i < hot; i += WAVES * kWave) s_hot[i] = a.contrib_in[i];
-    __syncthreads();
-  }
-  const uint32_t nw = gridDim.x * WAVES;
-  double l1 = 0.0;
-  for (uint32_t item = blockIdx.x * WAVES + wv; item < a.t.ni; item += nw) {
-    const PullItem it = a.t.items[item];
-    const bool chunk = it.slot != kNoSlot;
-    const uint32_t ne = it.ne < kWaveTile ? it.ne : kWaveTile;  // ne > kWaveTile only with bad offsets
-    const uint32_t nrows = chunk ? 0 : it.r1 - it.r0;
-    int32_t u[kPer];
+    for (uint32_t b = 0; b < hot; b += kHotBatch * kThreads) {
+      double h[kHotBatch];
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const uint32_t i = lane + k * kWave;
-      u[k] = ne ? __builtin_nontemporal_load(src + it.e0 + (i < ne ? i : ne - 1)) : 0;
-    }
-    if (!chunk) {
+      for (int k = 0; k < kHotBatch; ++k) {
+        const uint32_t i = b + threadIdx.x + k * kThreads;
+        h[k] = i < hot ? a.contrib_in[i] : 0.0;
+      }
 #pragma unroll
-      for (int k = 0; k < kRowPer; ++k) {
-        const uint32_t r = lane + k * kWave;
-        if (r <= nrows) soff[r] = static_cast<uint32_t>(off[it.r0 + r] - it.e0);
-        if (r < nrows) sdeg[r] = a.outdeg[it.r0 + r];
+      for (int k = 0; k < kHotBatch; ++k) {
+        const uint32_t i = b + threadIdx.x + k * kThreads;
+        if (i < hot) s_hot[i] = h[k];
       }
     }
-    double x[kPer];
+    __syncthreads();
+  }
+  double l1 = 0.0;
+  for (; item < ni; item += nw) {
+    const PullItem m2 = item + 2 * nw < ni ? a.t.items[item + 2 * nw] : no_item();
+    // Cold sources are gathered from memory and hot ones from LDS into
+    // separate registers, merged only where the values are used: a shared
+    // destination register would make every LDS read wait for all the
+    // gathers before it.
+    double xg[kPer], xh[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-      const uint32_t uk = static_cast<uint32_t>(u[k]);
-      x[k] = !ne ? 0.0 : (uk < hot ? s_hot[uk] : a.contrib_in[uk]);
+      const uint32_t uk = static_cast<uint32_t>(cur.u[k]);
+      xg[k] = 0.0;
+      if (cur.ne && uk >= hot) xg[k] = a.contrib_in[uk];
     }
-    if (chunk) {
+    if (hot) {
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const uint32_t uk = static_cast<uint32_t>(cur.u[k]);
+        xh[k] = s_hot[uk < hot ? uk : 0];
+      }
+    }
+    ItemRegs nxt;
+    load_item(a, m_next, nxt);
+    double x[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) x[k] = static_cast<uint32_t>(cur.u[k]) < hot ? xh[k] : xg[k];
+    if (cur.nrows == 0) {  // long-row chunk
       double s = 0.0;
 #pragma unroll
       for (int k = 0; k < kPer; ++k)
-        if (lane + k * kWave < ne) s += x[k];
+        if (lane + k * kWave < cur.ne) s += x[k];
       s = wave_sum(s);
-      if (lane == 0) a.partial[it.slot] = s;
-      continue;
-    }
+      if (lane == 0 && cur.it.slot != kNoSlot) a.partial[cur.it.slot] = s;
+    } else {
+      const uint32_t nrows = cur.nrows, ne = cur.ne, e0 = static_cast<uint32_t>(cur.it.e0);
+      if (lane < nrows) {  // offsets relative to the item: differences of the low words
+        soff[lane] = cur.off_lane - e0;
+        sdeg[lane] = cur.deg;
+      }
+      if (lane == 0) soff[nrows] = cur.off_end - e0;
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const uint32_t i = lane + k * kWave;
-      if (i < ne) tile[i] = x[k];
-    }
-    wave_lds_sync();
-    uint32_t G = kWave;
-    while (G > 1 && G * nrows > kWave) G >>= 1;
-    const uint32_t groups = kWave / G, gi = lane / G, li = lane % G;
-    for (uint32_t rb = 0; rb < nrows; rb += groups) {
-      const uint32_t row = rb + gi;
-      double s = 0.0;
-      if (row < nrows) {
-        uint32_t lo = soff[row], hi = soff[row + 1];
-        if (hi > ne) hi = ne;
-        for (uint32_t j = lo + li; j < hi; j += G) s += tile[j];
+      for (int k = 0; k < kPer; ++k) {
+        const uint32_t i = lane + k * kWave;
+        if (i < ne) tile[i] = x[k];
       }
-      for (uint32_t o = G >> 1; o >= 1; o >>= 1) s += __shfl_xor(s, static_cast<int>(o));
-      if (li == 0 && row < nrows) {
-        const uint32_t v = it.r0 + row;
-        const double rank = pr_ratio(a.ratio, a.part_n, v) + 0.85 * s;
-        pr_store(a, v, rank, sdeg[row], l1);
+      wave_lds_sync();
+      uint32_t G = kWave;
+      while (G > 1 && G * nrows > kWave) G >>= 1;
+      const uint32_t groups = kWave / G, gi = lane / G, li = lane % G;
+      for (uint32_t rb = 0; rb < nrows; rb += groups) {
+        const uint32_t row = rb + gi;
+        double s = 0.0;
+        if (row < nrows) {
+          uint32_t lo = soff[row], hi = soff[row + 1];
+          if (hi > ne) hi = ne;
+          for (uint32_t j = lo + li; j < hi; j += G) s += tile[j];
+        }
+        for (uint32_t o = G >> 1; o >= 1; o >>= 1) s += __shfl_xor(s, static_cast<int>(o));
+        if (li == 0 && row < nrows) {
+          const uint32_t v = cur.it.r0 + row;
+          const double rank = pr_ratio(a.ratio, a.part_n, v) + 0.85 * s;
+          pr_store(a, v, rank, sdeg[row], l1);
+        }
       }
+      wave_lds_sync();  // the tile is rewritten by the next item
     }
-    wave_lds_sync();  // the tile is rewritten by the next item
+    cur = nxt;
+    m_next = m2;
   }
   if (a.l1) flush_l1(a.l1, l1);
 }
@@ -185,6 +254,173 @@ __global__ __launch_bounds__(kBlock) void pr_longrow_kernel(PrPullArgs a) {
     for (uint32_t i = lane_id(); i < nch; i += kWave) s += a.partial[f + i];
     s = wave_sum(s);
     if (lane_id() == 0) pr_finish(a, a.t.long_rows[l], s, l1);
+  }
+  if (a.l1) flush_l1(a.l1, l1);
+}
+
+// Blocked pull (IPG_GRAPH_BLOCKED): the in-edges of each block of kBlkRows
+// destinations, sorted by source, streamed through one workgroup per slice.
+struct PrBlkArgs {
+  const uint32_t* edges;
+  const BlkChunk* chunks;
+  const BlkSlice* slices;
+  const BlkFin* fin;
+  double* partial;
+  uint32_t n;
+  uint32_t nfin;
+};
+constexpr uint32_t kBlkThreads = 1024;
+constexpr int kBlkGroup = 4;  // chunks a wavefront takes per step
+
+// A chunk past the slice's end: no edges (its loads read the slice table).
+__device__ __forceinline__ BlkChunk blk_chunk_at(const PrBlkArgs& b, uint64_t c, uint32_t c1) {
+  if (c < c1) return b.chunks[c];
+  BlkChunk z;
+  z.e0 = 0;
+  z.wbase = 0;
+  z.n = 0;
+  return z;
+}
+
+// The packed edges of a chunk, one per lane and register, the index clamped
+// into the chunk so that every load is unconditional.
+__device__ __forceinline__ void blk_load(const PrBlkArgs& b, const BlkChunk& ch, uint32_t (&p)[kBlkChunk / kWave]) {
+  const uint32_t lane = lane_id();
+  const uint32_t* base = ch.n ? b.edges + ch.e0 : reinterpret_cast<const uint32_t*>(b.slices);
+  const uint32_t last = ch.n ? ch.n - 1 : 0;
+#pragma unroll
+  for (int k = 0; k < static_cast<int>(kBlkChunk / kWave); ++k) {
+    const uint32_t i = lane + k * kWave;
+    p[k] = __builtin_nontemporal_load(base + (i < last ? i : last));
+  }
+}
+
+// Blocked pull, first launch: workgroup = slice.  The block's sums start at
+// zero in LDS; every wavefront streams its share of the slice's chunks
+// (software-pipelined: the packed edges of the next chunk load while the
+// outboxes of this one are gathered), gathers each edge's outbox -- the
+// sources of a chunk are sorted and share one window, so neighbouring lanes
+// mostly read the same cache lines -- and adds it into its destination's sum
+// with an LDS atomic.  A block's only slice then finishes the block's
+// vertices; a slice of a larger block stores its sums as a partial.
+__global__ __launch_bounds__(kBlkThreads) void pr_blocked_kernel(PrPullArgs a, PrBlkArgs b) {
+  constexpr int kPer = kBlkChunk / kWave;
+  constexpr uint32_t kWaves = kBlkThreads / kWave;
+  // + one slot per lane that lanes past a chunk's end add 0.0 into, so that
+  // the adds need no branch (a gather used only under a branch is issued
+  // late, inside it)
+  __shared__ double part[kBlkRows + kWave];
+  const BlkSlice sl = b.slices[blockIdx.x];
+  for (uint32_t r = threadIdx.x; r < kBlkRows; r += kBlkThreads) part[r] = 0.0;
+  __syncthreads();
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = lane_id();
+  // A wavefront takes kBlkGroup chunks per step: chunks c + g * kWaves of
+  // the slice.  One step gathers the outboxes of its chunks, starts loading
+  // the edges of the next step's chunks into `pn`, and adds its messages.
+  // The loop alternates two register sets, so no loaded value is copied (a
+  // copy would wait for the load).
+  using Group = BlkChunk[kBlkGroup];
+  using Edges = uint32_t[kBlkGroup][kPer];
+  auto meta = [&](uint64_t c, Group& ch) {
+#pragma unroll
+    for (int g = 0; g < kBlkGroup; ++g) ch[g] = blk_chunk_at(b, c + g * kWaves, sl.c1);
+  };
+  auto load = [&](const Group& ch, Edges& p) {
+#pragma unroll
+    for (int g = 0; g < kBlkGroup; ++g) blk_load(b, ch[g], p[g]);
+  };
+  auto step = [&](const Group& ch, const Edges& p, const Group& next, Edges& pn) {
+    double x[kBlkGroup][kPer];
+#pragma unroll
+    for (int g = 0; g < kBlkGroup; ++g)
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) x[g][k] = a.contrib_in[ch[g].wbase + ((ch[g].n ? p[g][k] : 0u) >> 16)];
+    load(next, pn);
+#pragma unroll
+    for (int g = 0; g < kBlkGroup; ++g)
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const bool in = lane + k * kWave < ch[g].n;
+        atomicAdd(&part[in ? p[g][k] & 0xFFFFu : kBlkRows + lane], in ? x[g][k] : 0.0);
+      }
+  };
+  constexpr uint64_t kStride = static_cast<uint64_t>(kWaves) * kBlkGroup;
+  uint64_t c = static_cast<uint64_t>(sl.c0) + wv;
+  Group ca, cb, n1, n2;
+  Edges pa, pb;
+  meta(c, ca);
+  meta(c + kStride, cb);
+  load(ca, pa);
+  // Two steps per iteration and no exit between them (past the slice's end
+  // the chunks are empty and add nothing): an exit there would let the
+  // compiler move the first step's prefetch behind it, to just before use.
+  while (c < sl.c1) {
+    meta(c + 2 * kStride, n1);
+    step(ca, pa, cb, pb);
+    meta(c + 3 * kStride, n2);
+    step(cb, pb, n1, pa);
+    c += 2 * kStride;
+#pragma unroll
+    for (int g = 0; g < kBlkGroup; ++g) {
+      ca[g] = n1[g];
+      cb[g] = n2[g];
+    }
+  }
+  __syncthreads();
+  const uint32_t r0 = sl.block * kBlkRows;
+  const uint32_t rows = b.n - r0 < kBlkRows ? b.n - r0 : kBlkRows;
+  double l1 = 0.0;
+  if (sl.slot == kNoSlot) {
+    for (uint32_t r = threadIdx.x; r < rows; r += kBlkThreads) pr_finish(a, r0 + r, part[r], l1);
+  } else {
+    double* dst = b.partial + static_cast<size_t>(sl.slot) * kBlkRows;
+    for (uint32_t r = threadIdx.x; r < rows; r += kBlkThreads) dst[r] = part[r];
+  }
+  if (a.l1) flush_l1(a.l1, l1);
+}
+
+// Blocked pull, second launch: the vertices of every block with several
+// slices add the slices' partial sums.  A workgroup takes 64 rows of one
+// block; its kFinWaves wavefronts each add a contiguous run of the slices
+// (in slice order, eight loads in flight per lane), and the runs' sums are
+// added in wavefront order: a fixed order.
+constexpr uint32_t kFinRows = 64;
+constexpr uint32_t kFinWaves = 8;
+__global__ __launch_bounds__(kFinWaves * kWave) void pr_blocked_finish_kernel(PrPullArgs a, PrBlkArgs b) {
+  constexpr uint32_t kGroups = (kBlkRows + kFinRows - 1) / kFinRows;
+  __shared__ double red[kFinWaves][kFinRows];
+  const uint64_t total = static_cast<uint64_t>(b.nfin) * kGroups;
+  const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
+  double l1 = 0.0;
+  for (uint64_t w = blockIdx.x; w < total; w += gridDim.x) {  // uniform over the workgroup
+    const BlkFin f = b.fin[w / kGroups];
+    const uint32_t r0 = f.block * kBlkRows;
+    const uint32_t rows = b.n - r0 < kBlkRows ? b.n - r0 : kBlkRows;
+    const uint32_t g0 = static_cast<uint32_t>(w % kGroups) * kFinRows;
+    if (g0 >= rows) continue;
+    const uint32_t r = g0 + lane, rr = r < rows ? r : rows - 1;
+    const uint32_t k0 = f.k * wv / kFinWaves, k1 = f.k * (wv + 1) / kFinWaves;
+    double sum = 0.0;
+    for (uint32_t k = k0; k < k1; k += 8) {
+      double x[8];
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j) {
+        const uint32_t kk = k + j < k1 ? k + j : k1 - 1;
+        x[j] = b.partial[static_cast<size_t>(f.slot0 + kk) * kBlkRows + rr];
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j)
+        if (k + j < k1) sum += x[j];
+    }
+    red[wv][lane] = sum;
+    __syncthreads();
+    if (wv == 0 && r < rows) {
+      double t = 0.0;
+#pragma unroll
+      for (uint32_t j = 0; j < kFinWaves; ++j) t += red[j][lane];
+      pr_finish(a, r0 + r, t, l1);
+    }
+    __syncthreads();
   }
   if (a.l1) flush_l1(a.l1, l1);
 }
@@ -329,6 +565,7 @@ struct PrPullStore {
   const uint32_t* outdeg;
   const uint32_t* perm;  // null: no renaming
   double* value;         // ranks as the supersteps store them
+  const BlockedTables* blk;  // blocked in-edges of the same CSC, or null
 };
 static PrPullStore pr_store_of(const ipg_graph* g, const RunWs& w) {
   PrPullStore p;
@@ -343,7 +580,36 @@ static PrPullStore pr_store_of(const ipg_graph* g, const RunWs& w) {
     p.perm = nullptr;
     p.value = w.value_f64;
   }
+  p.blk = g->t.blk.edges ? &g->t.blk : nullptr;
   return p;
+}
+
+// One pull superstep: the blocked launches when the store has blocked
+// in-edges and the tuning allows them, else the row items and the long-row
+// sums.
+static hipError_t launch_pr_pull(const PrPullArgs& a, const PrPullStore& ps, const Tune& tn, uint32_t n,
+                                 hipStream_t s) {
+  if (ps.blk && tn.pr_blocked) {
+    PrBlkArgs b;
+    b.edges = ps.blk->edges;
+    b.chunks = ps.blk->chunks;
+    b.slices = ps.blk->slices;
+    b.fin = ps.blk->fin;
+    b.partial = ps.blk->partial;
+    b.n = n;
+    b.nfin = ps.blk->nfin;
+    hipLaunchKernelGGL(pr_blocked_kernel, dim3(ps.blk->nslices), dim3(kBlkThreads), 0, s, a, b);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess || !b.nfin) return err;
+    constexpr uint32_t kGroups = (kBlkRows + kFinRows - 1) / kFinRows;
+    const uint32_t grid = grid_for(static_cast<uint64_t>(b.nfin) * kGroups, 1, 8192);
+    hipLaunchKernelGGL(pr_blocked_finish_kernel, dim3(grid), dim3(kFinWaves * kWave), 0, s, a, b);
+    return hipGetLastError();
+  }
+  hipError_t err = launch_pr_items(a, ps.perm != nullptr, tn, n, s);
+  if (err != hipSuccess || !ps.t.nl) return err;
+  hipLaunchKernelGGL(pr_longrow_kernel, dim3((ps.t.nl + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
 }
 
 // Every launch of one PageRank run, in order, on stream s (also used to
@@ -381,12 +647,7 @@ static hipError_t enqueue_pagerank(ipg_graph* g, uint32_t T, bool push, const Ru
       a.contrib_in = (step & 1) ? w.f64_a : w.f64_b;
       a.contrib_out = (step & 1) ? w.f64_b : w.f64_a;
       a.last = step == T;
-      if ((err = launch_pr_items(a, ps.perm != nullptr, tn, n, s)) != hipSuccess) return err;
-      if (ps.t.nl) {
-        hipLaunchKernelGGL(pr_longrow_kernel, dim3((ps.t.nl + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0,
-                           s, a);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
-      }
+      if ((err = launch_pr_pull(a, ps, tn, n, s)) != hipSuccess) return err;
       if (tm && (err = tm->step(s, step)) != hipSuccess) return err;
     }
     if (ps.perm) {
@@ -426,7 +687,7 @@ static ipg_status pagerank_graph(ipg_graph* g, uint32_t T, bool push, const RunW
                                  const uint32_t* part_off, uint32_t parts, const Tune& tn, hipGraphExec_t* out) {
   auto& k = g->pr_key;
   if (g->pr_exec && k.T == T && k.push == (push ? 1 : 0) && k.ws == ws && k.parts == part_off && k.num_parts == parts &&
-      k.hot == tn.pr_hot && k.grid == tn.pull_grid) {
+      k.hot == tn.pr_hot && k.grid == tn.pull_grid && k.blocked == tn.pr_blocked) {
     *out = g->pr_exec;
     return IPG_OK;
   }
@@ -457,6 +718,7 @@ static ipg_status pagerank_graph(ipg_graph* g, uint32_t T, bool push, const RunW
   k.num_parts = parts;
   k.hot = tn.pr_hot;
   k.grid = tn.pull_grid;
+  k.blocked = tn.pr_blocked;
   *out = g->pr_exec;
   return IPG_OK;
 }
@@ -515,12 +777,7 @@ static ipg_status run_pagerank_converge(ipg_graph* g, uint32_t Tmax, bool push, 
       IPG_HIP(fill_f64(w.l1, kSlotDoubles, 0.0, s));
       a.contrib_in = (step & 1) ? w.f64_a : w.f64_b;
       a.contrib_out = (step & 1) ? w.f64_b : w.f64_a;
-      IPG_HIP(launch_pr_items(a, ps.perm != nullptr, tn, n, s));
-      if (ps.t.nl) {
-        hipLaunchKernelGGL(pr_longrow_kernel, dim3((ps.t.nl + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0,
-                           s, a);
-        IPG_HIP(hipGetLastError());
-      }
+      IPG_HIP(launch_pr_pull(a, ps, tn, n, s));
       IPG_HIP(tm.step(s, step));
       double d = 0.0;
       const ipg_status rc = change(step, &d);

@@ -161,6 +161,13 @@ static size_t carve_graph(Carver& c, uint32_t n, uint64_t e, uint32_t flags, Gra
     tt.src_hot = c.take<int32_t>(e ? e : 1);
     carve_tiling(c, n, e, &tt.pull_hot);
   }
+  if (flags & IPG_GRAPH_BLOCKED) {
+    tt.blk.edges = c.take<uint32_t>(e ? e : 1);
+    tt.blk.chunks = c.take<BlkChunk>(blk_chunks_cap(n, e));
+    tt.blk.slices = c.take<BlkSlice>(blk_blocks(n) + blk_slots_cap(e));
+    tt.blk.fin = c.take<BlkFin>(blk_blocks(n));
+    tt.blk.partial = c.take<double>(blk_slots_cap(e) * kBlkRows);
+  }
   if (t) *t = tt;
   return align_up(c.used, 256);
 }
@@ -276,6 +283,158 @@ static ipg_status build_hot_store(const uint64_t* csc_off, const int32_t* csc_sr
   return build_tiling(t->off_hot, n, e, &t->pull_hot, t->flags + kNumFlags, s);
 }
 
+// The blocked in-edges of a CSC (validated): two stable counting sorts on
+// the host -- the edges by source (each source's edges in destination
+// order), then by destination block -- so that every block holds its edges
+// sorted by source; then the chunks, the slices and the finish list.
+static ipg_status build_blocked(const uint64_t* csc_off, const int32_t* csc_src, uint32_t n, uint64_t e,
+                                BlockedTables* b, hipStream_t s) {
+  std::vector<uint64_t> off((size_t)n + 1);
+  std::vector<int32_t> src(e);
+  IPG_HIP(hipMemcpyAsync(off.data(), csc_off, off.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  if (e) IPG_HIP(hipMemcpyAsync(src.data(), csc_src, e * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  IPG_HIP(hipStreamSynchronize(s));
+  // the host loops below index with these: check them here even without IPG_GRAPH_VALIDATE
+  if (off[0] != 0 || off[n] != e) return fail(IPG_EBADGRAPH, "offsets: off[0] != 0 or off[N] != E");
+  for (uint32_t v = 0; v < n; ++v)
+    if (off[v] > off[(size_t)v + 1]) return fail(IPG_EBADGRAPH, "offsets decreasing");
+  for (uint64_t i = 0; i < e; ++i)
+    if (src[i] < 0 || static_cast<uint32_t>(src[i]) >= n) return fail(IPG_EBADGRAPH, "CSC source id outside [0, N)");
+  const uint64_t nblk = blk_blocks(n), nwin = blk_windows(n);
+  // by source: dst_of[k] is the destination of the k-th edge in source order
+  std::vector<uint64_t> sstart((size_t)n + 1, 0);
+  for (uint64_t i = 0; i < e; ++i) ++sstart[(size_t)src[i] + 1];
+  for (uint32_t u = 0; u < n; ++u) sstart[(size_t)u + 1] += sstart[u];
+  std::vector<uint32_t> dst_of(e);
+  {
+    std::vector<uint64_t> cur(sstart.begin(), sstart.end() - 1);
+    for (uint32_t v = 0; v < n; ++v)
+      for (uint64_t i = off[v]; i < off[(size_t)v + 1]; ++i) dst_of[cur[src[i]]++] = v;
+  }
+  std::vector<int32_t>().swap(src);
+  // by block, counting the edges of every (block, window) segment
+  std::vector<uint64_t> bstart(nblk + 1, 0);
+  for (uint32_t v = 0; v < n; ++v) bstart[v / kBlkRows + 1] += off[(size_t)v + 1] - off[v];
+  for (uint64_t k = 0; k < nblk; ++k) bstart[k + 1] += bstart[k];
+  std::vector<uint64_t> seg(nblk * nwin, 0);
+  std::vector<uint32_t> packed(e);
+  {
+    std::vector<uint64_t> cur(bstart.begin(), bstart.end() - 1);
+    for (uint32_t u = 0; u < n; ++u) {
+      const uint64_t w = u >> kBlkWinBits;
+      const uint32_t hi = (u & ((1u << kBlkWinBits) - 1)) << 16;
+      for (uint64_t k = sstart[u]; k < sstart[(size_t)u + 1]; ++k) {
+        const uint32_t v = dst_of[k];
+        const uint64_t blk = v / kBlkRows;
+        packed[cur[blk]++] = hi | (v - static_cast<uint32_t>(blk) * kBlkRows);
+        ++seg[blk * nwin + w];
+      }
+    }
+  }
+  std::vector<uint32_t>().swap(dst_of);
+  // chunks: every segment cut into pieces of at most kBlkChunk edges; the
+  // cost of a chunk is its edges plus kBlkLineCost per outbox cache line its
+  // sources touch (runs of equal source >> 4: 16 FP64 outboxes per 128-byte
+  // line; the sources are sorted)
+  std::vector<BlkChunk> chunks;
+  std::vector<uint64_t> cost;
+  std::vector<uint64_t> cfirst(nblk + 1, 0);
+  for (uint64_t blk = 0; blk < nblk; ++blk) {
+    cfirst[blk] = chunks.size();
+    uint64_t at = bstart[blk];
+    for (uint64_t w = 0; w < nwin; ++w) {
+      for (uint64_t left = seg[blk * nwin + w]; left > 0;) {
+        const uint32_t m = static_cast<uint32_t>(left < kBlkChunk ? left : kBlkChunk);
+        chunks.push_back(BlkChunk{at, static_cast<uint32_t>(w << kBlkWinBits), m});
+        uint64_t lines = 1;
+        for (uint64_t i = at + 1; i < at + m; ++i) lines += (packed[i] >> 20) != (packed[i - 1] >> 20);
+        cost.push_back(m + kBlkLineCost * lines);
+        at += m;
+        left -= m;
+      }
+    }
+  }
+  cfirst[nblk] = chunks.size();
+  if (chunks.size() > blk_chunks_cap(n, e)) return fail(IPG_EBADGRAPH, "blocked chunk table overflow");
+  // slices: with fewer blocks than S (about one slice per CU, and only one
+  // workgroup fits a CU's LDS), at most S slices in one even wave: block b
+  // gets K_b = ceil(C_b / L) slices (at least one, at most one per chunk),
+  // C_b its chunks' cost, for the smallest limit L with sum K_b <= S, which
+  // minimises the largest slice; else one slice per block.  A block's
+  // slices hold about equal costs.
+  std::vector<uint64_t> cb(nblk, 0);
+  uint64_t ctotal = 0;
+  for (uint64_t blk = 0; blk < nblk; ++blk) {
+    for (uint64_t c = cfirst[blk]; c < cfirst[blk + 1]; ++c) cb[blk] += cost[c];
+    ctotal += cb[blk];
+  }
+  const uint64_t S = blk_target_slices(e);
+  std::vector<uint64_t> kb(nblk, 1);
+  if (nblk < S && e) {
+    auto slices_for = [&](uint64_t L, std::vector<uint64_t>* out) {
+      uint64_t total = 0;
+      for (uint64_t blk = 0; blk < nblk; ++blk) {
+        const uint64_t nc = cfirst[blk + 1] - cfirst[blk];
+        const uint64_t k = std::max<uint64_t>(1, std::min((cb[blk] + L - 1) / L, std::max<uint64_t>(nc, 1)));
+        if (out) (*out)[blk] = k;
+        if (nc) total += k;  // a block without edges only writes 0.15/N: not counted
+      }
+      return total;
+    };
+    uint64_t lo = 1, hi = ctotal;  // slices_for(ctotal) <= nblk <= S
+    while (lo < hi) {
+      const uint64_t mid = lo + (hi - lo) / 2;
+      if (slices_for(mid, nullptr) <= S) hi = mid;
+      else lo = mid + 1;
+    }
+    slices_for(lo, &kb);
+  }
+  std::vector<BlkSlice> slices;
+  std::vector<BlkFin> fin;
+  uint32_t nslots = 0;
+  // blocks without edges first: their workgroups end at once and free their
+  // CUs for the slices that do not fit the first wave
+  std::vector<uint64_t> border;
+  for (uint64_t blk = 0; blk < nblk; ++blk)
+    if (bstart[blk + 1] == bstart[blk]) border.push_back(blk);
+  for (uint64_t blk = 0; blk < nblk; ++blk)
+    if (bstart[blk + 1] != bstart[blk]) border.push_back(blk);
+  for (const uint64_t blk : border) {
+    const uint64_t K = kb[blk];
+    if (K == 1) {
+      slices.push_back(BlkSlice{static_cast<uint32_t>(blk), static_cast<uint32_t>(cfirst[blk]),
+                                static_cast<uint32_t>(cfirst[blk + 1]), kNoSlot});
+      continue;
+    }
+    fin.push_back(BlkFin{static_cast<uint32_t>(blk), nslots, static_cast<uint32_t>(K), 0});
+    uint64_t c = cfirst[blk], done = 0;
+    for (uint64_t j = 0; j < K; ++j) {
+      const uint64_t c0 = c, goal = cb[blk] * (j + 1) / K;
+      const uint64_t cmax = cfirst[blk + 1] - (K - 1 - j);  // leave a chunk for every later slice
+      do {
+        done += cost[c];
+        ++c;
+      } while (c < cmax && done < goal);
+      if (j == K - 1) c = cfirst[blk + 1];
+      slices.push_back(BlkSlice{static_cast<uint32_t>(blk), static_cast<uint32_t>(c0), static_cast<uint32_t>(c),
+                                nslots++});
+    }
+  }
+  if (nslots > blk_slots_cap(e) || slices.size() > nblk + blk_slots_cap(e))
+    return fail(IPG_EBADGRAPH, "blocked slice table overflow");
+  if (e) IPG_HIP(hipMemcpyAsync(b->edges, packed.data(), e * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  if (!chunks.empty())
+    IPG_HIP(hipMemcpyAsync(b->chunks, chunks.data(), chunks.size() * sizeof(BlkChunk), hipMemcpyHostToDevice, s));
+  IPG_HIP(hipMemcpyAsync(b->slices, slices.data(), slices.size() * sizeof(BlkSlice), hipMemcpyHostToDevice, s));
+  if (!fin.empty()) IPG_HIP(hipMemcpyAsync(b->fin, fin.data(), fin.size() * sizeof(BlkFin), hipMemcpyHostToDevice, s));
+  IPG_HIP(hipStreamSynchronize(s));
+  b->nchunks = static_cast<uint32_t>(chunks.size());
+  b->nslices = static_cast<uint32_t>(slices.size());
+  b->nfin = static_cast<uint32_t>(fin.size());
+  b->nslots = nslots;
+  return IPG_OK;
+}
+
 }  // namespace ipg
 
 using namespace ipg;
@@ -344,6 +503,11 @@ extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t
   if (rc != IPG_OK) return rc;
   if (d->flags & IPG_GRAPH_RENAME) {
     rc = build_hot_store(csc_off, csc_src, n, e, &t, s);
+    if (rc != IPG_OK) return rc;
+  }
+  if (d->flags & IPG_GRAPH_BLOCKED) {
+    rc = (d->flags & IPG_GRAPH_RENAME) ? build_blocked(t.off_hot, t.src_hot, n, e, &t.blk, s)
+                                       : build_blocked(csc_off, csc_src, n, e, &t.blk, s);
     if (rc != IPG_OK) return rc;
   }
 

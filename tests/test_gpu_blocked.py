@@ -1,0 +1,168 @@
+"""GPU parity of PageRank's blocked pull (graph flag IPG_GRAPH_BLOCKED) against
+the CPU oracle, through the C ABI.
+
+The blocked pull adds the same messages under the sum combiner of Fig. 8, but
+in an order that varies from run to run (LDS atomics), so -- as for push --
+ranks are compared with the oracle within the PageRank tolerance (max
+relative error <= 1e-12), at every update where the case is small.  Cases
+span: one destination block with one slice and with many slices (partial
+sums + the finish launch), many blocks, sources beyond the first window of
+65536, the plain and the hot-first store, blocks and rows without in-edges,
+the usual edge cases, disjoint unions, convergence runs, graph replay and the
+full-size symmetrised R-MAT scale 20 graph.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from tests.graphs_small import random_graph
+
+pytestmark = pytest.mark.gpu
+
+PR_RTOL = 1e-12
+OFF = 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def ipg():
+    import torch
+
+    import paper_2010_08781_amd as m
+
+    assert torch.cuda.is_available()
+    m.lib()
+    return m
+
+
+def max_rel(a, b):
+    return float(np.max(np.abs(a - b) / np.abs(b))) if b.size else 0.0
+
+
+def check(ipg, hg, Ts, rename=True, modes=("pull",)):
+    g = ipg.Graph.from_host(hg, rename=rename, blocked=True)
+    for T in Ts:
+        ref = oracle.run_graph("pagerank", hg, T)
+        for mode in modes:
+            vals, st = g.run("pagerank", T, mode=mode)
+            err = max_rel(ipg.values_to_numpy(vals), ref.values)
+            assert err <= PR_RTOL, f"T={T} {mode} rename={rename}: max rel err {err:.3e}"
+            assert st.supersteps == T + 1 and np.array_equal(st.trace, ref.trace)
+    return g
+
+
+@pytest.mark.parametrize("rename", [True, False])
+def test_one_block_many_slices_every_update(ipg, rename):
+    # N = 16384 < one block of 20224 rows; E = 262K edges -> 4 slices whose
+    # partial sums the finish launch adds.
+    hg = graphgen.workload("rmat-s14-dir")
+    check(ipg, hg, Ts=tuple(range(0, 11)), rename=rename)
+
+
+@pytest.mark.parametrize("sym", [False, True])
+def test_many_blocks_and_windows(ipg, sym):
+    # N = 131072: 7 blocks (the last one partial) and two source windows.
+    hg = graphgen.rmat(17, 16, seed=21, symmetric=sym)
+    check(ipg, hg, Ts=(1, 2, 10), rename=True)
+    check(ipg, hg, Ts=(3,), rename=False)
+
+
+def test_one_slice_blocks_and_empty_blocks(ipg):
+    # Few edges per block (every block one slice, finished by its own
+    # workgroup) and a range of high ids without in-edges: whole blocks with
+    # no edges still produce 0.15/N.
+    n = 90000
+    rng = np.random.default_rng(6)
+    src = rng.integers(0, n, 30000)
+    dst = rng.integers(0, 40000, 30000)
+    hg = graphgen.from_edges(n, src, dst)
+    check(ipg, hg, Ts=(0, 1, 2, 10), rename=False)
+    check(ipg, hg, Ts=(10,), rename=True)
+
+
+def test_hub_rows_and_ragged_chunks(ipg):
+    # A destination with in-degree far above a chunk, a source with a huge
+    # out-degree (one source feeding many chunks), and N not a multiple of 64.
+    n = 5000
+    rng = np.random.default_rng(4)
+    src = np.concatenate([np.arange(1, n), rng.integers(0, n, 20000), np.zeros(3000, np.int64)])
+    dst = np.concatenate([np.zeros(n - 1, np.int64), rng.integers(0, n, 20000), rng.integers(1, n, 3000)])
+    hg = graphgen.from_edges(n, src, dst)
+    check(ipg, hg, Ts=(1, 2, 10), modes=("pull", "push"))
+
+
+@pytest.mark.parametrize("case", ["loops_dups", "single", "no_edges", "cycle", "dense"])
+def test_edge_cases(ipg, case):
+    if case == "loops_dups":
+        hg = random_graph(333, 3000, seed=3, loops=True, dups=True)
+    elif case == "single":
+        hg = graphgen.from_edges(1, [], [])
+    elif case == "no_edges":
+        hg = graphgen.from_edges(70, [], [])
+    elif case == "cycle":
+        n = 1000
+        hg = graphgen.from_edges(n, np.arange(n), (np.arange(n) + 1) % n)
+    else:  # few vertices, many edges: many slices of one small block
+        hg = random_graph(300, 400000, seed=9, loops=True, dups=True)
+    check(ipg, hg, Ts=(0, 1, 5, 10))
+
+
+def test_item_kernels_when_switched_off(ipg):
+    # tuning pr_blocked = UINT32_MAX runs the row-item pull, bitwise equal to
+    # the same store without blocked in-edges
+    import torch
+
+    hg = graphgen.rmat(15, 16, seed=8, symmetric=True)
+    a = ipg.Graph.from_host(hg, blocked=True)
+    b = ipg.Graph.from_host(hg, blocked=False)
+    ra, _ = a.run("pagerank", 10, mode="pull", tuning={"pr_blocked": OFF})
+    rb, _ = b.run("pagerank", 10, mode="pull")
+    assert torch.equal(ra, rb)
+    rc, _ = a.run("pagerank", 10, mode="pull")
+    assert max_rel(ipg.values_to_numpy(rc), ipg.values_to_numpy(rb)) <= PR_RTOL
+
+
+def test_parts_converge_and_replay(ipg):
+    import torch
+
+    graphs = [graphgen.rmat_small(n, 8, seed=700 + n) for n in (1500, 30000, 900, 22000)]
+    u = graphgen.disjoint_union(graphs)
+    g = ipg.Graph.from_host(u, blocked=True)
+    parts = torch.from_numpy(u.meta["parts"].astype(np.int32)).cuda()
+    # each part's ranks equal a separate run on that part
+    r, _ = g.run("pagerank", 10, parts=parts)
+    r = ipg.values_to_numpy(r)
+    off = u.meta["parts"]
+    for i, hg in enumerate(graphs):
+        ref = oracle.run_graph("pagerank", hg, 10)
+        assert max_rel(r[off[i]:off[i + 1]], ref.values) <= PR_RTOL, i
+    # to convergence: the stopping update is the oracle's (tolerance placed
+    # away from every change of the run)
+    hg = graphs[1]
+    gb = ipg.Graph.from_host(hg, blocked=True)
+    d = oracle.pagerank_deltas(hg.n, hg.csr_off, hg.csr_dst, 200)
+    tol = 1e-9
+    while np.any(np.abs(d[1:] - tol) <= max(1e-6 * tol, 1e-12)):
+        tol *= 1.37
+    ref, T, _ = oracle.pagerank_converge(hg, tol, 200)
+    c, st = gb.run("pagerank", 200, mode="pull", tol=tol)
+    assert st.supersteps == T + 1 and max_rel(ipg.values_to_numpy(c), ref.values) <= PR_RTOL
+    np.testing.assert_allclose(st.residual[1:], d[1:T + 1], rtol=1e-9, atol=1e-13)
+    # graph replay, several times with eager work in between
+    ref = oracle.run_graph("pagerank", hg, 10)
+    for _ in range(3):
+        rr, _ = gb.run("pagerank", 10, mode="pull", graph=True)
+        assert max_rel(ipg.values_to_numpy(rr), ref.values) <= PR_RTOL
+        e, _ = gb.run("pagerank", 4, mode="pull")
+        assert max_rel(ipg.values_to_numpy(e), oracle.run_graph("pagerank", hg, 4).values) <= PR_RTOL
+
+
+def test_full_size_rmat_s20_symmetrised(ipg):
+    # the benchmark's graph and launch path (hot-first store + blocked in-edges)
+    hg = graphgen.workload("rmat-s20-sym")
+    g = ipg.Graph.from_host(hg, blocked=True)
+    ref = oracle.run_graph("pagerank", hg, 10)
+    vals, st = g.run("pagerank", 10, mode="pull")
+    assert max_rel(ipg.values_to_numpy(vals), ref.values) <= PR_RTOL
+    vals, st = g.run("pagerank", 10, mode="pull", graph=True)
+    assert max_rel(ipg.values_to_numpy(vals), ref.values) <= PR_RTOL
