@@ -242,6 +242,34 @@ __global__ __launch_bounds__(WAVES * kWave) void pr_items_kernel(PrPullArgs a, u
   if (a.l1) flush_l1(a.l1, l1);
 }
 
+// What finishing a row reads besides its sum: loaded for a batch of rows
+// before any is finished, so that the loads are in flight together.
+struct RowIn {
+  uint32_t deg;   // out-degree
+  uint32_t pn;    // vertex count of the row's part (part_n), else 0
+  double old;     // previous rank (convergence run), else 0
+};
+__device__ __forceinline__ RowIn pr_row_load(const PrPullArgs& a, uint32_t v) {
+  RowIn in;
+  in.deg = a.outdeg[v];
+  in.pn = a.part_n ? a.part_n[v] : 0u;
+  in.old = a.l1 ? a.value[v] : 0.0;
+  return in;
+}
+// pr_finish with the row's inputs already loaded.
+__device__ __forceinline__ void pr_row_finish(const PrPullArgs& a, uint32_t v, double sum, const RowIn& in, double& l1) {
+  const double ratio = a.part_n ? 0.15 / static_cast<double>(in.pn) : a.ratio;
+  const double rank = ratio + 0.85 * sum;
+  if (a.l1) {
+    l1 += fabs(rank - in.old);
+    a.value[v] = rank;
+  } else if (a.last) {
+    a.value[v] = rank;
+    return;
+  }
+  a.contrib_out[v] = in.deg ? rank / static_cast<double>(in.deg) : 0.0;
+}
+
 // Pull superstep, second launch: each long row adds its chunk partials in
 // chunk order (one wavefront per row; a fixed order, so results are
 // bitwise reproducible).
@@ -258,16 +286,17 @@ __global__ __launch_bounds__(kBlock) void pr_longrow_kernel(PrPullArgs a) {
   if (a.l1) flush_l1(a.l1, l1);
 }
 
-// Blocked pull (IPG_GRAPH_BLOCKED): the in-edges of each block of kBlkRows
-// destinations, sorted by source, streamed through one workgroup per slice.
+// Blocked pull (IPG_GRAPH_BLOCKED): the in-edges of each block of at most
+// kBlkRows destinations, sorted by source, streamed through one workgroup
+// per slice.
 struct PrBlkArgs {
   const uint32_t* edges;
   const BlkChunk* chunks;
   const BlkSlice* slices;
-  const BlkFin* fin;
+  const BlkGroup* groups;
   double* partial;
   uint32_t n;
-  uint32_t nfin;
+  uint32_t ngroups;
 };
 constexpr uint32_t kBlkThreads = 1024;
 constexpr int kBlkGroup = 4;  // chunks a wavefront takes per step
@@ -311,7 +340,8 @@ __global__ __launch_bounds__(kBlkThreads) void pr_blocked_kernel(PrPullArgs a, P
   // late, inside it)
   __shared__ double part[kBlkRows + kWave];
   const BlkSlice sl = b.slices[blockIdx.x];
-  for (uint32_t r = threadIdx.x; r < kBlkRows; r += kBlkThreads) part[r] = 0.0;
+  for (uint32_t r = threadIdx.x; r < sl.rows; r += kBlkThreads) part[r] = 0.0;
+  if (threadIdx.x < kWave) part[kBlkRows + threadIdx.x] = 0.0;
   __syncthreads();
   const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = lane_id();
   // A wavefront takes kBlkGroup chunks per step: chunks c + g * kWaves of
@@ -367,60 +397,58 @@ __global__ __launch_bounds__(kBlkThreads) void pr_blocked_kernel(PrPullArgs a, P
     }
   }
   __syncthreads();
-  const uint32_t r0 = sl.block * kBlkRows;
-  const uint32_t rows = b.n - r0 < kBlkRows ? b.n - r0 : kBlkRows;
+  const uint32_t r0 = sl.row0, rows = sl.rows;
   double l1 = 0.0;
-  if (sl.slot == kNoSlot) {
-    for (uint32_t r = threadIdx.x; r < rows; r += kBlkThreads) pr_finish(a, r0 + r, part[r], l1);
+  if (sl.poff == kNoPartial) {
+    // rows in batches of kFinBatch per thread, every batch's inputs loaded
+    // first (indices clamped into the block: the loads are unconditional)
+    constexpr uint32_t kFinBatch = 5;
+    for (uint32_t r = threadIdx.x; r < rows; r += kFinBatch * kBlkThreads) {
+      RowIn in[kFinBatch];
+#pragma unroll
+      for (uint32_t j = 0; j < kFinBatch; ++j) {
+        const uint32_t rj = r + j * kBlkThreads;
+        in[j] = pr_row_load(a, r0 + (rj < rows ? rj : rows - 1));
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < kFinBatch; ++j) {
+        const uint32_t rj = r + j * kBlkThreads;
+        if (rj < rows) pr_row_finish(a, r0 + rj, part[rj], in[j], l1);
+      }
+    }
   } else {
-    double* dst = b.partial + static_cast<size_t>(sl.slot) * kBlkRows;
+    double* dst = b.partial + sl.poff;
     for (uint32_t r = threadIdx.x; r < rows; r += kBlkThreads) dst[r] = part[r];
   }
   if (a.l1) flush_l1(a.l1, l1);
 }
 
-// Blocked pull, second launch: the vertices of every block with several
-// slices add the slices' partial sums.  A workgroup takes 64 rows of one
-// block; its kFinWaves wavefronts each add a contiguous run of the slices
-// (in slice order, eight loads in flight per lane), and the runs' sums are
-// added in wavefront order: a fixed order.
-constexpr uint32_t kFinRows = 64;
-constexpr uint32_t kFinWaves = 8;
-__global__ __launch_bounds__(kFinWaves * kWave) void pr_blocked_finish_kernel(PrPullArgs a, PrBlkArgs b) {
-  constexpr uint32_t kGroups = (kBlkRows + kFinRows - 1) / kFinRows;
-  __shared__ double red[kFinWaves][kFinRows];
-  const uint64_t total = static_cast<uint64_t>(b.nfin) * kGroups;
-  const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
+// Blocked pull, second launch: the rows of every block with several slices
+// add the slices' partial sums in slice order.  A wavefront takes one group
+// of 64 rows at a time (lane = row): one record load, then every partial
+// (eight at a time) and the row's inputs in flight together.
+__global__ __launch_bounds__(kBlock) void pr_blocked_finish_kernel(PrPullArgs a, PrBlkArgs b) {
+  const uint32_t lane = lane_id();
+  const uint32_t nw = gridDim.x * kWavesPerBlock;
   double l1 = 0.0;
-  for (uint64_t w = blockIdx.x; w < total; w += gridDim.x) {  // uniform over the workgroup
-    const BlkFin f = b.fin[w / kGroups];
-    const uint32_t r0 = f.block * kBlkRows;
-    const uint32_t rows = b.n - r0 < kBlkRows ? b.n - r0 : kBlkRows;
-    const uint32_t g0 = static_cast<uint32_t>(w % kGroups) * kFinRows;
-    if (g0 >= rows) continue;
-    const uint32_t r = g0 + lane, rr = r < rows ? r : rows - 1;
-    const uint32_t k0 = f.k * wv / kFinWaves, k1 = f.k * (wv + 1) / kFinWaves;
+  for (uint32_t w = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; w < b.ngroups; w += nw) {  // wave-uniform
+    const BlkGroup gr = b.groups[w];
+    const uint32_t rr = lane < gr.nrows ? lane : gr.nrows - 1;
+    const RowIn in = pr_row_load(a, gr.row0 + rr);
+    const double* p = b.partial + gr.poff + rr;
     double sum = 0.0;
-    for (uint32_t k = k0; k < k1; k += 8) {
+    for (uint32_t k = 0; k < gr.k; k += 8) {
       double x[8];
 #pragma unroll
       for (uint32_t j = 0; j < 8; ++j) {
-        const uint32_t kk = k + j < k1 ? k + j : k1 - 1;
-        x[j] = b.partial[static_cast<size_t>(f.slot0 + kk) * kBlkRows + rr];
+        const uint32_t kk = k + j < gr.k ? k + j : gr.k - 1;
+        x[j] = p[static_cast<uint64_t>(kk) * gr.stride];
       }
 #pragma unroll
       for (uint32_t j = 0; j < 8; ++j)
-        if (k + j < k1) sum += x[j];
+        if (k + j < gr.k) sum += x[j];
     }
-    red[wv][lane] = sum;
-    __syncthreads();
-    if (wv == 0 && r < rows) {
-      double t = 0.0;
-#pragma unroll
-      for (uint32_t j = 0; j < kFinWaves; ++j) t += red[j][lane];
-      pr_finish(a, r0 + r, t, l1);
-    }
-    __syncthreads();
+    if (lane < gr.nrows) pr_row_finish(a, gr.row0 + lane, sum, in, l1);
   }
   if (a.l1) flush_l1(a.l1, l1);
 }
@@ -594,16 +622,15 @@ static hipError_t launch_pr_pull(const PrPullArgs& a, const PrPullStore& ps, con
     b.edges = ps.blk->edges;
     b.chunks = ps.blk->chunks;
     b.slices = ps.blk->slices;
-    b.fin = ps.blk->fin;
+    b.groups = ps.blk->groups;
     b.partial = ps.blk->partial;
     b.n = n;
-    b.nfin = ps.blk->nfin;
+    b.ngroups = ps.blk->ngroups;
     hipLaunchKernelGGL(pr_blocked_kernel, dim3(ps.blk->nslices), dim3(kBlkThreads), 0, s, a, b);
     hipError_t err = hipGetLastError();
-    if (err != hipSuccess || !b.nfin) return err;
-    constexpr uint32_t kGroups = (kBlkRows + kFinRows - 1) / kFinRows;
-    const uint32_t grid = grid_for(static_cast<uint64_t>(b.nfin) * kGroups, 1, 8192);
-    hipLaunchKernelGGL(pr_blocked_finish_kernel, dim3(grid), dim3(kFinWaves * kWave), 0, s, a, b);
+    if (err != hipSuccess || !b.ngroups) return err;
+    const uint32_t grid = grid_for(b.ngroups, kWavesPerBlock, 4096);
+    hipLaunchKernelGGL(pr_blocked_finish_kernel, dim3(grid), dim3(kBlock), 0, s, a, b);
     return hipGetLastError();
   }
   hipError_t err = launch_pr_items(a, ps.perm != nullptr, tn, n, s);

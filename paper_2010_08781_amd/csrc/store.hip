@@ -164,9 +164,9 @@ static size_t carve_graph(Carver& c, uint32_t n, uint64_t e, uint32_t flags, Gra
   if (flags & IPG_GRAPH_BLOCKED) {
     tt.blk.edges = c.take<uint32_t>(e ? e : 1);
     tt.blk.chunks = c.take<BlkChunk>(blk_chunks_cap(n, e));
-    tt.blk.slices = c.take<BlkSlice>(blk_blocks(n) + blk_slots_cap(e));
-    tt.blk.fin = c.take<BlkFin>(blk_blocks(n));
-    tt.blk.partial = c.take<double>(blk_slots_cap(e) * kBlkRows);
+    tt.blk.slices = c.take<BlkSlice>(blk_blocks_cap(n, e) + blk_target_slices(e));
+    tt.blk.groups = c.take<BlkGroup>(blk_groups_cap(n, e));
+    tt.blk.partial = c.take<double>(blk_partial_cap(e));
   }
   if (t) *t = tt;
   return align_up(c.used, 256);
@@ -300,7 +300,27 @@ static ipg_status build_blocked(const uint64_t* csc_off, const int32_t* csc_src,
     if (off[v] > off[(size_t)v + 1]) return fail(IPG_EBADGRAPH, "offsets decreasing");
   for (uint64_t i = 0; i < e; ++i)
     if (src[i] < 0 || static_cast<uint32_t>(src[i]) >= n) return fail(IPG_EBADGRAPH, "CSC source id outside [0, N)");
-  const uint64_t nblk = blk_blocks(n), nwin = blk_windows(n);
+  // blocks: runs of consecutive rows, closed before the row that would take
+  // them past the edge target (a row above it alone forms a block) or at
+  // kBlkRows rows
+  const uint64_t target = blk_edge_target(e);
+  std::vector<uint32_t> row0{0};
+  std::vector<uint32_t> blk_of(n);
+  {
+    uint64_t acc = 0;
+    for (uint32_t v = 0; v < n; ++v) {
+      const uint64_t d = off[(size_t)v + 1] - off[v];
+      if (v > row0.back() && (acc + d > target || v - row0.back() == kBlkRows)) {
+        row0.push_back(v);
+        acc = 0;
+      }
+      acc += d;
+      blk_of[v] = static_cast<uint32_t>(row0.size() - 1);
+    }
+    row0.push_back(n);
+  }
+  const uint64_t nblk = row0.size() - 1, nwin = blk_windows(n);
+  if (nblk > blk_blocks_cap(n, e)) return fail(IPG_EBADGRAPH, "blocked block table overflow");
   // by source: dst_of[k] is the destination of the k-th edge in source order
   std::vector<uint64_t> sstart((size_t)n + 1, 0);
   for (uint64_t i = 0; i < e; ++i) ++sstart[(size_t)src[i] + 1];
@@ -314,7 +334,7 @@ static ipg_status build_blocked(const uint64_t* csc_off, const int32_t* csc_src,
   std::vector<int32_t>().swap(src);
   // by block, counting the edges of every (block, window) segment
   std::vector<uint64_t> bstart(nblk + 1, 0);
-  for (uint32_t v = 0; v < n; ++v) bstart[v / kBlkRows + 1] += off[(size_t)v + 1] - off[v];
+  for (uint32_t v = 0; v < n; ++v) bstart[(size_t)blk_of[v] + 1] += off[(size_t)v + 1] - off[v];
   for (uint64_t k = 0; k < nblk; ++k) bstart[k + 1] += bstart[k];
   std::vector<uint64_t> seg(nblk * nwin, 0);
   std::vector<uint32_t> packed(e);
@@ -325,8 +345,8 @@ static ipg_status build_blocked(const uint64_t* csc_off, const int32_t* csc_src,
       const uint32_t hi = (u & ((1u << kBlkWinBits) - 1)) << 16;
       for (uint64_t k = sstart[u]; k < sstart[(size_t)u + 1]; ++k) {
         const uint32_t v = dst_of[k];
-        const uint64_t blk = v / kBlkRows;
-        packed[cur[blk]++] = hi | (v - static_cast<uint32_t>(blk) * kBlkRows);
+        const uint64_t blk = blk_of[v];
+        packed[cur[blk]++] = hi | (v - row0[blk]);
         ++seg[blk * nwin + w];
       }
     }
@@ -370,7 +390,9 @@ static ipg_status build_blocked(const uint64_t* csc_off, const int32_t* csc_src,
   }
   const uint64_t S = blk_target_slices(e);
   std::vector<uint64_t> kb(nblk, 1);
-  if (nblk < S && e) {
+  uint64_t nonempty = 0;
+  for (uint64_t blk = 0; blk < nblk; ++blk) nonempty += cfirst[blk + 1] != cfirst[blk];
+  if (nonempty < S && e) {
     auto slices_for = [&](uint64_t L, std::vector<uint64_t>* out) {
       uint64_t total = 0;
       for (uint64_t blk = 0; blk < nblk; ++blk) {
@@ -381,7 +403,7 @@ static ipg_status build_blocked(const uint64_t* csc_off, const int32_t* csc_src,
       }
       return total;
     };
-    uint64_t lo = 1, hi = ctotal;  // slices_for(ctotal) <= nblk <= S
+    uint64_t lo = 1, hi = ctotal;  // slices_for(ctotal) == nonempty <= S
     while (lo < hi) {
       const uint64_t mid = lo + (hi - lo) / 2;
       if (slices_for(mid, nullptr) <= S) hi = mid;
@@ -390,8 +412,8 @@ static ipg_status build_blocked(const uint64_t* csc_off, const int32_t* csc_src,
     slices_for(lo, &kb);
   }
   std::vector<BlkSlice> slices;
-  std::vector<BlkFin> fin;
-  uint32_t nslots = 0;
+  std::vector<BlkGroup> groups;
+  uint64_t poff = 0;
   // blocks without edges first: their workgroups end at once and free their
   // CUs for the slices that do not fit the first wave
   std::vector<uint64_t> border;
@@ -401,12 +423,14 @@ static ipg_status build_blocked(const uint64_t* csc_off, const int32_t* csc_src,
     if (bstart[blk + 1] != bstart[blk]) border.push_back(blk);
   for (const uint64_t blk : border) {
     const uint64_t K = kb[blk];
+    const uint32_t r0 = row0[blk], rows = row0[blk + 1] - row0[blk];
     if (K == 1) {
-      slices.push_back(BlkSlice{static_cast<uint32_t>(blk), static_cast<uint32_t>(cfirst[blk]),
-                                static_cast<uint32_t>(cfirst[blk + 1]), kNoSlot});
+      slices.push_back(BlkSlice{r0, rows, static_cast<uint32_t>(cfirst[blk]), static_cast<uint32_t>(cfirst[blk + 1]),
+                                kNoPartial});
       continue;
     }
-    fin.push_back(BlkFin{static_cast<uint32_t>(blk), nslots, static_cast<uint32_t>(K), 0});
+    for (uint32_t g = 0; g < rows; g += 64)
+      groups.push_back(BlkGroup{r0 + g, std::min<uint32_t>(64, rows - g), static_cast<uint32_t>(K), rows, poff + g});
     uint64_t c = cfirst[blk], done = 0;
     for (uint64_t j = 0; j < K; ++j) {
       const uint64_t c0 = c, goal = cb[blk] * (j + 1) / K;
@@ -416,22 +440,23 @@ static ipg_status build_blocked(const uint64_t* csc_off, const int32_t* csc_src,
         ++c;
       } while (c < cmax && done < goal);
       if (j == K - 1) c = cfirst[blk + 1];
-      slices.push_back(BlkSlice{static_cast<uint32_t>(blk), static_cast<uint32_t>(c0), static_cast<uint32_t>(c),
-                                nslots++});
+      slices.push_back(BlkSlice{r0, rows, static_cast<uint32_t>(c0), static_cast<uint32_t>(c), poff});
+      poff += rows;
     }
   }
-  if (nslots > blk_slots_cap(e) || slices.size() > nblk + blk_slots_cap(e))
+  if (poff > blk_partial_cap(e) || slices.size() > blk_blocks_cap(n, e) + blk_target_slices(e) ||
+      groups.size() > blk_groups_cap(n, e))
     return fail(IPG_EBADGRAPH, "blocked slice table overflow");
   if (e) IPG_HIP(hipMemcpyAsync(b->edges, packed.data(), e * sizeof(uint32_t), hipMemcpyHostToDevice, s));
   if (!chunks.empty())
     IPG_HIP(hipMemcpyAsync(b->chunks, chunks.data(), chunks.size() * sizeof(BlkChunk), hipMemcpyHostToDevice, s));
   IPG_HIP(hipMemcpyAsync(b->slices, slices.data(), slices.size() * sizeof(BlkSlice), hipMemcpyHostToDevice, s));
-  if (!fin.empty()) IPG_HIP(hipMemcpyAsync(b->fin, fin.data(), fin.size() * sizeof(BlkFin), hipMemcpyHostToDevice, s));
+  if (!groups.empty())
+    IPG_HIP(hipMemcpyAsync(b->groups, groups.data(), groups.size() * sizeof(BlkGroup), hipMemcpyHostToDevice, s));
   IPG_HIP(hipStreamSynchronize(s));
   b->nchunks = static_cast<uint32_t>(chunks.size());
   b->nslices = static_cast<uint32_t>(slices.size());
-  b->nfin = static_cast<uint32_t>(fin.size());
-  b->nslots = nslots;
+  b->ngroups = static_cast<uint32_t>(groups.size());
   return IPG_OK;
 }
 
