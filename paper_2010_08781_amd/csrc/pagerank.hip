@@ -424,7 +424,8 @@ __global__ __launch_bounds__(kBlkThreads) void pr_blocked_kernel(PrPullArgs a, P
 }
 
 // Blocked pull, second launch: the rows of every block with several slices
-// add the slices' partial sums in slice order.  A wavefront takes one group
+// add the slices' partial sums in slice order (and the rows of blocks
+// without in-edges, with no partials, get 0.15/N).  A wavefront takes one group
 // of 64 rows at a time (lane = row): one record load, then every partial
 // (eight at a time) and the row's inputs in flight together.
 __global__ __launch_bounds__(kBlock) void pr_blocked_finish_kernel(PrPullArgs a, PrBlkArgs b) {
@@ -626,8 +627,11 @@ static hipError_t launch_pr_pull(const PrPullArgs& a, const PrPullStore& ps, con
     b.partial = ps.blk->partial;
     b.n = n;
     b.ngroups = ps.blk->ngroups;
-    hipLaunchKernelGGL(pr_blocked_kernel, dim3(ps.blk->nslices), dim3(kBlkThreads), 0, s, a, b);
-    hipError_t err = hipGetLastError();
+    hipError_t err = hipSuccess;
+    if (ps.blk->nslices) {  // none when the graph has no edges
+      hipLaunchKernelGGL(pr_blocked_kernel, dim3(ps.blk->nslices), dim3(kBlkThreads), 0, s, a, b);
+      err = hipGetLastError();
+    }
     if (err != hipSuccess || !b.ngroups) return err;
     const uint32_t grid = grid_for(b.ngroups, kWavesPerBlock, 4096);
     hipLaunchKernelGGL(pr_blocked_finish_kernel, dim3(grid), dim3(kBlock), 0, s, a, b);

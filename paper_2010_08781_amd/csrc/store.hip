@@ -414,16 +414,13 @@ static ipg_status build_blocked(const uint64_t* csc_off, const int32_t* csc_src,
   std::vector<BlkSlice> slices;
   std::vector<BlkGroup> groups;
   uint64_t poff = 0;
-  // blocks without edges first: their workgroups end at once and free their
-  // CUs for the slices that do not fit the first wave
-  std::vector<uint64_t> border;
-  for (uint64_t blk = 0; blk < nblk; ++blk)
-    if (bstart[blk + 1] == bstart[blk]) border.push_back(blk);
-  for (uint64_t blk = 0; blk < nblk; ++blk)
-    if (bstart[blk + 1] != bstart[blk]) border.push_back(blk);
-  for (const uint64_t blk : border) {
+  for (uint64_t blk = 0; blk < nblk; ++blk) {
     const uint64_t K = kb[blk];
     const uint32_t r0 = row0[blk], rows = row0[blk + 1] - row0[blk];
+    if (cfirst[blk + 1] == cfirst[blk]) {  // no in-edges: the finish launch writes its rows (0.15/N)
+      for (uint32_t g = 0; g < rows; g += 64) groups.push_back(BlkGroup{r0 + g, std::min<uint32_t>(64, rows - g), 0, rows, 0});
+      continue;
+    }
     if (K == 1) {
       slices.push_back(BlkSlice{r0, rows, static_cast<uint32_t>(cfirst[blk]), static_cast<uint32_t>(cfirst[blk + 1]),
                                 kNoPartial});
@@ -447,10 +444,34 @@ static ipg_status build_blocked(const uint64_t* csc_off, const int32_t* csc_src,
   if (poff > blk_partial_cap(e) || slices.size() > blk_blocks_cap(n, e) + blk_target_slices(e) ||
       groups.size() > blk_groups_cap(n, e))
     return fail(IPG_EBADGRAPH, "blocked slice table overflow");
+  // XCD-aware launch order: workgroup i of a launch runs on XCD i mod 8, and
+  // a slice's sources are a contiguous range (its chunks are sorted by
+  // source).  The slices are sorted by their first source and XCD x takes
+  // the x-th eighth of them, so that each XCD's L2 caches about an eighth
+  // of the outbox array instead of all of it.
+  {
+    constexpr size_t kXcds = 8;
+    const size_t ns = slices.size(), q = (ns + kXcds - 1) / kXcds;
+    auto first_src = [&](const BlkSlice& sl) -> uint64_t {
+      const BlkChunk& ch = chunks[sl.c0];
+      return static_cast<uint64_t>(ch.wbase) + (packed[ch.e0] >> 16);
+    };
+    std::vector<size_t> idx(ns);
+    for (size_t i = 0; i < ns; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](size_t x, size_t y) { return first_src(slices[x]) < first_src(slices[y]); });
+    std::vector<BlkSlice> dealt;
+    dealt.reserve(ns);
+    for (size_t j = 0; j < q; ++j)
+      for (size_t x = 0; x < kXcds; ++x)
+        if (x * q + j < ns) dealt.push_back(slices[idx[x * q + j]]);
+    slices.swap(dealt);
+  }
   if (e) IPG_HIP(hipMemcpyAsync(b->edges, packed.data(), e * sizeof(uint32_t), hipMemcpyHostToDevice, s));
   if (!chunks.empty())
     IPG_HIP(hipMemcpyAsync(b->chunks, chunks.data(), chunks.size() * sizeof(BlkChunk), hipMemcpyHostToDevice, s));
-  IPG_HIP(hipMemcpyAsync(b->slices, slices.data(), slices.size() * sizeof(BlkSlice), hipMemcpyHostToDevice, s));
+  if (!slices.empty())
+    IPG_HIP(hipMemcpyAsync(b->slices, slices.data(), slices.size() * sizeof(BlkSlice), hipMemcpyHostToDevice, s));
   if (!groups.empty())
     IPG_HIP(hipMemcpyAsync(b->groups, groups.data(), groups.size() * sizeof(BlkGroup), hipMemcpyHostToDevice, s));
   IPG_HIP(hipStreamSynchronize(s));
