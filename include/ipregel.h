@@ -66,19 +66,20 @@ typedef enum { IPG_MODE_AUTO = 0, IPG_MODE_PUSH = 1, IPG_MODE_PULL = 2 } ipg_mod
                                   that order: the most-read outbox entries share cache lines.  Results are
                                   unchanged (same values summed in the same order); costs 4E + 4N bytes of
                                   graph workspace. */
-#define IPG_GRAPH_BLOCKED 8u   /* keep a destination-blocked copy of the in-edges for PageRank's pull
-                                  exchange (of the hot-first CSC with IPG_GRAPH_RENAME): destinations cut into
-                                  blocks of 20224 rows whose FP64 sums fit one workgroup's LDS, each block's
-                                  in-edges sorted by source, 4 bytes per edge, so that a wavefront's outbox
-                                  reads share cache lines.  Every superstep streams the blocks and adds each
-                                  message into its destination's sum in LDS; blocks spread over several
-                                  workgroups add their partial sums in a fixed order.  The sums are the same
-                                  messages under the sum combiner (Fig. 8) in a varying order, as with push:
-                                  results agree with the oracle to rounding but are not bitwise reproducible.
-                                  Built on the host (two counting sorts, O(N + E) time and ~12E bytes of host
-                                  memory); costs about 4E bytes plus a partial-sum buffer of at most
-                                  (4/3 * 256 + 1) * 20224 doubles of graph workspace, which runs on the handle
-                                  share (runs on one handle must not overlap in time). */
+#define IPG_GRAPH_BLOCKED 8u   /* keep destination-blocked in-edges for PageRank's pull exchange (of the
+                                  hot-first CSC with IPG_GRAPH_RENAME): the destinations are cut into runs of
+                                  at most 20224 consecutive rows whose FP64 sums fit one workgroup's LDS
+                                  (closed early at 8/256 of the edges, so rows with many in-edges form narrow
+                                  blocks), and each block's in-edges are stored sorted by source, 4 bytes per
+                                  edge, so that a wavefront's outbox reads share cache lines.  Every superstep
+                                  streams the blocks and adds each message into its destination's sum in LDS;
+                                  blocks spread over several workgroups add their partial sums in a fixed
+                                  order.  The sums are the same messages under the sum combiner (Fig. 8) in a
+                                  varying order, as with push: results agree with the oracle to rounding but
+                                  are not bitwise reproducible.  Built on the host (two counting sorts, O(N + E)
+                                  time and about 16E + 24N bytes of host memory); costs about 4E bytes plus a
+                                  partial-sum buffer of at most 256 * 20224 doubles of graph workspace, which
+                                  runs on the handle share (runs on one handle must not overlap in time). */
 
 /*
  * A graph as CSR (out-adjacency, for push) plus CSC (in-adjacency, for pull).
