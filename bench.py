@@ -290,7 +290,7 @@ def main():
         nbytes = pr_pull_bytes(hg.n, hg.m)
         ach = nbytes / (avg_us * 1e-6) / 1e9
         traffic = measured_traffic(args.workload, tun.get("pagerank"))
-        blocked = g.blocked and (tun.get("pagerank") or {}).get("pr_blocked", 0) != 0xFFFFFFFF
+        blocked = g.blocked and (tun.get("pagerank") or {}).get("blocked", 0) != 0xFFFFFFFF
         kernel = ("pr_blocked_kernel + pr_blocked_finish_kernel" if blocked else
                   "pr_items_kernel + pr_longrow_kernel") + " (one PageRank pull superstep)"
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -133,8 +133,9 @@ typedef struct {
   uint32_t gate_div;   /* CC/SSSP pull: when fewer than N / gate_div vertices broadcast, the gather reads
                           a bitmap of the senders first and skips the others' outboxes (default 8;
                           UINT32_MAX = never) */
-  uint32_t pr_blocked; /* PageRank pull on a store built with IPG_GRAPH_BLOCKED: 0 (default) = use the
-                          blocked in-edges, UINT32_MAX = use the row-item kernels instead */
+  uint32_t blocked;    /* pull exchanges on a store built with IPG_GRAPH_BLOCKED (PageRank, CC and SSSP
+                          with unit weights): 0 (default) = use the blocked in-edges, UINT32_MAX = use
+                          the row-item kernels instead */
 } ipg_tuning;
 
 typedef struct {

@@ -56,10 +56,10 @@ class _Desc(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("pr_hot", ctypes.c_uint32), ("pull_grid", ctypes.c_uint32), ("push_div", ctypes.c_uint32),
-                ("list_div", ctypes.c_uint32), ("gate_div", ctypes.c_uint32), ("pr_blocked", ctypes.c_uint32)]
+                ("list_div", ctypes.c_uint32), ("gate_div", ctypes.c_uint32), ("blocked", ctypes.c_uint32)]
 
 
-TUNING_FIELDS = ("pr_hot", "pull_grid", "push_div", "list_div", "gate_div", "pr_blocked")
+TUNING_FIELDS = ("pr_hot", "pull_grid", "push_div", "list_div", "gate_div", "blocked")
 HOT_OFF = 0xFFFFFFFF
 
 

@@ -66,14 +66,20 @@ def _save(path, cache):
 
 def candidates(graph, app: str) -> list:
     """The parameter sets tried for `app` on this graph: the product of the
-    application's space; for PageRank on a graph with blocked in-edges, the
-    blocked pull (which has no launch parameters) and then the row-item
-    pull over the space."""
+    application's space; on a graph with blocked in-edges also the blocked
+    pull (PageRank: no launch parameters; CC/SSSP: the exchange rule's
+    divisors) before the row-item pull over the space."""
     space = SPACES[app]
     names = sorted(space)
     out = [dict(zip(names, combo)) for combo in itertools.product(*(space[k] for k in names))]
-    if app == "pagerank" and getattr(graph, "blocked", False):
-        out = [{"pr_blocked": 0}] + [dict(t, pr_blocked=0xFFFFFFFF) for t in out]
+    if getattr(graph, "blocked", False):
+        if app == "pagerank":
+            out = [{"blocked": 0}] + [dict(t, blocked=0xFFFFFFFF) for t in out]
+        elif app in ("cc", "sssp"):
+            # the blocked pull has no grid or gate; the rule's divisors still matter
+            blk = [dict(zip(("list_div", "push_div"), c), blocked=0)
+                   for c in itertools.product(space["list_div"], space["push_div"])]
+            out = blk + [dict(t, blocked=0xFFFFFFFF) for t in out]
     return out
 
 

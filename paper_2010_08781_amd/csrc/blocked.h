@@ -1,0 +1,121 @@
+// blocked.h -- streaming the destination-blocked, source-sorted in-edges
+// (IPG_GRAPH_BLOCKED; layout in common.h) through one workgroup per slice.
+// Shared by the PageRank pull (FP64 sums) and the CC/SSSP pull (u32 minima).
+#pragma once
+
+#include "common.h"
+
+namespace ipg {
+
+constexpr uint32_t kBlkThreads = 1024;  // one workgroup per slice, one per CU (its LDS holds the block's values)
+constexpr int kBlkGroup = 4;            // chunks a wavefront takes per step
+
+// Device view of one set of blocked tables.
+struct BlkView {
+  const uint32_t* edges;
+  const BlkChunk* chunks;
+  const BlkSlice* slices;
+  const BlkGroup* groups;
+  void* partial;
+  uint32_t ngroups;
+};
+inline BlkView blk_view(const BlockedTables& t) {
+  BlkView v;
+  v.edges = t.edges;
+  v.chunks = t.chunks;
+  v.slices = t.slices;
+  v.groups = t.groups;
+  v.partial = t.partial;
+  v.ngroups = t.ngroups;
+  return v;
+}
+
+// A chunk past the slice's end: no edges (its loads read the slice table).
+__device__ __forceinline__ BlkChunk blk_chunk_at(const BlkView& b, uint64_t c, uint32_t c1) {
+  if (c < c1) return b.chunks[c];
+  BlkChunk z;
+  z.e0 = 0;
+  z.wbase = 0;
+  z.n = 0;
+  return z;
+}
+
+// The packed edges of a chunk, one per lane and register, the index clamped
+// into the chunk so that every load is unconditional.
+__device__ __forceinline__ void blk_load(const BlkView& b, const BlkChunk& ch, uint32_t (&p)[kBlkChunk / kWave]) {
+  const uint32_t lane = lane_id();
+  const uint32_t* base = ch.n ? b.edges + ch.e0 : reinterpret_cast<const uint32_t*>(b.slices);
+  const uint32_t last = ch.n ? ch.n - 1 : 0;
+#pragma unroll
+  for (int k = 0; k < static_cast<int>(kBlkChunk / kWave); ++k) {
+    const uint32_t i = lane + k * kWave;
+    p[k] = __builtin_nontemporal_load(base + (i < last ? i : last));
+  }
+}
+
+// The edge loop of one slice, run by every wavefront of the workgroup:
+// chunk c of the slice goes to wavefront (c - c0) mod kWaves.  A wavefront
+// takes kBlkGroup chunks per step: it gathers their sources' values
+// (`value(wbase, packed)`: the sources of a chunk are sorted and share one
+// window, so neighbouring lanes mostly read the same cache lines), starts
+// loading the next step's packed edges, and then combines each value into
+// its destination's LDS slot (`combine(slot, v)`).  Lanes past a chunk's
+// end combine `idle` into their own pad slot kBlkRows + lane, so that no
+// combine is under a branch: a gather used only under a branch is issued
+// late, inside it.  Two steps per iteration and no exit between them (past
+// the slice's end the chunks are empty): an exit there would let the
+// compiler move the first step's prefetch behind it, to just before use.
+// The two register sets alternate, so no loaded value is copied (a copy
+// would wait for its load).
+template <class T, class Value, class Combine>
+__device__ __forceinline__ void blk_stream(const BlkView& b, const BlkSlice& sl, T idle, Value value, Combine combine) {
+  constexpr int kPer = kBlkChunk / kWave;
+  constexpr uint32_t kWaves = kBlkThreads / kWave;
+  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = lane_id();
+  using Group = BlkChunk[kBlkGroup];
+  using Edges = uint32_t[kBlkGroup][kPer];
+  auto meta = [&](uint64_t c, Group& ch) {
+#pragma unroll
+    for (int g = 0; g < kBlkGroup; ++g) ch[g] = blk_chunk_at(b, c + g * kWaves, sl.c1);
+  };
+  auto load = [&](const Group& ch, Edges& p) {
+#pragma unroll
+    for (int g = 0; g < kBlkGroup; ++g) blk_load(b, ch[g], p[g]);
+  };
+  auto step = [&](const Group& ch, const Edges& p, const Group& next, Edges& pn) {
+    T x[kBlkGroup][kPer];
+#pragma unroll
+    for (int g = 0; g < kBlkGroup; ++g)
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) x[g][k] = value(ch[g].wbase, ch[g].n ? p[g][k] : 0u);
+    load(next, pn);
+#pragma unroll
+    for (int g = 0; g < kBlkGroup; ++g)
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const bool in = lane + k * kWave < ch[g].n;
+        combine(in ? p[g][k] & 0xFFFFu : kBlkRows + lane, in ? x[g][k] : idle);
+      }
+  };
+  constexpr uint64_t kStride = static_cast<uint64_t>(kWaves) * kBlkGroup;
+  uint64_t c = static_cast<uint64_t>(sl.c0) + wv;
+  Group ca, cb, n1, n2;
+  Edges pa, pb;
+  meta(c, ca);
+  meta(c + kStride, cb);
+  load(ca, pa);
+  while (c < sl.c1) {
+    meta(c + 2 * kStride, n1);
+    step(ca, pa, cb, pb);
+    meta(c + 3 * kStride, n2);
+    step(cb, pb, n1, pa);
+    c += 2 * kStride;
+#pragma unroll
+    for (int g = 0; g < kBlkGroup; ++g) {
+      ca[g] = n1[g];
+      cb[g] = n2[g];
+    }
+  }
+}
+
+}  // namespace ipg

@@ -183,8 +183,11 @@ struct GraphTables {
   int32_t* src_hot;     // [e] CSC sources, new names
   TilingTables pull_hot;
   // IPG_GRAPH_BLOCKED: the blocked in-edges of the CSC PageRank's pull uses
-  // (the hot-first one when present), else edges == null.
+  // (the hot-first one when present), else edges == null; with a hot-first
+  // store also those of the caller's CSC (blk_ids), for the CC/SSSP pull,
+  // which works on the caller's vertex ids.
   BlockedTables blk;
+  BlockedTables blk_ids;
 };
 
 // Pull-side view of the CSC handed to the gather kernels.  A launch has nc

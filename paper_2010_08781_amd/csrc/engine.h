@@ -154,13 +154,13 @@ struct Tune {
   uint32_t push_div;
   uint32_t list_div;
   uint32_t gate_div;  // pull gathers only senders' outboxes when senders < N / gate_div (0 = never)
-  uint32_t pr_blocked;  // PageRank pull uses the blocked in-edges when the store has them
+  uint32_t blocked;  // pull exchanges use the blocked in-edges when the store has them
 };
 constexpr uint32_t kHotDefault = 8192;  // 64 KB of LDS; the launch also caps it to the LDS left by the tiles
 inline Tune resolve_tuning(const ipg_tuning* t) {
   Tune r{kHotDefault, kPullGrid, 20, 16, 8, 1};
   if (t) {
-    if (t->pr_blocked) r.pr_blocked = t->pr_blocked == 0xFFFFFFFFu ? 0 : 1;
+    if (t->blocked) r.blocked = t->blocked == 0xFFFFFFFFu ? 0 : 1;
     if (t->gate_div) r.gate_div = t->gate_div == 0xFFFFFFFFu ? 0 : t->gate_div;
     if (t->pr_hot) r.pr_hot = t->pr_hot == 0xFFFFFFFFu ? 0 : t->pr_hot;
     if (t->pull_grid) r.pull_grid = t->pull_grid;

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "common.h"
+#include "blocked.h"
 #include "engine.h"
 #include "scatter.h"
 #include "selector.h"
@@ -430,6 +431,111 @@ __global__ __launch_bounds__(kBlock) void minprop_pull_kernel(MinPullArgs a) {
   flush_counters(a.ctr, 0, 0, next_count, next_deg, overflow);
 }
 
+// Blocked pull (IPG_GRAPH_BLOCKED, CC and SSSP with unit weights): the
+// blocked in-edges of the caller's CSC streamed through one workgroup per
+// slice (blocked.h), each message min-combined into its destination's LDS
+// slot.  The minima do not depend on the order, so results are exact.
+struct MinBlkArgs {
+  BlkView v;
+  const uint32_t* outdeg;
+  const uint32_t* outbox;
+  uint32_t* mail_out;
+  CtrSlot* ctr;
+  CtrSlot* ctr_clear;
+  const DevCtl* ctl;  // device-driven loop: run only when it chose pull (else null)
+};
+
+// Counters of a workgroup of any width: summed over its wavefronts in LDS,
+// then at most one atomic per field into its slot.  Every thread calls it.
+__device__ __forceinline__ void flush_next_counters(CtrSlot* base, uint64_t next_count, uint64_t next_deg,
+                                                    uint32_t overflow) {
+  __shared__ unsigned long long red[3][kBlkThreads / kWave];
+  next_count = wave_sum_u64(next_count);
+  next_deg = wave_sum_u64(next_deg);
+  const bool ovf = __ballot(overflow != 0) != 0;
+  const uint32_t w = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    red[0][w] = next_count;
+    red[1][w] = next_deg;
+    red[2][w] = ovf ? 1 : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    unsigned long long t = 0;
+    for (uint32_t i = 0; i < blockDim.x / kWave; ++i) t += red[threadIdx.x][i];
+    CtrSlot* c = my_slot(base);
+    if (t && threadIdx.x == 0) atomicAdd(&c->next_count, static_cast<uint32_t>(t));
+    if (t && threadIdx.x == 1) atomicAdd(&c->next_deg, t);
+    if (t && threadIdx.x == 2) atomicOr(&c->overflow, 1u);
+  }
+}
+
+// Blocked pull, first launch: workgroup = slice.  The block's minima start
+// at INF in LDS; the workgroup streams the slice's chunks.  A block's only
+// slice then writes its rows' mailboxes (rows with a message) and counts
+// them; a slice of a larger block stores its minima as a partial.
+template <int APP>
+__global__ __launch_bounds__(kBlkThreads) void minprop_blocked_kernel(MinBlkArgs a) {
+  __shared__ uint32_t part[kBlkRows + kWave];  // + one pad slot per lane (see blk_stream)
+  if (a.ctl && (a.ctl->halted || a.ctl->mode != IPG_MODE_PULL)) return;  // uniform over the grid
+  clear_slots(a.ctr_clear);
+  const BlkSlice sl = a.v.slices[blockIdx.x];
+  for (uint32_t r = threadIdx.x; r < sl.rows; r += kBlkThreads) part[r] = kInf;
+  if (threadIdx.x < kWave) part[kBlkRows + threadIdx.x] = kInf;
+  __syncthreads();
+  uint32_t overflow = 0;
+  const uint32_t* outbox = a.outbox;
+  blk_stream<uint32_t>(
+      a.v, sl, kInf, [&](uint32_t wbase, uint32_t q) { return outbox[wbase + (q >> 16)]; },
+      [&](uint32_t slot, uint32_t o) { atomicMin(&part[slot], edge_msg<APP, false>(o, 1u, overflow)); });
+  __syncthreads();
+  const uint32_t r0 = sl.row0, rows = sl.rows;
+  uint64_t next_count = 0, next_deg = 0;
+  if (sl.poff == kNoPartial) {
+    for (uint32_t r = threadIdx.x; r < rows; r += kBlkThreads) {
+      const uint32_t m = part[r];
+      if (m < kInf) {
+        a.mail_out[r0 + r] = m;
+        next_count += 1;
+        next_deg += a.outdeg[r0 + r];
+      }
+    }
+  } else {
+    uint32_t* dst = static_cast<uint32_t*>(a.v.partial) + sl.poff;
+    for (uint32_t r = threadIdx.x; r < rows; r += kBlkThreads) dst[r] = part[r];
+  }
+  flush_next_counters(a.ctr, next_count, next_deg, overflow);
+}
+
+// Blocked pull, second launch: the rows of every block with several slices
+// take the minimum of the slices' partials (a wavefront per group of 64
+// rows, every partial load in flight at once).
+__global__ __launch_bounds__(kBlock) void minprop_blocked_finish_kernel(MinBlkArgs a) {
+  if (a.ctl && (a.ctl->halted || a.ctl->mode != IPG_MODE_PULL)) return;
+  const uint32_t lane = lane_id();
+  const uint32_t nw = gridDim.x * kWavesPerBlock;
+  uint64_t next_count = 0, next_deg = 0;
+  for (uint32_t w = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; w < a.v.ngroups; w += nw) {  // wave-uniform
+    const BlkGroup gr = a.v.groups[w];
+    const uint32_t rr = lane < gr.nrows ? lane : gr.nrows - 1;
+    const uint32_t* p = static_cast<const uint32_t*>(a.v.partial) + gr.poff + rr;
+    uint32_t m = kInf;
+    for (uint32_t k = 0; k < gr.k; k += 8) {
+      uint32_t x[8];
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j) x[j] = p[static_cast<uint64_t>(k + j < gr.k ? k + j : gr.k - 1) * gr.stride];
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j) m = min(m, x[j]);
+    }
+    if (lane < gr.nrows && m < kInf) {
+      a.mail_out[gr.row0 + lane] = m;
+      next_count += 1;
+      next_deg += a.outdeg[gr.row0 + lane];
+    }
+  }
+  flush_counters(a.ctr, 0, 0, next_count, next_deg, 0);
+}
+
 // End of a superstep: sum the counter slots (one wavefront, lane t reads
 // slot t) and, when a selector is given and work is pending, choose the
 // exchange of the next superstep with the network.
@@ -644,7 +750,10 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
     IPG_HIP(push_dispatch(app, weighted, a, grid, hubs, s));
   }
   if (device || mode == IPG_MODE_PULL) {
-    const bool gating = step > 0 && tn.gate_div != 0;
+    // the blocked in-edges of the caller's CSC (CC, unit-weight SSSP), if the store has them
+    const BlockedTables* bt = nullptr;
+    if (tn.blocked && !weighted) bt = g->t.blk_ids.edges ? &g->t.blk_ids : (g->t.blk.edges && !g->t.perm ? &g->t.blk : nullptr);
+    const bool gating = step > 0 && tn.gate_div != 0 && !bt;  // the blocked pull reads every outbox
     if (step > 0) {
       if (!device) IPG_HIP(fill_u32(w.outbox, n, kInf, s));
       if (gating) IPG_HIP(fill_u32(w.sent, (uint64_t)n / 64 * 2 + 2, 0, s));
@@ -666,6 +775,31 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
         hipLaunchKernelGGL(gate_kernel, dim3(1), dim3(kWave), 0, s, b.c, n, tn.gate_div, ctl, w.gate);
         IPG_HIP(hipGetLastError());
       }
+    }
+    if (bt) {
+      MinBlkArgs ba;
+      ba.v = blk_view(*bt);
+      ba.outdeg = g->t.outdeg;
+      ba.outbox = w.outbox;
+      ba.mail_out = b.mail_out;
+      ba.ctr = b.c;
+      ba.ctr_clear = b.cc;
+      ba.ctl = ctl;
+      if (bt->nslices) {
+        if (app == IPG_APP_CC_HASHMIN)
+          hipLaunchKernelGGL(minprop_blocked_kernel<IPG_APP_CC_HASHMIN>, dim3(bt->nslices), dim3(kBlkThreads), 0, s, ba);
+        else
+          hipLaunchKernelGGL(minprop_blocked_kernel<IPG_APP_SSSP>, dim3(bt->nslices), dim3(kBlkThreads), 0, s, ba);
+        IPG_HIP(hipGetLastError());
+      } else {  // no edges: nothing arrives, but the next superstep's counters are still cleared here
+        IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(b.cc), kCtrSlots * sizeof(CtrSlot) / 4, 0, s));
+      }
+      if (bt->ngroups) {
+        hipLaunchKernelGGL(minprop_blocked_finish_kernel, dim3(grid_for(bt->ngroups, kWavesPerBlock, 4096)),
+                           dim3(kBlock), 0, s, ba);
+        IPG_HIP(hipGetLastError());
+      }
+      return IPG_OK;
     }
     MinPullArgs pa;
     pa.t = pull_tiling(g);

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "common.h"
+#include "blocked.h"
 #include "engine.h"
 #include "scatter.h"
 
@@ -288,114 +289,28 @@ __global__ __launch_bounds__(kBlock) void pr_longrow_kernel(PrPullArgs a) {
 
 // Blocked pull (IPG_GRAPH_BLOCKED): the in-edges of each block of at most
 // kBlkRows destinations, sorted by source, streamed through one workgroup
-// per slice.
+// per slice (blocked.h).
 struct PrBlkArgs {
-  const uint32_t* edges;
-  const BlkChunk* chunks;
-  const BlkSlice* slices;
-  const BlkGroup* groups;
-  double* partial;
+  BlkView v;
   uint32_t n;
-  uint32_t ngroups;
 };
-constexpr uint32_t kBlkThreads = 1024;
-constexpr int kBlkGroup = 4;  // chunks a wavefront takes per step
-
-// A chunk past the slice's end: no edges (its loads read the slice table).
-__device__ __forceinline__ BlkChunk blk_chunk_at(const PrBlkArgs& b, uint64_t c, uint32_t c1) {
-  if (c < c1) return b.chunks[c];
-  BlkChunk z;
-  z.e0 = 0;
-  z.wbase = 0;
-  z.n = 0;
-  return z;
-}
-
-// The packed edges of a chunk, one per lane and register, the index clamped
-// into the chunk so that every load is unconditional.
-__device__ __forceinline__ void blk_load(const PrBlkArgs& b, const BlkChunk& ch, uint32_t (&p)[kBlkChunk / kWave]) {
-  const uint32_t lane = lane_id();
-  const uint32_t* base = ch.n ? b.edges + ch.e0 : reinterpret_cast<const uint32_t*>(b.slices);
-  const uint32_t last = ch.n ? ch.n - 1 : 0;
-#pragma unroll
-  for (int k = 0; k < static_cast<int>(kBlkChunk / kWave); ++k) {
-    const uint32_t i = lane + k * kWave;
-    p[k] = __builtin_nontemporal_load(base + (i < last ? i : last));
-  }
-}
 
 // Blocked pull, first launch: workgroup = slice.  The block's sums start at
-// zero in LDS; every wavefront streams its share of the slice's chunks
-// (software-pipelined: the packed edges of the next chunk load while the
-// outboxes of this one are gathered), gathers each edge's outbox -- the
-// sources of a chunk are sorted and share one window, so neighbouring lanes
-// mostly read the same cache lines -- and adds it into its destination's sum
-// with an LDS atomic.  A block's only slice then finishes the block's
-// vertices; a slice of a larger block stores its sums as a partial.
+// zero in LDS; the workgroup streams the slice's chunks, adding each edge's
+// outbox into its destination's sum with an LDS atomic.  A block's only
+// slice then finishes the block's vertices; a slice of a larger block
+// stores its sums as a partial.
 __global__ __launch_bounds__(kBlkThreads) void pr_blocked_kernel(PrPullArgs a, PrBlkArgs b) {
-  constexpr int kPer = kBlkChunk / kWave;
-  constexpr uint32_t kWaves = kBlkThreads / kWave;
-  // + one slot per lane that lanes past a chunk's end add 0.0 into, so that
-  // the adds need no branch (a gather used only under a branch is issued
-  // late, inside it)
+  // + one pad slot per lane (see blk_stream)
   __shared__ double part[kBlkRows + kWave];
-  const BlkSlice sl = b.slices[blockIdx.x];
+  const BlkSlice sl = b.v.slices[blockIdx.x];
   for (uint32_t r = threadIdx.x; r < sl.rows; r += kBlkThreads) part[r] = 0.0;
   if (threadIdx.x < kWave) part[kBlkRows + threadIdx.x] = 0.0;
   __syncthreads();
-  const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = lane_id();
-  // A wavefront takes kBlkGroup chunks per step: chunks c + g * kWaves of
-  // the slice.  One step gathers the outboxes of its chunks, starts loading
-  // the edges of the next step's chunks into `pn`, and adds its messages.
-  // The loop alternates two register sets, so no loaded value is copied (a
-  // copy would wait for the load).
-  using Group = BlkChunk[kBlkGroup];
-  using Edges = uint32_t[kBlkGroup][kPer];
-  auto meta = [&](uint64_t c, Group& ch) {
-#pragma unroll
-    for (int g = 0; g < kBlkGroup; ++g) ch[g] = blk_chunk_at(b, c + g * kWaves, sl.c1);
-  };
-  auto load = [&](const Group& ch, Edges& p) {
-#pragma unroll
-    for (int g = 0; g < kBlkGroup; ++g) blk_load(b, ch[g], p[g]);
-  };
-  auto step = [&](const Group& ch, const Edges& p, const Group& next, Edges& pn) {
-    double x[kBlkGroup][kPer];
-#pragma unroll
-    for (int g = 0; g < kBlkGroup; ++g)
-#pragma unroll
-      for (int k = 0; k < kPer; ++k) x[g][k] = a.contrib_in[ch[g].wbase + ((ch[g].n ? p[g][k] : 0u) >> 16)];
-    load(next, pn);
-#pragma unroll
-    for (int g = 0; g < kBlkGroup; ++g)
-#pragma unroll
-      for (int k = 0; k < kPer; ++k) {
-        const bool in = lane + k * kWave < ch[g].n;
-        atomicAdd(&part[in ? p[g][k] & 0xFFFFu : kBlkRows + lane], in ? x[g][k] : 0.0);
-      }
-  };
-  constexpr uint64_t kStride = static_cast<uint64_t>(kWaves) * kBlkGroup;
-  uint64_t c = static_cast<uint64_t>(sl.c0) + wv;
-  Group ca, cb, n1, n2;
-  Edges pa, pb;
-  meta(c, ca);
-  meta(c + kStride, cb);
-  load(ca, pa);
-  // Two steps per iteration and no exit between them (past the slice's end
-  // the chunks are empty and add nothing): an exit there would let the
-  // compiler move the first step's prefetch behind it, to just before use.
-  while (c < sl.c1) {
-    meta(c + 2 * kStride, n1);
-    step(ca, pa, cb, pb);
-    meta(c + 3 * kStride, n2);
-    step(cb, pb, n1, pa);
-    c += 2 * kStride;
-#pragma unroll
-    for (int g = 0; g < kBlkGroup; ++g) {
-      ca[g] = n1[g];
-      cb[g] = n2[g];
-    }
-  }
+  const double* contrib = a.contrib_in;
+  blk_stream<double>(
+      b.v, sl, 0.0, [&](uint32_t wbase, uint32_t q) { return contrib[wbase + (q >> 16)]; },
+      [&](uint32_t slot, double x) { atomicAdd(&part[slot], x); });
   __syncthreads();
   const uint32_t r0 = sl.row0, rows = sl.rows;
   double l1 = 0.0;
@@ -417,7 +332,7 @@ __global__ __launch_bounds__(kBlkThreads) void pr_blocked_kernel(PrPullArgs a, P
       }
     }
   } else {
-    double* dst = b.partial + sl.poff;
+    double* dst = static_cast<double*>(b.v.partial) + sl.poff;
     for (uint32_t r = threadIdx.x; r < rows; r += kBlkThreads) dst[r] = part[r];
   }
   if (a.l1) flush_l1(a.l1, l1);
@@ -432,11 +347,11 @@ __global__ __launch_bounds__(kBlock) void pr_blocked_finish_kernel(PrPullArgs a,
   const uint32_t lane = lane_id();
   const uint32_t nw = gridDim.x * kWavesPerBlock;
   double l1 = 0.0;
-  for (uint32_t w = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; w < b.ngroups; w += nw) {  // wave-uniform
-    const BlkGroup gr = b.groups[w];
+  for (uint32_t w = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; w < b.v.ngroups; w += nw) {  // wave-uniform
+    const BlkGroup gr = b.v.groups[w];
     const uint32_t rr = lane < gr.nrows ? lane : gr.nrows - 1;
     const RowIn in = pr_row_load(a, gr.row0 + rr);
-    const double* p = b.partial + gr.poff + rr;
+    const double* p = static_cast<const double*>(b.v.partial) + gr.poff + rr;
     double sum = 0.0;
     for (uint32_t k = 0; k < gr.k; k += 8) {
       double x[8];
@@ -618,22 +533,17 @@ static PrPullStore pr_store_of(const ipg_graph* g, const RunWs& w) {
 // sums.
 static hipError_t launch_pr_pull(const PrPullArgs& a, const PrPullStore& ps, const Tune& tn, uint32_t n,
                                  hipStream_t s) {
-  if (ps.blk && tn.pr_blocked) {
+  if (ps.blk && tn.blocked) {
     PrBlkArgs b;
-    b.edges = ps.blk->edges;
-    b.chunks = ps.blk->chunks;
-    b.slices = ps.blk->slices;
-    b.groups = ps.blk->groups;
-    b.partial = ps.blk->partial;
+    b.v = blk_view(*ps.blk);
     b.n = n;
-    b.ngroups = ps.blk->ngroups;
     hipError_t err = hipSuccess;
     if (ps.blk->nslices) {  // none when the graph has no edges
       hipLaunchKernelGGL(pr_blocked_kernel, dim3(ps.blk->nslices), dim3(kBlkThreads), 0, s, a, b);
       err = hipGetLastError();
     }
-    if (err != hipSuccess || !b.ngroups) return err;
-    const uint32_t grid = grid_for(b.ngroups, kWavesPerBlock, 4096);
+    if (err != hipSuccess || !b.v.ngroups) return err;
+    const uint32_t grid = grid_for(b.v.ngroups, kWavesPerBlock, 4096);
     hipLaunchKernelGGL(pr_blocked_finish_kernel, dim3(grid), dim3(kBlock), 0, s, a, b);
     return hipGetLastError();
   }
@@ -718,7 +628,7 @@ static ipg_status pagerank_graph(ipg_graph* g, uint32_t T, bool push, const RunW
                                  const uint32_t* part_off, uint32_t parts, const Tune& tn, hipGraphExec_t* out) {
   auto& k = g->pr_key;
   if (g->pr_exec && k.T == T && k.push == (push ? 1 : 0) && k.ws == ws && k.parts == part_off && k.num_parts == parts &&
-      k.hot == tn.pr_hot && k.grid == tn.pull_grid && k.blocked == tn.pr_blocked) {
+      k.hot == tn.pr_hot && k.grid == tn.pull_grid && k.blocked == tn.blocked) {
     *out = g->pr_exec;
     return IPG_OK;
   }
@@ -749,7 +659,7 @@ static ipg_status pagerank_graph(ipg_graph* g, uint32_t T, bool push, const RunW
   k.num_parts = parts;
   k.hot = tn.pr_hot;
   k.grid = tn.pull_grid;
-  k.blocked = tn.pr_blocked;
+  k.blocked = tn.blocked;
   *out = g->pr_exec;
   return IPG_OK;
 }

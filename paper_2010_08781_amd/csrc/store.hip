@@ -161,12 +161,16 @@ static size_t carve_graph(Carver& c, uint32_t n, uint64_t e, uint32_t flags, Gra
     tt.src_hot = c.take<int32_t>(e ? e : 1);
     carve_tiling(c, n, e, &tt.pull_hot);
   }
+  auto carve_blocked = [&](BlockedTables& b) {
+    b.edges = c.take<uint32_t>(e ? e : 1);
+    b.chunks = c.take<BlkChunk>(blk_chunks_cap(n, e));
+    b.slices = c.take<BlkSlice>(blk_blocks_cap(n, e) + blk_target_slices(e));
+    b.groups = c.take<BlkGroup>(blk_groups_cap(n, e));
+    b.partial = c.take<double>(blk_partial_cap(e));
+  };
   if (flags & IPG_GRAPH_BLOCKED) {
-    tt.blk.edges = c.take<uint32_t>(e ? e : 1);
-    tt.blk.chunks = c.take<BlkChunk>(blk_chunks_cap(n, e));
-    tt.blk.slices = c.take<BlkSlice>(blk_blocks_cap(n, e) + blk_target_slices(e));
-    tt.blk.groups = c.take<BlkGroup>(blk_groups_cap(n, e));
-    tt.blk.partial = c.take<double>(blk_partial_cap(e));
+    carve_blocked(tt.blk);
+    if (flags & IPG_GRAPH_RENAME) carve_blocked(tt.blk_ids);
   }
   if (t) *t = tt;
   return align_up(c.used, 256);
@@ -552,8 +556,12 @@ extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t
     if (rc != IPG_OK) return rc;
   }
   if (d->flags & IPG_GRAPH_BLOCKED) {
-    rc = (d->flags & IPG_GRAPH_RENAME) ? build_blocked(t.off_hot, t.src_hot, n, e, &t.blk, s)
-                                       : build_blocked(csc_off, csc_src, n, e, &t.blk, s);
+    if (d->flags & IPG_GRAPH_RENAME) {
+      rc = build_blocked(t.off_hot, t.src_hot, n, e, &t.blk, s);
+      if (rc == IPG_OK) rc = build_blocked(csc_off, csc_src, n, e, &t.blk_ids, s);
+    } else {
+      rc = build_blocked(csc_off, csc_src, n, e, &t.blk, s);
+    }
     if (rc != IPG_OK) return rc;
   }
 

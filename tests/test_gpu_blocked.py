@@ -108,14 +108,14 @@ def test_edge_cases(ipg, case):
 
 
 def test_item_kernels_when_switched_off(ipg):
-    # tuning pr_blocked = UINT32_MAX runs the row-item pull, bitwise equal to
+    # tuning blocked = UINT32_MAX runs the row-item pull, bitwise equal to
     # the same store without blocked in-edges
     import torch
 
     hg = graphgen.rmat(15, 16, seed=8, symmetric=True)
     a = ipg.Graph.from_host(hg, blocked=True)
     b = ipg.Graph.from_host(hg, blocked=False)
-    ra, _ = a.run("pagerank", 10, mode="pull", tuning={"pr_blocked": OFF})
+    ra, _ = a.run("pagerank", 10, mode="pull", tuning={"blocked": OFF})
     rb, _ = b.run("pagerank", 10, mode="pull")
     assert torch.equal(ra, rb)
     rc, _ = a.run("pagerank", 10, mode="pull")
@@ -166,3 +166,62 @@ def test_full_size_rmat_s20_symmetrised(ipg):
     assert max_rel(ipg.values_to_numpy(vals), ref.values) <= PR_RTOL
     vals, st = g.run("pagerank", 10, mode="pull", graph=True)
     assert max_rel(ipg.values_to_numpy(vals), ref.values) <= PR_RTOL
+
+
+# ---------------------------------------------------------------- CC / SSSP --
+# The blocked min-pull combines with atomic minima, which do not depend on
+# the order: values and per-superstep traces are bit-exact.
+
+def check_min(ipg, hg, app, source=0, rename=True, weighted=True, modes=("pull", "auto", "push")):
+    ref = oracle.run_graph(app, hg, 0, source=source, weighted=weighted)
+    assert ref.status == oracle.OK
+    g = ipg.Graph.from_host(hg, weighted=weighted, rename=rename, blocked=True)
+    for mode in modes:
+        for persistent in (False, True):
+            vals, st = g.run(app, source=source, mode=mode, persistent=persistent)
+            got = ipg.values_to_numpy(vals)
+            assert np.array_equal(got, ref.values), f"{app} {mode} persistent={persistent}: {np.sum(got != ref.values)} differ"
+            assert np.array_equal(st.trace, ref.trace), (app, mode, persistent)
+            assert st.halted
+    return g
+
+
+@pytest.mark.parametrize("rename", [True, False])
+@pytest.mark.parametrize("app", ["cc", "sssp"])
+def test_min_pull_rmat_s16_symmetrised(ipg, app, rename):
+    check_min(ipg, graphgen.rmat(16, 16, seed=31, symmetric=True), app, source=3, rename=rename)
+
+
+@pytest.mark.parametrize("app", ["cc", "sssp"])
+def test_min_pull_directed_and_multigraph(ipg, app):
+    check_min(ipg, graphgen.workload("rmat-s14-dir"), app, source=0)
+    check_min(ipg, random_graph(3000, 40000, seed=5, loops=True, dups=True), app, source=17, rename=False)
+
+
+def test_min_pull_long_path_and_edge_cases(ipg):
+    from tests.graphs_small import path
+    check_min(ipg, path(3000), "sssp", source=0, modes=("pull", "auto"))
+    check_min(ipg, path(3000), "cc", modes=("pull",))
+    for hg in (graphgen.from_edges(1, [], []), graphgen.from_edges(70, [], []),
+               graphgen.from_edges(90000, np.arange(0, 300), np.arange(1, 301))):
+        for app in ("cc", "sssp"):
+            check_min(ipg, hg, app, source=0, modes=("pull", "auto"))
+
+
+def test_min_pull_weighted_sssp_uses_row_items(ipg):
+    # weighted SSSP keeps the row-item pull on a blocked store; still exact
+    check_min(ipg, graphgen.grid_with_shortcuts(256, 0.02, seed=7), "sssp", source=0, modes=("pull", "auto"))
+
+
+def test_min_pull_full_size_and_switched_off(ipg):
+    import torch
+
+    hg = graphgen.workload("rmat-s20-sym")
+    g = check_min(ipg, hg, "cc", modes=("pull", "auto"))
+    for app in ("cc", "sssp"):
+        a, sa = g.run(app, mode="pull", persistent=True)
+        b, sb = g.run(app, mode="pull", persistent=True, tuning={"blocked": OFF})
+        assert torch.equal(a, b) and np.array_equal(sa.trace, sb.trace)
+    ref = oracle.run_graph("sssp", hg, 0, source=0)
+    v, st = g.run("sssp", source=0, mode="auto", persistent=True)
+    assert np.array_equal(ipg.values_to_numpy(v), ref.values) and np.array_equal(st.trace, ref.trace)
