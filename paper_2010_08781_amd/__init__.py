@@ -185,6 +185,7 @@ class _Trace:
 
     def __init__(self, cap: int, timing: bool):
         self.cap = cap
+        self.last = 0  # supersteps the previous run filled (for reuse)
         self.a = {k: np.zeros(cap, dtype=np.uint64) for k in ("active", "senders", "messages", "examined", "frontier_deg")}
         self.a["mode"] = np.zeros(cap, dtype=np.uint8)
         self.usec = np.zeros(cap, dtype=np.float32) if timing else None
@@ -195,15 +196,32 @@ class _Trace:
                          self.usec.ctypes.data if self.usec is not None else None, a["frontier_deg"].ctypes.data,
                          self.residual.ctypes.data)
 
+    def reset(self):
+        """Prepare the buffers for another run: clear the entries a run may
+        leave unwritten (per-superstep times, residuals) up to the previous
+        run's length."""
+        k = self.last
+        if k:
+            if self.usec is not None:
+                self.usec[:k] = 0
+            self.residual[:k] = 0
+        st = self.st
+        st.supersteps = st.halted = st.edges_traversed = st.edges_examined = 0
+        st.seconds = 0.0
+        return self
+
     def stats(self, rc: int) -> "RunStats":
         st, a = self.st, self.a
         if rc not in (OK, NOT_CONVERGED):
             return RunStats(rc, 0, False, 0, 0, 0.0, *(np.zeros(0),) * 5)
         k = min(int(st.supersteps), self.cap)
+        self.last = max(self.last, k)
+        # copies: the buffers are reused by the next run on the graph
         return RunStats(rc, int(st.supersteps), bool(st.halted), int(st.edges_traversed), int(st.edges_examined),
-                        float(st.seconds), a["active"][:k], a["senders"][:k], a["messages"][:k], a["examined"][:k],
-                        a["mode"][:k], self.usec[:k] if self.usec is not None else None, a["frontier_deg"][:k],
-                        self.residual[:k])
+                        float(st.seconds), a["active"][:k].copy(), a["senders"][:k].copy(), a["messages"][:k].copy(),
+                        a["examined"][:k].copy(), a["mode"][:k].copy(),
+                        self.usec[:k].copy() if self.usec is not None else None, a["frontier_deg"][:k].copy(),
+                        self.residual[:k].copy())
 
 
 class Graph:
@@ -250,6 +268,7 @@ class Graph:
         self._h = h
         self.device = csr_off.device
         self._run_ws = {}
+        self._traces = {}
 
     @classmethod
     def from_csr_csc(cls, *args, **kw) -> "Graph":
@@ -277,6 +296,14 @@ class Graph:
             csc_w = csr_w if sym else up(hg.csc_w.astype(np.uint32), np.int32)
         return cls(hg.n, csr_off, csr_dst, csc_off, csc_src, csr_w, csc_w, symmetric=sym, validate=validate,
                    rename=rename, blocked=blocked)
+
+    def _trace(self, cap: int, timing: bool) -> "_Trace":
+        """The host trace buffers of this graph's runs (kept and reused: a
+        fresh set per run cost measurable host time)."""
+        key = (int(cap), bool(timing))
+        if key not in self._traces:
+            self._traces[key] = _Trace(cap, timing)
+        return self._traces[key].reset()
 
     def workspace(self, app: int):
         import torch
@@ -320,7 +347,7 @@ class Graph:
         opts = _Opts(int(source), MODES[mode], flags, selector.data_ptr() if selector is not None else None,
                      parts.data_ptr() if parts is not None else None, parts.numel() - 1 if parts is not None else 0,
                      float(tol), ctypes.addressof(tun) if tun is not None else None)
-        tr = _Trace(trace_cap, timing)
+        tr = self._trace(trace_cap, timing)
         rc = lib().ipg_run(self._h, a, comb, int(max_supersteps), ctypes.byref(opts),
                            ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(stream),
                            None if enqueue else ctypes.byref(tr.st))
@@ -358,7 +385,7 @@ class Graph:
         tun = _tuning(tuning)
         flags = (RUN_PERSISTENT if persistent else 0) | (RUN_ENQUEUE if enqueue else 0)
         opts = _Opts(0, MODES[mode], flags, None, None, 0, 0.0, ctypes.addressof(tun) if tun is not None else None)
-        tr = _Trace(trace_cap, timing)
+        tr = self._trace(trace_cap, timing)
         self._ms_src = src  # the device ids must outlive an enqueued run
         rc = lib().ipg_run_multi_sssp(self._h, src.data_ptr(), q, int(max_supersteps), ctypes.byref(opts),
                                       out.data_ptr(), out.numel() * 4, ws.data_ptr(), nbytes, _stream_handle(stream),
@@ -373,7 +400,7 @@ class Graph:
     def multi_sssp_result(self, trace_cap: int = 1024, stream=None, check: bool = True):
         """RunStats of the last device-driven batched run (after an enqueued run executed)."""
         ws, nbytes = self._run_ws["multi_sssp"]
-        tr = _Trace(trace_cap, True)
+        tr = self._trace(trace_cap, True)
         rc = lib().ipg_multi_sssp_result(self._h, ws.data_ptr(), nbytes, _stream_handle(stream), ctypes.byref(tr.st))
         if check:
             _check(rc, "ipg_multi_sssp_result", allow_not_converged=True)

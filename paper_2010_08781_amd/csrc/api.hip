@@ -38,45 +38,55 @@ size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w) {
   return align_up(c.used, 256);
 }
 
-StepTimer::~StepTimer() {
-  if (start_) (void)hipEventDestroy(start_);
-  if (end_) (void)hipEventDestroy(end_);
-  for (hipEvent_t ev : steps_) (void)hipEventDestroy(ev);
+hipError_t pool_event(std::vector<hipEvent_t>* pool, size_t i, hipEvent_t* out) {
+  while (pool->size() <= i) {
+    hipEvent_t ev;
+    const hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
+    pool->push_back(ev);
+  }
+  *out = (*pool)[i];
+  return hipSuccess;
 }
 
 hipError_t StepTimer::start(hipStream_t s) {
-  if (!start_) {
-    hipError_t e = hipEventCreate(&start_);
-    if (e != hipSuccess) return e;
-  }
-  return hipEventRecord(start_, s);
+  hipEvent_t ev;
+  hipError_t e = event(0, &ev);
+  if (e != hipSuccess) return e;
+  started_ = true;
+  return hipEventRecord(ev, s);
 }
 
 hipError_t StepTimer::step(hipStream_t s, uint32_t k) {
   if (k >= cap_) return hipSuccess;
-  while (steps_.size() <= k) {
-    hipEvent_t ev;
-    hipError_t e = hipEventCreate(&ev);
-    if (e != hipSuccess) return e;
-    steps_.push_back(ev);
-  }
-  return hipEventRecord(steps_[k], s);
+  hipEvent_t ev;
+  hipError_t e = event(2 + k, &ev);
+  if (e != hipSuccess) return e;
+  if (k + 1 > nsteps_) nsteps_ = k + 1;
+  return hipEventRecord(ev, s);
 }
 
 hipError_t StepTimer::finish(hipStream_t s) {
-  hipError_t e;
-  if (!end_ && (e = hipEventCreate(&end_)) != hipSuccess) return e;
-  if ((e = hipEventRecord(end_, s)) != hipSuccess) return e;
-  if ((e = hipEventSynchronize(end_)) != hipSuccess) return e;
+  hipEvent_t end;
+  hipError_t e = event(1, &end);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventRecord(end, s)) != hipSuccess) return e;
+  if ((e = hipEventSynchronize(end)) != hipSuccess) return e;
   float ms = 0.f;
-  if (start_ && (e = hipEventElapsedTime(&ms, start_, end_)) != hipSuccess) return e;
+  if (started_ && (e = hipEventElapsedTime(&ms, (*pool_)[0], end)) != hipSuccess) return e;
   seconds_ = ms * 1e-3;
-  hipEvent_t prev = start_;
-  for (size_t k = 0; k < steps_.size() && k < cap_; ++k) {
+  hipEvent_t prev = (*pool_)[0];
+  for (uint32_t k = 0; k < nsteps_ && k < cap_; ++k) {
     float t = 0.f;
-    if ((e = hipEventElapsedTime(&t, prev, steps_[k])) != hipSuccess) return e;
+    if ((e = hipEventElapsedTime(&t, prev, (*pool_)[2 + k])) != hipSuccess) return e;
     usec_[k] = t * 1e3f;
-    prev = steps_[k];
+    prev = (*pool_)[2 + k];
+  }
+  // keep the events of up to kKeep supersteps for later runs
+  constexpr size_t kKeep = 2 + 1024;
+  while (pool_->size() > kKeep) {
+    (void)hipEventDestroy(pool_->back());
+    pool_->pop_back();
   }
   return hipSuccess;
 }
@@ -134,7 +144,7 @@ extern "C" ipg_status ipg_run(ipg_graph* g, ipg_app app, ipg_combiner combiner, 
   carve_run(c, g->n, g->e, app, &w);
   g->has_values = 0;
   const bool enqueue = o.flags & IPG_RUN_ENQUEUE;
-  StepTimer tm(st && !enqueue ? st->usec : nullptr, st && !enqueue ? st->trace_cap : 0);
+  StepTimer tm(&g->events, st && !enqueue ? st->usec : nullptr, st && !enqueue ? st->trace_cap : 0);
   ipg_status rc;
   if (app == IPG_APP_PAGERANK) rc = run_pagerank(g, max_supersteps, o, w, ws, s, tm, st);
   else rc = run_minprop(g, app, max_supersteps, o, w, s, tm, st);

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/ipregel.h"
 
@@ -235,6 +236,8 @@ struct ipg_graph {
     uint32_t num_parts;
     uint32_t hot, grid, blocked;
   } pr_key;
+  // HIP events reused by every run's timing (created on first use)
+  std::vector<hipEvent_t> events;
 };
 
 namespace ipg {

@@ -111,20 +111,28 @@ size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w);
 
 // HIP-event timing of the superstep loop (first launch -> halt decision) and,
 // when the caller asked for it, of every superstep.
+// Entry i of a graph handle's event pool, created on first use.
+hipError_t pool_event(std::vector<hipEvent_t>* pool, size_t i, hipEvent_t* out);
+
+// The events come from the graph handle's pool (created on first use, kept
+// until the handle is destroyed): creating and destroying a dozen events per
+// run cost more host time than a short run's launches.
 class StepTimer {
  public:
-  StepTimer(float* usec, uint32_t cap) : usec_(usec), cap_(usec ? cap : 0) {}
-  ~StepTimer();
+  StepTimer(std::vector<hipEvent_t>* pool, float* usec, uint32_t cap)
+      : pool_(pool), usec_(usec), cap_(usec ? cap : 0) {}
   hipError_t start(hipStream_t s);
   hipError_t step(hipStream_t s, uint32_t k);  // end of superstep k
   hipError_t finish(hipStream_t s);            // synchronises
   double seconds() const { return seconds_; }
 
  private:
+  hipError_t event(size_t i, hipEvent_t* out) { return pool_event(pool_, i, out); }  // 0 start, 1 end, 2 + k superstep k
+  std::vector<hipEvent_t>* pool_;
   float* usec_;
   uint32_t cap_;
-  hipEvent_t start_ = nullptr, end_ = nullptr;
-  std::vector<hipEvent_t> steps_;
+  bool started_ = false;
+  uint32_t nsteps_ = 0;  // supersteps recorded (k < nsteps_)
   double seconds_ = 0.0;
 };
 

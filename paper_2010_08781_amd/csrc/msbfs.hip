@@ -931,8 +931,8 @@ extern "C" ipg_status ipg_run_multi_sssp(ipg_graph* g, const uint32_t* sources, 
   if (device) {
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (!enqueue && st) {
-      IPG_HIP(hipEventCreate(&t0));
-      IPG_HIP(hipEventCreate(&t1));
+      IPG_HIP(pool_event(&g->events, 0, &t0));
+      IPG_HIP(pool_event(&g->events, 1, &t1));
       IPG_HIP(hipEventRecord(t0, s));
     }
     rc = run_msbfs_device(g, sources, num_sources, max_supersteps, o, dist, w, s, enqueue);
@@ -952,10 +952,8 @@ extern "C" ipg_status ipg_run_multi_sssp(ipg_graph* g, const uint32_t* sources, 
       IPG_HIP(hipEventElapsedTime(&ms, t0, t1));
       st->seconds = ms * 1e-3;
     }
-    if (t0) (void)hipEventDestroy(t0);
-    if (t1) (void)hipEventDestroy(t1);
   } else {
-    StepTimer tm(st ? st->usec : nullptr, st ? st->trace_cap : 0);
+    StepTimer tm(&g->events, st ? st->usec : nullptr, st ? st->trace_cap : 0);
     rc = run_msbfs(g, sources, num_sources, max_supersteps, o, dist, w, s, tm, st);
     if (st) st->seconds = tm.seconds();
   }

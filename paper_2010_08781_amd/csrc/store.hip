@@ -591,6 +591,7 @@ extern "C" void ipg_graph_destroy(ipg_graph* g) {
   if (g->pr_exec) (void)hipGraphExecDestroy(g->pr_exec);
   if (g->pr_graph) (void)hipGraphDestroy(g->pr_graph);
   if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+  for (hipEvent_t ev : g->events) (void)hipEventDestroy(ev);
   delete g;
 }
 
