@@ -238,6 +238,7 @@ struct ipg_graph {
   } pr_key;
   // HIP events reused by every run's timing (created on first use)
   std::vector<hipEvent_t> events;
+  int wall_khz;  // device wall-clock rate, queried on first use (0 until then)
 };
 
 namespace ipg {

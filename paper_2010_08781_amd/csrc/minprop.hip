@@ -873,9 +873,8 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
   MinStart m0;
   ipg_status rc = start_minprop(g, app, o, w, s, &m0);
   if (rc != IPG_OK) return rc;
-  int khz = 0;
-  IPG_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g->device));
-  const double us_per_tick = khz > 0 ? 1e3 / khz : 0.0;
+  if (!g->wall_khz) IPG_HIP(hipDeviceGetAttribute(&g->wall_khz, hipDeviceAttributeWallClockRate, g->device));
+  const double us_per_tick = g->wall_khz > 0 ? 1e3 / g->wall_khz : 0.0;
   const double* sel = o.mode == IPG_MODE_AUTO ? o.selector : nullptr;
   const int forced = o.mode == IPG_MODE_AUTO ? 0 : static_cast<int>(o.mode);
   ipg_mode mode0 = o.mode;
@@ -890,7 +889,7 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
   if (rc != IPG_OK) return rc;
   uint32_t enqueued = 0;  // supersteps whose launches are in the stream, minus one
   uint32_t recorded = 0;  // supersteps whose records were read
-  uint32_t chunk = 1;
+  uint32_t chunk = 2;  // supersteps enqueued per readback: 2, 4, 8, ... 64
   DevCtl h{};
   uint64_t tot_msgs = 0, tot_exam = 0;
   std::vector<DevRec> recs(kDevRec);
@@ -909,7 +908,12 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
     }
     enqueued += chunk;
     IPG_HIP(hipMemcpyAsync(&h, w.ctl, sizeof(h), hipMemcpyDeviceToHost, s));
-    IPG_HIP(hipMemcpyAsync(recs.data(), w.rec, kDevRec * sizeof(DevRec), hipMemcpyDeviceToHost, s));
+    {  // only the ring entries of the supersteps that may have run since the last readback
+      const uint32_t a = recorded % kDevRec, cnt = enqueued - recorded;
+      const uint32_t first = std::min(cnt, kDevRec - a);
+      IPG_HIP(hipMemcpyAsync(recs.data() + a, w.rec + a, first * sizeof(DevRec), hipMemcpyDeviceToHost, s));
+      if (cnt > first) IPG_HIP(hipMemcpyAsync(recs.data(), w.rec, (cnt - first) * sizeof(DevRec), hipMemcpyDeviceToHost, s));
+    }
     IPG_HIP(hipStreamSynchronize(s));
     for (; recorded < h.step; ++recorded) {
       const DevRec& r = recs[recorded % kDevRec];
