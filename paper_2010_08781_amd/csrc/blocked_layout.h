@@ -1,0 +1,292 @@
+// blocked_layout.h -- the destination-blocked, source-sorted in-edges of a
+// CSC (IPG_GRAPH_BLOCKED): layout, size bounds and the host build.  Plain
+// C++ (no HIP): the library builds the layout on the host and copies it to
+// the device; the CPU tests build it from the same code and check it.
+#pragma once
+
+#include <stdint.h>
+
+#include <algorithm>
+#include <utility>
+#include <vector>
+
+namespace ipg {
+
+// Destination-blocked, source-sorted copy of the in-edges for PageRank's
+// blocked pull (IPG_GRAPH_BLOCKED).  The destinations are cut into blocks:
+// runs of consecutive rows, at most kBlkRows of them (one workgroup's LDS
+// of FP64 partial sums), closed early once they hold kBlkEdgeFactor / S of
+// the edges, so that the rows with many in-edges form narrow blocks.  Each
+// block's in-edges are stored sorted by source (ties by destination), one
+// 32-bit word per edge: the source's offset within its window of
+// 2^kBlkWinBits sources in the high half, the destination's row within the
+// block in the low half.  The edges are cut into chunks of at most kBlkChunk
+// edges that never straddle a window (so a wavefront's window base is
+// uniform), and each block's chunks into slices, about one per CU.  A block
+// with one slice is finished by that slice's workgroup; the slices of a
+// larger block store partial sums that a second launch adds in slice order.
+constexpr uint32_t kBlkRows = 20224;
+constexpr uint32_t kBlkWinBits = 16;
+constexpr uint32_t kBlkChunk = 256;
+constexpr uint32_t kBlkSlices = 256;
+constexpr uint64_t kBlkMinSliceEdges = 65536;
+constexpr uint64_t kBlkEdgeFactor = 8;
+// Slice balancing: a 128-byte outbox line a chunk touches costs about as
+// much as this many edges (fitted to measured slice times on MI355X).
+constexpr uint64_t kBlkLineCost = 6;
+// XCDs of the chip: workgroup i of a launch runs on XCD i mod kBlkXcds.
+constexpr size_t kBlkXcds = 8;
+static_assert(kBlkRows <= (1u << 16), "row within a block fits 16 bits");
+
+struct BlkChunk {
+  uint64_t e0;     // first edge
+  uint32_t wbase;  // first source of the chunk's window
+  uint32_t n;      // edges (1 .. kBlkChunk)
+};
+struct BlkSlice {
+  uint32_t row0, rows;  // the block's rows [row0, row0 + rows)
+  uint32_t c0, c1;      // chunks [c0, c1)
+  uint64_t poff;        // partial sums at partial + poff (rows doubles), ~0 when the slice is the block's only one
+};
+// 64 rows of a block with more than one slice, for the finish launch.
+struct BlkGroup {
+  uint32_t row0;    // first row of the group
+  uint32_t nrows;   // rows in the group (1 .. 64)
+  uint32_t k;       // the block's slices
+  uint32_t stride;  // the block's rows: slice j's partial of row row0 + i is at partial[poff + j * stride + i]
+  uint64_t poff;
+};
+constexpr uint64_t kNoPartial = ~0ull;
+
+// Target number of slices: about one per CU, none under kBlkMinSliceEdges edges.
+inline uint32_t blk_target_slices(uint64_t e) {
+  const uint64_t s = (e + kBlkMinSliceEdges - 1) / kBlkMinSliceEdges;
+  return static_cast<uint32_t>(s < 1 ? 1 : (s > kBlkSlices ? kBlkSlices : s));
+}
+// Edges at which a block closes.
+inline uint64_t blk_edge_target(uint64_t e) {
+  const uint64_t t = kBlkEdgeFactor * e / blk_target_slices(e);
+  return t < 1 ? 1 : t;
+}
+inline uint64_t blk_windows(uint32_t n) { return (static_cast<uint64_t>(n) + (1u << kBlkWinBits) - 1) >> kBlkWinBits; }
+// Blocks: one closed by the row cap takes kBlkRows rows; two consecutive
+// blocks closed by the edge target hold more than the target together.
+inline uint64_t blk_blocks_cap(uint32_t n, uint64_t e) {
+  const uint64_t by_rows = n / kBlkRows + 1, by_edges = 2 * e / blk_edge_target(e) + 2;
+  return by_rows + by_edges;
+}
+// Chunks: at most one partial chunk per non-empty (block, window) segment.
+inline uint64_t blk_chunks_cap(uint32_t n, uint64_t e) {
+  const uint64_t segs = blk_blocks_cap(n, e) * blk_windows(n);
+  return e / kBlkChunk + (segs < e ? segs : e) + 1;
+}
+// Partial sums: the blocks with several slices hold at most S slices of at
+// most kBlkRows rows.
+inline uint64_t blk_partial_cap(uint64_t e) { return static_cast<uint64_t>(blk_target_slices(e)) * kBlkRows; }
+
+// Finish groups: a multi-slice block of R rows has ceil(R / 64) of them.
+inline uint64_t blk_groups_cap(uint32_t n, uint64_t e) { return n / 64 + blk_blocks_cap(n, e) + 1; }
+
+// The host-side layout: packed edges (in block order), chunks, slices in
+// launch order, finish groups; plus the block starts and each block's first
+// chunk (used by the checks).
+struct BlockedLayout {
+  std::vector<uint32_t> packed;
+  std::vector<BlkChunk> chunks;
+  std::vector<BlkSlice> slices;
+  std::vector<BlkGroup> groups;
+  std::vector<uint32_t> row0;    // [blocks + 1] first row of each block
+  std::vector<uint64_t> cfirst;  // [blocks + 1] first chunk of each block
+};
+
+// Build the layout of a CSC given in host memory (offsets [n+1], sources
+// [e]): two stable counting sorts -- the edges by source (each source's
+// edges in destination order), then by destination block -- so that every
+// block holds its edges sorted by source; then the chunks, the slices and
+// the finish groups.  Returns null, or a message when the CSC is malformed
+// (it is read with these indices even when the graph was not validated) or
+// a table would exceed its bound.
+inline const char* blocked_layout(uint32_t n, uint64_t e, const uint64_t* off, const int32_t* src,
+                                  BlockedLayout* out) {
+  // the host loops below index with these: check them here even without IPG_GRAPH_VALIDATE
+  if (off[0] != 0 || off[n] != e) return "offsets: off[0] != 0 or off[N] != E";
+  for (uint32_t v = 0; v < n; ++v)
+    if (off[v] > off[(size_t)v + 1]) return "offsets decreasing";
+  for (uint64_t i = 0; i < e; ++i)
+    if (src[i] < 0 || static_cast<uint32_t>(src[i]) >= n) return "CSC source id outside [0, N)";
+  // blocks: runs of consecutive rows, closed before the row that would take
+  // them past the edge target (a row above it alone forms a block) or at
+  // kBlkRows rows
+  const uint64_t target = blk_edge_target(e);
+  std::vector<uint32_t> row0{0};
+  std::vector<uint32_t> blk_of(n);
+  {
+    uint64_t acc = 0;
+    for (uint32_t v = 0; v < n; ++v) {
+      const uint64_t d = off[(size_t)v + 1] - off[v];
+      if (v > row0.back() && (acc + d > target || v - row0.back() == kBlkRows)) {
+        row0.push_back(v);
+        acc = 0;
+      }
+      acc += d;
+      blk_of[v] = static_cast<uint32_t>(row0.size() - 1);
+    }
+    row0.push_back(n);
+  }
+  const uint64_t nblk = row0.size() - 1, nwin = blk_windows(n);
+  if (nblk > blk_blocks_cap(n, e)) return "blocked block table overflow";
+  // by source: dst_of[k] is the destination of the k-th edge in source order
+  std::vector<uint64_t> sstart((size_t)n + 1, 0);
+  for (uint64_t i = 0; i < e; ++i) ++sstart[(size_t)src[i] + 1];
+  for (uint32_t u = 0; u < n; ++u) sstart[(size_t)u + 1] += sstart[u];
+  std::vector<uint32_t> dst_of(e);
+  {
+    std::vector<uint64_t> cur(sstart.begin(), sstart.end() - 1);
+    for (uint32_t v = 0; v < n; ++v)
+      for (uint64_t i = off[v]; i < off[(size_t)v + 1]; ++i) dst_of[cur[src[i]]++] = v;
+  }
+  // by block, counting the edges of every (block, window) segment
+  std::vector<uint64_t> bstart(nblk + 1, 0);
+  for (uint32_t v = 0; v < n; ++v) bstart[(size_t)blk_of[v] + 1] += off[(size_t)v + 1] - off[v];
+  for (uint64_t k = 0; k < nblk; ++k) bstart[k + 1] += bstart[k];
+  std::vector<uint64_t> seg(nblk * nwin, 0);
+  std::vector<uint32_t> packed(e);
+  {
+    std::vector<uint64_t> cur(bstart.begin(), bstart.end() - 1);
+    for (uint32_t u = 0; u < n; ++u) {
+      const uint64_t w = u >> kBlkWinBits;
+      const uint32_t hi = (u & ((1u << kBlkWinBits) - 1)) << 16;
+      for (uint64_t k = sstart[u]; k < sstart[(size_t)u + 1]; ++k) {
+        const uint32_t v = dst_of[k];
+        const uint64_t blk = blk_of[v];
+        packed[cur[blk]++] = hi | (v - row0[blk]);
+        ++seg[blk * nwin + w];
+      }
+    }
+  }
+  std::vector<uint32_t>().swap(dst_of);
+  // chunks: every segment cut into pieces of at most kBlkChunk edges; the
+  // cost of a chunk is its edges plus kBlkLineCost per outbox cache line its
+  // sources touch (runs of equal source >> 4: 16 FP64 outboxes per 128-byte
+  // line; the sources are sorted)
+  std::vector<BlkChunk> chunks;
+  std::vector<uint64_t> cost;
+  std::vector<uint64_t> cfirst(nblk + 1, 0);
+  for (uint64_t blk = 0; blk < nblk; ++blk) {
+    cfirst[blk] = chunks.size();
+    uint64_t at = bstart[blk];
+    for (uint64_t w = 0; w < nwin; ++w) {
+      for (uint64_t left = seg[blk * nwin + w]; left > 0;) {
+        const uint32_t m = static_cast<uint32_t>(left < kBlkChunk ? left : kBlkChunk);
+        chunks.push_back(BlkChunk{at, static_cast<uint32_t>(w << kBlkWinBits), m});
+        uint64_t lines = 1;
+        for (uint64_t i = at + 1; i < at + m; ++i) lines += (packed[i] >> 20) != (packed[i - 1] >> 20);
+        cost.push_back(m + kBlkLineCost * lines);
+        at += m;
+        left -= m;
+      }
+    }
+  }
+  cfirst[nblk] = chunks.size();
+  if (chunks.size() > blk_chunks_cap(n, e)) return "blocked chunk table overflow";
+  // slices: with fewer blocks than S (about one slice per CU, and only one
+  // workgroup fits a CU's LDS), at most S slices in one even wave: block b
+  // gets K_b = ceil(C_b / L) slices (at least one, at most one per chunk),
+  // C_b its chunks' cost, for the smallest limit L with sum K_b <= S, which
+  // minimises the largest slice; else one slice per block.  A block's
+  // slices hold about equal costs.
+  std::vector<uint64_t> cb(nblk, 0);
+  uint64_t ctotal = 0;
+  for (uint64_t blk = 0; blk < nblk; ++blk) {
+    for (uint64_t c = cfirst[blk]; c < cfirst[blk + 1]; ++c) cb[blk] += cost[c];
+    ctotal += cb[blk];
+  }
+  const uint64_t S = blk_target_slices(e);
+  std::vector<uint64_t> kb(nblk, 1);
+  uint64_t nonempty = 0;
+  for (uint64_t blk = 0; blk < nblk; ++blk) nonempty += cfirst[blk + 1] != cfirst[blk];
+  if (nonempty < S && e) {
+    auto slices_for = [&](uint64_t L, std::vector<uint64_t>* out) {
+      uint64_t total = 0;
+      for (uint64_t blk = 0; blk < nblk; ++blk) {
+        const uint64_t nc = cfirst[blk + 1] - cfirst[blk];
+        const uint64_t k = std::max<uint64_t>(1, std::min((cb[blk] + L - 1) / L, std::max<uint64_t>(nc, 1)));
+        if (out) (*out)[blk] = k;
+        if (nc) total += k;  // a block without edges only writes 0.15/N: not counted
+      }
+      return total;
+    };
+    uint64_t lo = 1, hi = ctotal;  // slices_for(ctotal) == nonempty <= S
+    while (lo < hi) {
+      const uint64_t mid = lo + (hi - lo) / 2;
+      if (slices_for(mid, nullptr) <= S) hi = mid;
+      else lo = mid + 1;
+    }
+    slices_for(lo, &kb);
+  }
+  std::vector<BlkSlice> slices;
+  std::vector<BlkGroup> groups;
+  uint64_t poff = 0;
+  for (uint64_t blk = 0; blk < nblk; ++blk) {
+    const uint64_t K = kb[blk];
+    const uint32_t r0 = row0[blk], rows = row0[blk + 1] - row0[blk];
+    if (cfirst[blk + 1] == cfirst[blk]) {  // no in-edges: the finish launch writes its rows (0.15/N)
+      for (uint32_t g = 0; g < rows; g += 64) groups.push_back(BlkGroup{r0 + g, std::min<uint32_t>(64, rows - g), 0, rows, 0});
+      continue;
+    }
+    if (K == 1) {
+      slices.push_back(BlkSlice{r0, rows, static_cast<uint32_t>(cfirst[blk]), static_cast<uint32_t>(cfirst[blk + 1]),
+                                kNoPartial});
+      continue;
+    }
+    for (uint32_t g = 0; g < rows; g += 64)
+      groups.push_back(BlkGroup{r0 + g, std::min<uint32_t>(64, rows - g), static_cast<uint32_t>(K), rows, poff + g});
+    uint64_t c = cfirst[blk], done = 0;
+    for (uint64_t j = 0; j < K; ++j) {
+      const uint64_t c0 = c, goal = cb[blk] * (j + 1) / K;
+      const uint64_t cmax = cfirst[blk + 1] - (K - 1 - j);  // leave a chunk for every later slice
+      do {
+        done += cost[c];
+        ++c;
+      } while (c < cmax && done < goal);
+      if (j == K - 1) c = cfirst[blk + 1];
+      slices.push_back(BlkSlice{r0, rows, static_cast<uint32_t>(c0), static_cast<uint32_t>(c), poff});
+      poff += rows;
+    }
+  }
+  if (poff > blk_partial_cap(e) || slices.size() > blk_blocks_cap(n, e) + blk_target_slices(e) ||
+      groups.size() > blk_groups_cap(n, e))
+    return "blocked slice table overflow";
+  // XCD-aware launch order: workgroup i of a launch runs on XCD i mod 8, and
+  // a slice's sources are a contiguous range (its chunks are sorted by
+  // source).  The slices are sorted by their first source and XCD x takes
+  // the x-th eighth of them, so that each XCD's L2 caches about an eighth
+  // of the outbox array instead of all of it.
+  {
+    const size_t ns = slices.size();
+    auto first_src = [&](const BlkSlice& sl) -> uint64_t {
+      const BlkChunk& ch = chunks[sl.c0];
+      return static_cast<uint64_t>(ch.wbase) + (packed[ch.e0] >> 16);
+    };
+    std::vector<size_t> idx(ns);
+    for (size_t i = 0; i < ns; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](size_t x, size_t y) { return first_src(slices[x]) < first_src(slices[y]); });
+    // XCD x runs the launch positions x, x + 8, ...: it takes that many
+    // consecutive slices of the sorted order
+    std::vector<BlkSlice> dealt(ns);
+    size_t at = 0;
+    for (size_t x = 0; x < kBlkXcds && x < ns; ++x)
+      for (size_t p = x; p < ns; p += kBlkXcds) dealt[p] = slices[idx[at++]];
+    slices.swap(dealt);
+  }
+  out->packed.swap(packed);
+  out->chunks.swap(chunks);
+  out->slices.swap(slices);
+  out->groups.swap(groups);
+  out->row0.swap(row0);
+  out->cfirst.swap(cfirst);
+  return nullptr;
+}
+
+}  // namespace ipg

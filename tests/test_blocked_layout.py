@@ -1,0 +1,129 @@
+"""Host logic of the blocked in-edge layout (graph flag IPG_GRAPH_BLOCKED).
+
+The library builds the layout on the host (csrc/blocked_layout.h) before it
+copies it to the device.  `blocked_layout_check.cpp` builds it from that same
+header with g++ and checks every table the kernels read against the CSC it
+came from (edges as a multiset, block and chunk tiling, source order, slice
+cuts, partial-sum offsets, finish groups, the XCD deal, size bounds); see
+its header for the list.  The graphs span the cases the GPU tests run: one
+block cut into many slices, many blocks and source windows, edge-less
+blocks, hubs, a dense multigraph, the empty and one-vertex graphs, and the
+symmetrised R-MAT scale 20 benchmark graph.
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import graphgen
+from tests.graphs_small import random_graph
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def checker(tmp_path_factory):
+    d = tmp_path_factory.mktemp("blk")
+    exe = str(d / "blocked_layout_check")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-Wall", "-Werror", "-I", os.path.join(ROOT, "paper_2010_08781_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "blocked_layout_check.cpp"), "-o", exe], check=True)
+    return exe, d
+
+
+def run_check(checker, n, off, src):
+    exe, d = checker
+    path = str(d / "csc.bin")
+    with open(path, "wb") as f:
+        f.write(np.uint32(n).tobytes())
+        f.write(np.uint64(len(src)).tobytes())
+        f.write(np.ascontiguousarray(off, dtype=np.uint64).tobytes())
+        f.write(np.ascontiguousarray(src, dtype=np.int32).tobytes())
+    r = subprocess.run([exe, path], capture_output=True, text=True, timeout=120)
+    line = r.stdout.strip()
+    assert r.returncode == 0 and not line.startswith("FAIL"), line or r.stderr
+    return line
+
+
+def stats(line):
+    assert line.startswith("OK "), line
+    return {k: int(v) for k, v in (t.split("=") for t in line.split()[1:])}
+
+
+def check_graph(checker, hg):
+    return stats(run_check(checker, hg.n, hg.csc_off, hg.csc_src))
+
+
+def test_one_block_many_slices(checker):
+    # N = 16384 fits one block; E = 262K edges -> 4 slices, 4 * N partial sums
+    s = check_graph(checker, graphgen.workload("rmat-s14-dir"))
+    assert s["blocks"] == 1 and s["slices"] == 4 and s["partial"] == 4 * 16384 and s["groups"] == 16384 // 64
+
+
+@pytest.mark.parametrize("sym", [False, True])
+def test_many_blocks_and_windows(checker, sym):
+    s = check_graph(checker, graphgen.rmat(17, 16, seed=21, symmetric=sym))
+    assert s["blocks"] > 1 and s["slices"] <= 256
+
+
+def test_edge_less_blocks(checker):
+    n = 90000
+    rng = np.random.default_rng(6)
+    hg = graphgen.from_edges(n, rng.integers(0, n, 30000), rng.integers(0, 40000, 30000))
+    s = check_graph(checker, hg)
+    # rows 40000.. have no in-edges: their blocks are finished by groups only
+    assert s["groups"] >= (n - 40000 - 20224) // 64
+
+
+def test_hubs_and_ragged_chunks(checker):
+    n = 5000
+    rng = np.random.default_rng(4)
+    src = np.concatenate([np.arange(1, n), rng.integers(0, n, 20000), np.zeros(3000, np.int64)])
+    dst = np.concatenate([np.zeros(n - 1, np.int64), rng.integers(0, n, 20000), rng.integers(1, n, 3000)])
+    check_graph(checker, graphgen.from_edges(n, src, dst))
+
+
+@pytest.mark.parametrize("case", ["loops_dups", "single", "no_edges", "cycle", "dense", "ragged_slices"])
+def test_edge_cases(checker, case):
+    if case == "loops_dups":
+        hg = random_graph(333, 3000, seed=3, loops=True, dups=True)
+    elif case == "single":
+        hg = graphgen.from_edges(1, [], [])
+    elif case == "no_edges":
+        hg = graphgen.from_edges(70, [], [])
+    elif case == "cycle":
+        n = 1000
+        hg = graphgen.from_edges(n, np.arange(n), (np.arange(n) + 1) % n)
+    elif case == "dense":  # few vertices, many edges: a small block cut into many slices
+        hg = random_graph(300, 400000, seed=9, loops=True, dups=True)
+    else:  # a slice count that is not a multiple of the 8 XCDs
+        hg = random_graph(20000, 11 * 65536 - 5, seed=12, loops=True, dups=True)
+    s = check_graph(checker, hg)
+    if case == "ragged_slices":
+        assert s["slices"] % 8 != 0
+
+
+def test_hot_first_order(checker):
+    # the hot-first store relabels the vertices by in-degree; the layout of
+    # such a CSC (hubs first, so the first blocks are narrow) holds the same
+    # invariants
+    hg = graphgen.rmat(16, 16, seed=31, symmetric=True)
+    order = np.argsort(-np.diff(hg.csc_off).astype(np.int64), kind="stable")
+    new_id = np.empty(hg.n, np.int64)
+    new_id[order] = np.arange(hg.n)
+    src = np.repeat(np.arange(hg.n), np.diff(hg.csr_off).astype(np.int64))
+    rg = graphgen.from_edges(hg.n, new_id[src], new_id[hg.csr_dst], keep_self_loops=True)
+    s = check_graph(checker, rg)
+    assert s["blocks"] > 1
+
+
+def test_rejects_malformed_csc(checker):
+    assert run_check(checker, 3, [0, 1, 2, 2], [0, 5]).startswith("ERR CSC source id")
+    assert run_check(checker, 3, [0, 2, 1, 2], [0, 1]).startswith("ERR offsets decreasing")
+    assert run_check(checker, 3, [1, 1, 2, 2], [0, 1]).startswith("ERR offsets")
+    assert run_check(checker, 2, [0, 1, 1], [-1]).startswith("ERR CSC source id")
+
+
+def test_benchmark_graph_rmat_s20_symmetrised(checker):
+    s = check_graph(checker, graphgen.workload("rmat-s20-sym"))
+    assert s["slices"] == 256
