@@ -106,7 +106,10 @@ typedef struct {
 } ipg_graph_desc;
 
 /* ipg_run_opts.flags */
-#define IPG_RUN_PERSISTENT 1u /* device-resident superstep loop: one cooperative launch, no per-superstep host sync */
+#define IPG_RUN_PERSISTENT 1u /* device-driven superstep loop (CC/SSSP): a control block in the workspace
+                                 decides halt, active set and exchange on the device, superstep 0
+                                 included; the host enqueues supersteps in chunks of 2, 4, ... 64 and
+                                 synchronises once per chunk, with no per-superstep host sync */
 #define IPG_RUN_ENQUEUE 4u    /* enqueue the run's work on the stream and return at once, with no host
                                  synchronisation and no readback, so that the caller can capture it into a
                                  graph: PageRank (fixed T; part_offsets are not checked; no timing) and
@@ -227,7 +230,11 @@ ipg_status ipg_graph_create(const ipg_graph_desc* desc, void* workspace, size_t 
  *   IPG_EINVAL for SSSP.
  *   workspace: ipg_run_workspace_bytes(N, E, app) bytes of device memory.
  * The host loop reads one small counter block per superstep (CC/SSSP) and
- * synchronises the stream before returning.
+ * synchronises the stream before returning.  The decide kernels of CC/SSSP
+ * and of the batched SSSP write that block (and the device-driven loop's
+ * trace records) into a small pinned host buffer owned by the graph handle
+ * (created on first use, freed by ipg_graph_destroy): runs on one handle
+ * must not overlap in time, from one host thread or several.
  */
 ipg_status ipg_run(ipg_graph* graph, ipg_app app, ipg_combiner combiner, uint32_t max_supersteps,
                    const ipg_run_opts* opts, void* workspace, size_t workspace_bytes, void* hip_stream,

@@ -29,9 +29,7 @@ size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w) {
     r.gate = c.take<uint32_t>(1);
     r.list_ctr = c.take<uint32_t>(4);
     r.hubs = c.take<Hub>(kHubCap);
-    r.decision = c.take<Decision>(1);
     r.ctl = c.take<DevCtl>(1);
-    r.rec = c.take<DevRec>(kDevRec);
   }
   r.ctr = c.take<CtrSlot>(2 * kCtrSlots);
   if (w) *w = r;
@@ -46,6 +44,26 @@ hipError_t pool_event(std::vector<hipEvent_t>* pool, size_t i, hipEvent_t* out) 
     pool->push_back(ev);
   }
   *out = (*pool)[i];
+  return hipSuccess;
+}
+
+hipError_t host_mirror(ipg_graph* g, HostMirror** host, HostMirror** dev) {
+  if (!g->mirror) {
+    void* p = nullptr;
+    void* d = nullptr;
+    hipError_t e = hipHostMalloc(&p, sizeof(HostMirror), hipHostMallocMapped);
+    if (e != hipSuccess) return e;
+    e = hipHostGetDevicePointer(&d, p, 0);
+    if (e != hipSuccess) {
+      (void)hipHostFree(p);
+      return e;
+    }
+    std::memset(p, 0, sizeof(HostMirror));
+    g->mirror = p;
+    g->mirror_dev = d;
+  }
+  *host = static_cast<HostMirror*>(g->mirror);
+  *dev = static_cast<HostMirror*>(g->mirror_dev);
   return hipSuccess;
 }
 

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/ipregel.h"
+#include "blocked_layout.h"
 
 namespace ipg {
 
@@ -89,79 +90,6 @@ struct TilingTables {
   uint32_t nb, nl, nc, ni;
 };
 
-// Destination-blocked, source-sorted copy of the in-edges for PageRank's
-// blocked pull (IPG_GRAPH_BLOCKED).  The destinations are cut into blocks:
-// runs of consecutive rows, at most kBlkRows of them (one workgroup's LDS
-// of FP64 partial sums), closed early once they hold kBlkEdgeFactor / S of
-// the edges, so that the rows with many in-edges form narrow blocks.  Each
-// block's in-edges are stored sorted by source (ties by destination), one
-// 32-bit word per edge: the source's offset within its window of
-// 2^kBlkWinBits sources in the high half, the destination's row within the
-// block in the low half.  The edges are cut into chunks of at most kBlkChunk
-// edges that never straddle a window (so a wavefront's window base is
-// uniform), and each block's chunks into slices, about one per CU.  A block
-// with one slice is finished by that slice's workgroup; the slices of a
-// larger block store partial sums that a second launch adds in slice order.
-constexpr uint32_t kBlkRows = 20224;
-constexpr uint32_t kBlkWinBits = 16;
-constexpr uint32_t kBlkChunk = 256;
-constexpr uint32_t kBlkSlices = 256;
-constexpr uint64_t kBlkMinSliceEdges = 65536;
-constexpr uint64_t kBlkEdgeFactor = 8;
-// Slice balancing: a 128-byte outbox line a chunk touches costs about as
-// much as this many edges (fitted to measured slice times on MI355X).
-constexpr uint64_t kBlkLineCost = 6;
-static_assert(kBlkRows <= (1u << 16), "row within a block fits 16 bits");
-
-struct BlkChunk {
-  uint64_t e0;     // first edge
-  uint32_t wbase;  // first source of the chunk's window
-  uint32_t n;      // edges (1 .. kBlkChunk)
-};
-struct BlkSlice {
-  uint32_t row0, rows;  // the block's rows [row0, row0 + rows)
-  uint32_t c0, c1;      // chunks [c0, c1)
-  uint64_t poff;        // partial sums at partial + poff (rows doubles), ~0 when the slice is the block's only one
-};
-// 64 rows of a block with more than one slice, for the finish launch.
-struct BlkGroup {
-  uint32_t row0;    // first row of the group
-  uint32_t nrows;   // rows in the group (1 .. 64)
-  uint32_t k;       // the block's slices
-  uint32_t stride;  // the block's rows: slice j's partial of row row0 + i is at partial[poff + j * stride + i]
-  uint64_t poff;
-};
-constexpr uint64_t kNoPartial = ~0ull;
-
-// Target number of slices: about one per CU, none under kBlkMinSliceEdges edges.
-inline uint32_t blk_target_slices(uint64_t e) {
-  const uint64_t s = (e + kBlkMinSliceEdges - 1) / kBlkMinSliceEdges;
-  return static_cast<uint32_t>(s < 1 ? 1 : (s > kBlkSlices ? kBlkSlices : s));
-}
-// Edges at which a block closes.
-inline uint64_t blk_edge_target(uint64_t e) {
-  const uint64_t t = kBlkEdgeFactor * e / blk_target_slices(e);
-  return t < 1 ? 1 : t;
-}
-inline uint64_t blk_windows(uint32_t n) { return (static_cast<uint64_t>(n) + (1u << kBlkWinBits) - 1) >> kBlkWinBits; }
-// Blocks: one closed by the row cap takes kBlkRows rows; two consecutive
-// blocks closed by the edge target hold more than the target together.
-inline uint64_t blk_blocks_cap(uint32_t n, uint64_t e) {
-  const uint64_t by_rows = n / kBlkRows + 1, by_edges = 2 * e / blk_edge_target(e) + 2;
-  return by_rows + by_edges;
-}
-// Chunks: at most one partial chunk per non-empty (block, window) segment.
-inline uint64_t blk_chunks_cap(uint32_t n, uint64_t e) {
-  const uint64_t segs = blk_blocks_cap(n, e) * blk_windows(n);
-  return e / kBlkChunk + (segs < e ? segs : e) + 1;
-}
-// Partial sums: the blocks with several slices hold at most S slices of at
-// most kBlkRows rows.
-inline uint64_t blk_partial_cap(uint64_t e) { return static_cast<uint64_t>(blk_target_slices(e)) * kBlkRows; }
-
-// Finish groups: a multi-slice block of R rows has ceil(R / 64) of them.
-inline uint64_t blk_groups_cap(uint32_t n, uint64_t e) { return n / 64 + blk_blocks_cap(n, e) + 1; }
-
 struct BlockedTables {
   uint32_t* edges;    // [e] packed edges (see above)
   BlkChunk* chunks;
@@ -239,6 +167,8 @@ struct ipg_graph {
   // HIP events reused by every run's timing (created on first use)
   std::vector<hipEvent_t> events;
   int wall_khz;  // device wall-clock rate, queried on first use (0 until then)
+  void* mirror;      // pinned host block the decide kernels write (created on first use)
+  void* mirror_dev;  // its device address
 };
 
 namespace ipg {

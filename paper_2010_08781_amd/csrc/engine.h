@@ -34,7 +34,7 @@ struct Decision {
   int32_t mode;   // IPG_MODE_PUSH / IPG_MODE_PULL from the selector, 0 if none ran
   double margin;  // predicted log2 time of push minus pull
   unsigned long long active;  // summed `active` counters (batched SSSP)
-  unsigned long long pad;
+  unsigned long long list_len;  // next-frontier list length left by a push (when the decide was given it)
 };
 static_assert(sizeof(Decision) == 64, "one 64-byte record");
 
@@ -64,10 +64,27 @@ struct DevRec {
 };
 constexpr uint32_t kDevRec = 256;  // ring of records; a chunk of supersteps never exceeds it
 
+// Pinned host memory that the decide kernels write directly, so that a
+// readback is one stream synchronisation and no copy: the device-driven
+// loop's control block as its last decide left it and its trace ring, and
+// the host-driven loops' end-of-superstep summary.  One per graph handle,
+// created on first use and freed with the handle (runs on one handle are
+// serial: each synchronises its stream before returning).
+struct HostMirror {
+  DevCtl ctl;
+  Decision decision;
+  DevRec rec[kDevRec];
+};
+// The block as the host reads it (*host) and as kernels address it (*dev).
+hipError_t host_mirror(ipg_graph* g, HostMirror** host, HostMirror** dev);
+
 // Sum the counter slots `c` of a superstep into *out (one wavefront) and,
 // with a selector, choose the exchange of the next superstep.
+// With `lc` / `hc` (a push superstep's list length and hub count) it also
+// reports the list length and clears both for their reuse two supersteps
+// later.
 hipError_t launch_decide(const CtrSlot* c, uint32_t next_superstep, uint64_t e, const double* sel, Decision* out,
-                         hipStream_t s);
+                         uint32_t* lc, uint32_t* hc, hipStream_t s);
 
 // Senders with at least kHubDeg out-edges are not expanded by their own
 // workgroup in a push superstep: they go to a hub list (up to kHubCap per
@@ -100,9 +117,7 @@ struct RunWs {
   uint32_t* gate;       // [1] 1 when that superstep's senders are few enough to gate the gathers
   uint32_t* list_ctr;   // [4] next-frontier list length (push form) at s & 1, hub count at 2 + (s & 1)
   Hub* hubs;            // [kHubCap] hub senders of a push superstep
-  struct Decision* decision;  // end-of-superstep summary read by the host
   DevCtl* ctl;          // device-driven loop state
-  DevRec* rec;          // [kDevRec] device-driven loop trace ring
   // both
   CtrSlot* ctr;         // [2][kCtrSlots] per-superstep counters (set s & 1)
 };

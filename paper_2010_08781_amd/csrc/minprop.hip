@@ -42,10 +42,12 @@ enum : int {
 
 // value = id (CC) or 0 at the source / INF elsewhere (SSSP).  With `pull_s0`
 // superstep 0 is exchanged by pull: the senders' broadcast values are written
-// to the outbox (INF for the others) and the senders are counted.
+// to the outbox (INF for the others) and the senders are counted.  With a
+// control block (device-driven loop) its exchange decides instead.
 __global__ __launch_bounds__(kBlock) void minprop_init_kernel(uint32_t n, int app, uint32_t source, uint32_t* value,
                                                               const uint32_t* outdeg, int pull_s0, uint32_t* outbox,
-                                                              CtrSlot* ctr) {
+                                                              CtrSlot* ctr, const DevCtl* ctl) {
+  if (ctl) pull_s0 = ctl->mode == IPG_MODE_PULL;  // uniform over the grid
   uint64_t senders = 0, messages = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
@@ -134,8 +136,10 @@ __device__ __forceinline__ void push_edge(const MinPushArgs& a, uint64_t e, uint
 }
 
 // Active set of a device-driven superstep s >= 1: the list left by a push
-// superstep, or the non-empty mailboxes.
-__device__ __forceinline__ Active device_active(const DevCtl& c, const uint32_t* list, uint32_t n) {
+// superstep, or the non-empty mailboxes.  (Superstep 0 keeps the launch's
+// own: every vertex for CC, the source for SSSP.)
+__device__ __forceinline__ Active device_active(const DevCtl& c, const Active& own, const uint32_t* list, uint32_t n) {
+  if (c.step == 0) return own;
   Active act;
   act.phase = c.list_ok ? kStepList : kStepDense;
   act.count = c.list_ok ? static_cast<uint32_t>(c.count) : n;
@@ -155,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void minprop_push_kernel(MinPushArgs a) {
   if (a.ctl) {
     const DevCtl c = *a.ctl;
     if (c.halted || c.mode != IPG_MODE_PUSH) return;  // uniform over the grid
-    act = device_active(c, a.act.list, a.n);
+    act = device_active(c, a.act, a.act.list, a.n);
   }
   clear_slots(a.ctr_clear);
   uint64_t senders = 0, messages = 0, next_count = 0, next_deg = 0;
@@ -540,7 +544,7 @@ __global__ __launch_bounds__(kBlock) void minprop_blocked_finish_kernel(MinBlkAr
 // slot t) and, when a selector is given and work is pending, choose the
 // exchange of the next superstep with the network.
 __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_t next_superstep, uint64_t e,
-                                                       const double* sel, Decision* out) {
+                                                       const double* sel, Decision* out, uint32_t* lc, uint32_t* hc) {
   static_assert(kCtrSlots == kWave, "one slot per lane");
   const CtrSlot& x = c[threadIdx.x];
   const uint64_t nc = wave_sum_u64(x.next_count);
@@ -562,20 +566,37 @@ __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_
     d.mode = m;
     d.margin = margin;
     d.active = ac;
-    d.pad = 0;
+    d.list_len = 0;
+    if (lc) {
+      d.list_len = *lc;
+      *lc = 0;  // the counters are reused two supersteps later
+      *hc = 0;
+    }
     *out = d;
   }
 }
 
-// Start of a device-driven run: the state before superstep 0.
-__global__ void dd_start_kernel(DevCtl* ctl, int mode, uint64_t count, uint64_t degsum, uint32_t cap) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+// Start of a device-driven run: the state before superstep 0 -- its active
+// set (every vertex for CC, the source for SSSP), their out-degree sum and
+// its exchange (forced, the selector, or the fixed heuristic), decided here
+// so that the host reads nothing before it enqueues.  One wavefront.
+__global__ __launch_bounds__(kWave) void dd_start_kernel(DevCtl* ctl, int app, uint32_t source, const uint64_t* off,
+                                                         uint32_t n, uint64_t e, const double* sel, int forced,
+                                                         uint32_t push_div, uint32_t cap) {
+  const unsigned long long now = static_cast<unsigned long long>(wall_clock64());
+  const bool cc = app == IPG_APP_CC_HASHMIN;
+  const uint64_t count = cc ? n : 1;
+  const uint64_t degsum = cc ? e : off[static_cast<uint64_t>(source) + 1] - off[source];
+  int mode = forced;
+  if (!mode && sel) sel_predict_mode_wave(sel, count, degsum, 0, e, &mode);  // uniform: the whole wavefront infers
+  if (!mode) mode = heuristic_pick(e, count, degsum, push_div);
+  if (threadIdx.x == 0) {
     DevCtl c{};
     c.mode = mode;
     c.cap = cap;
     c.count = count;
     c.degsum = degsum;
-    c.t_last = static_cast<unsigned long long>(wall_clock64());
+    c.t_last = now;
     *ctl = c;
   }
 }
@@ -588,7 +609,7 @@ __global__ void dd_start_kernel(DevCtl* ctl, int mode, uint64_t count, uint64_t 
 __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint32_t* lc, uint32_t* hc, uint64_t e,
                                                           uint32_t n, const double* sel, int forced,
                                                           uint64_t list_limit, uint32_t push_div, DevCtl* ctl,
-                                                          DevRec* rec) {
+                                                          HostMirror* hm) {
   static_assert(kCtrSlots == kWave, "one slot per lane");
   const unsigned long long now = static_cast<unsigned long long>(wall_clock64());
   const DevCtl k = *ctl;
@@ -613,7 +634,7 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
   r.ticks = now - k.t_last;
   r.mode = static_cast<uint32_t>(k.mode);
   r.pad = 0;
-  rec[s % kDevRec] = r;
+  hm->rec[s % kDevRec] = r;
   const uint32_t lcount = *lc;
   *lc = 0;  // the counters are reused two supersteps later
   *hc = 0;
@@ -643,13 +664,14 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
     nk.mode = heuristic_pick(e, nc, nd, push_div);
   }
   *ctl = nk;
+  hm->ctl = nk;
 }
 
 // ------------------------------------------------------------------ host --
 
 hipError_t launch_decide(const CtrSlot* c, uint32_t next_superstep, uint64_t e, const double* sel, Decision* out,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kWave), 0, s, c, next_superstep, e, sel, out);
+                         uint32_t* lc, uint32_t* hc, hipStream_t s) {
+  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kWave), 0, s, c, next_superstep, e, sel, out, lc, hc);
   return hipGetLastError();
 }
 
@@ -721,7 +743,7 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
   const bool device = ctl != nullptr;
   if (step == 0) {
     hipLaunchKernelGGL(minprop_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, static_cast<int>(app), source,
-                       w.value_u32, g->t.outdeg, mode == IPG_MODE_PULL ? 1 : 0, w.outbox, b.c);
+                       w.value_u32, g->t.outdeg, mode == IPG_MODE_PULL ? 1 : 0, w.outbox, b.c, ctl);
     IPG_HIP(hipGetLastError());
   }
   if (device || mode == IPG_MODE_PUSH) {
@@ -818,8 +840,17 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
 }
 
 // State before superstep 0 shared by both loops: mailboxes empty, counters
-// zero, and the superstep-0 active set (every vertex for CC, the source for
-// SSSP) with its out-degree sum.
+// zero.
+static ipg_status clear_minprop(const ipg_graph* g, const RunWs& w, hipStream_t s) {
+  IPG_HIP(fill_u32(w.mail_a, g->n, kInf, s));
+  IPG_HIP(fill_u32(w.mail_b, g->n, kInf, s));
+  IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.ctr), 2 * kCtrSlots * sizeof(CtrSlot) / 4, 0, s));
+  IPG_HIP(fill_u32(w.list_ctr, 4, 0, s));
+  return IPG_OK;
+}
+
+// The host loop's superstep 0: its active set (every vertex for CC, the
+// source for SSSP), their out-degree sum and the selector's choice.
 struct MinStart {
   uint64_t count, degsum;
   int sel_mode;  // the selector's choice for superstep 0, 0 if none
@@ -835,10 +866,8 @@ static ipg_status start_minprop(ipg_graph* g, ipg_app app, const ipg_run_opts& o
     IPG_HIP(hipStreamSynchronize(s));
     src_deg = h[1] - h[0];
   }
-  IPG_HIP(fill_u32(w.mail_a, n, kInf, s));
-  IPG_HIP(fill_u32(w.mail_b, n, kInf, s));
-  IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.ctr), 2 * kCtrSlots * sizeof(CtrSlot) / 4, 0, s));
-  IPG_HIP(fill_u32(w.list_ctr, 4, 0, s));
+  const ipg_status rc = clear_minprop(g, w, s);
+  if (rc != IPG_OK) return rc;
   out->count = app == IPG_APP_CC_HASHMIN ? n : 1;
   out->degsum = app == IPG_APP_CC_HASHMIN ? e : src_deg;
   out->sel_mode = 0;
@@ -862,37 +891,35 @@ static Active step0_active(ipg_app app, uint32_t n, uint32_t source) {
 
 // Device-driven loop (IPG_RUN_PERSISTENT): the host enqueues supersteps in
 // chunks of growing length without reading anything back; the control
-// block decides halt, active set and exchange on the device, the kernels
-// of the supersteps after the halt return at once, and the host reads the
-// control block and the chunk's trace records once per chunk.
+// block decides halt, active set and exchange on the device (superstep 0's
+// too), the kernels of the supersteps after the halt return at once, and
+// the decide kernels copy the control block and the trace records into
+// pinned host memory, which the host reads after one synchronisation per
+// chunk.
 static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_opts& o, const RunWs& w,
                                      hipStream_t s, StepTimer& tm, ipg_run_stats* st) {
   const uint32_t n = g->n;
   const uint64_t e = g->e;
   const Tune tn = resolve_tuning(o.tuning);
-  MinStart m0;
-  ipg_status rc = start_minprop(g, app, o, w, s, &m0);
+  HostMirror *hm = nullptr, *hm_dev = nullptr;
+  IPG_HIP(host_mirror(g, &hm, &hm_dev));
+  ipg_status rc = clear_minprop(g, w, s);
   if (rc != IPG_OK) return rc;
   if (!g->wall_khz) IPG_HIP(hipDeviceGetAttribute(&g->wall_khz, hipDeviceAttributeWallClockRate, g->device));
   const double us_per_tick = g->wall_khz > 0 ? 1e3 / g->wall_khz : 0.0;
   const double* sel = o.mode == IPG_MODE_AUTO ? o.selector : nullptr;
   const int forced = o.mode == IPG_MODE_AUTO ? 0 : static_cast<int>(o.mode);
-  ipg_mode mode0 = o.mode;
-  if (mode0 == IPG_MODE_AUTO)
-    mode0 = m0.sel_mode ? static_cast<ipg_mode>(m0.sel_mode)
-                        : static_cast<ipg_mode>(heuristic_pick(e, m0.count, m0.degsum, tn.push_div));
   IPG_HIP(tm.start(s));
-  hipLaunchKernelGGL(dd_start_kernel, dim3(1), dim3(1), 0, s, w.ctl, static_cast<int>(mode0), m0.count, m0.degsum,
-                     cap);
+  hipLaunchKernelGGL(dd_start_kernel, dim3(1), dim3(kWave), 0, s, w.ctl, static_cast<int>(app), o.source, g->csr_off, n,
+                     e, sel, forced, tn.push_div, cap);
   IPG_HIP(hipGetLastError());
-  rc = enqueue_step(g, app, o.source, 0, mode0, step0_active(app, n, o.source), m0.degsum, w, nullptr, tn, s);
+  rc = enqueue_step(g, app, o.source, 0, IPG_MODE_AUTO, step0_active(app, n, o.source), 0, w, w.ctl, tn, s);
   if (rc != IPG_OK) return rc;
   uint32_t enqueued = 0;  // supersteps whose launches are in the stream, minus one
   uint32_t recorded = 0;  // supersteps whose records were read
   uint32_t chunk = 2;  // supersteps enqueued per readback: 2, 4, 8, ... 64
   DevCtl h{};
   uint64_t tot_msgs = 0, tot_exam = 0;
-  std::vector<DevRec> recs(kDevRec);
   for (;;) {
     for (uint32_t k = 0; k < chunk; ++k) {
       const uint32_t step = enqueued + k;
@@ -903,20 +930,14 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
       }
       const StepBufs b = bufs_for(w, step);
       hipLaunchKernelGGL(dd_decide_kernel, dim3(1), dim3(kWave), 0, s, b.c, b.lc, b.hc, e, n, sel, forced,
-                         list_limit(n, tn.list_div), tn.push_div, w.ctl, w.rec);
+                         list_limit(n, tn.list_div), tn.push_div, w.ctl, hm_dev);
       IPG_HIP(hipGetLastError());
     }
     enqueued += chunk;
-    IPG_HIP(hipMemcpyAsync(&h, w.ctl, sizeof(h), hipMemcpyDeviceToHost, s));
-    {  // only the ring entries of the supersteps that may have run since the last readback
-      const uint32_t a = recorded % kDevRec, cnt = enqueued - recorded;
-      const uint32_t first = std::min(cnt, kDevRec - a);
-      IPG_HIP(hipMemcpyAsync(recs.data() + a, w.rec + a, first * sizeof(DevRec), hipMemcpyDeviceToHost, s));
-      if (cnt > first) IPG_HIP(hipMemcpyAsync(recs.data(), w.rec, (cnt - first) * sizeof(DevRec), hipMemcpyDeviceToHost, s));
-    }
     IPG_HIP(hipStreamSynchronize(s));
+    h = hm->ctl;  // as the chunk's last decide (before or at the halt) left it
     for (; recorded < h.step; ++recorded) {
-      const DevRec& r = recs[recorded % kDevRec];
+      const DevRec r = hm->rec[recorded % kDevRec];
       if (st && recorded < st->trace_cap) {
         if (st->active) st->active[recorded] = r.active;
         if (st->senders) st->senders[recorded] = r.senders;
@@ -951,6 +972,8 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
   const uint32_t n = g->n;
   const uint64_t e = g->e;
   const Tune tn = resolve_tuning(o.tuning);
+  HostMirror *hm = nullptr, *hm_dev = nullptr;
+  IPG_HIP(host_mirror(g, &hm, &hm_dev));
   MinStart m0;
   ipg_status status = start_minprop(g, app, o, w, s, &m0);
   if (status != IPG_OK) return status;
@@ -978,14 +1001,10 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
     if (status != IPG_OK) return status;
     IPG_HIP(tm.step(s, step));
     const double* sel = o.mode == IPG_MODE_AUTO ? o.selector : nullptr;
-    IPG_HIP(launch_decide(b.c, step + 1, e, sel, w.decision, s));
-    uint32_t lcount = 0;
-    Decision h;
-    IPG_HIP(hipMemcpyAsync(&h, w.decision, sizeof(h), hipMemcpyDeviceToHost, s));
-    IPG_HIP(hipMemcpyAsync(&lcount, b.lc, sizeof(lcount), hipMemcpyDeviceToHost, s));
-    IPG_HIP(fill_u32(b.lc, 1, 0, s));  // reused two supersteps later
-    IPG_HIP(fill_u32(b.hc, 1, 0, s));
+    IPG_HIP(launch_decide(b.c, step + 1, e, sel, &hm_dev->decision, b.lc, b.hc, s));
     IPG_HIP(hipStreamSynchronize(s));
+    const Decision h = hm->decision;
+    const uint64_t lcount = h.list_len;
     const uint64_t examined = mode == IPG_MODE_PUSH ? h.messages : e;
     if (st && step < st->trace_cap) {
       if (st->active) st->active[step] = step == 0 ? n : count;

@@ -579,7 +579,6 @@ struct MsWs {
   uint32_t* nzb;      // [kMsHist][words] union-frontier bitmap of each level slot
   uint32_t* touched;  // [words] push: recipients of the superstep
   CtrSlot* ctr;       // [2][kCtrSlots]
-  Decision* decision;
   MsCtl* ctl;         // device-driven form
   DevRec* rec;        // [kMsRec] its trace records
 };
@@ -600,7 +599,6 @@ static size_t carve_ms(Carver& c, uint32_t n, uint64_t e, MsWs* out) {
   w.ctl = c.take<MsCtl>(1);
   w.rec = c.take<DevRec>(kMsRec);
   w.ctr = c.take<CtrSlot>(2 * kCtrSlots);
-  w.decision = c.take<Decision>(1);
   if (out) *out = w;
   return align_up(c.used, 256);
 }
@@ -610,6 +608,8 @@ static ipg_status run_msbfs(ipg_graph* g, const uint32_t* sources, uint32_t q, u
   const uint32_t n = g->n;
   const uint64_t e = g->e;
   const Tune tn = resolve_tuning(o.tuning);
+  HostMirror *hm = nullptr, *hm_dev = nullptr;
+  IPG_HIP(host_mirror(g, &hm, &hm_dev));
   const size_t rowset = (size_t)n * kMsWords;  // u64 per level buffer
   const size_t words = ms_words(n);
   auto slot_buf = [&](uint32_t level) { return w.hist + (size_t)(level % kMsHist) * rowset; };
@@ -711,10 +711,9 @@ static ipg_status run_msbfs(ipg_graph* g, const uint32_t* sources, uint32_t q, u
     }
     used[slot] = true;
     IPG_HIP(tm.step(s, step));
-    IPG_HIP(launch_decide(c, step + 1, e, nullptr, w.decision, s));
-    Decision h;
-    IPG_HIP(hipMemcpyAsync(&h, w.decision, sizeof(h), hipMemcpyDeviceToHost, s));
+    IPG_HIP(launch_decide(c, step + 1, e, nullptr, &hm_dev->decision, nullptr, nullptr, s));
     IPG_HIP(hipStreamSynchronize(s));
+    const Decision h = hm->decision;
     const uint64_t active = step == 0 ? (uint64_t)q * n : h.active;
     if (st && step < st->trace_cap) {
       if (st->active) st->active[step] = active;

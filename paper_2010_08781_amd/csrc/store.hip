@@ -287,10 +287,8 @@ static ipg_status build_hot_store(const uint64_t* csc_off, const int32_t* csc_sr
   return build_tiling(t->off_hot, n, e, &t->pull_hot, t->flags + kNumFlags, s);
 }
 
-// The blocked in-edges of a CSC (validated): two stable counting sorts on
-// the host -- the edges by source (each source's edges in destination
-// order), then by destination block -- so that every block holds its edges
-// sorted by source; then the chunks, the slices and the finish list.
+// The blocked in-edges of a CSC (validated or not): built on the host
+// (blocked_layout.h) and copied to the device tables.
 static ipg_status build_blocked(const uint64_t* csc_off, const int32_t* csc_src, uint32_t n, uint64_t e,
                                 BlockedTables* b, hipStream_t s) {
   std::vector<uint64_t> off((size_t)n + 1);
@@ -298,190 +296,20 @@ static ipg_status build_blocked(const uint64_t* csc_off, const int32_t* csc_src,
   IPG_HIP(hipMemcpyAsync(off.data(), csc_off, off.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   if (e) IPG_HIP(hipMemcpyAsync(src.data(), csc_src, e * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   IPG_HIP(hipStreamSynchronize(s));
-  // the host loops below index with these: check them here even without IPG_GRAPH_VALIDATE
-  if (off[0] != 0 || off[n] != e) return fail(IPG_EBADGRAPH, "offsets: off[0] != 0 or off[N] != E");
-  for (uint32_t v = 0; v < n; ++v)
-    if (off[v] > off[(size_t)v + 1]) return fail(IPG_EBADGRAPH, "offsets decreasing");
-  for (uint64_t i = 0; i < e; ++i)
-    if (src[i] < 0 || static_cast<uint32_t>(src[i]) >= n) return fail(IPG_EBADGRAPH, "CSC source id outside [0, N)");
-  // blocks: runs of consecutive rows, closed before the row that would take
-  // them past the edge target (a row above it alone forms a block) or at
-  // kBlkRows rows
-  const uint64_t target = blk_edge_target(e);
-  std::vector<uint32_t> row0{0};
-  std::vector<uint32_t> blk_of(n);
-  {
-    uint64_t acc = 0;
-    for (uint32_t v = 0; v < n; ++v) {
-      const uint64_t d = off[(size_t)v + 1] - off[v];
-      if (v > row0.back() && (acc + d > target || v - row0.back() == kBlkRows)) {
-        row0.push_back(v);
-        acc = 0;
-      }
-      acc += d;
-      blk_of[v] = static_cast<uint32_t>(row0.size() - 1);
-    }
-    row0.push_back(n);
-  }
-  const uint64_t nblk = row0.size() - 1, nwin = blk_windows(n);
-  if (nblk > blk_blocks_cap(n, e)) return fail(IPG_EBADGRAPH, "blocked block table overflow");
-  // by source: dst_of[k] is the destination of the k-th edge in source order
-  std::vector<uint64_t> sstart((size_t)n + 1, 0);
-  for (uint64_t i = 0; i < e; ++i) ++sstart[(size_t)src[i] + 1];
-  for (uint32_t u = 0; u < n; ++u) sstart[(size_t)u + 1] += sstart[u];
-  std::vector<uint32_t> dst_of(e);
-  {
-    std::vector<uint64_t> cur(sstart.begin(), sstart.end() - 1);
-    for (uint32_t v = 0; v < n; ++v)
-      for (uint64_t i = off[v]; i < off[(size_t)v + 1]; ++i) dst_of[cur[src[i]]++] = v;
-  }
+  BlockedLayout L;
+  if (const char* msg = blocked_layout(n, e, off.data(), src.data(), &L)) return fail(IPG_EBADGRAPH, msg);
   std::vector<int32_t>().swap(src);
-  // by block, counting the edges of every (block, window) segment
-  std::vector<uint64_t> bstart(nblk + 1, 0);
-  for (uint32_t v = 0; v < n; ++v) bstart[(size_t)blk_of[v] + 1] += off[(size_t)v + 1] - off[v];
-  for (uint64_t k = 0; k < nblk; ++k) bstart[k + 1] += bstart[k];
-  std::vector<uint64_t> seg(nblk * nwin, 0);
-  std::vector<uint32_t> packed(e);
-  {
-    std::vector<uint64_t> cur(bstart.begin(), bstart.end() - 1);
-    for (uint32_t u = 0; u < n; ++u) {
-      const uint64_t w = u >> kBlkWinBits;
-      const uint32_t hi = (u & ((1u << kBlkWinBits) - 1)) << 16;
-      for (uint64_t k = sstart[u]; k < sstart[(size_t)u + 1]; ++k) {
-        const uint32_t v = dst_of[k];
-        const uint64_t blk = blk_of[v];
-        packed[cur[blk]++] = hi | (v - row0[blk]);
-        ++seg[blk * nwin + w];
-      }
-    }
-  }
-  std::vector<uint32_t>().swap(dst_of);
-  // chunks: every segment cut into pieces of at most kBlkChunk edges; the
-  // cost of a chunk is its edges plus kBlkLineCost per outbox cache line its
-  // sources touch (runs of equal source >> 4: 16 FP64 outboxes per 128-byte
-  // line; the sources are sorted)
-  std::vector<BlkChunk> chunks;
-  std::vector<uint64_t> cost;
-  std::vector<uint64_t> cfirst(nblk + 1, 0);
-  for (uint64_t blk = 0; blk < nblk; ++blk) {
-    cfirst[blk] = chunks.size();
-    uint64_t at = bstart[blk];
-    for (uint64_t w = 0; w < nwin; ++w) {
-      for (uint64_t left = seg[blk * nwin + w]; left > 0;) {
-        const uint32_t m = static_cast<uint32_t>(left < kBlkChunk ? left : kBlkChunk);
-        chunks.push_back(BlkChunk{at, static_cast<uint32_t>(w << kBlkWinBits), m});
-        uint64_t lines = 1;
-        for (uint64_t i = at + 1; i < at + m; ++i) lines += (packed[i] >> 20) != (packed[i - 1] >> 20);
-        cost.push_back(m + kBlkLineCost * lines);
-        at += m;
-        left -= m;
-      }
-    }
-  }
-  cfirst[nblk] = chunks.size();
-  if (chunks.size() > blk_chunks_cap(n, e)) return fail(IPG_EBADGRAPH, "blocked chunk table overflow");
-  // slices: with fewer blocks than S (about one slice per CU, and only one
-  // workgroup fits a CU's LDS), at most S slices in one even wave: block b
-  // gets K_b = ceil(C_b / L) slices (at least one, at most one per chunk),
-  // C_b its chunks' cost, for the smallest limit L with sum K_b <= S, which
-  // minimises the largest slice; else one slice per block.  A block's
-  // slices hold about equal costs.
-  std::vector<uint64_t> cb(nblk, 0);
-  uint64_t ctotal = 0;
-  for (uint64_t blk = 0; blk < nblk; ++blk) {
-    for (uint64_t c = cfirst[blk]; c < cfirst[blk + 1]; ++c) cb[blk] += cost[c];
-    ctotal += cb[blk];
-  }
-  const uint64_t S = blk_target_slices(e);
-  std::vector<uint64_t> kb(nblk, 1);
-  uint64_t nonempty = 0;
-  for (uint64_t blk = 0; blk < nblk; ++blk) nonempty += cfirst[blk + 1] != cfirst[blk];
-  if (nonempty < S && e) {
-    auto slices_for = [&](uint64_t L, std::vector<uint64_t>* out) {
-      uint64_t total = 0;
-      for (uint64_t blk = 0; blk < nblk; ++blk) {
-        const uint64_t nc = cfirst[blk + 1] - cfirst[blk];
-        const uint64_t k = std::max<uint64_t>(1, std::min((cb[blk] + L - 1) / L, std::max<uint64_t>(nc, 1)));
-        if (out) (*out)[blk] = k;
-        if (nc) total += k;  // a block without edges only writes 0.15/N: not counted
-      }
-      return total;
-    };
-    uint64_t lo = 1, hi = ctotal;  // slices_for(ctotal) == nonempty <= S
-    while (lo < hi) {
-      const uint64_t mid = lo + (hi - lo) / 2;
-      if (slices_for(mid, nullptr) <= S) hi = mid;
-      else lo = mid + 1;
-    }
-    slices_for(lo, &kb);
-  }
-  std::vector<BlkSlice> slices;
-  std::vector<BlkGroup> groups;
-  uint64_t poff = 0;
-  for (uint64_t blk = 0; blk < nblk; ++blk) {
-    const uint64_t K = kb[blk];
-    const uint32_t r0 = row0[blk], rows = row0[blk + 1] - row0[blk];
-    if (cfirst[blk + 1] == cfirst[blk]) {  // no in-edges: the finish launch writes its rows (0.15/N)
-      for (uint32_t g = 0; g < rows; g += 64) groups.push_back(BlkGroup{r0 + g, std::min<uint32_t>(64, rows - g), 0, rows, 0});
-      continue;
-    }
-    if (K == 1) {
-      slices.push_back(BlkSlice{r0, rows, static_cast<uint32_t>(cfirst[blk]), static_cast<uint32_t>(cfirst[blk + 1]),
-                                kNoPartial});
-      continue;
-    }
-    for (uint32_t g = 0; g < rows; g += 64)
-      groups.push_back(BlkGroup{r0 + g, std::min<uint32_t>(64, rows - g), static_cast<uint32_t>(K), rows, poff + g});
-    uint64_t c = cfirst[blk], done = 0;
-    for (uint64_t j = 0; j < K; ++j) {
-      const uint64_t c0 = c, goal = cb[blk] * (j + 1) / K;
-      const uint64_t cmax = cfirst[blk + 1] - (K - 1 - j);  // leave a chunk for every later slice
-      do {
-        done += cost[c];
-        ++c;
-      } while (c < cmax && done < goal);
-      if (j == K - 1) c = cfirst[blk + 1];
-      slices.push_back(BlkSlice{r0, rows, static_cast<uint32_t>(c0), static_cast<uint32_t>(c), poff});
-      poff += rows;
-    }
-  }
-  if (poff > blk_partial_cap(e) || slices.size() > blk_blocks_cap(n, e) + blk_target_slices(e) ||
-      groups.size() > blk_groups_cap(n, e))
-    return fail(IPG_EBADGRAPH, "blocked slice table overflow");
-  // XCD-aware launch order: workgroup i of a launch runs on XCD i mod 8, and
-  // a slice's sources are a contiguous range (its chunks are sorted by
-  // source).  The slices are sorted by their first source and XCD x takes
-  // the x-th eighth of them, so that each XCD's L2 caches about an eighth
-  // of the outbox array instead of all of it.
-  {
-    constexpr size_t kXcds = 8;
-    const size_t ns = slices.size(), q = (ns + kXcds - 1) / kXcds;
-    auto first_src = [&](const BlkSlice& sl) -> uint64_t {
-      const BlkChunk& ch = chunks[sl.c0];
-      return static_cast<uint64_t>(ch.wbase) + (packed[ch.e0] >> 16);
-    };
-    std::vector<size_t> idx(ns);
-    for (size_t i = 0; i < ns; ++i) idx[i] = i;
-    std::stable_sort(idx.begin(), idx.end(),
-                     [&](size_t x, size_t y) { return first_src(slices[x]) < first_src(slices[y]); });
-    std::vector<BlkSlice> dealt;
-    dealt.reserve(ns);
-    for (size_t j = 0; j < q; ++j)
-      for (size_t x = 0; x < kXcds; ++x)
-        if (x * q + j < ns) dealt.push_back(slices[idx[x * q + j]]);
-    slices.swap(dealt);
-  }
-  if (e) IPG_HIP(hipMemcpyAsync(b->edges, packed.data(), e * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-  if (!chunks.empty())
-    IPG_HIP(hipMemcpyAsync(b->chunks, chunks.data(), chunks.size() * sizeof(BlkChunk), hipMemcpyHostToDevice, s));
-  if (!slices.empty())
-    IPG_HIP(hipMemcpyAsync(b->slices, slices.data(), slices.size() * sizeof(BlkSlice), hipMemcpyHostToDevice, s));
-  if (!groups.empty())
-    IPG_HIP(hipMemcpyAsync(b->groups, groups.data(), groups.size() * sizeof(BlkGroup), hipMemcpyHostToDevice, s));
+  if (e) IPG_HIP(hipMemcpyAsync(b->edges, L.packed.data(), e * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  if (!L.chunks.empty())
+    IPG_HIP(hipMemcpyAsync(b->chunks, L.chunks.data(), L.chunks.size() * sizeof(BlkChunk), hipMemcpyHostToDevice, s));
+  if (!L.slices.empty())
+    IPG_HIP(hipMemcpyAsync(b->slices, L.slices.data(), L.slices.size() * sizeof(BlkSlice), hipMemcpyHostToDevice, s));
+  if (!L.groups.empty())
+    IPG_HIP(hipMemcpyAsync(b->groups, L.groups.data(), L.groups.size() * sizeof(BlkGroup), hipMemcpyHostToDevice, s));
   IPG_HIP(hipStreamSynchronize(s));
-  b->nchunks = static_cast<uint32_t>(chunks.size());
-  b->nslices = static_cast<uint32_t>(slices.size());
-  b->ngroups = static_cast<uint32_t>(groups.size());
+  b->nchunks = static_cast<uint32_t>(L.chunks.size());
+  b->nslices = static_cast<uint32_t>(L.slices.size());
+  b->ngroups = static_cast<uint32_t>(L.groups.size());
   return IPG_OK;
 }
 
@@ -592,6 +420,7 @@ extern "C" void ipg_graph_destroy(ipg_graph* g) {
   if (g->pr_graph) (void)hipGraphDestroy(g->pr_graph);
   if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
   for (hipEvent_t ev : g->events) (void)hipEventDestroy(ev);
+  if (g->mirror) (void)hipHostFree(g->mirror);
   delete g;
 }
 
