@@ -242,8 +242,10 @@ ipg_status ipg_run(ipg_graph* graph, ipg_app app, ipg_combiner combiner, uint32_
 
 /* Copy the values of the last run on `graph` (double for PageRank, uint32
  * otherwise; N entries) to dst, which is a device pointer when dst_is_device
- * is non-zero, else host memory.  Synchronises the stream.  IPG_EINVAL if no
- * run happened or dst_bytes is too small. */
+ * is non-zero, else host memory.  A host copy synchronises the stream; a
+ * device copy is only enqueued on it (work on other streams must wait for
+ * the stream first).  IPG_EINVAL if no run happened or dst_bytes is too
+ * small. */
 ipg_status ipg_read_values(const ipg_graph* graph, void* dst, size_t dst_bytes, int dst_is_device,
                            void* hip_stream);
 

@@ -413,6 +413,8 @@ class Graph:
         out = torch.empty(self.n, dtype=dt, device=self.device)
         _check(lib().ipg_read_values(self._h, out.data_ptr(), out.numel() * out.element_size(), 1,
                                      _stream_handle(stream)), "ipg_read_values")
+        if stream is not None:  # the copy is enqueued on `stream`: order torch's current stream after it
+            torch.cuda.current_stream().wait_stream(stream)
         return out
 
     def close(self):

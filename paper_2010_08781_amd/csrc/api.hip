@@ -22,13 +22,13 @@ size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w) {
     r.value_u32 = c.take<uint32_t>(nn);
     r.mail_a = c.take<uint32_t>(nn);
     r.mail_b = c.take<uint32_t>(nn);
-    r.fr_a = c.take<uint32_t>(nn);
-    r.fr_b = c.take<uint32_t>(nn);
+    r.fr_a = c.take<uint32_t>(static_cast<size_t>(kCtrSlots) * list_seg(static_cast<uint32_t>(nn)));
+    r.fr_b = c.take<uint32_t>(static_cast<size_t>(kCtrSlots) * list_seg(static_cast<uint32_t>(nn)));
     r.outbox = c.take<uint32_t>(nn);
     r.sent = c.take<uint32_t>(nn / 64 * 2 + 2);
     r.gate = c.take<uint32_t>(1);
-    r.list_ctr = c.take<uint32_t>(4);
-    r.hubs = c.take<Hub>(kHubCap);
+    r.lpre = c.take<uint32_t>(2 * (kCtrSlots + 1));
+    r.pieces = c.take<Piece>(kCtrSlots * piece_seg(e));
     r.ctl = c.take<DevCtl>(1);
   }
   r.ctr = c.take<CtrSlot>(2 * kCtrSlots);
@@ -185,6 +185,6 @@ extern "C" ipg_status ipg_read_values(const ipg_graph* g, void* dst, size_t dst_
   if (dst_bytes < bytes) return fail(IPG_EINVAL, "ipg_read_values: destination needs " + std::to_string(bytes) + " bytes");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   IPG_HIP(hipMemcpyAsync(dst, g->last_values, bytes, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
-  IPG_HIP(hipStreamSynchronize(s));
+  if (!dst_is_device) IPG_HIP(hipStreamSynchronize(s));  // a device copy is ordered on the stream
   return IPG_OK;
 }

@@ -248,7 +248,9 @@ struct alignas(128) CtrSlot {
   unsigned long long messages;  // sum of the senders' out-degrees
   unsigned long long next_deg;  // sum of out-degrees of the next frontier
   unsigned long long active;    // (batched SSSP) query-vertex pairs that received a message
-  unsigned long long pad[11];
+  uint32_t list_len;            // (push) recipients appended to this slot's segment of the next-frontier list
+  uint32_t pieces;              // (push) pieces queued in this slot's segment of the piece queue
+  unsigned long long pad[10];
 };
 static_assert(sizeof(CtrSlot) == 128, "one slot per 128-byte line");
 

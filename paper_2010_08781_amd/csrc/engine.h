@@ -80,21 +80,38 @@ hipError_t host_mirror(ipg_graph* g, HostMirror** host, HostMirror** dev);
 
 // Sum the counter slots `c` of a superstep into *out (one wavefront) and,
 // with a selector, choose the exchange of the next superstep.
-// With `lc` / `hc` (a push superstep's list length and hub count) it also
-// reports the list length and clears both for their reuse two supersteps
-// later.
+// It also reports the length of the next-frontier list a push superstep
+// left in the slots' segments (~0 when a segment overflowed: the list is
+// then incomplete) and, with `lpre_out`, writes the prefix of the
+// segments' lengths that the next superstep's list consumers read.
 hipError_t launch_decide(const CtrSlot* c, uint32_t next_superstep, uint64_t e, const double* sel, Decision* out,
-                         uint32_t* lc, uint32_t* hc, hipStream_t s);
+                         uint32_t lseg, uint32_t* lpre_out, hipStream_t s);
 
-// Senders with at least kHubDeg out-edges are not expanded by their own
-// workgroup in a push superstep: they go to a hub list (up to kHubCap per
-// superstep) whose edges a second launch spreads over the whole grid.
-constexpr uint32_t kHubDeg = 8192;
-constexpr uint32_t kHubCap = 4096;
-struct Hub {
-  unsigned long long beg, end;  // CSR edge range
-  uint32_t msg, pad;            // the value the hub broadcasts
+// Push exchange: a sender with at least kPieceMin out-edges is not expanded
+// by its own workgroup.  Its out-edges are cut into pieces of at most kPiece
+// edges and queued, and a second launch deals the pieces over the whole
+// grid.  (R-MAT's high-degree vertices have low ids: expanded in place, a
+// few workgroups would hold most of a dense superstep's edges.)  The queue,
+// like the next-frontier list, is cut into kCtrSlots segments, one per
+// counter slot, so that a workgroup's appends (one atomic per wavefront)
+// go to its own slot's counter instead of one device-wide address.
+constexpr uint32_t kPieceMin = 128;
+constexpr uint32_t kPiece = 1024;
+struct Piece {
+  unsigned long long beg;  // first CSR edge
+  uint32_t n;              // edges (0 = an unused entry, 1 .. kPiece)
+  uint32_t msg;            // the value the sender broadcasts
 };
+// Segment of the piece queue: a sender with d >= kPieceMin out-edges queues
+// ceil(d / kPiece) <= d / kPiece + d / kPieceMin pieces, so a superstep
+// queues at most E / kPiece + E / kPieceMin; each segment holds its share
+// of that plus slack.  A wavefront that finds its segment full expands its
+// senders in place.
+inline uint64_t piece_seg(uint64_t e) { return (e / kPiece + e / kPieceMin) / kCtrSlots + 64; }
+// Segment of the next-frontier list: its share of N plus slack.  A full
+// segment drops the list for that superstep (the next one sweeps the
+// mailboxes instead).
+inline uint32_t list_seg(uint32_t n) { return n / kCtrSlots + 64; }
 
 // Run workspace, carved from the caller's device buffer.
 struct RunWs {
@@ -110,13 +127,13 @@ struct RunWs {
   uint32_t* value_u32;  // [n] labels or distances
   uint32_t* mail_a;     // [n] one-slot min mailboxes, ping (INF = empty)
   uint32_t* mail_b;     // [n] pong
-  uint32_t* fr_a;       // [n] frontier list, ping
-  uint32_t* fr_b;       // [n] pong
+  uint32_t* fr_a;       // [kCtrSlots * list_seg(n)] frontier list in segments, ping
+  uint32_t* fr_b;       // pong
   uint32_t* outbox;     // [n] one-slot outbox of the pull form: the broadcast value, INF if none
   uint32_t* sent;       // [n/64*2 + 2] bitmap of the vertices that broadcast in a pull superstep
   uint32_t* gate;       // [1] 1 when that superstep's senders are few enough to gate the gathers
-  uint32_t* list_ctr;   // [4] next-frontier list length (push form) at s & 1, hub count at 2 + (s & 1)
-  Hub* hubs;            // [kHubCap] hub senders of a push superstep
+  uint32_t* lpre;       // [2][kCtrSlots + 1] prefix of the list segments' lengths, by superstep parity
+  Piece* pieces;        // [kCtrSlots * piece_seg(e)] piece queue of a push superstep
   DevCtl* ctl;          // device-driven loop state
   // both
   CtrSlot* ctr;         // [2][kCtrSlots] per-superstep counters (set s & 1)

@@ -68,14 +68,36 @@ __global__ __launch_bounds__(kBlock) void minprop_init_kernel(uint32_t n, int ap
 struct Active {
   int phase;
   uint32_t count;           // list length, or N for the dense and send-all phases
-  const uint32_t* list;
+  const uint32_t* list;     // the list, in kCtrSlots segments of `seg` entries
+  const uint32_t* pre;      // [kCtrSlots + 1] prefix of the segments' lengths
+  uint32_t seg;
   uint32_t source;
 };
 
-// Vertex of slot i of a launch.
-__device__ __forceinline__ uint32_t active_vertex(const Active& act, uint64_t i) {
+// The list prefix of a launch in LDS (zeros when the phase has no list).
+// Every thread calls it.
+__device__ __forceinline__ void load_list_prefix(const Active& act, uint32_t* s_pre) {
+  for (uint32_t t = threadIdx.x; t <= static_cast<uint32_t>(kCtrSlots); t += blockDim.x)
+    s_pre[t] = act.phase == kStepList ? act.pre[t] : 0u;
+  __syncthreads();
+}
+
+// Vertex of slot i of a launch.  List entry i lies in the segment k with
+// s_pre[k] <= i < s_pre[k + 1].
+__device__ __forceinline__ uint32_t active_vertex(const Active& act, const uint32_t* s_pre, uint64_t i) {
   const uint32_t id = static_cast<uint32_t>(i);
-  const uint32_t from_list = act.phase == kStepList ? act.list[i] : id;
+  const bool listed = act.phase == kStepList;  // uniform over the grid
+  uint32_t lo = 0;
+  if (listed) {
+    uint32_t hi = kCtrSlots - 1;  // the last k with s_pre[k] <= i
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (s_pre[mid] <= id) lo = mid;
+      else hi = mid - 1;
+    }
+  }
+  const uint64_t li = listed ? static_cast<uint64_t>(lo) * act.seg + (id - s_pre[lo]) : 0;
+  const uint32_t from_list = listed ? act.list[li] : id;
   return act.phase == kSendSource ? act.source : from_list;
 }
 
@@ -106,19 +128,41 @@ struct MinPushArgs {
   uint32_t* value;
   uint32_t* mail_in;
   uint32_t* mail_out;
-  uint32_t* list_out;   // next frontier (recipients whose mailbox was empty)
-  uint32_t* list_ctr;
+  uint32_t* list_out;   // next frontier (recipients whose mailbox was empty), in segments
+  uint32_t list_seg;
   CtrSlot* ctr;
   CtrSlot* ctr_clear;
   const DevCtl* ctl;    // device-driven loop: active set and exchange from here (else null)
   uint32_t n;
-  Hub* hubs;            // hub senders (see kHubDeg), or null to expand every sender in place
-  uint32_t* hub_ctr;
+  Piece* pieces;        // piece queue (see kPieceMin), or null to expand every sender in place
+  uint64_t piece_seg;
 };
+
+// Append the lanes' items with `pred` to the workgroup's segment of the
+// next-frontier list: one atomic per wavefront, on the slot's counter.
+// Entries past the segment's end are dropped (the list is then not used).
+__device__ __forceinline__ void seg_append(bool pred, uint32_t item, const MinPushArgs& a) {
+  const uint64_t mask = __ballot(pred);
+  if (mask == 0) return;
+  const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(mask)) - 1);
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(&my_slot(a.ctr)->list_len, static_cast<uint32_t>(__popcll(mask)));
+  base = __shfl(base, static_cast<int>(leader));
+  const uint32_t at = base + lanes_below(mask);
+  if (pred && at < a.list_seg) a.list_out[static_cast<uint64_t>(blockIdx.x % kCtrSlots) * a.list_seg + at] = item;
+}
 
 // One message of a push exchange along CSR edge e: the combiner (atomic
 // min into the recipient's next mailbox), the frontier append of a first
-// message, and the counters.
+// message, and the counters.  The mailbox is read first and the atomic
+// skipped when the message cannot lower it.  The read is a plain load that
+// may hit this XCD's L2: writes of earlier launches are visible to it, and
+// within the exchange only these atomics change a mailbox, and only
+// downwards, so a stale copy holds a value at least the current one and the
+// test never skips an atomic that would change anything -- nor the one that
+// finds the mailbox empty (the value read is then already below INF).
+// Device-scope atomics are performed past the XCDs' L2s; without the test,
+// every message would pay for one.
 template <int APP, bool W>
 __device__ __forceinline__ void push_edge(const MinPushArgs& a, uint64_t e, uint32_t p, uint64_t& next_count,
                                           uint64_t& next_deg, uint32_t& overflow) {
@@ -126,9 +170,13 @@ __device__ __forceinline__ void push_edge(const MinPushArgs& a, uint64_t e, uint
   uint64_t m = p;
   if (APP == IPG_APP_SSSP) m += W ? a.w[e] : 1u;
   bool fresh = false;
-  if (m >= kInf) overflow = 1;
-  else fresh = atomicMin(a.mail_out + x, static_cast<uint32_t>(m)) == kInf;
-  wave_append(fresh, x, a.list_out, a.list_ctr);
+  if (m >= kInf) {
+    overflow = 1;
+  } else {
+    const uint32_t cur = a.mail_out[x];
+    if (m < cur) fresh = atomicMin(a.mail_out + x, static_cast<uint32_t>(m)) == kInf;
+  }
+  seg_append(fresh, x, a);
   if (fresh) {
     next_count += 1;
     next_deg += a.outdeg[x];
@@ -140,7 +188,7 @@ __device__ __forceinline__ void push_edge(const MinPushArgs& a, uint64_t e, uint
 // own: every vertex for CC, the source for SSSP.)
 __device__ __forceinline__ Active device_active(const DevCtl& c, const Active& own, const uint32_t* list, uint32_t n) {
   if (c.step == 0) return own;
-  Active act;
+  Active act = own;
   act.phase = c.list_ok ? kStepList : kStepDense;
   act.count = c.list_ok ? static_cast<uint32_t>(c.count) : n;
   act.list = list;
@@ -148,19 +196,59 @@ __device__ __forceinline__ Active device_active(const DevCtl& c, const Active& o
   return act;
 }
 
+// Queue the out-edges of this wavefront's senders that have at least
+// kPieceMin of them as pieces in the workgroup's segment of the queue (one
+// atomic per wavefront, on the slot's counter); returns whether the lane
+// still expands its sender itself.  A sender whose pieces do not fit in
+// the segment is expanded in place and its entries marked unused.  All
+// lanes of the wavefront call it together.
+__device__ __forceinline__ bool queue_pieces(const MinPushArgs& a, bool has, uint64_t beg, uint64_t end, uint32_t msg) {
+  const uint64_t d = has ? end - beg : 0;
+  const uint32_t np = d >= kPieceMin ? static_cast<uint32_t>((d + kPiece - 1) / kPiece) : 0u;
+  if (__ballot(np != 0) == 0) return has;  // uniform: no sender to queue
+  const uint32_t lane = lane_id();
+  uint32_t inc = np;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t t = __shfl_up(inc, o);
+    if (lane >= static_cast<uint32_t>(o)) inc += t;
+  }
+  const uint32_t total = __shfl(inc, kWave - 1);
+  if (total == 0) return has;  // uniform
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(&my_slot(a.ctr)->pieces, total);
+  base = __shfl(base, 0);
+  if (np == 0) return has;
+  const uint64_t first = static_cast<uint64_t>(base) + (inc - np);
+  const bool fits = first + np <= a.piece_seg;
+  Piece* seg = a.pieces + static_cast<uint64_t>(blockIdx.x % kCtrSlots) * a.piece_seg;
+  for (uint32_t k = 0; k < np && first + k < a.piece_seg; ++k) {
+    const uint64_t b = beg + static_cast<uint64_t>(k) * kPiece;
+    Piece p;
+    p.beg = b;
+    p.n = fits ? static_cast<uint32_t>(min(static_cast<uint64_t>(kPiece), end - b)) : 0u;
+    p.msg = msg;
+    seg[first + k] = p;
+  }
+  return !fits;
+}
+
 // Fused compute + push scatter of one superstep: one thread per active
-// vertex (grid-stride in workgroup-uniform rounds), out-edges expanded by
-// twc_scatter.  Recipients whose mailbox was empty are appended to the
-// next-frontier list by wave-ballot compaction (one global atomic per wave
-// and ballot).
+// vertex (grid-stride in workgroup-uniform rounds); senders with many
+// out-edges queue them as pieces, the others are expanded by twc_scatter.
+// Recipients whose mailbox was empty are appended to the next-frontier list
+// by wave-ballot compaction (one atomic per wave and ballot, on the slot's
+// counter).
 template <int APP, bool W>
 __global__ __launch_bounds__(kBlock) void minprop_push_kernel(MinPushArgs a) {
+  __shared__ uint32_t s_lpre[kCtrSlots + 1];
   Active act = a.act;
   if (a.ctl) {
     const DevCtl c = *a.ctl;
     if (c.halted || c.mode != IPG_MODE_PUSH) return;  // uniform over the grid
     act = device_active(c, a.act, a.act.list, a.n);
   }
+  load_list_prefix(act, s_lpre);
   clear_slots(a.ctr_clear);
   uint64_t senders = 0, messages = 0, next_count = 0, next_deg = 0;
   uint32_t overflow = 0;
@@ -171,27 +259,16 @@ __global__ __launch_bounds__(kBlock) void minprop_push_kernel(MinPushArgs a) {
     uint64_t beg = 0, end = 0;
     uint32_t msg = 0;
     if (i < act.count) {
-      const uint32_t v = active_vertex(act, i);
+      const uint32_t v = active_vertex(act, s_lpre, i);
       has = compute_min(act.phase, v, a.value, a.mail_in, msg);
       if (has) {
         beg = a.off[v];
         end = a.off[v + 1];
         senders += 1;
         messages += end - beg;
-        if (a.hubs && end - beg >= kHubDeg) {
-          const uint32_t slot = atomicAdd(a.hub_ctr, 1u);
-          if (slot < kHubCap) {  // else: expanded here after all
-            Hub h;
-            h.beg = beg;
-            h.end = end;
-            h.msg = msg;
-            h.pad = 0;
-            a.hubs[slot] = h;
-            has = false;
-          }
-        }
       }
     }
+    if (a.pieces) has = queue_pieces(a, has, beg, end, msg);
     twc_scatter(has, beg, end, msg, [&](uint64_t e, uint32_t p) {
       push_edge<APP, W>(a, e, p, next_count, next_deg, overflow);
     });
@@ -199,60 +276,77 @@ __global__ __launch_bounds__(kBlock) void minprop_push_kernel(MinPushArgs a) {
   flush_counters(a.ctr, senders, messages, next_count, next_deg, overflow);
 }
 
-// Second launch of a push superstep: the out-edges of the hub senders,
-// concatenated (prefix of their degrees in LDS) and spread evenly over the
-// grid, one edge per thread and pass.
+// The messages of one piece: a workgroup, kPiece / kBlock edges per thread
+// with their loads issued together.
 template <int APP, bool W>
-__global__ __launch_bounds__(kBlock) void minprop_hub_kernel(MinPushArgs a) {
-  __shared__ unsigned long long s_pre[kHubCap + 1];
-  __shared__ unsigned long long s_part[kBlock];
+__device__ __forceinline__ void push_piece(const MinPushArgs& a, const Piece& pc, uint64_t& next_count,
+                                           uint64_t& next_deg, uint32_t& overflow) {
+  constexpr int kPer = kPiece / kBlock;
+  uint32_t x[kPer], cur[kPer];
+  uint64_t m[kPer];
+  bool ok[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const uint32_t j = threadIdx.x + k * kBlock;
+    ok[k] = j < pc.n;
+    const uint64_t e = pc.beg + (ok[k] ? j : 0u);
+    x[k] = ok[k] ? static_cast<uint32_t>(a.dst[e]) : 0u;
+    m[k] = pc.msg;
+    if (APP == IPG_APP_SSSP) m[k] += W ? (ok[k] ? a.w[e] : 0u) : 1u;
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) cur[k] = ok[k] && m[k] < kInf ? a.mail_out[x[k]] : 0u;  // see push_edge
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    bool fresh = false;
+    if (ok[k]) {
+      if (m[k] >= kInf) overflow = 1;
+      else if (m[k] < cur[k]) fresh = atomicMin(a.mail_out + x[k], static_cast<uint32_t>(m[k])) == kInf;
+    }
+    seg_append(fresh, x[k], a);
+    if (fresh) {
+      next_count += 1;
+      next_deg += a.outdeg[x[k]];
+    }
+  }
+}
+
+// Second launch of a push superstep: the queued pieces, dealt over the grid
+// (piece g, counted over the segments in slot order, to workgroup
+// g mod grid).
+template <int APP, bool W>
+__global__ __launch_bounds__(kBlock) void minprop_piece_kernel(MinPushArgs a) {
+  __shared__ uint32_t s_pre[kCtrSlots + 1];
   if (a.ctl) {
     const DevCtl c = *a.ctl;
     if (c.halted || c.mode != IPG_MODE_PUSH) return;
   }
-  const uint32_t H = min(*a.hub_ctr, kHubCap);
-  if (H == 0) return;  // uniform
-  constexpr uint32_t kPer = kHubCap / kBlock;
-  const uint32_t t = threadIdx.x;
-  unsigned long long own = 0;
-  for (uint32_t k = 0; k < kPer; ++k) {
-    const uint32_t h = t * kPer + k;
-    if (h < H) own += a.hubs[h].end - a.hubs[h].beg;
-  }
-  s_part[t] = own;
-  __syncthreads();
-  for (uint32_t o = 1; o < kBlock; o <<= 1) {  // inclusive scan of the per-thread sums
-    const unsigned long long y = t >= o ? s_part[t - o] : 0ull;
-    __syncthreads();
-    s_part[t] += y;
-    __syncthreads();
-  }
-  unsigned long long run = s_part[t] - own;
-  for (uint32_t k = 0; k < kPer; ++k) {
-    const uint32_t h = t * kPer + k;
-    if (h < H) {
-      s_pre[h] = run;
-      run += a.hubs[h].end - a.hubs[h].beg;
+  if (threadIdx.x < kWave) {  // prefix of the segments' lengths (one wavefront)
+    const uint32_t lane = lane_id();
+    const uint32_t cnt = static_cast<uint32_t>(min(static_cast<uint64_t>(a.ctr[lane].pieces), a.piece_seg));
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t t = __shfl_up(inc, o);
+      if (lane >= static_cast<uint32_t>(o)) inc += t;
     }
+    s_pre[lane + 1] = inc;
+    if (lane == 0) s_pre[0] = 0;
   }
-  if (t == kBlock - 1) s_pre[H] = s_part[kBlock - 1];
   __syncthreads();
-  const unsigned long long total = s_pre[H];
+  const uint32_t total = s_pre[kCtrSlots];
+  if (blockIdx.x >= total) return;  // uniform: no piece, nothing to count
   uint64_t next_count = 0, next_deg = 0;
   uint32_t overflow = 0;
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t base = blockIdx.x * (uint64_t)kBlock; base < total; base += stride) {
-    const uint64_t j = base + t;
-    if (j < total) {
-      uint32_t lo = 0, hi = H - 1;  // last hub h with s_pre[h] <= j
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (s_pre[mid] <= j) lo = mid;
-        else hi = mid - 1;
-      }
-      const Hub& h = a.hubs[lo];
-      push_edge<APP, W>(a, h.beg + (j - s_pre[lo]), h.msg, next_count, next_deg, overflow);
+  for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {  // uniform over the workgroup
+    uint32_t lo = 0, hi = kCtrSlots - 1;  // the last segment k with s_pre[k] <= g
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (s_pre[mid] <= g) lo = mid;
+      else hi = mid - 1;
     }
+    const Piece pc = a.pieces[static_cast<uint64_t>(lo) * a.piece_seg + (g - s_pre[lo])];
+    push_piece<APP, W>(a, pc, next_count, next_deg, overflow);
   }
   flush_counters(a.ctr, 0, 0, next_count, next_deg, overflow);
 }
@@ -274,6 +368,7 @@ struct MinApplyArgs {
 // outbox (Section 4.3.2: one broadcast value per vertex, read by the
 // out-neighbours).
 __global__ __launch_bounds__(kBlock) void minprop_apply_kernel(MinApplyArgs a) {
+  __shared__ uint32_t s_lpre[kCtrSlots + 1];
   Active act = a.act;
   if (a.ctl) {
     const DevCtl c = *a.ctl;
@@ -281,6 +376,7 @@ __global__ __launch_bounds__(kBlock) void minprop_apply_kernel(MinApplyArgs a) {
     act.phase = kStepDense;
     act.count = a.n;
   }
+  load_list_prefix(act, s_lpre);
   uint64_t senders = 0, messages = 0;
   // wavefront-uniform rounds (the sender bitmap is set a wavefront at a time)
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -290,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void minprop_apply_kernel(MinApplyArgs a) {
     bool sends = false;
     uint32_t v = 0;
     if (i < act.count) {
-      v = active_vertex(act, i);
+      v = active_vertex(act, s_lpre, i);
       uint32_t msg;
       sends = compute_min(act.phase, v, a.value, a.mail_in, msg);
       if (sends) {
@@ -543,8 +639,29 @@ __global__ __launch_bounds__(kBlock) void minprop_blocked_finish_kernel(MinBlkAr
 // End of a superstep: sum the counter slots (one wavefront, lane t reads
 // slot t) and, when a selector is given and work is pending, choose the
 // exchange of the next superstep with the network.
+// The next-frontier list of a push superstep, from the slots (one
+// wavefront, lane t reads slot t): its length (~0 if a segment overflowed)
+// and, into `pre` when given, the prefix of the segments' lengths.
+__device__ __forceinline__ uint64_t list_summary(const CtrSlot& x, uint32_t lseg, uint32_t* pre) {
+  const uint32_t ll = x.list_len;
+  const uint32_t lane = lane_id();
+  uint32_t inc = min(ll, lseg);
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t t = __shfl_up(inc, o);
+    if (lane >= static_cast<uint32_t>(o)) inc += t;
+  }
+  if (pre) {
+    pre[lane + 1] = inc;
+    if (lane == 0) pre[0] = 0;
+  }
+  const bool lovf = __ballot(ll > lseg) != 0;
+  const uint64_t sum = wave_sum_u64(ll);
+  return lovf ? ~0ull : sum;
+}
+
 __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_t next_superstep, uint64_t e,
-                                                       const double* sel, Decision* out, uint32_t* lc, uint32_t* hc) {
+                                                       const double* sel, Decision* out, uint32_t lseg, uint32_t* lpre_out) {
   static_assert(kCtrSlots == kWave, "one slot per lane");
   const CtrSlot& x = c[threadIdx.x];
   const uint64_t nc = wave_sum_u64(x.next_count);
@@ -553,6 +670,7 @@ __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_
   const uint64_t nd = wave_sum_u64(x.next_deg);
   const uint64_t ac = wave_sum_u64(x.active);
   const bool ovf = __ballot(x.overflow != 0) != 0;
+  const uint64_t ll = list_summary(x, lseg, lpre_out);
   int m = 0;
   double margin = 0.0;
   if (sel && nc) margin = sel_predict_mode_wave(sel, nc, nd, next_superstep, e, &m);  // whole wavefront
@@ -566,12 +684,7 @@ __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_
     d.mode = m;
     d.margin = margin;
     d.active = ac;
-    d.list_len = 0;
-    if (lc) {
-      d.list_len = *lc;
-      *lc = 0;  // the counters are reused two supersteps later
-      *hc = 0;
-    }
+    d.list_len = ll;
     *out = d;
   }
 }
@@ -606,7 +719,7 @@ __global__ __launch_bounds__(kWave) void dd_start_kernel(DevCtl* ctl, int app, u
 // (no message pending, an overflow, the cap) and, otherwise, the active set
 // and the exchange of the next superstep (forced, the selector, or the fixed
 // heuristic).  Does nothing once the run has halted.
-__global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint32_t* lc, uint32_t* hc, uint64_t e,
+__global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint32_t lseg, uint32_t* lpre_out, uint64_t e,
                                                           uint32_t n, const double* sel, int forced,
                                                           uint64_t list_limit, uint32_t push_div, DevCtl* ctl,
                                                           HostMirror* hm) {
@@ -620,6 +733,7 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
   const uint64_t me = wave_sum_u64(x.messages);
   const uint64_t nd = wave_sum_u64(x.next_deg);
   const bool ovf = __ballot(x.overflow != 0) != 0;
+  const uint64_t lcount = list_summary(x, lseg, lpre_out);  // ~0: a segment overflowed, no list
   const uint32_t s = k.step;
   int sel_mode = IPG_MODE_PUSH;
   if (sel && !forced && nc && !ovf && !(k.cap && s + 1 >= k.cap))  // uniform: the whole wavefront infers
@@ -635,15 +749,12 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
   r.mode = static_cast<uint32_t>(k.mode);
   r.pad = 0;
   hm->rec[s % kDevRec] = r;
-  const uint32_t lcount = *lc;
-  *lc = 0;  // the counters are reused two supersteps later
-  *hc = 0;
   DevCtl nk = k;
   nk.step = s + 1;
   nk.t_last = now;
   nk.count = nc;
   nk.degsum = nd;
-  nk.list_ok = (k.mode == IPG_MODE_PUSH && nc <= list_limit) ? 1u : 0u;
+  nk.list_ok = (k.mode == IPG_MODE_PUSH && nc <= list_limit && lcount != ~0ull) ? 1u : 0u;
   if (ovf) {
     nk.halted = 1;
     nk.status = IPG_EOVERFLOW;
@@ -653,7 +764,7 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
   } else if (k.cap && s + 1 >= k.cap) {
     nk.halted = 1;
     nk.status = IPG_NOT_CONVERGED;
-  } else if (k.mode == IPG_MODE_PUSH && lcount != nc) {
+  } else if (k.mode == IPG_MODE_PUSH && lcount != ~0ull && lcount != nc) {
     nk.halted = 1;
     nk.status = IPG_EDEVICE;
   } else if (forced) {
@@ -670,20 +781,20 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
 // ------------------------------------------------------------------ host --
 
 hipError_t launch_decide(const CtrSlot* c, uint32_t next_superstep, uint64_t e, const double* sel, Decision* out,
-                         uint32_t* lc, uint32_t* hc, hipStream_t s) {
-  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kWave), 0, s, c, next_superstep, e, sel, out, lc, hc);
+                         uint32_t lseg, uint32_t* lpre_out, hipStream_t s) {
+  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kWave), 0, s, c, next_superstep, e, sel, out, lseg, lpre_out);
   return hipGetLastError();
 }
 
-// Grid of the hub launch: enough passes-worth of threads for a few hubs.
-constexpr uint32_t kHubGrid = 1024;
+// Grid of the piece launch.
+constexpr uint32_t kPieceGrid = 2048;
 
 template <int APP, bool W>
-static hipError_t launch_push(const MinPushArgs& a, uint32_t grid, bool hubs, hipStream_t s) {
+static hipError_t launch_push(const MinPushArgs& a, uint32_t grid, hipStream_t s) {
   hipLaunchKernelGGL((minprop_push_kernel<APP, W>), dim3(grid), dim3(kBlock), 0, s, a);
   hipError_t err = hipGetLastError();
-  if (err != hipSuccess || !hubs) return err;
-  hipLaunchKernelGGL((minprop_hub_kernel<APP, W>), dim3(kHubGrid), dim3(kBlock), 0, s, a);
+  if (err != hipSuccess || !a.pieces) return err;
+  hipLaunchKernelGGL((minprop_piece_kernel<APP, W>), dim3(kPieceGrid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 template <int APP, bool W>
@@ -693,10 +804,9 @@ static hipError_t launch_pull(const MinPullArgs& a, uint32_t max_grid, hipStream
   return hipGetLastError();
 }
 
-static hipError_t push_dispatch(ipg_app app, bool weighted, const MinPushArgs& a, uint32_t grid, bool hubs,
-                                hipStream_t s) {
-  if (app == IPG_APP_CC_HASHMIN) return launch_push<IPG_APP_CC_HASHMIN, false>(a, grid, hubs, s);
-  return weighted ? launch_push<IPG_APP_SSSP, true>(a, grid, hubs, s) : launch_push<IPG_APP_SSSP, false>(a, grid, hubs, s);
+static hipError_t push_dispatch(ipg_app app, bool weighted, const MinPushArgs& a, uint32_t grid, hipStream_t s) {
+  if (app == IPG_APP_CC_HASHMIN) return launch_push<IPG_APP_CC_HASHMIN, false>(a, grid, s);
+  return weighted ? launch_push<IPG_APP_SSSP, true>(a, grid, s) : launch_push<IPG_APP_SSSP, false>(a, grid, s);
 }
 static hipError_t pull_dispatch(ipg_app app, bool weighted, const MinPullArgs& a, uint32_t grid, hipStream_t s) {
   if (app == IPG_APP_CC_HASHMIN) return launch_pull<IPG_APP_CC_HASHMIN, false>(a, grid, s);
@@ -711,8 +821,8 @@ static uint64_t list_limit(uint32_t n, uint32_t div) { return std::max<uint64_t>
 struct StepBufs {
   CtrSlot* c;    // this superstep's counters
   CtrSlot* cc;   // the next superstep's counters (cleared by this superstep's exchange)
-  uint32_t* lc;  // this superstep's list length
-  uint32_t* hc;  // this superstep's hub count
+  uint32_t* lpre_in;   // prefix of the list the previous superstep left (read by this one's list phase)
+  uint32_t* lpre_out;  // prefix of the list this superstep leaves (written by its decide)
   uint32_t *fin, *fout, *mail_in, *mail_out;
 };
 static StepBufs bufs_for(const RunWs& w, uint32_t step) {
@@ -720,8 +830,8 @@ static StepBufs bufs_for(const RunWs& w, uint32_t step) {
   StepBufs b;
   b.c = w.ctr + (odd ? kCtrSlots : 0);
   b.cc = w.ctr + (odd ? 0 : kCtrSlots);
-  b.lc = w.list_ctr + (odd ? 1 : 0);
-  b.hc = w.list_ctr + (odd ? 3 : 2);
+  b.lpre_out = w.lpre + (odd ? kCtrSlots + 1 : 0);
+  b.lpre_in = w.lpre + (odd ? 0 : kCtrSlots + 1);
   b.fin = odd ? w.fr_b : w.fr_a;
   b.fout = odd ? w.fr_a : w.fr_b;
   b.mail_in = odd ? w.mail_b : w.mail_a;
@@ -750,6 +860,8 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
     MinPushArgs a;
     a.act = act;
     a.act.list = b.fin;
+    a.act.pre = b.lpre_in;
+    a.act.seg = list_seg(n);
     a.off = g->csr_off;
     a.dst = g->csr_dst;
     a.w = weighted ? g->csr_w : nullptr;
@@ -758,18 +870,19 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
     a.mail_in = b.mail_in;
     a.mail_out = b.mail_out;
     a.list_out = b.fout;
-    a.list_ctr = b.lc;
+    a.list_seg = list_seg(n);
     a.ctr = b.c;
     a.ctr_clear = b.cc;
     a.ctl = ctl;
     a.n = n;
-    // hub launch: always in the device-driven loop (it returns at once
-    // without hubs), else when the frontier's out-degrees could hold one
-    const bool hubs = device || degsum >= kHubDeg;
-    a.hubs = hubs ? w.hubs : nullptr;
-    a.hub_ctr = b.hc;
+    // piece queue and launch: always in the device-driven loop (the launch
+    // returns at once without pieces), else when the frontier's out-degrees
+    // could make one
+    const bool pieces = device || degsum >= kPieceMin;
+    a.pieces = pieces ? w.pieces : nullptr;
+    a.piece_seg = piece_seg(g->e);
     const uint32_t grid = device ? kExchangeGrid : grid_for(act.count, kBlock, 0xFFFFFFFFu);
-    IPG_HIP(push_dispatch(app, weighted, a, grid, hubs, s));
+    IPG_HIP(push_dispatch(app, weighted, a, grid, s));
   }
   if (device || mode == IPG_MODE_PULL) {
     // the blocked in-edges of the caller's CSC (CC, unit-weight SSSP), if the store has them
@@ -782,6 +895,8 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
       MinApplyArgs ap;
       ap.act = act;
       ap.act.list = b.fin;
+      ap.act.pre = b.lpre_in;
+      ap.act.seg = list_seg(n);
       ap.outdeg = g->t.outdeg;
       ap.value = w.value_u32;
       ap.mail_in = b.mail_in;
@@ -845,7 +960,6 @@ static ipg_status clear_minprop(const ipg_graph* g, const RunWs& w, hipStream_t 
   IPG_HIP(fill_u32(w.mail_a, g->n, kInf, s));
   IPG_HIP(fill_u32(w.mail_b, g->n, kInf, s));
   IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.ctr), 2 * kCtrSlots * sizeof(CtrSlot) / 4, 0, s));
-  IPG_HIP(fill_u32(w.list_ctr, 4, 0, s));
   return IPG_OK;
 }
 
@@ -881,7 +995,7 @@ static ipg_status start_minprop(ipg_graph* g, ipg_app app, const ipg_run_opts& o
 }
 
 static Active step0_active(ipg_app app, uint32_t n, uint32_t source) {
-  Active act;
+  Active act{};
   act.source = source;
   act.list = nullptr;
   act.phase = app == IPG_APP_CC_HASHMIN ? kSendAll : kSendSource;
@@ -929,7 +1043,7 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
         if (rc != IPG_OK) return rc;
       }
       const StepBufs b = bufs_for(w, step);
-      hipLaunchKernelGGL(dd_decide_kernel, dim3(1), dim3(kWave), 0, s, b.c, b.lc, b.hc, e, n, sel, forced,
+      hipLaunchKernelGGL(dd_decide_kernel, dim3(1), dim3(kWave), 0, s, b.c, list_seg(n), b.lpre_out, e, n, sel, forced,
                          list_limit(n, tn.list_div), tn.push_div, w.ctl, hm_dev);
       IPG_HIP(hipGetLastError());
     }
@@ -988,7 +1102,7 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
     ipg_mode mode = o.mode;
     if (mode == IPG_MODE_AUTO) mode = next_sel_mode ? static_cast<ipg_mode>(next_sel_mode) : heuristic_mode(q, tn.push_div);
     const StepBufs b = bufs_for(w, step);
-    Active act;
+    Active act{};
     if (step == 0) {
       act = step0_active(app, n, o.source);
     } else {
@@ -1001,10 +1115,10 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
     if (status != IPG_OK) return status;
     IPG_HIP(tm.step(s, step));
     const double* sel = o.mode == IPG_MODE_AUTO ? o.selector : nullptr;
-    IPG_HIP(launch_decide(b.c, step + 1, e, sel, &hm_dev->decision, b.lc, b.hc, s));
+    IPG_HIP(launch_decide(b.c, step + 1, e, sel, &hm_dev->decision, list_seg(n), b.lpre_out, s));
     IPG_HIP(hipStreamSynchronize(s));
     const Decision h = hm->decision;
-    const uint64_t lcount = h.list_len;
+    const uint64_t lcount = h.list_len;  // ~0: a segment overflowed, no list
     const uint64_t examined = mode == IPG_MODE_PUSH ? h.messages : e;
     if (st && step < st->trace_cap) {
       if (st->active) st->active[step] = step == 0 ? n : count;
@@ -1026,14 +1140,14 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
       status = IPG_NOT_CONVERGED;
       break;
     }
-    if (mode == IPG_MODE_PUSH && lcount != h.next_count) {
+    if (mode == IPG_MODE_PUSH && lcount != ~0ull && lcount != h.next_count) {
       status = fail(IPG_EDEVICE, "frontier list length disagrees with the mailbox count");
       break;
     }
     count = h.next_count;
     degsum = h.next_deg;
     next_sel_mode = h.mode;
-    list_ok = mode == IPG_MODE_PUSH && count <= list_limit(n, tn.list_div);
+    list_ok = mode == IPG_MODE_PUSH && count <= list_limit(n, tn.list_div) && lcount != ~0ull;
   }
   IPG_HIP(tm.finish(s));
   if (st) {

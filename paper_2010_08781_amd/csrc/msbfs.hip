@@ -711,7 +711,7 @@ static ipg_status run_msbfs(ipg_graph* g, const uint32_t* sources, uint32_t q, u
     }
     used[slot] = true;
     IPG_HIP(tm.step(s, step));
-    IPG_HIP(launch_decide(c, step + 1, e, nullptr, &hm_dev->decision, nullptr, nullptr, s));
+    IPG_HIP(launch_decide(c, step + 1, e, nullptr, &hm_dev->decision, 0, nullptr, s));
     IPG_HIP(hipStreamSynchronize(s));
     const Decision h = hm->decision;
     const uint64_t active = step == 0 ? (uint64_t)q * n : h.active;

@@ -1,13 +1,14 @@
 """Training data, GPU training and evaluation of the learned exchange selector.
 
 Labels come from timing the plain method.  Every CC/SSSP run is repeated
-with the exchange forced to push and forced to pull, under the launch
-parameters the autotuner picks for that graph (the configuration the
-selector is deployed with).  The state at the start
-of a superstep does not depend on the exchange (values and traces are
-identical in both runs), so superstep s of the two runs starts from the same
-state and their per-superstep device times (HIP events) give the two targets
-for that state: log2 of the microseconds of a push and of a pull superstep.
+with the exchange forced to push and forced to pull, in the configuration
+the selector is deployed with: a store with the blocked in-edges, the
+device-driven superstep loop, and the launch parameters the autotuner picks
+for that graph.  The state at the start of a superstep does not depend on
+the exchange (values and traces are identical in both runs), so superstep s
+of the two runs starts from the same state and their per-superstep device
+times (the decide kernel's wall-clock stamps) give the two targets for that
+state: log2 of the microseconds of a push and of a pull superstep.
 
 The network is then trained on the device by the library's own FP64 forward,
 backward and SGD kernels (ipg_selector_train), and compared with the fixed
@@ -56,6 +57,16 @@ def _sources(hg, k, seed):
     return [0] + [int(x) for x in graphgen.pick_sources(hg, k, seed)]
 
 
+def decision_frontier(app: str, active) -> np.ndarray:
+    """Vertices whose messages the exchange of each superstep sends, as the
+    decision sees them: the trace's active counts, except at superstep 0,
+    where every vertex is active but only CC's all send (SSSP: the source)."""
+    f = np.asarray(active, dtype=np.uint64).copy()
+    if app == "sssp" and f.size:
+        f[0] = 1
+    return f
+
+
 def collect(kind: str = "train", reps: int = 3, verbose: bool = True):
     """Returns (X [n,4], T [n,2] log2-usec for push/pull, meta list)."""
     import paper_2010_08781_amd as ipg
@@ -64,22 +75,23 @@ def collect(kind: str = "train", reps: int = 3, verbose: bool = True):
 
     X, T, meta = [], [], []
     for name, hg in _graphs(kind):
-        g = ipg.Graph.from_host(hg)
-        tun = autotune.tune(g, hg, "cc", cache_path=None, reps=1)
+        g = ipg.Graph.from_host(hg, blocked=True)
+        tun = autotune.tune(g, hg, "cc", cache_path=None, reps=1, persistent=True)
         tun.pop("push_div", None)  # the fixed rule's divisor: irrelevant to forced exchanges
-        runs = [("cc", 0)] + [("sssp", s) for s in _sources(hg, 2, 99)]
+        runs = [("cc", 0)] + [("sssp", s) for s in _sources(hg, 4, 99)]
         for app, src in runs:
             times = {}
             for mode in ("push", "pull"):
                 us = []
                 for _ in range(reps):
-                    _, st = g.run(app, source=src, mode=mode, timing=True, tuning=tun)
+                    _, st = g.run(app, source=src, mode=mode, timing=True, tuning=tun, persistent=True)
                     us.append(st.usec.astype(np.float64))
                 times[mode] = np.median(np.stack(us), axis=0)
-            feats = ipg.selector_features(st.active, st.frontier_deg, np.arange(st.supersteps), hg.m)
+            front = decision_frontier(app, st.active)
+            feats = ipg.selector_features(front, st.frontier_deg, np.arange(st.supersteps), hg.m)
             X.append(feats)
             T.append(np.log2(np.maximum(np.stack([times["push"], times["pull"]], axis=1), 1.0)))
-            meta += [(name, app, src, s, int(st.active[s]), int(st.frontier_deg[s]), hg.m) for s in range(st.supersteps)]
+            meta += [(name, app, src, s, int(front[s]), int(st.frontier_deg[s]), hg.m) for s in range(st.supersteps)]
             if verbose:
                 print(f"[selector] {kind} {name} {app} src={src} {tun}: {st.supersteps} supersteps, "
                       f"push {times['push'].sum():.0f} us, pull {times['pull'].sum():.0f} us", file=sys.stderr, flush=True)
@@ -158,11 +170,15 @@ def main():
     ap.add_argument("--epochs", type=int, default=8000)
     ap.add_argument("--lr", type=float, default=0.05)
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--data-out", default=None, help="also write the timed samples (npz)")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))
     t0 = time.time()
     Xtr, Ttr, mtr = collect("train", reps=args.reps)
     Xte, Tte, mte = collect("test", reps=args.reps)
+    if args.data_out:
+        np.savez(args.data_out, Xtr=Xtr, Ttr=Ttr, mtr=np.array(mtr, dtype=object).astype(str), Xte=Xte, Tte=Tte,
+                 mte=np.array(mte, dtype=object).astype(str))
     p = train(Xtr, Ttr, epochs=args.epochs, lr=args.lr)
     pn = p.cpu().numpy()
     res = {}

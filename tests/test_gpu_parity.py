@@ -254,9 +254,9 @@ def test_small_workspace_rejected(ipg):
 
 
 def test_push_hub_senders(ipg):
-    # Senders with at least 8192 out-edges are expanded by the hub launch
-    # (edges spread over the grid); degrees on both sides of the threshold,
-    # several hubs in one superstep, and hubs reached in later supersteps.
+    # Senders with many out-edges queue them as pieces that a second launch
+    # spreads over the grid; degrees far above the piece size, several such
+    # senders in one superstep, and such senders reached in later supersteps.
     rng = np.random.default_rng(5)
     n = 60000
     src, dst = [], []
