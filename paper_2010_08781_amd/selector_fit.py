@@ -131,12 +131,17 @@ def cost_weighted(X, T, cap: int = 16):
     return np.repeat(X, reps, axis=0), np.repeat(T, reps, axis=0)
 
 
-def train(X, T, epochs: int = 4000, lr: float = 0.05, seed: int = 1):
+def train(X, T, epochs: int = 30000, lr: float = 0.1, seed: int = 1, weighted: bool = False):
+    """Full-batch gradient descent on the library's kernels.  The squared
+    error of the log-times is already relative, so the samples are used as
+    they are; cost replication (weighted=True) fitted the rare, costly dense
+    supersteps at the expense of the decisions near the crossover."""
     import torch
 
     import paper_2010_08781_amd as ipg
 
-    X, T = cost_weighted(X, T)
+    if weighted:
+        X, T = cost_weighted(X, T)
     p = torch.tensor(init_params(seed), dtype=torch.float64, device="cuda")
     x = torch.tensor(X, dtype=torch.float64, device="cuda")
     t = torch.tensor(T, dtype=torch.float64, device="cuda")
@@ -167,15 +172,24 @@ def load(path: str = DEFAULT_PARAMS):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_PARAMS)
-    ap.add_argument("--epochs", type=int, default=8000)
-    ap.add_argument("--lr", type=float, default=0.05)
+    ap.add_argument("--epochs", type=int, default=30000)
+    ap.add_argument("--lr", type=float, default=0.1)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--data-out", default=None, help="also write the timed samples (npz)")
+    ap.add_argument("--data-in", default=None, help="train on samples written by --data-out instead of timing")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))
     t0 = time.time()
-    Xtr, Ttr, mtr = collect("train", reps=args.reps)
-    Xte, Tte, mte = collect("test", reps=args.reps)
+    if args.data_in:
+        d = np.load(args.data_in, allow_pickle=False)
+
+        def meta(m):
+            return [(a, b, int(c), int(k), int(f), int(dd), int(e)) for a, b, c, k, f, dd, e in m]
+
+        Xtr, Ttr, mtr, Xte, Tte, mte = d["Xtr"], d["Ttr"], meta(d["mtr"]), d["Xte"], d["Tte"], meta(d["mte"])
+    else:
+        Xtr, Ttr, mtr = collect("train", reps=args.reps)
+        Xte, Tte, mte = collect("test", reps=args.reps)
     if args.data_out:
         np.savez(args.data_out, Xtr=Xtr, Ttr=Ttr, mtr=np.array(mtr, dtype=object).astype(str), Xte=Xte, Tte=Tte,
                  mte=np.array(mte, dtype=object).astype(str))
