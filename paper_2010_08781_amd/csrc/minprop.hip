@@ -367,6 +367,45 @@ struct MinApplyArgs {
 // vertices; a vertex whose value drops broadcasts it through its one-slot
 // outbox (Section 4.3.2: one broadcast value per vertex, read by the
 // out-neighbours).
+// The compute of a pull superstep over every vertex, four per thread with
+// 16-byte accesses (the arrays are 256-byte aligned): consume the mailboxes
+// (rewritten only when one of the four holds a message), lower the values,
+// and write every outbox slot -- the new value for a vertex that
+// broadcasts, INF otherwise.  The last N mod 4 vertices one per thread.
+__device__ __forceinline__ void apply_dense4(const MinApplyArgs& a, uint64_t& senders, uint64_t& messages) {
+  const uint64_t nq = a.n / 4;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t t0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint4* mail = reinterpret_cast<uint4*>(a.mail_in);
+  uint4* val = reinterpret_cast<uint4*>(a.value);
+  uint4* out = reinterpret_cast<uint4*>(a.outbox);
+  const uint4* deg = reinterpret_cast<const uint4*>(a.outdeg);
+  for (uint64_t q = t0; q < nq; q += stride) {
+    // The three loads are issued together -- one memory latency per thread
+    // instead of three in a row -- and every loaded value is used outside
+    // the branches (a value used only under a branch is loaded there).  A
+    // quad without a message reads 8 bytes per vertex in vain.
+    const uint4 m = mail[q];
+    const uint4 x = val[q];
+    const uint4 d = deg[q];
+    const bool s0 = m.x < x.x, s1 = m.y < x.y, s2 = m.z < x.z, s3 = m.w < x.w;  // INF: no message, no send
+    senders += static_cast<uint64_t>(s0) + s1 + s2 + s3;
+    messages += static_cast<uint64_t>(s0 ? d.x : 0u) + (s1 ? d.y : 0u) + (s2 ? d.z : 0u) + (s3 ? d.w : 0u);
+    if ((m.x & m.y & m.z & m.w) != kInf) mail[q] = make_uint4(kInf, kInf, kInf, kInf);  // consumed
+    if (s0 || s1 || s2 || s3) val[q] = make_uint4(s0 ? m.x : x.x, s1 ? m.y : x.y, s2 ? m.z : x.z, s3 ? m.w : x.w);
+    out[q] = make_uint4(s0 ? m.x : kInf, s1 ? m.y : kInf, s2 ? m.z : kInf, s3 ? m.w : kInf);
+  }
+  for (uint64_t v = 4 * nq + t0; v < a.n; v += stride) {
+    uint32_t msg = kInf;
+    const bool sends = compute_min(kStepDense, static_cast<uint32_t>(v), a.value, a.mail_in, msg);
+    a.outbox[v] = sends ? msg : kInf;
+    if (sends) {
+      senders += 1;
+      messages += a.outdeg[v];
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void minprop_apply_kernel(MinApplyArgs a) {
   __shared__ uint32_t s_lpre[kCtrSlots + 1];
   Active act = a.act;
@@ -376,8 +415,13 @@ __global__ __launch_bounds__(kBlock) void minprop_apply_kernel(MinApplyArgs a) {
     act.phase = kStepDense;
     act.count = a.n;
   }
-  load_list_prefix(act, s_lpre);
   uint64_t senders = 0, messages = 0;
+  if (act.phase == kStepDense && !a.sent) {  // uniform over the grid
+    apply_dense4(a, senders, messages);
+    flush_counters(a.ctr, senders, messages, 0, 0, 0);
+    return;
+  }
+  load_list_prefix(act, s_lpre);
   // wavefront-uniform rounds (the sender bitmap is set a wavefront at a time)
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const uint64_t first = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~static_cast<uint32_t>(kWave - 1));
@@ -905,7 +949,10 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
       ap.ctl = ctl;
       ap.n = n;
       ap.sent = gating ? w.sent : nullptr;
-      const uint32_t grid = device ? gv : grid_for(act.count, kBlock, 8192);
+      // the dense form without the sender bitmap takes four vertices per thread
+      const bool dense4 = (device || act.phase == kStepDense) && !gating;
+      const uint32_t grid = dense4 ? grid_for((static_cast<uint64_t>(n) + 3) / 4, kBlock, 16384)
+                                   : (device ? gv : grid_for(act.count, kBlock, 8192));
       hipLaunchKernelGGL(minprop_apply_kernel, dim3(grid), dim3(kBlock), 0, s, ap);
       IPG_HIP(hipGetLastError());
       if (gating) {
