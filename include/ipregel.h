@@ -69,8 +69,9 @@ typedef enum { IPG_MODE_AUTO = 0, IPG_MODE_PUSH = 1, IPG_MODE_PULL = 2 } ipg_mod
 #define IPG_GRAPH_BLOCKED 8u   /* keep destination-blocked in-edges for PageRank's pull exchange (of the
                                   hot-first CSC with IPG_GRAPH_RENAME): the destinations are cut into runs of
                                   at most 20224 consecutive rows whose FP64 sums fit one workgroup's LDS
-                                  (closed early at 8/256 of the edges, so rows with many in-edges form narrow
-                                  blocks), and each block's in-edges are stored sorted by source, 4 bytes per
+                                  (closed early at 8/256 of the edges -- or, when the row-capped blocks
+                                  outnumber the 256 slices, at twice their mean edges -- so rows with many
+                                  in-edges form narrow blocks), and each block's in-edges are stored sorted by source, 4 bytes per
                                   edge, so that a wavefront's outbox reads share cache lines.  Every superstep
                                   streams the blocks and adds each message into its destination's sum in LDS;
                                   blocks spread over several workgroups add their partial sums in a fixed

@@ -63,16 +63,21 @@ inline uint32_t blk_target_slices(uint64_t e) {
   const uint64_t s = (e + kBlkMinSliceEdges - 1) / kBlkMinSliceEdges;
   return static_cast<uint32_t>(s < 1 ? 1 : (s > kBlkSlices ? kBlkSlices : s));
 }
-// Edges at which a block closes.
-inline uint64_t blk_edge_target(uint64_t e) {
-  const uint64_t t = kBlkEdgeFactor * e / blk_target_slices(e);
+// Edges at which a block closes: kBlkEdgeFactor / S of the edges; on a
+// graph whose row-capped blocks alone outnumber the S slices (blocks then
+// run in several rounds, most as one slice), twice the mean edges of a
+// row-capped block instead, so that dense rows form narrow blocks rather
+// than a few blocks of E / 32 edges that one workgroup each would stream.
+inline uint64_t blk_edge_target(uint32_t n, uint64_t e) {
+  const uint64_t s = blk_target_slices(e), row_blocks = n / kBlkRows + 1;
+  const uint64_t t = row_blocks >= s ? 2 * e / row_blocks : kBlkEdgeFactor * e / s;
   return t < 1 ? 1 : t;
 }
 inline uint64_t blk_windows(uint32_t n) { return (static_cast<uint64_t>(n) + (1u << kBlkWinBits) - 1) >> kBlkWinBits; }
 // Blocks: one closed by the row cap takes kBlkRows rows; two consecutive
 // blocks closed by the edge target hold more than the target together.
 inline uint64_t blk_blocks_cap(uint32_t n, uint64_t e) {
-  const uint64_t by_rows = n / kBlkRows + 1, by_edges = 2 * e / blk_edge_target(e) + 2;
+  const uint64_t by_rows = n / kBlkRows + 1, by_edges = 2 * e / blk_edge_target(n, e) + 2;
   return by_rows + by_edges;
 }
 // Chunks: at most one partial chunk per non-empty (block, window) segment.
@@ -117,7 +122,7 @@ inline const char* blocked_layout(uint32_t n, uint64_t e, const uint64_t* off, c
   // blocks: runs of consecutive rows, closed before the row that would take
   // them past the edge target (a row above it alone forms a block) or at
   // kBlkRows rows
-  const uint64_t target = blk_edge_target(e);
+  const uint64_t target = blk_edge_target(n, e);
   std::vector<uint32_t> row0{0};
   std::vector<uint32_t> blk_of(n);
   {
@@ -189,12 +194,15 @@ inline const char* blocked_layout(uint32_t n, uint64_t e, const uint64_t* off, c
   }
   cfirst[nblk] = chunks.size();
   if (chunks.size() > blk_chunks_cap(n, e)) return "blocked chunk table overflow";
-  // slices: with fewer blocks than S (about one slice per CU, and only one
-  // workgroup fits a CU's LDS), at most S slices in one even wave: block b
-  // gets K_b = ceil(C_b / L) slices (at least one, at most one per chunk),
-  // C_b its chunks' cost, for the smallest limit L with sum K_b <= S, which
-  // minimises the largest slice; else one slice per block.  A block's
-  // slices hold about equal costs.
+  // slices.  With fewer blocks than S (about one slice per CU, and only one
+  // workgroup fits a CU's LDS): at most S slices in one even wave -- block
+  // b gets K_b = ceil(C_b / L) slices (at least one, at most one per
+  // chunk), C_b its chunks' cost, for the smallest limit L with
+  // sum K_b <= S, which minimises the largest slice.  With more: the blocks
+  // run in several rounds, one slice each, except those costlier than L,
+  // cut into K_b slices, for the smallest L whose cut blocks' partial sums
+  // (K_b x rows each) fit the partial buffer and add at most S slices.  A
+  // block's slices hold about equal costs.
   std::vector<uint64_t> cb(nblk, 0);
   uint64_t ctotal = 0;
   for (uint64_t blk = 0; blk < nblk; ++blk) {
@@ -205,24 +213,34 @@ inline const char* blocked_layout(uint32_t n, uint64_t e, const uint64_t* off, c
   std::vector<uint64_t> kb(nblk, 1);
   uint64_t nonempty = 0;
   for (uint64_t blk = 0; blk < nblk; ++blk) nonempty += cfirst[blk + 1] != cfirst[blk];
-  if (nonempty < S && e) {
-    auto slices_for = [&](uint64_t L, std::vector<uint64_t>* out) {
-      uint64_t total = 0;
+  if (e) {
+    const bool one_wave = nonempty < S;
+    // slices (of the blocks with edges) and partial rows under limit L
+    auto cut = [&](uint64_t L, std::vector<uint64_t>* out, uint64_t* prow) {
+      uint64_t total = 0, rows_cut = 0;
       for (uint64_t blk = 0; blk < nblk; ++blk) {
         const uint64_t nc = cfirst[blk + 1] - cfirst[blk];
         const uint64_t k = std::max<uint64_t>(1, std::min((cb[blk] + L - 1) / L, std::max<uint64_t>(nc, 1)));
         if (out) (*out)[blk] = k;
         if (nc) total += k;  // a block without edges only writes 0.15/N: not counted
+        if (k > 1) rows_cut += k * (row0[blk + 1] - row0[blk]);
       }
+      *prow = rows_cut;
       return total;
     };
-    uint64_t lo = 1, hi = ctotal;  // slices_for(ctotal) == nonempty <= S
+    auto fits = [&](uint64_t L) {
+      uint64_t prow = 0;
+      const uint64_t total = cut(L, nullptr, &prow);
+      return one_wave ? total <= S : (prow <= blk_partial_cap(e) && total <= nonempty + S);
+    };
+    uint64_t lo = 1, hi = ctotal;  // cut(ctotal): one slice per block, which fits either way
     while (lo < hi) {
       const uint64_t mid = lo + (hi - lo) / 2;
-      if (slices_for(mid, nullptr) <= S) hi = mid;
+      if (fits(mid)) hi = mid;
       else lo = mid + 1;
     }
-    slices_for(lo, &kb);
+    uint64_t prow = 0;
+    cut(lo, &kb, &prow);
   }
   std::vector<BlkSlice> slices;
   std::vector<BlkGroup> groups;

@@ -9,7 +9,8 @@
 //   * chunks tile [0, E) in order, hold 1 .. kBlkChunk edges, never leave
 //     their source window, never straddle two blocks;
 //   * each block's chunks are cut into K contiguous, non-empty slices, at
-//     most S in all when fewer than S blocks have edges, else one per block;
+//     most S in all when fewer than S blocks have edges, else adding at
+//     most S slices to one per block;
 //   * partial-sum offsets: none for a one-slice block, K disjoint runs of
 //     the block's rows otherwise, within the stated bound;
 //   * finish groups cover exactly the rows of the multi-slice and edge-less
@@ -67,7 +68,7 @@ int main(int argc, char** argv) {
   const size_t nb = R0.size() - 1;
   if (R0.empty() || R0.front() != 0 || R0.back() != n) return fail("block starts");
   if (nb > blk_blocks_cap(n, e)) return fail("block cap");
-  const uint64_t target = blk_edge_target(e);
+  const uint64_t target = blk_edge_target(n, e);
   auto deg = [&](uint32_t v) { return off[(size_t)v + 1] - off[v]; };
   std::vector<uint64_t> bedges(nb, 0);
   for (size_t b = 0; b < nb; ++b) {
@@ -168,8 +169,8 @@ int main(int argc, char** argv) {
   }
   if (nonempty < S) {
     if (e && ksum > S) return fail("more slices than the target");
-  } else if (maxk > 1) {
-    return fail("several slices per block although every CU has a block");
+  } else if (ksum > nonempty + S) {
+    return fail("cut blocks add more than S slices");
   }
   std::sort(runs.begin(), runs.end());
   for (size_t i = 0; i < runs.size(); ++i) {

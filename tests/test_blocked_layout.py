@@ -117,6 +117,16 @@ def test_hot_first_order(checker):
     assert s["blocks"] > 1
 
 
+def test_many_row_blocks_cut_dense_blocks(checker):
+    # 8.4M vertices: more row-capped blocks (415) than slices (256), so the
+    # blocks run in rounds; the dense rows form narrow blocks (at most twice
+    # the mean edges of a row-capped block) and the costliest blocks are cut
+    # into slices with partial sums
+    hg = graphgen.rmat(23, 4, seed=5)
+    s = check_graph(checker, hg)
+    assert s["blocks"] > 415 and s["slices"] > s["blocks"] - 2 and s["partial"] > 0
+
+
 def test_rejects_malformed_csc(checker):
     assert run_check(checker, 3, [0, 1, 2, 2], [0, 5]).startswith("ERR CSC source id")
     assert run_check(checker, 3, [0, 2, 1, 2], [0, 1]).startswith("ERR offsets decreasing")

@@ -157,6 +157,23 @@ def test_parts_converge_and_replay(ipg):
         assert max_rel(ipg.values_to_numpy(e), oracle.run_graph("pagerank", hg, 4).values) <= PR_RTOL
 
 
+def test_more_row_blocks_than_slices(ipg):
+    # 8.4M vertices: 415 row-capped blocks, more than the 256 slices of a
+    # wave, so blocks run in rounds; dense rows form narrow blocks and the
+    # costliest are cut into slices with partial sums
+    hg = graphgen.rmat(23, 4, seed=5)
+    g = ipg.Graph.from_host(hg, blocked=True)
+    for T in (1, 3):
+        ref = oracle.run_graph("pagerank", hg, T)
+        vals, st = g.run("pagerank", T, mode="pull")
+        assert max_rel(ipg.values_to_numpy(vals), ref.values) <= PR_RTOL
+        assert np.array_equal(st.trace, ref.trace)
+    ref = oracle.run_graph("cc", hg, 0)
+    for persistent in (False, True):
+        vals, st = g.run("cc", mode="pull", persistent=persistent)
+        assert np.array_equal(ipg.values_to_numpy(vals), ref.values) and np.array_equal(st.trace, ref.trace)
+
+
 def test_full_size_rmat_s20_symmetrised(ipg):
     # the benchmark's graph and launch path (hot-first store + blocked in-edges)
     hg = graphgen.workload("rmat-s20-sym")
