@@ -68,7 +68,8 @@ def candidates(graph, app: str) -> list:
     """The parameter sets tried for `app` on this graph: the product of the
     application's space; on a graph with blocked in-edges also the blocked
     pull (PageRank: no launch parameters; CC/SSSP: the exchange rule's
-    divisors) before the row-item pull over the space."""
+    divisors, with and without the sender gate) before the row-item pull
+    over the space."""
     space = SPACES[app]
     names = sorted(space)
     out = [dict(zip(names, combo)) for combo in itertools.product(*(space[k] for k in names))]
@@ -76,9 +77,9 @@ def candidates(graph, app: str) -> list:
         if app == "pagerank":
             out = [{"blocked": 0}] + [dict(t, blocked=0xFFFFFFFF) for t in out]
         elif app in ("cc", "sssp"):
-            # the blocked pull has no grid or gate; the rule's divisors still matter
-            blk = [dict(zip(("list_div", "push_div"), c), blocked=0)
-                   for c in itertools.product(space["list_div"], space["push_div"])]
+            # the blocked pull has no grid; the rule's divisors and the sender gate still matter
+            blk = [dict(zip(("list_div", "push_div", "gate_div"), c), blocked=0)
+                   for c in itertools.product(space["list_div"], space["push_div"], (0, 0xFFFFFFFF))]
             out = blk + [dict(t, blocked=0xFFFFFFFF) for t in out]
     return out
 

@@ -587,6 +587,8 @@ struct MinBlkArgs {
   CtrSlot* ctr;
   CtrSlot* ctr_clear;
   const DevCtl* ctl;  // device-driven loop: run only when it chose pull (else null)
+  const uint32_t* sent;  // bitmap of the senders, consulted when *gate is set (gate null: never)
+  const uint32_t* gate;
 };
 
 // Counters of a workgroup of any width: summed over its wavefronts in LDS,
@@ -629,9 +631,18 @@ __global__ __launch_bounds__(kBlkThreads) void minprop_blocked_kernel(MinBlkArgs
   __syncthreads();
   uint32_t overflow = 0;
   const uint32_t* outbox = a.outbox;
-  blk_stream<uint32_t>(
-      a.v, sl, kInf, [&](uint32_t wbase, uint32_t q) { return outbox[wbase + (q >> 16)]; },
-      [&](uint32_t slot, uint32_t o) { atomicMin(&part[slot], edge_msg<APP, false>(o, 1u, overflow)); });
+  const uint32_t* sent = (a.gate && *a.gate) ? a.sent : nullptr;  // uniform over the grid
+  auto combine = [&](uint32_t slot, uint32_t o) { atomicMin(&part[slot], edge_msg<APP, false>(o, 1u, overflow)); };
+  if (sent)  // few senders: a source's outbox is read only when its bit is set
+    blk_stream<uint32_t>(
+        a.v, sl, kInf,
+        [&](uint32_t wbase, uint32_t q) {
+          const uint32_t u = wbase + (q >> 16);
+          return row_live(sent, static_cast<int32_t>(u)) ? outbox[u] : kInf;
+        },
+        combine);
+  else
+    blk_stream<uint32_t>(a.v, sl, kInf, [&](uint32_t wbase, uint32_t q) { return outbox[wbase + (q >> 16)]; }, combine);
   __syncthreads();
   const uint32_t r0 = sl.row0, rows = sl.rows;
   uint64_t next_count = 0, next_deg = 0;
@@ -932,7 +943,7 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
     // the blocked in-edges of the caller's CSC (CC, unit-weight SSSP), if the store has them
     const BlockedTables* bt = nullptr;
     if (tn.blocked && !weighted) bt = g->t.blk_ids.edges ? &g->t.blk_ids : (g->t.blk.edges && !g->t.perm ? &g->t.blk : nullptr);
-    const bool gating = step > 0 && tn.gate_div != 0 && !bt;  // the blocked pull reads every outbox
+    const bool gating = step > 0 && tn.gate_div != 0;
     if (step > 0) {
       if (!device) IPG_HIP(fill_u32(w.outbox, n, kInf, s));
       if (gating) IPG_HIP(fill_u32(w.sent, (uint64_t)n / 64 * 2 + 2, 0, s));
@@ -969,6 +980,8 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
       ba.ctr = b.c;
       ba.ctr_clear = b.cc;
       ba.ctl = ctl;
+      ba.sent = w.sent;
+      ba.gate = gating ? w.gate : nullptr;
       if (bt->nslices) {
         if (app == IPG_APP_CC_HASHMIN)
           hipLaunchKernelGGL(minprop_blocked_kernel<IPG_APP_CC_HASHMIN>, dim3(bt->nslices), dim3(kBlkThreads), 0, s, ba);
