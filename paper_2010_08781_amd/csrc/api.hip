@@ -18,6 +18,7 @@ size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w) {
     r.part_n = c.take<uint32_t>(nn);
     r.l1 = c.take<double>(kCtrSlots * 16);  // one 128-byte line per slot
     r.value_hot = c.take<double>(nn);
+    r.pr_pieces = c.take<PrPiece>(kCtrSlots * piece_seg(e));
   } else {
     r.value_u32 = c.take<uint32_t>(nn);
     r.mail_a = c.take<uint32_t>(nn);

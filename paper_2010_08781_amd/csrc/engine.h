@@ -112,6 +112,14 @@ inline uint64_t piece_seg(uint64_t e) { return (e / kPiece + e / kPieceMin) / kC
 // segment drops the list for that superstep (the next one sweeps the
 // mailboxes instead).
 inline uint32_t list_seg(uint32_t n) { return n / kCtrSlots + 64; }
+// A piece of a PageRank push superstep: the sender's contribution instead
+// of a u32 message.
+struct PrPiece {
+  unsigned long long beg;  // first CSR edge
+  uint32_t n;              // edges (0 = an unused entry, 1 .. kPiece)
+  uint32_t pad;
+  double c;                // the sender's rank / out-degree
+};
 
 // Run workspace, carved from the caller's device buffer.
 struct RunWs {
@@ -123,6 +131,7 @@ struct RunWs {
   uint32_t* part_n;   // [n] vertex count of each vertex's part (disjoint unions)
   double* l1;         // [kCtrSlots] L1 change of an update, spread over slots (convergence runs)
   double* value_hot;  // [n] ranks under the hot-first names (renamed store), mapped back at the end
+  PrPiece* pr_pieces; // [kCtrSlots * piece_seg(e)] piece queue of a push superstep
   // CC / SSSP
   uint32_t* value_u32;  // [n] labels or distances
   uint32_t* mail_a;     // [n] one-slot min mailboxes, ping (INF = empty)

@@ -422,12 +422,53 @@ struct PrPushArgs {
   const uint32_t* part_n;
   double* l1;            // convergence run: rank stored every superstep, its L1 change added here
   int first, last;
+  PrPiece* pieces;       // piece queue (see kPieceMin)
+  uint64_t piece_seg;
+  CtrSlot* ctr;          // this superstep's slots (piece counts)
+  CtrSlot* ctr_clear;    // the next superstep's, cleared here
 };
+
+// Queue the out-edges of this wavefront's senders that have at least
+// kPieceMin of them as pieces in the workgroup's segment (one atomic per
+// wavefront, on the slot's counter); returns whether the lane still expands
+// its sender itself (also when the segment is full: its entries are then
+// marked unused).  All lanes of the wavefront call it together.
+__device__ __forceinline__ bool pr_queue_pieces(const PrPushArgs& a, bool has, uint64_t beg, uint64_t end, double c) {
+  const uint64_t d = has ? end - beg : 0;
+  const uint32_t np = d >= kPieceMin ? static_cast<uint32_t>((d + kPiece - 1) / kPiece) : 0u;
+  if (__ballot(np != 0) == 0) return has;  // uniform
+  const uint32_t lane = lane_id();
+  uint32_t inc = np;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t t = __shfl_up(inc, o);
+    if (lane >= static_cast<uint32_t>(o)) inc += t;
+  }
+  const uint32_t total = __shfl(inc, kWave - 1);
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(&my_slot(a.ctr)->pieces, total);
+  base = __shfl(base, 0);
+  if (np == 0) return has;
+  const uint64_t first = static_cast<uint64_t>(base) + (inc - np);
+  const bool fits = first + np <= a.piece_seg;
+  PrPiece* seg = a.pieces + static_cast<uint64_t>(blockIdx.x % kCtrSlots) * a.piece_seg;
+  for (uint32_t k = 0; k < np && first + k < a.piece_seg; ++k) {
+    const uint64_t b = beg + static_cast<uint64_t>(k) * kPiece;
+    PrPiece p;
+    p.beg = b;
+    p.n = fits ? static_cast<uint32_t>(min(static_cast<uint64_t>(kPiece), end - b)) : 0u;
+    p.pad = 0;
+    p.c = c;
+    seg[first + k] = p;
+  }
+  return !fits;
+}
 
 // Fused compute + push for one superstep: every vertex consumes its mailbox,
 // updates its rank and (unless last) adds rank/outdeg into each
 // out-neighbour's next mailbox.
 __global__ __launch_bounds__(kBlock) void pr_push_kernel(PrPushArgs a) {
+  clear_slots(a.ctr_clear);
   const uint64_t v = blockIdx.x * (uint64_t)kBlock + threadIdx.x;
   double l1 = 0.0;
   bool has = false;
@@ -451,10 +492,72 @@ __global__ __launch_bounds__(kBlock) void pr_push_kernel(PrPushArgs a) {
       if (has) c = rank / static_cast<double>(end - beg);
     }
   }
+  if (!a.last) has = pr_queue_pieces(a, has, beg, end, c);  // uniform condition
   double* mail = a.mail_out;
   const int32_t* dst = a.dst;
   twc_scatter(has, beg, end, c, [&](uint64_t e, double p) { unsafeAtomicAdd(mail + dst[e], p); });
   if (a.l1) flush_l1(a.l1, l1);
+}
+
+// Second launch of a push superstep: the queued pieces dealt over the grid
+// (piece g, counted over the segments in slot order, to workgroup
+// g mod grid), kPiece / kBlock edges per thread with their loads issued
+// together.
+__global__ __launch_bounds__(kBlock) void pr_push_piece_kernel(PrPushArgs a) {
+  __shared__ uint32_t s_pre[kCtrSlots + 1];
+  if (threadIdx.x < kWave) {  // prefix of the segments' lengths (one wavefront)
+    const uint32_t lane = lane_id();
+    const uint32_t cnt = static_cast<uint32_t>(min(static_cast<uint64_t>(a.ctr[lane].pieces), a.piece_seg));
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t t = __shfl_up(inc, o);
+      if (lane >= static_cast<uint32_t>(o)) inc += t;
+    }
+    s_pre[lane + 1] = inc;
+    if (lane == 0) s_pre[0] = 0;
+  }
+  __syncthreads();
+  const uint32_t total = s_pre[kCtrSlots];
+  double* mail = a.mail_out;
+  for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {  // uniform over the workgroup
+    uint32_t lo = 0, hi = kCtrSlots - 1;  // the last segment k with s_pre[k] <= g
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (s_pre[mid] <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    const PrPiece pc = a.pieces[static_cast<uint64_t>(lo) * a.piece_seg + (g - s_pre[lo])];
+    constexpr int kPer = kPiece / kBlock;
+    uint32_t x[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const uint32_t j = threadIdx.x + k * kBlock;
+      x[k] = j < pc.n ? static_cast<uint32_t>(a.dst[pc.beg + j]) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (threadIdx.x + k * kBlock < pc.n) unsafeAtomicAdd(mail + x[k], pc.c);
+  }
+}
+
+// Grid of the piece launch.
+constexpr uint32_t kPrPieceGrid = 2048;
+
+// One push superstep: the compute + scatter launch, then (unless it is the
+// last, which sends nothing) the piece launch.  The counter slots
+// alternate by superstep parity; each superstep clears the next one's.
+static hipError_t launch_pr_push(PrPushArgs a, const RunWs& w, uint64_t e, uint32_t grid, uint32_t step,
+                                 hipStream_t s) {
+  a.pieces = w.pr_pieces;
+  a.piece_seg = piece_seg(e);
+  a.ctr = w.ctr + (step & 1) * kCtrSlots;
+  a.ctr_clear = w.ctr + ((step + 1) & 1) * kCtrSlots;
+  hipLaunchKernelGGL(pr_push_kernel, dim3(grid), dim3(kBlock), 0, s, a);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess || a.last) return err;
+  hipLaunchKernelGGL(pr_push_piece_kernel, dim3(kPrPieceGrid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ host --
@@ -598,6 +701,8 @@ static hipError_t enqueue_pagerank(ipg_graph* g, uint32_t T, bool push, const Ru
   } else {
     if ((err = fill_f64(w.f64_a, n, 0.0, s)) != hipSuccess) return err;
     if ((err = fill_f64(w.f64_b, n, 0.0, s)) != hipSuccess) return err;
+    if ((err = fill_u32(reinterpret_cast<uint32_t*>(w.ctr), 2 * kCtrSlots * sizeof(CtrSlot) / 4, 0, s)) != hipSuccess)
+      return err;
     if (tm && (err = tm->start(s)) != hipSuccess) return err;
     PrPushArgs a;
     a.n = n;
@@ -614,8 +719,7 @@ static hipError_t enqueue_pagerank(ipg_graph* g, uint32_t T, bool push, const Ru
       a.mail_out = (step & 1) ? w.f64_a : w.f64_b;
       a.first = step == 0;
       a.last = step == T;
-      hipLaunchKernelGGL(pr_push_kernel, dim3(grid), dim3(kBlock), 0, s, a);
-      if ((err = hipGetLastError()) != hipSuccess) return err;
+      if ((err = launch_pr_push(a, w, g->e, grid, step, s)) != hipSuccess) return err;
       if (tm && (err = tm->step(s, step)) != hipSuccess) return err;
     }
   }
@@ -736,6 +840,7 @@ static ipg_status run_pagerank_converge(ipg_graph* g, uint32_t Tmax, bool push, 
   } else {
     IPG_HIP(fill_f64(w.f64_a, n, 0.0, s));
     IPG_HIP(fill_f64(w.f64_b, n, 0.0, s));
+    IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.ctr), 2 * kCtrSlots * sizeof(CtrSlot) / 4, 0, s));
     IPG_HIP(tm.start(s));
     PrPushArgs a;
     a.n = n;
@@ -753,8 +858,7 @@ static ipg_status run_pagerank_converge(ipg_graph* g, uint32_t Tmax, bool push, 
       a.mail_out = (step & 1) ? w.f64_a : w.f64_b;
       a.first = step == 0;
       a.last = step == Tmax;
-      hipLaunchKernelGGL(pr_push_kernel, dim3(grid), dim3(kBlock), 0, s, a);
-      IPG_HIP(hipGetLastError());
+      IPG_HIP(launch_pr_push(a, w, g->e, grid, step, s));
       IPG_HIP(tm.step(s, step));
       if (step == 0) continue;
       double d = 0.0;
