@@ -109,8 +109,10 @@ typedef struct {
 /* ipg_run_opts.flags */
 #define IPG_RUN_PERSISTENT 1u /* device-driven superstep loop (CC/SSSP): a control block in the workspace
                                  decides halt, active set and exchange on the device, superstep 0
-                                 included; the host enqueues supersteps in chunks of 2, 4, ... 64 and
-                                 synchronises once per chunk, with no per-superstep host sync */
+                                 included; the host enqueues supersteps in chunks -- first as many as
+                                 the last such run of the application on the handle took (else 2), then
+                                 doubling up to 64 -- and synchronises once per chunk, with no
+                                 per-superstep host sync */
 #define IPG_RUN_ENQUEUE 4u    /* enqueue the run's work on the stream and return at once, with no host
                                  synchronisation and no readback, so that the caller can capture it into a
                                  graph: PageRank (fixed T; part_offsets are not checked; no timing) and

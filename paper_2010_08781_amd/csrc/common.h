@@ -167,6 +167,7 @@ struct ipg_graph {
   // HIP events reused by every run's timing (created on first use)
   std::vector<hipEvent_t> events;
   int wall_khz;  // device wall-clock rate, queried on first use (0 until then)
+  uint32_t dd_steps[4];  // supersteps of the last device-driven run of each application (0: none yet)
   void* mirror;      // pinned host block the decide kernels write (created on first use)
   void* mirror_dev;  // its device address
 };

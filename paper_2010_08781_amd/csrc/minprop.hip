@@ -1091,7 +1091,12 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
   if (rc != IPG_OK) return rc;
   uint32_t enqueued = 0;  // supersteps whose launches are in the stream, minus one
   uint32_t recorded = 0;  // supersteps whose records were read
-  uint32_t chunk = 2;  // supersteps enqueued per readback: 2, 4, 8, ... 64
+  // supersteps enqueued per readback: first as many as the last device-driven
+  // run of this application on the handle took (repeated runs mostly take
+  // the same number, and then read back once; a longer guess costs only
+  // launches that return at once), else 2; then doubling, up to 64
+  const uint32_t last = g->dd_steps[static_cast<int>(app) & 3];
+  uint32_t chunk = last ? std::min<uint32_t>(std::max<uint32_t>(last, 2), 64) : 2;
   DevCtl h{};
   uint64_t tot_msgs = 0, tot_exam = 0;
   for (;;) {
@@ -1129,6 +1134,7 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
     chunk = std::min<uint32_t>(chunk * 2, 64);
   }
   IPG_HIP(tm.finish(s));
+  g->dd_steps[static_cast<int>(app) & 3] = h.step;
   if (st) {
     st->supersteps = h.step;
     st->halted = h.status == IPG_OK;
