@@ -183,20 +183,6 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
 }
 
-// Frontier compaction: every lane with `pred` appends `item` to `list`; one
-// atomic per wave reserves the slots (ballot -> popcount -> atomicAdd by the
-// lowest voting lane -> per-lane offset from mbcnt).  Safe in divergent code:
-// only active lanes vote and the leader is always an active voter.
-__device__ __forceinline__ void wave_append(bool pred, uint32_t item, uint32_t* list, uint32_t* counter) {
-  const uint64_t mask = __ballot(pred);
-  if (mask == 0) return;
-  const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(mask)) - 1);
-  uint32_t base = 0;
-  if (lane_id() == leader) base = atomicAdd(counter, static_cast<uint32_t>(__popcll(mask)));
-  base = __shfl(base, static_cast<int>(leader));
-  if (pred) list[base + lanes_below(mask)] = item;
-}
-
 // Bit v of a bitmap.
 __device__ __forceinline__ bool bit_of(const uint32_t* bm, uint32_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
 

@@ -84,6 +84,32 @@ def test_selector_drives_device_loop(ipg):
         check(ipg, hg, "sssp", modes=("auto",), selector=p)
 
 
+def test_first_chunk_from_previous_run(ipg):
+    # A run's first chunk is the previous device-driven run's superstep count
+    # for that application on the handle.  A long run (300 supersteps along a
+    # path) followed by short ones -- from the path's middle, and from an
+    # isolated vertex (one superstep), where most of the first chunk's
+    # supersteps return at once -- and a long one again, each matching the
+    # oracle; then a cap below the guessed chunk.
+    n = 300
+    hg = graphgen.from_edges(n + 1, np.arange(n - 1), np.arange(1, n), symmetric=True, name="path+isolated")  # vertex n: isolated
+    g = ipg.Graph.from_host(hg)
+    for source in (0, n // 2, n, 0, n):
+        ref = oracle.run_graph("sssp", hg, 0, source=source)
+        vals, st = g.run("sssp", source=source, mode="auto", persistent=True)
+        assert np.array_equal(ipg.values_to_numpy(vals), ref.values), source
+        assert st.supersteps == ref.supersteps and np.array_equal(st.trace, ref.trace), source
+    ref = oracle.run_graph("cc", hg, 0)
+    for _ in range(2):
+        vals, st = g.run("cc", persistent=True)
+        assert np.array_equal(ipg.values_to_numpy(vals), ref.values) and st.supersteps == ref.supersteps
+    g.run("sssp", source=0, persistent=True)  # the next guess: 300 supersteps, capped to a chunk of 64
+    ref = oracle.run_graph("sssp", hg, 5, source=0)
+    vals, st = g.run("sssp", 5, source=0, persistent=True)
+    assert st.status == ipg.NOT_CONVERGED and st.supersteps == 5 and not st.halted
+    assert np.array_equal(ipg.values_to_numpy(vals), ref.values) and np.array_equal(st.trace, ref.trace)
+
+
 def test_cap_and_overflow(ipg):
     import torch
 
