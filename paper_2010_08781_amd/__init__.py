@@ -348,8 +348,9 @@ class Graph:
                      parts.data_ptr() if parts is not None else None, parts.numel() - 1 if parts is not None else 0,
                      float(tol), ctypes.addressof(tun) if tun is not None else None)
         tr = self._trace(trace_cap, timing)
+        sh = _stream_handle(stream)
         rc = lib().ipg_run(self._h, a, comb, int(max_supersteps), ctypes.byref(opts),
-                           ws.data_ptr() if ws is not None else None, nbytes, _stream_handle(stream),
+                           ws.data_ptr() if ws is not None else None, nbytes, sh,
                            None if enqueue else ctypes.byref(tr.st))
         if enqueue:
             _check(rc, "ipg_run")
@@ -358,7 +359,7 @@ class Graph:
             _check(rc, "ipg_run", allow_not_converged=True)
         elif rc not in (OK, NOT_CONVERGED):
             return None, tr.stats(rc)
-        vals = self.read_values(a, stream=stream)
+        vals = self._values(a, sh, stream)
         return vals, tr.stats(rc)
 
     def run_multi_sssp(self, sources, max_supersteps: int = 0, mode: str = "auto", timing: bool = True,
@@ -407,12 +408,15 @@ class Graph:
         return tr.stats(rc)
 
     def read_values(self, app: int, stream=None):
+        return self._values(app, _stream_handle(stream), stream)
+
+    def _values(self, app: int, sh: int, stream):
         import torch
 
         dt = torch.float64 if app == APP_PAGERANK else torch.int32
         out = torch.empty(self.n, dtype=dt, device=self.device)
-        _check(lib().ipg_read_values(self._h, out.data_ptr(), out.numel() * out.element_size(), 1,
-                                     _stream_handle(stream)), "ipg_read_values")
+        _check(lib().ipg_read_values(self._h, out.data_ptr(), out.numel() * out.element_size(), 1, sh),
+               "ipg_read_values")
         if stream is not None:  # the copy is enqueued on `stream`: order torch's current stream after it
             torch.cuda.current_stream().wait_stream(stream)
         return out

@@ -85,11 +85,19 @@ hipError_t StepTimer::step(hipStream_t s, uint32_t k) {
   return hipEventRecord(ev, s);
 }
 
+hipError_t StepTimer::mark(hipStream_t s) {
+  hipEvent_t end;
+  hipError_t e = event(1, &end);
+  if (e != hipSuccess) return e;
+  marked_ = true;
+  return hipEventRecord(end, s);
+}
+
 hipError_t StepTimer::finish(hipStream_t s) {
   hipEvent_t end;
   hipError_t e = event(1, &end);
   if (e != hipSuccess) return e;
-  if ((e = hipEventRecord(end, s)) != hipSuccess) return e;
+  if (!marked_ && (e = hipEventRecord(end, s)) != hipSuccess) return e;
   if ((e = hipEventSynchronize(end)) != hipSuccess) return e;
   float ms = 0.f;
   if (started_ && (e = hipEventElapsedTime(&ms, (*pool_)[0], end)) != hipSuccess) return e;

@@ -164,6 +164,10 @@ class StepTimer {
       : pool_(pool), usec_(usec), cap_(usec ? cap : 0) {}
   hipError_t start(hipStream_t s);
   hipError_t step(hipStream_t s, uint32_t k);  // end of superstep k
+  // Record the end event now without waiting; finish() then waits for the
+  // last such record instead of recording one after the host has seen the
+  // halt (a loop that synchronises anyway saves a round trip to the device).
+  hipError_t mark(hipStream_t s);
   hipError_t finish(hipStream_t s);            // synchronises
   double seconds() const { return seconds_; }
 
@@ -173,6 +177,7 @@ class StepTimer {
   float* usec_;
   uint32_t cap_;
   bool started_ = false;
+  bool marked_ = false;
   uint32_t nsteps_ = 0;  // supersteps recorded (k < nsteps_)
   double seconds_ = 0.0;
 };

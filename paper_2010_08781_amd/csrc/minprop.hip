@@ -1015,11 +1015,22 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
 }
 
 // State before superstep 0 shared by both loops: mailboxes empty, counters
-// zero.
+// zero (one launch for the three arrays).
+__global__ void minprop_clear_kernel(uint32_t* mail_a, uint32_t* mail_b, uint32_t n, uint32_t* ctr, uint32_t words) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  const uint64_t t = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  for (uint64_t i = t; i < n; i += stride) {
+    mail_a[i] = kInf;
+    mail_b[i] = kInf;
+  }
+  for (uint64_t i = t; i < words; i += stride) ctr[i] = 0;
+}
 static ipg_status clear_minprop(const ipg_graph* g, const RunWs& w, hipStream_t s) {
-  IPG_HIP(fill_u32(w.mail_a, g->n, kInf, s));
-  IPG_HIP(fill_u32(w.mail_b, g->n, kInf, s));
-  IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.ctr), 2 * kCtrSlots * sizeof(CtrSlot) / 4, 0, s));
+  const uint32_t n = g->n;
+  const uint32_t words = 2 * kCtrSlots * sizeof(CtrSlot) / 4;
+  hipLaunchKernelGGL(minprop_clear_kernel, dim3(grid_for(std::max(n, words), kBlock * 4, 8192)), dim3(kBlock), 0, s,
+                     w.mail_a, w.mail_b, n, reinterpret_cast<uint32_t*>(w.ctr), words);
+  IPG_HIP(hipGetLastError());
   return IPG_OK;
 }
 
@@ -1113,6 +1124,7 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
       IPG_HIP(hipGetLastError());
     }
     enqueued += chunk;
+    IPG_HIP(tm.mark(s));  // the run's end if this chunk holds the halt
     IPG_HIP(hipStreamSynchronize(s));
     h = hm->ctl;  // as the chunk's last decide (before or at the halt) left it
     for (; recorded < h.step; ++recorded) {
