@@ -239,20 +239,15 @@ __device__ __forceinline__ bool queue_pieces(const MinPushArgs& a, bool has, uin
 // Recipients whose mailbox was empty are appended to the next-frontier list
 // by wave-ballot compaction (one atomic per wave and ballot, on the slot's
 // counter).
+// The kernel's work for the active set `act` by the first `grid`
+// workgroups of the launch.
 template <int APP, bool W>
-__global__ __launch_bounds__(kBlock) void minprop_push_kernel(MinPushArgs a) {
-  __shared__ uint32_t s_lpre[kCtrSlots + 1];
-  Active act = a.act;
-  if (a.ctl) {
-    const DevCtl c = *a.ctl;
-    if (c.halted || c.mode != IPG_MODE_PUSH) return;  // uniform over the grid
-    act = device_active(c, a.act, a.act.list, a.n);
-  }
+__device__ __forceinline__ void push_body(const MinPushArgs& a, const Active& act, uint32_t grid, uint32_t* s_lpre) {
   load_list_prefix(act, s_lpre);
   clear_slots(a.ctr_clear);
   uint64_t senders = 0, messages = 0, next_count = 0, next_deg = 0;
   uint32_t overflow = 0;
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  const uint64_t stride = (uint64_t)grid * kBlock;
   for (uint64_t base = blockIdx.x * (uint64_t)kBlock; base < act.count; base += stride) {
     const uint64_t i = base + threadIdx.x;
     bool has = false;
@@ -274,6 +269,17 @@ __global__ __launch_bounds__(kBlock) void minprop_push_kernel(MinPushArgs a) {
     });
   }
   flush_counters(a.ctr, senders, messages, next_count, next_deg, overflow);
+}
+template <int APP, bool W>
+__global__ __launch_bounds__(kBlock) void minprop_push_kernel(MinPushArgs a) {
+  __shared__ uint32_t s_lpre[kCtrSlots + 1];
+  Active act = a.act;
+  if (a.ctl) {
+    const DevCtl c = *a.ctl;
+    if (c.halted || c.mode != IPG_MODE_PUSH) return;  // uniform over the grid
+    act = device_active(c, a.act, a.act.list, a.n);
+  }
+  push_body<APP, W>(a, act, gridDim.x, s_lpre);
 }
 
 // The messages of one piece: a workgroup, kPiece / kBlock edges per thread
@@ -315,12 +321,7 @@ __device__ __forceinline__ void push_piece(const MinPushArgs& a, const Piece& pc
 // (piece g, counted over the segments in slot order, to workgroup
 // g mod grid).
 template <int APP, bool W>
-__global__ __launch_bounds__(kBlock) void minprop_piece_kernel(MinPushArgs a) {
-  __shared__ uint32_t s_pre[kCtrSlots + 1];
-  if (a.ctl) {
-    const DevCtl c = *a.ctl;
-    if (c.halted || c.mode != IPG_MODE_PUSH) return;
-  }
+__device__ __forceinline__ void piece_body(const MinPushArgs& a, uint32_t grid, uint32_t* s_pre) {
   if (threadIdx.x < kWave) {  // prefix of the segments' lengths (one wavefront)
     const uint32_t lane = lane_id();
     const uint32_t cnt = static_cast<uint32_t>(min(static_cast<uint64_t>(a.ctr[lane].pieces), a.piece_seg));
@@ -338,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void minprop_piece_kernel(MinPushArgs a) {
   if (blockIdx.x >= total) return;  // uniform: no piece, nothing to count
   uint64_t next_count = 0, next_deg = 0;
   uint32_t overflow = 0;
-  for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {  // uniform over the workgroup
+  for (uint32_t g = blockIdx.x; g < total; g += grid) {  // uniform over the workgroup
     uint32_t lo = 0, hi = kCtrSlots - 1;  // the last segment k with s_pre[k] <= g
     while (lo < hi) {
       const uint32_t mid = (lo + hi + 1) >> 1;
@@ -349,6 +350,15 @@ __global__ __launch_bounds__(kBlock) void minprop_piece_kernel(MinPushArgs a) {
     push_piece<APP, W>(a, pc, next_count, next_deg, overflow);
   }
   flush_counters(a.ctr, 0, 0, next_count, next_deg, overflow);
+}
+template <int APP, bool W>
+__global__ __launch_bounds__(kBlock) void minprop_piece_kernel(MinPushArgs a) {
+  __shared__ uint32_t s_pre[kCtrSlots + 1];
+  if (a.ctl) {
+    const DevCtl c = *a.ctl;
+    if (c.halted || c.mode != IPG_MODE_PUSH) return;
+  }
+  piece_body<APP, W>(a, gridDim.x, s_pre);
 }
 
 struct MinApplyArgs {
@@ -372,9 +382,10 @@ struct MinApplyArgs {
 // (rewritten only when one of the four holds a message), lower the values,
 // and write every outbox slot -- the new value for a vertex that
 // broadcasts, INF otherwise.  The last N mod 4 vertices one per thread.
-__device__ __forceinline__ void apply_dense4(const MinApplyArgs& a, uint64_t& senders, uint64_t& messages) {
+__device__ __forceinline__ void apply_dense4(const MinApplyArgs& a, uint32_t grid, uint64_t& senders,
+                                             uint64_t& messages) {
   const uint64_t nq = a.n / 4;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t stride = (uint64_t)grid * blockDim.x;
   const uint64_t t0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   uint4* mail = reinterpret_cast<uint4*>(a.mail_in);
   uint4* val = reinterpret_cast<uint4*>(a.value);
@@ -406,24 +417,18 @@ __device__ __forceinline__ void apply_dense4(const MinApplyArgs& a, uint64_t& se
   }
 }
 
-__global__ __launch_bounds__(kBlock) void minprop_apply_kernel(MinApplyArgs a) {
-  __shared__ uint32_t s_lpre[kCtrSlots + 1];
-  Active act = a.act;
-  if (a.ctl) {
-    const DevCtl c = *a.ctl;
-    if (c.halted || c.mode != IPG_MODE_PULL) return;
-    act.phase = kStepDense;
-    act.count = a.n;
-  }
+// The compute for the active set `act` by the first `grid` workgroups of
+// the launch.
+__device__ __forceinline__ void apply_body(const MinApplyArgs& a, const Active& act, uint32_t grid, uint32_t* s_lpre) {
   uint64_t senders = 0, messages = 0;
   if (act.phase == kStepDense && !a.sent) {  // uniform over the grid
-    apply_dense4(a, senders, messages);
+    apply_dense4(a, grid, senders, messages);
     flush_counters(a.ctr, senders, messages, 0, 0, 0);
     return;
   }
   load_list_prefix(act, s_lpre);
   // wavefront-uniform rounds (the sender bitmap is set a wavefront at a time)
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t stride = (uint64_t)grid * blockDim.x;
   const uint64_t first = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~static_cast<uint32_t>(kWave - 1));
   for (uint64_t base = first; base < act.count; base += stride) {
     const uint64_t i = base + lane_id();
@@ -444,6 +449,37 @@ __global__ __launch_bounds__(kBlock) void minprop_apply_kernel(MinApplyArgs a) {
     if (a.sent) wave_set_bits(sends, v, a.sent);
   }
   flush_counters(a.ctr, senders, messages, 0, 0, 0);
+}
+__global__ __launch_bounds__(kBlock) void minprop_apply_kernel(MinApplyArgs a) {
+  __shared__ uint32_t s_lpre[kCtrSlots + 1];
+  Active act = a.act;
+  if (a.ctl) {
+    const DevCtl c = *a.ctl;
+    if (c.halted || c.mode != IPG_MODE_PULL) return;
+    act.phase = kStepDense;
+    act.count = a.n;
+  }
+  apply_body(a, act, gridDim.x, s_lpre);
+}
+
+// First launch of a device-driven superstep s >= 1: the push kernel's work
+// when the control block chose push, the pull form's compute when it chose
+// pull -- one launch where there were two, one of which returned at once.
+// Each part runs on its own grid; the workgroups beyond it return.
+template <int APP, bool W>
+__global__ __launch_bounds__(kBlock) void minprop_front_kernel(MinPushArgs p, MinApplyArgs ap, uint32_t push_grid,
+                                                               uint32_t apply_grid) {
+  __shared__ uint32_t s_lpre[kCtrSlots + 1];
+  const DevCtl c = *p.ctl;
+  if (c.halted) return;  // uniform over the grid
+  if (c.mode == IPG_MODE_PUSH) {
+    if (blockIdx.x < push_grid) push_body<APP, W>(p, device_active(c, p.act, p.act.list, p.n), push_grid, s_lpre);
+  } else if (c.mode == IPG_MODE_PULL) {
+    Active act = ap.act;
+    act.phase = kStepDense;
+    act.count = ap.n;
+    if (blockIdx.x < apply_grid) apply_body(ap, act, apply_grid, s_lpre);
+  }
 }
 
 // Between the compute and the exchange of a pull superstep: whether so few
@@ -665,10 +701,9 @@ __global__ __launch_bounds__(kBlkThreads) void minprop_blocked_kernel(MinBlkArgs
 // Blocked pull, second launch: the rows of every block with several slices
 // take the minimum of the slices' partials (a wavefront per group of 64
 // rows, every partial load in flight at once).
-__global__ __launch_bounds__(kBlock) void minprop_blocked_finish_kernel(MinBlkArgs a) {
-  if (a.ctl && (a.ctl->halted || a.ctl->mode != IPG_MODE_PULL)) return;
+__device__ __forceinline__ void blocked_finish_body(const MinBlkArgs& a, uint32_t grid) {
   const uint32_t lane = lane_id();
-  const uint32_t nw = gridDim.x * kWavesPerBlock;
+  const uint32_t nw = grid * kWavesPerBlock;
   uint64_t next_count = 0, next_deg = 0;
   for (uint32_t w = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; w < a.v.ngroups; w += nw) {  // wave-uniform
     const BlkGroup gr = a.v.groups[w];
@@ -689,6 +724,27 @@ __global__ __launch_bounds__(kBlock) void minprop_blocked_finish_kernel(MinBlkAr
     }
   }
   flush_counters(a.ctr, 0, 0, next_count, next_deg, 0);
+}
+__global__ __launch_bounds__(kBlock) void minprop_blocked_finish_kernel(MinBlkArgs a) {
+  if (a.ctl && (a.ctl->halted || a.ctl->mode != IPG_MODE_PULL)) return;
+  blocked_finish_body(a, gridDim.x);
+}
+
+// Last launch of a device-driven superstep s >= 1 over blocked in-edges:
+// the piece launch's work when the control block chose push, the blocked
+// pull's second launch when it chose pull (one launch where there were
+// two).  Each part runs on its own grid; the workgroups beyond it return.
+template <int APP, bool W>
+__global__ __launch_bounds__(kBlock) void minprop_back_kernel(MinPushArgs p, MinBlkArgs b, uint32_t piece_grid,
+                                                              uint32_t finish_grid) {
+  __shared__ uint32_t s_pre[kCtrSlots + 1];
+  const DevCtl c = *p.ctl;
+  if (c.halted) return;  // uniform over the grid
+  if (c.mode == IPG_MODE_PUSH) {
+    if (blockIdx.x < piece_grid) piece_body<APP, W>(p, piece_grid, s_pre);
+  } else if (c.mode == IPG_MODE_PULL) {
+    if (blockIdx.x < finish_grid) blocked_finish_body(b, finish_grid);
+  }
 }
 
 // End of a superstep: sum the counter slots (one wavefront, lane t reads
@@ -859,6 +915,35 @@ static hipError_t launch_pull(const MinPullArgs& a, uint32_t max_grid, hipStream
   return hipGetLastError();
 }
 
+// The front launch and, unless the back launch will run them, the pieces.
+template <int APP, bool W>
+static hipError_t launch_front(const MinPushArgs& a, const MinApplyArgs& ap, uint32_t push_grid, uint32_t apply_grid,
+                               bool pieces, hipStream_t s) {
+  hipLaunchKernelGGL((minprop_front_kernel<APP, W>), dim3(std::max(push_grid, apply_grid)), dim3(kBlock), 0, s, a, ap,
+                     push_grid, apply_grid);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess || !a.pieces || !pieces) return err;
+  hipLaunchKernelGGL((minprop_piece_kernel<APP, W>), dim3(kPieceGrid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+static hipError_t front_dispatch(ipg_app app, bool weighted, const MinPushArgs& a, const MinApplyArgs& ap,
+                                 uint32_t push_grid, uint32_t apply_grid, bool pieces, hipStream_t s) {
+  if (app == IPG_APP_CC_HASHMIN) return launch_front<IPG_APP_CC_HASHMIN, false>(a, ap, push_grid, apply_grid, pieces, s);
+  return weighted ? launch_front<IPG_APP_SSSP, true>(a, ap, push_grid, apply_grid, pieces, s)
+                  : launch_front<IPG_APP_SSSP, false>(a, ap, push_grid, apply_grid, pieces, s);
+}
+template <int APP, bool W>
+static hipError_t launch_back(const MinPushArgs& a, const MinBlkArgs& b, uint32_t finish_grid, hipStream_t s) {
+  hipLaunchKernelGGL((minprop_back_kernel<APP, W>), dim3(std::max(kPieceGrid, finish_grid)), dim3(kBlock), 0, s, a, b,
+                     kPieceGrid, finish_grid);
+  return hipGetLastError();
+}
+static hipError_t back_dispatch(ipg_app app, bool weighted, const MinPushArgs& a, const MinBlkArgs& b,
+                                uint32_t finish_grid, hipStream_t s) {
+  if (app == IPG_APP_CC_HASHMIN) return launch_back<IPG_APP_CC_HASHMIN, false>(a, b, finish_grid, s);
+  return weighted ? launch_back<IPG_APP_SSSP, true>(a, b, finish_grid, s)
+                  : launch_back<IPG_APP_SSSP, false>(a, b, finish_grid, s);
+}
 static hipError_t push_dispatch(ipg_app app, bool weighted, const MinPushArgs& a, uint32_t grid, hipStream_t s) {
   if (app == IPG_APP_CC_HASHMIN) return launch_push<IPG_APP_CC_HASHMIN, false>(a, grid, s);
   return weighted ? launch_push<IPG_APP_SSSP, true>(a, grid, s) : launch_push<IPG_APP_SSSP, false>(a, grid, s);
@@ -906,6 +991,11 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
   const uint32_t gv = grid_for(n, kBlock, 16384);
   const StepBufs b = bufs_for(w, step);
   const bool device = ctl != nullptr;
+  // device-driven superstep s >= 1: the push and the pull form's compute
+  // share one launch (minprop_front_kernel), made where the compute's was
+  const bool front = device && step > 0;
+  MinPushArgs front_push{};
+  uint32_t front_push_grid = 0;
   if (step == 0) {
     hipLaunchKernelGGL(minprop_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, static_cast<int>(app), source,
                        w.value_u32, g->t.outdeg, mode == IPG_MODE_PULL ? 1 : 0, w.outbox, b.c, ctl);
@@ -937,13 +1027,20 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
     a.pieces = pieces ? w.pieces : nullptr;
     a.piece_seg = piece_seg(g->e);
     const uint32_t grid = device ? kExchangeGrid : grid_for(act.count, kBlock, 0xFFFFFFFFu);
-    IPG_HIP(push_dispatch(app, weighted, a, grid, s));
+    if (front) {
+      front_push = a;
+      front_push_grid = grid;
+    } else {
+      IPG_HIP(push_dispatch(app, weighted, a, grid, s));
+    }
   }
   if (device || mode == IPG_MODE_PULL) {
     // the blocked in-edges of the caller's CSC (CC, unit-weight SSSP), if the store has them
     const BlockedTables* bt = nullptr;
     if (tn.blocked && !weighted) bt = g->t.blk_ids.edges ? &g->t.blk_ids : (g->t.blk.edges && !g->t.perm ? &g->t.blk : nullptr);
     const bool gating = step > 0 && tn.gate_div != 0;
+    // the pieces share the blocked pull's second launch (minprop_back_kernel)
+    const bool back = front && bt && bt->ngroups && front_push.pieces;
     if (step > 0) {
       if (!device) IPG_HIP(fill_u32(w.outbox, n, kInf, s));
       if (gating) IPG_HIP(fill_u32(w.sent, (uint64_t)n / 64 * 2 + 2, 0, s));
@@ -964,8 +1061,12 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
       const bool dense4 = (device || act.phase == kStepDense) && !gating;
       const uint32_t grid = dense4 ? grid_for((static_cast<uint64_t>(n) + 3) / 4, kBlock, 16384)
                                    : (device ? gv : grid_for(act.count, kBlock, 8192));
-      hipLaunchKernelGGL(minprop_apply_kernel, dim3(grid), dim3(kBlock), 0, s, ap);
-      IPG_HIP(hipGetLastError());
+      if (front) {
+        IPG_HIP(front_dispatch(app, weighted, front_push, ap, front_push_grid, grid, !back, s));
+      } else {
+        hipLaunchKernelGGL(minprop_apply_kernel, dim3(grid), dim3(kBlock), 0, s, ap);
+        IPG_HIP(hipGetLastError());
+      }
       if (gating) {
         hipLaunchKernelGGL(gate_kernel, dim3(1), dim3(kWave), 0, s, b.c, n, tn.gate_div, ctl, w.gate);
         IPG_HIP(hipGetLastError());
@@ -991,7 +1092,9 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
       } else {  // no edges: nothing arrives, but the next superstep's counters are still cleared here
         IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(b.cc), kCtrSlots * sizeof(CtrSlot) / 4, 0, s));
       }
-      if (bt->ngroups) {
+      if (back) {
+        IPG_HIP(back_dispatch(app, weighted, front_push, ba, grid_for(bt->ngroups, kWavesPerBlock, 4096), s));
+      } else if (bt->ngroups) {
         hipLaunchKernelGGL(minprop_blocked_finish_kernel, dim3(grid_for(bt->ngroups, kWavesPerBlock, 4096)),
                            dim3(kBlock), 0, s, ba);
         IPG_HIP(hipGetLastError());
