@@ -29,10 +29,10 @@ def ipg():
     return m
 
 
-def check(ipg, hg, app, source=0, weighted=True, modes=("push", "auto")):
+def check(ipg, hg, app, source=0, weighted=True, modes=("push", "auto"), blocked=False):
     ref = oracle.run_graph(app, hg, 0, source=source, weighted=weighted)
     assert ref.status == oracle.OK
-    g = ipg.Graph.from_host(hg, weighted=weighted)
+    g = ipg.Graph.from_host(hg, weighted=weighted, blocked=blocked)
     for mode in modes:
         for persistent in (False, True):
             vals, st = g.run(app, source=source, mode=mode, persistent=persistent)
@@ -76,6 +76,15 @@ def test_rmat_low_id_hubs_forced_push(ipg, scale):
     hg = graphgen.rmat(scale, 16, seed=40 + scale, symmetric=True)
     for app, src in (("cc", 0), ("sssp", 0), ("sssp", 999)):
         check(ipg, hg, app, source=src)
+
+
+@pytest.mark.parametrize("app,src", [("sssp", 0), ("sssp", 7), ("cc", 0)])
+def test_pieces_with_blocked_in_edges(ipg, app, src):
+    # unit weights over blocked in-edges: in the device-driven loop a push
+    # superstep's pieces run in the launch that is the blocked pull's second
+    # launch in a pull superstep, and its push in the pull form's compute launch
+    for hg in (star(5000, extra=40000, seed=3), graphgen.rmat(15, 16, seed=41, symmetric=True)):
+        check(ipg, hg, app, source=src, weighted=False, blocked=True, modes=("push", "auto", "pull"))
 
 
 def test_weighted_directed_multigraph_forced_push(ipg):
