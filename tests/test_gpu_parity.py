@@ -83,6 +83,22 @@ def test_pagerank_pull_bitwise_deterministic(ipg):
     assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
 
 
+def test_pagerank_superstep_times(ipg):
+    # per-superstep times from the timing events between the launches: one
+    # per superstep, each positive, together within the run's time (the run
+    # also maps the ranks back after the last superstep); the ranks are the
+    # those of a run without per-superstep timing
+    hg = graphgen.workload("rmat-s14-dir")
+    g = ipg.Graph.from_host(hg, blocked=True)
+    for _ in range(3):
+        vals, st = g.run("pagerank", 10, mode="pull", timing=True)
+        assert st.usec.shape == (11,) and (st.usec > 0).all()
+        assert st.seconds > 0 and st.usec.sum() <= st.seconds * 1e6 * 1.001 + 1.0
+        plain, st2 = g.run("pagerank", 10, mode="pull", timing=False)
+        assert st2.seconds > 0
+        assert max_rel(to_np(vals), to_np(plain)) <= PR_RTOL  # blocked sums: order may vary
+
+
 def test_pagerank_long_rows_and_hubs(ipg):
     # A hub with in-degree far above the LDS tile (long-row path) plus a
     # ragged tail of small rows; N not a multiple of 64.
