@@ -156,7 +156,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="run with the library's default launch parameters")
     ap.add_argument("--no-blocked", action="store_true",
                     help="build the graph without blocked in-edges (PageRank then pulls with the row-item kernels)")
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tuning_cache.json"),
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "_build", "tuning_cache.json"),
                     help="autotuner cache file")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain comparison (256-source SSSP on R-MAT s22 + 64 small PageRank graphs)")
@@ -166,7 +166,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design, "
-              f"not part of this build", file=sys.stderr)
+              f"not implemented here", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

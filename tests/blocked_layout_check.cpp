@@ -1,7 +1,7 @@
 // Host check of the blocked in-edge layout (blocked_layout.h) on a CSC read
 // from a file.  It decodes the tables the kernels read -- packed edges,
 // chunks, slices in launch order, finish groups -- and checks, without
-// re-running the build's own steps:
+// re-running the layout construction's own steps:
 //   * the decoded (source, destination) pairs are the CSC's edges, as a multiset;
 //   * blocks partition [0, N) in order, each at most kBlkRows rows, closed by
 //     the stated rule (edge target or row cap), and hold their edges sorted

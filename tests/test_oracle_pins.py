@@ -122,7 +122,7 @@ def test_pr_matches_matrix_form(case):
 
 
 def test_pr_rmat_s14_matches_sparse_matrix_form():
-    # configs[0]-sized input (R-MAT scale 14, edge factor 16, seed 1).
+    # the small parity workload: R-MAT scale 14, edge factor 16, seed 1.
     g = graphgen.workload("rmat-s14-dir")
     ref = _pr_matrix_form(g, 10)
     got = pr(g, 10).values
