@@ -43,10 +43,13 @@ enum : int {
 // value = id (CC) or 0 at the source / INF elsewhere (SSSP).  With `pull_s0`
 // superstep 0 is exchanged by pull: the senders' broadcast values are written
 // to the outbox (INF for the others) and the senders are counted.  With a
-// control block (device-driven loop) its exchange decides instead.
+// control block (device-driven loop) its exchange decides instead.  Given
+// `mail_a` and `mail_b`, both mailboxes are emptied too (the device-driven
+// loop's start; the host-driven loop clears them before).
 __global__ __launch_bounds__(kBlock) void minprop_init_kernel(uint32_t n, int app, uint32_t source, uint32_t* value,
                                                               const uint32_t* outdeg, int pull_s0, uint32_t* outbox,
-                                                              CtrSlot* ctr, const DevCtl* ctl) {
+                                                              CtrSlot* ctr, const DevCtl* ctl, uint32_t* mail_a,
+                                                              uint32_t* mail_b) {
   if (ctl) pull_s0 = ctl->mode == IPG_MODE_PULL;  // uniform over the grid
   uint64_t senders = 0, messages = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -54,6 +57,10 @@ __global__ __launch_bounds__(kBlock) void minprop_init_kernel(uint32_t n, int ap
     const bool sends = (app == IPG_APP_CC_HASHMIN) || v == source;
     const uint32_t x = app == IPG_APP_CC_HASHMIN ? static_cast<uint32_t>(v) : (v == source ? 0u : kInf);
     value[v] = x;
+    if (mail_a) {
+      mail_a[v] = kInf;
+      mail_b[v] = kInf;
+    }
     if (pull_s0) {
       outbox[v] = sends ? x : kInf;
       if (sends) {
@@ -803,11 +810,14 @@ __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_
 // Start of a device-driven run: the state before superstep 0 -- its active
 // set (every vertex for CC, the source for SSSP), their out-degree sum and
 // its exchange (forced, the selector, or the fixed heuristic), decided here
-// so that the host reads nothing before it enqueues.  One wavefront.
+// so that the host reads nothing before it enqueues -- and both sets of
+// counter slots zeroed.  One wavefront.
 __global__ __launch_bounds__(kWave) void dd_start_kernel(DevCtl* ctl, int app, uint32_t source, const uint64_t* off,
                                                          uint32_t n, uint64_t e, const double* sel, int forced,
-                                                         uint32_t push_div, uint32_t cap) {
+                                                         uint32_t push_div, uint32_t cap, CtrSlot* ctr) {
   const unsigned long long now = static_cast<unsigned long long>(wall_clock64());
+  uint32_t* cw = reinterpret_cast<uint32_t*>(ctr);
+  for (uint32_t i = threadIdx.x; i < 2 * kCtrSlots * sizeof(CtrSlot) / 4; i += kWave) cw[i] = 0;
   const bool cc = app == IPG_APP_CC_HASHMIN;
   const uint64_t count = cc ? n : 1;
   const uint64_t degsum = cc ? e : off[static_cast<uint64_t>(source) + 1] - off[source];
@@ -998,7 +1008,8 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
   uint32_t front_push_grid = 0;
   if (step == 0) {
     hipLaunchKernelGGL(minprop_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, static_cast<int>(app), source,
-                       w.value_u32, g->t.outdeg, mode == IPG_MODE_PULL ? 1 : 0, w.outbox, b.c, ctl);
+                       w.value_u32, g->t.outdeg, mode == IPG_MODE_PULL ? 1 : 0, w.outbox, b.c, ctl,
+                       device ? w.mail_a : nullptr, device ? w.mail_b : nullptr);
     IPG_HIP(hipGetLastError());
   }
   if (device || mode == IPG_MODE_PUSH) {
@@ -1191,15 +1202,16 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
   const Tune tn = resolve_tuning(o.tuning);
   HostMirror *hm = nullptr, *hm_dev = nullptr;
   IPG_HIP(host_mirror(g, &hm, &hm_dev));
-  ipg_status rc = clear_minprop(g, w, s);
-  if (rc != IPG_OK) return rc;
+  ipg_status rc = IPG_OK;
   if (!g->wall_khz) IPG_HIP(hipDeviceGetAttribute(&g->wall_khz, hipDeviceAttributeWallClockRate, g->device));
   const double us_per_tick = g->wall_khz > 0 ? 1e3 / g->wall_khz : 0.0;
   const double* sel = o.mode == IPG_MODE_AUTO ? o.selector : nullptr;
   const int forced = o.mode == IPG_MODE_AUTO ? 0 : static_cast<int>(o.mode);
   IPG_HIP(tm.start(s));
+  // the counters are zeroed by dd_start_kernel and the mailboxes emptied by
+  // superstep 0's init kernel, so the run starts with no clearing launch
   hipLaunchKernelGGL(dd_start_kernel, dim3(1), dim3(kWave), 0, s, w.ctl, static_cast<int>(app), o.source, g->csr_off, n,
-                     e, sel, forced, tn.push_div, cap);
+                     e, sel, forced, tn.push_div, cap, w.ctr);
   IPG_HIP(hipGetLastError());
   rc = enqueue_step(g, app, o.source, 0, IPG_MODE_AUTO, step0_active(app, n, o.source), 0, w, w.ctl, tn, s);
   if (rc != IPG_OK) return rc;
