@@ -911,10 +911,10 @@ hipError_t launch_decide(const CtrSlot* c, uint32_t next_superstep, uint64_t e, 
 constexpr uint32_t kPieceGrid = 2048;
 
 template <int APP, bool W>
-static hipError_t launch_push(const MinPushArgs& a, uint32_t grid, hipStream_t s) {
+static hipError_t launch_push(const MinPushArgs& a, uint32_t grid, bool pieces, hipStream_t s) {
   hipLaunchKernelGGL((minprop_push_kernel<APP, W>), dim3(grid), dim3(kBlock), 0, s, a);
   hipError_t err = hipGetLastError();
-  if (err != hipSuccess || !a.pieces) return err;
+  if (err != hipSuccess || !a.pieces || !pieces) return err;
   hipLaunchKernelGGL((minprop_piece_kernel<APP, W>), dim3(kPieceGrid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
@@ -954,9 +954,12 @@ static hipError_t back_dispatch(ipg_app app, bool weighted, const MinPushArgs& a
   return weighted ? launch_back<IPG_APP_SSSP, true>(a, b, finish_grid, s)
                   : launch_back<IPG_APP_SSSP, false>(a, b, finish_grid, s);
 }
-static hipError_t push_dispatch(ipg_app app, bool weighted, const MinPushArgs& a, uint32_t grid, hipStream_t s) {
-  if (app == IPG_APP_CC_HASHMIN) return launch_push<IPG_APP_CC_HASHMIN, false>(a, grid, s);
-  return weighted ? launch_push<IPG_APP_SSSP, true>(a, grid, s) : launch_push<IPG_APP_SSSP, false>(a, grid, s);
+// The push launch and, unless the back launch will run them, the pieces.
+static hipError_t push_dispatch(ipg_app app, bool weighted, const MinPushArgs& a, uint32_t grid, bool pieces,
+                                hipStream_t s) {
+  if (app == IPG_APP_CC_HASHMIN) return launch_push<IPG_APP_CC_HASHMIN, false>(a, grid, pieces, s);
+  return weighted ? launch_push<IPG_APP_SSSP, true>(a, grid, pieces, s)
+                  : launch_push<IPG_APP_SSSP, false>(a, grid, pieces, s);
 }
 static hipError_t pull_dispatch(ipg_app app, bool weighted, const MinPullArgs& a, uint32_t grid, hipStream_t s) {
   if (app == IPG_APP_CC_HASHMIN) return launch_pull<IPG_APP_CC_HASHMIN, false>(a, grid, s);
@@ -1001,9 +1004,15 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
   const uint32_t gv = grid_for(n, kBlock, 16384);
   const StepBufs b = bufs_for(w, step);
   const bool device = ctl != nullptr;
+  // the blocked in-edges of the caller's CSC (CC, unit-weight SSSP), if the store has them
+  const BlockedTables* bt = nullptr;
+  if (tn.blocked && !weighted) bt = g->t.blk_ids.edges ? &g->t.blk_ids : (g->t.blk.edges && !g->t.perm ? &g->t.blk : nullptr);
   // device-driven superstep s >= 1: the push and the pull form's compute
   // share one launch (minprop_front_kernel), made where the compute's was
   const bool front = device && step > 0;
+  // device-driven loop over blocked in-edges: the pieces share the blocked
+  // pull's second launch (minprop_back_kernel)
+  const bool back = device && bt && bt->ngroups;
   MinPushArgs front_push{};
   uint32_t front_push_grid = 0;
   if (step == 0) {
@@ -1038,20 +1047,12 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
     a.pieces = pieces ? w.pieces : nullptr;
     a.piece_seg = piece_seg(g->e);
     const uint32_t grid = device ? kExchangeGrid : grid_for(act.count, kBlock, 0xFFFFFFFFu);
-    if (front) {
-      front_push = a;
-      front_push_grid = grid;
-    } else {
-      IPG_HIP(push_dispatch(app, weighted, a, grid, s));
-    }
+    front_push = a;
+    front_push_grid = grid;
+    if (!front) IPG_HIP(push_dispatch(app, weighted, a, grid, !back, s));
   }
   if (device || mode == IPG_MODE_PULL) {
-    // the blocked in-edges of the caller's CSC (CC, unit-weight SSSP), if the store has them
-    const BlockedTables* bt = nullptr;
-    if (tn.blocked && !weighted) bt = g->t.blk_ids.edges ? &g->t.blk_ids : (g->t.blk.edges && !g->t.perm ? &g->t.blk : nullptr);
     const bool gating = step > 0 && tn.gate_div != 0;
-    // the pieces share the blocked pull's second launch (minprop_back_kernel)
-    const bool back = front && bt && bt->ngroups && front_push.pieces;
     if (step > 0) {
       if (!device) IPG_HIP(fill_u32(w.outbox, n, kInf, s));
       if (gating) IPG_HIP(fill_u32(w.sent, (uint64_t)n / 64 * 2 + 2, 0, s));
