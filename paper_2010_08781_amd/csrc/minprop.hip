@@ -816,8 +816,8 @@ __global__ __launch_bounds__(kWave) void dd_start_kernel(DevCtl* ctl, int app, u
                                                          uint32_t n, uint64_t e, const double* sel, int forced,
                                                          uint32_t push_div, uint32_t cap, CtrSlot* ctr) {
   const unsigned long long now = static_cast<unsigned long long>(wall_clock64());
-  uint32_t* cw = reinterpret_cast<uint32_t*>(ctr);
-  for (uint32_t i = threadIdx.x; i < 2 * kCtrSlots * sizeof(CtrSlot) / 4; i += kWave) cw[i] = 0;
+  uint4* cw = reinterpret_cast<uint4*>(ctr);  // 16-byte stores (the slots are 256-byte aligned)
+  for (uint32_t i = threadIdx.x; i < 2 * kCtrSlots * sizeof(CtrSlot) / 16; i += kWave) cw[i] = make_uint4(0, 0, 0, 0);
   const bool cc = app == IPG_APP_CC_HASHMIN;
   const uint64_t count = cc ? n : 1;
   const uint64_t degsum = cc ? e : off[static_cast<uint64_t>(source) + 1] - off[source];
@@ -847,13 +847,16 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
   static_assert(kCtrSlots == kWave, "one slot per lane");
   const unsigned long long now = static_cast<unsigned long long>(wall_clock64());
   const DevCtl k = *ctl;
-  if (k.halted) return;
+  // The slots are summed before the halted test (cross-lane sums are not
+  // moved into a branch), so their loads are in flight with the control
+  // block's instead of after it.
   const CtrSlot& x = c[threadIdx.x];
   const uint64_t nc = wave_sum_u64(x.next_count);
   const uint64_t se = wave_sum_u64(x.senders);
   const uint64_t me = wave_sum_u64(x.messages);
   const uint64_t nd = wave_sum_u64(x.next_deg);
   const bool ovf = __ballot(x.overflow != 0) != 0;
+  if (k.halted) return;
   const uint64_t lcount = list_summary(x, lseg, lpre_out);  // ~0: a segment overflowed, no list
   const uint32_t s = k.step;
   int sel_mode = IPG_MODE_PUSH;
