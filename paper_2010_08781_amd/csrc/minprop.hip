@@ -1077,7 +1077,11 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
       const uint32_t grid = dense4 ? grid_for((static_cast<uint64_t>(n) + 3) / 4, kBlock, 16384)
                                    : (device ? gv : grid_for(act.count, kBlock, 8192));
       if (front) {
-        IPG_HIP(front_dispatch(app, weighted, front_push, ap, front_push_grid, grid, !back, s));
+        // the compute is grid-stride: capped at the push grid, the launch is
+        // no wider than the push needs (a wider one dispatched workgroups
+        // that return at once in every push superstep of a large graph)
+        IPG_HIP(front_dispatch(app, weighted, front_push, ap, front_push_grid, std::min(grid, front_push_grid), !back,
+                               s));
       } else {
         hipLaunchKernelGGL(minprop_apply_kernel, dim3(grid), dim3(kBlock), 0, s, ap);
         IPG_HIP(hipGetLastError());
