@@ -995,10 +995,13 @@ static StepBufs bufs_for(const RunWs& w, uint32_t step) {
   return b;
 }
 
-// The launches of one superstep.  With ctl == null the exchange is `mode`
-// and the active set `act` (host-driven loop, and superstep 0); with a
-// control block (device-driven superstep s >= 1) both exchanges are
-// launched on fixed grids and the control block picks one.
+// The launches of one superstep.  With ctl == null (host-driven loop) the
+// exchange is `mode` and the active set `act`; with a control block
+// (device-driven loop) both exchanges are launched on fixed grids, the
+// control block picks one (and, from superstep 1, the active set), and work
+// that only one exchange has shares a launch with the other's
+// (minprop_front_kernel from superstep 1, minprop_back_kernel over blocked
+// in-edges).
 static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint32_t step, ipg_mode mode,
                                const Active& act, uint64_t degsum, const RunWs& w, const DevCtl* ctl, const Tune& tn,
                                hipStream_t s) {
