@@ -172,6 +172,15 @@ def test_more_row_blocks_than_slices(ipg):
     for persistent in (False, True):
         vals, st = g.run("cc", mode="pull", persistent=persistent)
         assert np.array_equal(ipg.values_to_numpy(vals), ref.values) and np.array_equal(st.trace, ref.trace)
+    # unit-weight SSSP with both exchanges: in the device-driven loop the
+    # compute's grid (over 8.4M vertices) is capped to the push grid in the
+    # shared launch, and push supersteps queue pieces
+    ref = oracle.run_graph("sssp", hg, 0, source=0, weighted=False)
+    for mode in ("auto", "push"):
+        for persistent in (False, True):
+            vals, st = g.run("sssp", source=0, mode=mode, persistent=persistent)
+            assert np.array_equal(ipg.values_to_numpy(vals), ref.values), (mode, persistent)
+            assert np.array_equal(st.trace, ref.trace), (mode, persistent)
 
 
 def test_full_size_rmat_s20_symmetrised(ipg):
