@@ -311,6 +311,27 @@ ipg_status ipg_selector_grad(const double* params, const double* x, const double
 ipg_status ipg_selector_train(double* params, const double* x, const double* t, uint32_t n, uint32_t epochs,
                               double lr, void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/*
+ * ipg_selector_train without a workspace argument, for callers that cannot
+ * allocate device memory around the call (code under stream capture, tight
+ * serving or training loops, harnesses that forbid allocation).  The same
+ * kernel as ipg_selector_train, with the same result bit for bit; its
+ * gradient and batch scratch live in a static device array of the library,
+ * 8 * (IPG_SELECTOR_PARAMS + 66 * IPG_SELECTOR_NOALLOC_MAX_SAMPLES) bytes
+ * (8.7 MB), one copy per GPU, held from the first call on that GPU until the
+ * process ends.  The call allocates nothing: no hipMalloc, no hipFree, no
+ * allocating library routine.  params, x and t are DEVICE memory of the
+ * caller, as for ipg_selector_train.  n > IPG_SELECTOR_NOALLOC_MAX_SAMPLES
+ * (or n == 0, a NULL pointer, lr <= 0) is IPG_EINVAL.  Every call on one GPU
+ * shares that GPU's array, so calls that overlap in time on one GPU (two
+ * streams, two threads) race and must be serialised by the caller;
+ * consecutive calls are independent (nothing an earlier call left in the
+ * array is read).  Stream-ordered, no synchronisation.
+ */
+#define IPG_SELECTOR_NOALLOC_MAX_SAMPLES 16384
+ipg_status ipg_selector_train_noalloc(double* params, const double* x, const double* t, uint32_t n, uint32_t epochs,
+                                      double lr, void* hip_stream);
+
 /* Free the handle (host memory only; caller buffers are untouched). */
 void ipg_graph_destroy(ipg_graph* graph);
 

@@ -132,6 +132,8 @@ def lib():
         L.ipg_selector_grad.restype = i32
         L.ipg_selector_train.argtypes = [P, P, P, u32, u32, ctypes.c_double, P, sz, P]
         L.ipg_selector_train.restype = i32
+        L.ipg_selector_train_noalloc.argtypes = [P, P, P, u32, u32, ctypes.c_double, P]
+        L.ipg_selector_train_noalloc.restype = i32
         _lib = L
     return _lib
 
@@ -496,6 +498,21 @@ def selector_train(params, x, t, epochs: int, lr: float, stream=None):
     ws, nbytes = _selector_ws(x.shape[0], x.device)
     _check(lib().ipg_selector_train(params.data_ptr(), x.data_ptr(), t.data_ptr(), x.shape[0], int(epochs), float(lr),
                                     ws.data_ptr(), nbytes, _stream_handle(stream)), "ipg_selector_train")
+    return params
+
+
+SELECTOR_NOALLOC_MAX_SAMPLES = 16384
+
+
+def selector_train_noalloc(params, x, t, epochs: int, lr: float, stream=None):
+    """ipg_selector_train_noalloc: the same training with the library's
+    static scratch instead of a workspace (no device allocation)."""
+    _check_selector(params)
+    _check_batch(x, t)
+    if not (x.is_contiguous() and t.is_contiguous()):
+        raise ValueError("selector inputs and targets must be contiguous (no copies are made)")
+    _check(lib().ipg_selector_train_noalloc(params.data_ptr(), x.data_ptr(), t.data_ptr(), x.shape[0], int(epochs),
+                                            float(lr), _stream_handle(stream)), "ipg_selector_train_noalloc")
     return params
 
 

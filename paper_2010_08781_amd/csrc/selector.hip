@@ -12,6 +12,8 @@
 // min(superstep, 128)/64, log2(1+E)/32.  Loss: half the mean squared error
 // of the predicted log2-times.  Training is full-batch gradient descent by a
 // single workgroup in a fixed reduction order (bitwise reproducible).
+#include <mutex>
+
 #include "common.h"
 #include "engine.h"
 #include "selector.h"
@@ -125,6 +127,36 @@ __global__ __launch_bounds__(kBlock) void sel_train_kernel(double* p, const doub
   }
 }
 
+// Scratch of the allocation-free training entry point: the gradient
+// followed by the batch scratch of up to IPG_SELECTOR_NOALLOC_MAX_SAMPLES
+// samples, in a device array the library owns (one copy per GPU, held until
+// the process ends).  Host code never passes `scratch` itself to a kernel:
+// on the host the name stands for a host-side shadow, not for the device
+// copy, so every use goes through the per-device address below.
+constexpr size_t kNoAllocDoubles = kSelParams + (size_t)IPG_SELECTOR_NOALLOC_MAX_SAMPLES * (4 * kSelH + kSelK);
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[kMaxDevices];  // device address of `scratch` on each GPU, looked up once
+
+// Device address of the current GPU's copy of `scratch`, found with
+// hipGetSymbolAddress on the first call made with that GPU current.
+static ipg_status noalloc_scratch(double** out) {
+  int dev = -1;
+  IPG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(IPG_EDEVICE, "ipg_selector_train_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    IPG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(IPG_EDEVICE, "ipg_selector_train_noalloc: no device address for the scratch array");
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return IPG_OK;
+}
+
 }  // namespace ipg
 
 using namespace ipg;
@@ -163,6 +195,24 @@ extern "C" ipg_status ipg_selector_train(double* params, const double* x, const 
   double* g = static_cast<double*>(ws);
   double* scr = g + kSelParams;
   hipLaunchKernelGGL(sel_train_kernel, dim3(1), dim3(kBlock), 0, s, params, x, t, n, epochs, lr, g, scr);
+  IPG_HIP(hipGetLastError());
+  return IPG_OK;
+}
+
+extern "C" ipg_status ipg_selector_train_noalloc(double* params, const double* x, const double* t, uint32_t n,
+                                                 uint32_t epochs, double lr, void* hip_stream) {
+  if (!params || !x || !t || n == 0) return fail(IPG_EINVAL, "ipg_selector_train_noalloc: NULL argument or n == 0");
+  if (n > IPG_SELECTOR_NOALLOC_MAX_SAMPLES)
+    return fail(IPG_EINVAL, "ipg_selector_train_noalloc: n exceeds IPG_SELECTOR_NOALLOC_MAX_SAMPLES (" +
+                                std::to_string(IPG_SELECTOR_NOALLOC_MAX_SAMPLES) + ")");
+  if (!(lr > 0.0)) return fail(IPG_EINVAL, "ipg_selector_train_noalloc: lr must be > 0");
+  double* ws = nullptr;
+  const ipg_status rc = noalloc_scratch(&ws);
+  if (rc != IPG_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  // every gradient entry and every scratch entry the kernel reads is written
+  // by it first in each epoch, so nothing left by an earlier call is read
+  hipLaunchKernelGGL(sel_train_kernel, dim3(1), dim3(kBlock), 0, s, params, x, t, n, epochs, lr, ws, ws + kSelParams);
   IPG_HIP(hipGetLastError());
   return IPG_OK;
 }
