@@ -24,8 +24,10 @@
  *     pending (the Pregel rule the paper quotes in Section 8.3).
  *
  * Readings where the paper is silent (each is listed in the design notes):
- *   - PageRank: initial value 1/N, ratio 0.15/N (Pregel's form, Fig. 12),
- *     damping 0.85 as printed in Fig. 8; `threshold` is the superstep number at
+ *   - PageRank: initial value 1/N, ratio (1 - d)/N with the damping d a run
+ *     parameter (0.85 as printed in Fig. 8; the teleport term 0.15/N of
+ *     Pregel's form, Fig. 12, is its d = 0.85 case: 1 - 0.85 is evaluated in
+ *     double); `threshold` is the superstep number at
  *     which vertices stop broadcasting and halt (10 in Fig. 8), so the result
  *     is the rank after `threshold` updates and `threshold`+1 supersteps run.
  *     A vertex without out-edges broadcasts to nobody: its mass is not
@@ -43,9 +45,21 @@
  * trace[3*s+1] = vertices that broadcast, trace[3*s+2] = messages delivered
  * (sum of the senders' out-degrees).
  *
- * Build: gcc -O2 -ffp-contract=off (no fast-math; IEEE round-to-nearest).
+ * A second entry point, orc_run_pull, executes the same supersteps in the
+ * pull form (Section 4.3.2): every vertex that broadcasts leaves one value in
+ * its outbox, and every vertex combines the outboxes of its in-neighbours
+ * (CSC) that broadcast.  Its vertex loop runs under an OpenMP static schedule
+ * (the paper's parallelisation, Section 4.2); each vertex combines its
+ * in-neighbours in CSC order whatever the thread count, so the output does
+ * not depend on the number of threads, and with every CSC list sorted by
+ * source it equals the push form's bit for bit (the same additions in the
+ * same order).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp (no fast-math; IEEE
+ * round-to-nearest).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -89,11 +103,11 @@ static void orc_send_sum(orc_fbox* next, uint32_t w, double m) {
   }
 }
 
-static int orc_pagerank(uint32_t n, const uint64_t* off, const int32_t* adj, uint32_t threshold,
+static int orc_pagerank(uint32_t n, const uint64_t* off, const int32_t* adj, uint32_t threshold, double damping,
                         uint32_t max_supersteps, double* value, uint64_t* trace, uint32_t trace_cap,
                         uint32_t* supersteps_out, double* deltas) {
   const double initial_value = 1.0 / (double)n;
-  const double ratio = 0.15 / (double)n;
+  const double ratio = (1.0 - damping) / (double)n;
   uint8_t* halted = calloc(n ? n : 1, 1);
   orc_fbox in = {calloc(n ? n : 1, sizeof(double)), calloc(n ? n : 1, 1)};
   orc_fbox next = {calloc(n ? n : 1, sizeof(double)), calloc(n ? n : 1, 1)};
@@ -113,7 +127,7 @@ static int orc_pagerank(uint32_t n, const uint64_t* off, const int32_t* adj, uin
         double sum = 0.0;
         if (in.has[v]) sum += in.box[v]; /* at most one combined message */
         const double old = value[v];
-        value[v] = ratio + 0.85 * sum;
+        value[v] = ratio + damping * sum;
         if (deltas) l1 += fabs(value[v] - old);
       }
       if (s < threshold) {
@@ -291,7 +305,7 @@ int orc_run(int app, uint32_t n, const uint64_t* off, const int32_t* adj, const 
   if (!orc_check_graph(n, off, adj)) return ORC_EBADGRAPH;
   if (app == ORC_APP_PAGERANK) {
     if (n == 0) return ORC_EINVAL;
-    return orc_pagerank(n, off, adj, param, 0, (double*)values, trace, trace_cap, supersteps, NULL);
+    return orc_pagerank(n, off, adj, param, 0.85, 0, (double*)values, trace, trace_cap, supersteps, NULL);
   }
   if (app == ORC_APP_CC) return orc_minprop(app, n, off, adj, NULL, 0, param, (uint32_t*)values, trace, trace_cap, supersteps);
   if (app == ORC_APP_SSSP) {
@@ -310,10 +324,184 @@ int orc_run(int app, uint32_t n, const uint64_t* off, const int32_t* adj, const 
  * deltas[0] = 0.  The caller picks the first update whose change is below
  * its tolerance.
  */
-int orc_pagerank_deltas(uint32_t n, const uint64_t* off, const int32_t* adj, uint32_t threshold, double* values,
-                        double* deltas) {
+int orc_pagerank_deltas(uint32_t n, const uint64_t* off, const int32_t* adj, uint32_t threshold, double damping,
+                        double* values, double* deltas) {
   uint32_t steps = 0;
   if (!off || (!adj && n && off[n]) || !values || !deltas || n == 0) return ORC_EINVAL;
+  if (!(damping > 0.0 && damping <= 1.0)) return ORC_EINVAL;
   if (!orc_check_graph(n, off, adj)) return ORC_EBADGRAPH;
-  return orc_pagerank(n, off, adj, threshold, 0, values, NULL, 0, &steps, deltas);
+  return orc_pagerank(n, off, adj, threshold, damping, 0, values, NULL, 0, &steps, deltas);
 }
+
+/*
+ * PageRank of Fig. 8 with damping d (0 < d <= 1): orc_run's PageRank with
+ * ratio (1 - d)/N and the message sum weighted by d.
+ */
+int orc_pagerank_run(uint32_t n, const uint64_t* off, const int32_t* adj, uint32_t threshold, double damping,
+                     double* values, uint64_t* trace, uint32_t trace_cap, uint32_t* supersteps) {
+  *supersteps = 0;
+  if (!off || (!adj && n && off[n]) || !values || n == 0) return ORC_EINVAL;
+  if (!(damping > 0.0 && damping <= 1.0)) return ORC_EINVAL;
+  if (!orc_check_graph(n, off, adj)) return ORC_EBADGRAPH;
+  return orc_pagerank(n, off, adj, threshold, damping, 0, values, trace, trace_cap, supersteps, NULL);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Pull form under an OpenMP static schedule.                             */
+
+/*
+ * Supersteps of Figs. 8-10 in the pull form.  State per vertex: value,
+ * halted, and the outbox of the previous superstep (the value it broadcast,
+ * with a flag saying whether it broadcast at all).  Superstep s:
+ *   1. every vertex v (static schedule) combines the outboxes of the
+ *      in-neighbours that broadcast in s-1, in CSC order (its mailbox);
+ *   2. v runs compute if s == 0, or it has not voted to halt, or its mailbox
+ *      is non-empty (selection, Section 4.3.1), writing its own outbox for
+ *      s+1 when it broadcasts;
+ *   3. stop when every vertex has voted to halt and nobody sent a message.
+ * The per-superstep trace counts are integer sums (thread-count independent).
+ * An SSSP broadcast whose message to some out-neighbour would reach INF is an
+ * overflow, detected when the vertex broadcasts (as in the push form).
+ *   csr_off: out-degrees (and, with csr_w, the overflow check of weighted SSSP);
+ *   csc_off/csc_src/csc_w: in-adjacency, weights aligned with csc_src.
+ */
+int orc_run_pull(int app, uint32_t n, const uint64_t* csr_off, const uint32_t* csr_w, const uint64_t* csc_off,
+                 const int32_t* csc_src, const uint32_t* csc_w, uint32_t source, uint32_t param, double damping,
+                 int threads, void* values, uint64_t* trace, uint32_t trace_cap, uint32_t* supersteps_out) {
+  *supersteps_out = 0;
+  if (!csr_off || !csc_off || (!csc_src && n && csc_off[n]) || !values) return ORC_EINVAL;
+  if (app != ORC_APP_PAGERANK && app != ORC_APP_CC && app != ORC_APP_SSSP) return ORC_EINVAL;
+  if (app == ORC_APP_PAGERANK && (n == 0 || !(damping > 0.0 && damping <= 1.0))) return ORC_EINVAL;
+  if (app == ORC_APP_SSSP && source >= n) return ORC_EINVAL;
+  if (!orc_check_graph(n, csc_off, csc_src) || csr_off[0] != 0 || csr_off[n] != csc_off[n]) return ORC_EBADGRAPH;
+  for (uint32_t v = 0; v < n; ++v)
+    if (csr_off[v + 1] < csr_off[v]) return ORC_EBADGRAPH;
+  if (threads < 1) threads = 1;
+  const size_t nn = n ? n : 1;
+  const int pr = app == ORC_APP_PAGERANK;
+  double* fval = pr ? (double*)values : NULL;
+  uint32_t* uval = pr ? NULL : (uint32_t*)values;
+  double* fout[2] = {pr ? malloc(nn * sizeof(double)) : NULL, pr ? malloc(nn * sizeof(double)) : NULL};
+  uint32_t* uout[2] = {pr ? NULL : malloc(nn * sizeof(uint32_t)), pr ? NULL : malloc(nn * sizeof(uint32_t))};
+  uint8_t* sent[2] = {calloc(nn, 1), calloc(nn, 1)};
+  uint8_t* halted = calloc(nn, 1);
+  const double initial_value = pr ? 1.0 / (double)n : 0.0;
+  const double ratio = pr ? (1.0 - damping) / (double)n : 0.0;
+  const uint32_t threshold = param, cap = pr ? 0 : param;
+  int status = ORC_OK;
+  uint32_t s = 0;
+  for (;; ++s) {
+    const uint8_t* sin = sent[(s + 1) & 1]; /* broadcasts of superstep s-1 */
+    uint8_t* sout = sent[s & 1];
+    const double* fin = pr ? fout[(s + 1) & 1] : NULL;
+    double* fo = pr ? fout[s & 1] : NULL;
+    const uint32_t* uin = pr ? NULL : uout[(s + 1) & 1];
+    uint32_t* uo = pr ? NULL : uout[s & 1];
+    unsigned long long active = 0, senders = 0, messages = 0, awake = 0, overflow = 0;
+#pragma omp parallel for schedule(static) num_threads(threads) \
+    reduction(+ : active, senders, messages, awake, overflow)
+    for (int64_t iv = 0; iv < (int64_t)n; ++iv) {
+      const uint32_t v = (uint32_t)iv;
+      /* 1. the mailbox: the in-neighbours' broadcasts, combined in CSC order */
+      int has = 0;
+      double facc = 0.0;
+      uint32_t umin = ORC_INF;
+      if (s > 0) {
+        for (uint64_t e = csc_off[v]; e < csc_off[v + 1]; ++e) {
+          const uint32_t u = (uint32_t)csc_src[e];
+          if (!sin[u]) continue;
+          if (pr) {
+            if (has) facc += fin[u]; /* the sum combiner of Fig. 8 */
+            else facc = fin[u];
+          } else {
+            uint32_t m = uin[u];
+            if (app == ORC_APP_SSSP) m += csc_w ? csc_w[e] : 1u; /* checked at the broadcast */
+            if (!has || m < umin) umin = m; /* the min combiner of Fig. 5 */
+          }
+          has = 1;
+        }
+      }
+      sout[v] = 0;
+      /* 2. selection and compute */
+      if (!(s == 0 || !halted[v] || has)) continue;
+      halted[v] = 0;
+      ++active;
+      int send = 0;
+      if (pr) {
+        if (s == 0) {
+          fval[v] = initial_value;
+        } else {
+          double sum = 0.0;
+          if (has) sum += facc;
+          fval[v] = ratio + damping * sum;
+        }
+        if (s < threshold) send = 1;
+        else halted[v] = 1;
+      } else if (app == ORC_APP_CC) {
+        if (s == 0) {
+          uval[v] = v;
+          send = 1;
+        } else {
+          const uint32_t old_value = uval[v];
+          if (has && umin < uval[v]) uval[v] = umin;
+          if (uval[v] < old_value) send = 1;
+        }
+        halted[v] = 1;
+      } else {
+        if (s == 0) {
+          uval[v] = v == source ? 0u : ORC_INF;
+          send = v == source;
+        } else {
+          const uint32_t mindist = has ? umin : ORC_INF;
+          if (mindist < uval[v]) {
+            uval[v] = mindist;
+            send = 1;
+          }
+        }
+        halted[v] = 1;
+      }
+      if (!halted[v]) ++awake;
+      if (!send) continue;
+      /* broadcast: one outbox value read by every out-neighbour */
+      const uint64_t deg = csr_off[v + 1] - csr_off[v];
+      ++senders;
+      messages += deg;
+      sout[v] = 1;
+      if (pr) {
+        fo[v] = deg ? fval[v] / (double)deg : 0.0;
+      } else {
+        uo[v] = uval[v];
+        if (app == ORC_APP_SSSP)
+          for (uint64_t e = csr_off[v]; e < csr_off[v + 1]; ++e)
+            if ((uint64_t)uval[v] + (csr_w ? (uint64_t)csr_w[e] : 1u) >= ORC_INF) ++overflow;
+      }
+    }
+    if (s < trace_cap) {
+      trace[3 * (uint64_t)s + 0] = active;
+      trace[3 * (uint64_t)s + 1] = senders;
+      trace[3 * (uint64_t)s + 2] = messages;
+    }
+    if (overflow) {
+      status = ORC_EOVERFLOW;
+      break;
+    }
+    /* 3. every vertex halted and no message pending */
+    if (awake == 0 && messages == 0) break;
+    if (cap && s + 1 >= cap) {
+      status = ORC_NOT_CONVERGED;
+      break;
+    }
+  }
+  *supersteps_out = s + 1;
+  free(fout[0]);
+  free(fout[1]);
+  free(uout[0]);
+  free(uout[1]);
+  free(sent[0]);
+  free(sent[1]);
+  free(halted);
+  return status;
+}
+
+/* Threads the OpenMP runtime offers to orc_run_pull by default. */
+int orc_max_threads(void) { return omp_get_max_threads(); }

@@ -53,15 +53,19 @@ def test_pr_complete_digraph_is_uniform(n):
         np.testing.assert_allclose(pr(g, T).values, 1.0 / n, rtol=1e-14, atol=0)
 
 
-def test_pr_source_only_vertices_get_exactly_the_teleport_term():
+@pytest.mark.parametrize("d", [0.85, 0.5, 0.3])
+def test_pr_source_only_vertices_get_exactly_the_teleport_term(d):
     # A vertex without in-edges receives no message: after any update its rank
-    # is exactly 0.15/N (the sum is 0.0).
+    # is exactly the teleport term (1-d)/N (the sum is 0.0), and no other
+    # vertex's is below it.
     g = random_graph(300, 900, seed=3)
     indeg = np.diff(g.csc_off)
     assert (indeg == 0).any()
     for T in (1, 3, 10):
-        r = pr(g, T)
-        assert np.all(r.values[indeg == 0] == 0.15 / g.n)
+        r = oracle.run_graph("pagerank", g, T, damping=d)
+        assert r.status == oracle.OK
+        assert np.all(r.values[indeg == 0] == (1.0 - d) / g.n)
+        assert np.all(r.values[indeg > 0] > (1.0 - d) / g.n)
 
 
 def test_pr_T0_is_initial_value():
@@ -376,3 +380,68 @@ def test_pr_converge_equals_fixed_run():
     # never below the tolerance: runs the cap
     _, T2, _ = oracle.pagerank_converge(g, 0.0, 15)
     assert T2 == 15
+
+
+# ------------------------------------------------ PageRank, general damping --
+
+def _dense_pr(g, T, d):
+    # r <- (1-d)/N + d * A^T (D^+ r): the matrix form of Fig. 8 with damping d
+    # (Ligra's Fig. 16 form), dense numpy, dangling mass dropped.
+    A = adjacency(g).toarray()
+    outdeg = A.sum(axis=1)
+    dinv = np.where(outdeg > 0, 1.0 / np.where(outdeg > 0, outdeg, 1), 0.0)
+    r = np.full(g.n, 1.0 / g.n)
+    for _ in range(T):
+        r = (1.0 - d) / g.n + d * (A.T @ (dinv * r))
+    return r
+
+
+@pytest.mark.parametrize("d", [0.3, 0.6, 0.99, 1.0])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_pr_general_damping_matches_matrix_form(d, seed):
+    g = random_graph(120, 700, seed=seed, loops=True, dups=True)
+    for T in (1, 4, 10):
+        r = oracle.run_graph("pagerank", g, T, damping=d)
+        assert r.status == oracle.OK
+        np.testing.assert_allclose(r.values, _dense_pr(g, T, d), rtol=1e-13, atol=0)
+
+
+def test_pr_damping_half_exact_rationals():
+    # d = 1/2: the exact rational iterate r <- 1/(2N) + 1/2 * sum of the
+    # in-neighbours' r/outdeg, on a multigraph with self-loops and a dangling
+    # vertex; the double result is within 1e-14 relative of it.
+    n = 9
+    src = [0, 0, 1, 2, 2, 3, 4, 4, 5, 6, 6, 7, 1, 3]
+    dst = [1, 1, 2, 0, 3, 3, 5, 0, 6, 7, 2, 4, 4, 8]
+    g = graphgen.from_edges(n, src, dst, keep_self_loops=True, keep_duplicates=True)
+    half = Fraction(1, 2)
+    r = [Fraction(1, n)] * n
+    for T in range(1, 8):
+        acc = [Fraction(0)] * n
+        for u, v in zip(src, dst):
+            acc[v] += r[u] / src.count(u)
+        r = [(1 - half) / n + half * a for a in acc]
+        got = oracle.run_graph("pagerank", g, T, damping=0.5).values
+        exact = np.array([float(x) for x in r])
+        np.testing.assert_allclose(got, exact, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("d", [0.2, 0.7])
+def test_pr_general_damping_mass_balance(d):
+    # sum r_{k+1} = (1-d) + d * (sum r_k - sum of the dangling r_k)
+    g = random_graph(400, 1500, seed=9)
+    dangling = np.diff(g.csr_off) == 0
+    assert dangling.any()
+    prev = oracle.run_graph("pagerank", g, 0, damping=d).values
+    for T in range(1, 8):
+        cur = oracle.run_graph("pagerank", g, T, damping=d).values
+        expect = (1.0 - d) + d * (prev.sum() - prev[dangling].sum())
+        assert abs(cur.sum() - expect) <= 1e-13
+        prev = cur
+
+
+@pytest.mark.parametrize("d", [0.0, -0.5, 1.5, float("nan")])
+def test_pr_damping_out_of_range_rejected(d):
+    g = directed_cycle(5)
+    assert oracle.run_graph("pagerank", g, 3, damping=d).status == oracle.EINVAL
+    assert oracle.run_pull("pagerank", g, 3, damping=d).status == oracle.EINVAL
