@@ -146,6 +146,9 @@ typedef struct {
 
 typedef struct {
   uint32_t source;          /* SSSP source vertex (ignored by the other applications) */
+  double damping;           /* PageRank's d (Fig. 8 prints 0.85): rank = (1 - d)/N + d * (sum of the
+                               messages); 0 = 0.85; anything outside (0, 1] is IPG_EINVAL.  Ignored by
+                               the other applications. */
   ipg_mode mode;
   uint32_t flags;
   const double* selector;   /* DEVICE pointer to IPG_SELECTOR_PARAMS trained selector parameters
@@ -203,12 +206,17 @@ typedef struct {
 
 /* Bytes of graph workspace ipg_graph_create needs for this graph size.  The
  * workspace is device memory (256-byte aligned) owned by the caller and must
- * outlive the handle. */
+ * outlive the handle.  Paper: Section 4.2 (the framework's global arrays of
+ * vertex data and adjacency) and Table 3 (memory footprint as an evaluation
+ * axis); this query makes the device-side footprint explicit. */
 size_t ipg_graph_workspace_bytes(uint32_t num_vertices, uint64_t num_edges, uint32_t flags);
 
 /* Bytes of run workspace ipg_run needs for `app` on a graph of this size
  * (device memory, 256-byte aligned, owned by the caller).  The application's
- * values live inside it until the next ipg_run on the same graph. */
+ * values live inside it until the next ipg_run on the same graph.  Paper:
+ * Section 4.3.3 (one message slot per vertex, combined on arrival) and
+ * Section 4.2 (vertex values; double-buffered message boxes between
+ * supersteps, Fig. 3). */
 size_t ipg_run_workspace_bytes(uint32_t num_vertices, uint64_t num_edges, ipg_app app);
 
 /*
@@ -216,12 +224,22 @@ size_t ipg_run_workspace_bytes(uint32_t num_vertices, uint64_t num_edges, ipg_ap
  * out-degrees and the pull-side tiling of the CSC.  Synchronises the stream.
  * On success *out receives a handle; on failure *out is NULL and the status
  * is IPG_EINVAL, IPG_EBADGRAPH, IPG_EWORKSPACE or IPG_EDEVICE.
+ * Paper: Section 3 (a directed graph whose vertices know their in- and
+ * out-neighbours: the out-edges carry a broadcast, the in-edges are what the
+ * pull form of Section 4.3.2 reads) and Section 4.2 (vertices and edges
+ * loaded into the framework's arrays before processing, outside the timed
+ * part, Section 7).
  */
 ipg_status ipg_graph_create(const ipg_graph_desc* desc, void* workspace, size_t workspace_bytes,
                             void* hip_stream, ipg_graph** out);
 
 /*
  * Run one application to completion (or to the cap) on the graph.
+ * Paper: Fig. 1 and Fig. 2 (the user's compute and combine functions and the
+ * superstep loop that calls them), Section 4.1-4.2 (synchronous supersteps,
+ * vote to halt, a message sent in superstep s read in s + 1), Section 4.3
+ * (selection, push/pull exchange, combiners) and Figs. 8-10 (the three
+ * applications).
  *   (app, combiner) must be (PAGERANK, SUM), (CC_HASHMIN, MIN) or (SSSP, MIN):
  *   anything else is IPG_EUNSUPPORTED.
  *   max_supersteps: PageRank -> number of rank updates T (vertices broadcast
@@ -248,7 +266,9 @@ ipg_status ipg_run(ipg_graph* graph, ipg_app app, ipg_combiner combiner, uint32_
  * is non-zero, else host memory.  A host copy synchronises the stream; a
  * device copy is only enqueued on it (work on other streams must wait for
  * the stream first).  IPG_EINVAL if no run happened or dst_bytes is too
- * small. */
+ * small.  Paper: Fig. 2 and Section 4.1 (the result of a vertex-centric
+ * program is the value every vertex holds when the last superstep ends;
+ * Section 7 times processing without dumping it). */
 ipg_status ipg_read_values(const ipg_graph* graph, void* dst, size_t dst_bytes, int dst_is_device,
                            void* hip_stream);
 
@@ -332,10 +352,14 @@ ipg_status ipg_selector_train(double* params, const double* x, const double* t, 
 ipg_status ipg_selector_train_noalloc(double* params, const double* x, const double* t, uint32_t n, uint32_t epochs,
                                       double lr, void* hip_stream);
 
-/* Free the handle (host memory only; caller buffers are untouched). */
+/* Free the handle (host memory only; caller buffers are untouched).  Paper:
+ * the counterpart of ipg_graph_create (Section 4.2's arrays live as long as
+ * the graph is processed); the caller's device buffers stay the caller's. */
 void ipg_graph_destroy(ipg_graph* graph);
 
-/* Message for the last error on the calling thread ("" if none). */
+/* Message for the last error on the calling thread ("" if none).  Not from
+ * the paper, which has no error channel: the library reports every failure
+ * as a status code plus this thread-local text instead of aborting. */
 const char* ipg_last_error(void);
 
 #ifdef __cplusplus

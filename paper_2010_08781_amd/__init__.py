@@ -73,7 +73,8 @@ def _tuning(t):
 
 
 class _Opts(ctypes.Structure):
-    _fields_ = [("source", ctypes.c_uint32), ("mode", ctypes.c_int), ("flags", ctypes.c_uint32),
+    _fields_ = [("source", ctypes.c_uint32), ("damping", ctypes.c_double), ("mode", ctypes.c_int),
+                ("flags", ctypes.c_uint32),
                 ("selector", ctypes.c_void_p), ("part_offsets", ctypes.c_void_p), ("num_parts", ctypes.c_uint32),
                 ("tolerance", ctypes.c_double), ("tuning", ctypes.c_void_p)]
 
@@ -318,7 +319,7 @@ class Graph:
     def run(self, app, max_supersteps: Optional[int] = None, source: int = 0, mode: str = "auto",
             timing: bool = True, trace_cap: int = 1 << 16, persistent: bool = False, stream=None,
             combiner: Optional[int] = None, check: bool = True, selector=None, parts=None, graph: bool = False,
-            tol: float = 0.0, tuning: Optional[dict] = None, enqueue: bool = False):
+            tol: float = 0.0, tuning: Optional[dict] = None, enqueue: bool = False, damping: float = 0.0):
         """Run an application; returns (values tensor on the device, RunStats).
 
         max_supersteps: PageRank -> number of rank updates (default 10, Fig. 8);
@@ -329,7 +330,8 @@ class Graph:
         change is below tol; max_supersteps caps the updates); tuning: launch
         parameters (see TUNING_FIELDS and the autotune module); enqueue:
         PageRank work only enqueued on the stream (capturable; returns
-        (None, None), read the ranks with read_values afterwards)."""
+        (None, None), read the ranks with read_values afterwards); damping:
+        PageRank's d (0 = 0.85, Fig. 8)."""
         import torch
 
         a = APPS[app] if isinstance(app, str) else int(app)
@@ -346,7 +348,8 @@ class Graph:
                 raise ValueError("parts must be a contiguous int32 CUDA tensor of P+1 offsets")
         flags = (RUN_PERSISTENT if persistent else 0) | (RUN_GRAPH if graph else 0) | (RUN_ENQUEUE if enqueue else 0)
         tun = _tuning(tuning)
-        opts = _Opts(int(source), MODES[mode], flags, selector.data_ptr() if selector is not None else None,
+        opts = _Opts(int(source), float(damping), MODES[mode], flags,
+                     selector.data_ptr() if selector is not None else None,
                      parts.data_ptr() if parts is not None else None, parts.numel() - 1 if parts is not None else 0,
                      float(tol), ctypes.addressof(tun) if tun is not None else None)
         tr = self._trace(trace_cap, timing)
@@ -387,7 +390,8 @@ class Graph:
         ws, nbytes = self._run_ws[key]
         tun = _tuning(tuning)
         flags = (RUN_PERSISTENT if persistent else 0) | (RUN_ENQUEUE if enqueue else 0)
-        opts = _Opts(0, MODES[mode], flags, None, None, 0, 0.0, ctypes.addressof(tun) if tun is not None else None)
+        opts = _Opts(0, 0.0, MODES[mode], flags, None, None, 0, 0.0,
+                     ctypes.addressof(tun) if tun is not None else None)
         tr = self._trace(trace_cap, timing)
         self._ms_src = src  # the device ids must outlive an enqueued run
         rc = lib().ipg_run_multi_sssp(self._h, src.data_ptr(), q, int(max_supersteps), ctypes.byref(opts),

@@ -19,6 +19,8 @@ size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w) {
     r.l1 = c.take<double>(kCtrSlots * 16);  // one 128-byte line per slot
     r.value_hot = c.take<double>(nn);
     r.pr_pieces = c.take<PrPiece>(kCtrSlots * piece_seg(e));
+    r.pr_cnt = c.take<PrCntSlot>(2 * kCtrSlots);
+    r.pr_rec = c.take<unsigned long long>(3 * static_cast<size_t>(kPrTraceCap));
   } else {
     r.value_u32 = c.take<uint32_t>(nn);
     r.mail_a = c.take<uint32_t>(nn);
@@ -144,7 +146,7 @@ extern "C" ipg_status ipg_run(ipg_graph* g, ipg_app app, ipg_combiner combiner, 
                        (app == IPG_APP_CC_HASHMIN && combiner == IPG_COMBINE_MIN) ||
                        (app == IPG_APP_SSSP && combiner == IPG_COMBINE_MIN);
   if (!ok_pair) return fail(IPG_EUNSUPPORTED, "ipg_run: (app, combiner) must be (PAGERANK, SUM), (CC, MIN) or (SSSP, MIN)");
-  ipg_run_opts o{0, IPG_MODE_AUTO, 0, nullptr, nullptr, 0, 0.0, nullptr};
+  ipg_run_opts o{0, 0.0, IPG_MODE_AUTO, 0, nullptr, nullptr, 0, 0.0, nullptr};
   if (opts) o = *opts;
   if (o.mode != IPG_MODE_AUTO && o.mode != IPG_MODE_PUSH && o.mode != IPG_MODE_PULL)
     return fail(IPG_EINVAL, "ipg_run: unknown mode");

@@ -163,6 +163,7 @@ struct ipg_graph {
     const uint32_t* parts;
     uint32_t num_parts;
     uint32_t hot, grid, blocked;
+    double damp;
   } pr_key;
   // HIP events reused by every run's timing (created on first use)
   std::vector<hipEvent_t> events;

@@ -121,6 +121,15 @@ struct PrPiece {
   double c;                // the sender's rank / out-degree
 };
 
+// Per-superstep counts of a PageRank run (vertices that ran compute, that
+// broadcast, and their out-degree sum), added by the workgroups into one of
+// kCtrSlots slots each.
+struct alignas(64) PrCntSlot {
+  unsigned long long active, senders, messages, pad[5];
+};
+static_assert(sizeof(PrCntSlot) == 64, "one slot per 64-byte line");
+constexpr uint32_t kPrTraceCap = 4096;  // PageRank supersteps with a trace record (later ones are not recorded)
+
 // Run workspace, carved from the caller's device buffer.
 struct RunWs {
   // PageRank
@@ -132,6 +141,8 @@ struct RunWs {
   double* l1;         // [kCtrSlots] L1 change of an update, spread over slots (convergence runs)
   double* value_hot;  // [n] ranks under the hot-first names (renamed store), mapped back at the end
   PrPiece* pr_pieces; // [kCtrSlots * piece_seg(e)] piece queue of a push superstep
+  PrCntSlot* pr_cnt;  // [2][kCtrSlots] per-superstep counts (set s & 1)
+  unsigned long long* pr_rec;  // [kPrTraceCap][3] trace records: active, senders, messages
   // CC / SSSP
   uint32_t* value_u32;  // [n] labels or distances
   uint32_t* mail_a;     // [n] one-slot min mailboxes, ping (INF = empty)

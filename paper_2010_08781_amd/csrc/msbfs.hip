@@ -893,7 +893,7 @@ extern "C" ipg_status ipg_run_multi_sssp(ipg_graph* g, const uint32_t* sources, 
   if (num_sources == 0 || num_sources > kMsMaxQueries)
     return fail(IPG_EINVAL, "ipg_run_multi_sssp: num_sources must be in [1, 256]");
   if (g->csr_w) return fail(IPG_EUNSUPPORTED, "ipg_run_multi_sssp: the graph has edge weights (unit weights only)");
-  ipg_run_opts o{0, IPG_MODE_AUTO, 0, nullptr, nullptr, 0, 0.0, nullptr};
+  ipg_run_opts o{0, 0.0, IPG_MODE_AUTO, 0, nullptr, nullptr, 0, 0.0, nullptr};
   if (opts) o = *opts;
   if (o.mode != IPG_MODE_AUTO && o.mode != IPG_MODE_PUSH && o.mode != IPG_MODE_PULL)
     return fail(IPG_EINVAL, "ipg_run_multi_sssp: unknown mode");

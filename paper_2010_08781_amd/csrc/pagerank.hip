@@ -1,10 +1,15 @@
 // pagerank.hip -- PageRank (Fig. 8) on the superstep engine, FP64.
 //
 // Superstep 0 sets every rank to 1/N; superstep s >= 1 sets
-//   rank(v) = 0.15/N + 0.85 * (sum of the messages v received),
-// and while s < T every vertex broadcasts rank / out-degree (a vertex
-// without out-edges reaches nobody).  At s = T all vertices halt.  Messages
-// are combined by '+=' (the sum combiner of Fig. 8).
+//   rank(v) = (1 - d)/N + d * (sum of the messages v received),
+// with the damping d a run parameter (0.85 in Fig. 8), and while s < T every
+// vertex broadcasts rank / out-degree (a vertex without out-edges reaches
+// nobody).  At s = T all vertices halt.  Messages are combined by '+=' (the
+// sum combiner of Fig. 8).
+//
+// Every kernel that runs compute on a vertex counts it (active), and, when
+// the vertex broadcasts, counts it as a sender and adds its out-degree
+// (messages): the trace of the run is counted on the device (PrTrace).
 //
 // Pull form (Section 4.3.2): a broadcast writes one outbox value per vertex,
 // contrib(u) = rank(u)/outdeg(u) (0 when outdeg is 0), and every vertex
@@ -25,6 +30,66 @@
 
 namespace ipg {
 
+// Per-superstep counts of a PageRank run (PrCntSlot): the first launch of
+// superstep s + 1 (and a one-wavefront launch after the last superstep)
+// folds the slots of superstep s into record s and clears them; the slot
+// sets alternate by superstep parity.
+static_assert(kCtrSlots == kWave, "one slot per lane of the folding wavefront");
+struct PrTrace {
+  PrCntSlot* add;            // the slots this superstep's kernels add into
+  PrCntSlot* fold;           // the previous superstep's slots, or null (superstep 0)
+  unsigned long long* rec;   // [kPrTraceCap][3]: active, senders, messages
+  uint32_t fold_step;        // the superstep whose slots `fold` holds
+};
+
+// Per-thread counts of the vertices a thread finished.
+struct PrTally {
+  unsigned long long rows = 0, senders = 0, messages = 0;
+};
+
+// Workgroup 0, wavefront 0: record superstep t.fold_step and clear its slots.
+// Called at the start of a kernel; no barrier (the slots it reads and
+// clears are not those the kernel adds into).
+__device__ __forceinline__ void pr_trace_fold(const PrTrace& t) {
+  if (!t.fold || blockIdx.x != 0 || threadIdx.x >= kWave) return;
+  PrCntSlot* sl = t.fold + threadIdx.x;
+  unsigned long long a = sl->active, b = sl->senders, c = sl->messages;
+  sl->active = 0;
+  sl->senders = 0;
+  sl->messages = 0;
+  a = wave_sum_u64(a);
+  b = wave_sum_u64(b);
+  c = wave_sum_u64(c);
+  if (threadIdx.x == 0 && t.fold_step < kPrTraceCap) {
+    t.rec[3 * t.fold_step + 0] = a;
+    t.rec[3 * t.fold_step + 1] = b;
+    t.rec[3 * t.fold_step + 2] = c;
+  }
+}
+
+// Workgroup sum of the threads' tallies added to the workgroup's slot
+// (every thread must call; at most 1024 threads).
+__device__ __forceinline__ void pr_tally_flush(const PrTrace& t, const PrTally& x) {
+  __shared__ unsigned long long part[3][1024 / kWave];
+  const unsigned long long a = wave_sum_u64(x.rows), b = wave_sum_u64(x.senders), c = wave_sum_u64(x.messages);
+  const uint32_t w = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    part[0][w] = a;
+    part[1][w] = b;
+    part[2][w] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    unsigned long long sum = 0;
+    for (uint32_t i = 0; i < blockDim.x / kWave; ++i) sum += part[threadIdx.x][i];
+    PrCntSlot* sl = t.add + (blockIdx.x % kCtrSlots);
+    if (sum) atomicAdd(threadIdx.x == 0 ? &sl->active : threadIdx.x == 1 ? &sl->senders : &sl->messages, sum);
+  }
+}
+
+// Folds the slots of the last superstep of a run (one wavefront).
+__global__ void pr_trace_last_kernel(PrTrace t) { pr_trace_fold(t); }
+
 struct PrPullArgs {
   PullTiling t;
   const uint32_t* outdeg;
@@ -32,16 +97,30 @@ struct PrPullArgs {
   double* contrib_out;
   double* value;
   double* partial;        // per long-row chunk
-  double ratio;           // 0.15 / N
+  double ratio;           // (1 - d) / N
+  double damp;            // d
+  double teleport;        // 1 - d (divided by the part's vertex count with part_n)
   const uint32_t* part_n; // vertex count of each vertex's part, or null (one part)
+  PrTrace tr;
   double* l1;             // convergence run: rank stored every update, its L1 change added here (else null)
   int last;               // superstep == T: store the rank, no broadcast
 };
 
+// Counts of a vertex that ran compute, and broadcast unless `last`.
+__device__ __forceinline__ void pr_tally(PrTally& t, int last, uint32_t d) {
+  ++t.rows;
+  if (!last) {
+    ++t.senders;
+    t.messages += d;
+  }
+}
+
 // The rank of v after this update: the outbox for the next update, the
 // stored rank when this is the last update, and both (plus the change of
 // the rank) in a convergence run.
-__device__ __forceinline__ void pr_store(const PrPullArgs& a, uint32_t v, double rank, uint32_t d, double& l1) {
+__device__ __forceinline__ void pr_store(const PrPullArgs& a, uint32_t v, double rank, uint32_t d, double& l1,
+                                         PrTally& tl) {
+  pr_tally(tl, a.last, d);
   if (a.l1) {
     l1 += fabs(rank - a.value[v]);
     a.value[v] = rank;
@@ -66,14 +145,14 @@ __device__ __forceinline__ void flush_l1(double* slots, double x) {
   }
 }
 
-// 0.15 / N for the part that holds v.
-__device__ __forceinline__ double pr_ratio(double ratio, const uint32_t* part_n, uint32_t v) {
-  return part_n ? 0.15 / static_cast<double>(part_n[v]) : ratio;
+// (1 - d) / N for the part that holds v.
+__device__ __forceinline__ double pr_ratio(double ratio, double teleport, const uint32_t* part_n, uint32_t v) {
+  return part_n ? teleport / static_cast<double>(part_n[v]) : ratio;
 }
 
-__device__ __forceinline__ void pr_finish(const PrPullArgs& a, uint32_t v, double sum, double& l1) {
-  const double rank = pr_ratio(a.ratio, a.part_n, v) + 0.85 * sum;
-  pr_store(a, v, rank, a.outdeg[v], l1);
+__device__ __forceinline__ void pr_finish(const PrPullArgs& a, uint32_t v, double sum, double& l1, PrTally& tl) {
+  const double rank = pr_ratio(a.ratio, a.teleport, a.part_n, v) + a.damp * sum;
+  pr_store(a, v, rank, a.outdeg[v], l1, tl);
 }
 
 // One pull item held in registers ahead of its gathers: its metadata, its
@@ -146,6 +225,7 @@ __global__ __launch_bounds__(WAVES * kWave) void pr_items_kernel(PrPullArgs a, u
   __shared__ uint32_t s_off[WAVES][kItemRows + 1];
   __shared__ uint32_t s_deg[WAVES][kItemRows];
   extern __shared__ double s_hot[];
+  pr_trace_fold(a.tr);
   const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
   double* tile = s_tile[wv];
   uint32_t* soff = s_off[wv];
@@ -172,6 +252,7 @@ __global__ __launch_bounds__(WAVES * kWave) void pr_items_kernel(PrPullArgs a, u
     __syncthreads();
   }
   double l1 = 0.0;
+  PrTally tl;
   for (; item < ni; item += nw) {
     const PullItem m2 = item + 2 * nw < ni ? a.t.items[item + 2 * nw] : no_item();
     // Cold sources are gathered from memory and hot ones from LDS into
@@ -231,8 +312,8 @@ __global__ __launch_bounds__(WAVES * kWave) void pr_items_kernel(PrPullArgs a, u
         for (uint32_t o = G >> 1; o >= 1; o >>= 1) s += __shfl_xor(s, static_cast<int>(o));
         if (li == 0 && row < nrows) {
           const uint32_t v = cur.it.r0 + row;
-          const double rank = pr_ratio(a.ratio, a.part_n, v) + 0.85 * s;
-          pr_store(a, v, rank, sdeg[row], l1);
+          const double rank = pr_ratio(a.ratio, a.teleport, a.part_n, v) + a.damp * s;
+          pr_store(a, v, rank, sdeg[row], l1, tl);
         }
       }
       wave_lds_sync();  // the tile is rewritten by the next item
@@ -241,6 +322,7 @@ __global__ __launch_bounds__(WAVES * kWave) void pr_items_kernel(PrPullArgs a, u
     m_next = m2;
   }
   if (a.l1) flush_l1(a.l1, l1);
+  pr_tally_flush(a.tr, tl);
 }
 
 // What finishing a row reads besides its sum: loaded for a batch of rows
@@ -258,9 +340,11 @@ __device__ __forceinline__ RowIn pr_row_load(const PrPullArgs& a, uint32_t v) {
   return in;
 }
 // pr_finish with the row's inputs already loaded.
-__device__ __forceinline__ void pr_row_finish(const PrPullArgs& a, uint32_t v, double sum, const RowIn& in, double& l1) {
-  const double ratio = a.part_n ? 0.15 / static_cast<double>(in.pn) : a.ratio;
-  const double rank = ratio + 0.85 * sum;
+__device__ __forceinline__ void pr_row_finish(const PrPullArgs& a, uint32_t v, double sum, const RowIn& in, double& l1,
+                                              PrTally& tl) {
+  const double ratio = a.part_n ? a.teleport / static_cast<double>(in.pn) : a.ratio;
+  const double rank = ratio + a.damp * sum;
+  pr_tally(tl, a.last, in.deg);
   if (a.l1) {
     l1 += fabs(rank - in.old);
     a.value[v] = rank;
@@ -275,16 +359,19 @@ __device__ __forceinline__ void pr_row_finish(const PrPullArgs& a, uint32_t v, d
 // chunk order (one wavefront per row; a fixed order, so results are
 // bitwise reproducible).
 __global__ __launch_bounds__(kBlock) void pr_longrow_kernel(PrPullArgs a) {
+  pr_trace_fold(a.tr);
   const uint32_t l = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   double l1 = 0.0;
+  PrTally tl;
   if (l < a.t.nl) {  // wave-uniform
     const uint32_t f = a.t.lr_first[l], nch = a.t.lr_first[l + 1] - f;
     double s = 0.0;
     for (uint32_t i = lane_id(); i < nch; i += kWave) s += a.partial[f + i];
     s = wave_sum(s);
-    if (lane_id() == 0) pr_finish(a, a.t.long_rows[l], s, l1);
+    if (lane_id() == 0) pr_finish(a, a.t.long_rows[l], s, l1, tl);
   }
   if (a.l1) flush_l1(a.l1, l1);
+  pr_tally_flush(a.tr, tl);
 }
 
 // Blocked pull (IPG_GRAPH_BLOCKED): the in-edges of each block of at most
@@ -303,6 +390,7 @@ struct PrBlkArgs {
 __global__ __launch_bounds__(kBlkThreads) void pr_blocked_kernel(PrPullArgs a, PrBlkArgs b) {
   // + one pad slot per lane (see blk_stream)
   __shared__ double part[kBlkRows + kWave];
+  pr_trace_fold(a.tr);
   const BlkSlice sl = b.v.slices[blockIdx.x];
   for (uint32_t r = threadIdx.x; r < sl.rows; r += kBlkThreads) part[r] = 0.0;
   if (threadIdx.x < kWave) part[kBlkRows + threadIdx.x] = 0.0;
@@ -314,6 +402,7 @@ __global__ __launch_bounds__(kBlkThreads) void pr_blocked_kernel(PrPullArgs a, P
   __syncthreads();
   const uint32_t r0 = sl.row0, rows = sl.rows;
   double l1 = 0.0;
+  PrTally tl;
   if (sl.poff == kNoPartial) {
     // rows in batches of kFinBatch per thread, every batch's inputs loaded
     // first (indices clamped into the block: the loads are unconditional)
@@ -328,7 +417,7 @@ __global__ __launch_bounds__(kBlkThreads) void pr_blocked_kernel(PrPullArgs a, P
 #pragma unroll
       for (uint32_t j = 0; j < kFinBatch; ++j) {
         const uint32_t rj = r + j * kBlkThreads;
-        if (rj < rows) pr_row_finish(a, r0 + rj, part[rj], in[j], l1);
+        if (rj < rows) pr_row_finish(a, r0 + rj, part[rj], in[j], l1, tl);
       }
     }
   } else {
@@ -336,6 +425,7 @@ __global__ __launch_bounds__(kBlkThreads) void pr_blocked_kernel(PrPullArgs a, P
     for (uint32_t r = threadIdx.x; r < rows; r += kBlkThreads) dst[r] = part[r];
   }
   if (a.l1) flush_l1(a.l1, l1);
+  pr_tally_flush(a.tr, tl);
 }
 
 // Blocked pull, second launch: the rows of every block with several slices
@@ -344,9 +434,11 @@ __global__ __launch_bounds__(kBlkThreads) void pr_blocked_kernel(PrPullArgs a, P
 // of 64 rows at a time (lane = row): one record load, then every partial
 // (eight at a time) and the row's inputs in flight together.
 __global__ __launch_bounds__(kBlock) void pr_blocked_finish_kernel(PrPullArgs a, PrBlkArgs b) {
+  pr_trace_fold(a.tr);
   const uint32_t lane = lane_id();
   const uint32_t nw = gridDim.x * kWavesPerBlock;
   double l1 = 0.0;
+  PrTally tl;
   for (uint32_t w = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; w < b.v.ngroups; w += nw) {  // wave-uniform
     const BlkGroup gr = b.v.groups[w];
     const uint32_t rr = lane < gr.nrows ? lane : gr.nrows - 1;
@@ -364,9 +456,10 @@ __global__ __launch_bounds__(kBlock) void pr_blocked_finish_kernel(PrPullArgs a,
       for (uint32_t j = 0; j < 8; ++j)
         if (k + j < gr.k) sum += x[j];
     }
-    if (lane < gr.nrows) pr_row_finish(a, gr.row0 + lane, sum, in, l1);
+    if (lane < gr.nrows) pr_row_finish(a, gr.row0 + lane, sum, in, l1, tl);
   }
   if (a.l1) flush_l1(a.l1, l1);
+  pr_tally_flush(a.tr, tl);
 }
 
 // 1 / N for the part that holds v.
@@ -376,17 +469,19 @@ __device__ __forceinline__ double pr_init(double init, const uint32_t* part_n, u
 
 // Superstep 0 of the pull form: rank 1/N, outbox 1/N/outdeg (and the rank
 // itself when a convergence run tracks its changes).
-__global__ void pr_pull_init_kernel(uint32_t n, const uint32_t* outdeg, double init, const uint32_t* part_n,
-                                    double* contrib, double* value, int last, int track) {
+__global__ __launch_bounds__(kBlock) void pr_pull_init_kernel(uint32_t n, const uint32_t* outdeg, double init,
+                                                               const uint32_t* part_n, double* contrib, double* value,
+                                                               int last, int track, PrTrace tr) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  PrTally tl;
   for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
     const double x = pr_init(init, part_n, static_cast<uint32_t>(v));
     if (last || track) value[v] = x;
-    if (!last) {
-      const uint32_t d = outdeg[v];
-      contrib[v] = d ? x / static_cast<double>(d) : 0.0;
-    }
+    const uint32_t d = outdeg[v];
+    pr_tally(tl, last, d);
+    if (!last) contrib[v] = d ? x / static_cast<double>(d) : 0.0;
   }
+  pr_tally_flush(tr, tl);
 }
 
 // Vertex count of the part of every vertex: part p holds [off[p], off[p+1]);
@@ -419,7 +514,9 @@ struct PrPushArgs {
   double* mail_out;      // atomically accumulated
   double* value;
   double ratio, init;
+  double damp, teleport; // d and 1 - d
   const uint32_t* part_n;
+  PrTrace tr;
   double* l1;            // convergence run: rank stored every superstep, its L1 change added here
   int first, last;
   PrPiece* pieces;       // piece queue (see kPieceMin)
@@ -469,8 +566,10 @@ __device__ __forceinline__ bool pr_queue_pieces(const PrPushArgs& a, bool has, u
 // out-neighbour's next mailbox.
 __global__ __launch_bounds__(kBlock) void pr_push_kernel(PrPushArgs a) {
   clear_slots(a.ctr_clear);
+  pr_trace_fold(a.tr);
   const uint64_t v = blockIdx.x * (uint64_t)kBlock + threadIdx.x;
   double l1 = 0.0;
+  PrTally tl;
   bool has = false;
   uint64_t beg = 0, end = 0;
   double c = 0.0;
@@ -481,13 +580,14 @@ __global__ __launch_bounds__(kBlock) void pr_push_kernel(PrPushArgs a) {
     } else {
       const double m = a.mail_in[v];
       a.mail_in[v] = 0.0;
-      rank = pr_ratio(a.ratio, a.part_n, static_cast<uint32_t>(v)) + 0.85 * m;
+      rank = pr_ratio(a.ratio, a.teleport, a.part_n, static_cast<uint32_t>(v)) + a.damp * m;
       if (a.l1) l1 += fabs(rank - a.value[v]);
     }
     if (a.last || a.l1) a.value[v] = rank;
+    beg = a.off[v];
+    end = a.off[v + 1];
+    pr_tally(tl, a.last, static_cast<uint32_t>(end - beg));
     if (!a.last) {
-      beg = a.off[v];
-      end = a.off[v + 1];
       has = end > beg;
       if (has) c = rank / static_cast<double>(end - beg);
     }
@@ -497,6 +597,7 @@ __global__ __launch_bounds__(kBlock) void pr_push_kernel(PrPushArgs a) {
   const int32_t* dst = a.dst;
   twc_scatter(has, beg, end, c, [&](uint64_t e, double p) { unsafeAtomicAdd(mail + dst[e], p); });
   if (a.l1) flush_l1(a.l1, l1);
+  pr_tally_flush(a.tr, tl);
 }
 
 // Second launch of a push superstep: the queued pieces dealt over the grid
@@ -640,29 +741,71 @@ static hipError_t launch_pr_pull(const PrPullArgs& a, const PrPullStore& ps, con
     PrBlkArgs b;
     b.v = blk_view(*ps.blk);
     b.n = n;
+    // the first launch folds the previous superstep's counts, the second
+    // only adds (when the first has no workgroups, the second folds)
+    PrPullArgs a2 = a;
     hipError_t err = hipSuccess;
     if (ps.blk->nslices) {  // none when the graph has no edges
       hipLaunchKernelGGL(pr_blocked_kernel, dim3(ps.blk->nslices), dim3(kBlkThreads), 0, s, a, b);
       err = hipGetLastError();
+      a2.tr.fold = nullptr;
     }
-    if (err != hipSuccess || !b.v.ngroups) return err;
-    const uint32_t grid = grid_for(b.v.ngroups, kWavesPerBlock, 4096);
-    hipLaunchKernelGGL(pr_blocked_finish_kernel, dim3(grid), dim3(kBlock), 0, s, a, b);
+    if (err != hipSuccess) return err;
+    if (b.v.ngroups) {
+      const uint32_t grid = grid_for(b.v.ngroups, kWavesPerBlock, 4096);
+      hipLaunchKernelGGL(pr_blocked_finish_kernel, dim3(grid), dim3(kBlock), 0, s, a2, b);
+      err = hipGetLastError();
+      a2.tr.fold = nullptr;
+    }
+    if (err != hipSuccess || !a2.tr.fold) return err;
+    hipLaunchKernelGGL(pr_trace_last_kernel, dim3(1), dim3(kWave), 0, s, a2.tr);
     return hipGetLastError();
   }
   hipError_t err = launch_pr_items(a, ps.perm != nullptr, tn, n, s);
-  if (err != hipSuccess || !ps.t.nl) return err;
-  hipLaunchKernelGGL(pr_longrow_kernel, dim3((ps.t.nl + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0, s, a);
+  if (err != hipSuccess) return err;
+  PrPullArgs a2 = a;
+  if (a.t.ni) a2.tr.fold = nullptr;
+  if (ps.t.nl) {
+    hipLaunchKernelGGL(pr_longrow_kernel, dim3((ps.t.nl + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0, s,
+                       a2);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    a2.tr.fold = nullptr;
+  }
+  if (!a2.tr.fold) return hipSuccess;
+  hipLaunchKernelGGL(pr_trace_last_kernel, dim3(1), dim3(kWave), 0, s, a2.tr);
+  return hipGetLastError();
+}
+
+// The trace slots of superstep `step` (and those it folds).
+static PrTrace pr_trace_at(const RunWs& w, uint32_t step) {
+  PrTrace t;
+  t.add = w.pr_cnt + (step & 1) * kCtrSlots;
+  t.fold = step ? w.pr_cnt + ((step - 1) & 1) * kCtrSlots : nullptr;
+  t.rec = w.pr_rec;
+  t.fold_step = step ? step - 1 : 0;
+  return t;
+}
+
+// Clears both trace slot sets before superstep 0 adds into them.
+static hipError_t pr_trace_begin(const RunWs& w, hipStream_t s) {
+  return fill_u32(reinterpret_cast<uint32_t*>(w.pr_cnt), 2 * kCtrSlots * sizeof(PrCntSlot) / 4, 0, s);
+}
+
+// Folds the last superstep's counts into its record.
+static hipError_t pr_trace_end(const RunWs& w, uint32_t last_step, hipStream_t s) {
+  PrTrace t = pr_trace_at(w, last_step + 1);
+  hipLaunchKernelGGL(pr_trace_last_kernel, dim3(1), dim3(kWave), 0, s, t);
   return hipGetLastError();
 }
 
 // Every launch of one PageRank run, in order, on stream s (also used to
 // capture the run as a graph, with tm == nullptr).
-static hipError_t enqueue_pagerank(ipg_graph* g, uint32_t T, bool push, const RunWs& w, const uint32_t* part_off,
-                                   uint32_t parts, const Tune& tn, hipStream_t s, StepTimer* tm) {
+static hipError_t enqueue_pagerank(ipg_graph* g, uint32_t T, double d, bool push, const RunWs& w,
+                                   const uint32_t* part_off, uint32_t parts, const Tune& tn, hipStream_t s,
+                                   StepTimer* tm) {
   hipError_t err;
   const uint32_t n = g->n;
-  const double ratio = 0.15 / static_cast<double>(n);
+  const double ratio = (1.0 - d) / static_cast<double>(n);
   const double init = 1.0 / static_cast<double>(n);
   const uint32_t gv = grid_for(n, kBlock, 16384);
   const PrPullStore ps = pr_store_of(g, w);
@@ -673,10 +816,11 @@ static hipError_t enqueue_pagerank(ipg_graph* g, uint32_t T, bool push, const Ru
     if ((err = hipGetLastError()) != hipSuccess) return err;
     part_n = w.part_n;
   }
+  if ((err = pr_trace_begin(w, s)) != hipSuccess) return err;
   if (!push) {
     if (tm && (err = tm->start(s)) != hipSuccess) return err;
     hipLaunchKernelGGL(pr_pull_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, ps.outdeg, init, part_n, w.f64_a, ps.value,
-                       T == 0, 0);
+                       T == 0, 0, pr_trace_at(w, 0));
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if (tm && (err = tm->step(s, 0)) != hipSuccess) return err;
     PrPullArgs a;
@@ -685,15 +829,19 @@ static hipError_t enqueue_pagerank(ipg_graph* g, uint32_t T, bool push, const Ru
     a.value = ps.value;
     a.partial = w.partial;
     a.ratio = ratio;
+    a.damp = d;
+    a.teleport = 1.0 - d;
     a.part_n = part_n;
     a.l1 = nullptr;
     for (uint32_t step = 1; step <= T; ++step) {
       a.contrib_in = (step & 1) ? w.f64_a : w.f64_b;
       a.contrib_out = (step & 1) ? w.f64_b : w.f64_a;
       a.last = step == T;
+      a.tr = pr_trace_at(w, step);
       if ((err = launch_pr_pull(a, ps, tn, n, s)) != hipSuccess) return err;
       if (tm && (err = tm->step(s, step)) != hipSuccess) return err;
     }
+    if ((err = pr_trace_end(w, T, s)) != hipSuccess) return err;
     if (ps.perm) {
       hipLaunchKernelGGL(pr_unrename_kernel, dim3(gv), dim3(kBlock), 0, s, ps.value, ps.perm, n, w.value_f64);
       if ((err = hipGetLastError()) != hipSuccess) return err;
@@ -711,6 +859,8 @@ static hipError_t enqueue_pagerank(ipg_graph* g, uint32_t T, bool push, const Ru
     a.value = w.value_f64;
     a.ratio = ratio;
     a.init = init;
+    a.damp = d;
+    a.teleport = 1.0 - d;
     a.part_n = part_n;
     a.l1 = nullptr;
     const uint32_t grid = grid_for(n, kBlock, 0xFFFFFFFFu);
@@ -719,20 +869,22 @@ static hipError_t enqueue_pagerank(ipg_graph* g, uint32_t T, bool push, const Ru
       a.mail_out = (step & 1) ? w.f64_a : w.f64_b;
       a.first = step == 0;
       a.last = step == T;
+      a.tr = pr_trace_at(w, step);
       if ((err = launch_pr_push(a, w, g->e, grid, step, s)) != hipSuccess) return err;
       if (tm && (err = tm->step(s, step)) != hipSuccess) return err;
     }
+    if ((err = pr_trace_end(w, T, s)) != hipSuccess) return err;
   }
   return hipSuccess;
 }
 
 // The captured graph of the run described by the arguments, capturing it
 // (again) when the handle holds none or one for another run.
-static ipg_status pagerank_graph(ipg_graph* g, uint32_t T, bool push, const RunWs& w, const void* ws,
+static ipg_status pagerank_graph(ipg_graph* g, uint32_t T, double d, bool push, const RunWs& w, const void* ws,
                                  const uint32_t* part_off, uint32_t parts, const Tune& tn, hipGraphExec_t* out) {
   auto& k = g->pr_key;
-  if (g->pr_exec && k.T == T && k.push == (push ? 1 : 0) && k.ws == ws && k.parts == part_off && k.num_parts == parts &&
-      k.hot == tn.pr_hot && k.grid == tn.pull_grid && k.blocked == tn.blocked) {
+  if (g->pr_exec && k.T == T && k.damp == d && k.push == (push ? 1 : 0) && k.ws == ws && k.parts == part_off &&
+      k.num_parts == parts && k.hot == tn.pr_hot && k.grid == tn.pull_grid && k.blocked == tn.blocked) {
     *out = g->pr_exec;
     return IPG_OK;
   }
@@ -746,7 +898,7 @@ static ipg_status pagerank_graph(ipg_graph* g, uint32_t T, bool push, const RunW
   }
   if (!g->cap_stream) IPG_HIP(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
   IPG_HIP(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
-  const hipError_t qe = enqueue_pagerank(g, T, push, w, part_off, parts, tn, g->cap_stream, nullptr);
+  const hipError_t qe = enqueue_pagerank(g, T, d, push, w, part_off, parts, tn, g->cap_stream, nullptr);
   hipGraph_t graph = nullptr;
   const hipError_t ce = hipStreamEndCapture(g->cap_stream, &graph);
   if (qe != hipSuccess) {
@@ -757,6 +909,7 @@ static ipg_status pagerank_graph(ipg_graph* g, uint32_t T, bool push, const RunW
   g->pr_graph = graph;
   IPG_HIP(hipGraphInstantiate(&g->pr_exec, graph, nullptr, nullptr, 0));
   k.T = T;
+  k.damp = d;
   k.push = push ? 1 : 0;
   k.ws = ws;
   k.parts = part_off;
@@ -772,12 +925,12 @@ static ipg_status pagerank_graph(ipg_graph* g, uint32_t T, bool push, const RunW
 // change reduced on the device and read back; the run stops after the
 // first update whose change is below `tol`, or after Tmax updates.
 // Returns the number of updates run in *T_out.
-static ipg_status run_pagerank_converge(ipg_graph* g, uint32_t Tmax, bool push, double tol, const RunWs& w,
-                                        const uint32_t* part_off, uint32_t parts, const Tune& tn, hipStream_t s,
-                                        StepTimer& tm,
-                                        ipg_run_stats* st, uint32_t* T_out, bool* converged) {
+static ipg_status run_pagerank_converge(ipg_graph* g, uint32_t Tmax, double d, bool push, double tol,
+                                        const RunWs& w, const uint32_t* part_off, uint32_t parts, const Tune& tn,
+                                        hipStream_t s, StepTimer& tm, ipg_run_stats* st, uint32_t* T_out,
+                                        bool* converged) {
   const uint32_t n = g->n;
-  const double ratio = 0.15 / static_cast<double>(n);
+  const double ratio = (1.0 - d) / static_cast<double>(n);
   const double init = 1.0 / static_cast<double>(n);
   const uint32_t gv = grid_for(n, kBlock, 16384);
   const PrPullStore ps = pr_store_of(g, w);
@@ -803,10 +956,11 @@ static ipg_status run_pagerank_converge(ipg_graph* g, uint32_t Tmax, bool push, 
   *converged = false;
   uint32_t T = Tmax;
   if (st && st->residual && st->trace_cap) st->residual[0] = 0.0;
+  IPG_HIP(pr_trace_begin(w, s));
   if (!push) {
     IPG_HIP(tm.start(s));
     hipLaunchKernelGGL(pr_pull_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, ps.outdeg, init, part_n, w.f64_a, ps.value,
-                       0, 1);
+                       0, 1, pr_trace_at(w, 0));
     IPG_HIP(hipGetLastError());
     IPG_HIP(tm.step(s, 0));
     PrPullArgs a;
@@ -815,6 +969,8 @@ static ipg_status run_pagerank_converge(ipg_graph* g, uint32_t Tmax, bool push, 
     a.value = ps.value;
     a.partial = w.partial;
     a.ratio = ratio;
+    a.damp = d;
+    a.teleport = 1.0 - d;
     a.part_n = part_n;
     a.l1 = w.l1;
     a.last = 0;
@@ -822,6 +978,7 @@ static ipg_status run_pagerank_converge(ipg_graph* g, uint32_t Tmax, bool push, 
       IPG_HIP(fill_f64(w.l1, kSlotDoubles, 0.0, s));
       a.contrib_in = (step & 1) ? w.f64_a : w.f64_b;
       a.contrib_out = (step & 1) ? w.f64_b : w.f64_a;
+      a.tr = pr_trace_at(w, step);
       IPG_HIP(launch_pr_pull(a, ps, tn, n, s));
       IPG_HIP(tm.step(s, step));
       double d = 0.0;
@@ -849,6 +1006,8 @@ static ipg_status run_pagerank_converge(ipg_graph* g, uint32_t Tmax, bool push, 
     a.value = w.value_f64;
     a.ratio = ratio;
     a.init = init;
+    a.damp = d;
+    a.teleport = 1.0 - d;
     a.part_n = part_n;
     a.l1 = w.l1;
     const uint32_t grid = grid_for(n, kBlock, 0xFFFFFFFFu);
@@ -858,6 +1017,7 @@ static ipg_status run_pagerank_converge(ipg_graph* g, uint32_t Tmax, bool push, 
       a.mail_out = (step & 1) ? w.f64_a : w.f64_b;
       a.first = step == 0;
       a.last = step == Tmax;
+      a.tr = pr_trace_at(w, step);
       IPG_HIP(launch_pr_push(a, w, g->e, grid, step, s));
       IPG_HIP(tm.step(s, step));
       if (step == 0) continue;
@@ -871,6 +1031,7 @@ static ipg_status run_pagerank_converge(ipg_graph* g, uint32_t Tmax, bool push, 
       }
     }
   }
+  IPG_HIP(pr_trace_end(w, T, s));
   IPG_HIP(tm.finish(s));
   *T_out = T;
   return IPG_OK;
@@ -881,12 +1042,14 @@ ipg_status run_pagerank(ipg_graph* g, uint32_t T, const ipg_run_opts& o, const R
   const uint32_t n = g->n;
   const bool push = (o.mode == IPG_MODE_PUSH);
   const Tune tn = resolve_tuning(o.tuning);
+  const double d = o.damping == 0.0 ? 0.85 : o.damping;
+  if (!(d > 0.0 && d <= 1.0)) return fail(IPG_EINVAL, "ipg_run: damping must be in (0, 1] (0 = 0.85)");
   uint32_t room = 0;
   IPG_HIP(max_hot_entries(&room));  // queried here, never during a stream capture
   const uint32_t* part_off = nullptr;
   uint32_t parts = 0;
   if (o.flags & IPG_RUN_ENQUEUE) {  // no host synchronisation: the offsets are the caller's to get right
-    IPG_HIP(enqueue_pagerank(g, T, push, w, o.num_parts ? o.part_offsets : nullptr, o.num_parts, tn, s, nullptr));
+    IPG_HIP(enqueue_pagerank(g, T, d, push, w, o.num_parts ? o.part_offsets : nullptr, o.num_parts, tn, s, nullptr));
     return IPG_OK;
   }
   if (o.part_offsets && o.num_parts) {
@@ -902,33 +1065,47 @@ ipg_status run_pagerank(ipg_graph* g, uint32_t T, const ipg_run_opts& o, const R
   bool converged = true;
   if (o.tolerance > 0.0) {
     uint32_t Tdone = T;
-    const ipg_status rc = run_pagerank_converge(g, T, push, o.tolerance, w, part_off, parts, tn, s, tm, st, &Tdone,
+    const ipg_status rc = run_pagerank_converge(g, T, d, push, o.tolerance, w, part_off, parts, tn, s, tm, st, &Tdone,
                                                 &converged);
     if (rc != IPG_OK) return rc;
     T = Tdone;
   } else if (o.flags & IPG_RUN_GRAPH) {
     hipGraphExec_t exec = nullptr;
-    const ipg_status rc = pagerank_graph(g, T, push, w, ws, part_off, parts, tn, &exec);
+    const ipg_status rc = pagerank_graph(g, T, d, push, w, ws, part_off, parts, tn, &exec);
     if (rc != IPG_OK) return rc;
     IPG_HIP(tm.start(s));
     IPG_HIP(hipGraphLaunch(exec, s));
     IPG_HIP(tm.finish(s));
   } else {
-    IPG_HIP(enqueue_pagerank(g, T, push, w, part_off, parts, tn, s, &tm));
+    IPG_HIP(enqueue_pagerank(g, T, d, push, w, part_off, parts, tn, s, &tm));
     IPG_HIP(tm.finish(s));
   }
-  // The PageRank trace is fixed by Fig. 8: every vertex runs in every
-  // superstep and broadcasts while s < T.
   if (st) {
+    // The trace as the kernels counted it: per superstep, the vertices that
+    // ran compute, those that broadcast and their out-degree sum.  The
+    // stream has been synchronised (tm.finish).
     const uint32_t steps = T + 1;
+    const uint32_t nrec = std::min(steps, kPrTraceCap);
+    std::vector<unsigned long long> rec(3 * static_cast<size_t>(nrec));
+    IPG_HIP(hipMemcpy(rec.data(), w.pr_rec, 3 * sizeof(unsigned long long) * nrec, hipMemcpyDeviceToHost));
+    if (o.tolerance > 0.0 && nrec == steps) {
+      // a convergence run stops after update T: the outboxes its kernels
+      // wrote in that superstep are never read (the run with a fixed T
+      // broadcasts nothing there)
+      rec[3 * (steps - 1) + 1] = 0;
+      rec[3 * (steps - 1) + 2] = 0;
+    }
+    uint64_t traversed = 0;
+    for (uint32_t k = 0; k < nrec; ++k) traversed += rec[3 * k + 2];
     st->supersteps = steps;
     st->halted = converged ? 1 : 0;
-    st->edges_traversed = static_cast<uint64_t>(T) * g->e;
+    // supersteps past the last record (nrec .. T - 1) each broadcast E messages
+    st->edges_traversed = traversed + (steps > nrec ? static_cast<uint64_t>(T - nrec) * g->e : 0);
     st->edges_examined = static_cast<uint64_t>(T) * g->e;
-    for (uint32_t k = 0; k < steps && k < st->trace_cap; ++k) {
-      if (st->active) st->active[k] = n;
-      if (st->senders) st->senders[k] = k < T ? n : 0;
-      if (st->messages) st->messages[k] = k < T ? g->e : 0;
+    for (uint32_t k = 0; k < nrec && k < st->trace_cap; ++k) {
+      if (st->active) st->active[k] = rec[3 * k + 0];
+      if (st->senders) st->senders[k] = rec[3 * k + 1];
+      if (st->messages) st->messages[k] = rec[3 * k + 2];
       if (st->examined) st->examined[k] = k < T ? g->e : 0;
       if (st->mode) st->mode[k] = push ? IPG_MODE_PUSH : IPG_MODE_PULL;
       if (st->frontier_deg) st->frontier_deg[k] = g->e;

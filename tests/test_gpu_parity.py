@@ -75,6 +75,36 @@ def test_pagerank_rmat_s14_every_superstep(ipg):
     check_pagerank(ipg, hg, Ts=tuple(range(0, 11)))
 
 
+@pytest.mark.parametrize("d", [0.5, 0.6, 0.99])
+def test_pagerank_damping(ipg, d):
+    # damping d != 0.85 (rank = (1-d)/N + d * sum) in every exchange and store:
+    # row items, blocked in-edges, push, the replayed graph, and a
+    # convergence run; trace counted on the device
+    hg = graphgen.workload("rmat-s14-dir")
+    plain = ipg.Graph.from_host(hg, rename=False)
+    blocked = ipg.Graph.from_host(hg, blocked=True)
+    for T in (1, 4, 10):
+        ref = oracle.run_graph("pagerank", hg, T, damping=d)
+        for g, mode, graph in ((plain, "pull", False), (plain, "push", False), (blocked, "pull", False),
+                               (blocked, "pull", True)):
+            vals, st = g.run("pagerank", T, mode=mode, damping=d, graph=graph)
+            err = max_rel(to_np(vals), ref.values)
+            assert err <= PR_RTOL, f"d={d} T={T} {mode} graph={graph}: {err:.3e}"
+            assert np.array_equal(st.trace, ref.trace)
+    want, T, _ = oracle.pagerank_converge(hg, 1e-6, 100, damping=d)
+    vals, st = blocked.run("pagerank", 100, mode="pull", damping=d, tol=1e-6)
+    assert st.supersteps == T + 1
+    assert max_rel(to_np(vals), want.values) <= PR_RTOL
+    assert np.array_equal(st.trace, want.trace)
+
+
+def test_pagerank_damping_rejected(ipg):
+    g = ipg.Graph.from_host(graphgen.workload("rmat-s14-dir"))
+    for d in (-0.1, 1.5, float("nan")):
+        with pytest.raises(ipg.IpgError):
+            g.run("pagerank", 3, damping=d)
+
+
 def test_pagerank_pull_bitwise_deterministic(ipg):
     hg = graphgen.workload("rmat-s14-dir")
     g = ipg.Graph.from_host(hg)
