@@ -1,12 +1,16 @@
 #!/usr/bin/env python3
 """Benchmark of the superstep engine on one MI355X.
 
-One step = one pass of the whole hot path over the workload graph: PageRank
-(10 rank updates, FP64, pull exchange), hash-min connected components to
-vote-to-halt and SSSP from vertex 0 to vote-to-halt (push/pull chosen per
-superstep by the trained selector, device-driven superstep loop), with
-launch parameters from the autotuner.  The graph (synthetic R-MAT, scale 20, edge factor 16,
-symmetrised, seed 2) is resident in HBM before timing starts.
+One step = one pass of the whole hot path over the workload: PageRank (10
+rank updates, d = 0.85, FP64, pull exchange) on the directed graph, then
+hash-min connected components and SSSP from vertex 0, each to vote-to-halt,
+on its symmetrised form (push/pull chosen per superstep by the trained
+selector, device-driven superstep loop), with launch parameters from the
+autotuner.  Default workload: the billion-edge configuration, synthetic
+R-MAT scale 26, edge factor 16, seed 5 (67.1M vertices; 1.06B directed
+edges, 2.10B symmetrised).  Graphs are resident in HBM before timing starts.
+A shorter pass of the same step on R-MAT scale 20 symmetrised (seed 2) is
+reported as a secondary object.
 
 Prints ONE JSON line.  `value` = GTEPS over the step: messages delivered
 (edges traversed by the method: the senders' out-degrees, summed over
@@ -67,15 +71,18 @@ def measured_traffic(workload: str, tuning) -> "int | None":
     return int(m.group(1))
 
 
-def batched_vs_plain(ipg, graphgen, np, torch, reps: int = 3, tune_cache=None) -> dict:
+def batched_vs_plain(ipg, graphgen, np, torch, reps: int = 3, tune_cache=None, cap: int = 64) -> dict:
     """End-to-end time of the batched workload against the plain form on the
     same GPU: 256 unit-weight SSSP queries (sources seeded among vertices with
     out-edges) on R-MAT scale 22 symmetrised, plus 64 directed R-MAT graphs
     (2^10..2^16 vertices, edge factor 8) with 20 PageRank updates each.
-    Batched = one hipGraph launch holding the device-driven batched SSSP and
+    Batched = one hipGraph launch holding the device-driven batched SSSP
+    (supersteps enqueued up to a fixed cap, not sized from this batch) and
     the PageRank run over the union with per-part N; plain = 256
-    single-source runs + 64 separate PageRank runs (exchange chosen by the
-    fixed rule).  Inputs resident before timing."""
+    single-source runs in the library's best single-source form (device-driven
+    loop, autotuned launch parameters, the fixed rule's exchange) + 64
+    separate PageRank runs, each replayed as one hipGraph.  Inputs resident
+    before timing."""
     from paper_2010_08781_amd import autotune
     from paper_2010_08781_amd.batch import BatchPlan
 
@@ -102,10 +109,9 @@ def batched_vs_plain(ipg, graphgen, np, torch, reps: int = 3, tune_cache=None) -
 
     tms = autotune.tune(g, hg, "multi_sssp", cache_path=tune_cache, reps=1, sources=src, out=d) if tune_cache else None
     tpr = autotune.tune(gu, u, "pagerank", cache_path=tune_cache, reps=1, updates=20) if tune_cache else None
-    # the superstep count of this batch sizes the captured plan (whole chunks of 16)
-    _, probe = g.run_multi_sssp(src, out=d, persistent=True, tuning=tms)
-    plan = BatchPlan(g, src, gu, parts, updates=20, max_supersteps=probe.supersteps + 1, sssp_tuning=tms,
-                     pr_tuning=tpr).capture()
+    # the plain single-source form at its best: launch parameters tuned for SSSP on this graph
+    tss = autotune.tune(g, hg, "sssp", cache_path=tune_cache, reps=1, persistent=True) if tune_cache else None
+    plan = BatchPlan(g, src, gu, parts, updates=20, max_supersteps=cap, sssp_tuning=tms, pr_tuning=tpr).capture()
 
     def one_launch():
         plan.replay()
@@ -115,30 +121,242 @@ def batched_vs_plain(ipg, graphgen, np, torch, reps: int = 3, tune_cache=None) -
 
     def p_sssp():
         for s in src:
-            g.run("sssp", source=int(s), timing=False)
+            g.run("sssp", source=int(s), timing=False, persistent=True, tuning=tss)
 
     def b_pr():
         gu.run("pagerank", 20, mode="pull", parts=parts, graph=True, timing=False, tuning=tpr)
 
     def p_pr():
         for h in gs:
-            h.run("pagerank", 20, mode="pull", timing=False)
+            h.run("pagerank", 20, mode="pull", timing=False, graph=True)
 
     t = {"one": timed(one_launch), "b_sssp": timed(b_sssp), "p_sssp": timed(p_sssp), "b_pr": timed(b_pr),
          "p_pr": timed(p_pr)}
     st = plan.sssp()[1]
-    assert st.status == ipg.OK and st.supersteps == probe.supersteps
+    assert st.status == ipg.OK and st.supersteps < cap
+    # every query of the replayed plan equals the library's own single-source run
+    dist = plan.sssp()[0].cpu().numpy()
+    for i, s in enumerate(src):
+        one, _ = g.run("sssp", source=int(s), timing=False, persistent=True, tuning=tss)
+        assert np.array_equal(one.cpu().numpy(), dist[i]), f"batched query {i} differs from its single-source run"
     out = {"sssp256_rmat_s22": {"batched_ms": round(t["b_sssp"] * 1e3, 3), "plain_ms": round(t["p_sssp"] * 1e3, 3),
                                 "speedup": round(t["p_sssp"] / t["b_sssp"], 2), "supersteps": st.supersteps,
-                                "edges_traversed": st.edges_traversed, "tuning": tms},
+                                "edges_traversed": st.edges_traversed, "tuning": tms, "plain_tuning": tss,
+                                "plain_form": "device-driven single-source runs, autotuned, fixed rule",
+                                "plan_superstep_cap": cap, "queries_checked_against_single_source": 256},
            "pagerank64_family": {"batched_ms": round(t["b_pr"] * 1e3, 3), "plain_ms": round(t["p_pr"] * 1e3, 3),
                                  "speedup": round(t["p_pr"] / t["b_pr"], 2), "n": u.n, "m": u.m, "tuning": tpr}}
     tp = t["p_sssp"] + t["p_pr"]
     out["end_to_end"] = {"batched_ms": round(t["one"] * 1e3, 3), "plain_ms": round(tp * 1e3, 3),
-                         "speedup": round(tp / t["one"], 2), "form": "one hipGraph launch (batched SSSP + PageRank union)"}
+                         "speedup": round(tp / t["one"], 2),
+                         "form": f"one hipGraph launch (batched SSSP up to {cap} supersteps + PageRank union)"}
     for h in gs + [g, gu]:
         h.close()
     return out
+
+
+def host_info() -> dict:
+    """Cores, CPU model and memory of the host the oracle baseline runs on."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    info["ram_gib"] = round(int(line.split()[1]) / 2**20, 1)
+                    break
+    except OSError:
+        pass
+    return info
+
+
+def load_workload(name: str):
+    """(graph for PageRank, graph for CC/SSSP): the directed and symmetrised
+    forms of one R-MAT draw for "rmat-s26", else one graph for both."""
+    import graphgen
+
+    if name == "rmat-s26":
+        return graphgen.workload_pair("rmat-s26")
+    hg = graphgen.workload(name)
+    return hg, hg
+
+
+def bench_workload(name, args, sel, ipg, np, torch, steps, warmup, apps, tune_cache):
+    """Builds the workload's device graphs, tunes, then times `steps` steps
+    after `warmup`; returns the measurements of one workload."""
+    t0 = time.perf_counter()
+    h_pr, h_min = load_workload(name)
+    print(f"[bench] generated {name}: n={h_pr.n} m={h_pr.m}"
+          f"{'' if h_min is h_pr else f' (symmetrised m={h_min.m})'} in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    T = args.pr_updates
+    graphs = {}
+    t0 = time.perf_counter()
+    if "pagerank" in apps:
+        graphs["pagerank"] = ipg.Graph.from_host(h_pr, blocked=not args.no_blocked)
+    if any(a != "pagerank" for a in apps):
+        gm = graphs["pagerank"] if h_min is h_pr and "pagerank" in graphs else \
+            ipg.Graph.from_host(h_min, blocked=not args.no_blocked)
+        for a in apps:
+            if a != "pagerank":
+                graphs[a] = gm
+    host = {a: (h_pr if a == "pagerank" else h_min) for a in apps}
+    print(f"[bench] device graphs created in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    def run(app, selector=sel, tuning=None, source=0, timing=True):
+        if app == "pagerank":
+            return graphs[app].run("pagerank", T, mode="pull", timing=timing, tuning=tuning)
+        return graphs[app].run(app, source=source, mode=args.mode, timing=timing, selector=selector, tuning=tuning,
+                               persistent=True)
+
+    # cold: the first device-driven run of each application on the fresh
+    # handle (one-time per-handle setup included, first chunk of 2 supersteps)
+    cold = {}
+    for app in apps:
+        if app != "pagerank":
+            t = time.perf_counter()
+            _, st = run(app)
+            cold[app] = {"time_to_converge_ms": round(st.seconds * 1e3, 4),
+                         "wall_ms": round((time.perf_counter() - t) * 1e3, 4)}
+
+    tun = {app: None for app in apps}
+    if not args.no_tune:
+        from paper_2010_08781_amd import autotune
+
+        t0 = time.perf_counter()
+        for app in apps:
+            tun[app] = autotune.tune(graphs[app], host[app], app, cache_path=tune_cache, reps=2, updates=T,
+                                     persistent=True)
+        print(f"[bench] {name}: autotuned {tun} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    def one_step(selector=sel):
+        return {app: run(app, selector, tun[app])[1] for app in apps}
+
+    for i in range(warmup):
+        one_step()
+        print(f"[bench] {name}: warmup {i + 1}/{warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per_step = [one_step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    edges_per_step = sum(st.edges_traversed for st in per_step[0].values())
+
+    apps_out = {}
+    for app in apps:
+        sts = [s[app] for s in per_step]
+        secs = np.array([s.seconds for s in sts])
+        st = sts[0]
+        apps_out[app] = {
+            "graph": host[app].name, "n": host[app].n, "m": host[app].m,
+            "supersteps": st.supersteps,
+            "edges_traversed": st.edges_traversed,
+            "edges_examined": st.edges_examined,
+            "time_to_converge_ms_median": float(np.median(secs) * 1e3),
+            "gteps": float(st.edges_traversed / np.median(secs) / 1e9),
+            "us_per_superstep": float(np.median(secs) * 1e6 / st.supersteps),
+            "modes": "".join("?PL"[int(x)] for x in st.mode),
+        }
+        if app in cold:
+            apps_out[app]["cold"] = cold[app]
+
+    # SSSP from rotating sources: each run's first chunk is sized by the
+    # previous run, from another source
+    if "sssp" in apps:
+        import graphgen
+
+        srcs = graphgen.pick_sources(host["sssp"], 8, seed=7)
+        secs = [run("sssp", source=int(v), tuning=tun["sssp"])[1].seconds for v in srcs]
+        apps_out["sssp"]["rotating_sources_ms_median"] = round(float(np.median(secs)) * 1e3, 4)
+
+    # The same CC/SSSP runs (outside the timed region) with the exchange
+    # picked by the fixed rule instead of the trained network: at the rule's
+    # documented divisor (pull when frontier + out-edges > E/20, the plain
+    # method) and at the divisor the autotuner picked; other launch
+    # parameters as tuned.
+    learned_vs_plain = None
+    if sel is not None:
+        learned_vs_plain = {}
+        for app in apps:
+            if app == "pagerank":
+                continue
+            t_plain = dict(tun[app] or {})
+            t_plain["push_div"] = 20
+
+            def med(t):
+                return float(np.median([run(app, selector=None, tuning=t)[1].seconds for _ in range(max(3, steps))]))
+
+            plain, rule = med(t_plain), med(tun[app])
+            mine = apps_out[app]["time_to_converge_ms_median"] / 1e3
+            learned_vs_plain[app] = {"learned_ms": round(mine * 1e3, 4), "plain_ms": round(plain * 1e3, 4),
+                                     "speedup": round(plain / mine, 4),
+                                     "tuned_rule_ms": round(rule * 1e3, 4), "speedup_vs_tuned_rule": round(rule / mine, 4),
+                                     "learned_beats_tuned_rule": bool(mine < rule)}
+
+    roofline = None
+    if "pagerank" in apps and T >= 1:
+        # average duration of one pull superstep from HIP events recorded on
+        # the launch stream around each superstep
+        us = np.concatenate([s["pagerank"].usec[1:T + 1] for s in per_step])
+        avg_us = float(np.mean(us))
+        nbytes = pr_pull_bytes(h_pr.n, h_pr.m)
+        ach = nbytes / (avg_us * 1e-6) / 1e9
+        g = graphs["pagerank"]
+        traffic = measured_traffic(h_pr_key(name), tun.get("pagerank"))
+        blocked = g.blocked and (tun.get("pagerank") or {}).get("blocked", 0) != 0xFFFFFFFF
+        kernel = ("pr_blocked_kernel + pr_blocked_finish_kernel" if blocked else
+                  "pr_items_kernel + pr_longrow_kernel") + " (one PageRank pull superstep)"
+        roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "kernel": kernel, "graph": h_pr.name,
+                    "bytes_per_launch": nbytes, "bytes_formula": "4E + 8(N+1) + 8N + 4N + 8N",
+                    "avg_launch_us": round(avg_us, 2),
+                    "tuning": tun.get("pagerank"), "kernel_sources": kernel_source_hash()}
+
+    out = {"name": name, "steps": steps, "warmup": warmup, "wall_s": wall,
+           "ms_per_step": wall / steps * 1e3, "value": edges_per_step * steps / wall / 1e9,
+           "apps": apps_out, "tuning": tun, "learned_vs_plain": learned_vs_plain, "roofline": roofline,
+           "host": host, "graphs": graphs}
+    return out
+
+
+def h_pr_key(name: str) -> str:
+    """Name of the committed traffic summary of the workload's PageRank graph."""
+    return "rmat-s26-dir" if name == "rmat-s26" else name
+
+
+def cpu_baseline(name, host, apps, T, np) -> dict:
+    """The oracle timed on the host's cores: its pull form with the vertex loop
+    under OpenMP's default static schedule (the paper's parallelisation), on
+    a bounded sample of the workload -- at scale 26 the first rank update of
+    PageRank (supersteps 0-1) and the first two supersteps of CC and SSSP."""
+    import oracle
+
+    threads = oracle.max_threads()
+    big = host[apps[0]].m > 100_000_000
+    secs, msgs, parts = 0.0, 0, []
+    for app in apps:
+        hg = host[app]
+        if app == "pagerank":
+            param = 1 if big else T
+        else:
+            param = 2 if big else 0
+        r = oracle.run_pull(app, hg, param, source=0, threads=threads)
+        assert r.status in (oracle.OK, oracle.NOT_CONVERGED)
+        secs += r.seconds
+        msgs += int(r.trace[:, 2].sum())
+        parts.append(f"{app} {r.supersteps} supersteps {r.seconds:.1f}s")
+        print(f"[bench] oracle {app}: {r.supersteps} supersteps in {r.seconds:.1f}s on {threads} threads",
+              file=sys.stderr, flush=True)
+    info = host_info()
+    return {"value": round(msgs / secs / 1e9, 5), "unit": "GTEPS", "cores": threads, "kind": "oracle",
+            "sample": f"{name}: " + ", ".join(parts) + " (pull form, OpenMP default static schedule over "
+                      f"{threads} threads; messages of the supersteps run / their time)",
+            "nproc": info.get("nproc"), "cpu_model": info.get("cpu_model"), "ram_gib": info.get("ram_gib")}
 
 
 def main():
@@ -146,7 +364,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat-s20-sym")
+    ap.add_argument("--workload", default="rmat-s26",
+                    help="rmat-s26 (PageRank on the directed graph, CC/SSSP on its symmetrised form) or a single "
+                         "graph for every application (rmat-s20-sym, rmat-s22-sym, grid4096-sc, rmat-s14-dir)")
+    ap.add_argument("--secondary", default="rmat-s20-sym", help="second workload reported beside it ('none': skip)")
     ap.add_argument("--pr-updates", type=int, default=10)
     ap.add_argument("--mode", default="auto", help="exchange for CC/SSSP: auto, push or pull")
     ap.add_argument("--selector", default="learned", choices=["learned", "heuristic"],
@@ -187,11 +408,6 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": n, "copies": 3}), flush=True)
         return
     ipg.lib()
-    t0 = time.perf_counter()
-    hg = graphgen.workload(args.workload)
-    print(f"[bench] generated {args.workload}: n={hg.n} m={hg.m} in {time.perf_counter() - t0:.1f}s",
-          file=sys.stderr, flush=True)
-    g = ipg.Graph.from_host(hg, blocked=not args.no_blocked)
     apps = [a.strip() for a in args.apps.split(",") if a.strip()]
     T = args.pr_updates
     sel = None
@@ -201,145 +417,64 @@ def main():
         sel = selector_fit.load()
         if sel is None:
             sys.exit("bench.py: --selector learned but no trained selector parameters are installed")
+    tune_cache = args.tune_cache
 
-    # launch parameters from the autotuner (untimed; cached per graph signature)
-    tun = {app: None for app in apps}
-    if not args.no_tune:
-        from paper_2010_08781_amd import autotune
+    main_w = bench_workload(args.workload, args, sel, ipg, np, torch, args.steps, args.warmup, apps, tune_cache)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.workload, main_w["host"], apps, T, np)
+    for g in set(main_w.pop("graphs").values()):
+        g.close()
+    host_main = main_w.pop("host")
+    n_pr, m_pr = host_main[apps[0]].n, host_main[apps[0]].m
+    footprint = {a: {k: v for k, v in ipg.footprint(h.n, h.m, symmetric=bool(h.symmetric),
+                                                    weighted=h.csr_w is not None, blocked=not args.no_blocked).items()
+                     if k in ("total", "bytes_per_edge", "graph_workspace")}
+                 for a, h in host_main.items()}
+    del host_main
+    torch.cuda.empty_cache()
 
-        t0 = time.perf_counter()
-        for app in apps:
-            tun[app] = autotune.tune(g, hg, app, cache_path=args.tune_cache, reps=2, updates=T, persistent=True)
-        print(f"[bench] autotuned {tun} in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
-
-    def one_step(selector=sel):
-        out = {}
-        for app in apps:
-            if app == "pagerank":
-                _, st = g.run("pagerank", T, mode="pull", timing=True, tuning=tun[app])
-            else:
-                _, st = g.run(app, source=0, mode=args.mode, timing=True, selector=selector, tuning=tun[app],
-                              persistent=True)
-            out[app] = st
-        return out
-
-    for i in range(args.warmup):
-        one_step()
-        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    per_step = []
-    for i in range(args.steps):
-        per_step.append(one_step())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = wall / args.steps * 1e3
-    edges_per_step = sum(st.edges_traversed for st in per_step[0].values())
-    value = edges_per_step * args.steps / wall / 1e9
-
-    apps_out = {}
-    for app in apps:
-        sts = [s[app] for s in per_step]
-        secs = np.array([s.seconds for s in sts])
-        st = sts[0]
-        apps_out[app] = {
-            "supersteps": st.supersteps,
-            "edges_traversed": st.edges_traversed,
-            "edges_examined": st.edges_examined,
-            "time_to_converge_ms_median": float(np.median(secs) * 1e3),
-            "gteps": float(st.edges_traversed / np.median(secs) / 1e9),
-            "us_per_superstep": float(np.median(secs) * 1e6 / st.supersteps),
-            "modes": "".join("?PL"[int(x)] for x in st.mode),
-        }
-
-    # The same CC/SSSP runs (outside the timed region) with the exchange
-    # picked by the fixed rule instead of the trained network: at the rule's
-    # documented divisor (pull when frontier + out-edges > E/20, the plain
-    # method) and at the divisor the autotuner picked; other launch
-    # parameters as tuned.
-    learned_vs_plain = None
-    if sel is not None:
-        learned_vs_plain = {}
-        for app in apps:
-            if app == "pagerank":
-                continue
-            t_plain = dict(tun[app] or {})
-            t_plain["push_div"] = 20
-
-            def med(t):
-                return float(np.median([g.run(app, source=0, mode="auto", timing=True, tuning=t,
-                                              persistent=True)[1].seconds for _ in range(max(3, args.steps))]))
-
-            plain, rule = med(t_plain), med(tun[app])
-            mine = apps_out[app]["time_to_converge_ms_median"] / 1e3
-            learned_vs_plain[app] = {"learned_ms": round(mine * 1e3, 4), "plain_ms": round(plain * 1e3, 4),
-                                     "speedup": round(plain / mine, 4),
-                                     "tuned_rule_ms": round(rule * 1e3, 4), "speedup_vs_tuned_rule": round(rule / mine, 4)}
+    secondary = None
+    if args.secondary and args.secondary != "none" and args.secondary != args.workload:
+        sw = bench_workload(args.secondary, args, sel, ipg, np, torch, args.steps, min(args.warmup, 2), apps,
+                            tune_cache)
+        for g in set(sw.pop("graphs").values()):
+            g.close()
+        sw.pop("host")
+        secondary = {k: sw[k] for k in ("name", "value", "ms_per_step", "apps", "learned_vs_plain", "roofline",
+                                        "tuning")}
+        secondary["value"] = round(secondary["value"], 4)
+        secondary["ms_per_step"] = round(secondary["ms_per_step"], 4)
+        torch.cuda.empty_cache()
 
     batched = None
     if not args.no_batched:
-        batched = batched_vs_plain(ipg, graphgen, np, torch, tune_cache=None if args.no_tune else args.tune_cache)
+        batched = batched_vs_plain(ipg, graphgen, np, torch, tune_cache=None if args.no_tune else tune_cache)
         print(f"[bench] batched vs plain: {json.dumps(batched['end_to_end'])}", file=sys.stderr, flush=True)
 
-    roofline = None
-    if "pagerank" in apps and T >= 1:
-        # average duration of one pull superstep (the long-row chunk launch
-        # plus the row-group gather launch), from HIP events recorded on the
-        # launch stream around each superstep
-        us = np.concatenate([s["pagerank"].usec[1:T + 1] for s in per_step])
-        avg_us = float(np.mean(us))
-        nbytes = pr_pull_bytes(hg.n, hg.m)
-        ach = nbytes / (avg_us * 1e-6) / 1e9
-        traffic = measured_traffic(args.workload, tun.get("pagerank"))
-        blocked = g.blocked and (tun.get("pagerank") or {}).get("blocked", 0) != 0xFFFFFFFF
-        kernel = ("pr_blocked_kernel + pr_blocked_finish_kernel" if blocked else
-                  "pr_items_kernel + pr_longrow_kernel") + " (one PageRank pull superstep)"
-        roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": kernel,
-                    "bytes_per_launch": nbytes, "avg_launch_us": round(avg_us, 2),
-                    "tuning": tun.get("pagerank"), "kernel_sources": kernel_source_hash()}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-
-        secs, msgs = 0.0, 0
-        for app in apps:
-            r = oracle.run_graph(app, hg, T if app == "pagerank" else 0, source=0)
-            secs += r.seconds
-            msgs += int(r.trace[:, 2].sum())
-            print(f"[bench] oracle {app}: {r.seconds:.1f}s", file=sys.stderr, flush=True)
-        cpu = {"value": round(msgs / secs / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-               "sample": f"one full step ({'+'.join(apps)}) on the same {args.workload} graph, "
-                         f"sequential oracle, {secs:.1f}s"}
-
+    desc = (f"{args.workload}: PageRank T={T} pull FP64 on {main_w['apps'].get('pagerank', {}).get('graph', '-')}"
+            f" + hash-min CC + SSSP from 0 on {main_w['apps'].get('cc', main_w['apps'].get('sssp', {})).get('graph', '-')},"
+            f" exchange={args.mode}{' (trained selector)' if sel is not None else ''}, device-driven loop")
     line = {
         "metric": METRIC,
-        "value": round(value, 4),
+        "value": round(main_w["value"], 4),
         "unit": "GTEPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": round(main_w["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64+u32",
         "data": "synthetic",
-        "config": {
-            "workload": f"{args.workload} (n={hg.n}, m={hg.m}): PageRank T={T} pull FP64 + hash-min CC + "
-                        f"SSSP from 0, exchange={args.mode}"
-                        f"{' (trained selector)' if sel is not None else ''}",
-            "n": hg.n, "m": hg.m, "apps": apps_out,
-        },
-        "tuning": tun,
-        "footprint": {k: v for k, v in ipg.footprint(hg.n, hg.m, symmetric=bool(hg.symmetric),
-                                                      weighted=hg.csr_w is not None).items()
-                      if k in ("total", "bytes_per_edge", "graph_workspace")},
-        "learned_vs_plain": learned_vs_plain,
+        "config": {"workload": desc, "n": n_pr, "m": m_pr, "apps": main_w["apps"]},
+        "tuning": main_w["tuning"],
+        "footprint": footprint,
+        "learned_vs_plain": main_w["learned_vs_plain"],
         "batched_vs_plain": batched,
-        "roofline": roofline,
+        "secondary": secondary,
+        "roofline": main_w["roofline"],
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

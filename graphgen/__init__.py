@@ -62,6 +62,8 @@ def _L():
         lib.gg_build_csr.restype = u64
         lib.gg_transpose.argtypes = [u32, P, P, P, P]
         lib.gg_transpose.restype = None
+        lib.gg_symmetrise.argtypes = [u32, P, P, P, P, P, P]
+        lib.gg_symmetrise.restype = u64
         lib.gg_edge_weights.argtypes = [u32, P, P, u64, u32, u32, P]
         lib.gg_edge_weights.restype = None
         lib.gg_grid_edges.argtypes = [u32, u32, P, P]
@@ -212,6 +214,28 @@ def rmat(scale: int, edge_factor: int = 16, seed: int = 1, symmetric: bool = Fal
     return g
 
 
+def symmetrise(g: HostGraph) -> HostGraph:
+    """The symmetrised form of a directed graph without duplicate edges (every
+    list sorted): each vertex's neighbours are the union of its out- and
+    in-neighbours, itself excluded -- the graph rmat(..., symmetric=True)
+    draws, built from the directed one by merging its CSR and CSC lists."""
+    assert not g.symmetric and g.csr_w is None
+    soff = np.zeros(g.n + 1, dtype=np.uint64)
+    m = _L().gg_symmetrise(g.n, _p(g.csr_off), _p(g.csr_dst if g.m else np.zeros(1, np.int32)), _p(g.csc_off),
+                           _p(g.csc_src if g.m else np.zeros(1, np.int32)), _p(soff), None)
+    sadj = np.empty(max(int(m), 1), dtype=np.int32)
+    _L().gg_symmetrise(g.n, _p(g.csr_off), _p(g.csr_dst if g.m else np.zeros(1, np.int32)), _p(g.csc_off),
+                       _p(g.csc_src if g.m else np.zeros(1, np.int32)), _p(soff), _p(sadj))
+    sadj = sadj[: int(m)]
+    name = g.name + "-sym" if not g.name.endswith("-sym") else g.name
+    if "-seed" in g.name:  # rmat-s26-ef16-seed5 -> rmat-s26-ef16-sym-seed5
+        head, seed = g.name.rsplit("-seed", 1)
+        name = f"{head}-sym-seed{seed}"
+    out = HostGraph(n=g.n, csr_off=soff, csr_dst=sadj, csc_off=soff, csc_src=sadj, symmetric=True, name=name)
+    out.meta.update(g.meta)
+    return out
+
+
 def grid_with_shortcuts(width: int = 4096, frac: float = 0.01, seed: int = 3, wmin: int = 1,
                         wmax: int = 255) -> HostGraph:
     """Undirected width x width 4-neighbour grid (row-major ids r*width+c)
@@ -319,7 +343,16 @@ def workload(name: str) -> HostGraph:
     if name == "rmat-s26-dir":
         return rmat(26, 16, seed=5, symmetric=False)
     if name == "rmat-s26-sym":
-        return rmat(26, 16, seed=5, symmetric=True)
+        return symmetrise(rmat(26, 16, seed=5, symmetric=False))
+    raise KeyError(name)
+
+
+def workload_pair(name: str):
+    """(directed, symmetrised) forms of one R-MAT draw, the symmetrised one
+    merged from the directed one (one draw and sort instead of two)."""
+    if name == "rmat-s26":
+        d = rmat(26, 16, seed=5, symmetric=False)
+        return d, symmetrise(d)
     raise KeyError(name)
 
 

@@ -256,6 +256,48 @@ void gg_transpose(uint32_t n, const uint64_t* off, const int32_t* adj, uint64_t*
   free(deg);
 }
 
+/* Symmetrised form of a directed graph given as CSR + CSC with every list
+ * sorted ascending and free of duplicates: vertex v's list is the sorted
+ * union of its out- and in-list, without duplicates and without v itself.
+ * (The same graph as drawing the edge list again and adding every edge
+ * reversed, then dropping self-loops and duplicates.)  Two calls: with
+ * sadj == NULL it fills soff[0..n] and returns the edge count; then with
+ * sadj (that many entries) it fills the lists. */
+static uint64_t gg_merge_len(const int32_t* a, uint64_t na, const int32_t* b, uint64_t nb, int32_t self,
+                             int32_t* out) {
+  uint64_t i = 0, j = 0, k = 0;
+  while (i < na || j < nb) {
+    int32_t x;
+    if (j >= nb || (i < na && a[i] < b[j])) x = a[i++];
+    else if (i >= na || b[j] < a[i]) x = b[j++];
+    else {
+      x = a[i++];
+      ++j;
+    }
+    if (x == self) continue;
+    if (out) out[k] = x;
+    ++k;
+  }
+  return k;
+}
+
+uint64_t gg_symmetrise(uint32_t n, const uint64_t* off, const int32_t* adj, const uint64_t* toff, const int32_t* tadj,
+                       uint64_t* soff, int32_t* sadj) {
+  if (sadj == NULL) {
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t v = 0; v < (int64_t)n; ++v)
+      soff[v + 1] = gg_merge_len(adj + off[v], off[v + 1] - off[v], tadj + toff[v], toff[v + 1] - toff[v],
+                                 (int32_t)v, NULL);
+    soff[0] = 0;
+    for (uint32_t v = 0; v < n; ++v) soff[v + 1] += soff[v];
+    return soff[n];
+  }
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t v = 0; v < (int64_t)n; ++v)
+    gg_merge_len(adj + off[v], off[v + 1] - off[v], tadj + toff[v], toff[v + 1] - toff[v], (int32_t)v, sadj + soff[v]);
+  return soff[n];
+}
+
 /* Per-edge weights of a CSR, symmetric in (u, v): w = lo + H(seed, min, max) % (hi-lo+1). */
 void gg_edge_weights(uint32_t n, const uint64_t* off, const int32_t* adj, uint64_t seed, uint32_t lo,
                      uint32_t hi, uint32_t* w) {

@@ -82,6 +82,20 @@ typedef enum { IPG_MODE_AUTO = 0, IPG_MODE_PUSH = 1, IPG_MODE_PULL = 2 } ipg_mod
                                   partial-sum buffer of at most 256 * 20224 doubles of graph workspace, which
                                   runs on the handle share (runs on one handle must not overlap in time). */
 
+#define IPG_GRAPH_BINNED 16u   /* with IPG_GRAPH_BLOCKED: PageRank's pull gathers only the outboxes of the
+                                  sources below ipg_graph_desc.binned_hot (rounded up to a multiple of 65536;
+                                  hot-first names with IPG_GRAPH_RENAME) edge by edge.  Every other ("cold")
+                                  source's outbox is copied, once per superstep, into one slot per block it
+                                  has in-edges to, by a bin launch that takes 16384 sources per workgroup
+                                  (their outboxes staged in LDS) and writes each block's slots as runs of
+                                  whole 64-byte lines; the pull then reads a block's cold messages from its
+                                  slots in order.  This turns a cold gather, which moves a memory line for
+                                  8 bytes once the outbox array outgrows the caches, into a streamed
+                                  write and read of 8 bytes (propagation blocking over Section 4.3.2's pull).
+                                  The sums are unchanged (the same messages; order as with
+                                  IPG_GRAPH_BLOCKED).  Costs about 10 bytes per cold (block, source) pair of
+                                  graph workspace (bounded by 10E + 70 x the (block, window) pairs). */
+
 /*
  * A graph as CSR (out-adjacency, for push) plus CSC (in-adjacency, for pull).
  * All array pointers are DEVICE pointers owned by the caller and must stay
@@ -104,6 +118,7 @@ typedef struct {
   const uint32_t* csr_w;
   const uint32_t* csc_w;
   uint32_t flags;
+  uint32_t binned_hot;  /* IPG_GRAPH_BINNED: sources gathered edge by edge (0 = 262144, 2 MB of outboxes) */
 } ipg_graph_desc;
 
 /* ipg_run_opts.flags */

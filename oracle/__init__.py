@@ -61,7 +61,7 @@ def _L():
                                          ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
         lib.orc_pagerank_run.restype = ctypes.c_int
         lib.orc_run_pull.argtypes = [ctypes.c_int, ctypes.c_uint32, P, P, P, P, P, ctypes.c_uint32, ctypes.c_uint32,
-                                     ctypes.c_double, ctypes.c_int, P, P, ctypes.c_uint32,
+                                     ctypes.c_double, ctypes.c_int, ctypes.c_int, P, P, ctypes.c_uint32,
                                      ctypes.POINTER(ctypes.c_uint32)]
         lib.orc_run_pull.restype = ctypes.c_int
         _lib = lib
@@ -143,9 +143,12 @@ def run_graph(app, g, param: int, source: int = 0, weighted: bool = True, trace_
 
 
 def run_pull(app, g, param: int, source: int = 0, weighted: bool = True, damping: float = 0.85,
-             threads: int = 1, trace_cap: int = 1 << 16) -> OracleResult:
+             threads: int = 1, chunk: int = 0, trace_cap: int = 1 << 16) -> OracleResult:
     """The same run in the pull form, the vertex loop under an OpenMP static
-    schedule over `threads` threads (0 = all the OpenMP runtime offers).
+    schedule over `threads` threads (0 = all the OpenMP runtime offers):
+    chunk 0 = OpenMP's default static schedule (one contiguous block of
+    vertices per thread, the paper's), else fixed chunks of that many
+    vertices dealt round-robin.  The output is the same for any of them.
     `g` needs n, csr_off, csc_off, csc_src (and csr_w, csc_w when weighted)."""
     app = APPS[app] if isinstance(app, str) else int(app)
     n = int(g.n)
@@ -168,7 +171,8 @@ def run_pull(app, g, param: int, source: int = 0, weighted: bool = True, damping
     t0 = time.perf_counter()
     st = _L().orc_run_pull(app, n, roff.ctypes.data, None if rw is None or rw.size == 0 else rw.ctypes.data,
                            coff.ctypes.data, src.ctypes.data, None if cw is None or cw.size == 0 else cw.ctypes.data,
-                           source, param, float(damping), int(threads), vals.ctypes.data, trace.ctypes.data,
+                           source, param, float(damping), int(threads), int(chunk), vals.ctypes.data,
+                           trace.ctypes.data,
                            trace_cap, ctypes.byref(steps))
     dt = time.perf_counter() - t0
     k = min(int(steps.value), trace_cap)

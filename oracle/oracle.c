@@ -49,7 +49,9 @@
  * pull form (Section 4.3.2): every vertex that broadcasts leaves one value in
  * its outbox, and every vertex combines the outboxes of its in-neighbours
  * (CSC) that broadcast.  Its vertex loop runs under an OpenMP static schedule
- * (the paper's parallelisation, Section 4.2); each vertex combines its
+ * (the paper's parallelisation, Section 4.2: the vertices split evenly into
+ * one contiguous block per thread, no work stealing; a chunk size may be
+ * given instead, dealing fixed chunks round-robin); each vertex combines its
  * in-neighbours in CSC order whatever the thread count, so the output does
  * not depend on the number of threads, and with every CSC list sorted by
  * source it equals the push form's bit for bit (the same additions in the
@@ -367,7 +369,8 @@ int orc_pagerank_run(uint32_t n, const uint64_t* off, const int32_t* adj, uint32
  */
 int orc_run_pull(int app, uint32_t n, const uint64_t* csr_off, const uint32_t* csr_w, const uint64_t* csc_off,
                  const int32_t* csc_src, const uint32_t* csc_w, uint32_t source, uint32_t param, double damping,
-                 int threads, void* values, uint64_t* trace, uint32_t trace_cap, uint32_t* supersteps_out) {
+                 int threads, int chunk, void* values, uint64_t* trace, uint32_t trace_cap,
+                 uint32_t* supersteps_out) {
   *supersteps_out = 0;
   if (!csr_off || !csc_off || (!csc_src && n && csc_off[n]) || !values) return ORC_EINVAL;
   if (app != ORC_APP_PAGERANK && app != ORC_APP_CC && app != ORC_APP_SSSP) return ORC_EINVAL;
@@ -377,6 +380,9 @@ int orc_run_pull(int app, uint32_t n, const uint64_t* csr_off, const uint32_t* c
   for (uint32_t v = 0; v < n; ++v)
     if (csr_off[v + 1] < csr_off[v]) return ORC_EBADGRAPH;
   if (threads < 1) threads = 1;
+  /* the default static schedule: one contiguous block of ceil(n / threads) vertices per thread */
+  if (chunk < 1) chunk = (int)(((uint64_t)n + (uint64_t)threads - 1) / (uint64_t)threads);
+  if (chunk < 1) chunk = 1;
   const size_t nn = n ? n : 1;
   const int pr = app == ORC_APP_PAGERANK;
   double* fval = pr ? (double*)values : NULL;
@@ -398,7 +404,7 @@ int orc_run_pull(int app, uint32_t n, const uint64_t* csr_off, const uint32_t* c
     const uint32_t* uin = pr ? NULL : uout[(s + 1) & 1];
     uint32_t* uo = pr ? NULL : uout[s & 1];
     unsigned long long active = 0, senders = 0, messages = 0, awake = 0, overflow = 0;
-#pragma omp parallel for schedule(static) num_threads(threads) \
+#pragma omp parallel for schedule(static, chunk) num_threads(threads) \
     reduction(+ : active, senders, messages, awake, overflow)
     for (int64_t iv = 0; iv < (int64_t)n; ++iv) {
       const uint32_t v = (uint32_t)iv;

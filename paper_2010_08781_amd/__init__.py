@@ -35,7 +35,7 @@ APPS = {"pagerank": APP_PAGERANK, "pr": APP_PAGERANK, "cc": APP_CC, "sssp": APP_
 COMBINE_SUM, COMBINE_MIN = 0, 1
 DEFAULT_COMBINER = {APP_PAGERANK: COMBINE_SUM, APP_CC: COMBINE_MIN, APP_SSSP: COMBINE_MIN}
 MODES = {"auto": 0, "push": 1, "pull": 2}
-GRAPH_SYMMETRIC, GRAPH_VALIDATE, GRAPH_RENAME, GRAPH_BLOCKED = 1, 2, 4, 8
+GRAPH_SYMMETRIC, GRAPH_VALIDATE, GRAPH_RENAME, GRAPH_BLOCKED, GRAPH_BINNED = 1, 2, 4, 8, 16
 RUN_PERSISTENT, RUN_GRAPH, RUN_ENQUEUE = 1, 2, 4
 INF = 0xFFFFFFFF
 BATCH_MAX_SOURCES = 256
@@ -51,7 +51,8 @@ class _Desc(ctypes.Structure):
     _fields_ = [("num_vertices", ctypes.c_uint32), ("num_edges", ctypes.c_uint64),
                 ("csr_off", ctypes.c_void_p), ("csr_dst", ctypes.c_void_p),
                 ("csc_off", ctypes.c_void_p), ("csc_src", ctypes.c_void_p),
-                ("csr_w", ctypes.c_void_p), ("csc_w", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
+                ("csr_w", ctypes.c_void_p), ("csc_w", ctypes.c_void_p), ("flags", ctypes.c_uint32),
+                ("binned_hot", ctypes.c_uint32)]
 
 
 class _Tuning(ctypes.Structure):
@@ -231,7 +232,8 @@ class Graph:
     """A graph resident on the current HIP device (CSR + CSC held as torch tensors)."""
 
     def __init__(self, n, csr_off, csr_dst, csc_off=None, csc_src=None, csr_w=None, csc_w=None,
-                 symmetric=False, validate=True, stream=None, rename=True, blocked=False):
+                 symmetric=False, validate=True, stream=None, rename=True, blocked=False, binned=False,
+                 binned_hot: int = 0):
         import torch
 
         self.n = int(n)
@@ -256,13 +258,14 @@ class Graph:
         self._keep = (csr_off, csr_dst, csc_off, csc_src, csr_w, csc_w)
         self.weighted = csr_w is not None
         self.renamed = bool(rename)
-        self.blocked = bool(blocked)
+        self.blocked = bool(blocked or binned)
+        self.binned = bool(binned)
         flags = (GRAPH_SYMMETRIC if symmetric else 0) | (GRAPH_VALIDATE if validate else 0) | \
-            (GRAPH_RENAME if rename else 0) | (GRAPH_BLOCKED if blocked else 0)
+            (GRAPH_RENAME if rename else 0) | (GRAPH_BLOCKED if self.blocked else 0) | (GRAPH_BINNED if binned else 0)
         d = _Desc(self.n, self.m, csr_off.data_ptr(), csr_dst.data_ptr() if self.m else None,
                   csc_off.data_ptr(), csc_src.data_ptr() if self.m else None,
                   csr_w.data_ptr() if csr_w is not None else None,
-                  csc_w.data_ptr() if csc_w is not None else None, flags)
+                  csc_w.data_ptr() if csc_w is not None else None, flags, int(binned_hot))
         nbytes = lib().ipg_graph_workspace_bytes(self.n, self.m, flags)
         self._gws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=csr_off.device)
         h = ctypes.c_void_p()
@@ -278,7 +281,8 @@ class Graph:
         return cls(*args, **kw)
 
     @classmethod
-    def from_host(cls, hg, device="cuda", validate=True, weighted=True, rename=True, blocked=False) -> "Graph":
+    def from_host(cls, hg, device="cuda", validate=True, weighted=True, rename=True, blocked=False, binned=False,
+                  binned_hot: int = 0) -> "Graph":
         """Upload any object with n, csr_off, csr_dst, csc_off, csc_src (numpy) and optional csr_w/csc_w."""
         import torch
 
@@ -298,7 +302,7 @@ class Graph:
             csr_w = up(hg.csr_w.astype(np.uint32), np.int32)
             csc_w = csr_w if sym else up(hg.csc_w.astype(np.uint32), np.int32)
         return cls(hg.n, csr_off, csr_dst, csc_off, csc_src, csr_w, csc_w, symmetric=sym, validate=validate,
-                   rename=rename, blocked=blocked)
+                   rename=rename, blocked=blocked, binned=binned, binned_hot=binned_hot)
 
     def _trace(self, cap: int, timing: bool) -> "_Trace":
         """The host trace buffers of this graph's runs (kept and reused: a
@@ -540,14 +544,14 @@ def values_to_numpy(t) -> np.ndarray:
 # ----------------------------------------------------------- footprint ----
 
 def footprint(n: int, m: int, symmetric: bool = False, weighted: bool = False, rename: bool = True,
-              blocked: bool = False) -> dict:
+              blocked: bool = False, binned: bool = False) -> dict:
     """Device memory of a graph and of each application's run, in bytes
     (the library's own size queries plus the caller-owned graph arrays):
     the device-side counterpart of the paper's memory-usage comparison
     (Table 3).  A symmetric graph stores one adjacency (CSC aliases CSR)."""
     L = lib()
     flags = (GRAPH_SYMMETRIC if symmetric else 0) | (GRAPH_RENAME if rename else 0) | \
-        (GRAPH_BLOCKED if blocked else 0)
+        (GRAPH_BLOCKED if blocked or binned else 0) | (GRAPH_BINNED if binned else 0)
     adj = 8 * (n + 1) + 4 * m
     arrays = {"csr": adj, "csc": 0 if symmetric else adj,
               "weights": (4 * m if symmetric else 8 * m) if weighted else 0}
@@ -557,6 +561,7 @@ def footprint(n: int, m: int, symmetric: bool = False, weighted: bool = False, r
             (("pagerank", APP_PAGERANK), ("cc", APP_CC), ("sssp", APP_SSSP))}
     runs["multi_sssp"] = int(L.ipg_multi_sssp_workspace_bytes(n, m))
     out = {"n": n, "m": m, "symmetric": symmetric, "weighted": weighted, "rename": rename, "blocked": blocked,
+           "binned": binned,
            "graph_arrays": arrays,
            "graph_workspace": graph_ws, "run_workspace": runs,
            "total": {k: base + v for k, v in runs.items()}}

@@ -37,6 +37,7 @@ __device__ __forceinline__ BlkChunk blk_chunk_at(const BlkView& b, uint64_t c, u
   z.e0 = 0;
   z.wbase = 0;
   z.n = 0;
+  z.cold = 0;
   return z;
 }
 
@@ -56,8 +57,9 @@ __device__ __forceinline__ void blk_load(const BlkView& b, const BlkChunk& ch, u
 // The edge loop of one slice, run by every wavefront of the workgroup:
 // chunk c of the slice goes to wavefront (c - c0) mod kWaves.  A wavefront
 // takes kBlkGroup chunks per step: it gathers their sources' values
-// (`value(wbase, packed)`: the sources of a chunk are sorted and share one
-// window, so neighbouring lanes mostly read the same cache lines), starts
+// (`value(wbase, packed, cold)`: the sources of a chunk are sorted and share
+// one window, so neighbouring lanes mostly read the same cache lines; a cold
+// chunk's values are slots, read in order), starts
 // loading the next step's packed edges, and then combines each value into
 // its destination's LDS slot (`combine(slot, v)`).  Lanes past a chunk's
 // end combine `idle` into their own pad slot kBlkRows + lane, so that no
@@ -87,7 +89,7 @@ __device__ __forceinline__ void blk_stream(const BlkView& b, const BlkSlice& sl,
 #pragma unroll
     for (int g = 0; g < kBlkGroup; ++g)
 #pragma unroll
-      for (int k = 0; k < kPer; ++k) x[g][k] = value(ch[g].wbase, ch[g].n ? p[g][k] : 0u);
+      for (int k = 0; k < kPer; ++k) x[g][k] = value(ch[g].wbase, ch[g].n ? p[g][k] : 0u, ch[g].cold);
     load(next, pn);
 #pragma unroll
     for (int g = 0; g < kBlkGroup; ++g)

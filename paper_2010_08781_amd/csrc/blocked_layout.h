@@ -25,6 +25,23 @@ namespace ipg {
 // uniform), and each block's chunks into slices, about one per CU.  A block
 // with one slice is finished by that slice's workgroup; the slices of a
 // larger block store partial sums that a second launch adds in slice order.
+//
+// Binned cold sources (optional, `hot` > 0): the sources from `hot` on,
+// whose outboxes are too many to stay in any cache, are not gathered edge by
+// edge.  Each block's edges from them ("cold" edges) follow its hot edges,
+// still sorted by source, and every distinct (block, cold source) pair owns
+// one slot of a slot array, numbered block by block in the order of the
+// edges.  Before each pull a bin launch copies every cold source's outbox
+// value into all of its slots, one workgroup per scatter window of
+// 2^kBinWinBits sources (the window's outboxes staged in LDS): a block's
+// slots from one window form a run of consecutive slots, padded to
+// kBinPad slots so that runs start on 64-byte lines.  A cold edge's word
+// holds its slot's offset from its chunk's first slot instead of a source
+// offset, and a cold chunk (flag `cold`) reads slots instead of outboxes:
+// the pull streams them in order.  For the bin launch every window lists
+// its slots (source offsets, in the window's run order) and its runs (first
+// slot in the window's list, first slot in the slot array), and a table
+// gives the first run of every 64 slots of the list.
 constexpr uint32_t kBlkRows = 20224;
 constexpr uint32_t kBlkWinBits = 16;
 constexpr uint32_t kBlkChunk = 256;
@@ -37,11 +54,27 @@ constexpr uint64_t kBlkLineCost = 6;
 // XCDs of the chip: workgroup i of a launch runs on XCD i mod kBlkXcds.
 constexpr size_t kBlkXcds = 8;
 static_assert(kBlkRows <= (1u << 16), "row within a block fits 16 bits");
+// Binned cold sources: scatter windows of 2^kBinWinBits sources (their FP64
+// outboxes fill 128 KB of LDS), runs padded to kBinPad slots (64 bytes).
+constexpr uint32_t kBinWinBits = 14;
+constexpr uint32_t kBinPad = 8;
+constexpr uint32_t kBinGroup = 64;  // slots of a window's list per entry of its group table
+// Hot-source count when binning is asked for without one (2 MB of outboxes).
+constexpr uint32_t kBinHotDefault = 1u << 18;
 
 struct BlkChunk {
   uint64_t e0;     // first edge
-  uint32_t wbase;  // first source of the chunk's window
-  uint32_t n;      // edges (1 .. kBlkChunk)
+  uint32_t wbase;  // first source of the chunk's window; for a cold chunk, its first slot
+  uint16_t n;      // edges (1 .. kBlkChunk)
+  uint16_t cold;   // 1: the edges' high halves are slot offsets from wbase
+};
+static_assert(sizeof(BlkChunk) == 16, "16-byte chunk record");
+// A run of one window's list: its first slot in the list (relative to the
+// window's first) and in the slot array; it ends where the next run of the
+// window starts.
+struct BinRun {
+  uint32_t flat;
+  uint32_t dst;
 };
 struct BlkSlice {
   uint32_t row0, rows;  // the block's rows [row0, row0 + rows)
@@ -92,6 +125,19 @@ inline uint64_t blk_partial_cap(uint64_t e) { return static_cast<uint64_t>(blk_t
 // Finish groups: a multi-slice block of R rows has ceil(R / 64) of them.
 inline uint64_t blk_groups_cap(uint32_t n, uint64_t e) { return n / 64 + blk_blocks_cap(n, e) + 1; }
 
+// Binned cold sources: scatter windows, runs (at most one per (block,
+// window) pair with edges), slots (one per pair plus padding), group table.
+inline uint64_t bin_windows(uint32_t n) { return (static_cast<uint64_t>(n) + (1u << kBinWinBits) - 1) >> kBinWinBits; }
+inline uint64_t bin_runs_cap(uint32_t n, uint64_t e) {
+  const uint64_t pairs = blk_blocks_cap(n, e) * bin_windows(n);
+  return e < pairs ? e : pairs;
+}
+inline uint64_t bin_slots_cap(uint32_t n, uint64_t e) { return e + (kBinPad - 1) * bin_runs_cap(n, e); }
+inline uint64_t bin_groups_cap(uint32_t n, uint64_t e) { return bin_slots_cap(n, e) / kBinGroup + bin_windows(n) + 1; }
+// Chunks of a binned layout: the hot ones as before, plus at most one partial
+// cold chunk per block.
+inline uint64_t bin_chunks_cap(uint32_t n, uint64_t e) { return blk_chunks_cap(n, e) + blk_blocks_cap(n, e); }
+
 // The host-side layout: packed edges (in block order), chunks, slices in
 // launch order, finish groups; plus the block starts and each block's first
 // chunk (used by the checks).
@@ -102,6 +148,16 @@ struct BlockedLayout {
   std::vector<BlkGroup> groups;
   std::vector<uint32_t> row0;    // [blocks + 1] first row of each block
   std::vector<uint64_t> cfirst;  // [blocks + 1] first chunk of each block
+  // binned cold sources (hot == 0: none)
+  uint32_t hot = 0;               // sources below are gathered, the others binned (a multiple of the windows)
+  uint64_t nslots = 0;            // entries of the slot array
+  uint32_t bin_w0 = 0;            // first scatter window holding cold sources
+  std::vector<uint16_t> bin_src;  // window lists: source offset within the window of every slot
+  std::vector<BinRun> bin_runs;   // runs of every window, window by window, each window's in block order
+  std::vector<uint64_t> bin_wflat;  // [cold windows + 1] first list entry of each window
+  std::vector<uint32_t> bin_wrun;   // [cold windows + 1] first run of each window
+  std::vector<uint64_t> bin_wgroup; // [cold windows + 1] first group of each window
+  std::vector<uint32_t> bin_group;  // first run (window-relative) of every kBinGroup list entries of a window
 };
 
 // Build the layout of a CSC given in host memory (offsets [n+1], sources
@@ -112,7 +168,7 @@ struct BlockedLayout {
 // (it is read with these indices even when the graph was not validated) or
 // a table would exceed its bound.
 inline const char* blocked_layout(uint32_t n, uint64_t e, const uint64_t* off, const int32_t* src,
-                                  BlockedLayout* out) {
+                                  BlockedLayout* out, uint32_t hot = 0) {
   // the host loops below index with these: check them here even without IPG_GRAPH_VALIDATE
   if (off[0] != 0 || off[n] != e) return "offsets: off[0] != 0 or off[N] != E";
   for (uint32_t v = 0; v < n; ++v)
@@ -140,6 +196,13 @@ inline const char* blocked_layout(uint32_t n, uint64_t e, const uint64_t* off, c
   }
   const uint64_t nblk = row0.size() - 1, nwin = blk_windows(n);
   if (nblk > blk_blocks_cap(n, e)) return "blocked block table overflow";
+  // binning: the hot count rounded up to whole windows (of both sizes); none
+  // when every source is hot
+  if (hot) {
+    const uint64_t unit = 1u << kBlkWinBits;
+    const uint64_t h = (static_cast<uint64_t>(hot) + unit - 1) / unit * unit;
+    hot = h >= n ? 0u : static_cast<uint32_t>(h);
+  }
   // by source: dst_of[k] is the destination of the k-th edge in source order
   std::vector<uint64_t> sstart((size_t)n + 1, 0);
   for (uint64_t i = 0; i < e; ++i) ++sstart[(size_t)src[i] + 1];
@@ -150,26 +213,88 @@ inline const char* blocked_layout(uint32_t n, uint64_t e, const uint64_t* off, c
     for (uint32_t v = 0; v < n; ++v)
       for (uint64_t i = off[v]; i < off[(size_t)v + 1]; ++i) dst_of[cur[src[i]]++] = v;
   }
-  // by block, counting the edges of every (block, window) segment
+  // by block, counting the edges of every (block, window) segment; with
+  // binning a block's cold edges (sources >= hot) follow its hot ones
   std::vector<uint64_t> bstart(nblk + 1, 0);
   for (uint32_t v = 0; v < n; ++v) bstart[(size_t)blk_of[v] + 1] += off[(size_t)v + 1] - off[v];
   for (uint64_t k = 0; k < nblk; ++k) bstart[k + 1] += bstart[k];
+  std::vector<uint64_t> hot_n(nblk, 0);  // hot edges of each block
+  if (hot)
+    for (uint32_t u = 0; u < hot; ++u)
+      for (uint64_t k = sstart[u]; k < sstart[(size_t)u + 1]; ++k) ++hot_n[blk_of[dst_of[k]]];
   std::vector<uint64_t> seg(nblk * nwin, 0);
   std::vector<uint32_t> packed(e);
+  std::vector<uint32_t> cold_src;  // source of every edge from the first cold edge of block 0 on (binning)
+  if (hot) cold_src.assign(e, 0);
   {
-    std::vector<uint64_t> cur(bstart.begin(), bstart.end() - 1);
+    std::vector<uint64_t> cur(bstart.begin(), bstart.end() - 1), ccur(nblk);
+    for (uint64_t b = 0; b < nblk; ++b) ccur[b] = bstart[b] + hot_n[b];
     for (uint32_t u = 0; u < n; ++u) {
       const uint64_t w = u >> kBlkWinBits;
       const uint32_t hi = (u & ((1u << kBlkWinBits) - 1)) << 16;
+      const bool cold = hot && u >= hot;
       for (uint64_t k = sstart[u]; k < sstart[(size_t)u + 1]; ++k) {
         const uint32_t v = dst_of[k];
         const uint64_t blk = blk_of[v];
-        packed[cur[blk]++] = hi | (v - row0[blk]);
-        ++seg[blk * nwin + w];
+        if (cold) {
+          const uint64_t at = ccur[blk]++;
+          packed[at] = v - row0[blk];  // the slot offset comes with the cold chunks
+          cold_src[at] = u;
+        } else {
+          packed[cur[blk]++] = hi | (v - row0[blk]);
+          ++seg[blk * nwin + w];
+        }
       }
     }
   }
   std::vector<uint32_t>().swap(dst_of);
+  // slots: a new one at every change of source within a block's cold edges,
+  // runs by (block, scatter window) padded to kBinPad slots; cold_src then
+  // holds the edge's slot
+  std::vector<uint32_t> slot_src;  // source of every slot (padding: its run's first source)
+  struct RunRec {
+    uint32_t w;    // scatter window
+    uint64_t dst;  // first slot
+    uint64_t len;  // slots, padding included
+  };
+  std::vector<RunRec> runs;
+  if (hot) {
+    uint64_t next = 0;
+    for (uint64_t blk = 0; blk < nblk; ++blk) {
+      uint32_t prev = 0xFFFFFFFFu;
+      for (uint64_t i = bstart[blk] + hot_n[blk]; i < bstart[blk + 1]; ++i) {
+        const uint32_t u = cold_src[i];
+        if (u != prev) {
+          const uint32_t w = u >> kBinWinBits;
+          if (prev == 0xFFFFFFFFu || w != (prev >> kBinWinBits)) {
+            if (!runs.empty() && runs.back().len % kBinPad) {  // pad the run this one follows
+              const uint64_t pad = kBinPad - runs.back().len % kBinPad;
+              const uint32_t fill = slot_src[runs.back().dst];
+              slot_src.insert(slot_src.end(), pad, fill);
+              runs.back().len += pad;
+              next += pad;
+            }
+            runs.push_back(RunRec{w, next, 0});
+          }
+          slot_src.push_back(u);
+          ++runs.back().len;
+          ++next;
+          prev = u;
+        }
+        cold_src[i] = static_cast<uint32_t>(next - 1);
+        if (next - 1 > 0xFFFFFFFFull) return "binned slot index overflow";
+      }
+    }
+    if (!runs.empty() && runs.back().len % kBinPad) {
+      const uint64_t pad = kBinPad - runs.back().len % kBinPad;
+      const uint32_t fill = slot_src[runs.back().dst];
+      slot_src.insert(slot_src.end(), pad, fill);
+      runs.back().len += pad;
+      next += pad;
+    }
+    if (next > bin_slots_cap(n, e) || runs.size() > bin_runs_cap(n, e) || next >= 0xFFFFFFFFull)
+      return "binned slot table overflow";
+  }
   // chunks: every segment cut into pieces of at most kBlkChunk edges; the
   // cost of a chunk is its edges plus kBlkLineCost per outbox cache line its
   // sources touch (runs of equal source >> 4: 16 FP64 outboxes per 128-byte
@@ -183,7 +308,7 @@ inline const char* blocked_layout(uint32_t n, uint64_t e, const uint64_t* off, c
     for (uint64_t w = 0; w < nwin; ++w) {
       for (uint64_t left = seg[blk * nwin + w]; left > 0;) {
         const uint32_t m = static_cast<uint32_t>(left < kBlkChunk ? left : kBlkChunk);
-        chunks.push_back(BlkChunk{at, static_cast<uint32_t>(w << kBlkWinBits), m});
+        chunks.push_back(BlkChunk{at, static_cast<uint32_t>(w << kBlkWinBits), static_cast<uint16_t>(m), 0});
         uint64_t lines = 1;
         for (uint64_t i = at + 1; i < at + m; ++i) lines += (packed[i] >> 20) != (packed[i - 1] >> 20);
         cost.push_back(m + kBlkLineCost * lines);
@@ -191,9 +316,25 @@ inline const char* blocked_layout(uint32_t n, uint64_t e, const uint64_t* off, c
         left -= m;
       }
     }
+    // cold chunks: up to kBlkChunk consecutive cold edges, their slots as
+    // offsets from the first edge's slot (a line holds 16 slots)
+    for (const uint64_t end = bstart[blk + 1]; at < end;) {
+      const uint32_t m = static_cast<uint32_t>(end - at < kBlkChunk ? end - at : kBlkChunk);
+      const uint32_t base = cold_src[at];
+      uint64_t lines = 1;
+      for (uint64_t i = at; i < at + m; ++i) {
+        const uint32_t d = cold_src[i] - base;
+        if (d >= (1u << 16)) return "binned chunk slot span exceeds 16 bits";
+        packed[i] |= d << 16;
+        if (i > at) lines += (cold_src[i] >> 4) != (cold_src[i - 1] >> 4);
+      }
+      chunks.push_back(BlkChunk{at, base, static_cast<uint16_t>(m), 1});
+      cost.push_back(m + kBlkLineCost * lines);
+      at += m;
+    }
   }
   cfirst[nblk] = chunks.size();
-  if (chunks.size() > blk_chunks_cap(n, e)) return "blocked chunk table overflow";
+  if (chunks.size() > (hot ? bin_chunks_cap(n, e) : blk_chunks_cap(n, e))) return "blocked chunk table overflow";
   // slices.  With fewer blocks than S (about one slice per CU, and only one
   // workgroup fits a CU's LDS): at most S slices in one even wave -- block
   // b gets K_b = ceil(C_b / L) slices (at least one, at most one per
@@ -284,7 +425,8 @@ inline const char* blocked_layout(uint32_t n, uint64_t e, const uint64_t* off, c
     const size_t ns = slices.size();
     auto first_src = [&](const BlkSlice& sl) -> uint64_t {
       const BlkChunk& ch = chunks[sl.c0];
-      return static_cast<uint64_t>(ch.wbase) + (packed[ch.e0] >> 16);
+      const uint64_t at = static_cast<uint64_t>(ch.wbase) + (packed[ch.e0] >> 16);
+      return ch.cold ? slot_src[at] : at;
     };
     std::vector<size_t> idx(ns);
     for (size_t i = 0; i < ns; ++i) idx[i] = i;
@@ -297,6 +439,58 @@ inline const char* blocked_layout(uint32_t n, uint64_t e, const uint64_t* off, c
     for (size_t x = 0; x < kBlkXcds && x < ns; ++x)
       for (size_t p = x; p < ns; p += kBlkXcds) dealt[p] = slices[idx[at++]];
     slices.swap(dealt);
+  }
+  // the bin launch's tables: every cold window's runs in block order (a
+  // stable counting sort of the runs by window), its list of slot sources,
+  // and the first run of every kBinGroup list entries
+  if (hot) {
+    std::vector<uint32_t>().swap(cold_src);
+    const uint32_t w0 = hot >> kBinWinBits;
+    const uint64_t nw = bin_windows(n) - w0;
+    std::vector<uint64_t> rstart(nw + 1, 0), fstart(nw + 1, 0);
+    for (const RunRec& r : runs) {
+      ++rstart[r.w - w0 + 1];
+      fstart[r.w - w0 + 1] += r.len;
+    }
+    for (uint64_t w = 0; w < nw; ++w) {
+      rstart[w + 1] += rstart[w];
+      fstart[w + 1] += fstart[w];
+    }
+    std::vector<BinRun> wruns(runs.size());
+    std::vector<uint16_t> wsrc(fstart[nw]);
+    {
+      std::vector<uint64_t> rc(rstart.begin(), rstart.end() - 1), fc(fstart.begin(), fstart.end() - 1);
+      for (const RunRec& r : runs) {
+        const uint64_t w = r.w - w0;
+        const uint64_t f = fc[w];
+        wruns[rc[w]++] = BinRun{static_cast<uint32_t>(f - fstart[w]), static_cast<uint32_t>(r.dst)};
+        for (uint64_t j = 0; j < r.len; ++j)
+          wsrc[f + j] = static_cast<uint16_t>(slot_src[r.dst + j] & ((1u << kBinWinBits) - 1));
+        fc[w] += r.len;
+      }
+    }
+    std::vector<uint64_t> gstart(nw + 1, 0);
+    std::vector<uint32_t> group;
+    for (uint64_t w = 0; w < nw; ++w) {
+      gstart[w] = group.size();
+      const uint64_t len = fstart[w + 1] - fstart[w];
+      uint64_t r = rstart[w];
+      for (uint64_t j = 0; j < len; j += kBinGroup) {
+        while (r + 1 < rstart[w + 1] && wruns[r + 1].flat <= j) ++r;
+        group.push_back(static_cast<uint32_t>(r - rstart[w]));
+      }
+    }
+    gstart[nw] = group.size();
+    if (group.size() > bin_groups_cap(n, e)) return "binned group table overflow";
+    out->hot = hot;
+    out->nslots = slot_src.size();
+    out->bin_w0 = w0;
+    out->bin_src.swap(wsrc);
+    out->bin_runs.swap(wruns);
+    out->bin_wflat.swap(fstart);
+    out->bin_wrun.assign(rstart.begin(), rstart.end());
+    out->bin_wgroup.swap(gstart);
+    out->bin_group.swap(group);
   }
   out->packed.swap(packed);
   out->chunks.swap(chunks);

@@ -97,6 +97,16 @@ struct BlockedTables {
   BlkGroup* groups;   // 64-row groups of the multi-slice blocks
   double* partial;    // partial sums of the multi-slice blocks
   uint32_t nchunks, nslices, ngroups;
+  // binned cold sources (IPG_GRAPH_BINNED; hot == 0: none)
+  double* slots;        // [nslots] one cold source's outbox per (block, source) pair
+  uint16_t* bin_src;    // window lists: source offset of every slot
+  BinRun* bin_runs;
+  uint64_t* bin_wflat;  // [bin_nwin + 1]
+  uint32_t* bin_wrun;   // [bin_nwin + 1]
+  uint64_t* bin_wgroup; // [bin_nwin + 1]
+  uint32_t* bin_group;
+  uint32_t hot, bin_w0, bin_nwin;
+  uint64_t nslots;
 };
 
 struct GraphTables {

@@ -679,13 +679,14 @@ __global__ __launch_bounds__(kBlkThreads) void minprop_blocked_kernel(MinBlkArgs
   if (sent)  // few senders: a source's outbox is read only when its bit is set
     blk_stream<uint32_t>(
         a.v, sl, kInf,
-        [&](uint32_t wbase, uint32_t q) {
+        [&](uint32_t wbase, uint32_t q, uint32_t) {
           const uint32_t u = wbase + (q >> 16);
           return row_live(sent, static_cast<int32_t>(u)) ? outbox[u] : kInf;
         },
         combine);
   else
-    blk_stream<uint32_t>(a.v, sl, kInf, [&](uint32_t wbase, uint32_t q) { return outbox[wbase + (q >> 16)]; }, combine);
+    blk_stream<uint32_t>(
+        a.v, sl, kInf, [&](uint32_t wbase, uint32_t q, uint32_t) { return outbox[wbase + (q >> 16)]; }, combine);
   __syncthreads();
   const uint32_t r0 = sl.row0, rows = sl.rows;
   uint64_t next_count = 0, next_deg = 0;
@@ -1012,7 +1013,9 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
   const bool device = ctl != nullptr;
   // the blocked in-edges of the caller's CSC (CC, unit-weight SSSP), if the store has them
   const BlockedTables* bt = nullptr;
-  if (tn.blocked && !weighted) bt = g->t.blk_ids.edges ? &g->t.blk_ids : (g->t.blk.edges && !g->t.perm ? &g->t.blk : nullptr);
+  // (a binned table is PageRank's: its cold chunks read slots, not outboxes)
+  if (tn.blocked && !weighted)
+    bt = g->t.blk_ids.edges ? &g->t.blk_ids : (g->t.blk.edges && !g->t.perm && !g->t.blk.hot ? &g->t.blk : nullptr);
   // device-driven superstep s >= 1: the push and the pull form's compute
   // share one launch (minprop_front_kernel), made where the compute's was
   const bool front = device && step > 0;

@@ -161,16 +161,27 @@ static size_t carve_graph(Carver& c, uint32_t n, uint64_t e, uint32_t flags, Gra
     tt.src_hot = c.take<int32_t>(e ? e : 1);
     carve_tiling(c, n, e, &tt.pull_hot);
   }
-  auto carve_blocked = [&](BlockedTables& b) {
+  auto carve_blocked = [&](BlockedTables& b, bool binned) {
     b.edges = c.take<uint32_t>(e ? e : 1);
-    b.chunks = c.take<BlkChunk>(blk_chunks_cap(n, e));
+    b.chunks = c.take<BlkChunk>(binned ? bin_chunks_cap(n, e) : blk_chunks_cap(n, e));
     b.slices = c.take<BlkSlice>(blk_blocks_cap(n, e) + blk_target_slices(e));
     b.groups = c.take<BlkGroup>(blk_groups_cap(n, e));
     b.partial = c.take<double>(blk_partial_cap(e));
+    if (binned) {
+      const uint64_t nw = bin_windows(n) + 1;
+      b.slots = c.take<double>(bin_slots_cap(n, e) + 1);
+      b.bin_src = c.take<uint16_t>(bin_slots_cap(n, e) + 1);
+      b.bin_runs = c.take<BinRun>(bin_runs_cap(n, e) + 1);
+      b.bin_wflat = c.take<uint64_t>(nw);
+      b.bin_wrun = c.take<uint32_t>(nw);
+      b.bin_wgroup = c.take<uint64_t>(nw);
+      b.bin_group = c.take<uint32_t>(bin_groups_cap(n, e));
+    }
   };
   if (flags & IPG_GRAPH_BLOCKED) {
-    carve_blocked(tt.blk);
-    if (flags & IPG_GRAPH_RENAME) carve_blocked(tt.blk_ids);
+    // binning applies to PageRank's table (the first)
+    carve_blocked(tt.blk, (flags & IPG_GRAPH_BINNED) != 0);
+    if (flags & IPG_GRAPH_RENAME) carve_blocked(tt.blk_ids, false);
   }
   if (t) *t = tt;
   return align_up(c.used, 256);
@@ -290,14 +301,14 @@ static ipg_status build_hot_store(const uint64_t* csc_off, const int32_t* csc_sr
 // The blocked in-edges of a CSC (validated or not): built on the host
 // (blocked_layout.h) and copied to the device tables.
 static ipg_status build_blocked(const uint64_t* csc_off, const int32_t* csc_src, uint32_t n, uint64_t e,
-                                BlockedTables* b, hipStream_t s) {
+                                BlockedTables* b, uint32_t hot, hipStream_t s) {
   std::vector<uint64_t> off((size_t)n + 1);
   std::vector<int32_t> src(e);
   IPG_HIP(hipMemcpyAsync(off.data(), csc_off, off.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   if (e) IPG_HIP(hipMemcpyAsync(src.data(), csc_src, e * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   IPG_HIP(hipStreamSynchronize(s));
   BlockedLayout L;
-  if (const char* msg = blocked_layout(n, e, off.data(), src.data(), &L)) return fail(IPG_EBADGRAPH, msg);
+  if (const char* msg = blocked_layout(n, e, off.data(), src.data(), &L, hot)) return fail(IPG_EBADGRAPH, msg);
   std::vector<int32_t>().swap(src);
   if (e) IPG_HIP(hipMemcpyAsync(b->edges, L.packed.data(), e * sizeof(uint32_t), hipMemcpyHostToDevice, s));
   if (!L.chunks.empty())
@@ -306,6 +317,21 @@ static ipg_status build_blocked(const uint64_t* csc_off, const int32_t* csc_src,
     IPG_HIP(hipMemcpyAsync(b->slices, L.slices.data(), L.slices.size() * sizeof(BlkSlice), hipMemcpyHostToDevice, s));
   if (!L.groups.empty())
     IPG_HIP(hipMemcpyAsync(b->groups, L.groups.data(), L.groups.size() * sizeof(BlkGroup), hipMemcpyHostToDevice, s));
+  b->hot = L.hot;
+  b->bin_w0 = L.bin_w0;
+  b->bin_nwin = L.hot ? static_cast<uint32_t>(L.bin_wflat.size() - 1) : 0u;
+  b->nslots = L.nslots;
+  if (L.hot) {
+    auto put = [&](void* dst, const void* src_, size_t bytes) -> hipError_t {
+      return bytes ? hipMemcpyAsync(dst, src_, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+    };
+    IPG_HIP(put(b->bin_src, L.bin_src.data(), L.bin_src.size() * sizeof(uint16_t)));
+    IPG_HIP(put(b->bin_runs, L.bin_runs.data(), L.bin_runs.size() * sizeof(BinRun)));
+    IPG_HIP(put(b->bin_wflat, L.bin_wflat.data(), L.bin_wflat.size() * sizeof(uint64_t)));
+    IPG_HIP(put(b->bin_wrun, L.bin_wrun.data(), L.bin_wrun.size() * sizeof(uint32_t)));
+    IPG_HIP(put(b->bin_wgroup, L.bin_wgroup.data(), L.bin_wgroup.size() * sizeof(uint64_t)));
+    IPG_HIP(put(b->bin_group, L.bin_group.data(), L.bin_group.size() * sizeof(uint32_t)));
+  }
   IPG_HIP(hipStreamSynchronize(s));
   b->nchunks = static_cast<uint32_t>(L.chunks.size());
   b->nslices = static_cast<uint32_t>(L.slices.size());
@@ -384,11 +410,12 @@ extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t
     if (rc != IPG_OK) return rc;
   }
   if (d->flags & IPG_GRAPH_BLOCKED) {
+    const uint32_t hot = (d->flags & IPG_GRAPH_BINNED) ? (d->binned_hot ? d->binned_hot : kBinHotDefault) : 0u;
     if (d->flags & IPG_GRAPH_RENAME) {
-      rc = build_blocked(t.off_hot, t.src_hot, n, e, &t.blk, s);
-      if (rc == IPG_OK) rc = build_blocked(csc_off, csc_src, n, e, &t.blk_ids, s);
+      rc = build_blocked(t.off_hot, t.src_hot, n, e, &t.blk, hot, s);
+      if (rc == IPG_OK) rc = build_blocked(csc_off, csc_src, n, e, &t.blk_ids, 0, s);
     } else {
-      rc = build_blocked(csc_off, csc_src, n, e, &t.blk, s);
+      rc = build_blocked(csc_off, csc_src, n, e, &t.blk, hot, s);
     }
     if (rc != IPG_OK) return rc;
   }

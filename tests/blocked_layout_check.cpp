@@ -18,12 +18,19 @@
 //   * launch position p runs on XCD p mod 8: each XCD holds the number of
 //     positions that mapping gives it, and the XCDs take consecutive runs
 //     of the slices sorted by first source;
-//   * every table stays within its size bound.
+//   * every table stays within its size bound;
+//   * with binned cold sources (a hot count as second argument): the bin
+//     launch's tables give every slot exactly one source, runs of whole
+//     kBinPad-slot lines, each window's runs in slot order, group entries
+//     naming the run that holds their first list entry; cold chunks decode
+//     through them (and hold only cold sources, after the block's hot
+//     chunks), so that the edge multiset check covers the binned edges too.
 // Input file: uint32 N, uint64 E, uint64 off[N + 1], int32 src[E].
 // Prints "OK blocks=.. chunks=.. slices=.. groups=.. partial=..", or
 // "ERR <message>" when the build rejects the CSC, or "FAIL <what>".
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <string>
 #include <tuple>
 
@@ -37,7 +44,8 @@ static int fail(const std::string& what) {
 }
 
 int main(int argc, char** argv) {
-  if (argc != 2) return fail("usage: blocked_layout_check <csc file>");
+  if (argc != 2 && argc != 3) return fail("usage: blocked_layout_check <csc file> [hot sources]");
+  const uint32_t hot_arg = argc == 3 ? static_cast<uint32_t>(std::strtoul(argv[2], nullptr, 10)) : 0u;
   FILE* f = std::fopen(argv[1], "rb");
   if (!f) return fail("cannot open input");
   uint32_t n = 0;
@@ -50,7 +58,7 @@ int main(int argc, char** argv) {
   std::fclose(f);
 
   BlockedLayout L;
-  if (const char* msg = blocked_layout(n, e, off.data(), src.data(), &L)) {
+  if (const char* msg = blocked_layout(n, e, off.data(), src.data(), &L, hot_arg)) {
     std::printf("ERR %s\n", msg);
     return 0;
   }
@@ -59,7 +67,52 @@ int main(int argc, char** argv) {
   const auto& SL = L.slices;
   const auto& G = L.groups;
   if (P.size() != e) return fail("packed size");
-  if (C.size() > blk_chunks_cap(n, e)) return fail("chunk cap");
+  if (C.size() > (L.hot ? bin_chunks_cap(n, e) : blk_chunks_cap(n, e))) return fail("chunk cap");
+  if (hot_arg && L.hot && (L.hot < hot_arg || L.hot % (1u << kBlkWinBits))) return fail("hot count not rounded up to windows");
+
+  // bin tables: the source of every slot
+  const uint32_t kNone = 0xFFFFFFFFu;
+  std::vector<uint32_t> slot_src(L.nslots, kNone);
+  if (L.hot) {
+    const uint64_t nw = bin_windows(n) - L.bin_w0;
+    if (L.bin_w0 != (L.hot >> kBinWinBits)) return fail("first cold window");
+    if (L.bin_wflat.size() != nw + 1 || L.bin_wrun.size() != nw + 1 || L.bin_wgroup.size() != nw + 1)
+      return fail("window table sizes");
+    if (L.nslots > bin_slots_cap(n, e) || L.bin_runs.size() > bin_runs_cap(n, e) ||
+        L.bin_group.size() > bin_groups_cap(n, e) || L.bin_src.size() != L.nslots)
+      return fail("bin table caps");
+    for (uint64_t w = 0; w < nw; ++w) {
+      const uint64_t f0 = L.bin_wflat[w], f1 = L.bin_wflat[w + 1];
+      const uint32_t r0 = L.bin_wrun[w], r1 = L.bin_wrun[w + 1];
+      if (f1 < f0 || r1 < r0) return fail("window tables not ascending");
+      if ((r0 == r1) != (f0 == f1)) return fail("window with slots but no runs, or runs but no slots");
+      const uint64_t len = f1 - f0;
+      for (uint32_t r = r0; r < r1; ++r) {
+        const BinRun& R = L.bin_runs[r];
+        const uint64_t end = r + 1 < r1 ? L.bin_runs[r + 1].flat : len;
+        if (r == r0 && R.flat != 0) return fail("window's first run does not start its list");
+        if (end <= R.flat || (end - R.flat) % kBinPad || R.dst % kBinPad) return fail("run not whole lines");
+        if (r > r0 && R.dst <= L.bin_runs[r - 1].dst) return fail("window's runs not in slot order");
+        for (uint64_t j = R.flat; j < end; ++j) {
+          const uint64_t slot = R.dst + (j - R.flat);
+          if (slot >= L.nslots) return fail("run past the slot array");
+          if (slot_src[slot] != kNone) return fail("slot in two runs");
+          slot_src[slot] = static_cast<uint32_t>(((L.bin_w0 + w) << kBinWinBits) + L.bin_src[f0 + j]);
+          if (slot_src[slot] >= n) return fail("slot source outside the graph");
+        }
+      }
+      const uint64_t g0 = L.bin_wgroup[w], g1 = L.bin_wgroup[w + 1];
+      if (g1 - g0 != (len + kBinGroup - 1) / kBinGroup) return fail("group count of a window");
+      for (uint64_t g = g0; g < g1; ++g) {
+        const uint64_t j = (g - g0) * kBinGroup;
+        const uint32_t r = r0 + L.bin_group[g];
+        if (r >= r1 || L.bin_runs[r].flat > j || (r + 1 < r1 && L.bin_runs[r + 1].flat <= j))
+          return fail("group entry does not name the run of its first slot");
+      }
+    }
+    for (uint64_t k = 0; k < L.nslots; ++k)
+      if (slot_src[k] == kNone) return fail("slot without a run");
+  }
   if (G.size() > blk_groups_cap(n, e)) return fail("group cap");
   if (SL.size() > blk_blocks_cap(n, e) + blk_target_slices(e)) return fail("slice cap");
 
@@ -93,13 +146,22 @@ int main(int argc, char** argv) {
     for (size_t c = 0; c < C.size(); ++c) {
       const BlkChunk& ch = C[c];
       if (ch.e0 != at) return fail("chunks do not tile the edges");
-      if (ch.n < 1 || ch.n > kBlkChunk) return fail("chunk size");
-      if (ch.wbase & ((1u << kBlkWinBits) - 1)) return fail("window base not aligned");
+      if (ch.n < 1 || ch.n > kBlkChunk || ch.cold > 1) return fail("chunk size or flag");
+      if (ch.cold && !L.hot) return fail("cold chunk without binning");
+      if (!ch.cold && (ch.wbase & ((1u << kBlkWinBits) - 1))) return fail("window base not aligned");
       while (b + 1 < nb && at >= bend) bend += bedges[++b];
       if (at >= bend || at + ch.n > bend) return fail("chunk straddles two blocks");
       chunk_blk[c] = static_cast<uint32_t>(b);
+      if (c && chunk_blk[c - 1] == b && C[c - 1].cold && !ch.cold) return fail("hot chunk after a cold one");
       for (uint64_t i = at; i < at + ch.n; ++i) {
-        const uint64_t u = static_cast<uint64_t>(ch.wbase) + (P[i] >> 16);
+        uint64_t u = static_cast<uint64_t>(ch.wbase) + (P[i] >> 16);
+        if (ch.cold) {
+          if (u >= L.nslots) return fail("cold edge past the slot array");
+          u = slot_src[u];
+          if (u < L.hot) return fail("cold chunk holds a hot source");
+        } else if (L.hot && u >= L.hot) {
+          return fail("hot chunk holds a cold source");
+        }
         const uint64_t v = static_cast<uint64_t>(R0[b]) + (P[i] & 0xFFFFu);
         if (u >= n || v >= R0[b + 1]) return fail("decoded edge outside the graph or the block");
         dec[i] = {static_cast<uint32_t>(u), static_cast<uint32_t>(v)};
@@ -219,7 +281,8 @@ int main(int argc, char** argv) {
   }
   uint64_t partial = 0;
   for (const auto& r : runs) partial = std::max(partial, r.second);
-  std::printf("OK blocks=%zu chunks=%zu slices=%zu groups=%zu partial=%llu\n", nb, C.size(), SL.size(), G.size(),
-              static_cast<unsigned long long>(partial));
+  std::printf("OK blocks=%zu chunks=%zu slices=%zu groups=%zu partial=%llu hot=%u slots=%llu runs=%zu\n", nb,
+              C.size(), SL.size(), G.size(), static_cast<unsigned long long>(partial), L.hot,
+              static_cast<unsigned long long>(L.nslots), L.bin_runs.size());
   return 0;
 }

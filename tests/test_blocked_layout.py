@@ -31,7 +31,7 @@ def checker(tmp_path_factory):
     return exe, d
 
 
-def run_check(checker, n, off, src):
+def run_check(checker, n, off, src, hot=None):
     exe, d = checker
     path = str(d / "csc.bin")
     with open(path, "wb") as f:
@@ -39,7 +39,8 @@ def run_check(checker, n, off, src):
         f.write(np.uint64(len(src)).tobytes())
         f.write(np.ascontiguousarray(off, dtype=np.uint64).tobytes())
         f.write(np.ascontiguousarray(src, dtype=np.int32).tobytes())
-    r = subprocess.run([exe, path], capture_output=True, text=True, timeout=120)
+    r = subprocess.run([exe, path] + ([str(hot)] if hot is not None else []), capture_output=True, text=True,
+                       timeout=300)
     line = r.stdout.strip()
     assert r.returncode == 0 and not line.startswith("FAIL"), line or r.stderr
     return line
@@ -50,8 +51,8 @@ def stats(line):
     return {k: int(v) for k, v in (t.split("=") for t in line.split()[1:])}
 
 
-def check_graph(checker, hg):
-    return stats(run_check(checker, hg.n, hg.csc_off, hg.csc_src))
+def check_graph(checker, hg, hot=None):
+    return stats(run_check(checker, hg.n, hg.csc_off, hg.csc_src, hot))
 
 
 def test_one_block_many_slices(checker):
@@ -137,3 +138,87 @@ def test_rejects_malformed_csc(checker):
 def test_benchmark_graph_rmat_s20_symmetrised(checker):
     s = check_graph(checker, graphgen.workload("rmat-s20-sym"))
     assert s["slices"] == 256
+
+
+# ------------------------------------------------- binned cold sources ----
+
+@pytest.mark.parametrize("sym", [False, True])
+def test_binned_rmat_s17(checker, sym):
+    # N = 131072: hot sources [0, 65536), cold scatter windows 4..7
+    hg = graphgen.rmat(17, 16, seed=21, symmetric=sym)
+    s = check_graph(checker, hg, hot=65536)
+    assert s["hot"] == 65536 and s["slots"] > 0 and s["runs"] > 0 and s["slots"] % 8 == 0
+    # a hot count past N: no binning
+    assert check_graph(checker, hg, hot=1 << 20)["hot"] == 0
+
+
+def test_binned_rounds_hot_up_to_windows(checker):
+    hg = graphgen.rmat(18, 8, seed=3)
+    assert check_graph(checker, hg, hot=1000)["hot"] == 65536
+    assert check_graph(checker, hg, hot=65537)["hot"] == 131072
+
+
+def test_binned_multigraph_hubs_and_empty_ranges(checker):
+    # loops, duplicate edges (two edges from one source to one row share a
+    # slot), a hub destination, a cold source hitting many blocks, and a
+    # range of rows without in-edges
+    n = 300000
+    rng = np.random.default_rng(8)
+    src = np.concatenate([rng.integers(0, n, 400000), np.full(50000, 250001), rng.integers(0, n, 30000)])
+    dst = np.concatenate([rng.integers(0, 200000, 400000), rng.integers(0, 200000, 50000), np.zeros(30000, np.int64)])
+    hg = graphgen.from_edges(n, src, dst, keep_self_loops=True, keep_duplicates=True)
+    s = check_graph(checker, hg, hot=65536)
+    assert s["hot"] == 65536 and s["slots"] >= 1
+
+
+def test_binned_every_source_cold_window(checker):
+    # all edges from cold sources in one scatter window
+    n = 140000
+    rng = np.random.default_rng(2)
+    hg = graphgen.from_edges(n, rng.integers(131072, 131072 + 16384, 60000), rng.integers(0, n, 60000))
+    s = check_graph(checker, hg, hot=65536)
+    assert s["hot"] == 65536
+
+
+@pytest.mark.slow
+def test_binned_rmat_s20(checker):
+    hg = graphgen.rmat(20, 16, seed=5)
+    s = check_graph(checker, hg, hot=1 << 18)
+    assert s["hot"] == 1 << 18
+
+
+BIN_PLANTS = {
+    "slot offset off by one": ("packed[i] |= d << 16;", "packed[i] |= (d + 1) << 16;"),
+    "group entry past its run": ("while (r + 1 < rstart[w + 1] && wruns[r + 1].flat <= j) ++r;",
+                                 "while (r + 1 < rstart[w + 1] && wruns[r + 1].flat < j) ++r;"),
+    "source offset truncated": ("slot_src[r.dst + j] & ((1u << kBinWinBits) - 1)",
+                                "slot_src[r.dst + j] & ((1u << (kBinWinBits - 1)) - 1)"),
+    "cold chunk base off by one": ("chunks.push_back(BlkChunk{at, base, static_cast<uint16_t>(m), 1});",
+                                   "chunks.push_back(BlkChunk{at, base + 1, static_cast<uint16_t>(m), 1});"),
+    "runs not padded": ("if (!runs.empty() && runs.back().len % kBinPad) {  // pad the run this one follows",
+                        "if (false) {"),
+}
+
+
+@pytest.mark.parametrize("plant", sorted(BIN_PLANTS))
+def test_checker_catches_planted_binning_mistakes(tmp_path, plant):
+    # the same build with one mistake planted in a copy of the header: the
+    # checker must reject its tables
+    old, new = BIN_PLANTS[plant]
+    src_dir = os.path.join(ROOT, "paper_2010_08781_amd", "csrc")
+    text = open(os.path.join(src_dir, "blocked_layout.h")).read()
+    assert text.count(old) == 1, plant
+    (tmp_path / "blocked_layout.h").write_text(text.replace(old, new))
+    exe = str(tmp_path / "check")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", str(tmp_path), os.path.join(ROOT, "tests", "blocked_layout_check.cpp"),
+                    "-o", exe], check=True)
+    hg = random_graph(200000, 600000, seed=12, loops=True, dups=True)
+    path = str(tmp_path / "csc.bin")
+    with open(path, "wb") as f:
+        f.write(np.uint32(hg.n).tobytes())
+        f.write(np.uint64(hg.m).tobytes())
+        f.write(np.ascontiguousarray(hg.csc_off, dtype=np.uint64).tobytes())
+        f.write(np.ascontiguousarray(hg.csc_src, dtype=np.int32).tobytes())
+    r = subprocess.run([exe, path, "65536"], capture_output=True, text=True, timeout=300)
+    out = r.stdout.strip()
+    assert out.startswith("FAIL") or out.startswith("ERR"), f"planted mistake passed: {out!r} rc={r.returncode}"

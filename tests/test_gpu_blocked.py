@@ -251,3 +251,63 @@ def test_min_pull_full_size_and_switched_off(ipg):
     ref = oracle.run_graph("sssp", hg, 0, source=0)
     v, st = g.run("sssp", source=0, mode="auto", persistent=True)
     assert np.array_equal(ipg.values_to_numpy(v), ref.values) and np.array_equal(st.trace, ref.trace)
+
+
+# ------------------------------------------------- binned cold sources ----
+
+def check_binned(ipg, hg, Ts, hot=65536, rename=True, modes=("pull",)):
+    g = ipg.Graph.from_host(hg, rename=rename, blocked=True, binned=True, binned_hot=hot)
+    for T in Ts:
+        ref = oracle.run_graph("pagerank", hg, T)
+        for mode in modes:
+            print(f"[binned] {hg.name} T={T} {mode} rename={rename} hot={hot}", flush=True)
+            vals, st = g.run("pagerank", T, mode=mode)
+            err = max_rel(ipg.values_to_numpy(vals), ref.values)
+            assert err <= PR_RTOL, f"T={T} {mode}: max rel err {err:.3e}"
+            assert st.supersteps == T + 1 and np.array_equal(st.trace, ref.trace)
+    return g
+
+
+@pytest.mark.parametrize("rename", [True, False])
+def test_binned_rmat_s17_every_update(ipg, rename):
+    # N = 131072: sources from 65536 on binned, the rest gathered
+    check_binned(ipg, graphgen.rmat(17, 16, seed=21), Ts=tuple(range(0, 11)), rename=rename)
+
+
+def test_binned_symmetrised_and_switched_off(ipg):
+    hg = graphgen.rmat(18, 16, seed=4, symmetric=True)
+    g = check_binned(ipg, hg, Ts=(1, 10))
+    ref = oracle.run_graph("pagerank", hg, 10)
+    vals, _ = g.run("pagerank", 10, mode="pull", tuning={"blocked": 0xFFFFFFFF})  # row items on the same store
+    assert max_rel(ipg.values_to_numpy(vals), ref.values) <= PR_RTOL
+    # CC and SSSP on the store keep their own (unbinned) blocked in-edges
+    for app in ("cc", "sssp"):
+        r = oracle.run_graph(app, hg, 0)
+        for persistent in (False, True):
+            v, st = g.run(app, source=0, persistent=persistent)
+            assert np.array_equal(ipg.values_to_numpy(v), r.values) and np.array_equal(st.trace, r.trace)
+
+
+def test_binned_multigraph_hubs_and_empty_ranges(ipg):
+    n = 300000
+    rng = np.random.default_rng(8)
+    src = np.concatenate([rng.integers(0, n, 400000), np.full(50000, 250001), rng.integers(0, n, 30000)])
+    dst = np.concatenate([rng.integers(0, 200000, 400000), rng.integers(0, 200000, 50000), np.zeros(30000, np.int64)])
+    hg = graphgen.from_edges(n, src, dst, keep_self_loops=True, keep_duplicates=True)
+    check_binned(ipg, hg, Ts=(0, 1, 3, 10), rename=False)
+    check_binned(ipg, hg, Ts=(10,), rename=True, hot=1)
+
+
+def test_binned_cold_only_and_convergence(ipg):
+    # every edge from one cold window; a convergence run and a replayed graph on the binned store
+    n = 140000
+    rng = np.random.default_rng(2)
+    hg = graphgen.from_edges(n, rng.integers(131072, 131072 + 16384, 60000), rng.integers(0, n, 60000))
+    g = check_binned(ipg, hg, Ts=(1, 2, 10), rename=False)
+    want, T, _ = oracle.pagerank_converge(hg, 1e-9, 60)
+    vals, st = g.run("pagerank", 60, mode="pull", tol=1e-9)
+    assert st.supersteps == T + 1 and max_rel(ipg.values_to_numpy(vals), want.values) <= PR_RTOL
+    ref = oracle.run_graph("pagerank", hg, 10)
+    for _ in range(3):
+        vals, _ = g.run("pagerank", 10, mode="pull", graph=True)
+        assert max_rel(ipg.values_to_numpy(vals), ref.values) <= PR_RTOL

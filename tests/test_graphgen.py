@@ -1,5 +1,6 @@
 """Input generators: determinism, structure and the recipe's invariants."""
 import numpy as np
+import pytest
 
 import graphgen
 from tests.graphs_small import edge_arrays
@@ -99,3 +100,25 @@ def test_disjoint_union_renumbers_and_records_parts():
     # CSC of the union is the union of the CSCs
     cs = np.repeat(np.arange(u.n), np.diff(u.csc_off).astype(np.int64))
     assert sorted(zip(u.csc_src.tolist(), cs.tolist())) == sorted(zip(us.tolist(), ud.tolist()))
+
+
+@pytest.mark.parametrize("scale,seed", [(10, 5), (14, 5), (16, 2)])
+def test_symmetrise_equals_symmetric_draw(scale, seed):
+    # merging the directed CSR and CSC gives the graph a symmetric draw of the
+    # same edge list builds (reverses added, loops and duplicates dropped)
+    d = graphgen.rmat(scale, 16, seed=seed)
+    s = graphgen.rmat(scale, 16, seed=seed, symmetric=True)
+    m = graphgen.symmetrise(d)
+    assert m.symmetric and m.csc_src is m.csr_dst
+    assert np.array_equal(m.csr_off, s.csr_off)
+    assert np.array_equal(m.csr_dst, s.csr_dst)
+    assert m.name == s.name
+
+
+def test_symmetrise_small_cases():
+    e = graphgen.symmetrise(graphgen.from_edges(4, [], []))
+    assert e.m == 0 and np.array_equal(e.csr_off, np.zeros(5, np.uint64))
+    g = graphgen.from_edges(3, [0, 1, 2, 2], [1, 0, 2, 0], keep_self_loops=True)
+    m = graphgen.symmetrise(g)
+    assert m.csr_off.tolist() == [0, 2, 3, 4]
+    assert m.csr_dst.tolist() == [1, 2, 0, 0]

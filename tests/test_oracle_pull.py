@@ -36,6 +36,8 @@ def test_pull_equals_push_bitwise_and_any_thread_count(name, g):
         push = oracle.run_graph(app, g, param, source=src)
         one = oracle.run_pull(app, g, param, source=src, threads=1)
         many = oracle.run_pull(app, g, param, source=src, threads=8)
+        dealt = oracle.run_pull(app, g, param, source=src, threads=5, chunk=7)
+        assert dealt.values.tobytes() == many.values.tobytes() and np.array_equal(dealt.trace, many.trace)
         assert push.status == one.status == many.status == oracle.OK, (app, src)
         assert push.supersteps == one.supersteps == many.supersteps
         # bit for bit (PageRank too: same additions in the same order)
