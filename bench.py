@@ -196,8 +196,11 @@ def bench_workload(name, args, sel, ipg, np, torch, steps, warmup, apps, tune_ca
     T = args.pr_updates
     graphs = {}
     t0 = time.perf_counter()
+    # binned cold sources when the outbox array (8 bytes per vertex) outgrows the 256 MB Infinity Cache
+    binned = not args.no_blocked and (args.binned == "on" or (args.binned == "auto" and 8 * h_pr.n > (256 << 20)))
     if "pagerank" in apps:
-        graphs["pagerank"] = ipg.Graph.from_host(h_pr, blocked=not args.no_blocked)
+        graphs["pagerank"] = ipg.Graph.from_host(h_pr, blocked=not args.no_blocked, binned=binned,
+                                                 binned_hot=args.binned_hot)
     if any(a != "pagerank" for a in apps):
         gm = graphs["pagerank"] if h_min is h_pr and "pagerank" in graphs else \
             ipg.Graph.from_host(h_min, blocked=not args.no_blocked)
@@ -308,8 +311,9 @@ def bench_workload(name, args, sel, ipg, np, torch, steps, warmup, apps, tune_ca
         g = graphs["pagerank"]
         traffic = measured_traffic(h_pr_key(name), tun.get("pagerank"))
         blocked = g.blocked and (tun.get("pagerank") or {}).get("blocked", 0) != 0xFFFFFFFF
-        kernel = ("pr_blocked_kernel + pr_blocked_finish_kernel" if blocked else
-                  "pr_items_kernel + pr_longrow_kernel") + " (one PageRank pull superstep)"
+        kernel = (("pr_bin_kernel + " if blocked and g.binned else "") +
+                  ("pr_blocked_kernel + pr_blocked_finish_kernel" if blocked else
+                   "pr_items_kernel + pr_longrow_kernel") + " (one PageRank pull superstep)")
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": kernel, "graph": h_pr.name,
@@ -377,6 +381,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="run with the library's default launch parameters")
     ap.add_argument("--no-blocked", action="store_true",
                     help="build the graph without blocked in-edges (PageRank then pulls with the row-item kernels)")
+    ap.add_argument("--binned", default="auto", choices=["auto", "on", "off"],
+                    help="bin PageRank's cold sources (auto: when the outbox array exceeds 256 MB)")
+    ap.add_argument("--binned-hot", type=int, default=0, help="sources gathered edge by edge when binned (0: default)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "_build", "tuning_cache.json"),
                     help="autotuner cache file")
     ap.add_argument("--no-batched", action="store_true",

@@ -33,7 +33,7 @@ namespace ipg {
 // one slot of a slot array, numbered block by block in the order of the
 // edges.  Before each pull a bin launch copies every cold source's outbox
 // value into all of its slots, one workgroup per scatter window of
-// 2^kBinWinBits sources (the window's outboxes staged in LDS): a block's
+// 2^kBinWinBits sources or part of one (the window's outboxes staged in LDS): a block's
 // slots from one window form a run of consecutive slots, padded to
 // kBinPad slots so that runs start on 64-byte lines.  A cold edge's word
 // holds its slot's offset from its chunk's first slot instead of a source
@@ -55,12 +55,17 @@ constexpr uint64_t kBlkLineCost = 6;
 constexpr size_t kBlkXcds = 8;
 static_assert(kBlkRows <= (1u << 16), "row within a block fits 16 bits");
 // Binned cold sources: scatter windows of 2^kBinWinBits sources (their FP64
-// outboxes fill 128 KB of LDS), runs padded to kBinPad slots (64 bytes).
-constexpr uint32_t kBinWinBits = 14;
+// outboxes fill 64 KB of LDS, so two bin workgroups share a CU), runs padded
+// to kBinPad slots (64 bytes).
+constexpr uint32_t kBinWinBits = 13;
 constexpr uint32_t kBinPad = 8;
 constexpr uint32_t kBinGroup = 64;  // slots of a window's list per entry of its group table
-// Hot-source count when binning is asked for without one (2 MB of outboxes).
-constexpr uint32_t kBinHotDefault = 1u << 18;
+// Hot-source count when binning is asked for without one (8 MB of outboxes).
+constexpr uint32_t kBinHotDefault = 1u << 20;
+// Work unit of the bin launch: at most this many groups of one window, so
+// that the windows of many-slot sources are shared by several workgroups
+// (each stages the window's outboxes itself).
+constexpr uint32_t kBinUnitGroups = 4096;
 
 struct BlkChunk {
   uint64_t e0;     // first edge
@@ -75,6 +80,12 @@ static_assert(sizeof(BlkChunk) == 16, "16-byte chunk record");
 struct BinRun {
   uint32_t flat;
   uint32_t dst;
+};
+// One workgroup of the bin launch: groups [g0, g1) of cold window `win`
+// (counted from the first cold window).
+struct BinUnit {
+  uint32_t win;
+  uint32_t g0, g1;
 };
 struct BlkSlice {
   uint32_t row0, rows;  // the block's rows [row0, row0 + rows)
@@ -134,6 +145,7 @@ inline uint64_t bin_runs_cap(uint32_t n, uint64_t e) {
 }
 inline uint64_t bin_slots_cap(uint32_t n, uint64_t e) { return e + (kBinPad - 1) * bin_runs_cap(n, e); }
 inline uint64_t bin_groups_cap(uint32_t n, uint64_t e) { return bin_slots_cap(n, e) / kBinGroup + bin_windows(n) + 1; }
+inline uint64_t bin_units_cap(uint32_t n, uint64_t e) { return bin_groups_cap(n, e) / kBinUnitGroups + bin_windows(n) + 1; }
 // Chunks of a binned layout: the hot ones as before, plus at most one partial
 // cold chunk per block.
 inline uint64_t bin_chunks_cap(uint32_t n, uint64_t e) { return blk_chunks_cap(n, e) + blk_blocks_cap(n, e); }
@@ -158,6 +170,7 @@ struct BlockedLayout {
   std::vector<uint32_t> bin_wrun;   // [cold windows + 1] first run of each window
   std::vector<uint64_t> bin_wgroup; // [cold windows + 1] first group of each window
   std::vector<uint32_t> bin_group;  // first run (window-relative) of every kBinGroup list entries of a window
+  std::vector<BinUnit> bin_units;   // the bin launch's workgroups, window by window
 };
 
 // Build the layout of a CSC given in host memory (offsets [n+1], sources
@@ -326,7 +339,7 @@ inline const char* blocked_layout(uint32_t n, uint64_t e, const uint64_t* off, c
         const uint32_t d = cold_src[i] - base;
         if (d >= (1u << 16)) return "binned chunk slot span exceeds 16 bits";
         packed[i] |= d << 16;
-        if (i > at) lines += (cold_src[i] >> 4) != (cold_src[i - 1] >> 4);
+        if (i > at) lines += (packed[i] >> 20) != (packed[i - 1] >> 20);
       }
       chunks.push_back(BlkChunk{at, base, static_cast<uint16_t>(m), 1});
       cost.push_back(m + kBlkLineCost * lines);
@@ -416,12 +429,27 @@ inline const char* blocked_layout(uint32_t n, uint64_t e, const uint64_t* off, c
   if (poff > blk_partial_cap(e) || slices.size() > blk_blocks_cap(n, e) + blk_target_slices(e) ||
       groups.size() > blk_groups_cap(n, e))
     return "blocked slice table overflow";
-  // XCD-aware launch order: workgroup i of a launch runs on XCD i mod 8, and
-  // a slice's sources are a contiguous range (its chunks are sorted by
-  // source).  The slices are sorted by their first source and XCD x takes
-  // the x-th eighth of them, so that each XCD's L2 caches about an eighth
-  // of the outbox array instead of all of it.
-  {
+  // Launch order.  With more slices than one wave of CUs (several rounds of
+  // workgroups), the costliest first: workgroups are dispatched in launch
+  // order as CUs free up, so the long slices start early and the short ones
+  // fill the gaps at the end (measured at R-MAT scale 26: 3.76 -> 2.00 ms per
+  // pull, every block holding edges of the same hot sources).
+  if (slices.size() > kBlkSlices) {
+    std::vector<uint64_t> sc(slices.size(), 0);
+    for (size_t i = 0; i < slices.size(); ++i)
+      for (uint32_t c = slices[i].c0; c < slices[i].c1; ++c) sc[i] += cost[c];
+    std::vector<size_t> idx(slices.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return sc[x] > sc[y]; });
+    std::vector<BlkSlice> sorted(slices.size());
+    for (size_t i = 0; i < idx.size(); ++i) sorted[i] = slices[idx[i]];
+    slices.swap(sorted);
+  } else {
+    // Within one wave, XCD-aware: workgroup i of a launch runs on XCD i mod
+    // 8, and a slice's sources are a contiguous range (its chunks are sorted
+    // by source).  The slices are sorted by their first source and XCD x
+    // takes the x-th eighth of them, so that each XCD's L2 caches about an
+    // eighth of the outbox array instead of all of it.
     const size_t ns = slices.size();
     auto first_src = [&](const BlkSlice& sl) -> uint64_t {
       const BlkChunk& ch = chunks[sl.c0];
@@ -482,6 +510,13 @@ inline const char* blocked_layout(uint32_t n, uint64_t e, const uint64_t* off, c
     }
     gstart[nw] = group.size();
     if (group.size() > bin_groups_cap(n, e)) return "binned group table overflow";
+    std::vector<BinUnit> units;
+    for (uint64_t w = 0; w < nw; ++w) {
+      const uint32_t ng = static_cast<uint32_t>(gstart[w + 1] - gstart[w]);
+      for (uint32_t g = 0; g < ng; g += kBinUnitGroups)
+        units.push_back(BinUnit{static_cast<uint32_t>(w), g, std::min(ng, g + kBinUnitGroups)});
+    }
+    if (units.size() > bin_units_cap(n, e)) return "binned unit table overflow";
     out->hot = hot;
     out->nslots = slot_src.size();
     out->bin_w0 = w0;
@@ -491,6 +526,7 @@ inline const char* blocked_layout(uint32_t n, uint64_t e, const uint64_t* off, c
     out->bin_wrun.assign(rstart.begin(), rstart.end());
     out->bin_wgroup.swap(gstart);
     out->bin_group.swap(group);
+    out->bin_units.swap(units);
   }
   out->packed.swap(packed);
   out->chunks.swap(chunks);

@@ -105,7 +105,8 @@ struct BlockedTables {
   uint32_t* bin_wrun;   // [bin_nwin + 1]
   uint64_t* bin_wgroup; // [bin_nwin + 1]
   uint32_t* bin_group;
-  uint32_t hot, bin_w0, bin_nwin;
+  BinUnit* bin_units;   // [bin_nunits] the bin launch's workgroups
+  uint32_t hot, bin_w0, bin_nwin, bin_nunits;
   uint64_t nslots;
 };
 

@@ -176,6 +176,7 @@ static size_t carve_graph(Carver& c, uint32_t n, uint64_t e, uint32_t flags, Gra
       b.bin_wrun = c.take<uint32_t>(nw);
       b.bin_wgroup = c.take<uint64_t>(nw);
       b.bin_group = c.take<uint32_t>(bin_groups_cap(n, e));
+      b.bin_units = c.take<BinUnit>(bin_units_cap(n, e));
     }
   };
   if (flags & IPG_GRAPH_BLOCKED) {
@@ -331,7 +332,9 @@ static ipg_status build_blocked(const uint64_t* csc_off, const int32_t* csc_src,
     IPG_HIP(put(b->bin_wrun, L.bin_wrun.data(), L.bin_wrun.size() * sizeof(uint32_t)));
     IPG_HIP(put(b->bin_wgroup, L.bin_wgroup.data(), L.bin_wgroup.size() * sizeof(uint64_t)));
     IPG_HIP(put(b->bin_group, L.bin_group.data(), L.bin_group.size() * sizeof(uint32_t)));
+    IPG_HIP(put(b->bin_units, L.bin_units.data(), L.bin_units.size() * sizeof(BinUnit)));
   }
+  b->bin_nunits = static_cast<uint32_t>(L.bin_units.size());
   IPG_HIP(hipStreamSynchronize(s));
   b->nchunks = static_cast<uint32_t>(L.chunks.size());
   b->nslices = static_cast<uint32_t>(L.slices.size());

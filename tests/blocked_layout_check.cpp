@@ -112,6 +112,26 @@ int main(int argc, char** argv) {
     }
     for (uint64_t k = 0; k < L.nslots; ++k)
       if (slot_src[k] == kNone) return fail("slot without a run");
+    // work units: each window's groups in order, once, at most kBinUnitGroups per unit
+    if (L.bin_units.size() > bin_units_cap(n, e)) return fail("unit cap");
+    {
+      uint64_t w = 0, g = 0;
+      for (const BinUnit& u : L.bin_units) {
+        while (w < nw && g == L.bin_wgroup[w + 1] - L.bin_wgroup[w]) {
+          ++w;
+          g = 0;
+        }
+        if (u.win != w || u.g0 != g || u.g1 <= u.g0 || u.g1 - u.g0 > kBinUnitGroups ||
+            u.g1 > L.bin_wgroup[w + 1] - L.bin_wgroup[w])
+          return fail("bin units do not tile the windows' groups");
+        g = u.g1;
+      }
+      while (w < nw && g == L.bin_wgroup[w + 1] - L.bin_wgroup[w]) {
+        ++w;
+        g = 0;
+      }
+      if (w != nw) return fail("bin units miss groups");
+    }
   }
   if (G.size() > blk_groups_cap(n, e)) return fail("group cap");
   if (SL.size() > blk_blocks_cap(n, e) + blk_target_slices(e)) return fail("slice cap");
@@ -260,8 +280,23 @@ int main(int argc, char** argv) {
     for (uint32_t r = R0[b]; r < R0[b + 1]; ++r)
       if (covered[r] != (kb[b] != 1)) return fail("row not finished exactly once");
 
-  // XCD deal
-  {
+  // launch order: with more slices than kBlkSlices, costliest first (cost =
+  // edges + kBlkLineCost per 128-byte line of values the chunk reads: 16
+  // outboxes, or 16 slots of a cold chunk); else the XCD deal
+  if (SL.size() > kBlkSlices) {
+    auto chunk_cost = [&](const BlkChunk& ch) {
+      uint64_t lines = 1;
+      for (uint64_t i = ch.e0 + 1; i < ch.e0 + ch.n; ++i) lines += (P[i] >> 20) != (P[i - 1] >> 20);
+      return ch.n + kBlkLineCost * lines;
+    };
+    uint64_t prev = UINT64_MAX;
+    for (const BlkSlice& s : SL) {
+      uint64_t c = 0;
+      for (uint32_t k = s.c0; k < s.c1; ++k) c += chunk_cost(C[k]);
+      if (c > prev) return fail("slices not in descending cost order");
+      prev = c;
+    }
+  } else {
     const size_t ns = SL.size();
     auto first_src = [&](const BlkSlice& s) { return dec[C[s.c0].e0].first; };
     std::vector<uint32_t> last_on(kBlkXcds, 0), first_on(kBlkXcds, UINT32_MAX);

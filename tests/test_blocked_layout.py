@@ -222,3 +222,16 @@ def test_checker_catches_planted_binning_mistakes(tmp_path, plant):
     r = subprocess.run([exe, path, "65536"], capture_output=True, text=True, timeout=300)
     out = r.stdout.strip()
     assert out.startswith("FAIL") or out.startswith("ERR"), f"planted mistake passed: {out!r} rc={r.returncode}"
+
+
+@pytest.mark.parametrize("hot", [None, 65536])
+def test_several_rounds_costliest_first(checker, hot):
+    # more row-capped blocks than one wave of slices: the launch order is by
+    # descending cost (the checker recomputes each slice's cost)
+    n = 6_000_000
+    rng = np.random.default_rng(13)
+    src = np.concatenate([rng.integers(0, n, 1_500_000), rng.integers(0, 1000, 500_000)])
+    dst = np.concatenate([rng.integers(0, n, 1_500_000), rng.integers(0, 40_000, 500_000)])
+    hg = graphgen.from_edges(n, src, dst)
+    s = check_graph(checker, hg, hot=hot)
+    assert s["slices"] > 256
