@@ -28,17 +28,12 @@
 #include "blocked.h"
 #include "engine.h"
 #include "scatter.h"
+#include "select.h"
 #include "selector.h"
 
 namespace ipg {
 
-// Which vertices run compute in a launch.
-enum : int {
-  kSendAll = 0,     // superstep 0 of CC: every vertex broadcasts its id
-  kSendSource = 1,  // superstep 0 of SSSP: the source broadcasts
-  kStepList = 2,    // s >= 1, active vertices given as a list
-  kStepDense = 3    // s >= 1, active vertices = non-empty mailboxes (sweep all N)
-};
+static_assert(kListSegs == static_cast<uint32_t>(kCtrSlots), "one list segment per counter slot");
 
 // value = id (CC) or 0 at the source / INF elsewhere (SSSP).  With `pull_s0`
 // superstep 0 is exchanged by pull: the senders' broadcast values are written
@@ -72,40 +67,12 @@ __global__ __launch_bounds__(kBlock) void minprop_init_kernel(uint32_t n, int ap
   if (pull_s0) flush_counters(ctr, senders, messages, 0, 0, 0);
 }
 
-struct Active {
-  int phase;
-  uint32_t count;           // list length, or N for the dense and send-all phases
-  const uint32_t* list;     // the list, in kCtrSlots segments of `seg` entries
-  const uint32_t* pre;      // [kCtrSlots + 1] prefix of the segments' lengths
-  uint32_t seg;
-  uint32_t source;
-};
-
 // The list prefix of a launch in LDS (zeros when the phase has no list).
 // Every thread calls it.
 __device__ __forceinline__ void load_list_prefix(const Active& act, uint32_t* s_pre) {
   for (uint32_t t = threadIdx.x; t <= static_cast<uint32_t>(kCtrSlots); t += blockDim.x)
     s_pre[t] = act.phase == kStepList ? act.pre[t] : 0u;
   __syncthreads();
-}
-
-// Vertex of slot i of a launch.  List entry i lies in the segment k with
-// s_pre[k] <= i < s_pre[k + 1].
-__device__ __forceinline__ uint32_t active_vertex(const Active& act, const uint32_t* s_pre, uint64_t i) {
-  const uint32_t id = static_cast<uint32_t>(i);
-  const bool listed = act.phase == kStepList;  // uniform over the grid
-  uint32_t lo = 0;
-  if (listed) {
-    uint32_t hi = kCtrSlots - 1;  // the last k with s_pre[k] <= i
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (s_pre[mid] <= id) lo = mid;
-      else hi = mid - 1;
-    }
-  }
-  const uint64_t li = listed ? static_cast<uint64_t>(lo) * act.seg + (id - s_pre[lo]) : 0;
-  const uint32_t from_list = listed ? act.list[li] : id;
-  return act.phase == kSendSource ? act.source : from_list;
 }
 
 // Compute of vertex v in a launch: returns whether v broadcasts, and the
