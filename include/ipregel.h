@@ -93,8 +93,11 @@ typedef enum { IPG_MODE_AUTO = 0, IPG_MODE_PUSH = 1, IPG_MODE_PULL = 2 } ipg_mod
                                   8 bytes once the outbox array outgrows the caches, into a streamed
                                   write and read of 8 bytes (propagation blocking over Section 4.3.2's pull).
                                   The sums are unchanged (the same messages; order as with
-                                  IPG_GRAPH_BLOCKED).  Costs about 10 bytes per cold (block, source) pair of
-                                  graph workspace (bounded by 10E + 70 x the (block, window) pairs). */
+                                  IPG_GRAPH_BLOCKED).  The CC/SSSP pull's blocked in-edges (of the caller's
+                                  ids) are binned the same way, with their u32 outboxes (INF for a source
+                                  that did not broadcast) in the slots and the same hot count of ids.
+                                  Costs about 10 bytes per cold (block, source) pair of graph workspace per
+                                  binned table (bounded by 10E + 70 x the (block, window) pairs). */
 
 /*
  * A graph as CSR (out-adjacency, for push) plus CSC (in-adjacency, for pull).

@@ -120,4 +120,99 @@ __device__ __forceinline__ void blk_stream(const BlkView& b, const BlkSlice& sl,
   }
 }
 
+// Tables of the bin launch of a binned layout (IPG_GRAPH_BINNED).
+struct BinTables {
+  const uint16_t* src;
+  const BinRun* runs;
+  const uint64_t* wflat;
+  const uint32_t* wrun;
+  const uint64_t* wgroup;
+  const uint32_t* group;
+  const BinUnit* units;
+  uint32_t w0;
+};
+inline BinTables bin_tables(const BlockedTables& t) {
+  BinTables b;
+  b.src = t.bin_src;
+  b.runs = t.bin_runs;
+  b.wflat = t.bin_wflat;
+  b.wrun = t.bin_wrun;
+  b.wgroup = t.bin_wgroup;
+  b.group = t.bin_group;
+  b.units = t.bin_units;
+  b.w0 = t.hot >> kBinWinBits;
+  return b;
+}
+constexpr uint32_t kBinWin = 1u << kBinWinBits;
+constexpr int kBinBatch = 8;  // groups of kBinGroup list entries a wavefront handles per iteration
+// Runs a group of kBinGroup list entries can meet: runs hold whole kBinPad
+// lines, so a group meets at most kBinGroup / kBinPad of them after its first.
+constexpr int kBinCand = kBinGroup / kBinPad + 1;
+static_assert(kBinCand <= kWave && kBinGroup == kWave, "one group entry per lane, one candidate run per lane");
+
+// The bin launch's work for one workgroup (one work unit: at most
+// kBinUnitGroups groups of one cold window of kBinWin sources; kBlkThreads
+// threads).  The window's values -- value(u) for source u < n -- are staged
+// in LDS, then every entry of the unit's part of the window's list (its
+// slots, in the window's run order) copies its source's value into its slot.
+// Lane j of a group takes list entry j; the group's first run and the runs
+// after it are loaded by the first kBinCand lanes, and each lane picks the
+// last of them that starts at or before its entry.  Consecutive entries of a
+// run go to consecutive slots, so a wavefront's stores are runs of whole
+// lines.
+template <class T, class Value>
+__device__ __forceinline__ void bin_unit(const BinTables& bv, T* slots, uint32_t n, Value value) {
+  __shared__ T win[kBinWin];
+  const BinUnit unit = bv.units[blockIdx.x];
+  const uint32_t k = unit.win;
+  const uint64_t base = static_cast<uint64_t>(bv.w0 + k) << kBinWinBits;
+  {
+    constexpr int kPer = kBinWin / kBlkThreads;
+    T x[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const uint64_t u = base + threadIdx.x + i * kBlkThreads;
+      x[i] = value(static_cast<uint32_t>(u < n ? u : n - 1));  // sources past N have no slots
+    }
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) win[threadIdx.x + i * kBlkThreads] = x[i];
+  }
+  __syncthreads();
+  const uint64_t f0 = bv.wflat[k];
+  const uint32_t len = static_cast<uint32_t>(bv.wflat[k + 1] - f0);
+  const uint32_t r0 = bv.wrun[k], nr = bv.wrun[k + 1] - r0;
+  const uint64_t g0 = bv.wgroup[k];
+  const uint32_t ng = unit.g1;  // groups [unit.g0, unit.g1) of the window, g1 <= ceil(len / kBinGroup)
+  const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
+  constexpr uint32_t kWaves = kBlkThreads / kWave;
+  for (uint32_t g = unit.g0 + wv * kBinBatch; g < ng; g += kWaves * kBinBatch) {  // wave-uniform
+    uint32_t fr[kBinBatch], so[kBinBatch];
+    BinRun cand[kBinBatch];
+#pragma unroll
+    for (int b = 0; b < kBinBatch; ++b) {
+      const uint32_t gi = g + b < ng ? g + b : ng - 1;
+      fr[b] = bv.group[g0 + gi];
+      const uint32_t j = gi * kBinGroup + lane;
+      so[b] = bv.src[f0 + (j < len ? j : len - 1)];
+    }
+#pragma unroll
+    for (int b = 0; b < kBinBatch; ++b) {
+      const uint32_t r = fr[b] + (lane < kBinCand ? lane : 0);
+      cand[b] = bv.runs[r0 + (r < nr ? r : nr - 1)];
+      if (lane >= kBinCand || r >= nr) cand[b].flat = 0xFFFFFFFFu;  // not a run of this group
+    }
+#pragma unroll
+    for (int b = 0; b < kBinBatch; ++b) {
+      const uint32_t j = (g + b) * kBinGroup + lane;
+      int t = 0;
+#pragma unroll
+      for (int c = 1; c < kBinCand; ++c)
+        if (static_cast<uint32_t>(__shfl(static_cast<int>(cand[b].flat), c)) <= j) t = c;
+      const uint32_t flat = static_cast<uint32_t>(__shfl(static_cast<int>(cand[b].flat), t));
+      const uint32_t dst = static_cast<uint32_t>(__shfl(static_cast<int>(cand[b].dst), t));
+      if (g + b < ng && j < len) slots[static_cast<uint64_t>(dst) + (j - flat)] = win[so[b]];
+    }
+  }
+}
+
 }  // namespace ipg

@@ -599,7 +599,18 @@ struct MinBlkArgs {
   const DevCtl* ctl;  // device-driven loop: run only when it chose pull (else null)
   const uint32_t* sent;  // bitmap of the senders, consulted when *gate is set (gate null: never)
   const uint32_t* gate;
+  const uint32_t* slots;  // binned cold sources' outboxes (INF: did not broadcast), one per (block, source)
 };
+
+// Bin launch of a binned layout (IPG_GRAPH_BINNED): every cold source's
+// outbox (INF when it did not broadcast) copied into its slots (bin_unit).
+// The window's outboxes are read as one coalesced block, so the senders'
+// bitmap would only add a dependent load: the gate is not consulted.
+__global__ __launch_bounds__(kBlkThreads) void min_bin_kernel(MinBlkArgs a, BinTables bv, uint32_t* slots, uint32_t n) {
+  if (a.ctl && (a.ctl->halted || a.ctl->mode != IPG_MODE_PULL)) return;  // uniform over the grid
+  const uint32_t* outbox = a.outbox;
+  bin_unit<uint32_t>(bv, slots, n, [&](uint32_t u) { return outbox[u]; });
+}
 
 // Counters of a workgroup of any width: summed over its wavefronts in LDS,
 // then at most one atomic per field into its slot.  Every thread calls it.
@@ -643,17 +654,25 @@ __global__ __launch_bounds__(kBlkThreads) void minprop_blocked_kernel(MinBlkArgs
   const uint32_t* outbox = a.outbox;
   const uint32_t* sent = (a.gate && *a.gate) ? a.sent : nullptr;  // uniform over the grid
   auto combine = [&](uint32_t slot, uint32_t o) { atomicMin(&part[slot], edge_msg<APP, false>(o, 1u, overflow)); };
-  if (sent)  // few senders: a source's outbox is read only when its bit is set
+  // a cold chunk reads its slots, in which the bin launch already applied the gate
+  const uint32_t* slots = a.slots;
+  if (sent)  // few senders: a hot source's outbox is read only when its bit is set
     blk_stream<uint32_t>(
         a.v, sl, kInf,
-        [&](uint32_t wbase, uint32_t q, uint32_t) {
-          const uint32_t u = wbase + (q >> 16);
-          return row_live(sent, static_cast<int32_t>(u)) ? outbox[u] : kInf;
+        [&](uint32_t wbase, uint32_t q, uint32_t cold) {
+          const uint64_t i = static_cast<uint64_t>(wbase) + (q >> 16);
+          const uint32_t u = cold ? 0u : static_cast<uint32_t>(i);  // a bitmap index within [0, N)
+          const uint32_t x = (cold ? slots : outbox)[i];
+          return cold || row_live(sent, static_cast<int32_t>(u)) ? x : kInf;
         },
         combine);
   else
     blk_stream<uint32_t>(
-        a.v, sl, kInf, [&](uint32_t wbase, uint32_t q, uint32_t) { return outbox[wbase + (q >> 16)]; }, combine);
+        a.v, sl, kInf,
+        [&](uint32_t wbase, uint32_t q, uint32_t cold) {
+          return (cold ? slots : outbox)[static_cast<uint64_t>(wbase) + (q >> 16)];
+        },
+        combine);
   __syncthreads();
   const uint32_t r0 = sl.row0, rows = sl.rows;
   uint64_t next_count = 0, next_deg = 0;
@@ -980,9 +999,8 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
   const bool device = ctl != nullptr;
   // the blocked in-edges of the caller's CSC (CC, unit-weight SSSP), if the store has them
   const BlockedTables* bt = nullptr;
-  // (a binned table is PageRank's: its cold chunks read slots, not outboxes)
   if (tn.blocked && !weighted)
-    bt = g->t.blk_ids.edges ? &g->t.blk_ids : (g->t.blk.edges && !g->t.perm && !g->t.blk.hot ? &g->t.blk : nullptr);
+    bt = g->t.blk_ids.edges ? &g->t.blk_ids : (g->t.blk.edges && !g->t.perm ? &g->t.blk : nullptr);
   // device-driven superstep s >= 1: the push and the pull form's compute
   // share one launch (minprop_front_kernel), made where the compute's was
   const bool front = device && step > 0;
@@ -1074,7 +1092,15 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
       ba.ctr_clear = b.cc;
       ba.ctl = ctl;
       ba.sent = w.sent;
-      ba.gate = gating ? w.gate : nullptr;
+      // over binned in-edges the gathers left are the hot sources' (a few MB
+      // of outboxes): the senders' bitmap would only add a dependent load
+      ba.gate = gating && !bt->hot ? w.gate : nullptr;
+      ba.slots = bt->hot ? reinterpret_cast<const uint32_t*>(bt->slots) : nullptr;
+      if (bt->hot && bt->bin_nunits) {
+        hipLaunchKernelGGL(min_bin_kernel, dim3(bt->bin_nunits), dim3(kBlkThreads), 0, s, ba, bin_tables(*bt),
+                           reinterpret_cast<uint32_t*>(bt->slots), n);
+        IPG_HIP(hipGetLastError());
+      }
       if (bt->nslices) {
         if (app == IPG_APP_CC_HASHMIN)
           hipLaunchKernelGGL(minprop_blocked_kernel<IPG_APP_CC_HASHMIN>, dim3(bt->nslices), dim3(kBlkThreads), 0, s, ba);

@@ -383,85 +383,11 @@ struct PrBlkArgs {
   uint32_t n;
 };
 
-// Bin launch of the binned layout (IPG_GRAPH_BINNED): the view of its tables.
-struct BinView {
-  const uint16_t* src;
-  const BinRun* runs;
-  const uint64_t* wflat;
-  const uint32_t* wrun;
-  const uint64_t* wgroup;
-  const uint32_t* group;
-  const BinUnit* units;
-  double* slots;
-  uint32_t w0;
-};
-constexpr uint32_t kBinWin = 1u << kBinWinBits;
-constexpr int kBinBatch = 8;  // groups of kBinGroup list entries a wavefront handles per iteration
-// Runs a group of kBinGroup list entries can meet: runs hold whole kBinPad
-// lines, so a group meets at most kBinGroup / kBinPad of them after its first.
-constexpr int kBinCand = kBinGroup / kBinPad + 1;
-static_assert(kBinCand <= kWave && kBinGroup == kWave, "one group entry per lane, one candidate run per lane");
-
-// One workgroup per work unit (at most kBinUnitGroups groups of one cold
-// window of kBinWin sources): the window's outboxes are staged in LDS, then
-// every entry of the unit's part of the window's list (its slots, in the
-// window's run order) copies its source's outbox into its slot.  Lane j
-// of a group takes list entry j; the group's first run and the runs after it
-// are loaded by the first kBinCand lanes, and each lane picks the last of
-// them that starts at or before its entry.  Consecutive entries of a run go
-// to consecutive slots, so a wavefront's stores are runs of whole lines.
-__global__ __launch_bounds__(kBlkThreads) void pr_bin_kernel(const double* contrib, uint32_t n, BinView bv) {
-  __shared__ double win[kBinWin];
-  const BinUnit unit = bv.units[blockIdx.x];
-  const uint32_t k = unit.win;
-  const uint64_t base = static_cast<uint64_t>(bv.w0 + k) << kBinWinBits;
-  {
-    constexpr int kPer = kBinWin / kBlkThreads;
-    double x[kPer];
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      const uint64_t u = base + threadIdx.x + i * kBlkThreads;
-      x[i] = contrib[u < n ? u : n - 1];  // sources past N have no slots
-    }
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) win[threadIdx.x + i * kBlkThreads] = x[i];
-  }
-  __syncthreads();
-  const uint64_t f0 = bv.wflat[k];
-  const uint32_t len = static_cast<uint32_t>(bv.wflat[k + 1] - f0);
-  const uint32_t r0 = bv.wrun[k], nr = bv.wrun[k + 1] - r0;
-  const uint64_t g0 = bv.wgroup[k];
-  const uint32_t ng = unit.g1;  // groups [unit.g0, unit.g1) of the window, g1 <= ceil(len / kBinGroup)
-  const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
-  constexpr uint32_t kWaves = kBlkThreads / kWave;
-  for (uint32_t g = unit.g0 + wv * kBinBatch; g < ng; g += kWaves * kBinBatch) {  // wave-uniform
-    uint32_t fr[kBinBatch], so[kBinBatch];
-    BinRun cand[kBinBatch];
-#pragma unroll
-    for (int b = 0; b < kBinBatch; ++b) {
-      const uint32_t gi = g + b < ng ? g + b : ng - 1;
-      fr[b] = bv.group[g0 + gi];
-      const uint32_t j = gi * kBinGroup + lane;
-      so[b] = bv.src[f0 + (j < len ? j : len - 1)];
-    }
-#pragma unroll
-    for (int b = 0; b < kBinBatch; ++b) {
-      const uint32_t r = fr[b] + (lane < kBinCand ? lane : 0);
-      cand[b] = bv.runs[r0 + (r < nr ? r : nr - 1)];
-      if (lane >= kBinCand || r >= nr) cand[b].flat = 0xFFFFFFFFu;  // not a run of this group
-    }
-#pragma unroll
-    for (int b = 0; b < kBinBatch; ++b) {
-      const uint32_t j = (g + b) * kBinGroup + lane;
-      int t = 0;
-#pragma unroll
-      for (int c = 1; c < kBinCand; ++c)
-        if (static_cast<uint32_t>(__shfl(static_cast<int>(cand[b].flat), c)) <= j) t = c;
-      const uint32_t flat = static_cast<uint32_t>(__shfl(static_cast<int>(cand[b].flat), t));
-      const uint32_t dst = static_cast<uint32_t>(__shfl(static_cast<int>(cand[b].dst), t));
-      if (g + b < ng && j < len) bv.slots[static_cast<uint64_t>(dst) + (j - flat)] = win[so[b]];
-    }
-  }
+// Bin launch of the binned layout (IPG_GRAPH_BINNED): every cold source's
+// outbox copied into its slots (bin_unit).
+__global__ __launch_bounds__(kBlkThreads) void pr_bin_kernel(const double* contrib, uint32_t n, BinTables bv,
+                                                             double* slots) {
+  bin_unit<double>(bv, slots, n, [&](uint32_t u) { return contrib[u]; });
 }
 
 // Blocked pull, first launch: workgroup = slice.  The block's sums start at
@@ -829,17 +755,8 @@ static hipError_t launch_pr_pull(const PrPullArgs& a, const PrPullStore& ps, con
     b.slots = ps.blk->hot ? ps.blk->slots : nullptr;
     b.n = n;
     if (ps.blk->hot && ps.blk->bin_nunits) {
-      BinView bv;
-      bv.src = ps.blk->bin_src;
-      bv.runs = ps.blk->bin_runs;
-      bv.wflat = ps.blk->bin_wflat;
-      bv.wrun = ps.blk->bin_wrun;
-      bv.wgroup = ps.blk->bin_wgroup;
-      bv.group = ps.blk->bin_group;
-      bv.units = ps.blk->bin_units;
-      bv.slots = ps.blk->slots;
-      bv.w0 = ps.blk->bin_w0;
-      hipLaunchKernelGGL(pr_bin_kernel, dim3(ps.blk->bin_nunits), dim3(kBlkThreads), 0, s, a.contrib_in, n, bv);
+      hipLaunchKernelGGL(pr_bin_kernel, dim3(ps.blk->bin_nunits), dim3(kBlkThreads), 0, s, a.contrib_in, n,
+                         bin_tables(*ps.blk), ps.blk->slots);
       const hipError_t e0 = hipGetLastError();
       if (e0 != hipSuccess) return e0;
     }

@@ -180,9 +180,8 @@ static size_t carve_graph(Carver& c, uint32_t n, uint64_t e, uint32_t flags, Gra
     }
   };
   if (flags & IPG_GRAPH_BLOCKED) {
-    // binning applies to PageRank's table (the first)
     carve_blocked(tt.blk, (flags & IPG_GRAPH_BINNED) != 0);
-    if (flags & IPG_GRAPH_RENAME) carve_blocked(tt.blk_ids, false);
+    if (flags & IPG_GRAPH_RENAME) carve_blocked(tt.blk_ids, (flags & IPG_GRAPH_BINNED) != 0);
   }
   if (t) *t = tt;
   return align_up(c.used, 256);
@@ -416,7 +415,7 @@ extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t
     const uint32_t hot = (d->flags & IPG_GRAPH_BINNED) ? (d->binned_hot ? d->binned_hot : kBinHotDefault) : 0u;
     if (d->flags & IPG_GRAPH_RENAME) {
       rc = build_blocked(t.off_hot, t.src_hot, n, e, &t.blk, hot, s);
-      if (rc == IPG_OK) rc = build_blocked(csc_off, csc_src, n, e, &t.blk_ids, 0, s);
+      if (rc == IPG_OK) rc = build_blocked(csc_off, csc_src, n, e, &t.blk_ids, hot, s);
     } else {
       rc = build_blocked(csc_off, csc_src, n, e, &t.blk, hot, s);
     }

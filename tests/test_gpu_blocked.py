@@ -255,7 +255,7 @@ def test_min_pull_full_size_and_switched_off(ipg):
 
 # ------------------------------------------------- binned cold sources ----
 
-def check_binned(ipg, hg, Ts, hot=65536, rename=True, modes=("pull",)):
+def check_binned(ipg, hg, Ts, hot=65536, rename=True, modes=("pull",), min_apps=True):
     g = ipg.Graph.from_host(hg, rename=rename, blocked=True, binned=True, binned_hot=hot)
     for T in Ts:
         ref = oracle.run_graph("pagerank", hg, T)
@@ -265,6 +265,18 @@ def check_binned(ipg, hg, Ts, hot=65536, rename=True, modes=("pull",)):
             err = max_rel(ipg.values_to_numpy(vals), ref.values)
             assert err <= PR_RTOL, f"T={T} {mode}: max rel err {err:.3e}"
             assert st.supersteps == T + 1 and np.array_equal(st.trace, ref.trace)
+    if min_apps:
+        # CC and SSSP over the binned in-edges of the caller's ids: every
+        # exchange, both loops, the sender gate on (default) and off
+        for app in ("cc", "sssp"):
+            ref = oracle.run_graph(app, hg, 0, weighted=False)
+            for mode in ("pull", "auto"):
+                for persistent in (False, True):
+                    for tuning in (None, {"gate_div": 0xFFFFFFFF}, {"gate_div": 1}):
+                        print(f"[binned] {hg.name} {app} {mode} persistent={persistent} tuning={tuning}", flush=True)
+                        vals, st = g.run(app, source=0, mode=mode, persistent=persistent, tuning=tuning)
+                        assert np.array_equal(ipg.values_to_numpy(vals), ref.values), (app, mode, persistent, tuning)
+                        assert np.array_equal(st.trace, ref.trace), (app, mode, persistent, tuning)
     return g
 
 
