@@ -7,7 +7,8 @@ GPU library):
   sources binned) and in the row-item form -- sampled ranks within 1e-12, the rank sum, the device-
   counted trace, and the mass balance of the GPU's own ranks between updates
   9 and 10 (Fig. 8 with dangling mass dropped);
-* its symmetrised form (2.10B edges > 2^31: the 64-bit edge paths): hash-min
+* its symmetrised form (2.10B edges > 2^31: the 64-bit edge paths), on the
+  benchmark's store (blocked in-edges, cold sources binned): hash-min
   CC and SSSP from vertex 0, SHA-256 of the whole u32 result and the trace,
   host- and device-driven loops, every exchange policy;
 * the 4096 x 4096 weighted grid with shortcuts: SSSP from vertex 0, both
@@ -114,8 +115,8 @@ def test_s26_pagerank(ipg, s26):
 def s26_sym(ipg, s26):
     _, s, _ = s26
     t = time.time()
-    g = ipg.Graph.from_host(s, blocked=True)
-    log(f"symmetrised store (blocked, {s.m} edges) created in {time.time() - t:.1f}s")
+    g = ipg.Graph.from_host(s, blocked=True, binned=True)
+    log(f"symmetrised store (blocked, binned, {s.m} edges) created in {time.time() - t:.1f}s")
     yield g
     g.close()
 
