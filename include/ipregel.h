@@ -160,6 +160,11 @@ typedef struct {
   uint32_t blocked;    /* pull exchanges on a store built with IPG_GRAPH_BLOCKED (PageRank, CC and SSSP
                           with unit weights): 0 (default) = use the blocked in-edges, UINT32_MAX = use
                           the row-item kernels instead */
+  uint32_t late_div;   /* CC/SSSP under IPG_MODE_AUTO, superstep >= 1: a superstep chosen as pull whose
+                          broadcasts, counted after its compute, carry at most E / late_div messages is
+                          exchanged by push instead -- the choice of Section 4.3.2 taken once the
+                          messages are known (default 20; UINT32_MAX = never).  Reported as a push
+                          superstep in the stats. */
 } ipg_tuning;
 
 typedef struct {

@@ -57,10 +57,11 @@ class _Desc(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("pr_hot", ctypes.c_uint32), ("pull_grid", ctypes.c_uint32), ("push_div", ctypes.c_uint32),
-                ("list_div", ctypes.c_uint32), ("gate_div", ctypes.c_uint32), ("blocked", ctypes.c_uint32)]
+                ("list_div", ctypes.c_uint32), ("gate_div", ctypes.c_uint32), ("blocked", ctypes.c_uint32),
+                ("late_div", ctypes.c_uint32)]
 
 
-TUNING_FIELDS = ("pr_hot", "pull_grid", "push_div", "list_div", "gate_div", "blocked")
+TUNING_FIELDS = ("pr_hot", "pull_grid", "push_div", "list_div", "gate_div", "blocked", "late_div")
 HOT_OFF = 0xFFFFFFFF
 
 

@@ -2,9 +2,9 @@
 
 For a graph and an application it times the runs of a small grid of
 candidate parameter sets (ipg_tuning: the PageRank LDS outbox cache size,
-the pull grid, the push/pull rule's divisor and the frontier-list limit; on a
-graph with blocked in-edges also the row-item form of PageRank's pull) and
-keeps the fastest.  The choice is cached in a JSON file under a key made of
+the pull grid, the push/pull rule's divisor, the frontier-list limit, the
+sender gate and the late push of CC/SSSP; on a graph with blocked in-edges
+also the row-item form of the pull) and keeps the fastest.  The choice is cached in a JSON file under a key made of
 the graph's signature -- vertex and edge counts, symmetry, weights, naming
 and a coarse profile of its out-degrees -- so a graph of the same shape is
 not tuned twice.  Parameters never change results beyond the PageRank
@@ -73,14 +73,18 @@ def candidates(graph, app: str) -> list:
     space = SPACES[app]
     names = sorted(space)
     out = [dict(zip(names, combo)) for combo in itertools.product(*(space[k] for k in names))]
+    # CC/SSSP: the late push at its default divisor and switched off
+    late = (0, 0xFFFFFFFF) if app in ("cc", "sssp") else ()
     if getattr(graph, "blocked", False):
         if app == "pagerank":
             out = [{"blocked": 0}] + [dict(t, blocked=0xFFFFFFFF) for t in out]
         elif app in ("cc", "sssp"):
-            # the blocked pull has no grid; the rule's divisors and the sender gate still matter
-            blk = [dict(zip(("list_div", "push_div", "gate_div"), c), blocked=0)
-                   for c in itertools.product(space["list_div"], space["push_div"], (0, 0xFFFFFFFF))]
+            # the blocked pull has no grid; the rule's divisors, the sender gate and the late push still matter
+            blk = [dict(zip(("list_div", "push_div", "gate_div", "late_div"), c), blocked=0)
+                   for c in itertools.product(space["list_div"], space["push_div"], (0, 0xFFFFFFFF), late)]
             out = blk + [dict(t, blocked=0xFFFFFFFF) for t in out]
+    elif late:
+        out = [dict(t, late_div=x) for t in out for x in late]
     return out
 
 

@@ -31,6 +31,7 @@ size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w) {
     r.sent = c.take<uint32_t>(nn / 64 * 2 + 2);
     r.gate = c.take<uint32_t>(1);
     r.lpre = c.take<uint32_t>(2 * (kCtrSlots + 1));
+    r.late = c.take<uint32_t>(1);
     r.pieces = c.take<Piece>(kCtrSlots * piece_seg(e));
     r.ctl = c.take<DevCtl>(1);
   }

@@ -30,7 +30,8 @@ inline PullTiling pull_tiling(const ipg_graph* g) { return make_tiling(g->csc_of
 // summed, and the selector's choice for the next superstep.
 struct Decision {
   unsigned long long next_count, senders, messages, next_deg;
-  uint32_t overflow;
+  uint16_t overflow;
+  uint16_t late;  // the superstep was chosen as pull and exchanged by push (pick_kernel)
   int32_t mode;   // IPG_MODE_PUSH / IPG_MODE_PULL from the selector, 0 if none ran
   double margin;  // predicted log2 time of push minus pull
   unsigned long long active;  // summed `active` counters (batched SSSP)
@@ -85,7 +86,7 @@ hipError_t host_mirror(ipg_graph* g, HostMirror** host, HostMirror** dev);
 // then incomplete) and, with `lpre_out`, writes the prefix of the
 // segments' lengths that the next superstep's list consumers read.
 hipError_t launch_decide(const CtrSlot* c, uint32_t next_superstep, uint64_t e, const double* sel, Decision* out,
-                         uint32_t lseg, uint32_t* lpre_out, hipStream_t s);
+                         uint32_t lseg, uint32_t* lpre_out, hipStream_t s, const uint32_t* late = nullptr);
 
 // Push exchange: a sender with at least kPieceMin out-edges is not expanded
 // by its own workgroup.  Its out-edges are cut into pieces of at most kPiece
@@ -153,6 +154,7 @@ struct RunWs {
   uint32_t* sent;       // [n/64*2 + 2] bitmap of the vertices that broadcast in a pull superstep
   uint32_t* gate;       // [1] 1 when that superstep's senders are few enough to gate the gathers
   uint32_t* lpre;       // [2][kCtrSlots + 1] prefix of the list segments' lengths, by superstep parity
+  uint32_t* late;       // [1] 1 when the pull superstep under way is exchanged by push (few messages)
   Piece* pieces;        // [kCtrSlots * piece_seg(e)] piece queue of a push superstep
   DevCtl* ctl;          // device-driven loop state
   // both
@@ -220,10 +222,11 @@ struct Tune {
   uint32_t list_div;
   uint32_t gate_div;  // pull gathers only senders' outboxes when senders < N / gate_div (0 = never)
   uint32_t blocked;  // pull exchanges use the blocked in-edges when the store has them
+  uint32_t late_div;  // AUTO: a pull superstep with messages <= E / late_div is exchanged by push instead (0 = never)
 };
 constexpr uint32_t kHotDefault = 8192;  // 64 KB of LDS; the launch also caps it to the LDS left by the tiles
 inline Tune resolve_tuning(const ipg_tuning* t) {
-  Tune r{kHotDefault, kPullGrid, 20, 16, 8, 1};
+  Tune r{kHotDefault, kPullGrid, 20, 16, 8, 1, 20};
   if (t) {
     if (t->blocked) r.blocked = t->blocked == 0xFFFFFFFFu ? 0 : 1;
     if (t->gate_div) r.gate_div = t->gate_div == 0xFFFFFFFFu ? 0 : t->gate_div;
@@ -231,6 +234,7 @@ inline Tune resolve_tuning(const ipg_tuning* t) {
     if (t->pull_grid) r.pull_grid = t->pull_grid;
     if (t->push_div) r.push_div = t->push_div;
     if (t->list_div) r.list_div = t->list_div;
+    if (t->late_div) r.late_div = t->late_div == 0xFFFFFFFFu ? 0 : t->late_div;
   }
   return r;
 }

@@ -110,6 +110,7 @@ struct MinPushArgs {
   uint32_t n;
   Piece* pieces;        // piece queue (see kPieceMin), or null to expand every sender in place
   uint64_t piece_seg;
+  const uint32_t* late;  // a pull superstep's late push: runs only when *late (else null)
 };
 
 // Append the lanes' items with `pred` to the workgroup's segment of the
@@ -325,13 +326,16 @@ __device__ __forceinline__ void piece_body(const MinPushArgs& a, uint32_t grid, 
   }
   flush_counters(a.ctr, 0, 0, next_count, next_deg, overflow);
 }
+// With `late` set it belongs to the late push of a pull superstep (after
+// minprop_late_kernel) and runs only when that push was chosen.
 template <int APP, bool W>
 __global__ __launch_bounds__(kBlock) void minprop_piece_kernel(MinPushArgs a) {
   __shared__ uint32_t s_pre[kCtrSlots + 1];
   if (a.ctl) {
     const DevCtl c = *a.ctl;
-    if (c.halted || c.mode != IPG_MODE_PUSH) return;
+    if (c.halted || c.mode != (a.late ? IPG_MODE_PULL : IPG_MODE_PUSH)) return;
   }
+  if (a.late && !*a.late) return;  // uniform over the grid
   piece_body<APP, W>(a, gridDim.x, s_pre);
 }
 
@@ -456,14 +460,25 @@ __global__ __launch_bounds__(kBlock) void minprop_front_kernel(MinPushArgs p, Mi
   }
 }
 
-// Between the compute and the exchange of a pull superstep: whether so few
-// vertices broadcast that the gather should consult the sender bitmap first
-// (senders < N / div).  One wavefront sums the counter slots.
-__global__ __launch_bounds__(kWave) void gate_kernel(const CtrSlot* c, uint32_t n, uint32_t div, const DevCtl* ctl,
-                                                     uint32_t* gate) {
+// Between the compute and the exchange of a pull superstep, once the
+// broadcasts are counted (one wavefront sums the counter slots):
+// - whether so few vertices broadcast that the gather should consult the
+//   sender bitmap first (senders < N / gate_div; `gate`, when given);
+// - whether their messages are so few (<= E / late_div) that the exchange is
+//   done by push instead (`late`, when given): the push/pull choice of
+//   Section 4.3.2 taken on the messages themselves rather than on the active
+//   set before the compute, which overestimates them when most active
+//   vertices do not improve.
+__global__ __launch_bounds__(kWave) void pick_kernel(const CtrSlot* c, uint32_t n, uint64_t e, uint32_t gate_div,
+                                                     uint32_t late_div, const DevCtl* ctl, uint32_t* gate,
+                                                     uint32_t* late) {
   if (ctl && (ctl->halted || ctl->mode != IPG_MODE_PULL)) return;
   const uint64_t se = wave_sum_u64(c[threadIdx.x].senders);
-  if (threadIdx.x == 0) *gate = (div && se < n / div) ? 1u : 0u;
+  const uint64_t me = wave_sum_u64(c[threadIdx.x].messages);
+  if (threadIdx.x == 0) {
+    if (gate) *gate = (gate_div && se < n / gate_div) ? 1u : 0u;
+    if (late) *late = (late_div && me <= e / late_div) ? 1u : 0u;
+  }
 }
 
 struct MinPullArgs {
@@ -477,6 +492,7 @@ struct MinPullArgs {
   const DevCtl* ctl;       // device-driven loop: run only when it chose pull (else null)
   const uint32_t* sent;    // bitmap of the senders, read when *gate is set
   const uint32_t* gate;    // or null: gather every outbox
+  const uint32_t* late;    // the superstep is exchanged by push instead when *late (or null)
 };
 
 // The message an in-edge carries: the source's broadcast value o (CC), plus
@@ -508,7 +524,8 @@ __global__ __launch_bounds__(kBlock) void minprop_pull_kernel(MinPullArgs a) {
   __shared__ uint32_t s_tile[kWavesPerBlock][kWaveTile];
   __shared__ uint32_t s_off[kWavesPerBlock][kItemRows + 1];
   if (a.ctl && (a.ctl->halted || a.ctl->mode != IPG_MODE_PULL)) return;  // uniform over the grid
-  const uint32_t* sent = (a.gate && *a.gate) ? a.sent : nullptr;          // uniform as well
+  if (a.late && *a.late) return;                                          // uniform as well
+  const uint32_t* sent = (a.gate && *a.gate) ? a.sent : nullptr;
   clear_slots(a.ctr_clear);
   const uint32_t wv = threadIdx.x / kWave, lane = lane_id();
   uint32_t* tile = s_tile[wv];
@@ -585,6 +602,57 @@ __global__ __launch_bounds__(kBlock) void minprop_pull_kernel(MinPullArgs a) {
   flush_counters(a.ctr, 0, 0, next_count, next_deg, overflow);
 }
 
+// Late push of a pull superstep (pick_kernel set *late): the
+// compute already ran over every vertex and left each broadcast value in the
+// outbox (INF for a vertex that does not broadcast), so the senders are
+// found by sweeping the outbox, and each one's message goes along its
+// out-edges as in push_body (pieces for long rows, the other rows expanded
+// by twc_scatter, recipients appended to the next-frontier list).  The
+// senders and their messages were counted by the compute.
+template <int APP, bool W>
+__global__ __launch_bounds__(kBlock) void minprop_late_kernel(MinPushArgs a, const uint32_t* outbox) {
+  if (a.ctl && (a.ctl->halted || a.ctl->mode != IPG_MODE_PULL)) return;  // uniform over the grid
+  if (!*a.late) return;
+  clear_slots(a.ctr_clear);
+  uint64_t next_count = 0, next_deg = 0;
+  uint32_t overflow = 0;
+  // four outbox entries per thread (16-byte loads; the outbox is 256-byte
+  // aligned); a round in which no vertex of the workgroup broadcasts skips
+  // the expansion and its barriers
+  const uint64_t nq = (static_cast<uint64_t>(a.n) + 3) / 4;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kBlock;
+  for (uint64_t qb = blockIdx.x * static_cast<uint64_t>(kBlock); qb < nq; qb += stride) {  // uniform rounds
+    const uint64_t q = qb + threadIdx.x;
+    uint32_t m[4] = {kInf, kInf, kInf, kInf};
+    if (4 * q + 3 < a.n) {
+      const uint4 x = reinterpret_cast<const uint4*>(outbox)[q];
+      m[0] = x.x;
+      m[1] = x.y;
+      m[2] = x.z;
+      m[3] = x.w;
+    } else {
+      for (uint32_t k = 0; k < 4; ++k)
+        if (4 * q + k < a.n) m[k] = outbox[4 * q + k];
+    }
+    if (!__syncthreads_or((m[0] & m[1] & m[2] & m[3]) != kInf)) continue;  // uniform
+#pragma unroll 1
+    for (uint32_t k = 0; k < 4; ++k) {
+      const uint64_t v = 4 * q + k;
+      bool has = m[k] != kInf;
+      uint64_t beg = 0, end = 0;
+      if (has) {
+        beg = a.off[v];
+        end = a.off[v + 1];
+      }
+      if (a.pieces) has = queue_pieces(a, has, beg, end, m[k]);
+      twc_scatter(has, beg, end, m[k], [&](uint64_t e, uint32_t p) {
+        push_edge<APP, W>(a, e, p, next_count, next_deg, overflow);
+      });
+    }
+  }
+  flush_counters(a.ctr, 0, 0, next_count, next_deg, overflow);
+}
+
 // Blocked pull (IPG_GRAPH_BLOCKED, CC and SSSP with unit weights): the
 // blocked in-edges of the caller's CSC streamed through one workgroup per
 // slice (blocked.h), each message min-combined into its destination's LDS
@@ -600,14 +668,20 @@ struct MinBlkArgs {
   const uint32_t* sent;  // bitmap of the senders, consulted when *gate is set (gate null: never)
   const uint32_t* gate;
   const uint32_t* slots;  // binned cold sources' outboxes (INF: did not broadcast), one per (block, source)
+  const uint32_t* late;   // the superstep is exchanged by push instead when *late (or null)
 };
+// Whether the blocked pull's launches run in this superstep (uniform over the grid).
+__device__ __forceinline__ bool blk_pulls(const MinBlkArgs& a) {
+  if (a.ctl && (a.ctl->halted || a.ctl->mode != IPG_MODE_PULL)) return false;
+  return !(a.late && *a.late);
+}
 
 // Bin launch of a binned layout (IPG_GRAPH_BINNED): every cold source's
 // outbox (INF when it did not broadcast) copied into its slots (bin_unit).
 // The window's outboxes are read as one coalesced block, so the senders'
 // bitmap would only add a dependent load: the gate is not consulted.
 __global__ __launch_bounds__(kBlkThreads) void min_bin_kernel(MinBlkArgs a, BinTables bv, uint32_t* slots, uint32_t n) {
-  if (a.ctl && (a.ctl->halted || a.ctl->mode != IPG_MODE_PULL)) return;  // uniform over the grid
+  if (!blk_pulls(a)) return;
   const uint32_t* outbox = a.outbox;
   bin_unit<uint32_t>(bv, slots, n, [&](uint32_t u) { return outbox[u]; });
 }
@@ -644,7 +718,7 @@ __device__ __forceinline__ void flush_next_counters(CtrSlot* base, uint64_t next
 template <int APP>
 __global__ __launch_bounds__(kBlkThreads) void minprop_blocked_kernel(MinBlkArgs a) {
   __shared__ uint32_t part[kBlkRows + kWave];  // + one pad slot per lane (see blk_stream)
-  if (a.ctl && (a.ctl->halted || a.ctl->mode != IPG_MODE_PULL)) return;  // uniform over the grid
+  if (!blk_pulls(a)) return;
   clear_slots(a.ctr_clear);
   const BlkSlice sl = a.v.slices[blockIdx.x];
   for (uint32_t r = threadIdx.x; r < sl.rows; r += kBlkThreads) part[r] = kInf;
@@ -720,21 +794,23 @@ __device__ __forceinline__ void blocked_finish_body(const MinBlkArgs& a, uint32_
   flush_counters(a.ctr, 0, 0, next_count, next_deg, 0);
 }
 __global__ __launch_bounds__(kBlock) void minprop_blocked_finish_kernel(MinBlkArgs a) {
-  if (a.ctl && (a.ctl->halted || a.ctl->mode != IPG_MODE_PULL)) return;
+  if (!blk_pulls(a)) return;
   blocked_finish_body(a, gridDim.x);
 }
 
 // Last launch of a device-driven superstep s >= 1 over blocked in-edges:
-// the piece launch's work when the control block chose push, the blocked
-// pull's second launch when it chose pull (one launch where there were
-// two).  Each part runs on its own grid; the workgroups beyond it return.
+// the piece launch's work when the control block chose push (or the pull
+// superstep turned to a late push), the blocked pull's second launch when
+// it pulls (one launch where there were two).  Each part runs on its own
+// grid; the workgroups beyond it return.
 template <int APP, bool W>
 __global__ __launch_bounds__(kBlock) void minprop_back_kernel(MinPushArgs p, MinBlkArgs b, uint32_t piece_grid,
                                                               uint32_t finish_grid) {
   __shared__ uint32_t s_pre[kCtrSlots + 1];
   const DevCtl c = *p.ctl;
   if (c.halted) return;  // uniform over the grid
-  if (c.mode == IPG_MODE_PUSH) {
+  const bool late = c.mode == IPG_MODE_PULL && b.late && *b.late;
+  if (c.mode == IPG_MODE_PUSH || late) {
     if (blockIdx.x < piece_grid) piece_body<APP, W>(p, piece_grid, s_pre);
   } else if (c.mode == IPG_MODE_PULL) {
     if (blockIdx.x < finish_grid) blocked_finish_body(b, finish_grid);
@@ -766,7 +842,8 @@ __device__ __forceinline__ uint64_t list_summary(const CtrSlot& x, uint32_t lseg
 }
 
 __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_t next_superstep, uint64_t e,
-                                                       const double* sel, Decision* out, uint32_t lseg, uint32_t* lpre_out) {
+                                                       const double* sel, Decision* out, uint32_t lseg, uint32_t* lpre_out,
+                                                       const uint32_t* late) {
   static_assert(kCtrSlots == kWave, "one slot per lane");
   const CtrSlot& x = c[threadIdx.x];
   const uint64_t nc = wave_sum_u64(x.next_count);
@@ -786,6 +863,7 @@ __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_
     d.messages = me;
     d.next_deg = nd;
     d.overflow = ovf ? 1u : 0u;
+    d.late = late && *late ? 1u : 0u;
     d.mode = m;
     d.margin = margin;
     d.active = ac;
@@ -830,7 +908,7 @@ __global__ __launch_bounds__(kWave) void dd_start_kernel(DevCtl* ctl, int app, u
 __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint32_t lseg, uint32_t* lpre_out, uint64_t e,
                                                           uint32_t n, const double* sel, int forced,
                                                           uint64_t list_limit, uint32_t push_div, DevCtl* ctl,
-                                                          HostMirror* hm) {
+                                                          HostMirror* hm, const uint32_t* late) {
   static_assert(kCtrSlots == kWave, "one slot per lane");
   const unsigned long long now = static_cast<unsigned long long>(wall_clock64());
   const DevCtl k = *ctl;
@@ -846,6 +924,8 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
   if (k.halted) return;
   const uint64_t lcount = list_summary(x, lseg, lpre_out);  // ~0: a segment overflowed, no list
   const uint32_t s = k.step;
+  // the exchange that ran: a pull superstep turned to a late push counts as a push
+  const int ran = (k.mode == IPG_MODE_PULL && late && *late) ? IPG_MODE_PUSH : k.mode;
   int sel_mode = IPG_MODE_PUSH;
   if (sel && !forced && nc && !ovf && !(k.cap && s + 1 >= k.cap))  // uniform: the whole wavefront infers
     sel_predict_mode_wave(sel, nc, nd, s + 1, e, &sel_mode);
@@ -854,10 +934,10 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
   r.active = s == 0 ? n : k.count;
   r.senders = se;
   r.messages = me;
-  r.examined = k.mode == IPG_MODE_PUSH ? me : e;
+  r.examined = ran == IPG_MODE_PUSH ? me : e;
   r.frontier_deg = k.degsum;
   r.ticks = now - k.t_last;
-  r.mode = static_cast<uint32_t>(k.mode);
+  r.mode = static_cast<uint32_t>(ran);
   r.pad = 0;
   hm->rec[s % kDevRec] = r;
   DevCtl nk = k;
@@ -865,7 +945,7 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
   nk.t_last = now;
   nk.count = nc;
   nk.degsum = nd;
-  nk.list_ok = (k.mode == IPG_MODE_PUSH && nc <= list_limit && lcount != ~0ull) ? 1u : 0u;
+  nk.list_ok = (ran == IPG_MODE_PUSH && nc <= list_limit && lcount != ~0ull) ? 1u : 0u;
   if (ovf) {
     nk.halted = 1;
     nk.status = IPG_EOVERFLOW;
@@ -875,7 +955,7 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
   } else if (k.cap && s + 1 >= k.cap) {
     nk.halted = 1;
     nk.status = IPG_NOT_CONVERGED;
-  } else if (k.mode == IPG_MODE_PUSH && lcount != ~0ull && lcount != nc) {
+  } else if (ran == IPG_MODE_PUSH && lcount != ~0ull && lcount != nc) {
     nk.halted = 1;
     nk.status = IPG_EDEVICE;
   } else if (forced) {
@@ -892,8 +972,8 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
 // ------------------------------------------------------------------ host --
 
 hipError_t launch_decide(const CtrSlot* c, uint32_t next_superstep, uint64_t e, const double* sel, Decision* out,
-                         uint32_t lseg, uint32_t* lpre_out, hipStream_t s) {
-  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kWave), 0, s, c, next_superstep, e, sel, out, lseg, lpre_out);
+                         uint32_t lseg, uint32_t* lpre_out, hipStream_t s, const uint32_t* late) {
+  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kWave), 0, s, c, next_superstep, e, sel, out, lseg, lpre_out, late);
   return hipGetLastError();
 }
 
@@ -950,6 +1030,22 @@ static hipError_t push_dispatch(ipg_app app, bool weighted, const MinPushArgs& a
   if (app == IPG_APP_CC_HASHMIN) return launch_push<IPG_APP_CC_HASHMIN, false>(a, grid, pieces, s);
   return weighted ? launch_push<IPG_APP_SSSP, true>(a, grid, pieces, s)
                   : launch_push<IPG_APP_SSSP, false>(a, grid, pieces, s);
+}
+// The late push of a device-driven pull superstep and, unless the back
+// launch will run them, its pieces (both return at once unless *a.late).
+template <int APP, bool W>
+static hipError_t launch_late(const MinPushArgs& a, const uint32_t* outbox, bool pieces, hipStream_t s) {
+  hipLaunchKernelGGL((minprop_late_kernel<APP, W>), dim3(kExchangeGrid), dim3(kBlock), 0, s, a, outbox);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess || !pieces) return err;
+  hipLaunchKernelGGL((minprop_piece_kernel<APP, W>), dim3(kPieceGrid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+static hipError_t late_dispatch(ipg_app app, bool weighted, const MinPushArgs& a, const uint32_t* outbox, bool pieces,
+                                hipStream_t s) {
+  if (app == IPG_APP_CC_HASHMIN) return launch_late<IPG_APP_CC_HASHMIN, false>(a, outbox, pieces, s);
+  return weighted ? launch_late<IPG_APP_SSSP, true>(a, outbox, pieces, s)
+                  : launch_late<IPG_APP_SSSP, false>(a, outbox, pieces, s);
 }
 static hipError_t pull_dispatch(ipg_app app, bool weighted, const MinPullArgs& a, uint32_t grid, hipStream_t s) {
   if (app == IPG_APP_CC_HASHMIN) return launch_pull<IPG_APP_CC_HASHMIN, false>(a, grid, s);
@@ -1009,13 +1105,17 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
   const bool back = device && bt && bt->ngroups;
   MinPushArgs front_push{};
   uint32_t front_push_grid = 0;
+  // pull superstep s >= 1 that may turn to a push once its messages are
+  // counted (pick_kernel); the caller zeroes late_div when the exchange is
+  // forced
+  const bool late_on = step > 0 && tn.late_div != 0 && (device || mode == IPG_MODE_PULL);
   if (step == 0) {
     hipLaunchKernelGGL(minprop_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, static_cast<int>(app), source,
                        w.value_u32, g->t.outdeg, mode == IPG_MODE_PULL ? 1 : 0, w.outbox, b.c, ctl,
                        device ? w.mail_a : nullptr, device ? w.mail_b : nullptr);
     IPG_HIP(hipGetLastError());
   }
-  if (device || mode == IPG_MODE_PUSH) {
+  if (device || mode == IPG_MODE_PUSH || late_on) {
     MinPushArgs a;
     a.act = act;
     a.act.list = b.fin;
@@ -1037,13 +1137,14 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
     // piece queue and launch: always in the device-driven loop (the launch
     // returns at once without pieces), else when the frontier's out-degrees
     // could make one
-    const bool pieces = device || degsum >= kPieceMin;
+    const bool pieces = device || late_on || degsum >= kPieceMin;
     a.pieces = pieces ? w.pieces : nullptr;
     a.piece_seg = piece_seg(g->e);
+    a.late = nullptr;
     const uint32_t grid = device ? kExchangeGrid : grid_for(act.count, kBlock, 0xFFFFFFFFu);
     front_push = a;
     front_push_grid = grid;
-    if (!front) IPG_HIP(push_dispatch(app, weighted, a, grid, !back, s));
+    if (!front && (device || mode == IPG_MODE_PUSH)) IPG_HIP(push_dispatch(app, weighted, a, grid, !back, s));
   }
   if (device || mode == IPG_MODE_PULL) {
     const bool gating = step > 0 && tn.gate_div != 0;
@@ -1077,11 +1178,14 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
         hipLaunchKernelGGL(minprop_apply_kernel, dim3(grid), dim3(kBlock), 0, s, ap);
         IPG_HIP(hipGetLastError());
       }
-      if (gating) {
-        hipLaunchKernelGGL(gate_kernel, dim3(1), dim3(kWave), 0, s, b.c, n, tn.gate_div, ctl, w.gate);
+      if (gating || late_on) {
+        hipLaunchKernelGGL(pick_kernel, dim3(1), dim3(kWave), 0, s, b.c, n, g->e, gating ? tn.gate_div : 0u,
+                           late_on ? tn.late_div : 0u, ctl, gating ? w.gate : nullptr, late_on ? w.late : nullptr);
         IPG_HIP(hipGetLastError());
       }
     }
+    MinPushArgs late_push = front_push;
+    late_push.late = w.late;
     if (bt) {
       MinBlkArgs ba;
       ba.v = blk_view(*bt);
@@ -1096,6 +1200,7 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
       // of outboxes): the senders' bitmap would only add a dependent load
       ba.gate = gating && !bt->hot ? w.gate : nullptr;
       ba.slots = bt->hot ? reinterpret_cast<const uint32_t*>(bt->slots) : nullptr;
+      ba.late = late_on ? w.late : nullptr;
       if (bt->hot && bt->bin_nunits) {
         hipLaunchKernelGGL(min_bin_kernel, dim3(bt->bin_nunits), dim3(kBlkThreads), 0, s, ba, bin_tables(*bt),
                            reinterpret_cast<uint32_t*>(bt->slots), n);
@@ -1110,6 +1215,7 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
       } else {  // no edges: nothing arrives, but the next superstep's counters are still cleared here
         IPG_HIP(fill_u32(reinterpret_cast<uint32_t*>(b.cc), kCtrSlots * sizeof(CtrSlot) / 4, 0, s));
       }
+      if (late_on) IPG_HIP(late_dispatch(app, weighted, late_push, w.outbox, !back, s));
       if (back) {
         IPG_HIP(back_dispatch(app, weighted, front_push, ba, grid_for(bt->ngroups, kWavesPerBlock, 4096), s));
       } else if (bt->ngroups) {
@@ -1130,7 +1236,9 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
     pa.ctl = ctl;
     pa.sent = w.sent;
     pa.gate = gating ? w.gate : nullptr;
+    pa.late = late_on ? w.late : nullptr;
     IPG_HIP(pull_dispatch(app, weighted, pa, tn.pull_grid, s));
+    if (late_on) IPG_HIP(late_dispatch(app, weighted, late_push, w.outbox, true, s));
   }
   return IPG_OK;
 }
@@ -1206,7 +1314,7 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
                                      hipStream_t s, StepTimer& tm, ipg_run_stats* st) {
   const uint32_t n = g->n;
   const uint64_t e = g->e;
-  const Tune tn = resolve_tuning(o.tuning);
+  Tune tn = resolve_tuning(o.tuning);
   HostMirror *hm = nullptr, *hm_dev = nullptr;
   IPG_HIP(host_mirror(g, &hm, &hm_dev));
   ipg_status rc = IPG_OK;
@@ -1214,6 +1322,7 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
   const double us_per_tick = g->wall_khz > 0 ? 1e3 / g->wall_khz : 0.0;
   const double* sel = o.mode == IPG_MODE_AUTO ? o.selector : nullptr;
   const int forced = o.mode == IPG_MODE_AUTO ? 0 : static_cast<int>(o.mode);
+  if (forced) tn.late_div = 0;  // a forced exchange stays as forced
   IPG_HIP(tm.start(s));
   // the counters are zeroed by dd_start_kernel and the mailboxes emptied by
   // superstep 0's init kernel, so the run starts with no clearing launch
@@ -1242,7 +1351,8 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
       }
       const StepBufs b = bufs_for(w, step);
       hipLaunchKernelGGL(dd_decide_kernel, dim3(1), dim3(kWave), 0, s, b.c, list_seg(n), b.lpre_out, e, n, sel, forced,
-                         list_limit(n, tn.list_div), tn.push_div, w.ctl, hm_dev);
+                         list_limit(n, tn.list_div), tn.push_div, w.ctl, hm_dev,
+                         step > 0 && tn.late_div ? static_cast<const uint32_t*>(w.late) : nullptr);
       IPG_HIP(hipGetLastError());
     }
     enqueued += chunk;
@@ -1285,7 +1395,8 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
   if (o.flags & IPG_RUN_PERSISTENT) return run_minprop_device(g, app, cap, o, w, s, tm, st);
   const uint32_t n = g->n;
   const uint64_t e = g->e;
-  const Tune tn = resolve_tuning(o.tuning);
+  Tune tn = resolve_tuning(o.tuning);
+  if (o.mode != IPG_MODE_AUTO) tn.late_div = 0;  // a forced exchange stays as forced
   HostMirror *hm = nullptr, *hm_dev = nullptr;
   IPG_HIP(host_mirror(g, &hm, &hm_dev));
   MinStart m0;
@@ -1315,17 +1426,20 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
     if (status != IPG_OK) return status;
     IPG_HIP(tm.step(s, step));
     const double* sel = o.mode == IPG_MODE_AUTO ? o.selector : nullptr;
-    IPG_HIP(launch_decide(b.c, step + 1, e, sel, &hm_dev->decision, list_seg(n), b.lpre_out, s));
+    const bool late_on = step > 0 && mode == IPG_MODE_PULL && tn.late_div != 0;
+    IPG_HIP(launch_decide(b.c, step + 1, e, sel, &hm_dev->decision, list_seg(n), b.lpre_out, s,
+                          late_on ? w.late : nullptr));
     IPG_HIP(hipStreamSynchronize(s));
     const Decision h = hm->decision;
     const uint64_t lcount = h.list_len;  // ~0: a segment overflowed, no list
-    const uint64_t examined = mode == IPG_MODE_PUSH ? h.messages : e;
+    const ipg_mode ran = h.late ? IPG_MODE_PUSH : mode;  // a late push counts as a push
+    const uint64_t examined = ran == IPG_MODE_PUSH ? h.messages : e;
     if (st && step < st->trace_cap) {
       if (st->active) st->active[step] = step == 0 ? n : count;
       if (st->senders) st->senders[step] = h.senders;
       if (st->messages) st->messages[step] = h.messages;
       if (st->examined) st->examined[step] = examined;
-      if (st->mode) st->mode[step] = static_cast<uint8_t>(mode);
+      if (st->mode) st->mode[step] = static_cast<uint8_t>(ran);
       if (st->frontier_deg) st->frontier_deg[step] = degsum;
     }
     tot_msgs += h.messages;
@@ -1340,14 +1454,14 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
       status = IPG_NOT_CONVERGED;
       break;
     }
-    if (mode == IPG_MODE_PUSH && lcount != ~0ull && lcount != h.next_count) {
+    if (ran == IPG_MODE_PUSH && lcount != ~0ull && lcount != h.next_count) {
       status = fail(IPG_EDEVICE, "frontier list length disagrees with the mailbox count");
       break;
     }
     count = h.next_count;
     degsum = h.next_deg;
     next_sel_mode = h.mode;
-    list_ok = mode == IPG_MODE_PUSH && count <= list_limit(n, tn.list_div) && lcount != ~0ull;
+    list_ok = ran == IPG_MODE_PUSH && count <= list_limit(n, tn.list_div) && lcount != ~0ull;
   }
   IPG_HIP(tm.finish(s));
   if (st) {
