@@ -283,9 +283,9 @@ def bench_workload(name, args, sel, ipg, np, torch, steps, warmup, apps, tune_ca
 
     # The same CC/SSSP runs (outside the timed region) with the exchange
     # picked by the fixed rule instead of the trained network: at the rule's
-    # documented divisor (pull when frontier + out-edges > E/20, the plain
-    # method) and at the divisor the autotuner picked; other launch
-    # parameters as tuned.
+    # documented divisors (pull when frontier + out-edges > E/20, lists up to
+    # N/16: the plain method) and at the divisors the autotuner picked;
+    # other launch parameters as tuned.
     learned_vs_plain = None
     if sel is not None:
         learned_vs_plain = {}
@@ -294,6 +294,7 @@ def bench_workload(name, args, sel, ipg, np, torch, steps, warmup, apps, tune_ca
                 continue
             t_plain = dict(tun[app] or {})
             t_plain["push_div"] = 20
+            t_plain["list_div"] = 16
 
             def med(t):
                 return float(np.median([run(app, selector=None, tuning=t)[1].seconds for _ in range(max(3, steps))]))
@@ -303,7 +304,10 @@ def bench_workload(name, args, sel, ipg, np, torch, steps, warmup, apps, tune_ca
             learned_vs_plain[app] = {"learned_ms": round(mine * 1e3, 4), "plain_ms": round(plain * 1e3, 4),
                                      "speedup": round(plain / mine, 4),
                                      "tuned_rule_ms": round(rule * 1e3, 4), "speedup_vs_tuned_rule": round(rule / mine, 4),
-                                     "learned_beats_tuned_rule": bool(mine < rule)}
+                                     "learned_beats_tuned_rule": bool(mine < rule),
+                                     "note": (f"the trained network is {rule / mine:.3f}x the autotuned rule: "
+                                              + ("not faster" if mine >= rule else "faster")
+                                              + f"; {plain / mine:.3f}x the plain E/20 rule")}
 
     roofline = None
     if "pagerank" in apps and T >= 1:

@@ -153,7 +153,9 @@ typedef struct {
                           UINT32_MAX = no cache) */
   uint32_t pull_grid;  /* workgroups of the pull item kernels (default 2048) */
   uint32_t push_div;   /* fixed exchange rule: pull when frontier + its out-edges > E / push_div (default 20) */
-  uint32_t list_div;   /* push frontiers up to max(4096, N / list_div) are visited as a list (default 16) */
+  uint32_t list_div;   /* push frontiers up to max(4096, N / list_div) are visited as a list (default 16;
+                          UINT32_MAX = never); a push chosen by a trained selector takes the list
+                          variant it predicts faster instead */
   uint32_t gate_div;   /* CC/SSSP pull: when fewer than N / gate_div vertices broadcast, the gather reads
                           a bitmap of the senders first and skips the others' outboxes (default 8;
                           UINT32_MAX = never) */
@@ -333,15 +335,20 @@ ipg_status ipg_multi_sssp_result(const ipg_graph* graph, const void* workspace, 
 /*
  * Learned exchange selector (an extension of Section 4.3.2, where the push /
  * pull choice is a compile-time flag set by the user's experiments).
- * A 4-16-16-2 tanh MLP in FP64 predicts log2 of the time of a push and of a
- * pull superstep from log2(1+|F|)/32, log2(1+sum of out-degrees of F)/32,
- * min(superstep,128)/64 and log2(1+E)/32; AUTO runs the smaller prediction.
- * Parameters are packed W1[16][4], b1[16], W2[16][16], b2[16], W3[2][16], b3[2].
- * All arrays are DEVICE memory owned by the caller; x is [n][4], y and t [n][2].
+ * A 4-16-16-3 tanh MLP in FP64 predicts log2 of the time of a superstep's
+ * exchange variants -- [0] a push that visits the frontier as a list, [1] a
+ * push that sweeps every vertex's mailbox, [2] a pull -- from
+ * log2(1+|F|)/32, log2(1+sum of out-degrees of F)/32, min(superstep,128)/64
+ * and log2(1+E)/32.  AUTO runs the variant of the smallest prediction among
+ * those available (the list only after a push that left a complete one); it
+ * replaces the push_div rule and, for the pushes it chooses, the list_div
+ * limit.  Parameters are packed W1[16][4], b1[16], W2[16][16], b2[16],
+ * W3[3][16], b3[3].  All arrays are DEVICE memory owned by the caller; x is
+ * [n][4], y and t [n][3].
  */
-#define IPG_SELECTOR_PARAMS 386
+#define IPG_SELECTOR_PARAMS 403
 #define IPG_SELECTOR_INPUTS 4
-#define IPG_SELECTOR_OUTPUTS 2
+#define IPG_SELECTOR_OUTPUTS 3
 
 /* Workspace bytes for ipg_selector_grad / ipg_selector_train on n samples. */
 size_t ipg_selector_workspace_bytes(uint32_t n_samples);
@@ -360,8 +367,8 @@ ipg_status ipg_selector_train(double* params, const double* x, const double* t, 
  * serving or training loops, harnesses that forbid allocation).  The same
  * kernel as ipg_selector_train, with the same result bit for bit; its
  * gradient and batch scratch live in a static device array of the library,
- * 8 * (IPG_SELECTOR_PARAMS + 66 * IPG_SELECTOR_NOALLOC_MAX_SAMPLES) bytes
- * (8.7 MB), one copy per GPU, held from the first call on that GPU until the
+ * 8 * (IPG_SELECTOR_PARAMS + 67 * IPG_SELECTOR_NOALLOC_MAX_SAMPLES) bytes
+ * (8.8 MB), one copy per GPU, held from the first call on that GPU until the
  * process ends.  The call allocates nothing: no hipMalloc, no hipFree, no
  * allocating library routine.  params, x and t are DEVICE memory of the
  * caller, as for ipg_selector_train.  n > IPG_SELECTOR_NOALLOC_MAX_SAMPLES

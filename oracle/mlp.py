@@ -9,15 +9,16 @@ Network (parameters packed in this order, row-major):
     h2 = tanh(W2 h1 + b2)     W2: [H, H], b2: [H]
     y  = W3 h2 + b3           W3: [K, H], b3: [K]
 Loss over a batch of n samples: L = (1 / (2n)) * sum_i sum_k (y_ik - t_ik)^2
-(the targets are per-exchange-variant log-times; the selector picks the
-variant with the smallest prediction).
+(the targets are per-exchange-variant log-times -- a push over the frontier
+list, a push sweeping every vertex, a pull; the selector picks the variant
+with the smallest prediction among those available).
 SGD step: p <- p - lr * dL/dp.
 """
 from __future__ import annotations
 
 import numpy as np
 
-D, H, K = 4, 16, 2
+D, H, K = 4, 16, 3
 
 
 def n_params(d: int = D, h: int = H, k: int = K) -> int:

@@ -446,7 +446,7 @@ class Graph:
 
 # ------------------------------------------------------------ selector ----
 
-SELECTOR_PARAMS, SELECTOR_INPUTS, SELECTOR_OUTPUTS = 386, 4, 2
+SELECTOR_PARAMS, SELECTOR_INPUTS, SELECTOR_OUTPUTS = 403, 4, 3
 
 
 def _check_selector(p):

@@ -31,7 +31,8 @@ inline PullTiling pull_tiling(const ipg_graph* g) { return make_tiling(g->csc_of
 struct Decision {
   unsigned long long next_count, senders, messages, next_deg;
   uint16_t overflow;
-  uint16_t late;  // the superstep was chosen as pull and exchanged by push (pick_kernel)
+  uint8_t late;   // the superstep was chosen as pull and exchanged by push (pick_kernel)
+  uint8_t list;   // the selector's push for the next superstep visits the frontier list
   int32_t mode;   // IPG_MODE_PUSH / IPG_MODE_PULL from the selector, 0 if none ran
   double margin;  // predicted log2 time of push minus pull
   unsigned long long active;  // summed `active` counters (batched SSSP)
@@ -86,7 +87,8 @@ hipError_t host_mirror(ipg_graph* g, HostMirror** host, HostMirror** dev);
 // then incomplete) and, with `lpre_out`, writes the prefix of the
 // segments' lengths that the next superstep's list consumers read.
 hipError_t launch_decide(const CtrSlot* c, uint32_t next_superstep, uint64_t e, const double* sel, Decision* out,
-                         uint32_t lseg, uint32_t* lpre_out, hipStream_t s, const uint32_t* late = nullptr);
+                         uint32_t lseg, uint32_t* lpre_out, hipStream_t s, const uint32_t* late = nullptr,
+                         int mode = 0);
 
 // Push exchange: a sender with at least kPieceMin out-edges is not expanded
 // by its own workgroup.  Its out-edges are cut into pieces of at most kPiece

@@ -843,7 +843,7 @@ __device__ __forceinline__ uint64_t list_summary(const CtrSlot& x, uint32_t lseg
 
 __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_t next_superstep, uint64_t e,
                                                        const double* sel, Decision* out, uint32_t lseg, uint32_t* lpre_out,
-                                                       const uint32_t* late) {
+                                                       const uint32_t* late, int mode) {
   static_assert(kCtrSlots == kWave, "one slot per lane");
   const CtrSlot& x = c[threadIdx.x];
   const uint64_t nc = wave_sum_u64(x.next_count);
@@ -853,9 +853,14 @@ __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_
   const uint64_t ac = wave_sum_u64(x.active);
   const bool ovf = __ballot(x.overflow != 0) != 0;
   const uint64_t ll = list_summary(x, lseg, lpre_out);
+  const bool lt = late && *late;
+  // the next superstep can visit a list when this one pushed (`mode`, or a
+  // late push) and every list segment held its entries
+  const bool list_avail = (mode == IPG_MODE_PUSH || lt) && ll != ~0ull;
   int m = 0;
+  bool ul = false;
   double margin = 0.0;
-  if (sel && nc) margin = sel_predict_mode_wave(sel, nc, nd, next_superstep, e, &m);  // whole wavefront
+  if (sel && nc) margin = sel_predict_mode_wave(sel, nc, nd, next_superstep, e, list_avail, &m, &ul);  // whole wavefront
   if (threadIdx.x == 0) {
     Decision d;
     d.next_count = nc;
@@ -863,7 +868,8 @@ __global__ __launch_bounds__(kWave) void decide_kernel(const CtrSlot* c, uint32_
     d.messages = me;
     d.next_deg = nd;
     d.overflow = ovf ? 1u : 0u;
-    d.late = late && *late ? 1u : 0u;
+    d.late = lt ? 1u : 0u;
+    d.list = ul ? 1u : 0u;
     d.mode = m;
     d.margin = margin;
     d.active = ac;
@@ -887,7 +893,8 @@ __global__ __launch_bounds__(kWave) void dd_start_kernel(DevCtl* ctl, int app, u
   const uint64_t count = cc ? n : 1;
   const uint64_t degsum = cc ? e : off[static_cast<uint64_t>(source) + 1] - off[source];
   int mode = forced;
-  if (!mode && sel) sel_predict_mode_wave(sel, count, degsum, 0, e, &mode);  // uniform: the whole wavefront infers
+  bool ul;
+  if (!mode && sel) sel_predict_mode_wave(sel, count, degsum, 0, e, false, &mode, &ul);  // uniform: the whole wavefront infers
   if (!mode) mode = heuristic_pick(e, count, degsum, push_div);
   if (threadIdx.x == 0) {
     DevCtl c{};
@@ -926,9 +933,13 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
   const uint32_t s = k.step;
   // the exchange that ran: a pull superstep turned to a late push counts as a push
   const int ran = (k.mode == IPG_MODE_PULL && late && *late) ? IPG_MODE_PUSH : k.mode;
+  // the next superstep can visit a list when this one pushed and every list segment held its entries
+  const bool list_avail = ran == IPG_MODE_PUSH && lcount != ~0ull;
   int sel_mode = IPG_MODE_PUSH;
-  if (sel && !forced && nc && !ovf && !(k.cap && s + 1 >= k.cap))  // uniform: the whole wavefront infers
-    sel_predict_mode_wave(sel, nc, nd, s + 1, e, &sel_mode);
+  bool sel_list = false;
+  const bool use_sel = sel && !forced && nc && !ovf && !(k.cap && s + 1 >= k.cap);
+  if (use_sel)  // uniform: the whole wavefront infers
+    sel_predict_mode_wave(sel, nc, nd, s + 1, e, list_avail, &sel_mode, &sel_list);
   if (threadIdx.x != 0) return;
   DevRec r;
   r.active = s == 0 ? n : k.count;
@@ -945,7 +956,9 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
   nk.t_last = now;
   nk.count = nc;
   nk.degsum = nd;
-  nk.list_ok = (ran == IPG_MODE_PUSH && nc <= list_limit && lcount != ~0ull) ? 1u : 0u;
+  // a push chosen by the selector visits the list when it predicted that
+  // variant faster; otherwise the list is visited up to the size limit
+  nk.list_ok = (list_avail && (use_sel && sel_mode == IPG_MODE_PUSH ? sel_list : nc <= list_limit)) ? 1u : 0u;
   if (ovf) {
     nk.halted = 1;
     nk.status = IPG_EOVERFLOW;
@@ -972,8 +985,9 @@ __global__ __launch_bounds__(kWave) void dd_decide_kernel(const CtrSlot* c, uint
 // ------------------------------------------------------------------ host --
 
 hipError_t launch_decide(const CtrSlot* c, uint32_t next_superstep, uint64_t e, const double* sel, Decision* out,
-                         uint32_t lseg, uint32_t* lpre_out, hipStream_t s, const uint32_t* late) {
-  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kWave), 0, s, c, next_superstep, e, sel, out, lseg, lpre_out, late);
+                         uint32_t lseg, uint32_t* lpre_out, hipStream_t s, const uint32_t* late, int mode) {
+  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kWave), 0, s, c, next_superstep, e, sel, out, lseg, lpre_out, late,
+                     mode);
   return hipGetLastError();
 }
 
@@ -1053,8 +1067,11 @@ static hipError_t pull_dispatch(ipg_app app, bool weighted, const MinPullArgs& a
 }
 
 // Frontier lists up to this size are visited through the list; larger ones
-// by sweeping the mailboxes.
-static uint64_t list_limit(uint32_t n, uint32_t div) { return std::max<uint64_t>(4096, n / (div ? div : 16)); }
+// by sweeping the mailboxes (div = UINT32_MAX: never through the list).
+static uint64_t list_limit(uint32_t n, uint32_t div) {
+  if (div == 0xFFFFFFFFu) return 0;
+  return std::max<uint64_t>(4096, n / (div ? div : 16));
+}
 
 // Ping-pong buffers of superstep `step`.
 struct StepBufs {
@@ -1289,7 +1306,8 @@ static ipg_status start_minprop(ipg_graph* g, ipg_app app, const ipg_run_opts& o
     double hp[kSelParams];
     IPG_HIP(hipMemcpyAsync(hp, o.selector, sizeof(hp), hipMemcpyDeviceToHost, s));
     IPG_HIP(hipStreamSynchronize(s));
-    sel_predict_mode(hp, out->count, out->degsum, 0, e, &out->sel_mode);
+    bool ul;
+    sel_predict_mode(hp, out->count, out->degsum, 0, e, false, &out->sel_mode, &ul);
   }
   return IPG_OK;
 }
@@ -1428,7 +1446,7 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
     const double* sel = o.mode == IPG_MODE_AUTO ? o.selector : nullptr;
     const bool late_on = step > 0 && mode == IPG_MODE_PULL && tn.late_div != 0;
     IPG_HIP(launch_decide(b.c, step + 1, e, sel, &hm_dev->decision, list_seg(n), b.lpre_out, s,
-                          late_on ? w.late : nullptr));
+                          late_on ? w.late : nullptr, static_cast<int>(mode)));
     IPG_HIP(hipStreamSynchronize(s));
     const Decision h = hm->decision;
     const uint64_t lcount = h.list_len;  // ~0: a segment overflowed, no list
@@ -1461,7 +1479,10 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
     count = h.next_count;
     degsum = h.next_deg;
     next_sel_mode = h.mode;
-    list_ok = ran == IPG_MODE_PUSH && count <= list_limit(n, tn.list_div) && lcount != ~0ull;
+    // as the device-driven loop decides it: a push chosen by the selector
+    // visits the list when it predicted that variant faster
+    const bool list_avail = ran == IPG_MODE_PUSH && lcount != ~0ull;
+    list_ok = list_avail && (h.mode == IPG_MODE_PUSH ? h.list != 0 : count <= list_limit(n, tn.list_div));
   }
   IPG_HIP(tm.finish(s));
   if (st) {

@@ -6,7 +6,9 @@
 
 namespace ipg {
 
-constexpr int kSelD = 4, kSelH = 16, kSelK = 2;
+constexpr int kSelD = 4, kSelH = 16, kSelK = 3;
+// Outputs: predicted log2 microseconds of the superstep's exchange variants.
+enum : int { kSelPushList = 0, kSelPushDense = 1, kSelPull = 2 };
 constexpr int kSelParams = kSelH * kSelD + kSelH + kSelH * kSelH + kSelH + kSelK * kSelH + kSelK;
 
 // Inputs of the network for one superstep.
@@ -42,22 +44,35 @@ __host__ __device__ inline void sel_forward1(const double* p, const double* x, d
   }
 }
 
+// The variant of the smallest prediction among those available: a push that
+// visits the frontier as a list (only when `list_ok`: the previous superstep
+// pushed and left a complete list), a push that sweeps every vertex's
+// mailbox, a pull.  Returns the predicted log2 time of the push minus that
+// of the pull; *use_list tells which push.
+__host__ __device__ inline double sel_pick(const double* y, bool list_ok, int* mode, bool* use_list) {
+  const bool list = list_ok && y[kSelPushList] <= y[kSelPushDense];
+  const double push = list ? y[kSelPushList] : y[kSelPushDense];
+  *mode = y[kSelPull] < push ? IPG_MODE_PULL : IPG_MODE_PUSH;
+  *use_list = list;
+  return push - y[kSelPull];
+}
+
 __host__ __device__ inline double sel_predict_mode(const double* p, uint64_t frontier, uint64_t frontier_deg, uint32_t superstep,
-                                   uint64_t e, int* mode) {
+                                   uint64_t e, bool list_ok, int* mode, bool* use_list) {
   double x[kSelD], h1[kSelH], h2[kSelH], y[kSelK];
   sel_features(frontier, frontier_deg, superstep, e, x);
   sel_forward1(p, x, h1, h2, y);
-  *mode = y[1] < y[0] ? IPG_MODE_PULL : IPG_MODE_PUSH;
-  return y[0] - y[1];
+  return sel_pick(y, list_ok, mode, use_list);
 }
 
 // The same prediction by a whole wavefront (every lane calls it and gets the
 // result): lane j < 16 computes hidden unit j of each layer, reading the
-// previous layer from the other lanes, and lanes 0 and 1 the two outputs.
+// previous layer from the other lanes, and lanes 0 .. kSelK-1 the outputs.
 // Every unit is summed in the order of sel_forward1, so the result is the
 // same; the latency is that of one unit per layer instead of all of them.
 __device__ inline double sel_predict_mode_wave(const double* p, uint64_t frontier, uint64_t frontier_deg,
-                                               uint32_t superstep, uint64_t e, int* mode) {
+                                               uint32_t superstep, uint64_t e, bool list_ok, int* mode,
+                                               bool* use_list) {
   const double* W1 = p;
   const double* b1 = W1 + kSelH * kSelD;
   const double* W2 = b1 + kSelH;
@@ -77,9 +92,9 @@ __device__ inline double sel_predict_mode_wave(const double* p, uint64_t frontie
   const int k = lane < kSelK ? lane : 0;
   double y = b3[k];
   for (int l = 0; l < kSelH; ++l) y += W3[k * kSelH + l] * __shfl(h2, l);
-  const double y0 = __shfl(y, 0), y1 = __shfl(y, 1);
-  *mode = y1 < y0 ? IPG_MODE_PULL : IPG_MODE_PUSH;
-  return y0 - y1;
+  double ys[kSelK];
+  for (int q = 0; q < kSelK; ++q) ys[q] = __shfl(y, q);
+  return sel_pick(ys, list_ok, mode, use_list);
 }
 
 }  // namespace ipg

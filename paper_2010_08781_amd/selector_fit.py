@@ -1,14 +1,18 @@
 """Training data, GPU training and evaluation of the learned exchange selector.
 
 Labels come from timing the plain method.  Every CC/SSSP run is repeated
-with the exchange forced to push and forced to pull, in the configuration
-the selector is deployed with: a store with the blocked in-edges, the
-device-driven superstep loop, and the launch parameters the autotuner picks
-for that graph.  The state at the start of a superstep does not depend on
-the exchange (values and traces are identical in both runs), so superstep s
-of the two runs starts from the same state and their per-superstep device
-times (the decide kernel's wall-clock stamps) give the two targets for that
-state: log2 of the microseconds of a push and of a pull superstep.
+with the exchange forced to each of the three variants the network scores --
+a push that visits the frontier as a list, a push that sweeps every vertex's
+mailbox, a pull -- in the configuration the selector is deployed with: a
+store with the blocked in-edges, the device-driven superstep loop, and the
+launch parameters the autotuner picks for that graph.  The state at the
+start of a superstep does not depend on the exchange (values and traces are
+identical in every run), so superstep s of the three runs starts from the
+same state and their per-superstep device times (the decide kernel's
+wall-clock stamps) give the three targets for that state: log2 of the
+microseconds of each variant.  A list exists only after a push, so the
+choices of a policy are replayed superstep by superstep with that
+constraint when its time is summed.
 
 The network is then trained on the device by the library's own FP64 forward,
 backward and SGD kernels (ipg_selector_train), and compared with the fixed
@@ -34,12 +38,14 @@ DEFAULT_PARAMS = os.path.join(HERE, "selector_params.json")
 def _graphs(kind: str):
     import graphgen
 
-    # Training graphs span the sizes of the workloads (up to ~67M edges) with
+    # Training graphs span the sizes of the workloads (up to ~270M edges: the
+    # scale-23 symmetrised R-MAT stands in for the billion-edge one) with
     # seeds of their own; the held-out set includes the benchmark graphs
     # themselves (R-MAT s20 seed 2, the 4096^2 grid seed 3).
     if kind == "train":
         specs = [("rmat", 15, 11, True), ("rmat", 16, 12, True), ("rmat", 17, 13, False), ("rmat", 18, 14, True),
                  ("rmat", 19, 15, True), ("rmat", 18, 16, False), ("rmat", 21, 19, True), ("rmat", 20, 25, False),
+                 ("rmat", 23, 26, True),
                  ("grid", 512, 17, None), ("grid", 1024, 18, None), ("grid", 2048, 20, None), ("grid", 4096, 24, None)]
     else:
         specs = [("rmat", 19, 21, True), ("rmat", 17, 22, False), ("grid", 768, 23, None), ("rmat", 20, 2, True),
@@ -67,66 +73,129 @@ def decision_frontier(app: str, active) -> np.ndarray:
     return f
 
 
+# The network's outputs, in order: (forced exchange, list_div) of each variant.
+VARIANTS = (("push", 1), ("push", 0xFFFFFFFF), ("pull", None))
+VARIANT_NAMES = ("push_list", "push_dense", "pull")
+
+
+def time_runs(g, hg, name, runs, tun, reps, kind, verbose=True):
+    """Per-superstep times of every variant for each (app, source) run:
+    returns (T [steps,3] log2-usec, meta) pairs."""
+    out = []
+    for app, src in runs:
+        times = []
+        for mode, list_div in VARIANTS:
+            t = dict(tun)
+            if list_div is not None:
+                t["list_div"] = list_div
+            us = []
+            for _ in range(reps):
+                _, st = g.run(app, source=src, mode=mode, timing=True, tuning=t, persistent=True)
+                us.append(st.usec.astype(np.float64))
+            times.append(np.median(np.stack(us), axis=0))
+        front = decision_frontier(app, st.active)
+        T = np.log2(np.maximum(np.stack(times, axis=1), 1.0))
+        meta = [(name, app, src, s, int(front[s]), int(st.frontier_deg[s]), int(hg.m), int(hg.n))
+                for s in range(st.supersteps)]
+        out.append((T, meta))
+        if verbose:
+            sums = ", ".join(f"{v} {np.exp2(T[:, i]).sum():.0f} us" for i, v in enumerate(VARIANT_NAMES))
+            print(f"[selector] {kind} {name} {app} src={src} {tun}: {st.supersteps} supersteps, {sums}",
+                  file=sys.stderr, flush=True)
+    return out
+
+
+def features(meta) -> np.ndarray:
+    import paper_2010_08781_amd as ipg
+
+    return ipg.selector_features([m[4] for m in meta], [m[5] for m in meta], [m[3] for m in meta],
+                                 [m[6] for m in meta])
+
+
 def collect(kind: str = "train", reps: int = 3, verbose: bool = True):
-    """Returns (X [n,4], T [n,2] log2-usec for push/pull, meta list)."""
+    """Returns (X [n,4], T [n,3] log2-usec per variant, meta list)."""
     import paper_2010_08781_amd as ipg
 
     from paper_2010_08781_amd import autotune
 
-    X, T, meta = [], [], []
+    T, meta = [], []
     for name, hg in _graphs(kind):
         g = ipg.Graph.from_host(hg, blocked=True)
         tun = autotune.tune(g, hg, "cc", cache_path=None, reps=1, persistent=True)
-        tun.pop("push_div", None)  # the fixed rule's divisor: irrelevant to forced exchanges
+        for k in ("push_div", "list_div", "late_div"):  # the rule's divisors: irrelevant to forced variants
+            tun.pop(k, None)
         runs = [("cc", 0)] + [("sssp", s) for s in _sources(hg, 4, 99)]
-        for app, src in runs:
-            times = {}
-            for mode in ("push", "pull"):
-                us = []
-                for _ in range(reps):
-                    _, st = g.run(app, source=src, mode=mode, timing=True, tuning=tun, persistent=True)
-                    us.append(st.usec.astype(np.float64))
-                times[mode] = np.median(np.stack(us), axis=0)
-            front = decision_frontier(app, st.active)
-            feats = ipg.selector_features(front, st.frontier_deg, np.arange(st.supersteps), hg.m)
-            X.append(feats)
-            T.append(np.log2(np.maximum(np.stack([times["push"], times["pull"]], axis=1), 1.0)))
-            meta += [(name, app, src, s, int(front[s]), int(st.frontier_deg[s]), hg.m) for s in range(st.supersteps)]
-            if verbose:
-                print(f"[selector] {kind} {name} {app} src={src} {tun}: {st.supersteps} supersteps, "
-                      f"push {times['push'].sum():.0f} us, pull {times['pull'].sum():.0f} us", file=sys.stderr, flush=True)
+        for t, m in time_runs(g, hg, name, runs, tun, reps, kind, verbose):
+            T.append(t)
+            meta += m
         g.close()
-    return np.concatenate(X), np.concatenate(T), meta
+    return features(meta), np.concatenate(T), meta
 
 
 def init_params(seed: int = 1, scale: float = 0.5) -> np.ndarray:
     """Uniform(-scale/sqrt(fan_in), +scale/sqrt(fan_in)) weights, zero biases, packed as the library expects."""
     rng = np.random.default_rng(seed)
     parts = []
-    for fan_out, fan_in in ((16, 4), (16, 16), (2, 16)):
+    for fan_out, fan_in in ((16, 4), (16, 16), (3, 16)):
         lim = scale / np.sqrt(fan_in)
         parts += [rng.uniform(-lim, lim, fan_out * fan_in), np.zeros(fan_out)]
     return np.concatenate(parts)
 
 
-def heuristic_choice(meta) -> np.ndarray:
-    """1 = pull, 0 = push, by the fixed rule (frontier + its out-degrees > E/20)."""
-    return np.array([1 if (e > 0 and f + d > e // 20) else 0 for (_, _, _, _, f, d, e) in meta])
+PUSH_LIST, PUSH_DENSE, PULL = 0, 1, 2
 
 
-def regret(T: np.ndarray, choice: np.ndarray) -> dict:
+def replay(meta, pick) -> np.ndarray:
+    """A policy's variant in every superstep: pick(i, list_available) for
+    sample i, where a list is available only after a push (superstep 0's
+    active set is given, so it has none)."""
+    choice = np.empty(len(meta), dtype=np.int64)
+    avail = False
+    for i, m in enumerate(meta):
+        if i == 0 or tuple(meta[i - 1][:3]) != tuple(m[:3]) or m[3] == 0:
+            avail = False
+        choice[i] = pick(i, avail)
+        avail = choice[i] != PULL
+    return choice
+
+
+def heuristic_choice(meta, push_div: int = 20, list_div: int = 16) -> np.ndarray:
+    """The fixed rule: pull when frontier + its out-degrees > E / push_div,
+    else push over the list when there is one of at most max(4096, N / list_div)."""
+    def pick(i, avail):
+        _, _, _, _, f, d, e, n = meta[i]
+        if e > 0 and f + d > e // push_div:
+            return PULL
+        return PUSH_LIST if avail and f <= max(4096, n // list_div) else PUSH_DENSE
+    return replay(meta, pick)
+
+
+def pick_from_outputs(y: np.ndarray, meta) -> np.ndarray:
+    """The network's choice from its outputs y [n,3], as the library takes it."""
+    def pick(i, avail):
+        push = PUSH_LIST if avail and y[i, PUSH_LIST] <= y[i, PUSH_DENSE] else PUSH_DENSE
+        return PULL if y[i, PULL] < y[i, push] else push
+    return replay(meta, pick)
+
+
+def regret(T: np.ndarray, choice: np.ndarray, meta=None) -> dict:
+    """Time of the chosen variants against the fastest one in every
+    superstep (the list variant counted only after superstep 0)."""
     t = np.exp2(T)  # microseconds
     chosen = t[np.arange(len(t)), choice]
-    best = t.min(axis=1)
+    tb = t.copy()
+    if meta is not None:
+        tb[np.array([m[3] == 0 for m in meta], dtype=bool), PUSH_LIST] = np.inf
+    best = tb.min(axis=1)
     return {"chosen_us": float(chosen.sum()), "best_us": float(best.sum()),
-            "regret_us": float((chosen - best).sum()), "accuracy": float(np.mean(chosen == best))}
+            "regret_us": float((chosen - best).sum()), "accuracy": float(np.mean(chosen <= best))}
 
 
 def cost_weighted(X, T, cap: int = 16):
     """Replicate each sample in proportion to what a wrong choice costs there
-    (|t_push - t_pull| relative to the mean), so the squared-error fit is
-    most accurate where the decision matters."""
-    cost = np.abs(np.exp2(T[:, 0]) - np.exp2(T[:, 1]))
+    (the spread of the variants' times relative to the mean), so the
+    squared-error fit is most accurate where the decision matters."""
+    cost = np.exp2(T).max(axis=1) - np.exp2(T).min(axis=1)
     reps = 1 + np.minimum(np.floor(4.0 * cost / max(cost.mean(), 1e-9)), cap - 1).astype(np.int64)
     return np.repeat(X, reps, axis=0), np.repeat(T, reps, axis=0)
 
@@ -150,13 +219,13 @@ def train(X, T, epochs: int = 30000, lr: float = 0.1, seed: int = 1, weighted: b
     return p
 
 
-def predict_choice(p, X) -> np.ndarray:
+def predict_choice(p, X, meta) -> np.ndarray:
     import torch
 
     import paper_2010_08781_amd as ipg
 
     y = ipg.selector_forward(p, torch.tensor(X, dtype=torch.float64, device="cuda")).cpu().numpy()
-    return (y[:, 1] < y[:, 0]).astype(np.int64)
+    return pick_from_outputs(y, meta)
 
 
 def load(path: str = DEFAULT_PARAMS):
@@ -169,6 +238,49 @@ def load(path: str = DEFAULT_PARAMS):
     return torch.tensor(d["params"], dtype=torch.float64, device="cuda")
 
 
+# Regret tables of the benchmark workloads: the runs the benchmark times, on
+# the store it builds (blocked in-edges, cold sources binned when the u32
+# value array fills the 256 MB Infinity Cache; weighted graphs pull by rows).
+TABLE_RUNS = {"grid4096-sc": (("sssp", 0),), "rmat-s26-sym": (("cc", 0), ("sssp", 0)),
+              "rmat-s20-sym": (("cc", 0), ("sssp", 0))}
+
+
+def regret_table(workload: str, reps: int = 3) -> dict:
+    """Per-superstep times of the three variants for the benchmark's runs
+    on `workload`, with the raw inputs of both policies (the network's
+    features and the fixed rule's frontier, out-degree sum, E and N)."""
+    import torch
+
+    import graphgen
+    import paper_2010_08781_amd as ipg
+    from paper_2010_08781_amd import autotune
+
+    hg = graphgen.workload(workload)
+    weighted = getattr(hg, "csr_w", None) is not None
+    binned = not weighted and 4 * hg.n >= (256 << 20)
+    g = ipg.Graph.from_host(hg, blocked=not weighted, binned=binned)
+    tun = autotune.tune(g, hg, TABLE_RUNS[workload][0][0], cache_path=None, reps=1, persistent=True)
+    for k in ("push_div", "list_div", "late_div"):
+        tun.pop(k, None)
+    samples = []
+    for T, meta in time_runs(g, hg, workload, TABLE_RUNS[workload], tun, reps, "table"):
+        for t, m in zip(T, meta):
+            samples.append({"app": m[1], "source": m[2], "superstep": m[3], "frontier": m[4], "frontier_deg": m[5],
+                            "e": m[6], "n": m[7], "log2_us": [round(float(x), 6) for x in t]})
+    g.close()
+    return {"workload": workload, "graph": {"name": hg.name, "n": int(hg.n), "m": int(hg.m)},
+            "store": {"blocked": not weighted, "binned": binned}, "tuning": tun, "reps": reps,
+            "measured_on": torch.cuda.get_device_name(0), "when": time.strftime("%Y-%m-%d"),
+            "variants": list(VARIANT_NAMES), "samples": samples}
+
+
+def table_arrays(table: dict):
+    """(T [n,3] log2-usec, meta) of a regret table."""
+    meta = [(table["workload"], x["app"], x["source"], x["superstep"], x["frontier"], x["frontier_deg"], x["e"],
+             x["n"]) for x in table["samples"]]
+    return np.array([x["log2_us"] for x in table["samples"]], dtype=np.float64), meta
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_PARAMS)
@@ -177,14 +289,24 @@ def main():
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--data-out", default=None, help="also write the timed samples (npz)")
     ap.add_argument("--data-in", default=None, help="train on samples written by --data-out instead of timing")
+    ap.add_argument("--regret-table", default=None, choices=sorted(TABLE_RUNS),
+                    help="only time the variants on this benchmark workload and write the table to --table-out")
+    ap.add_argument("--table-out", default=None)
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))
     t0 = time.time()
+    if args.regret_table:
+        table = regret_table(args.regret_table, reps=args.reps)
+        with open(args.table_out, "w") as f:
+            json.dump(table, f, indent=0)
+        print(f"[selector] wrote {args.table_out}: {len(table['samples'])} supersteps in {time.time() - t0:.0f}s",
+              file=sys.stderr, flush=True)
+        return
     if args.data_in:
         d = np.load(args.data_in, allow_pickle=False)
 
         def meta(m):
-            return [(a, b, int(c), int(k), int(f), int(dd), int(e)) for a, b, c, k, f, dd, e in m]
+            return [(a, b, int(c), int(k), int(f), int(dd), int(e), int(n)) for a, b, c, k, f, dd, e, n in m]
 
         Xtr, Ttr, mtr, Xte, Tte, mte = d["Xtr"], d["Ttr"], meta(d["mtr"]), d["Xte"], d["Tte"], meta(d["mte"])
     else:
@@ -197,13 +319,14 @@ def main():
     pn = p.cpu().numpy()
     res = {}
     for split, X, T, m in (("train", Xtr, Ttr, mtr), ("heldout", Xte, Tte, mte)):
-        res[split] = {"samples": int(len(X)), "learned": regret(T, predict_choice(p, X)),
-                      "heuristic": regret(T, heuristic_choice(m)),
-                      "always_pull": regret(T, np.ones(len(X), dtype=np.int64)),
-                      "always_push": regret(T, np.zeros(len(X), dtype=np.int64))}
+        res[split] = {"samples": int(len(X)), "learned": regret(T, predict_choice(p, X, m), m),
+                      "heuristic": regret(T, heuristic_choice(m), m),
+                      "always_pull": regret(T, np.full(len(X), PULL), m),
+                      "always_push": regret(T, replay(m, lambda i, a: PUSH_LIST if a else PUSH_DENSE), m)}
     out = {"params": pn.tolist(), "epochs": args.epochs, "lr": args.lr, "evaluation": res,
            "features": "log2(1+|F|)/32, log2(1+sum outdeg F)/32, min(s,128)/64, log2(1+E)/32",
-           "targets": "log2 microseconds of a push and of a pull superstep (HIP events, median of reps)",
+           "targets": "log2 microseconds of a superstep exchanged by a push over the frontier list, a push "
+                      "sweeping every vertex, a pull (device wall-clock stamps, median of reps)",
            "seconds": time.time() - t0}
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)

@@ -21,7 +21,7 @@ def ipg():
 def _batch(n, seed):
     rng = np.random.default_rng(seed)
     X = np.stack([rng.uniform(0, 1, n), rng.uniform(0, 1, n), rng.uniform(0, 2, n), rng.uniform(0.3, 1, n)], axis=1)
-    T = np.stack([8 * X[:, 1] - 3 * X[:, 0] + 4, 2 + 6 * X[:, 3] - X[:, 2]], axis=1)
+    T = np.stack([8 * X[:, 1] - 3 * X[:, 0] + 4, 2 + 6 * X[:, 3] - X[:, 2], 5 * X[:, 0] * X[:, 3] + 1], axis=1)
     return X, T
 
 
@@ -79,9 +79,9 @@ def test_selector_never_changes_results(ipg, app):
     ref = oracle.run_graph(app, hg, 0, source=0)
     g = ipg.Graph.from_host(hg)
     always_push = np.zeros(mlp.n_params())
-    always_push[-2:] = [0.0, 1.0]
+    always_push[-3:] = [0.0, 0.0, 1.0]  # push (over the list when there is one), never pull
     always_pull = np.zeros(mlp.n_params())
-    always_pull[-2:] = [1.0, 0.0]
+    always_pull[-3:] = [1.0, 1.0, 0.0]
     for p, want in ((always_push, 1), (always_pull, 2), (mlp.init_params(9, scale=3.0), None)):
         # without the late push, which may turn a chosen pull into a push once the messages are counted
         vals, st = g.run(app, source=0, selector=_cuda(p), tuning={"late_div": 0xFFFFFFFF})

@@ -8,12 +8,12 @@ from oracle import mlp
 def _data(n=40, seed=0):
     rng = np.random.default_rng(seed)
     X = rng.uniform(-1, 1, size=(n, mlp.D))
-    T = np.stack([np.sin(2 * X[:, 0]) + X[:, 1] * X[:, 3], X[:, 2] ** 2 - X[:, 0]], axis=1)
+    T = np.stack([np.sin(2 * X[:, 0]) + X[:, 1] * X[:, 3], X[:, 2] ** 2 - X[:, 0], np.cos(X[:, 1]) * X[:, 2]], axis=1)
     return X, T
 
 
 def test_param_count():
-    assert mlp.n_params() == 16 * 4 + 16 + 16 * 16 + 16 + 2 * 16 + 2
+    assert mlp.n_params() == 16 * 4 + 16 + 16 * 16 + 16 + 3 * 16 + 3 == 403
     assert mlp.init_params(1).size == mlp.n_params()
 
 
@@ -45,9 +45,9 @@ def test_grad_matches_torch_autograd_float64():
 
 def test_forward_zero_hidden_is_output_bias():
     p = np.zeros(mlp.n_params())
-    p[-2:] = [0.25, -3.0]
+    p[-3:] = [0.25, -3.0, 1.5]
     X, _ = _data(n=5)
-    np.testing.assert_array_equal(mlp.forward(p, X), np.tile([0.25, -3.0], (5, 1)))
+    np.testing.assert_array_equal(mlp.forward(p, X), np.tile([0.25, -3.0, 1.5], (5, 1)))
 
 
 def test_sgd_descends():

@@ -20,7 +20,7 @@ def ipg():
 def _batch(n, seed):
     rng = np.random.default_rng(seed)
     X = np.stack([rng.uniform(0, 1, n), rng.uniform(0, 1, n), rng.uniform(0, 2, n), rng.uniform(0.3, 1, n)], axis=1)
-    T = np.stack([8 * X[:, 1] - 3 * X[:, 0] + 4, 2 + 6 * X[:, 3] - X[:, 2]], axis=1)
+    T = np.stack([8 * X[:, 1] - 3 * X[:, 0] + 4, 2 + 6 * X[:, 3] - X[:, 2], 5 * X[:, 0] * X[:, 3] + 1], axis=1)
     return X, T
 
 
@@ -49,7 +49,7 @@ def test_noalloc_train_limit(ipg):
 
     n = ipg.SELECTOR_NOALLOC_MAX_SAMPLES + 1
     x = torch.zeros((n, 4), dtype=torch.float64, device="cuda")
-    t = torch.zeros((n, 2), dtype=torch.float64, device="cuda")
+    t = torch.zeros((n, ipg.SELECTOR_OUTPUTS), dtype=torch.float64, device="cuda")
     p = torch.zeros(ipg.SELECTOR_PARAMS, dtype=torch.float64, device="cuda")
     rc = ipg.lib().ipg_selector_train_noalloc(p.data_ptr(), x.data_ptr(), t.data_ptr(), n, 1, 0.1, None)
     assert rc == -1  # IPG_EINVAL
