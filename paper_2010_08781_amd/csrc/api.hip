@@ -23,6 +23,7 @@ size_t carve_run(Carver& c, uint32_t n, uint64_t e, ipg_app app, RunWs* w) {
     r.pr_rec = c.take<unsigned long long>(3 * static_cast<size_t>(kPrTraceCap));
   } else {
     r.value_u32 = c.take<uint32_t>(nn);
+    r.value_u32_hot = c.take<uint32_t>(nn);
     r.mail_a = c.take<uint32_t>(nn);
     r.mail_b = c.take<uint32_t>(nn);
     r.fr_a = c.take<uint32_t>(static_cast<size_t>(kCtrSlots) * list_seg(static_cast<uint32_t>(nn)));

@@ -118,6 +118,7 @@ struct GraphTables {
   // descending out-degree, and the CSC rebuilt under the new names (rows in
   // the new order, each row's sources in their original order).
   uint32_t* perm;       // [n] new name of every vertex
+  uint32_t* iperm;      // [n] the vertex of every new name
   uint32_t* outdeg_hot; // [n] out-degree by new name
   uint64_t* off_hot;    // [n+1] CSC offsets by new name
   int32_t* src_hot;     // [e] CSC sources, new names
@@ -125,7 +126,8 @@ struct GraphTables {
   // IPG_GRAPH_BLOCKED: the blocked in-edges of the CSC PageRank's pull uses
   // (the hot-first one when present), else edges == null; with a hot-first
   // store also those of the caller's CSC (blk_ids), for the CC/SSSP pull,
-  // which works on the caller's vertex ids.
+  // which works on the caller's vertex ids -- except on a symmetric binned
+  // store, where CC and SSSP run under the new names on `blk` (min_space).
   BlockedTables blk;
   BlockedTables blk_ids;
 };
@@ -180,6 +182,7 @@ struct ipg_graph {
   std::vector<hipEvent_t> events;
   int wall_khz;  // device wall-clock rate, queried on first use (0 until then)
   uint32_t dd_steps[4];  // supersteps of the last device-driven run of each application (0: none yet)
+  std::vector<uint32_t> perm_host;  // hot-first store: the new name of every vertex (host copy)
   void* mirror;      // pinned host block the decide kernels write (created on first use)
   void* mirror_dev;  // its device address
 };

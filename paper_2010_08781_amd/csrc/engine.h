@@ -148,6 +148,7 @@ struct RunWs {
   unsigned long long* pr_rec;  // [kPrTraceCap][3] trace records: active, senders, messages
   // CC / SSSP
   uint32_t* value_u32;  // [n] labels or distances
+  uint32_t* value_u32_hot;  // [n] the same under the hot-first names, when the run works under them (min_space)
   uint32_t* mail_a;     // [n] one-slot min mailboxes, ping (INF = empty)
   uint32_t* mail_b;     // [n] pong
   uint32_t* fr_a;       // [kCtrSlots * list_seg(n)] frontier list in segments, ping

@@ -35,7 +35,8 @@ namespace ipg {
 
 static_assert(kListSegs == static_cast<uint32_t>(kCtrSlots), "one list segment per counter slot");
 
-// value = id (CC) or 0 at the source / INF elsewhere (SSSP).  With `pull_s0`
+// value = id (CC: `ids[v]` when the run works under other names than the
+// caller's) or 0 at the source / INF elsewhere (SSSP).  With `pull_s0`
 // superstep 0 is exchanged by pull: the senders' broadcast values are written
 // to the outbox (INF for the others) and the senders are counted.  With a
 // control block (device-driven loop) its exchange decides instead.  Given
@@ -44,13 +45,13 @@ static_assert(kListSegs == static_cast<uint32_t>(kCtrSlots), "one list segment p
 __global__ __launch_bounds__(kBlock) void minprop_init_kernel(uint32_t n, int app, uint32_t source, uint32_t* value,
                                                               const uint32_t* outdeg, int pull_s0, uint32_t* outbox,
                                                               CtrSlot* ctr, const DevCtl* ctl, uint32_t* mail_a,
-                                                              uint32_t* mail_b) {
+                                                              uint32_t* mail_b, const uint32_t* ids) {
   if (ctl) pull_s0 = ctl->mode == IPG_MODE_PULL;  // uniform over the grid
   uint64_t senders = 0, messages = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += stride) {
     const bool sends = (app == IPG_APP_CC_HASHMIN) || v == source;
-    const uint32_t x = app == IPG_APP_CC_HASHMIN ? static_cast<uint32_t>(v) : (v == source ? 0u : kInf);
+    const uint32_t x = app == IPG_APP_CC_HASHMIN ? (ids ? ids[v] : static_cast<uint32_t>(v)) : (v == source ? 0u : kInf);
     value[v] = x;
     if (mail_a) {
       mail_a[v] = kInf;
@@ -1073,6 +1074,71 @@ static uint64_t list_limit(uint32_t n, uint32_t div) {
   return std::max<uint64_t>(4096, n / (div ? div : 16));
 }
 
+// The names a CC/SSSP run works under.  The caller's, with the caller's CSR
+// for the push and the blocked in-edges of the caller's CSC (blk_ids, or
+// blk on a store without renaming) for the pull.  Or, on a symmetric store
+// that is hot-first and binned, the new names (Section 4.2's vertex arrays
+// in another order): the push reads the renamed CSC as the CSR (the graph is
+// symmetric), the pull PageRank's table, whose hot sources are the most-read
+// ones; CC's labels start from the caller's ids (iperm), SSSP starts at the
+// source's new name, and the values go back to the caller's order at the
+// end (w.value_u32[v] = value under v's new name).  Hash-min labels are the
+// caller's ids either way, and a vertex's distance does not depend on the
+// names, so results and traces are the same.
+struct MinSpace {
+  bool renamed;
+  const uint64_t* off;      // CSR offsets
+  const int32_t* dst;       // CSR destinations
+  const uint32_t* w;        // CSR weights or null
+  const uint32_t* outdeg;
+  uint32_t* value;
+  const uint32_t* ids;      // CC's initial label of every vertex (null: its id)
+  uint32_t source;
+  const BlockedTables* bt;  // blocked in-edges for the pull, or null (row items)
+};
+static MinSpace min_space(const ipg_graph* g, ipg_app app, uint32_t source, const RunWs& w, const Tune& tn) {
+  MinSpace sp;
+  const bool weighted = app == IPG_APP_SSSP && g->csr_w != nullptr;
+  const GraphTables& t = g->t;
+  sp.renamed = (g->flags & IPG_GRAPH_SYMMETRIC) && t.perm && t.blk.edges && t.blk.hot && !weighted && tn.blocked &&
+               g->perm_host.size() == g->n;
+  if (sp.renamed) {
+    sp.off = t.off_hot;
+    sp.dst = t.src_hot;
+    sp.w = nullptr;
+    sp.outdeg = t.outdeg_hot;
+    sp.value = w.value_u32_hot;
+    sp.ids = t.iperm;
+    sp.source = app == IPG_APP_SSSP ? g->perm_host[source] : 0u;
+    sp.bt = &t.blk;
+    return sp;
+  }
+  sp.off = g->csr_off;
+  sp.dst = g->csr_dst;
+  sp.w = weighted ? g->csr_w : nullptr;
+  sp.outdeg = t.outdeg;
+  sp.value = w.value_u32;
+  sp.ids = nullptr;
+  sp.source = source;
+  // the blocked in-edges of the caller's CSC (CC, unit-weight SSSP), if the store has them
+  sp.bt = nullptr;
+  if (tn.blocked && !weighted) sp.bt = t.blk_ids.edges ? &t.blk_ids : (t.blk.edges && !t.perm ? &t.blk : nullptr);
+  return sp;
+}
+
+// Values of a run under the new names back to the caller's order.
+__global__ void min_unrename_kernel(const uint32_t* value_hot, const uint32_t* perm, uint32_t n, uint32_t* value) {
+  for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
+    value[v] = value_hot[perm[v]];
+}
+static ipg_status finish_space(const ipg_graph* g, const MinSpace& sp, const RunWs& w, hipStream_t s) {
+  if (!sp.renamed) return IPG_OK;
+  hipLaunchKernelGGL(min_unrename_kernel, dim3(grid_for(g->n, kBlock, 16384)), dim3(kBlock), 0, s, sp.value, g->t.perm,
+                     g->n, w.value_u32);
+  IPG_HIP(hipGetLastError());
+  return IPG_OK;
+}
+
 // Ping-pong buffers of superstep `step`.
 struct StepBufs {
   CtrSlot* c;    // this superstep's counters
@@ -1102,18 +1168,15 @@ static StepBufs bufs_for(const RunWs& w, uint32_t step) {
 // that only one exchange has shares a launch with the other's
 // (minprop_front_kernel from superstep 1, minprop_back_kernel over blocked
 // in-edges).
-static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint32_t step, ipg_mode mode,
+static ipg_status enqueue_step(ipg_graph* g, ipg_app app, const MinSpace& sp, uint32_t step, ipg_mode mode,
                                const Active& act, uint64_t degsum, const RunWs& w, const DevCtl* ctl, const Tune& tn,
                                hipStream_t s) {
   const uint32_t n = g->n;
-  const bool weighted = app == IPG_APP_SSSP && g->csr_w != nullptr;
+  const bool weighted = sp.w != nullptr;
   const uint32_t gv = grid_for(n, kBlock, 16384);
   const StepBufs b = bufs_for(w, step);
   const bool device = ctl != nullptr;
-  // the blocked in-edges of the caller's CSC (CC, unit-weight SSSP), if the store has them
-  const BlockedTables* bt = nullptr;
-  if (tn.blocked && !weighted)
-    bt = g->t.blk_ids.edges ? &g->t.blk_ids : (g->t.blk.edges && !g->t.perm ? &g->t.blk : nullptr);
+  const BlockedTables* bt = sp.bt;
   // device-driven superstep s >= 1: the push and the pull form's compute
   // share one launch (minprop_front_kernel), made where the compute's was
   const bool front = device && step > 0;
@@ -1127,9 +1190,9 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
   // forced
   const bool late_on = step > 0 && tn.late_div != 0 && (device || mode == IPG_MODE_PULL);
   if (step == 0) {
-    hipLaunchKernelGGL(minprop_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, static_cast<int>(app), source,
-                       w.value_u32, g->t.outdeg, mode == IPG_MODE_PULL ? 1 : 0, w.outbox, b.c, ctl,
-                       device ? w.mail_a : nullptr, device ? w.mail_b : nullptr);
+    hipLaunchKernelGGL(minprop_init_kernel, dim3(gv), dim3(kBlock), 0, s, n, static_cast<int>(app), sp.source,
+                       sp.value, sp.outdeg, mode == IPG_MODE_PULL ? 1 : 0, w.outbox, b.c, ctl,
+                       device ? w.mail_a : nullptr, device ? w.mail_b : nullptr, sp.ids);
     IPG_HIP(hipGetLastError());
   }
   if (device || mode == IPG_MODE_PUSH || late_on) {
@@ -1138,11 +1201,11 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
     a.act.list = b.fin;
     a.act.pre = b.lpre_in;
     a.act.seg = list_seg(n);
-    a.off = g->csr_off;
-    a.dst = g->csr_dst;
-    a.w = weighted ? g->csr_w : nullptr;
-    a.outdeg = g->t.outdeg;
-    a.value = w.value_u32;
+    a.off = sp.off;
+    a.dst = sp.dst;
+    a.w = sp.w;
+    a.outdeg = sp.outdeg;
+    a.value = sp.value;
     a.mail_in = b.mail_in;
     a.mail_out = b.mail_out;
     a.list_out = b.fout;
@@ -1173,8 +1236,8 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
       ap.act.list = b.fin;
       ap.act.pre = b.lpre_in;
       ap.act.seg = list_seg(n);
-      ap.outdeg = g->t.outdeg;
-      ap.value = w.value_u32;
+      ap.outdeg = sp.outdeg;
+      ap.value = sp.value;
       ap.mail_in = b.mail_in;
       ap.outbox = w.outbox;
       ap.ctr = b.c;
@@ -1206,7 +1269,7 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
     if (bt) {
       MinBlkArgs ba;
       ba.v = blk_view(*bt);
-      ba.outdeg = g->t.outdeg;
+      ba.outdeg = sp.outdeg;
       ba.outbox = w.outbox;
       ba.mail_out = b.mail_out;
       ba.ctr = b.c;
@@ -1245,7 +1308,7 @@ static ipg_status enqueue_step(ipg_graph* g, ipg_app app, uint32_t source, uint3
     MinPullArgs pa;
     pa.t = pull_tiling(g);
     pa.w = weighted ? g->csc_w : nullptr;
-    pa.outdeg = g->t.outdeg;
+    pa.outdeg = sp.outdeg;
     pa.outbox = w.outbox;
     pa.mail_out = b.mail_out;
     pa.ctr = b.c;
@@ -1341,13 +1404,14 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
   const double* sel = o.mode == IPG_MODE_AUTO ? o.selector : nullptr;
   const int forced = o.mode == IPG_MODE_AUTO ? 0 : static_cast<int>(o.mode);
   if (forced) tn.late_div = 0;  // a forced exchange stays as forced
+  const MinSpace sp = min_space(g, app, o.source, w, tn);
   IPG_HIP(tm.start(s));
   // the counters are zeroed by dd_start_kernel and the mailboxes emptied by
   // superstep 0's init kernel, so the run starts with no clearing launch
-  hipLaunchKernelGGL(dd_start_kernel, dim3(1), dim3(kWave), 0, s, w.ctl, static_cast<int>(app), o.source, g->csr_off, n,
+  hipLaunchKernelGGL(dd_start_kernel, dim3(1), dim3(kWave), 0, s, w.ctl, static_cast<int>(app), sp.source, sp.off, n,
                      e, sel, forced, tn.push_div, cap, w.ctr);
   IPG_HIP(hipGetLastError());
-  rc = enqueue_step(g, app, o.source, 0, IPG_MODE_AUTO, step0_active(app, n, o.source), 0, w, w.ctl, tn, s);
+  rc = enqueue_step(g, app, sp, 0, IPG_MODE_AUTO, step0_active(app, n, sp.source), 0, w, w.ctl, tn, s);
   if (rc != IPG_OK) return rc;
   uint32_t enqueued = 0;  // supersteps whose launches are in the stream, minus one
   uint32_t recorded = 0;  // supersteps whose records were read
@@ -1364,7 +1428,7 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
       const uint32_t step = enqueued + k;
       if (step > 0) {
         Active unused{};
-        rc = enqueue_step(g, app, o.source, step, IPG_MODE_AUTO, unused, 0, w, w.ctl, tn, s);
+        rc = enqueue_step(g, app, sp, step, IPG_MODE_AUTO, unused, 0, w, w.ctl, tn, s);
         if (rc != IPG_OK) return rc;
       }
       const StepBufs b = bufs_for(w, step);
@@ -1395,6 +1459,8 @@ static ipg_status run_minprop_device(ipg_graph* g, ipg_app app, uint32_t cap, co
     if (h.halted) break;
     chunk = std::min<uint32_t>(chunk * 2, 64);
   }
+  rc = finish_space(g, sp, w, s);
+  if (rc != IPG_OK) return rc;
   IPG_HIP(tm.finish(s));
   g->dd_steps[static_cast<int>(app) & 3] = h.step;
   if (st) {
@@ -1415,6 +1481,7 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
   const uint64_t e = g->e;
   Tune tn = resolve_tuning(o.tuning);
   if (o.mode != IPG_MODE_AUTO) tn.late_div = 0;  // a forced exchange stays as forced
+  const MinSpace sp = min_space(g, app, o.source, w, tn);
   HostMirror *hm = nullptr, *hm_dev = nullptr;
   IPG_HIP(host_mirror(g, &hm, &hm_dev));
   MinStart m0;
@@ -1433,14 +1500,14 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
     const StepBufs b = bufs_for(w, step);
     Active act{};
     if (step == 0) {
-      act = step0_active(app, n, o.source);
+      act = step0_active(app, n, sp.source);
     } else {
-      act.source = o.source;
+      act.source = sp.source;
       act.list = b.fin;
       act.phase = list_ok ? kStepList : kStepDense;
       act.count = list_ok ? static_cast<uint32_t>(count) : n;
     }
-    status = enqueue_step(g, app, o.source, step, mode, act, degsum, w, nullptr, tn, s);
+    status = enqueue_step(g, app, sp, step, mode, act, degsum, w, nullptr, tn, s);
     if (status != IPG_OK) return status;
     IPG_HIP(tm.step(s, step));
     const double* sel = o.mode == IPG_MODE_AUTO ? o.selector : nullptr;
@@ -1484,6 +1551,8 @@ ipg_status run_minprop(ipg_graph* g, ipg_app app, uint32_t cap, const ipg_run_op
     const bool list_avail = ran == IPG_MODE_PUSH && lcount != ~0ull;
     list_ok = list_avail && (h.mode == IPG_MODE_PUSH ? h.list != 0 : count <= list_limit(n, tn.list_div));
   }
+  const ipg_status fs = finish_space(g, sp, w, s);
+  if (fs != IPG_OK) return fs;
   IPG_HIP(tm.finish(s));
   if (st) {
     st->supersteps = step;

@@ -149,6 +149,16 @@ static void carve_tiling(Carver& c, uint32_t n, uint64_t e, TilingTables* t) {
   t->nb = t->nl = t->nc = t->ni = 0;
 }
 
+// Whether a blocked store also holds the blocked in-edges of the caller's
+// CSC (blk_ids): with a hot-first store, for CC/SSSP, which keep the caller's
+// names -- but not when it is symmetric and binned: CC and SSSP then run
+// under the new names on the hot-first table (min_space), whose hot sources
+// are the most-read ones.
+static bool ids_table(uint32_t flags) {
+  if (!(flags & IPG_GRAPH_RENAME)) return false;
+  return !((flags & IPG_GRAPH_SYMMETRIC) && (flags & IPG_GRAPH_BINNED));
+}
+
 static size_t carve_graph(Carver& c, uint32_t n, uint64_t e, uint32_t flags, GraphTables* t) {
   GraphTables tt{};
   tt.outdeg = c.take<uint32_t>(n ? n : 1);
@@ -156,6 +166,7 @@ static size_t carve_graph(Carver& c, uint32_t n, uint64_t e, uint32_t flags, Gra
   carve_tiling(c, n, e, &tt.pull);
   if (flags & IPG_GRAPH_RENAME) {
     tt.perm = c.take<uint32_t>(n ? n : 1);
+    tt.iperm = c.take<uint32_t>(n ? n : 1);
     tt.outdeg_hot = c.take<uint32_t>(n ? n : 1);
     tt.off_hot = c.take<uint64_t>((size_t)n + 1);
     tt.src_hot = c.take<int32_t>(e ? e : 1);
@@ -181,7 +192,7 @@ static size_t carve_graph(Carver& c, uint32_t n, uint64_t e, uint32_t flags, Gra
   };
   if (flags & IPG_GRAPH_BLOCKED) {
     carve_blocked(tt.blk, (flags & IPG_GRAPH_BINNED) != 0);
-    if (flags & IPG_GRAPH_RENAME) carve_blocked(tt.blk_ids, (flags & IPG_GRAPH_BINNED) != 0);
+    if (ids_table(flags)) carve_blocked(tt.blk_ids, (flags & IPG_GRAPH_BINNED) != 0);
   }
   if (t) *t = tt;
   return align_up(c.used, 256);
@@ -270,8 +281,9 @@ static ipg_status build_tiling(const uint64_t* csc_off, uint32_t n, uint64_t e, 
 // tie; ties in id order -- a counting sort on the host), the CSC rebuilt
 // under those names and its tiling.
 static ipg_status build_hot_store(const uint64_t* csc_off, const int32_t* csc_src, uint32_t n, uint64_t e,
-                                  GraphTables* t, hipStream_t s) {
-  std::vector<uint32_t> deg(n), perm(n);
+                                  GraphTables* t, std::vector<uint32_t>& perm, hipStream_t s) {
+  std::vector<uint32_t> deg(n), iperm(n);
+  perm.assign(n, 0);
   IPG_HIP(hipMemcpyAsync(deg.data(), t->outdeg, n * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   std::vector<uint64_t> off((size_t)n + 1), off_hot((size_t)n + 1, 0);
   IPG_HIP(hipMemcpyAsync(off.data(), csc_off, off.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
@@ -282,9 +294,11 @@ static ipg_status build_hot_store(const uint64_t* csc_off, const int32_t* csc_sr
   for (uint32_t v = 0; v < n; ++v) ++start[key(v) + 1];
   for (uint32_t k = 0; k < kKeys; ++k) start[k + 1] += start[k];
   for (uint32_t v = 0; v < n; ++v) perm[v] = static_cast<uint32_t>(start[key(v)]++);
+  for (uint32_t v = 0; v < n; ++v) iperm[perm[v]] = v;
   for (uint32_t v = 0; v < n; ++v) off_hot[(size_t)perm[v] + 1] = off[v + 1] - off[v];
   for (uint32_t r = 0; r < n; ++r) off_hot[(size_t)r + 1] += off_hot[r];
   IPG_HIP(hipMemcpyAsync(t->perm, perm.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  IPG_HIP(hipMemcpyAsync(t->iperm, iperm.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, s));
   IPG_HIP(hipMemcpyAsync(t->off_hot, off_hot.data(), off_hot.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s));
   const uint32_t gv = grid_for(n, kBlock, 16384);
   hipLaunchKernelGGL(scatter_u32_kernel, dim3(gv), dim3(kBlock), 0, s, t->outdeg, t->perm, n, t->outdeg_hot);
@@ -407,15 +421,16 @@ extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t
   if (h[kFlagDegree]) return fail(IPG_EBADGRAPH, "an out-degree exceeds 2^32-1");
   ipg_status rc = build_tiling(csc_off, n, e, &t.pull, t.flags + kNumFlags, s);
   if (rc != IPG_OK) return rc;
+  std::vector<uint32_t> perm_host;
   if (d->flags & IPG_GRAPH_RENAME) {
-    rc = build_hot_store(csc_off, csc_src, n, e, &t, s);
+    rc = build_hot_store(csc_off, csc_src, n, e, &t, perm_host, s);
     if (rc != IPG_OK) return rc;
   }
   if (d->flags & IPG_GRAPH_BLOCKED) {
     const uint32_t hot = (d->flags & IPG_GRAPH_BINNED) ? (d->binned_hot ? d->binned_hot : kBinHotDefault) : 0u;
     if (d->flags & IPG_GRAPH_RENAME) {
       rc = build_blocked(t.off_hot, t.src_hot, n, e, &t.blk, hot, s);
-      if (rc == IPG_OK) rc = build_blocked(csc_off, csc_src, n, e, &t.blk_ids, hot, s);
+      if (rc == IPG_OK && ids_table(d->flags)) rc = build_blocked(csc_off, csc_src, n, e, &t.blk_ids, hot, s);
     } else {
       rc = build_blocked(csc_off, csc_src, n, e, &t.blk, hot, s);
     }
@@ -434,6 +449,7 @@ extern "C" ipg_status ipg_graph_create(const ipg_graph_desc* d, void* ws, size_t
   g->csr_w = d->csr_w;
   g->csc_w = csc_w;
   g->t = t;
+  g->perm_host.swap(perm_host);
   IPG_HIP(hipGetDevice(&g->device));
   g->has_values = 0;
   g->last_app = -1;

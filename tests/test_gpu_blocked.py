@@ -292,12 +292,53 @@ def test_binned_symmetrised_and_switched_off(ipg):
     ref = oracle.run_graph("pagerank", hg, 10)
     vals, _ = g.run("pagerank", 10, mode="pull", tuning={"blocked": 0xFFFFFFFF})  # row items on the same store
     assert max_rel(ipg.values_to_numpy(vals), ref.values) <= PR_RTOL
-    # CC and SSSP on the store keep their own (unbinned) blocked in-edges
+    # CC and SSSP on the symmetric binned store run under the hot-first names
+    # on PageRank's table; with the blocked pull switched off, on the caller's
+    # names with row items
     for app in ("cc", "sssp"):
         r = oracle.run_graph(app, hg, 0)
         for persistent in (False, True):
-            v, st = g.run(app, source=0, persistent=persistent)
-            assert np.array_equal(ipg.values_to_numpy(v), r.values) and np.array_equal(st.trace, r.trace)
+            for tuning in (None, {"blocked": 0xFFFFFFFF}):
+                v, st = g.run(app, source=0, persistent=persistent, tuning=tuning)
+                assert np.array_equal(ipg.values_to_numpy(v), r.values) and np.array_equal(st.trace, r.trace)
+
+
+@pytest.mark.parametrize("app", ["cc", "sssp"])
+def test_symmetric_binned_runs_under_new_names(ipg, app):
+    # Sources mapped to their new names, CC labels started from the caller's
+    # ids, values mapped back: every exchange, both loops, several sources,
+    # and a graph with isolated vertices and several components (the labels
+    # are the smallest caller id of each component, not of its new names).
+    n = 70000
+    rng = np.random.default_rng(31)
+    a = rng.integers(0, 40000, 300000)
+    b = np.minimum(a + rng.integers(1, 3000, 300000), 39999)  # one component among 0..39999, mostly
+    c = rng.integers(45000, 60000, 50000)
+    d = rng.integers(45000, 60000, 50000)                       # another among 45000..59999; the rest isolated
+    hg = graphgen.from_edges(n, np.concatenate([a, c]), np.concatenate([b, d]), symmetric=True)
+    g = ipg.Graph.from_host(hg, blocked=True, binned=True, binned_hot=4096)
+    sources = [0] if app == "cc" else [0, 45000, 65000, int(graphgen.pick_sources(hg, 1, seed=3)[0])]
+    for src in sources:
+        ref = oracle.run_graph(app, hg, 0, source=src)
+        for mode in ("auto", "push", "pull"):
+            for persistent in (False, True):
+                print(f"[renamed] {app} src={src} {mode} persistent={persistent}", flush=True)
+                v, st = g.run(app, source=src, mode=mode, persistent=persistent)
+                assert np.array_equal(ipg.values_to_numpy(v), ref.values), (src, mode, persistent)
+                assert np.array_equal(st.trace, ref.trace), (src, mode, persistent)
+
+
+def test_symmetric_binned_weighted_sssp_keeps_caller_names(ipg):
+    # weighted SSSP on a symmetric binned store: the renamed CSC has no weights,
+    # so the run keeps the caller's names (row-item pull with CSC weights)
+    hg = graphgen.grid_with_shortcuts(128, 0.01, seed=5)
+    assert hg.csr_w is not None
+    g = ipg.Graph.from_host(hg, blocked=True, binned=True, binned_hot=1024)
+    ref = oracle.run_graph("sssp", hg, 0, source=7)
+    for mode in ("auto", "pull", "push"):
+        for persistent in (False, True):
+            v, st = g.run("sssp", source=7, mode=mode, persistent=persistent)
+            assert np.array_equal(ipg.values_to_numpy(v), ref.values) and np.array_equal(st.trace, ref.trace)
 
 
 def test_binned_multigraph_hubs_and_empty_ranges(ipg):

@@ -394,4 +394,4 @@ def test_autotune_on_device(ipg, tmp_path):
     r, _ = g.run("pagerank", 10, tuning=best)
     assert max_rel(to_np(r), oracle.run_graph("pagerank", hg, 10).values) <= PR_RTOL
     best = autotune.tune(g, hg, "sssp", cache_path=str(tmp_path / "t.json"), reps=1)
-    assert set(best) == {"push_div", "list_div", "pull_grid", "gate_div"}
+    assert set(best) == {"push_div", "list_div", "pull_grid", "gate_div", "late_div"}
