@@ -63,9 +63,13 @@ typedef enum { IPG_MODE_AUTO = 0, IPG_MODE_PUSH = 1, IPG_MODE_PULL = 2 } ipg_mod
 #define IPG_GRAPH_VALIDATE 2u  /* check offsets and ids on the device at create time */
 #define IPG_GRAPH_RENAME 4u    /* keep a second copy of the CSC source ids renamed hot-first (by descending
                                   out-degree) for PageRank's pull exchange, whose outbox is then stored in
-                                  that order: the most-read outbox entries share cache lines.  Results are
-                                  unchanged (same values summed in the same order); costs 4E + 4N bytes of
-                                  graph workspace. */
+                                  that order: the most-read outbox entries share cache lines.  On a symmetric
+                                  blocked store CC and SSSP run under the new names too (the renamed CSC
+                                  serves as the CSR; CC's labels start from the caller's ids; values come
+                                  back in the caller's order).  Results are unchanged (PageRank: the same
+                                  values summed in the same order; CC/SSSP: the same minima); costs about
+                                  4E + 20N bytes of graph workspace (ids, both directions of the renaming,
+                                  out-degrees and offsets) plus a second pull tiling. */
 #define IPG_GRAPH_BLOCKED 8u   /* keep destination-blocked in-edges for PageRank's pull exchange (of the
                                   hot-first CSC with IPG_GRAPH_RENAME): the destinations are cut into runs of
                                   at most 20224 consecutive rows whose FP64 sums fit one workgroup's LDS
@@ -80,22 +84,26 @@ typedef enum { IPG_MODE_AUTO = 0, IPG_MODE_PUSH = 1, IPG_MODE_PULL = 2 } ipg_mod
                                   are not bitwise reproducible.  Built on the host (two counting sorts, O(N + E)
                                   time and about 16E + 24N bytes of host memory); costs about 4E bytes plus a
                                   partial-sum buffer of at most 256 * 20224 doubles of graph workspace, which
-                                  runs on the handle share (runs on one handle must not overlap in time). */
+                                  runs on the handle share (runs on one handle must not overlap in time).
+                                  CC and SSSP with unit weights pull over the same table on a symmetric
+                                  store with IPG_GRAPH_RENAME (u32 minima in LDS, exact), else over a
+                                  second one built on the caller's CSC (with IPG_GRAPH_RENAME) or the same
+                                  one (without). */
 
 #define IPG_GRAPH_BINNED 16u   /* with IPG_GRAPH_BLOCKED: PageRank's pull gathers only the outboxes of the
                                   sources below ipg_graph_desc.binned_hot (rounded up to a multiple of 65536;
                                   hot-first names with IPG_GRAPH_RENAME) edge by edge.  Every other ("cold")
                                   source's outbox is copied, once per superstep, into one slot per block it
-                                  has in-edges to, by a bin launch that takes 16384 sources per workgroup
-                                  (their outboxes staged in LDS) and writes each block's slots as runs of
-                                  whole 64-byte lines; the pull then reads a block's cold messages from its
-                                  slots in order.  This turns a cold gather, which moves a memory line for
+                                  has in-edges to, by a bin launch whose workgroups take up to 4096 groups
+                                  of 64 slots of one window of 8192 sources (their outboxes staged in LDS)
+                                  and write each block's slots as runs of whole 8-slot lines; the pull then
+                                  reads a block's cold messages from its slots in order.  This turns a cold gather, which moves a memory line for
                                   8 bytes once the outbox array outgrows the caches, into a streamed
                                   write and read of 8 bytes (propagation blocking over Section 4.3.2's pull).
                                   The sums are unchanged (the same messages; order as with
-                                  IPG_GRAPH_BLOCKED).  The CC/SSSP pull's blocked in-edges (of the caller's
-                                  ids) are binned the same way, with their u32 outboxes (INF for a source
-                                  that did not broadcast) in the slots and the same hot count of ids.
+                                  IPG_GRAPH_BLOCKED).  The CC/SSSP pull's blocked in-edges are binned the
+                                  same way, with their u32 outboxes (INF for a source that did not
+                                  broadcast) in the slots and the same hot count.
                                   Costs about 10 bytes per cold (block, source) pair of graph workspace per
                                   binned table (bounded by 10E + 70 x the (block, window) pairs). */
 
@@ -121,7 +129,7 @@ typedef struct {
   const uint32_t* csr_w;
   const uint32_t* csc_w;
   uint32_t flags;
-  uint32_t binned_hot;  /* IPG_GRAPH_BINNED: sources gathered edge by edge (0 = 262144, 2 MB of outboxes) */
+  uint32_t binned_hot;  /* IPG_GRAPH_BINNED: sources gathered edge by edge (0 = 1048576, 8 MB of FP64 outboxes) */
 } ipg_graph_desc;
 
 /* ipg_run_opts.flags */

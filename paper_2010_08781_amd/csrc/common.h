@@ -126,8 +126,8 @@ struct GraphTables {
   // IPG_GRAPH_BLOCKED: the blocked in-edges of the CSC PageRank's pull uses
   // (the hot-first one when present), else edges == null; with a hot-first
   // store also those of the caller's CSC (blk_ids), for the CC/SSSP pull,
-  // which works on the caller's vertex ids -- except on a symmetric binned
-  // store, where CC and SSSP run under the new names on `blk` (min_space).
+  // which works on the caller's vertex ids -- except on a symmetric store,
+  // where CC and SSSP run under the new names on `blk` (min_space).
   BlockedTables blk;
   BlockedTables blk_ids;
 };

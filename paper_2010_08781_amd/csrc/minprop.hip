@@ -1077,7 +1077,7 @@ static uint64_t list_limit(uint32_t n, uint32_t div) {
 // The names a CC/SSSP run works under.  The caller's, with the caller's CSR
 // for the push and the blocked in-edges of the caller's CSC (blk_ids, or
 // blk on a store without renaming) for the pull.  Or, on a symmetric store
-// that is hot-first and binned, the new names (Section 4.2's vertex arrays
+// that is hot-first and blocked, the new names (Section 4.2's vertex arrays
 // in another order): the push reads the renamed CSC as the CSR (the graph is
 // symmetric), the pull PageRank's table, whose hot sources are the most-read
 // ones; CC's labels start from the caller's ids (iperm), SSSP starts at the
@@ -1100,7 +1100,7 @@ static MinSpace min_space(const ipg_graph* g, ipg_app app, uint32_t source, cons
   MinSpace sp;
   const bool weighted = app == IPG_APP_SSSP && g->csr_w != nullptr;
   const GraphTables& t = g->t;
-  sp.renamed = (g->flags & IPG_GRAPH_SYMMETRIC) && t.perm && t.blk.edges && t.blk.hot && !weighted && tn.blocked &&
+  sp.renamed = (g->flags & IPG_GRAPH_SYMMETRIC) && t.perm && t.blk.edges && !weighted && tn.blocked &&
                g->perm_host.size() == g->n;
   if (sp.renamed) {
     sp.off = t.off_hot;

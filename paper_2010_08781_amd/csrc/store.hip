@@ -151,13 +151,10 @@ static void carve_tiling(Carver& c, uint32_t n, uint64_t e, TilingTables* t) {
 
 // Whether a blocked store also holds the blocked in-edges of the caller's
 // CSC (blk_ids): with a hot-first store, for CC/SSSP, which keep the caller's
-// names -- but not when it is symmetric and binned: CC and SSSP then run
-// under the new names on the hot-first table (min_space), whose hot sources
-// are the most-read ones.
-static bool ids_table(uint32_t flags) {
-  if (!(flags & IPG_GRAPH_RENAME)) return false;
-  return !((flags & IPG_GRAPH_SYMMETRIC) && (flags & IPG_GRAPH_BINNED));
-}
+// names -- but not when it is symmetric: CC and SSSP then run under the new
+// names on the hot-first table (min_space), whose hot sources are the
+// most-read ones.
+static bool ids_table(uint32_t flags) { return (flags & IPG_GRAPH_RENAME) && !(flags & IPG_GRAPH_SYMMETRIC); }
 
 static size_t carve_graph(Carver& c, uint32_t n, uint64_t e, uint32_t flags, GraphTables* t) {
   GraphTables tt{};
