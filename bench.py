@@ -206,9 +206,11 @@ def bench_workload(name, args, sel, ipg, np, torch, steps, warmup, apps, tune_ca
                                                  binned_hot=args.binned_hot)
         print(f"[bench] PageRank graph created in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     if any(a != "pagerank" for a in apps):
+        # the hot sources' values held in 8 MB either way: 2^20 FP64 outboxes
+        # for PageRank (the library's default), 2^21 u32 ones for CC/SSSP
         gm = graphs["pagerank"] if h_min is h_pr and "pagerank" in graphs else \
             ipg.Graph.from_host(h_min, blocked=not args.no_blocked, binned=binned(h_min.n, 4),
-                                binned_hot=args.binned_hot)
+                                binned_hot=args.binned_hot or (1 << 21))
         for a in apps:
             if a != "pagerank":
                 graphs[a] = gm

@@ -69,7 +69,8 @@ typedef enum { IPG_MODE_AUTO = 0, IPG_MODE_PUSH = 1, IPG_MODE_PULL = 2 } ipg_mod
                                   back in the caller's order).  Results are unchanged (PageRank: the same
                                   values summed in the same order; CC/SSSP: the same minima); costs about
                                   4E + 20N bytes of graph workspace (ids, both directions of the renaming,
-                                  out-degrees and offsets) plus a second pull tiling. */
+                                  out-degrees and offsets) plus a second pull tiling, and 4N bytes of host
+                                  memory in the handle (the renaming, to map an SSSP source). */
 #define IPG_GRAPH_BLOCKED 8u   /* keep destination-blocked in-edges for PageRank's pull exchange (of the
                                   hot-first CSC with IPG_GRAPH_RENAME): the destinations are cut into runs of
                                   at most 20224 consecutive rows whose FP64 sums fit one workgroup's LDS

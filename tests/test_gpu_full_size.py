@@ -115,7 +115,7 @@ def test_s26_pagerank(ipg, s26):
 def s26_sym(ipg, s26):
     _, s, _ = s26
     t = time.time()
-    g = ipg.Graph.from_host(s, blocked=True, binned=True)
+    g = ipg.Graph.from_host(s, blocked=True, binned=True, binned_hot=1 << 21)
     log(f"symmetrised store (blocked, binned, {s.m} edges) created in {time.time() - t:.1f}s")
     yield g
     g.close()
