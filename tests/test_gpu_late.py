@@ -118,3 +118,20 @@ def test_edge_cases(ipg):
                     (path(40), "sssp"), (random_graph(3000, 20000, seed=10, loops=True, dups=True), "cc")):
         g = ipg.Graph.from_host(hg)
         runs(ipg, g, hg, app, 0)
+
+
+@pytest.mark.parametrize("app", ["cc", "sssp"])
+def test_push_variants_of_the_selector(ipg, app):
+    # The variants the selector scores, forced as its training forces them:
+    # every push over the list (list_div = 1), every push sweeping the
+    # mailboxes (list_div = UINT32_MAX), every pull -- same values and trace,
+    # on the caller's names (directed) and under the hot-first names
+    # (symmetric, blocked), in both loops.
+    for hg in (graphgen.rmat(15, 16, seed=12, symmetric=True), graphgen.rmat(14, 16, seed=13)):
+        ref = oracle.run_graph(app, hg, 0, source=0)
+        g = ipg.Graph.from_host(hg, blocked=True)
+        for mode, tuning in (("push", {"list_div": 1}), ("push", {"list_div": NEVER}), ("pull", None)):
+            for persistent in (False, True):
+                v, st = g.run(app, source=0, mode=mode, tuning=tuning, persistent=persistent)
+                assert np.array_equal(ipg.values_to_numpy(v), ref.values), (hg.name, mode, tuning, persistent)
+                assert np.array_equal(st.trace, ref.trace), (hg.name, mode, tuning, persistent)
