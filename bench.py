@@ -40,7 +40,7 @@ def pr_pull_bytes(n: int, m: int) -> int:
 # summary: valid only while the kernel sources are the ones it was taken on.
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "pr_pull_traffic_{workload}.md")
 KERNEL_SOURCES = ("paper_2010_08781_amd/csrc/pagerank.hip", "paper_2010_08781_amd/csrc/common.h",
-                  "paper_2010_08781_amd/csrc/blocked_layout.h",
+                  "paper_2010_08781_amd/csrc/blocked_layout.h", "paper_2010_08781_amd/csrc/blocked.h",
                   "paper_2010_08781_amd/csrc/engine.h", "paper_2010_08781_amd/csrc/store.hip")
 
 

@@ -210,7 +210,9 @@ __device__ __forceinline__ void bin_unit(const BinTables& bv, T* slots, uint32_t
         if (static_cast<uint32_t>(__shfl(static_cast<int>(cand[b].flat), c)) <= j) t = c;
       const uint32_t flat = static_cast<uint32_t>(__shfl(static_cast<int>(cand[b].flat), t));
       const uint32_t dst = static_cast<uint32_t>(__shfl(static_cast<int>(cand[b].dst), t));
-      if (g + b < ng && j < len) slots[static_cast<uint64_t>(dst) + (j - flat)] = win[so[b]];
+      // non-temporal: the slots are read once, by the next launch, long after
+      // the lines would have left L2
+      if (g + b < ng && j < len) __builtin_nontemporal_store(win[so[b]], slots + static_cast<uint64_t>(dst) + (j - flat));
     }
   }
 }
