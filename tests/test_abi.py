@@ -99,3 +99,22 @@ def test_footprint_report_adds_up(lib):
     # the hot-first copy of the sources adds 4 bytes per edge and 4 per vertex
     r = ipg.footprint(n, m, symmetric=True, rename=True)
     assert r["graph_workspace"] - f["graph_workspace"] >= 4 * m + 4 * n
+
+
+def test_blocked_tables_per_store(lib):
+    # A hot-first blocked store keeps a second blocked table, on the caller's
+    # CSC, for CC/SSSP -- unless it is symmetric: CC and SSSP then run under
+    # the new names on the hot-first table, so the symmetric store is one
+    # table (about 4E bytes) smaller than the directed one of the same size.
+    import paper_2010_08781_amd as ipg
+
+    n, m = 1 << 20, 31 << 20
+    for binned in (False, True):
+        sym = ipg.footprint(n, m, symmetric=True, rename=True, blocked=True, binned=binned)["graph_workspace"]
+        dirg = ipg.footprint(n, m, symmetric=False, rename=True, blocked=True, binned=binned)["graph_workspace"]
+        plain = ipg.footprint(n, m, symmetric=True, rename=True)["graph_workspace"]
+        assert dirg - sym >= 4 * m, binned
+        assert sym - plain >= 4 * m, binned  # the one table it keeps
+    # the renaming itself: ids, both directions, by-name out-degrees and offsets
+    base = ipg.footprint(n, m, symmetric=True, rename=False)["graph_workspace"]
+    assert ipg.footprint(n, m, symmetric=True, rename=True)["graph_workspace"] - base >= 4 * m + 20 * n
