@@ -54,8 +54,11 @@ typedef enum { IPG_COMBINE_SUM = 0, IPG_COMBINE_MIN = 1 } ipg_combiner;
 
 /* Message exchange (Section 4.3.2).  The mode never changes results.  AUTO
  * picks per superstep: the learned selector when ipg_run_opts.selector is
- * set, else a fixed frontier-size heuristic.  PageRank runs every vertex in
- * every superstep, so its AUTO is pull. */
+ * set (push over the frontier list, push sweeping every vertex, or pull),
+ * else a fixed frontier-size heuristic; a CC/SSSP superstep it picks as pull
+ * may then turn to a push once its messages are counted (ipg_tuning.late_div).
+ * PUSH and PULL force the exchange of every superstep.  PageRank runs every
+ * vertex in every superstep, so its AUTO is pull. */
 typedef enum { IPG_MODE_AUTO = 0, IPG_MODE_PUSH = 1, IPG_MODE_PULL = 2 } ipg_mode;
 
 /* ipg_graph_desc.flags */
